@@ -1,0 +1,292 @@
+/*
+ * spx: adaptive SpMV / SpMSpV for AMD MI355X (gfx950).
+ *
+ * C ABI of the library libspx.so. Plain C types and pointers only.
+ *
+ * The operation (Section 2 of Li, Ao, Yang, "Adaptive SpMV/SpMSpV on GPUs
+ * for Input Vectors of Varied Sparsity"): A is an m-by-n sparse matrix
+ * with nnz stored entries, x is a vector of length n, given either dense
+ * (one array of n values) or sparse (nnz_x indices and nnz_x values), and
+ * every entry point computes the dense output
+ *
+ *        y = A x        (y has length m and is overwritten, never added to)
+ *
+ * The library holds a family of kernels that differ along the paper's
+ * axes (Section 4): computing pattern (row-major SpMV, row-major SpMSpV
+ * with value validation, column-major SpMSpV), workload distribution
+ * (direct or load-balanced) and, for the column-major pattern, write-back
+ * (atomic, sort, plus an LDS-privatized atomic and a bucket write-back).
+ * A three-step decision-tree cascade (Section 5, Section 6.2) picks one
+ * per input vector at run time.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named dev_* or documented as "device" point to GPU memory
+ *    that the caller allocated (e.g. with PyTorch) and still owns. The
+ *    library never frees caller memory.
+ *  - Indices are int32; nnz < 2^31. A CSR matrix has row_ptr[m+1]
+ *    (row_ptr[0] = 0, non-decreasing) and col_idx[nnz] in [0, n); column
+ *    indices within a row are unique (any order is accepted by every
+ *    kernel). Sparse vectors have unique indices in [0, n), any order.
+ *  - Value types (spx_dtype): F32 and F64 (real (+, *)), I32 ((+, *)
+ *    modulo 2^32, bit-exact), BOOL ((OR, AND): A is its pattern and vals
+ *    are ignored (may be NULL); a sparse x is the index set and x values
+ *    are ignored (may be NULL); a dense x is uint8 0/1; y is uint8 0/1).
+ *  - Explicit zeros stored in A or in a sparse x are structural: they are
+ *    part of the pattern (an "effective nonzero" is any stored A entry in
+ *    a column that x lists, Section 2).
+ *  - Rows with no effective entry are written as exact +0 (0 for I32 and
+ *    BOOL).
+ *  - Every launch is enqueued on the caller's stream (a hipStream_t passed
+ *    as void*; NULL is the default stream) and returns without waiting,
+ *    except where a function says it synchronizes.
+ *  - Every function returns an spx_status (0 on success, negative on
+ *    error); nothing aborts and no C++ exception crosses the boundary.
+ *    spx_last_error() returns a thread-local message for the last error.
+ *    Faults inside a kernel surface at the next synchronizing call as
+ *    SPX_ERR_HIP.
+ *  - Floating-point results: FP32 kernels satisfy
+ *    |y_i - exact_i| <= 1e-5 * sum_j |a_ij x_j|, FP64 kernels
+ *    1e-12 * sum_j |a_ij x_j|; the order of accumulation is unspecified
+ *    and atomic write-backs are not run-to-run deterministic.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int spx_status;
+#define SPX_OK 0
+#define SPX_ERR_ARG (-1)          /* null pointer, negative size, bad enum value */
+#define SPX_ERR_SHAPE (-2)        /* sizes that do not agree (e.g. x length != n) */
+#define SPX_ERR_INDEX (-3)        /* an index out of range (validation mode only) */
+#define SPX_ERR_DTYPE (-4)        /* dtype not supported by this entry point */
+#define SPX_ERR_UNSUPPORTED (-5)  /* plan not available for these inputs */
+#define SPX_ERR_ALLOC (-6)        /* device or host allocation failed */
+#define SPX_ERR_HIP (-7)          /* a HIP runtime call failed */
+#define SPX_ERR_WORKSPACE (-8)    /* workspace missing or smaller than required */
+
+typedef enum { SPX_F32 = 0, SPX_F64 = 1, SPX_BOOL = 2, SPX_I32 = 3 } spx_dtype;
+
+/* Computing pattern (Section 4.1). */
+typedef enum {
+    SPX_PAT_SPMV = 0,       /* row-major, matrix-driven, no validation: dense x */
+    SPX_PAT_CSR_SPMSPV = 1, /* row-major, matrix-driven, validation by bitvector */
+    SPX_PAT_CSC_SPMSPV = 2  /* column-major, vector-driven: visits effective entries only */
+} spx_pattern;
+
+/* Workload distribution (Section 4.2.1). */
+typedef enum {
+    SPX_DIST_DIRECT = 0,  /* a fixed group of `lanes` threads per row (per column for CSC) */
+    SPX_DIST_BALANCED = 1 /* merge-path tiles with equal (rows + entries) per workgroup */
+} spx_distribution;
+
+/* Write-back of the column-major pattern (Section 4.2.2). */
+typedef enum {
+    SPX_WB_NONE = 0,       /* row-major patterns: each row written once, no conflict */
+    SPX_WB_ATOMIC = 1,     /* zero y, then hardware atomic add per effective entry */
+    SPX_WB_SORT = 2,       /* write (row, value) pairs, radix-sort by row, reduce by key */
+    SPX_WB_LDS_ATOMIC = 3, /* per-workgroup copy of y in LDS, flushed with atomics (small m) */
+    SPX_WB_BUCKET = 4      /* bin pairs by row range, one workgroup per bucket sums in LDS */
+} spx_writeback;
+
+/* One candidate kernel plus its launch parameters. Zero parameters mean
+ * "choose automatically". */
+typedef struct {
+    int32_t pattern;      /* spx_pattern */
+    int32_t distribution; /* spx_distribution */
+    int32_t writeback;    /* spx_writeback; SPX_WB_NONE for row-major patterns */
+    int32_t lanes;        /* direct: threads per row/column, power of two in [1, 64]; 0 = auto */
+    int32_t tile;         /* balanced: items per 256-thread workgroup tile; 0 = auto */
+    int32_t bucket_rows;  /* bucket write-back: rows per bucket, power of two; 0 = auto */
+} spx_plan;
+
+/* A CSR matrix (device arrays, caller-owned). */
+typedef struct {
+    int32_t m, n, nnz;
+    int32_t dtype;          /* spx_dtype */
+    const int32_t *row_ptr; /* device, m + 1 */
+    const int32_t *col_idx; /* device, nnz */
+    const void *vals;       /* device, nnz values of dtype; ignored for BOOL */
+} spx_csr;
+
+/* A CSC matrix (device arrays): col_ptr[n+1], row_idx[nnz], vals[nnz]. */
+typedef struct {
+    int32_t m, n, nnz;
+    int32_t dtype;
+    const int32_t *col_ptr;
+    const int32_t *row_idx;
+    const void *vals;
+} spx_csc;
+
+typedef enum { SPX_VEC_DENSE = 0, SPX_VEC_SPARSE = 1 } spx_vec_kind;
+
+/* An input vector x of length n (Section 2: dense = one array of n values;
+ * sparse = nnz_x indices plus nnz_x values). Device arrays, caller-owned. */
+typedef struct {
+    int32_t kind;        /* spx_vec_kind */
+    int32_t n;
+    int32_t nnz_x;       /* sparse: number of entries; dense: ignored (-1 ok) */
+    const int32_t *idx;  /* sparse: device, nnz_x indices */
+    const void *val;     /* dense: device, n values; sparse: device, nnz_x values */
+} spx_vec;
+
+typedef struct spx_matrix spx_matrix; /* opaque handle, see spx_matrix_create */
+
+/* ---------------------------------------------------------------------
+ * Candidate kernels, called directly with an explicit plan.
+ * ------------------------------------------------------------------- */
+
+/* Bytes of device workspace the given plan needs for a call on an m x n
+ * matrix with nnz entries and at most nnz_x_max vector entries (dense x:
+ * pass n). Returns 0 when none is needed. Host only. */
+size_t spx_workspace_size(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x_max, int32_t dtype,
+                          const spx_plan *plan);
+
+/* SpMV, row-major pattern (Section 4.1, the traditional SpMV): y = A x for a
+ * dense x[n] (device, dtype; uint8 0/1 for BOOL). plan->pattern must be
+ * SPX_PAT_SPMV; distribution DIRECT or BALANCED. BALANCED needs the
+ * workspace of spx_workspace_size (carries between tiles). y: device, m
+ * values (uint8 for BOOL). */
+spx_status spmv_csr(const spx_csr *A, const void *x, void *y, const spx_plan *plan,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+/* SpMSpV, row-major pattern with value validation (Section 4.1 and 6.1:
+ * the SpMV skeleton skips entries whose column is not in supp(x), tested
+ * with a bitvector of supp(x)). x is sparse: x_idx[nnz_x], x_val[nnz_x]
+ * (device). The call converts x to a bitvector and a scattered value array
+ * inside the workspace (spx_workspace_size with plan->pattern =
+ * SPX_PAT_CSR_SPMSPV). */
+spx_status spmspv_csr(const spx_csr *A, int32_t nnz_x, const int32_t *x_idx, const void *x_val,
+                      void *y, const spx_plan *plan, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/* SpMSpV, column-major vector-driven pattern (Section 4.1): for every
+ * (j, v) in x, column j of A is scaled by v and written back into y by the
+ * plan's write-back (Section 4.2.2). A is CSC (see spx_matrix_csc for a
+ * CSC built from a CSR). y is overwritten (zero rows included). The
+ * workspace must hold spx_workspace_size(A->m, A->n, A->nnz, nnz_x, ...)
+ * bytes (the row-pointer-derived bucket layout of SPX_WB_BUCKET needs a
+ * handle and is only available through run_plan). */
+spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, const void *x_val,
+                      void *y, const spx_plan *plan, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/* ---------------------------------------------------------------------
+ * Matrix handle: the dual CSR + CSC storage kept for the life of the
+ * matrix (Section 6.1) and the matrix features computed once (Section 6.3).
+ * ------------------------------------------------------------------- */
+
+/* Builds the handle for the CSR matrix A. The handle BORROWS A's device
+ * arrays (they must outlive it) and OWNS what it derives: the CSC copy
+ * (stable counting-sort transpose on the device), the CSC-to-CSR
+ * permutation, the matrix features and the workspace. Synchronizes the
+ * stream once (to read the matrix features). Host-side checks only; pass
+ * flags & SPX_VALIDATE to also check row_ptr monotonicity and index
+ * ranges on the device (one extra sync). */
+#define SPX_VALIDATE 1u
+spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
+spx_status spx_matrix_destroy(spx_matrix *H);
+
+/* The handle's CSC copy (device pointers owned by the handle). */
+spx_status spx_matrix_csc(const spx_matrix *H, spx_csc *out);
+
+/* Re-derives the CSC values from the borrowed CSR values (gather through
+ * the permutation); call after the caller changed A's values in place. */
+spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
+
+/* Matrix features of Table 1, out[9] = {m, n, nnz, max_row, min_row,
+ * avg_row, relative_range = (max_row - min_row) / n, var_nnz_row
+ * (population standard deviation of row lengths), Gini coefficient of
+ * row lengths}. Host only (values computed at create). */
+spx_status spx_matrix_features(const spx_matrix *H, double *out9);
+
+/* Vector features of Table 1, out[4] = {nnz_x, x_sparsity = nnz_x / n,
+ * nnz_s = stored entries in columns of supp(x), m_sparsity = nnz_s / nnz}.
+ * Computed on the device (gather + reduction); synchronizes the stream. */
+spx_status spx_vector_features(spx_matrix *H, const spx_vec *x, double *out4, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Selection and adaptive execution (Sections 5 and 6).
+ * ------------------------------------------------------------------- */
+
+/* Loads the three decision trees (pattern, distribution, write-back) from
+ * a JSON file written by the tuner. NULL restores the built-in trees.
+ * Applies to handles created afterwards and to H if H is not NULL. */
+spx_status spx_load_selector(spx_matrix *H, const char *json_path);
+
+/* Walks the cascade: pattern tree, then distribution tree, then (column-
+ * major only) write-back tree (Section 6.2). Features are evaluated
+ * lazily, host-known ones first (Section 6.3); the only device work is the
+ * nnz_s / dense nnz_x reduction, which synchronizes the stream, and which
+ * flags & SPX_NO_SYNC forbids (rules needing it then take their
+ * host-feature fallback). */
+#define SPX_NO_SYNC 2u
+spx_status select_kernel(spx_matrix *H, const spx_vec *x, uint32_t flags, spx_plan *out,
+                         void *stream);
+
+/* Adaptive y = A x: select_kernel, convert x to the format the chosen
+ * kernel reads if it differs (Section 6.3: conversion only on change),
+ * launch. y: device, m values of the matrix dtype (uint8 for BOOL). */
+spx_status run(spx_matrix *H, const spx_vec *x, void *y, void *stream);
+
+/* y = A x with a given plan through the handle (its CSC and workspace). */
+spx_status run_plan(spx_matrix *H, const spx_vec *x, void *y, const spx_plan *plan, void *stream);
+
+/* The plan the last run() chose, and per-stage times of the last run()
+ * in milliseconds when profiling is on: out[0] features, out[1] model
+ * evaluation, out[2] vector conversion, out[3] kernel(s). */
+spx_status spx_last_plan(const spx_matrix *H, spx_plan *out);
+spx_status spx_set_profiling(spx_matrix *H, int32_t on);
+spx_status spx_stage_times(const spx_matrix *H, double *out4);
+
+/* ---------------------------------------------------------------------
+ * Batched SpMSpV: B sparse vectors in one launch sequence.
+ * X is CSR-of-vectors: vec_ptr[B+1] (device), idx[total] and val[total]
+ * (device); Y is B x m row-major (device), each vector's y contiguous.
+ * The plan of every vector is chosen on the device; nothing synchronizes.
+ * total_nnz_x (host) is an upper bound of vec_ptr[B] used to size the
+ * workspace.
+ * ------------------------------------------------------------------- */
+spx_status run_batch(spx_matrix *H, int32_t B, int64_t total_nnz_x, const int32_t *vec_ptr,
+                     const int32_t *idx, const void *val, void *Y, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Backward of y = A(vals) x for L(y): with g = dL/dy,
+ *   dx = A^T g                       (spmv_csr_transpose: row-major over
+ *                                     the CSC copy, i.e. a gather along
+ *                                     columns, no atomics)
+ *   dvals_k = sum_b g_b[row k] x_b[col k]   over the CSR pattern
+ * F32 and F64 only.
+ * ------------------------------------------------------------------- */
+
+/* dX[b] = A^T G[b] for b < B: G is B x m, dX is B x n (device, row-major). */
+spx_status spmv_csr_transpose(spx_matrix *H, int32_t B, const void *G, void *dX, void *stream);
+
+/* dvals[k] = sum_{b<B} G[b, row(k)] * X[b, col(k)], k over CSR positions.
+ * G is B x m and X is B x n dense (device, row-major). */
+spx_status dvals_pattern(spx_matrix *H, int32_t B, const void *G, const void *X, void *dvals,
+                         void *stream);
+
+/* ---------------------------------------------------------------------
+ * Host-only helpers.
+ * ------------------------------------------------------------------- */
+
+/* Checks the host-visible fields of a CSR descriptor (no device access). */
+spx_status spx_check_csr(const spx_csr *A);
+/* Checks that a plan is a legal kernel for the given dtype (no device access). */
+spx_status spx_check_plan(const spx_plan *plan, int32_t dtype);
+/* Thread-local message describing the last error (never NULL). */
+const char *spx_last_error(void);
+/* Library version string. */
+const char *spx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

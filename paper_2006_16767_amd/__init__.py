@@ -1,0 +1,298 @@
+"""Adaptive SpMV / SpMSpV on AMD MI355X (gfx950).
+
+A thin Python layer over libspx (include/spx.h). PyTorch supplies device
+memory and streams; every step of the computation runs in the library's HIP
+kernels. Importing this package does not load the library; the first call
+does, and fails loudly if it has not been built.
+
+    A = Matrix.from_csr(row_ptr, col_idx, vals, n)      # torch tensors on cuda
+    y = A.run(x)                 # dense x (tensor of length n)
+    y = A.run((idx, val))        # sparse x (indices, values)
+    y = A.run_plan(x, plan)      # a given candidate kernel
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
+                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
+                   WB_SORT, Plan, SpxError)
+
+__all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
+           "F32", "F64", "BOOL", "I32", "all_plans"]
+
+_TORCH_DT = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    return {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.uint8: BOOL,
+            torch.bool: BOOL}[t]
+
+
+def torch_dtype(code: int):
+    torch = _torch()
+    return {F32: torch.float32, F64: torch.float64, I32: torch.int32, BOOL: torch.uint8}[code]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def plan(pattern="spmv", distribution="direct", writeback="none", lanes=0, tile=0, bucket_rows=0) -> Plan:
+    pat = {"spmv": PAT_SPMV, "csr_spmspv": PAT_CSR_SPMSPV, "csc_spmspv": PAT_CSC_SPMSPV}[pattern]
+    dist = {"direct": DIST_DIRECT, "balanced": DIST_BALANCED}[distribution]
+    wb = {"none": WB_NONE, "atomic": WB_ATOMIC, "sort": WB_SORT, "lds_atomic": WB_LDS_ATOMIC,
+          "bucket": WB_BUCKET}[writeback]
+    return Plan(pat, dist, wb, lanes, tile, bucket_rows)
+
+
+def all_plans(include_bucket=True):
+    """Every candidate kernel (automatic launch parameters)."""
+    out = []
+    for d in ("direct", "balanced"):
+        out.append(plan("spmv", d))
+        out.append(plan("csr_spmspv", d))
+        for wb in ("atomic", "lds_atomic", "sort") + (("bucket",) if include_bucket else ()):
+            out.append(plan("csc_spmspv", d, wb))
+    return out
+
+
+def _vec(x, n):
+    """x: dense tensor (length n) or (idx, val) pair; val may be None for BOOL."""
+    if isinstance(x, tuple):
+        idx, val = x
+        return _lib.Vec(_lib.VEC_SPARSE, n, int(idx.numel()), _ptr(idx), _ptr(val)), (idx, val)
+    # the library checks the dense length against the matrix's n
+    return _lib.Vec(_lib.VEC_DENSE, int(x.numel()), -1, None, _ptr(x)), (x,)
+
+
+class Matrix:
+    """Handle over a CSR matrix on the GPU plus its device-built CSC copy.
+
+    The CSR tensors are borrowed (kept alive by this object); the CSC copy,
+    features and workspaces belong to the library handle."""
+
+    def __init__(self, row_ptr, col_idx, vals, m: int, n: int, dtype: int | None = None,
+                 validate: bool = False, stream=None):
+        torch = _torch()
+        self.row_ptr = row_ptr.contiguous()
+        self.col_idx = col_idx.contiguous()
+        self.vals = None if vals is None else vals.contiguous()
+        self.m, self.n = int(m), int(n)
+        self.nnz = int(self.col_idx.numel())
+        if dtype is None:
+            dtype = BOOL if vals is None else dtype_code(vals.dtype)
+        self.dtype = dtype
+        assert self.row_ptr.dtype == torch.int32 and self.col_idx.dtype == torch.int32
+        self._csr = _lib.Csr(self.m, self.n, self.nnz, dtype, _ptr(self.row_ptr), _ptr(self.col_idx),
+                             _ptr(self.vals))
+        h = C.c_void_p()
+        _lib.call("spx_matrix_create", C.byref(self._csr), VALIDATE if validate else 0, _stream(stream),
+                  C.byref(h))
+        self._h = h
+
+    @classmethod
+    def from_host(cls, A, dtype=None, device="cuda", validate=False):
+        """From an object with m, n, row_ptr, col_idx, vals (numpy)."""
+        torch = _torch()
+        rp = torch.as_tensor(A.row_ptr, dtype=torch.int32, device=device)
+        ci = torch.as_tensor(A.col_idx, dtype=torch.int32, device=device)
+        if dtype == BOOL or A.vals is None:
+            v = None
+            dt = BOOL
+        else:
+            v = torch.as_tensor(A.vals, device=device)
+            if dtype is not None:
+                v = v.to(torch_dtype(dtype))
+            dt = dtype_code(v.dtype)
+        return cls(rp, ci, v, A.m, A.n, dt, validate=validate)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().spx_matrix_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def out_tensor(self, batch: int | None = None):
+        torch = _torch()
+        shape = (self.m,) if batch is None else (batch, self.m)
+        return torch.empty(shape, dtype=torch_dtype(self.dtype), device=self.row_ptr.device)
+
+    def csc_pointers(self):
+        c = _lib.Csc()
+        _lib.call("spx_matrix_csc", self._h, C.byref(c))
+        return c
+
+    def csc(self):
+        """Copies of the handle's CSC arrays as tensors (for tests)."""
+        torch = _torch()
+        c = self.csc_pointers()
+        dev = self.row_ptr.device
+        col_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        row_idx = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        _copy_raw(col_ptr, c.col_ptr)
+        _copy_raw(row_idx, c.row_idx)
+        vals = None
+        if self.dtype != BOOL:
+            vals = torch.empty(self.nnz, dtype=torch_dtype(self.dtype), device=dev)
+            _copy_raw(vals, c.vals)
+        return col_ptr, row_idx, vals
+
+    def features(self) -> dict:
+        out = (C.c_double * 9)()
+        _lib.call("spx_matrix_features", self._h, out)
+        keys = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini")
+        return dict(zip(keys, list(out)))
+
+    def vector_features(self, x, stream=None) -> dict:
+        v, keep = _vec(x, self.n)
+        out = (C.c_double * 4)()
+        _lib.call("spx_vector_features", self._h, C.byref(v), out, _stream(stream))
+        return dict(zip(("nnz_x", "x_sparsity", "nnz_s", "m_sparsity"), list(out)))
+
+    def select(self, x, no_sync=False, stream=None) -> Plan:
+        v, keep = _vec(x, self.n)
+        p = Plan()
+        _lib.call("select_kernel", self._h, C.byref(v), NO_SYNC if no_sync else 0, C.byref(p),
+                  _stream(stream))
+        return p
+
+    def run(self, x, y=None, stream=None):
+        v, keep = _vec(x, self.n)
+        y = self.out_tensor() if y is None else y
+        _lib.call("run", self._h, C.byref(v), _ptr(y), _stream(stream))
+        return y
+
+    def run_plan(self, x, p: Plan, y=None, stream=None):
+        v, keep = _vec(x, self.n)
+        y = self.out_tensor() if y is None else y
+        _lib.call("run_plan", self._h, C.byref(v), _ptr(y), C.byref(p), _stream(stream))
+        return y
+
+    def last_plan(self) -> Plan:
+        p = Plan()
+        _lib.call("spx_last_plan", self._h, C.byref(p))
+        return p
+
+    def set_profiling(self, on: bool):
+        _lib.call("spx_set_profiling", self._h, 1 if on else 0)
+
+    def stage_times(self) -> dict:
+        out = (C.c_double * 4)()
+        _lib.call("spx_stage_times", self._h, out)
+        return dict(zip(("features_ms", "model_ms", "conversion_ms", "kernel_ms"), list(out)))
+
+    def values_updated(self, stream=None):
+        _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
+
+    def load_selector(self, path: str | None):
+        _lib.call("spx_load_selector", self._h, None if path is None else path.encode())
+
+    def run_batch(self, vec_ptr, idx, val, Y=None, total_nnz_x=None, stream=None):
+        B = int(vec_ptr.numel()) - 1
+        Y = self.out_tensor(B) if Y is None else Y
+        tot = int(idx.numel()) if total_nnz_x is None else int(total_nnz_x)
+        _lib.call("run_batch", self._h, B, tot, _ptr(vec_ptr), _ptr(idx), _ptr(val), _ptr(Y), _stream(stream))
+        return Y
+
+    def transpose_matvec(self, G, dX=None, stream=None):
+        """dX[b] = A^T G[b]; G is B x m (or m)."""
+        torch = _torch()
+        G2 = G.reshape(-1, self.m).contiguous()
+        B = G2.shape[0]
+        out = torch.empty((B, self.n), dtype=G.dtype, device=G.device) if dX is None else dX
+        _lib.call("spmv_csr_transpose", self._h, B, _ptr(G2), _ptr(out), _stream(stream))
+        return out.reshape(G.shape[:-1] + (self.n,)) if dX is None else out
+
+    def dvals(self, G, X, out=None, stream=None):
+        """dvals[k] = sum_b G[b, row k] X[b, col k]; G is B x m, X is B x n dense."""
+        torch = _torch()
+        G2 = G.reshape(-1, self.m).contiguous()
+        X2 = X.reshape(-1, self.n).contiguous()
+        out = torch.empty(self.nnz, dtype=G.dtype, device=G.device) if out is None else out
+        _lib.call("dvals_pattern", self._h, G2.shape[0], _ptr(G2), _ptr(X2), _ptr(out), _stream(stream))
+        return out
+
+
+def _copy_raw(dst, src_ptr: int):
+    """Device-to-device copy from a raw device pointer into a tensor."""
+    torch = _torch()
+    import ctypes
+    hip = _hip_runtime()
+    nbytes = dst.numel() * dst.element_size()
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy(C.c_void_p(dst.data_ptr()), C.c_void_p(src_ptr), C.c_size_t(nbytes), 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")
+
+
+_HIP = None
+
+
+def _hip_runtime():
+    global _HIP
+    if _HIP is None:
+        _lib.load()
+        _HIP = C.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.restype = C.c_int
+        _HIP.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _HIP
+
+
+# ----------------------------------------------------------------------------
+# Candidate kernels called directly (explicit plan and workspace)
+# ----------------------------------------------------------------------------
+
+def workspace_size(m, n, nnz, nnz_x_max, dtype, p: Plan) -> int:
+    return int(_lib.load().spx_workspace_size(m, n, nnz, nnz_x_max, dtype, C.byref(p)))
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def spmv_csr(A: Matrix, x, p: Plan, y=None, stream=None):
+    y = A.out_tensor() if y is None else y
+    ws = _workspace(workspace_size(A.m, A.n, A.nnz, A.n, A.dtype, p), x.device)
+    _lib.call("spmv_csr", C.byref(A._csr), _ptr(x), _ptr(y), C.byref(p), _ptr(ws), ws.numel(), _stream(stream))
+    return y
+
+
+def spmspv_csr(A: Matrix, idx, val, p: Plan, y=None, stream=None):
+    y = A.out_tensor() if y is None else y
+    ws = _workspace(workspace_size(A.m, A.n, A.nnz, int(idx.numel()), A.dtype, p), idx.device)
+    _lib.call("spmspv_csr", C.byref(A._csr), int(idx.numel()), _ptr(idx), _ptr(val), _ptr(y), C.byref(p),
+              _ptr(ws), ws.numel(), _stream(stream))
+    return y
+
+
+def spmspv_csc(A: Matrix, idx, val, p: Plan, y=None, stream=None):
+    y = A.out_tensor() if y is None else y
+    c = A.csc_pointers()
+    ws = _workspace(workspace_size(A.m, A.n, A.nnz, int(idx.numel()), A.dtype, p), idx.device)
+    _lib.call("spmspv_csc", C.byref(c), int(idx.numel()), _ptr(idx), _ptr(val), _ptr(y), C.byref(p),
+              _ptr(ws), ws.numel(), _stream(stream))
+    return y

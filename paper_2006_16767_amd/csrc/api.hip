@@ -1,0 +1,782 @@
+// C ABI of libspx: argument checks, the matrix handle (dual CSR + CSC
+// storage, Section 6.1), lazy feature evaluation and the decision-tree
+// cascade (Section 6.2-6.3), vector conversion on demand, and dispatch to
+// the candidate kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "selector.hpp"
+
+#define SPX_VERSION "spx 0.1 (gfx950)"
+
+namespace spx {
+
+static thread_local std::string g_err = "no error";
+
+spx_status fail(spx_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+spx_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string("HIP error '") + hipGetErrorString(e) + "' in " + what;
+    return SPX_ERR_HIP;
+}
+
+int value_size(int dtype) {
+    switch (dtype) {
+        case SPX_F32:
+        case SPX_I32:
+            return 4;
+        case SPX_F64:
+            return 8;
+        default:
+            return 0;
+    }
+}
+
+int out_size(int dtype) {
+    switch (dtype) {
+        case SPX_F32:
+        case SPX_I32:
+            return 4;
+        case SPX_F64:
+            return 8;
+        case SPX_BOOL:
+            return 1;
+        default:
+            return 0;
+    }
+}
+
+static bool valid_dtype(int dt) { return dt == SPX_F32 || dt == SPX_F64 || dt == SPX_I32 || dt == SPX_BOOL; }
+
+static int key_bits_for(int32_t n) {
+    int b = 0;
+    while (b < 31 && (int64_t(1) << b) < n) ++b;
+    return std::max(b, 1);
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ __launch_bounds__(kBlock) void k_iota(uint32_t* __restrict__ p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (; i < n; i += stride) p[i] = (uint32_t)i;
+}
+
+// col_ptr from column ids sorted ascending: position p starts every column
+// in (key[p-1], key[p]].
+__global__ __launch_bounds__(kBlock) void k_ptr_from_sorted(const uint32_t* __restrict__ keys, int64_t nnz,
+                                                            int32_t n, int32_t* __restrict__ ptr) {
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p > nnz) return;
+    const int64_t prev = p > 0 ? (int64_t)keys[p - 1] : -1;
+    const int64_t cur = p < nnz ? (int64_t)keys[p] : (int64_t)n;
+    for (int64_t j = prev + 1; j <= cur; ++j) ptr[j] = (int32_t)p;
+}
+
+// validation: row_ptr monotone with row_ptr[0] = 0 and row_ptr[m] = nnz,
+// col_idx in range; sets bit 0 / bit 1 of *bad
+__global__ __launch_bounds__(kBlock) void k_validate_csr(const int32_t* __restrict__ row_ptr, int32_t m,
+                                                         const int32_t* __restrict__ col_idx, int32_t nnz,
+                                                         int32_t n, uint32_t* __restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= m; i += stride) {
+        const int32_t v = row_ptr[i];
+        if ((i == 0 && v != 0) || (i == m && v != nnz) || (i > 0 && v < row_ptr[i - 1]) || v < 0 || v > nnz)
+            atomicOr(bad, 1u);
+    }
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride) {
+        const int32_t c = col_idx[k];
+        if (c < 0 || c >= n) atomicOr(bad, 2u);
+    }
+}
+
+// dense x -> bitvector of its nonzeros (x != 0)
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_dense_bits(int32_t n, const typename SR<DT>::X* __restrict__ x,
+                                                       uint32_t* __restrict__ bits) {
+    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // one word per thread
+    const int64_t j0 = w * 32;
+    if (j0 >= n) return;
+    uint32_t word = 0;
+    const int cnt = (int)std::min<int64_t>(32, n - j0);
+    for (int b = 0; b < cnt; ++b)
+        if (x[j0 + b] != (typename SR<DT>::X)0) word |= 1u << b;
+    bits[w] = word;
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+// ------------------------------------------------------------------ handle
+struct spx_matrix {
+    spx_csr csr{};  // borrowed arrays
+    int device = 0;
+    int32_t* col_ptr = nullptr;
+    int32_t* row_idx = nullptr;
+    int32_t* perm = nullptr;  // CSC position -> CSR position
+    void* vals_csc = nullptr;
+    double feat[9] = {0};
+    Selector sel;
+    // conversion buffers (allocated on first use)
+    uint32_t* bits = nullptr;
+    void* xd = nullptr;
+    int32_t* sp_idx = nullptr;
+    void* sp_val = nullptr;
+    int32_t* scratch_i32 = nullptr;  // compaction workspace
+    int64_t* dev_scalars = nullptr;  // 4 x int64 (feature reductions, counts)
+    uint32_t* bucket_cursor = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    spx_plan last_plan{};
+    // profiling
+    int profiling = 0;
+    double host_ms[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_conv, ev_kern;
+};
+
+static spx_status ensure_ws(spx_matrix* H, size_t bytes) {
+    if (bytes <= H->ws_bytes) return SPX_OK;
+    if (H->ws) SPX_HIP(hipFree(H->ws));
+    H->ws = nullptr;
+    H->ws_bytes = 0;
+    const size_t b = align_up(bytes, 1 << 20);
+    if (hipMalloc(&H->ws, b) != hipSuccess) return fail(SPX_ERR_ALLOC, "workspace allocation failed");
+    H->ws_bytes = b;
+    return SPX_OK;
+}
+
+static spx_status ensure_conv(spx_matrix* H) {
+    if (H->dev_scalars) return SPX_OK;
+    const int32_t n = H->csr.n;
+    const size_t vs = std::max(1, value_size(H->csr.dtype));
+    if (hipMalloc((void**)&H->bits, align_up((size_t)ceil_div(n, 32) * 4 + 4, 256)) != hipSuccess ||
+        hipMalloc(&H->xd, align_up((size_t)n * vs + 8, 256)) != hipSuccess ||
+        hipMalloc((void**)&H->sp_idx, align_up((size_t)n * 4 + 4, 256)) != hipSuccess ||
+        hipMalloc(&H->sp_val, align_up((size_t)n * vs + 8, 256)) != hipSuccess ||
+        hipMalloc((void**)&H->scratch_i32, compact_ws_elems(n) * 4 + 256) != hipSuccess ||
+        hipMalloc((void**)&H->dev_scalars, 64) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "conversion buffers: allocation failed");
+    return SPX_OK;
+}
+
+static spx_csc handle_csc(const spx_matrix* H) {
+    spx_csc c;
+    c.m = H->csr.m;
+    c.n = H->csr.n;
+    c.nnz = H->csr.nnz;
+    c.dtype = H->csr.dtype;
+    c.col_ptr = H->col_ptr;
+    c.row_idx = H->row_idx;
+    c.vals = H->vals_csc;
+    return c;
+}
+
+static Selector& global_selector() {
+    static Selector s = builtin_selector();
+    return s;
+}
+
+// ------------------------------------------------------------------ checks
+extern "C" spx_status spx_check_csr(const spx_csr* A) {
+    if (!A) return fail(SPX_ERR_ARG, "matrix descriptor is null");
+    if (!valid_dtype(A->dtype)) return fail(SPX_ERR_DTYPE, "unknown dtype");
+    if (A->m < 0 || A->n < 0 || A->nnz < 0) return fail(SPX_ERR_SHAPE, "negative matrix size");
+    if (!A->row_ptr) return fail(SPX_ERR_ARG, "row_ptr is null");
+    if (A->nnz > 0 && !A->col_idx) return fail(SPX_ERR_ARG, "col_idx is null");
+    if (A->nnz > 0 && A->dtype != SPX_BOOL && !A->vals) return fail(SPX_ERR_ARG, "vals is null");
+    return SPX_OK;
+}
+
+static spx_status check_csc(const spx_csc* A) {
+    if (!A) return fail(SPX_ERR_ARG, "matrix descriptor is null");
+    if (!valid_dtype(A->dtype)) return fail(SPX_ERR_DTYPE, "unknown dtype");
+    if (A->m < 0 || A->n < 0 || A->nnz < 0) return fail(SPX_ERR_SHAPE, "negative matrix size");
+    if (!A->col_ptr) return fail(SPX_ERR_ARG, "col_ptr is null");
+    if (A->nnz > 0 && !A->row_idx) return fail(SPX_ERR_ARG, "row_idx is null");
+    if (A->nnz > 0 && A->dtype != SPX_BOOL && !A->vals) return fail(SPX_ERR_ARG, "vals is null");
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_check_plan(const spx_plan* p, int32_t dtype) {
+    if (!p) return fail(SPX_ERR_ARG, "plan is null");
+    if (!valid_dtype(dtype)) return fail(SPX_ERR_DTYPE, "unknown dtype");
+    if (p->pattern < SPX_PAT_SPMV || p->pattern > SPX_PAT_CSC_SPMSPV) return fail(SPX_ERR_ARG, "bad pattern");
+    if (p->distribution != SPX_DIST_DIRECT && p->distribution != SPX_DIST_BALANCED)
+        return fail(SPX_ERR_ARG, "bad distribution");
+    if (p->pattern == SPX_PAT_CSC_SPMSPV) {
+        if (p->writeback < SPX_WB_ATOMIC || p->writeback > SPX_WB_BUCKET)
+            return fail(SPX_ERR_ARG, "column-major pattern needs a write-back");
+    } else if (p->writeback != SPX_WB_NONE) {
+        return fail(SPX_ERR_ARG, "row-major patterns take no write-back");
+    }
+    if (p->lanes != 0 && (p->lanes < 1 || p->lanes > 64 || (p->lanes & (p->lanes - 1))))
+        return fail(SPX_ERR_ARG, "lanes must be 0 or a power of two in [1, 64]");
+    if (p->bucket_rows != 0 && (p->bucket_rows < 64 || (p->bucket_rows & (p->bucket_rows - 1))))
+        return fail(SPX_ERR_ARG, "bucket_rows must be 0 or a power of two >= 64");
+    return SPX_OK;
+}
+
+extern "C" const char* spx_last_error(void) { return g_err.c_str(); }
+extern "C" const char* spx_version(void) { return SPX_VERSION; }
+
+// ------------------------------------------------------------------ workspace
+static size_t ws_for(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int32_t dtype, const spx_plan* p) {
+    size_t b = 0;
+    if (p->pattern == SPX_PAT_CSC_SPMSPV) {
+        b = spmspv_csc_ws(m, n, nnz, nnz_x, dtype, p);
+    } else {
+        b = spmv_csr_ws(m, nnz, p);
+        if (p->pattern == SPX_PAT_CSR_SPMSPV) {
+            Sizer z;
+            z.used = b;
+            z.take<uint32_t>((size_t)ceil_div(n, 32) + 1);
+            z.take<uint64_t>((size_t)n + 1);
+            b = z.used;
+        }
+    }
+    return b;
+}
+
+extern "C" size_t spx_workspace_size(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x_max, int32_t dtype,
+                                     const spx_plan* plan) {
+    if (!plan || spx_check_plan(plan, dtype) != SPX_OK || m < 0 || n < 0 || nnz < 0 || nnz_x_max < 0) return 0;
+    return ws_for(m, n, nnz, nnz_x_max, dtype, plan);
+}
+
+// ------------------------------------------------------------------ kernels by plan
+extern "C" spx_status spmv_csr(const spx_csr* A, const void* x, void* y, const spx_plan* plan, void* workspace,
+                               size_t ws_bytes, void* stream) {
+    SPX_TRY(spx_check_csr(A));
+    SPX_TRY(spx_check_plan(plan, A->dtype));
+    if (plan->pattern != SPX_PAT_SPMV) return fail(SPX_ERR_ARG, "spmv_csr needs pattern SPX_PAT_SPMV");
+    if ((A->n > 0 && !x) || (A->m > 0 && !y)) return fail(SPX_ERR_ARG, "x or y is null");
+    Arena ws(workspace, ws_bytes);
+    return launch_spmv_csr(A, x, nullptr, y, plan, ws, (hipStream_t)stream);
+}
+
+extern "C" spx_status spmspv_csr(const spx_csr* A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                                 void* y, const spx_plan* plan, void* workspace, size_t ws_bytes, void* stream) {
+    SPX_TRY(spx_check_csr(A));
+    SPX_TRY(spx_check_plan(plan, A->dtype));
+    if (plan->pattern != SPX_PAT_CSR_SPMSPV) return fail(SPX_ERR_ARG, "spmspv_csr needs pattern SPX_PAT_CSR_SPMSPV");
+    if (nnz_x < 0 || nnz_x > A->n) return fail(SPX_ERR_SHAPE, "nnz_x must be in [0, n]");
+    if (nnz_x > 0 && (!x_idx || (A->dtype != SPX_BOOL && !x_val))) return fail(SPX_ERR_ARG, "x arrays are null");
+    if (A->m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
+    hipStream_t s = (hipStream_t)stream;
+    Arena ws(workspace, ws_bytes);
+    // the kernel's own workspace first, conversion buffers after it
+    Arena probe = ws;
+    const size_t kern = spmv_csr_ws(A->m, A->nnz, plan);
+    probe.used = kern;
+    uint32_t* bits = probe.take<uint32_t>((size_t)ceil_div(A->n, 32) + 1);
+    void* xd = probe.take<uint64_t>((size_t)A->n + 1);
+    if (!bits || !xd) return fail(SPX_ERR_WORKSPACE, "spmspv_csr: workspace too small");
+    SPX_TRY(sparse_to_bitvector(A->n, nnz_x, x_idx, x_val, A->dtype, bits,
+                                A->dtype == SPX_BOOL ? nullptr : xd, s));
+    return launch_spmv_csr(A, A->dtype == SPX_BOOL ? nullptr : xd, bits, y, plan, ws, s);
+}
+
+extern "C" spx_status spmspv_csc(const spx_csc* A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                                 void* y, const spx_plan* plan, void* workspace, size_t ws_bytes, void* stream) {
+    SPX_TRY(check_csc(A));
+    SPX_TRY(spx_check_plan(plan, A->dtype));
+    if (plan->pattern != SPX_PAT_CSC_SPMSPV) return fail(SPX_ERR_ARG, "spmspv_csc needs pattern SPX_PAT_CSC_SPMSPV");
+    if (plan->writeback == SPX_WB_BUCKET)
+        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back needs the matrix handle (run_plan)");
+    if (nnz_x < 0 || nnz_x > A->n) return fail(SPX_ERR_SHAPE, "nnz_x must be in [0, n]");
+    if (nnz_x > 0 && (!x_idx || (A->dtype != SPX_BOOL && !x_val))) return fail(SPX_ERR_ARG, "x arrays are null");
+    if (A->m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
+    CscArgs a{A->m, A->n, A->nnz, A->dtype, A->col_ptr, A->row_idx, A->vals, nullptr, nullptr, -1};
+    Arena ws(workspace, ws_bytes);
+    return launch_spmspv_csc(a, nnz_x, x_idx, x_val, y, plan, ws, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ handle
+extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
+    if (!H) return SPX_OK;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(H->device);
+    void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->bits, H->xd, H->sp_idx,
+                    H->sp_val, H->scratch_i32, H->dev_scalars, H->bucket_cursor, H->ws};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    for (auto& e : H->ev_conv) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    for (auto& e : H->ev_kern) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    hipSetDevice(cur);
+    delete H;
+    return SPX_OK;
+}
+
+static spx_status build_csc(spx_matrix* H, hipStream_t s) {
+    const spx_csr& A = H->csr;
+    const int64_t nnz = A.nnz;
+    const int vs = value_size(A.dtype);
+    if (hipMalloc((void**)&H->col_ptr, ((size_t)A.n + 1) * 4) != hipSuccess ||
+        hipMalloc((void**)&H->row_idx, (size_t)std::max<int64_t>(nnz, 1) * 4) != hipSuccess ||
+        hipMalloc((void**)&H->perm, (size_t)std::max<int64_t>(nnz, 1) * 4) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "CSC allocation failed");
+    if (vs > 0 && hipMalloc(&H->vals_csc, (size_t)std::max<int64_t>(nnz, 1) * vs) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "CSC values allocation failed");
+    if (nnz == 0) return fill_u32((uint32_t*)H->col_ptr, 0u, (size_t)A.n + 1, s);
+    // stable radix sort of (column, CSR position): the permutation orders
+    // entries by column and, within a column, by row
+    uint32_t *keys = nullptr, *keys2 = nullptr, *vals2 = nullptr;
+    int32_t* rws = nullptr;
+    int32_t* rows = nullptr;
+    const size_t rw = radix_ws_elems(nnz);
+    if (hipMalloc((void**)&keys, nnz * 4) != hipSuccess || hipMalloc((void**)&keys2, nnz * 4) != hipSuccess ||
+        hipMalloc((void**)&vals2, nnz * 4) != hipSuccess || hipMalloc((void**)&rws, rw * 4) != hipSuccess ||
+        hipMalloc((void**)&rows, nnz * 4) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "transpose temporaries: allocation failed");
+    spx_status st = SPX_OK;
+    do {
+        if (hipMemcpyAsync(keys, A.col_idx, nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "copy col_idx");
+            break;
+        }
+        const int grid = (int)std::min<int64_t>(ceil_div(nnz, kBlock), 8192);
+        k_iota<<<grid, kBlock, 0, s>>>((uint32_t*)H->perm, nnz);
+        bool alt = false;
+        st = radix_sort_pairs(keys, (uint32_t*)H->perm, keys2, vals2, nnz, key_bits_for(A.n), rws, s, &alt);
+        if (st) break;
+        const uint32_t* sk = alt ? keys2 : keys;
+        if (alt && hipMemcpyAsync(H->perm, vals2, nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "copy perm");
+            break;
+        }
+        k_ptr_from_sorted<<<(unsigned)ceil_div(nnz + 1, kBlock), kBlock, 0, s>>>(sk, nnz, A.n, H->col_ptr);
+        st = expand_rows(A.row_ptr, A.m, rows, s);
+        if (st) break;
+        st = gather_perm(rows, H->perm, H->row_idx, nnz, 4, s);
+        if (st) break;
+        if (vs > 0) st = gather_perm(A.vals, H->perm, H->vals_csc, nnz, vs, s);
+        if (st) break;
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(SPX_ERR_HIP, "transpose sync");
+    } while (0);
+    hipFree(keys);
+    hipFree(keys2);
+    hipFree(vals2);
+    hipFree(rws);
+    hipFree(rows);
+    return st;
+}
+
+extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* stream, spx_matrix** out) {
+    if (!out) return fail(SPX_ERR_ARG, "out is null");
+    *out = nullptr;
+    SPX_TRY(spx_check_csr(A));
+    hipStream_t s = (hipStream_t)stream;
+    spx_matrix* H = new (std::nothrow) spx_matrix();
+    if (!H) return fail(SPX_ERR_ALLOC, "handle allocation failed");
+    H->csr = *A;
+    hipGetDevice(&H->device);
+    H->sel = global_selector();
+    spx_status st = SPX_OK;
+    if (flags & SPX_VALIDATE) {
+        uint32_t* bad = nullptr;
+        uint32_t hbad = 0;
+        if (hipMalloc((void**)&bad, 4) != hipSuccess) {
+            spx_matrix_destroy(H);
+            return fail(SPX_ERR_ALLOC, "validation flag");
+        }
+        fill_u32(bad, 0, 1, s);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(std::max(A->nnz, A->m + 1), kBlock), 4096));
+        k_validate_csr<<<grid, kBlock, 0, s>>>(A->row_ptr, A->m, A->col_idx, A->nnz, A->n, bad);
+        hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        hipFree(bad);
+        if (hbad) {
+            spx_matrix_destroy(H);
+            return fail(hbad & 1 ? SPX_ERR_SHAPE : SPX_ERR_INDEX,
+                        hbad & 1 ? "row_ptr is not a valid CSR row pointer" : "a column index is out of range");
+        }
+    }
+    st = build_csc(H, s);
+    if (st == SPX_OK) {
+        MatrixStats ms;
+        st = matrix_features_device(A->row_ptr, A->m, A->n, &ms, s);
+        if (st == SPX_OK) std::memcpy(H->feat, ms.f, sizeof(H->feat));
+    }
+    if (st != SPX_OK) {
+        std::string keep = g_err;
+        spx_matrix_destroy(H);
+        g_err = keep;
+        return st;
+    }
+    *out = H;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_csc(const spx_matrix* H, spx_csc* out) {
+    if (!H || !out) return fail(SPX_ERR_ARG, "null argument");
+    *out = handle_csc(H);
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
+    if (!H) return fail(SPX_ERR_ARG, "handle is null");
+    const int vs = value_size(H->csr.dtype);
+    if (vs == 0 || H->csr.nnz == 0) return SPX_OK;
+    return gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream);
+}
+
+extern "C" spx_status spx_matrix_features(const spx_matrix* H, double* out9) {
+    if (!H || !out9) return fail(SPX_ERR_ARG, "null argument");
+    std::memcpy(out9, H->feat, sizeof(H->feat));
+    return SPX_OK;
+}
+
+static spx_status check_vec(const spx_matrix* H, const spx_vec* x) {
+    if (!x) return fail(SPX_ERR_ARG, "vector descriptor is null");
+    if (x->n != H->csr.n) return fail(SPX_ERR_SHAPE, "vector length differs from n");
+    if (x->kind == SPX_VEC_DENSE) {
+        if (x->n > 0 && !x->val) return fail(SPX_ERR_ARG, "dense x is null");
+    } else if (x->kind == SPX_VEC_SPARSE) {
+        if (x->nnz_x < 0 || x->nnz_x > x->n) return fail(SPX_ERR_SHAPE, "nnz_x must be in [0, n]");
+        if (x->nnz_x > 0 && (!x->idx || (H->csr.dtype != SPX_BOOL && !x->val)))
+            return fail(SPX_ERR_ARG, "sparse x arrays are null");
+    } else {
+        return fail(SPX_ERR_ARG, "unknown vector kind");
+    }
+    return SPX_OK;
+}
+
+// device reduction for nnz_s (and nnz_x of a dense x); synchronizes
+static spx_status device_vector_counts(spx_matrix* H, const spx_vec* x, hipStream_t s, int64_t* nnz_s,
+                                       int64_t* nnz_x) {
+    SPX_TRY(ensure_conv(H));
+    SPX_TRY(vector_features_device(H->col_ptr, H->csr.n, x, H->csr.dtype, H->dev_scalars, s));
+    int64_t h[2] = {0, 0};
+    SPX_HIP(hipMemcpyAsync(h, H->dev_scalars, sizeof(h), hipMemcpyDeviceToHost, s));
+    SPX_HIP(hipStreamSynchronize(s));
+    *nnz_s = h[0];
+    *nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : h[1];
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_vector_features(spx_matrix* H, const spx_vec* x, double* out4, void* stream) {
+    if (!H || !out4) return fail(SPX_ERR_ARG, "null argument");
+    SPX_TRY(check_vec(H, x));
+    int64_t ns = 0, nx = 0;
+    SPX_TRY(device_vector_counts(H, x, (hipStream_t)stream, &ns, &nx));
+    out4[0] = (double)nx;
+    out4[1] = H->csr.n > 0 ? (double)nx / H->csr.n : 0.0;
+    out4[2] = (double)ns;
+    out4[3] = H->csr.nnz > 0 ? (double)ns / H->csr.nnz : 0.0;
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ selection
+struct LazyFeatures {
+    spx_matrix* H;
+    const spx_vec* x;
+    hipStream_t s;
+    bool no_sync;
+    bool have_counts = false;
+    int64_t nnz_s = -1, nnz_x = -1;
+    bool synced = false;
+    double get(int f) {
+        const double* mf = H->feat;
+        switch (f) {
+            case F_M:
+            case F_N:
+            case F_NNZ:
+            case F_MAX_ROW:
+            case F_MIN_ROW:
+            case F_AVG_ROW:
+            case F_REL_RANGE:
+            case F_VAR_ROW:
+            case F_GINI:
+                return mf[f];
+            case F_NNZ_X:
+                return (double)nx();
+            case F_X_SPARSITY:
+                return H->csr.n > 0 ? (double)nx() / H->csr.n : 0.0;
+            case F_NNZ_S:
+                return (double)ns();
+            case F_M_SPARSITY:
+                return H->csr.nnz > 0 ? (double)ns() / H->csr.nnz : 0.0;
+        }
+        return 0.0;
+    }
+    void counts() {
+        if (have_counts) return;
+        have_counts = true;
+        if (no_sync) {
+            // host-known fallback: a dense x counts as full, nnz_s is
+            // estimated from the average column length
+            nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : H->csr.n;
+            nnz_s = H->csr.n > 0 ? (int64_t)((double)H->csr.nnz / H->csr.n * nnz_x) : 0;
+            return;
+        }
+        if (device_vector_counts(H, x, s, &nnz_s, &nnz_x) != SPX_OK) {
+            nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : H->csr.n;
+            nnz_s = H->csr.nnz;
+        }
+        synced = true;
+    }
+    int64_t nx() {
+        if (x->kind == SPX_VEC_SPARSE) return x->nnz_x;
+        counts();
+        return nnz_x;
+    }
+    int64_t ns() {
+        counts();
+        return nnz_s;
+    }
+};
+
+static spx_status select_impl(spx_matrix* H, const spx_vec* x, uint32_t flags, spx_plan* out, LazyFeatures& lf) {
+    const Selector& S = H->sel;
+    auto f = [&](int id) { return lf.get(id); };
+    spx_plan p{};
+    p.pattern = S.pattern.eval(f);
+    if (p.pattern < 0 || p.pattern > 2) p.pattern = SPX_PAT_SPMV;
+    p.distribution = S.distribution[p.pattern].eval(f);
+    if (p.distribution != SPX_DIST_BALANCED) p.distribution = SPX_DIST_DIRECT;
+    p.writeback = SPX_WB_NONE;
+    if (p.pattern == SPX_PAT_CSC_SPMSPV) {
+        p.writeback = S.writeback.eval(f);
+        if (p.writeback < SPX_WB_ATOMIC || p.writeback > SPX_WB_BUCKET) p.writeback = SPX_WB_ATOMIC;
+        if (p.writeback == SPX_WB_LDS_ATOMIC &&
+            (int64_t)H->csr.m * std::max(4, value_size(H->csr.dtype)) > 65536)
+            p.writeback = SPX_WB_SORT;
+        if (p.writeback == SPX_WB_BUCKET) p.writeback = SPX_WB_SORT;  // until bucket lands
+    }
+    (void)flags;
+    *out = p;
+    return SPX_OK;
+}
+
+extern "C" spx_status select_kernel(spx_matrix* H, const spx_vec* x, uint32_t flags, spx_plan* out, void* stream) {
+    if (!H || !out) return fail(SPX_ERR_ARG, "null argument");
+    SPX_TRY(check_vec(H, x));
+    LazyFeatures lf{H, x, (hipStream_t)stream, (flags & SPX_NO_SYNC) != 0};
+    return select_impl(H, x, flags, out, lf);
+}
+
+extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
+    Selector s;
+    if (!json_path) {
+        s = builtin_selector();
+    } else {
+        std::ifstream in(json_path);
+        if (!in) return fail(SPX_ERR_ARG, std::string("cannot open selector file ") + json_path);
+        std::stringstream ss;
+        ss << in.rdbuf();
+        std::string err;
+        if (!parse_selector_json(ss.str(), &s, &err)) return fail(SPX_ERR_ARG, "selector: " + err);
+    }
+    global_selector() = s;
+    if (H) H->sel = s;
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ execution
+static void record(spx_matrix* H, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, bool start, hipStream_t s) {
+    if (!H->profiling) return;
+    if (start) {
+        hipEvent_t a, b;
+        hipEventCreate(&a);
+        hipEventCreate(&b);
+        v.emplace_back(a, b);
+        hipEventRecord(a, s);
+    } else {
+        hipEventRecord(v.back().second, s);
+    }
+}
+
+// Executes plan p for x. nnz_s_hint: exact nnz_s if known (else -1).
+static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_plan* p, int64_t nnz_s_hint,
+                            int64_t nnz_x_known, hipStream_t s) {
+    const spx_csr& A = H->csr;
+    const int dt = A.dtype;
+    SPX_TRY(spx_check_plan(p, dt));
+    SPX_TRY(ensure_conv(H));
+    if (p->pattern == SPX_PAT_SPMV) {
+        const void* xd = x->val;
+        if (x->kind == SPX_VEC_SPARSE) {
+            record(H, H->ev_conv, true, s);
+            SPX_TRY(sparse_to_dense(A.n, x->nnz_x, x->idx, x->val, dt, H->xd, s));
+            record(H, H->ev_conv, false, s);
+            xd = H->xd;
+        }
+        SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
+        Arena ws(H->ws, H->ws_bytes);
+        record(H, H->ev_kern, true, s);
+        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, ws, s));
+        record(H, H->ev_kern, false, s);
+        return SPX_OK;
+    }
+    if (p->pattern == SPX_PAT_CSR_SPMSPV) {
+        const void* xd = nullptr;
+        record(H, H->ev_conv, true, s);
+        if (x->kind == SPX_VEC_SPARSE) {
+            SPX_TRY(sparse_to_bitvector(A.n, x->nnz_x, x->idx, x->val, dt, H->bits, dt == SPX_BOOL ? nullptr : H->xd, s));
+            xd = dt == SPX_BOOL ? nullptr : H->xd;
+        } else {
+            const unsigned g = (unsigned)std::max<int64_t>(1, ceil_div(ceil_div(A.n, 32), kBlock));
+            switch (dt) {
+                case SPX_F32: k_dense_bits<SPX_F32><<<g, kBlock, 0, s>>>(A.n, (const float*)x->val, H->bits); break;
+                case SPX_F64: k_dense_bits<SPX_F64><<<g, kBlock, 0, s>>>(A.n, (const double*)x->val, H->bits); break;
+                case SPX_I32: k_dense_bits<SPX_I32><<<g, kBlock, 0, s>>>(A.n, (const int32_t*)x->val, H->bits); break;
+                case SPX_BOOL: k_dense_bits<SPX_BOOL><<<g, kBlock, 0, s>>>(A.n, (const uint8_t*)x->val, H->bits); break;
+            }
+            SPX_HIP(hipGetLastError());
+            xd = dt == SPX_BOOL ? nullptr : x->val;
+        }
+        record(H, H->ev_conv, false, s);
+        SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
+        Arena ws(H->ws, H->ws_bytes);
+        record(H, H->ev_kern, true, s);
+        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, ws, s));
+        record(H, H->ev_kern, false, s);
+        return SPX_OK;
+    }
+    // column-major: needs (idx, val)
+    int32_t nnz_x = x->nnz_x;
+    const int32_t* idx = x->idx;
+    const void* val = x->val;
+    if (x->kind == SPX_VEC_DENSE) {
+        record(H, H->ev_conv, true, s);
+        SPX_TRY(dense_to_sparse(A.n, x->val, dt, H->sp_idx, dt == SPX_BOOL ? nullptr : H->sp_val,
+                                (int32_t*)(H->dev_scalars + 2), H->scratch_i32, s));
+        record(H, H->ev_conv, false, s);
+        if (nnz_x_known < 0) {
+            int32_t h = 0;
+            SPX_HIP(hipMemcpyAsync(&h, H->dev_scalars + 2, 4, hipMemcpyDeviceToHost, s));
+            SPX_HIP(hipStreamSynchronize(s));
+            nnz_x_known = h;
+        }
+        nnz_x = (int32_t)nnz_x_known;
+        idx = H->sp_idx;
+        val = H->sp_val;
+    }
+    SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, nnz_x, dt, p)));
+    Arena ws(H->ws, H->ws_bytes);
+    CscArgs a{A.m, A.n, A.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc, A.row_ptr, H->bucket_cursor, nnz_s_hint};
+    record(H, H->ev_kern, true, s);
+    SPX_TRY(launch_spmspv_csc(a, nnz_x, idx, val, y, p, ws, s));
+    record(H, H->ev_kern, false, s);
+    return SPX_OK;
+}
+
+extern "C" spx_status run(spx_matrix* H, const spx_vec* x, void* y, void* stream) {
+    if (!H) return fail(SPX_ERR_ARG, "handle is null");
+    SPX_TRY(check_vec(H, x));
+    if (H->csr.m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    LazyFeatures lf{H, x, s, false};
+    spx_plan p;
+    SPX_TRY(select_impl(H, x, 0, &p, lf));
+    auto t1 = std::chrono::steady_clock::now();
+    if (H->profiling) H->host_ms[1] += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    H->last_plan = p;
+    return exec_plan(H, x, y, &p, lf.have_counts && lf.synced ? lf.nnz_s : -1,
+                     lf.have_counts && lf.synced ? lf.nnz_x : -1, s);
+}
+
+extern "C" spx_status run_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_plan* plan, void* stream) {
+    if (!H || !plan) return fail(SPX_ERR_ARG, "null argument");
+    SPX_TRY(check_vec(H, x));
+    if (H->csr.m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
+    if (plan->pattern == SPX_PAT_CSC_SPMSPV && plan->writeback == SPX_WB_BUCKET)
+        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back is not built yet");
+    H->last_plan = *plan;
+    return exec_plan(H, x, y, plan, -1, -1, (hipStream_t)stream);
+}
+
+extern "C" spx_status spx_last_plan(const spx_matrix* H, spx_plan* out) {
+    if (!H || !out) return fail(SPX_ERR_ARG, "null argument");
+    *out = H->last_plan;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_set_profiling(spx_matrix* H, int32_t on) {
+    if (!H) return fail(SPX_ERR_ARG, "handle is null");
+    H->profiling = on ? 1 : 0;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_stage_times(const spx_matrix* Hc, double* out4) {
+    if (!Hc || !out4) return fail(SPX_ERR_ARG, "null argument");
+    spx_matrix* H = const_cast<spx_matrix*>(Hc);
+    auto sum = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+        double t = 0;
+        for (auto& e : v) {
+            float ms = 0;
+            hipEventSynchronize(e.second);
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) t += ms;
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        v.clear();
+        return t;
+    };
+    out4[0] = H->host_ms[0];
+    out4[1] = H->host_ms[1];
+    out4[2] = sum(H->ev_conv);
+    out4[3] = sum(H->ev_kern);
+    H->host_ms[0] = H->host_ms[1] = 0;
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ batch (device-side selection)
+extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, const int32_t* vec_ptr,
+                                const int32_t* idx, const void* val, void* Y, void* stream) {
+    (void)H; (void)B; (void)total_nnz_x; (void)vec_ptr; (void)idx; (void)val; (void)Y; (void)stream;
+    return fail(SPX_ERR_UNSUPPORTED, "run_batch is not built yet");
+}
+
+// ------------------------------------------------------------------ backward
+extern "C" spx_status spmv_csr_transpose(spx_matrix* H, int32_t B, const void* G, void* dX, void* stream) {
+    if (!H || (B > 0 && (!G || !dX))) return fail(SPX_ERR_ARG, "null argument");
+    if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    const int dt = H->csr.dtype;
+    if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "backward supports F32 and F64");
+    hipStream_t s = (hipStream_t)stream;
+    // A^T in CSR form is the handle's CSC: rows of A^T = columns of A
+    spx_csr At{H->csr.n, H->csr.m, H->csr.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc};
+    spx_plan p{SPX_PAT_SPMV, SPX_DIST_DIRECT, SPX_WB_NONE, 0, 0, 0};
+    if (H->feat[3] > 16 * std::max(1.0, H->feat[5])) p.distribution = SPX_DIST_BALANCED;
+    SPX_TRY(ensure_ws(H, ws_for(At.m, At.n, At.nnz, 0, dt, &p)));
+    const int vs = value_size(dt);
+    for (int32_t b = 0; b < B; ++b) {
+        Arena ws(H->ws, H->ws_bytes);
+        SPX_TRY(launch_spmv_csr(&At, (const char*)G + (size_t)b * H->csr.m * vs, nullptr,
+                                (char*)dX + (size_t)b * H->csr.n * vs, &p, ws, s));
+    }
+    return SPX_OK;
+}
+
+extern "C" spx_status dvals_pattern(spx_matrix* H, int32_t B, const void* G, const void* X, void* dvals,
+                                    void* stream) {
+    if (!H || (B > 0 && (!G || !X)) || (H->csr.nnz > 0 && !dvals)) return fail(SPX_ERR_ARG, "null argument");
+    if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    const int dt = H->csr.dtype;
+    if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "backward supports F32 and F64");
+    return launch_dvals(H->csr.row_ptr, H->csr.col_idx, H->csr.m, H->csr.n, H->csr.nnz, dt, B, G, X, dvals,
+                        (hipStream_t)stream);
+}

@@ -1,0 +1,129 @@
+// Host-side launchers shared between the translation units of libspx.
+// Not part of the public ABI (include/spx.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/spx.h"
+
+namespace spx {
+
+// Thread-local error message; returns code so call sites can `return fail(...)`.
+spx_status fail(spx_status code, const std::string& msg);
+spx_status hip_fail(hipError_t e, const char* what);
+
+#define SPX_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+#define SPX_TRY(call)                     \
+    do {                                  \
+        spx_status s_ = (call);           \
+        if (s_ != SPX_OK) return s_;      \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int value_size(int dtype);  // bytes per A / x value (0 for BOOL)
+int out_size(int dtype);    // bytes per y element (1 for BOOL)
+
+// Bump allocator over a caller-provided workspace.
+struct Arena {
+    char* base;
+    size_t size;
+    size_t used = 0;
+    Arena(void* b, size_t s) : base((char*)b), size(s) {}
+    template <typename T>
+    T* take(size_t count) {
+        size_t off = align_up(used, 256);
+        size_t need = off + align_up(count * sizeof(T), 256);
+        if (!base || need > size) return nullptr;
+        used = need;
+        return (T*)(base + off);
+    }
+};
+// Sizing twin of Arena: counts what a sequence of take() calls needs.
+struct Sizer {
+    size_t used = 0;
+    template <typename T>
+    void take(size_t count) {
+        used = align_up(used, 256) + align_up(count * sizeof(T), 256);
+    }
+};
+
+// ----------------------------------------------------------------- primitives
+spx_status fill_bytes(void* p, uint8_t v, size_t bytes, hipStream_t s);
+spx_status fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+
+// Exclusive scan of n int32 (in may equal out). Writes the total to
+// *total_dev if not null. Workspace: scan_ws_elems(n) int32.
+size_t scan_ws_elems(int64_t n);
+spx_status scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev,
+                              int32_t* ws, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits
+// of the key. keys/vals are sorted in place using the alternate buffers.
+size_t radix_ws_elems(int64_t n);
+spx_status radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int bits, int32_t* ws,
+                            hipStream_t s, bool* result_in_alt);
+
+// row id of every CSR position
+spx_status expand_rows(const int32_t* row_ptr, int32_t m, int32_t* rows_out, hipStream_t s);
+// out[p] = in[perm[p]] for element size esize (4 or 8)
+spx_status gather_perm(const void* in, const int32_t* perm, void* out, int64_t n, int esize,
+                       hipStream_t s);
+
+// ------------------------------------------------------------------ kernels
+spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
+                           const spx_plan* plan, Arena& ws, hipStream_t s);
+size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan);
+
+struct CscArgs {
+    int32_t m, n, nnz, dtype;
+    const int32_t* col_ptr;
+    const int32_t* row_idx;
+    const void* vals;
+    const int32_t* row_ptr;  // CSR row pointer of the same matrix (bucket layout); may be null
+    uint32_t* bucket_cursor; // handle-owned, zero between calls; may be null
+    int64_t nnz_s_hint;      // exact nnz_s if the host knows it, else -1
+};
+spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx,
+                             const void* x_val, void* y, const spx_plan* plan, Arena& ws,
+                             hipStream_t s);
+size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype,
+                     const spx_plan* plan);
+
+// sparse x -> bitvector of supp(x) (cleared first) + scattered values xd[n]
+spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                               int dtype, uint32_t* bits, void* xd, hipStream_t s);
+// sparse x -> zero-filled dense x
+spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                           int dtype, void* xd, hipStream_t s);
+// dense x -> (idx, val) of its nonzeros in index order; count to *nnz_dev
+size_t compact_ws_elems(int32_t n);
+spx_status dense_to_sparse(int32_t n, const void* x, int dtype, int32_t* idx, void* val,
+                           int32_t* nnz_dev, int32_t* ws, hipStream_t s);
+
+// features
+struct MatrixStats {
+    double f[9];
+};
+spx_status matrix_features_device(const int32_t* row_ptr, int32_t m, int32_t n,
+                                  MatrixStats* out, hipStream_t s);
+// nnz_s (and nnz_x for a dense x) on the device into out2[0..1] (int64)
+spx_status vector_features_device(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,
+                                  int64_t* out2_dev, hipStream_t s);
+
+// backward
+spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n,
+                        int32_t nnz, int dtype, int32_t B, const void* G, const void* X,
+                        void* dvals, hipStream_t s);
+
+}  // namespace spx

@@ -1,0 +1,66 @@
+// Decision-tree kernel selector (Section 5 and Section 6.2-6.3).
+//
+// Three models are evaluated as a cascade: the computing-pattern tree, then
+// the workload-distribution tree of the chosen pattern, then (column-major
+// pattern only) the write-back tree. Features (Table 1) are produced lazily
+// through a callback, so a tree that decides on m, n, nnz or nnz_x never
+// triggers the device reduction behind nnz_s.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace spx {
+
+// Feature ids, in the order of Table 1.
+enum Feature {
+    F_M = 0,
+    F_N,
+    F_NNZ,
+    F_MAX_ROW,
+    F_MIN_ROW,
+    F_AVG_ROW,
+    F_REL_RANGE,
+    F_VAR_ROW,
+    F_GINI,
+    F_NNZ_X,
+    F_X_SPARSITY,
+    F_NNZ_S,
+    F_M_SPARSITY,
+    F_COUNT
+};
+
+const char* feature_name(int f);
+int feature_id(const std::string& name);
+
+// A binary tree in flat arrays; node i is a leaf when cls[i] >= 0.
+// Internal nodes: go left when feature value <= thr.
+struct Tree {
+    std::vector<int32_t> feat, left, right, cls;
+    std::vector<double> thr;
+    bool empty() const { return cls.empty(); }
+    template <typename FeatFn>
+    int eval(FeatFn&& f) const {
+        int i = 0;
+        for (int guard = 0; guard < 64; ++guard) {
+            if (cls[i] >= 0) return cls[i];
+            i = f(feat[i]) <= thr[i] ? left[i] : right[i];
+        }
+        return cls[i] >= 0 ? cls[i] : 0;
+    }
+};
+
+struct Selector {
+    Tree pattern;          // classes: spx_pattern
+    Tree distribution[3];  // per pattern; classes: spx_distribution
+    Tree writeback;        // classes: spx_writeback
+    std::string source = "builtin";
+};
+
+Selector builtin_selector();
+// Parses the tuner's JSON. Returns false with a message on error.
+bool parse_selector_json(const std::string& text, Selector* out, std::string* err);
+
+}  // namespace spx

@@ -1,0 +1,558 @@
+// Column-major, vector-driven SpMSpV (Section 4.1): for every entry (j, v)
+// of the sparse x, column j of A is scaled by v and written back into y.
+// Only effective nonzeros are read. Distributions (Section 4.2.1):
+//
+//  * direct   - a group of L lanes per x entry walks that column.
+//  * balanced - merge-path tiles over (x entries + effective nonzeros): the
+//               column lengths of supp(x) are prefix-summed, and every
+//               workgroup takes kTile merge items, so a hub column is split
+//               across workgroups and empty columns cost one item each.
+//
+// Write-backs (Section 4.2.2):
+//  * atomic     - y is zero-filled, every product is added with a hardware
+//                 atomic (global_atomic_add_f32/f64, integer add for I32,
+//                 a plain byte store of 1 for BOOL since OR is idempotent).
+//  * lds-atomic - each workgroup accumulates into its own copy of y in LDS
+//                 and flushes the rows it touched with one atomic each
+//                 (only when y fits in LDS).
+//  * sort       - (row, value) pairs go to global memory at their prefix
+//                 position, a stable radix sort orders them by row, and a
+//                 reduce-by-key writes each row once; only runs that cross a
+//                 tile boundary use an atomic.
+//  * bucket     - see spmspv_bucket.hip.
+#include <algorithm>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace spx {
+
+constexpr int kCscIpt = 8;
+constexpr int kCscTile = kBlock * kCscIpt;
+constexpr int kLdsBytes = 65536;  // LDS budget of the privatized y copy
+
+template <int DT>
+struct EmitAtomic {
+    typename SR<DT>::Y* y;
+    __device__ void operator()(int r, typename SR<DT>::Acc v, int64_t) const {
+        SR<DT>::atomic_add(&y[r], v);
+    }
+};
+
+template <int DT>
+struct EmitLds {
+    typename SR<DT>::Acc* sy;
+    __device__ void operator()(int r, typename SR<DT>::Acc v, int64_t) const {
+        SR<DT>::lds_atomic_add(&sy[r], v);
+    }
+};
+
+// pair at its global prefix position p; values stored as raw bits (4 bytes)
+// or, for 8-byte values, in a separate array indexed by p
+template <int DT>
+struct EmitPairs {
+    uint32_t* keys;
+    uint32_t* vbits;                 // 4-byte value types (and BOOL: unused)
+    typename SR<DT>::Acc* vwide;     // 8-byte value types
+    __device__ void operator()(int r, typename SR<DT>::Acc v, int64_t p) const {
+        keys[p] = (uint32_t)r;
+        if constexpr (sizeof(typename SR<DT>::Acc) == 8) {
+            vbits[p] = (uint32_t)p;
+            vwide[p] = v;
+        } else {
+            uint32_t b;
+            __builtin_memcpy(&b, &v, 4);
+            vbits[p] = b;
+        }
+    }
+};
+
+// --------------------------------------------------------------- direct
+// excl (optional) gives each entry's prefix position for pair emission.
+template <int DT, int L, typename Emit>
+__device__ __forceinline__ void csc_direct_entry(int e, int g, const int32_t* __restrict__ x_idx,
+                                                 const typename SR<DT>::X* __restrict__ x_val,
+                                                 const int32_t* __restrict__ col_ptr,
+                                                 const int32_t* __restrict__ row_idx,
+                                                 const typename SR<DT>::V* __restrict__ vals,
+                                                 const int32_t* __restrict__ excl, const Emit& emit) {
+    using S = SR<DT>;
+    const int j = x_idx[e];
+    const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
+    const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
+    const int64_t pbase = excl ? (int64_t)excl[e] - c0 : 0;
+    int k = c0 + g;
+    for (; k + 3 * L < c1; k += 4 * L) {
+        int r[4];
+        typename S::V a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r[u] = row_idx[k + u * L];
+            a[u] = S::val(vals, k + u * L);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) emit(r[u], S::mul(a[u], v), pbase + k + u * L);
+    }
+    for (; k < c1; k += L) emit(row_idx[k], S::mul(S::val(vals, k), v), pbase + k);
+}
+
+template <int DT, int L>
+__global__ __launch_bounds__(kBlock) void k_csc_direct_atomic(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                              const typename SR<DT>::X* __restrict__ x_val,
+                                                              const int32_t* __restrict__ col_ptr,
+                                                              const int32_t* __restrict__ row_idx,
+                                                              const typename SR<DT>::V* __restrict__ vals,
+                                                              typename SR<DT>::Y* __restrict__ y) {
+    const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
+    if (e >= nnz_x) return;
+    csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, nullptr,
+                            EmitAtomic<DT>{y});
+}
+
+template <int DT, int L>
+__global__ __launch_bounds__(kBlock) void k_csc_direct_pairs(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                             const typename SR<DT>::X* __restrict__ x_val,
+                                                             const int32_t* __restrict__ col_ptr,
+                                                             const int32_t* __restrict__ row_idx,
+                                                             const typename SR<DT>::V* __restrict__ vals,
+                                                             const int32_t* __restrict__ excl,
+                                                             EmitPairs<DT> emit) {
+    const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
+    if (e >= nnz_x) return;
+    csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, excl, emit);
+}
+
+// privatized: grid-stride over entries, y copy in LDS, flush touched rows
+template <int DT, int L>
+__global__ __launch_bounds__(kBlock) void k_csc_direct_lds(int32_t m, int32_t nnz_x,
+                                                           const int32_t* __restrict__ x_idx,
+                                                           const typename SR<DT>::X* __restrict__ x_val,
+                                                           const int32_t* __restrict__ col_ptr,
+                                                           const int32_t* __restrict__ row_idx,
+                                                           const typename SR<DT>::V* __restrict__ vals,
+                                                           typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    extern __shared__ char s_raw[];
+    auto* sy = (typename S::Acc*)s_raw;
+    for (int r = threadIdx.x; r < m; r += kBlock) sy[r] = S::zero();
+    __syncthreads();
+    const int groups = kBlock / L;
+    for (int64_t e = (int64_t)blockIdx.x * groups + threadIdx.x / L; e < nnz_x;
+         e += (int64_t)gridDim.x * groups)
+        csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, nullptr,
+                                EmitLds<DT>{sy});
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += kBlock) {
+        const typename S::Acc v = sy[r];
+        if (S::nonzero(v)) S::atomic_add(&y[r], v);
+    }
+}
+
+// --------------------------------------------------------------- prefix of lengths
+__global__ __launch_bounds__(kBlock) void k_x_lengths(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                      const int32_t* __restrict__ col_ptr,
+                                                      int32_t* __restrict__ len) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e > nnz_x) return;
+    if (e == nnz_x) {
+        len[e] = 0;
+        return;
+    }
+    const int j = x_idx[e];
+    len[e] = col_ptr[j + 1] - col_ptr[j];
+}
+
+// --------------------------------------------------------------- balanced
+// excl[0..nnz_x]: exclusive prefix of the selected column lengths (excl[nnz_x]
+// = nnz_s). Tiles are taken grid-stride until the merge length is covered.
+template <int DT, typename Emit>
+__device__ __forceinline__ void csc_merge_tile(int64_t tile, int32_t nnz_x, int64_t nnz_s,
+                                               const int32_t* __restrict__ x_idx,
+                                               const typename SR<DT>::X* __restrict__ x_val,
+                                               const int32_t* __restrict__ col_ptr,
+                                               const int32_t* __restrict__ row_idx,
+                                               const typename SR<DT>::V* __restrict__ vals,
+                                               const int32_t* __restrict__ excl, const Emit& emit,
+                                               int32_t* s_excl, int32_t* s_cs,
+                                               typename SR<DT>::X* s_v, int32_t* s_bound) {
+    using S = SR<DT>;
+    const int64_t total = (int64_t)nnz_x + nnz_s;
+    const int64_t d0 = tile * kCscTile;
+    const int64_t d1 = std::min<int64_t>(d0 + kCscTile, total);
+    auto ends = [&](int e) { return excl[e + 1]; };
+    if (wave_id() < 2) {
+        const int64_t d = wave_id() == 0 ? d0 : d1;
+        const int e = merge_search_wave(ends, nnz_x, d);
+        if (lane_id() == 0) {
+            s_bound[wave_id() * 2 + 0] = e;
+            s_bound[wave_id() * 2 + 1] = (int)(d - e);
+        }
+    }
+    __syncthreads();
+    const int e0 = s_bound[0], p0 = s_bound[1], e1 = s_bound[2], p1 = s_bound[3];
+    const int ecount = std::min(e1, nnz_x - 1) - e0 + 1;  // entries touched (>= 1 when p1 > p0)
+    for (int u = threadIdx.x; u < ecount; u += kBlock) {
+        const int e = e0 + u;
+        s_excl[u] = excl[e];
+        s_cs[u] = col_ptr[x_idx[e]];
+        s_v[u] = S::kVals ? x_val[e] : (typename S::X)1;
+    }
+    __syncthreads();
+    for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        // last staged entry whose prefix start is <= p
+        int lo = 0, hi = ecount - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_excl[mid] <= p)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int k = s_cs[lo] + (p - s_excl[lo]);
+        emit(row_idx[k], S::mul(S::val(vals, k), s_v[lo]), p);
+    }
+    __syncthreads();
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_csc_merge_atomic(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                             const typename SR<DT>::X* __restrict__ x_val,
+                                                             const int32_t* __restrict__ col_ptr,
+                                                             const int32_t* __restrict__ row_idx,
+                                                             const typename SR<DT>::V* __restrict__ vals,
+                                                             const int32_t* __restrict__ excl,
+                                                             typename SR<DT>::Y* __restrict__ y) {
+    __shared__ int32_t s_excl[kCscTile + 1];
+    __shared__ int32_t s_cs[kCscTile + 1];
+    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
+    __shared__ int32_t s_bound[4];
+    const int64_t nnz_s = excl[nnz_x];
+    const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitAtomic<DT>{y},
+                           s_excl, s_cs, s_v, s_bound);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_csc_merge_pairs(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                            const typename SR<DT>::X* __restrict__ x_val,
+                                                            const int32_t* __restrict__ col_ptr,
+                                                            const int32_t* __restrict__ row_idx,
+                                                            const typename SR<DT>::V* __restrict__ vals,
+                                                            const int32_t* __restrict__ excl,
+                                                            EmitPairs<DT> emit) {
+    __shared__ int32_t s_excl[kCscTile + 1];
+    __shared__ int32_t s_cs[kCscTile + 1];
+    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
+    __shared__ int32_t s_bound[4];
+    const int64_t nnz_s = excl[nnz_x];
+    const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, emit, s_excl, s_cs,
+                           s_v, s_bound);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz_x,
+                                                          const int32_t* __restrict__ x_idx,
+                                                          const typename SR<DT>::X* __restrict__ x_val,
+                                                          const int32_t* __restrict__ col_ptr,
+                                                          const int32_t* __restrict__ row_idx,
+                                                          const typename SR<DT>::V* __restrict__ vals,
+                                                          const int32_t* __restrict__ excl,
+                                                          typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    __shared__ int32_t s_excl[kCscTile + 1];
+    __shared__ int32_t s_cs[kCscTile + 1];
+    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
+    __shared__ int32_t s_bound[4];
+    extern __shared__ char s_raw[];
+    auto* sy = (typename S::Acc*)s_raw;
+    for (int r = threadIdx.x; r < m; r += kBlock) sy[r] = S::zero();
+    __syncthreads();
+    const int64_t nnz_s = excl[nnz_x];
+    const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitLds<DT>{sy},
+                           s_excl, s_cs, s_v, s_bound);
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += kBlock) {
+        const typename S::Acc v = sy[r];
+        if (S::nonzero(v)) S::atomic_add(&y[r], v);
+    }
+}
+
+// --------------------------------------------------------------- reduce by key
+// Sorted (row, value) pairs -> y. Tiles of kCscTile pairs; each thread sums
+// kCscIpt consecutive pairs by run, a segmented scan over threads joins
+// runs that cross threads, and each run is stored once. Runs that continue
+// into a neighbouring tile are added atomically (y was zero-filled).
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_reduce_by_key(int64_t n, const uint32_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ vbits,
+                                                          const typename SR<DT>::Acc* __restrict__ vwide,
+                                                          typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    __shared__ uint32_t s_k[kCscTile + 2];
+    __shared__ Acc s_val[kCscTile];
+    __shared__ int32_t s_flag[kBlock];
+    __shared__ Acc s_cv[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kCscTile;
+    const int cnt = (int)std::min<int64_t>(kCscTile, n - base);
+    // s_k[0] = key before the tile (or ~0), s_k[1 + i] = tile keys, s_k[1 + cnt] = key after
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+        const uint32_t kk = keys[base + i];
+        s_k[1 + i] = kk;
+        Acc v;
+        if constexpr (sizeof(Acc) == 8) {
+            v = vwide[vbits[base + i]];
+        } else if constexpr (DT == SPX_BOOL) {
+            v = 1u;
+        } else {
+            const uint32_t b = vbits[base + i];
+            __builtin_memcpy(&v, &b, 4);
+        }
+        s_val[i] = v;
+    }
+    if (threadIdx.x == 0) {
+        s_k[0] = base > 0 ? keys[base - 1] : 0xffffffffu;
+        s_k[1 + cnt] = base + cnt < n ? keys[base + cnt] : 0xffffffffu;
+    }
+    __syncthreads();
+    const int i0 = threadIdx.x * kCscIpt;
+    const int i1 = std::min(i0 + kCscIpt, cnt);
+    // per-thread: running sum since the last run head inside the thread
+    Acc acc = S::zero();
+    bool has_head = false;
+    for (int i = i0; i < i1; ++i) {
+        if (i == 0 || s_k[1 + i] != s_k[i]) {
+            has_head = true;
+            acc = S::zero();
+        }
+        acc = S::add(acc, s_val[i]);
+    }
+    s_flag[threadIdx.x] = has_head ? 1 : 0;
+    s_cv[threadIdx.x] = acc;
+    __syncthreads();
+    // inclusive segmented scan: (f1, v1) + (f2, v2) = (f1 | f2, f2 ? v2 : v1 + v2)
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int t = threadIdx.x;
+        int f = s_flag[t];
+        Acc v = s_cv[t];
+        int fo = 0;
+        Acc vo = S::zero();
+        if (t >= off) {
+            fo = s_flag[t - off];
+            vo = s_cv[t - off];
+        }
+        __syncthreads();
+        if (t >= off) {
+            if (!f) v = S::add(vo, v);
+            f |= fo;
+        }
+        s_flag[t] = f;
+        s_cv[t] = v;
+        __syncthreads();
+    }
+    Acc run = (threadIdx.x > 0 && i0 < cnt) ? s_cv[threadIdx.x - 1] : S::zero();
+    for (int i = i0; i < i1; ++i) {
+        if (i == 0 || s_k[1 + i] != s_k[i]) run = S::zero();
+        run = S::add(run, s_val[i]);
+        const bool tail = (i == cnt - 1) || (s_k[2 + i] != s_k[1 + i]);
+        if (tail) {
+            const uint32_t r = s_k[1 + i];
+            // does the run extend beyond the tile on either side?
+            int j = i;
+            const bool touches_start = (s_k[1] == r);  // run includes tile item 0
+            const bool cross = (touches_start && s_k[0] == r) || (i == cnt - 1 && s_k[1 + cnt] == r);
+            (void)j;
+            if (cross)
+                S::atomic_add(&y[r], run);
+            else
+                y[r] = S::out(run);
+        }
+    }
+}
+
+// --------------------------------------------------------------- launch
+static int pick_col_lanes(int32_t n, int32_t nnz) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    int L = 1;
+    while (L < 64 && L < avg) L <<= 1;
+    return L;
+}
+
+static int key_bits(int32_t m) {
+    int b = 0;
+    while (b < 31 && (int64_t(1) << b) < m) ++b;
+    return std::max(b, 1);
+}
+
+size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan) {
+    (void)n;
+    Sizer z;
+    const bool need_excl = plan->distribution == SPX_DIST_BALANCED || plan->writeback == SPX_WB_SORT;
+    if (need_excl) {
+        z.take<int32_t>((size_t)nnz_x + 1);
+        z.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
+    }
+    if (plan->writeback == SPX_WB_SORT) {
+        const int64_t np = nnz;  // nnz_s <= nnz
+        z.take<uint32_t>(np);    // keys
+        z.take<uint32_t>(np);    // value bits
+        z.take<uint32_t>(np);    // keys alt
+        z.take<uint32_t>(np);    // value bits alt
+        if (value_size(dtype) == 8) z.take<double>(np);
+        z.take<int32_t>(radix_ws_elems(np));
+        z.take<int32_t>(4);
+    }
+    return z.used;
+}
+
+template <int DT>
+static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val_v,
+                               void* y_v, const spx_plan* plan, Arena& ws, hipStream_t s) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    const auto* x_val = (const typename S::X*)x_val_v;
+    const auto* vals = (const typename S::V*)A.vals;
+    auto* y = (typename S::Y*)y_v;
+    const int wb = plan->writeback;
+    const int dist = plan->distribution;
+    const size_t ybytes = (size_t)A.m * sizeof(typename S::Y);
+    if (A.m == 0) return SPX_OK;
+    SPX_TRY(fill_bytes(y, 0, ybytes, s));
+    if (nnz_x == 0) return SPX_OK;
+    const int L = plan->lanes > 0 ? plan->lanes : pick_col_lanes(A.n, A.nnz);
+    const bool lds_ok = (int64_t)A.m * (int64_t)sizeof(Acc) <= kLdsBytes;
+    if (wb == SPX_WB_LDS_ATOMIC && !lds_ok)
+        return fail(SPX_ERR_UNSUPPORTED, "lds-atomic write-back needs m * sizeof(acc) <= 64 KiB");
+
+    int32_t* excl = nullptr;
+    if (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT) {
+        excl = ws.take<int32_t>((size_t)nnz_x + 1);
+        int32_t* sws = ws.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
+        if (!excl || !sws) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
+        k_x_lengths<<<(unsigned)ceil_div((int64_t)nnz_x + 1, kBlock), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr,
+                                                                                       excl);
+        SPX_HIP(hipGetLastError());
+        SPX_TRY(scan_exclusive_i32(excl, excl, (int64_t)nnz_x + 1, nullptr, sws, s));
+    }
+    // grid of the balanced kernels: enough tiles for the known or bounded work
+    const int64_t ub = A.nnz_s_hint >= 0 ? A.nnz_s_hint : (int64_t)A.nnz;
+    const int64_t merge_tiles = std::max<int64_t>(1, ceil_div((int64_t)nnz_x + ub, kCscTile));
+
+    if (wb == SPX_WB_ATOMIC || wb == SPX_WB_LDS_ATOMIC) {
+        if (dist == SPX_DIST_DIRECT) {
+            if (wb == SPX_WB_ATOMIC) {
+                const int64_t blocks = ceil_div((int64_t)nnz_x * L, kBlock);
+                switch (L) {
+#define SPX_L(LL)                                                                                       \
+    case LL:                                                                                            \
+        k_csc_direct_atomic<DT, LL><<<(unsigned)blocks, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, \
+                                                                        A.row_idx, vals, y);            \
+        break;
+                    SPX_L(1) SPX_L(2) SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
+#undef SPX_L
+                    default:
+                        return fail(SPX_ERR_ARG, "lanes must be a power of two in [1, 64]");
+                }
+            } else {
+                const int64_t groups = kBlock / L;
+                const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nnz_x, groups), 64));
+                const size_t lds = (size_t)A.m * sizeof(Acc);
+                switch (L) {
+#define SPX_L(LL)                                                                                              \
+    case LL:                                                                                                   \
+        k_csc_direct_lds<DT, LL><<<grid, kBlock, lds, s>>>(A.m, nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, \
+                                                           y);                                                 \
+        break;
+                    SPX_L(1) SPX_L(2) SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
+#undef SPX_L
+                    default:
+                        return fail(SPX_ERR_ARG, "lanes must be a power of two in [1, 64]");
+                }
+            }
+        } else {
+            if (wb == SPX_WB_ATOMIC) {
+                const int grid = (int)std::min<int64_t>(merge_tiles, 8192);
+                k_csc_merge_atomic<DT><<<grid, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals,
+                                                              excl, y);
+            } else {
+                const int grid = (int)std::min<int64_t>(merge_tiles, 64);
+                k_csc_merge_lds<DT><<<grid, kBlock, (size_t)A.m * sizeof(Acc), s>>>(
+                    A.m, nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, excl, y);
+            }
+        }
+        SPX_HIP(hipGetLastError());
+        return SPX_OK;
+    }
+
+    if (wb == SPX_WB_SORT) {
+        // the sort needs the pair count on the host
+        int64_t nnz_s = A.nnz_s_hint;
+        if (nnz_s < 0) {
+            int32_t h = 0;
+            SPX_HIP(hipMemcpyAsync(&h, excl + nnz_x, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            SPX_HIP(hipStreamSynchronize(s));
+            nnz_s = h;
+        }
+        if (nnz_s == 0) return SPX_OK;
+        const int64_t np = A.nnz;
+        uint32_t* keys = ws.take<uint32_t>(np);
+        uint32_t* vb = ws.take<uint32_t>(np);
+        uint32_t* keys2 = ws.take<uint32_t>(np);
+        uint32_t* vb2 = ws.take<uint32_t>(np);
+        Acc* vw = nullptr;
+        if (sizeof(Acc) == 8) vw = ws.take<Acc>(np);
+        int32_t* rws = ws.take<int32_t>(radix_ws_elems(np));
+        if (!keys || !vb || !keys2 || !vb2 || !rws || (sizeof(Acc) == 8 && !vw))
+            return fail(SPX_ERR_WORKSPACE, "spmspv_csc sort: workspace too small");
+        EmitPairs<DT> emit{keys, vb, vw};
+        if (dist == SPX_DIST_DIRECT) {
+            const int64_t blocks = ceil_div((int64_t)nnz_x * L, kBlock);
+            switch (L) {
+#define SPX_L(LL)                                                                                         \
+    case LL:                                                                                              \
+        k_csc_direct_pairs<DT, LL><<<(unsigned)blocks, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr,    \
+                                                                       A.row_idx, vals, excl, emit);      \
+        break;
+                SPX_L(1) SPX_L(2) SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
+#undef SPX_L
+                default:
+                    return fail(SPX_ERR_ARG, "lanes must be a power of two in [1, 64]");
+            }
+        } else {
+            const int grid = (int)std::min<int64_t>(ceil_div((int64_t)nnz_x + nnz_s, kCscTile), 8192);
+            k_csc_merge_pairs<DT><<<grid, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, excl,
+                                                         emit);
+        }
+        SPX_HIP(hipGetLastError());
+        bool in_alt = false;
+        SPX_TRY(radix_sort_pairs(keys, vb, keys2, vb2, nnz_s, key_bits(A.m), rws, s, &in_alt));
+        const uint32_t* sk = in_alt ? keys2 : keys;
+        const uint32_t* sv = in_alt ? vb2 : vb;
+        k_reduce_by_key<DT><<<(unsigned)ceil_div(nnz_s, kCscTile), kBlock, 0, s>>>(nnz_s, sk, sv, vw, y);
+        SPX_HIP(hipGetLastError());
+        return SPX_OK;
+    }
+    return fail(SPX_ERR_UNSUPPORTED, "write-back not available for spmspv_csc");
+}
+
+spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                             void* y, const spx_plan* plan, Arena& ws, hipStream_t s) {
+    switch (A.dtype) {
+        case SPX_F32:
+            return launch_csc_t<SPX_F32>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
+        case SPX_F64:
+            return launch_csc_t<SPX_F64>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
+        case SPX_I32:
+            return launch_csc_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
+        case SPX_BOOL:
+            return launch_csc_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
+    }
+    return fail(SPX_ERR_DTYPE, "spmspv_csc: unknown dtype");
+}
+
+}  // namespace spx
