@@ -170,8 +170,8 @@ spx_status spmspv_csr(const spx_csr *A, int32_t nnz_x, const int32_t *x_idx, con
  * plan's write-back (Section 4.2.2). A is CSC (see spx_matrix_csc for a
  * CSC built from a CSR). y is overwritten (zero rows included). The
  * workspace must hold spx_workspace_size(A->m, A->n, A->nnz, nnz_x, ...)
- * bytes (the row-pointer-derived bucket layout of SPX_WB_BUCKET needs a
- * handle and is only available through run_plan). */
+ * bytes; SPX_WB_BUCKET returns SPX_ERR_UNSUPPORTED when a bucket of rows
+ * cannot fit 64 KiB of LDS within 4096 buckets. */
 spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, const void *x_val,
                       void *y, const spx_plan *plan, void *workspace, size_t ws_bytes,
                       void *stream);
@@ -243,6 +243,13 @@ spx_status run_plan(spx_matrix *H, const spx_vec *x, void *y, const spx_plan *pl
 spx_status spx_last_plan(const spx_matrix *H, spx_plan *out);
 spx_status spx_set_profiling(spx_matrix *H, int32_t on);
 spx_status spx_stage_times(const spx_matrix *H, double *out4);
+
+/* Kernel time (ms, HIP events on the caller's stream around the launches of
+ * the chosen kernel) of each run()/run_plan() since the last call, in call
+ * order, while profiling is on. Writes min(count, cap) values to out and
+ * the number of runs to *count, then forgets them. Synchronizes on the
+ * recorded events. */
+spx_status spx_run_times(spx_matrix *H, double *out, int32_t cap, int32_t *count);
 
 /* ---------------------------------------------------------------------
  * Batched SpMSpV: B sparse vectors in one launch sequence.

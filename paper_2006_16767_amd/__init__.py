@@ -204,6 +204,13 @@ class Matrix:
         _lib.call("spx_stage_times", self._h, out)
         return dict(zip(("features_ms", "model_ms", "conversion_ms", "kernel_ms"), list(out)))
 
+    def run_times(self, cap: int = 1 << 16):
+        """Per-run kernel times (ms) recorded while profiling was on."""
+        out = (C.c_double * cap)()
+        cnt = C.c_int32()
+        _lib.call("spx_run_times", self._h, out, cap, C.byref(cnt))
+        return list(out[:min(cnt.value, cap)])
+
     def values_updated(self, stream=None):
         _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
 

@@ -75,6 +75,7 @@ SIGNATURES = {
     "spx_last_plan": (C.c_int, [P, C.POINTER(Plan)]),
     "spx_set_profiling": (C.c_int, [P, _i32]),
     "spx_stage_times": (C.c_int, [P, C.POINTER(C.c_double)]),
+    "spx_run_times": (C.c_int, [P, C.POINTER(C.c_double), _i32, C.POINTER(_i32)]),
     "run_batch": (C.c_int, [P, _i32, C.c_int64, P, P, P, P, P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),

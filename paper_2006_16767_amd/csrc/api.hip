@@ -295,8 +295,6 @@ extern "C" spx_status spmspv_csc(const spx_csc* A, int32_t nnz_x, const int32_t*
     SPX_TRY(check_csc(A));
     SPX_TRY(spx_check_plan(plan, A->dtype));
     if (plan->pattern != SPX_PAT_CSC_SPMSPV) return fail(SPX_ERR_ARG, "spmspv_csc needs pattern SPX_PAT_CSC_SPMSPV");
-    if (plan->writeback == SPX_WB_BUCKET)
-        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back needs the matrix handle (run_plan)");
     if (nnz_x < 0 || nnz_x > A->n) return fail(SPX_ERR_SHAPE, "nnz_x must be in [0, n]");
     if (nnz_x > 0 && (!x_idx || (A->dtype != SPX_BOOL && !x_val))) return fail(SPX_ERR_ARG, "x arrays are null");
     if (A->m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
@@ -562,7 +560,6 @@ static spx_status select_impl(spx_matrix* H, const spx_vec* x, uint32_t flags, s
         if (p.writeback == SPX_WB_LDS_ATOMIC &&
             (int64_t)H->csr.m * std::max(4, value_size(H->csr.dtype)) > 65536)
             p.writeback = SPX_WB_SORT;
-        if (p.writeback == SPX_WB_BUCKET) p.writeback = SPX_WB_SORT;  // until bucket lands
     }
     (void)flags;
     *out = p;
@@ -702,8 +699,6 @@ extern "C" spx_status run_plan(spx_matrix* H, const spx_vec* x, void* y, const s
     if (!H || !plan) return fail(SPX_ERR_ARG, "null argument");
     SPX_TRY(check_vec(H, x));
     if (H->csr.m > 0 && !y) return fail(SPX_ERR_ARG, "y is null");
-    if (plan->pattern == SPX_PAT_CSC_SPMSPV && plan->writeback == SPX_WB_BUCKET)
-        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back is not built yet");
     H->last_plan = *plan;
     return exec_plan(H, x, y, plan, -1, -1, (hipStream_t)stream);
 }
@@ -717,6 +712,23 @@ extern "C" spx_status spx_last_plan(const spx_matrix* H, spx_plan* out) {
 extern "C" spx_status spx_set_profiling(spx_matrix* H, int32_t on) {
     if (!H) return fail(SPX_ERR_ARG, "handle is null");
     H->profiling = on ? 1 : 0;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_run_times(spx_matrix* H, double* out, int32_t cap, int32_t* count) {
+    if (!H || !count || (cap > 0 && !out)) return fail(SPX_ERR_ARG, "null argument");
+    int32_t i = 0;
+    for (auto& e : H->ev_kern) {
+        float ms = 0;
+        hipEventSynchronize(e.second);
+        hipEventElapsedTime(&ms, e.first, e.second);
+        if (i < cap) out[i] = ms;
+        ++i;
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    H->ev_kern.clear();
+    *count = i;
     return SPX_OK;
 }
 

@@ -99,6 +99,11 @@ spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
                              hipStream_t s);
 size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype,
                      const spx_plan* plan);
+// bucket write-back (spmspv_bucket.hip); excl = prefix of selected column lengths
+spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
+                             void* y, const spx_plan* plan, const int32_t* excl, Arena& ws,
+                             hipStream_t s);
+size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
 
 // sparse x -> bitvector of supp(x) (cleared first) + scattered values xd[n]
 spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,

@@ -491,11 +491,25 @@ __global__ __launch_bounds__(kBlock) void k_row_stats(const int32_t* __restrict_
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_len_hist(const int32_t* __restrict__ row_ptr, int32_t m,
+// Histogram of row lengths; lengths below kLdsBins are counted in LDS first
+// (most rows are short), longer ones go straight to global atomics.
+constexpr int kLdsBins = 4096;
+__global__ __launch_bounds__(kBlock) void k_len_hist(const int32_t* __restrict__ row_ptr, int32_t m, int32_t nbins,
                                                      int32_t* __restrict__ hist) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * kBlock)
-        atomicAdd(&hist[row_ptr[i + 1] - row_ptr[i]], 1);
+    __shared__ int32_t s_h[kLdsBins];
+    const int lb = nbins < kLdsBins ? nbins : kLdsBins;
+    for (int i = threadIdx.x; i < lb; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const int L = row_ptr[i + 1] - row_ptr[i];
+        if (L < lb)
+            atomicAdd(&s_h[L], 1);
+        else
+            atomicAdd(&hist[L], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < lb; i += kBlock)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
 spx_status matrix_features_device(const int32_t* row_ptr, int32_t m, int32_t n, MatrixStats* out,
@@ -524,7 +538,7 @@ spx_status matrix_features_device(const int32_t* row_ptr, int32_t m, int32_t n, 
     int32_t* d_hist = nullptr;
     SPX_HIP(hipMallocAsync((void**)&d_hist, (size_t)(mx + 1) * sizeof(int32_t), s));
     SPX_TRY(fill_u32((uint32_t*)d_hist, 0u, (size_t)(mx + 1), s));
-    k_len_hist<<<grid, kBlock, 0, s>>>(row_ptr, m, d_hist);
+    k_len_hist<<<grid, kBlock, 0, s>>>(row_ptr, m, (int32_t)(mx + 1), d_hist);
     SPX_HIP(hipGetLastError());
     std::vector<int32_t> hist((size_t)mx + 1);
     SPX_HIP(hipMemcpyAsync(hist.data(), d_hist, hist.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));

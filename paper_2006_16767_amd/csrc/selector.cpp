@@ -37,15 +37,16 @@ static Tree make_tree(std::initializer_list<std::initializer_list<double>> rows)
     return t;
 }
 
-// Untrained defaults: vector density picks the pattern (column-major when
-// very sparse, row-major with validation in between, SpMV when dense);
-// an unequal row-length distribution (Gini) picks the balanced
-// distribution; few effective entries pick atomics, a y that fits in LDS
-// the privatized atomics, otherwise the sort.
+// Untrained defaults, written on host-known features only so that run()
+// needs no device-to-host sync: vector density picks the pattern
+// (column-major when sparse, row-major with validation in between, SpMV
+// when dense); an unequal row-length distribution (Gini) picks the
+// balanced distribution; few vector entries pick atomics, a y that fits in
+// LDS the privatized atomics, otherwise the bucket write-back.
 Selector builtin_selector() {
     Selector s;
     s.pattern = make_tree({
-        {F_X_SPARSITY, 0.05, 1, 2, -1},
+        {F_X_SPARSITY, 0.1, 1, 2, -1},
         {0, 0, 0, 0, SPX_PAT_CSC_SPMSPV},
         {F_X_SPARSITY, 0.3, 3, 4, -1},
         {0, 0, 0, 0, SPX_PAT_CSR_SPMSPV},
@@ -58,11 +59,11 @@ Selector builtin_selector() {
             {0, 0, 0, 0, SPX_DIST_BALANCED},
         });
     s.writeback = make_tree({
-        {F_NNZ_S, 65536, 1, 2, -1},
+        {F_NNZ_X, 2048, 1, 2, -1},
         {0, 0, 0, 0, SPX_WB_ATOMIC},
         {F_M, 16384, 3, 4, -1},
         {0, 0, 0, 0, SPX_WB_LDS_ATOMIC},
-        {0, 0, 0, 0, SPX_WB_SORT},
+        {0, 0, 0, 0, SPX_WB_BUCKET},
     });
     s.source = "builtin";
     return s;

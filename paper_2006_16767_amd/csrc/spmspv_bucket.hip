@@ -1,0 +1,348 @@
+// Bucket write-back of the column-major SpMSpV.
+//
+// The rows of y are cut into NB buckets of R rows (R a power of two, R * acc
+// size <= 64 KiB so a bucket's slice of y fits in LDS). Two kernels:
+//
+//  scatter     each workgroup takes a chunk of effective positions (one
+//              merge-path tile for the balanced distribution, a contiguous
+//              range of x entries for the direct one), counts its pairs per
+//              bucket in LDS, prefix-sums the counts and writes every pair
+//              (local row as uint16, product) into the chunk's own range of
+//              the pair buffer, grouped by bucket. The chunk's range is its
+//              range of prefix positions, so no global atomic and no count
+//              pass are needed. Per (bucket, chunk) it records the offset and
+//              count of that group, bucket-major.
+//  accumulate  one workgroup per bucket zeroes an LDS copy of its R rows,
+//              adds the pairs of every chunk's group with LDS atomics, and
+//              writes all R rows of y once (rows that received nothing get 0,
+//              so y needs no zero fill).
+//
+// Traffic per effective entry: the CSC read (index + value) plus one pair
+// write and one pair read (6 bytes for FP32 values), instead of a global
+// atomic per entry.
+#include <algorithm>
+
+#include "common.hpp"
+#include "csc_tile.hpp"
+#include "internal.hpp"
+
+namespace spx {
+
+constexpr int kMaxBuckets = 4096;
+constexpr int kBucketLdsBytes = 65536;
+constexpr int kDirectChunks = 1024;  // chunk count of the direct distribution
+
+// exclusive scan of s_cnt[0..NB) into s_off[0..NB) by the whole workgroup
+__device__ __forceinline__ void bucket_scan(const int32_t* s_cnt, int32_t* s_off, int NB, int32_t* s_tmp) {
+    const int per = (NB + kBlock - 1) / kBlock;
+    const int b0 = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int b = b0; b < b0 + per && b < NB; ++b) sum += s_cnt[b];
+    int32_t tot;
+    const int32_t incl = block_incl_scan(sum, s_tmp, &tot);
+    int32_t run = incl - sum;
+    for (int b = b0; b < b0 + per && b < NB; ++b) {
+        s_off[b] = run;
+        run += s_cnt[b];
+    }
+}
+
+template <int DT>
+struct BucketOut {
+    uint16_t* prow;
+    typename SR<DT>::Acc* pval;  // unused for BOOL
+    int32_t* moff;               // [NB][stride]
+    int32_t* mcnt;               // [NB][stride]
+    int32_t stride;
+};
+
+// ------------------------------------------------------------------ balanced scatter
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
+    int32_t nnz_x, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
+    const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+    const typename SR<DT>::V* __restrict__ vals, const int32_t* __restrict__ excl, int logR, int NB,
+    BucketOut<DT> out) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    __shared__ CscTileLds<DT> L;
+    __shared__ int32_t s_cnt[kMaxBuckets];
+    __shared__ int32_t s_off[kMaxBuckets];
+    __shared__ int32_t s_tmp[kWavesPerBlock];
+    const int64_t nnz_s = excl[nnz_x];
+    const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
+    const int64_t tile = blockIdx.x;
+    if (tile >= tiles) return;  // the accumulate pass reads only the first `tiles` chunks
+    for (int b = threadIdx.x; b < NB; b += kBlock) s_cnt[b] = 0;
+    const CscTile t = csc_tile_setup<DT>(tile, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
+    int32_t bkt[kCscIpt], slot[kCscIpt];
+    uint16_t lrow[kCscIpt];
+    Acc val[kCscIpt];
+#pragma unroll
+    for (int i = 0; i < kCscIpt; ++i) {
+        const int p = t.p0 + threadIdx.x + i * kBlock;
+        bkt[i] = -1;
+        if (p < t.p1) {
+            const int u = csc_tile_locate<DT>(p, t, L);
+            const int k = L.cs[u] + (p - L.excl[u]);
+            const int r = row_idx[k];
+            val[i] = S::mul(S::val(vals, k), L.v[u]);
+            bkt[i] = r >> logR;
+            lrow[i] = (uint16_t)(r & ((1 << logR) - 1));
+            slot[i] = atomicAdd(&s_cnt[bkt[i]], 1);
+        }
+    }
+    __syncthreads();
+    bucket_scan(s_cnt, s_off, NB, s_tmp);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kCscIpt; ++i) {
+        if (bkt[i] >= 0) {
+            const int64_t pos = (int64_t)t.p0 + s_off[bkt[i]] + slot[i];
+            out.prow[pos] = lrow[i];
+            if constexpr (S::kVals) out.pval[pos] = val[i];
+        }
+    }
+    for (int b = threadIdx.x; b < NB; b += kBlock) {
+        const int64_t mi = (int64_t)b * out.stride + tile;
+        out.moff[mi] = t.p0 + s_off[b];
+        out.mcnt[mi] = s_cnt[b];
+    }
+}
+
+// ------------------------------------------------------------------ direct scatter
+// Chunk c = x entries [c * E, (c + 1) * E); a group of L lanes per entry walks
+// the column twice: once to count per bucket, once to write.
+template <int DT, int L>
+__global__ __launch_bounds__(kBlock) void k_bucket_scatter_direct(
+    int32_t nnz_x, int32_t E, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
+    const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+    const typename SR<DT>::V* __restrict__ vals, const int32_t* __restrict__ excl, int logR, int NB,
+    BucketOut<DT> out) {
+    using S = SR<DT>;
+    __shared__ int32_t s_cnt[kMaxBuckets];
+    __shared__ int32_t s_off[kMaxBuckets];
+    __shared__ int32_t s_tmp[kWavesPerBlock];
+    const int c = blockIdx.x;
+    const int e_begin = (int)std::min<int64_t>((int64_t)c * E, nnz_x);
+    const int e_end = (int)std::min<int64_t>((int64_t)(c + 1) * E, nnz_x);
+    const int P0 = excl[e_begin];
+    const int groups = kBlock / L;
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    for (int b = threadIdx.x; b < NB; b += kBlock) s_cnt[b] = 0;
+    __syncthreads();
+    for (int e = e_begin + g; e < e_end; e += groups) {
+        const int j = x_idx[e];
+        const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
+        for (int k = c0 + lane; k < c1; k += L) atomicAdd(&s_cnt[row_idx[k] >> logR], 1);
+    }
+    __syncthreads();
+    bucket_scan(s_cnt, s_off, NB, s_tmp);
+    __syncthreads();
+    for (int b = threadIdx.x; b < NB; b += kBlock) {
+        const int64_t mi = (int64_t)b * out.stride + c;
+        out.moff[mi] = P0 + s_off[b];
+        out.mcnt[mi] = s_cnt[b];
+        s_cnt[b] = 0;  // becomes the write cursor
+    }
+    __syncthreads();
+    for (int e = e_begin + g; e < e_end; e += groups) {
+        const int j = x_idx[e];
+        const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
+        const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
+        for (int k = c0 + lane; k < c1; k += L) {
+            const int r = row_idx[k];
+            const int b = r >> logR;
+            const int64_t pos = (int64_t)P0 + s_off[b] + atomicAdd(&s_cnt[b], 1);
+            out.prow[pos] = (uint16_t)(r & ((1 << logR) - 1));
+            if constexpr (S::kVals) out.pval[pos] = S::mul(S::val(vals, k), v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ accumulate
+// nch_fixed >= 0: number of chunks; otherwise the merge-tile count derived
+// from excl[nnz_x]. The bucket's groups are taken kAccWin chunks at a time:
+// their counts are prefix-summed in LDS, which flattens the window into one
+// run of pairs that all 256 threads stream through (each pair finds its
+// chunk by a binary search in LDS), so the loads of different pairs are
+// independent and stay in flight together.
+constexpr int kAccWin = 2048;
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_bucket_accumulate(int32_t m, int logR, int32_t nch_fixed,
+                                                              int32_t nnz_x, const int32_t* __restrict__ excl,
+                                                              const uint16_t* __restrict__ prow,
+                                                              const typename SR<DT>::Acc* __restrict__ pval,
+                                                              const int32_t* __restrict__ moff,
+                                                              const int32_t* __restrict__ mcnt, int32_t stride,
+                                                              typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    extern __shared__ char s_raw[];
+    Acc* acc = (Acc*)s_raw;
+    __shared__ int32_t s_pre[kAccWin + 1];
+    __shared__ int32_t s_off[kAccWin];
+    __shared__ int32_t s_tmp[kWavesPerBlock];
+    const int R = 1 << logR;
+    const int b = blockIdx.x;
+    for (int r = threadIdx.x; r < R; r += kBlock) acc[r] = S::zero();
+    const int64_t nch = nch_fixed >= 0 ? nch_fixed : ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);
+    const int32_t* mo = moff + (int64_t)b * stride;
+    const int32_t* mc = mcnt + (int64_t)b * stride;
+    constexpr int kPer = kAccWin / kBlock;
+    for (int64_t w0 = 0; w0 < nch; w0 += kAccWin) {
+        const int wn = (int)std::min<int64_t>(kAccWin, nch - w0);
+        // counts of this window, prefix-summed (each thread owns kPer consecutive chunks)
+        int32_t cnt[kPer];
+        int32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int c = threadIdx.x * kPer + i;
+            cnt[i] = c < wn ? mc[w0 + c] : 0;
+            if (c < wn) s_off[c] = mo[w0 + c];
+            sum += cnt[i];
+        }
+        int32_t tot;
+        const int32_t incl = block_incl_scan(sum, s_tmp, &tot);
+        int32_t run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            s_pre[threadIdx.x * kPer + i] = run;
+            run += cnt[i];
+        }
+        if (threadIdx.x == 0) s_pre[kAccWin] = tot;
+        __syncthreads();
+        for (int i = threadIdx.x; i < tot; i += kBlock) {
+            // last chunk whose prefix start is <= i
+            int lo = 0, hi = wn - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pre[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int q = s_off[lo] + (i - s_pre[lo]);
+            if constexpr (S::kVals)
+                S::lds_atomic_add(&acc[prow[q]], pval[q]);
+            else
+                acc[prow[q]] = 1u;
+        }
+        __syncthreads();
+    }
+    const int64_t base = (int64_t)b << logR;
+    for (int r = threadIdx.x; r < R; r += kBlock)
+        if (base + r < m) y[base + r] = S::out(acc[r]);
+}
+
+// ------------------------------------------------------------------ launch
+struct BucketGeom {
+    int logR, NB;
+};
+
+static bool bucket_geometry(int32_t m, int dtype, int bucket_rows, BucketGeom* g) {
+    const int asz = dtype == SPX_F64 ? 8 : 4;
+    const int rmax = kBucketLdsBytes / asz;
+    int R;
+    if (bucket_rows > 0) {
+        R = bucket_rows;
+    } else {
+        R = 64;
+        while (R < rmax && (int64_t)R * 256 < m) R <<= 1;
+        while (R < rmax && ceil_div(m, R) > kMaxBuckets) R <<= 1;
+    }
+    if (R > rmax || R > 65536) return false;
+    int logR = 0;
+    while ((1 << logR) < R) ++logR;
+    g->logR = logR;
+    g->NB = (int)std::max<int64_t>(1, ceil_div(m, R));
+    return g->NB <= kMaxBuckets;
+}
+
+static int64_t bucket_chunks(int32_t nnz_x, int64_t nnz_s_ub, const spx_plan* plan) {
+    if (plan->distribution == SPX_DIST_BALANCED) return std::max<int64_t>(1, ceil_div((int64_t)nnz_x + nnz_s_ub, kCscTile));
+    return std::max<int64_t>(1, std::min<int64_t>(nnz_x, kDirectChunks));
+}
+
+size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan) {
+    BucketGeom g;
+    if (!bucket_geometry(m, dtype, plan->bucket_rows, &g)) return 0;
+    const int64_t ch = bucket_chunks(nnz_x, nnz, plan);
+    Sizer z;
+    z.take<uint16_t>((size_t)nnz + 1);
+    if (dtype != SPX_BOOL) z.take<double>((size_t)nnz + 1);
+    z.take<int32_t>((size_t)g.NB * ch);
+    z.take<int32_t>((size_t)g.NB * ch);
+    return z.used;
+}
+
+template <int DT>
+static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val_v,
+                                  void* y_v, const spx_plan* plan, const int32_t* excl, Arena& ws, hipStream_t s) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    BucketGeom g;
+    if (!bucket_geometry(A.m, DT, plan->bucket_rows, &g))
+        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back: rows per bucket must fit 64 KiB of LDS and at most 4096 buckets");
+    const auto* x_val = (const typename S::X*)x_val_v;
+    const auto* vals = (const typename S::V*)A.vals;
+    auto* y = (typename S::Y*)y_v;
+    const int64_t ub = A.nnz_s_hint >= 0 ? A.nnz_s_hint : (int64_t)A.nnz;
+    const int64_t ch = bucket_chunks(nnz_x, ub, plan);
+    BucketOut<DT> out;
+    out.prow = ws.take<uint16_t>((size_t)ub + 1);
+    out.pval = S::kVals ? ws.take<Acc>((size_t)ub + 1) : nullptr;
+    out.moff = ws.take<int32_t>((size_t)g.NB * ch);
+    out.mcnt = ws.take<int32_t>((size_t)g.NB * ch);
+    out.stride = (int32_t)ch;
+    if (!out.prow || (S::kVals && !out.pval) || !out.moff || !out.mcnt)
+        return fail(SPX_ERR_WORKSPACE, "bucket write-back: workspace too small");
+    int32_t nch_fixed = -1;
+    if (plan->distribution == SPX_DIST_BALANCED) {
+        k_bucket_scatter_merge<DT><<<(unsigned)ch, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals,
+                                                                   excl, g.logR, g.NB, out);
+    } else {
+        const int32_t E = (int32_t)ceil_div(nnz_x, ch);
+        nch_fixed = (int32_t)ceil_div(nnz_x, E);
+        const double avg = A.n > 0 ? (double)A.nnz / A.n : 0.0;
+        int L = plan->lanes > 0 ? plan->lanes : 1;
+        if (plan->lanes <= 0)
+            while (L < 64 && L < avg) L <<= 1;
+        switch (L) {
+#define SPX_L(LL)                                                                                              \
+    case LL:                                                                                                   \
+        k_bucket_scatter_direct<DT, LL><<<(unsigned)nch_fixed, kBlock, 0, s>>>(nnz_x, E, x_idx, x_val, A.col_ptr, \
+                                                                               A.row_idx, vals, excl, g.logR,  \
+                                                                               g.NB, out);                     \
+        break;
+            SPX_L(1) SPX_L(2) SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
+#undef SPX_L
+            default:
+                return fail(SPX_ERR_ARG, "lanes must be a power of two in [1, 64]");
+        }
+    }
+    SPX_HIP(hipGetLastError());
+    const size_t lds = ((size_t)1 << g.logR) * sizeof(Acc);
+    k_bucket_accumulate<DT><<<(unsigned)g.NB, kBlock, lds, s>>>(A.m, g.logR, nch_fixed, nnz_x, excl, out.prow,
+                                                                out.pval, out.moff, out.mcnt, out.stride, y);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
+                             const spx_plan* plan, const int32_t* excl, Arena& ws, hipStream_t s) {
+    switch (A.dtype) {
+        case SPX_F32:
+            return launch_bucket_t<SPX_F32>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
+        case SPX_F64:
+            return launch_bucket_t<SPX_F64>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
+        case SPX_I32:
+            return launch_bucket_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
+        case SPX_BOOL:
+            return launch_bucket_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
+    }
+    return fail(SPX_ERR_DTYPE, "bucket: unknown dtype");
+}
+
+}  // namespace spx

@@ -23,12 +23,11 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "csc_tile.hpp"
 #include "internal.hpp"
 
 namespace spx {
 
-constexpr int kCscIpt = 8;
-constexpr int kCscTile = kBlock * kCscIpt;
 constexpr int kLdsBytes = 65536;  // LDS budget of the privatized y copy
 
 template <int DT>
@@ -173,43 +172,13 @@ __device__ __forceinline__ void csc_merge_tile(int64_t tile, int32_t nnz_x, int6
                                                const int32_t* __restrict__ row_idx,
                                                const typename SR<DT>::V* __restrict__ vals,
                                                const int32_t* __restrict__ excl, const Emit& emit,
-                                               int32_t* s_excl, int32_t* s_cs,
-                                               typename SR<DT>::X* s_v, int32_t* s_bound) {
+                                               CscTileLds<DT>& L) {
     using S = SR<DT>;
-    const int64_t total = (int64_t)nnz_x + nnz_s;
-    const int64_t d0 = tile * kCscTile;
-    const int64_t d1 = std::min<int64_t>(d0 + kCscTile, total);
-    auto ends = [&](int e) { return excl[e + 1]; };
-    if (wave_id() < 2) {
-        const int64_t d = wave_id() == 0 ? d0 : d1;
-        const int e = merge_search_wave(ends, nnz_x, d);
-        if (lane_id() == 0) {
-            s_bound[wave_id() * 2 + 0] = e;
-            s_bound[wave_id() * 2 + 1] = (int)(d - e);
-        }
-    }
-    __syncthreads();
-    const int e0 = s_bound[0], p0 = s_bound[1], e1 = s_bound[2], p1 = s_bound[3];
-    const int ecount = std::min(e1, nnz_x - 1) - e0 + 1;  // entries touched (>= 1 when p1 > p0)
-    for (int u = threadIdx.x; u < ecount; u += kBlock) {
-        const int e = e0 + u;
-        s_excl[u] = excl[e];
-        s_cs[u] = col_ptr[x_idx[e]];
-        s_v[u] = S::kVals ? x_val[e] : (typename S::X)1;
-    }
-    __syncthreads();
-    for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
-        // last staged entry whose prefix start is <= p
-        int lo = 0, hi = ecount - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_excl[mid] <= p)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const int k = s_cs[lo] + (p - s_excl[lo]);
-        emit(row_idx[k], S::mul(S::val(vals, k), s_v[lo]), p);
+    const CscTile t = csc_tile_setup<DT>(tile, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
+    for (int p = t.p0 + threadIdx.x; p < t.p1; p += kBlock) {
+        const int u = csc_tile_locate<DT>(p, t, L);
+        const int k = L.cs[u] + (p - L.excl[u]);
+        emit(row_idx[k], S::mul(S::val(vals, k), L.v[u]), p);
     }
     __syncthreads();
 }
@@ -222,15 +191,11 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_atomic(int32_t nnz_x, cons
                                                              const typename SR<DT>::V* __restrict__ vals,
                                                              const int32_t* __restrict__ excl,
                                                              typename SR<DT>::Y* __restrict__ y) {
-    __shared__ int32_t s_excl[kCscTile + 1];
-    __shared__ int32_t s_cs[kCscTile + 1];
-    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
-    __shared__ int32_t s_bound[4];
+    __shared__ CscTileLds<DT> L;
     const int64_t nnz_s = excl[nnz_x];
     const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
-        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitAtomic<DT>{y},
-                           s_excl, s_cs, s_v, s_bound);
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitAtomic<DT>{y}, L);
 }
 
 template <int DT>
@@ -241,15 +206,11 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_pairs(int32_t nnz_x, const
                                                             const typename SR<DT>::V* __restrict__ vals,
                                                             const int32_t* __restrict__ excl,
                                                             EmitPairs<DT> emit) {
-    __shared__ int32_t s_excl[kCscTile + 1];
-    __shared__ int32_t s_cs[kCscTile + 1];
-    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
-    __shared__ int32_t s_bound[4];
+    __shared__ CscTileLds<DT> L;
     const int64_t nnz_s = excl[nnz_x];
     const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
-        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, emit, s_excl, s_cs,
-                           s_v, s_bound);
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, emit, L);
 }
 
 template <int DT>
@@ -262,10 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz
                                                           const int32_t* __restrict__ excl,
                                                           typename SR<DT>::Y* __restrict__ y) {
     using S = SR<DT>;
-    __shared__ int32_t s_excl[kCscTile + 1];
-    __shared__ int32_t s_cs[kCscTile + 1];
-    __shared__ typename SR<DT>::X s_v[kCscTile + 1];
-    __shared__ int32_t s_bound[4];
+    __shared__ CscTileLds<DT> L;
     extern __shared__ char s_raw[];
     auto* sy = (typename S::Acc*)s_raw;
     for (int r = threadIdx.x; r < m; r += kBlock) sy[r] = S::zero();
@@ -273,8 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz
     const int64_t nnz_s = excl[nnz_x];
     const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x)
-        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitLds<DT>{sy},
-                           s_excl, s_cs, s_v, s_bound);
+        csc_merge_tile<DT>(t, nnz_x, nnz_s, x_idx, x_val, col_ptr, row_idx, vals, excl, EmitLds<DT>{sy}, L);
     __syncthreads();
     for (int r = threadIdx.x; r < m; r += kBlock) {
         const typename S::Acc v = sy[r];
@@ -392,10 +349,16 @@ static int key_bits(int32_t m) {
 size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan) {
     (void)n;
     Sizer z;
-    const bool need_excl = plan->distribution == SPX_DIST_BALANCED || plan->writeback == SPX_WB_SORT;
+    const bool need_excl = plan->distribution == SPX_DIST_BALANCED || plan->writeback == SPX_WB_SORT ||
+                           plan->writeback == SPX_WB_BUCKET;
     if (need_excl) {
         z.take<int32_t>((size_t)nnz_x + 1);
         z.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
+    }
+    if (plan->writeback == SPX_WB_BUCKET) {
+        const size_t b = csc_bucket_ws(m, nnz, nnz_x, dtype, plan);
+        if (b == 0) return 0;
+        z.used = align_up(z.used, 256) + b;
     }
     if (plan->writeback == SPX_WB_SORT) {
         const int64_t np = nnz;  // nnz_s <= nnz
@@ -422,7 +385,8 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int dist = plan->distribution;
     const size_t ybytes = (size_t)A.m * sizeof(typename S::Y);
     if (A.m == 0) return SPX_OK;
-    SPX_TRY(fill_bytes(y, 0, ybytes, s));
+    // the bucket write-back writes every row itself
+    if (wb != SPX_WB_BUCKET || nnz_x == 0) SPX_TRY(fill_bytes(y, 0, ybytes, s));
     if (nnz_x == 0) return SPX_OK;
     const int L = plan->lanes > 0 ? plan->lanes : pick_col_lanes(A.n, A.nnz);
     const bool lds_ok = (int64_t)A.m * (int64_t)sizeof(Acc) <= kLdsBytes;
@@ -430,7 +394,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
         return fail(SPX_ERR_UNSUPPORTED, "lds-atomic write-back needs m * sizeof(acc) <= 64 KiB");
 
     int32_t* excl = nullptr;
-    if (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT) {
+    if (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET) {
         excl = ws.take<int32_t>((size_t)nnz_x + 1);
         int32_t* sws = ws.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
         if (!excl || !sws) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
@@ -442,6 +406,8 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     // grid of the balanced kernels: enough tiles for the known or bounded work
     const int64_t ub = A.nnz_s_hint >= 0 ? A.nnz_s_hint : (int64_t)A.nnz;
     const int64_t merge_tiles = std::max<int64_t>(1, ceil_div((int64_t)nnz_x + ub, kCscTile));
+
+    if (wb == SPX_WB_BUCKET) return launch_csc_bucket(A, nnz_x, x_idx, x_val_v, y_v, plan, excl, ws, s);
 
     if (wb == SPX_WB_ATOMIC || wb == SPX_WB_LDS_ATOMIC) {
         if (dist == SPX_DIST_DIRECT) {

@@ -1,0 +1,399 @@
+"""Kernel-selector training on timings from this GPU (Section 5.2).
+
+    python -m paper_2006_16767_amd.tune sweep --out sweep.jsonl   # on the GPU
+    python -m paper_2006_16767_amd.tune train sweep.jsonl --out selector.json
+
+sweep  builds a synthetic corpus (uniform, banded, R-MAT, Poisson, power-law
+       and Bernoulli matrices; for each, input vectors whose nnz_x grows from
+       1 to n on a log scale, uniformly placed), times every candidate kernel
+       with HIP events (median of several runs, the result of each run
+       discarded), and appends one JSON record per (matrix, vector): the 13
+       features of Table 1 and the time of every plan. An interrupted sweep
+       resumes by skipping keys already in the file.
+train  labels each record per factor (the pattern of the fastest kernel;
+       the best distribution within that pattern; the best write-back within
+       the column-major pattern and the chosen distribution; times within 2%
+       go to the cheaper alternative), splits 7:3, and grid-searches a
+       project-written CART decision tree (max_depth 1..10, class weights
+       balanced or uniform, 3-fold cross-validation on the training part).
+       The three trees are written as the JSON the library loads
+       (spx_load_selector).
+
+By default the trees use only features the host knows without a device
+round trip (everything except nnz_s and m_sparsity); see --all-features.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+FEATURES = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini",
+            "nnz_x", "x_sparsity", "nnz_s", "m_sparsity")
+CHEAP = tuple(f for f in FEATURES if f not in ("nnz_s", "m_sparsity"))
+PATTERNS = ("spmv", "csr_spmspv", "csc_spmspv")
+DISTS = ("direct", "balanced")
+WBS = ("none", "atomic", "sort", "lds_atomic", "bucket")
+# cheaper-first order used to break near-ties (within 2%)
+COST_ORDER = {("spmv",): 0, ("csr_spmspv",): 1, ("csc_spmspv", "atomic"): 2, ("csc_spmspv", "lds_atomic"): 3,
+              ("csc_spmspv", "bucket"): 4, ("csc_spmspv", "sort"): 5}
+TIE = 1.02
+
+
+# ----------------------------------------------------------------------------- corpus
+def corpus(quick: bool = False):
+    """(name, generator) pairs of the synthetic training matrices."""
+    from . import synth
+    mats = [
+        ("uniform_64k_d8", lambda: synth.uniform_rows(65536, 65536, 8, 11)),
+        ("uniform_256k_d32", lambda: synth.uniform_rows(262144, 262144, 32, 12)),
+        ("uniform_1m_d16", lambda: synth.uniform_rows(1 << 20, 1 << 20, 16, 13)),
+        ("rmat14_d16", lambda: synth.rmat(14, 16, 21)),
+        ("rmat17_d8", lambda: synth.rmat(17, 8, 22)),
+        ("rmat18_d32", lambda: synth.rmat(18, 32, 23)),
+        ("rmat20_d16", lambda: synth.rmat(20, 16, 24)),
+        ("rmat20_d16_nrl", lambda: synth.rmat(20, 16, 25, relabel=False)),
+        ("poisson64", lambda: synth.poisson3d(64)),
+        ("poisson128", lambda: synth.poisson3d(128)),
+        ("powerlaw_100k_50k", lambda: synth.powerlaw_rows(100_000, 50_000, 40.0, 31)),
+        ("powerlaw_500k_500k", lambda: synth.powerlaw_rows(500_000, 500_000, 12.0, 32)),
+        ("bernoulli_16k_4k", lambda: synth.bernoulli(16384, 4096, 0.05, 41)),
+        ("bernoulli_4k_16k", lambda: synth.bernoulli(4096, 16384, 0.02, 42)),
+        ("uniform_4k_d16", lambda: synth.uniform_rows(4096, 4096, 16, 43)),
+    ]
+    if quick:
+        mats = [m for m in mats if m[0] in ("uniform_4k_d16", "rmat14_d16", "poisson64")]
+    return mats
+
+
+def densities(n: int, count: int = 16):
+    """nnz_x from 1 to n, log-spaced (the paper grows nnz_x from 1 to n)."""
+    vals = np.unique(np.round(np.geomspace(1, n, count)).astype(np.int64))
+    return [int(v) for v in vals]
+
+
+def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None):
+    import torch
+    from . import Matrix, all_plans, synth
+
+    done = set()
+    if os.path.exists(out_path):
+        with open(out_path) as f:
+            for line in f:
+                try:
+                    done.add(json.loads(line)["key"])
+                except Exception:
+                    pass
+    plans = plans or all_plans()
+    with open(out_path, "a") as fout:
+        for name, gen in corpus(quick):
+            t0 = time.time()
+            A = gen()
+            M = Matrix.from_host(A)
+            mf = M.features()
+            print(f"[tune] {name}: m={A.m} n={A.n} nnz={A.nnz} gen {time.time() - t0:.1f}s", flush=True)
+            y = M.out_tensor()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            for i, nx in enumerate(densities(A.n)):
+                key = f"{name}:{nx}"
+                if key in done:
+                    continue
+                v = synth.sparse_vector(A.n, nx, 5000 + i, lo=0.0, hi=1.0)
+                x = (torch.as_tensor(v.idx, device="cuda"),
+                     torch.as_tensor(np.asarray(v.val, np.float32), device="cuda"))
+                vf = M.vector_features(x)
+                times = {}
+                for p in plans:
+                    label = repr(p)
+                    try:
+                        M.run_plan(x, p, y)
+                    except Exception:
+                        continue  # plan not available for this matrix (e.g. LDS too small)
+                    ts = []
+                    for _ in range(reps):
+                        ev0.record()
+                        M.run_plan(x, p, y)
+                        ev1.record()
+                        ev1.synchronize()
+                        ts.append(ev0.elapsed_time(ev1))
+                    times[label] = float(np.median(ts))
+                rec = {"key": key, "matrix": name, "features": {**mf, **vf}, "times_ms": times}
+                fout.write(json.dumps(rec) + "\n")
+                fout.flush()
+            print(f"[tune] {name}: done in {time.time() - t0:.1f}s", flush=True)
+            del M
+
+
+# ----------------------------------------------------------------------------- labels
+def _parse_plan(label: str):
+    body = label[label.index("(") + 1:label.index(")")]
+    parts = [p.strip() for p in body.split(",")]
+    return parts[0], parts[1], parts[2]
+
+
+def _pick(cands):
+    """cands: list of (time, cost, value); fastest, ties within 2% go to
+    the cheaper alternative."""
+    best_t = min(c[0] for c in cands)
+    close = [c for c in cands if c[0] <= best_t * TIE]
+    return min(close, key=lambda c: (c[1], c[0]))[2]
+
+
+def labels(rec):
+    """Per-factor labels of one record (the other factors at their best)."""
+    t = {}
+    for label, ms in rec["times_ms"].items():
+        t[_parse_plan(label)] = ms
+    if not t:
+        return None
+
+    def cost(pat, wb):
+        return COST_ORDER.get((pat,) if pat != "csc_spmspv" else (pat, wb), 9)
+
+    # pattern: pattern of the fastest kernel
+    per_pat = {}
+    for (pat, dist, wb), ms in t.items():
+        per_pat.setdefault(pat, []).append(ms)
+    pat = _pick([(min(v), cost(p, "atomic" if p == "csc_spmspv" else "none"), p) for p, v in per_pat.items()])
+    # distribution: best within the pattern
+    per_dist = {}
+    for (p, dist, wb), ms in t.items():
+        if p == pat:
+            per_dist.setdefault(dist, []).append(ms)
+    dist = _pick([(min(v), 0 if d == "direct" else 1, d) for d, v in per_dist.items()])
+    # write-back: best within the column-major pattern and the chosen distribution
+    cands = [(ms, cost("csc_spmspv", wb), wb) for (p, d, wb), ms in t.items() if p == "csc_spmspv" and d == dist]
+    if not cands:
+        cands = [(ms, cost("csc_spmspv", wb), wb) for (p, d, wb), ms in t.items() if p == "csc_spmspv"]
+    wb = _pick(cands) if cands else "atomic"
+    return {"pattern": PATTERNS.index(pat), "distribution": DISTS.index(dist), "writeback": WBS.index(wb),
+            "best_ms": min(t.values()), "times": t}
+
+
+# ----------------------------------------------------------------------------- CART
+class Cart:
+    """Binary decision tree with Gini impurity (CART), weighted samples."""
+
+    def __init__(self, max_depth: int, min_leaf: int = 1):
+        self.max_depth = max_depth
+        self.min_leaf = min_leaf
+        self.nodes = []  # [feature, threshold, left, right, class]
+
+    def fit(self, X, y, w=None, n_classes=None):
+        X = np.asarray(X, np.float64)
+        y = np.asarray(y, np.int64)
+        w = np.ones(len(y)) if w is None else np.asarray(w, np.float64)
+        self.k = int(n_classes or (y.max() + 1))
+        self.nodes = []
+        self._grow(X, y, w, 0)
+        return self
+
+    def _leaf(self, y, w):
+        cnt = np.bincount(y, weights=w, minlength=self.k)
+        self.nodes.append([0, 0.0, 0, 0, int(np.argmax(cnt))])
+        return len(self.nodes) - 1
+
+    def _grow(self, X, y, w, depth):
+        cnt = np.bincount(y, weights=w, minlength=self.k)
+        if depth >= self.max_depth or (cnt > 0).sum() <= 1 or len(y) < 2 * self.min_leaf:
+            return self._leaf(y, w)
+        best = None
+        tot = w.sum()
+        parent = 1.0 - ((cnt / tot) ** 2).sum()
+        for f in range(X.shape[1]):
+            order = np.argsort(X[:, f], kind="stable")
+            xs = X[order, f]
+            ys = y[order]
+            ws = w[order]
+            onehot = np.zeros((len(ys), self.k))
+            onehot[np.arange(len(ys)), ys] = ws
+            left = np.cumsum(onehot, axis=0)[:-1]
+            right = cnt[None, :] - left
+            wl = left.sum(1)
+            wr = right.sum(1)
+            valid = (xs[1:] > xs[:-1]) & (np.arange(1, len(ys)) >= self.min_leaf) & \
+                    (np.arange(len(ys) - 1, 0, -1) >= self.min_leaf) & (wl > 0) & (wr > 0)
+            if not valid.any():
+                continue
+            with np.errstate(invalid="ignore", divide="ignore"):
+                gl = 1.0 - ((left / wl[:, None]) ** 2).sum(1)
+                gr = 1.0 - ((right / wr[:, None]) ** 2).sum(1)
+                imp = (wl * gl + wr * gr) / tot
+            imp[~valid] = np.inf
+            i = int(np.argmin(imp))
+            if best is None or imp[i] < best[0]:
+                best = (imp[i], f, 0.5 * (xs[i] + xs[i + 1]))
+        if best is None or best[0] >= parent - 1e-12:
+            return self._leaf(y, w)
+        _, f, thr = best
+        me = len(self.nodes)
+        self.nodes.append([f, float(thr), -1, -1, -1])
+        mask = X[:, f] <= thr
+        l = self._grow(X[mask], y[mask], w[mask], depth + 1)
+        r = self._grow(X[~mask], y[~mask], w[~mask], depth + 1)
+        self.nodes[me][2] = l
+        self.nodes[me][3] = r
+        return me
+
+    def predict(self, X):
+        X = np.asarray(X, np.float64)
+        out = np.empty(len(X), np.int64)
+        for i, row in enumerate(X):
+            j = 0
+            while self.nodes[j][4] < 0:
+                f, thr, l, r, _ = self.nodes[j]
+                j = l if row[f] <= thr else r
+            out[i] = self.nodes[j][4]
+        return out
+
+
+def _weights(y, mode):
+    if mode == "uniform":
+        return np.ones(len(y))
+    cls, cnt = np.unique(y, return_counts=True)
+    wmap = {c: len(y) / (len(cls) * n) for c, n in zip(cls, cnt)}
+    return np.array([wmap[c] for c in y])
+
+
+def grid_search(X, y, n_classes, seed=0):
+    """max_depth 1..10 x class weight {balanced, uniform}, 3-fold CV."""
+    rng = np.random.default_rng(seed)
+    idx = rng.permutation(len(y))
+    folds = np.array_split(idx, 3)
+    best = None
+    for depth in range(1, 11):
+        for cw in ("balanced", "uniform"):
+            accs = []
+            for k in range(3):
+                te = folds[k]
+                tr = np.concatenate([folds[j] for j in range(3) if j != k])
+                if len(tr) == 0 or len(te) == 0:
+                    continue
+                t = Cart(depth).fit(X[tr], y[tr], _weights(y[tr], cw), n_classes)
+                accs.append((t.predict(X[te]) == y[te]).mean())
+            acc = float(np.mean(accs)) if accs else 0.0
+            if best is None or acc > best[0] + 1e-9:
+                best = (acc, depth, cw)
+    return best
+
+
+def train(paths, out_path, all_features=False, seed=0):
+    recs = []
+    for p in paths:
+        with open(p) as f:
+            recs += [json.loads(l) for l in f if l.strip()]
+    rows = []
+    for r in recs:
+        lab = labels(r)
+        if lab is None:
+            continue
+        rows.append((r, lab))
+    feats = FEATURES if all_features else CHEAP
+    fidx = [FEATURES.index(f) for f in feats]
+    X = np.array([[r["features"][f] for f in FEATURES] for r, _ in rows], np.float64)
+    Xs = X[:, fidx]
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(len(rows))
+    ntr = int(round(0.7 * len(rows)))
+    tr, te = perm[:ntr], perm[ntr:]
+    report = {"records": len(rows), "train": len(tr), "test": len(te), "features": list(feats)}
+    trees = {}
+
+    def fit_tree(name, ysel, mask, n_classes):
+        y = np.array([ysel(lab) for _, lab in rows])
+        trm = tr[mask[tr]]
+        tem = te[mask[te]]
+        if len(trm) == 0:
+            return None
+        acc, depth, cw = grid_search(Xs[trm], y[trm], n_classes, seed)
+        t = Cart(depth).fit(Xs[trm], y[trm], _weights(y[trm], cw), n_classes)
+        test_acc = float((t.predict(Xs[tem]) == y[tem]).mean()) if len(tem) else float("nan")
+        report[name] = {"cv_acc": acc, "max_depth": depth, "class_weight": cw, "test_acc": test_acc,
+                        "n_train": int(len(trm)), "n_test": int(len(tem)),
+                        "classes": np.bincount(y[trm], minlength=n_classes).tolist()}
+        # map feature columns back to Table 1 ids for the library
+        nodes = [[fidx[n[0]] if n[4] < 0 else 0, n[1], n[2], n[3], n[4]] for n in t.nodes]
+        return {"nodes": nodes, "max_depth": depth, "class_weight": cw}
+
+    allm = np.ones(len(rows), bool)
+    trees["pattern"] = fit_tree("pattern", lambda l: l["pattern"], allm, 3)
+    trees["distribution"] = {}
+    for pi, pn in enumerate(PATTERNS):
+        # distribution labels of records whose best pattern is this one; fall
+        # back to all records if the pattern never wins
+        def dsel(l, pi=pi):
+            ts = {k: v for k, v in l["times"].items() if k[0] == PATTERNS[pi]}
+            if not ts:
+                return 0
+            per = {}
+            for (p, d, w), ms in ts.items():
+                per.setdefault(d, []).append(ms)
+            return DISTS.index(_pick([(min(v), 0 if d == "direct" else 1, d) for d, v in per.items()]))
+        mask = np.array([l["pattern"] == pi for _, l in rows])
+        if mask.sum() < 10:
+            mask = allm
+        t = fit_tree(f"distribution_{pn}", dsel, mask, 2)
+        trees["distribution"][pn] = t or {"nodes": [[0, 0, 0, 0, 0]]}
+    mask = np.array([l["pattern"] == 2 for _, l in rows])
+    if mask.sum() < 10:
+        mask = allm
+    trees["writeback"] = fit_tree("writeback", lambda l: l["writeback"], mask, 5)
+    # selection quality against exhaustive search on the held-out part:
+    # time of the predicted kernel vs the fastest kernel
+    out = {"format": "spx-selector-v1", "source": "tuned on MI355X timings", "report": report, **trees}
+    loss = []
+    hits = 0
+    for i in te:
+        r, lab = rows[i]
+        x = Xs[i]
+        pat = _eval(trees["pattern"]["nodes"], X[i])
+        dist = _eval(trees["distribution"][PATTERNS[pat]]["nodes"], X[i])
+        wb = _eval(trees["writeback"]["nodes"], X[i]) if pat == 2 else 0
+        key = (PATTERNS[pat], DISTS[dist], WBS[wb])
+        t_pred = lab["times"].get(key)
+        if t_pred is None:
+            continue
+        loss.append(t_pred / lab["best_ms"] - 1.0)
+        hits += int(t_pred <= lab["best_ms"] * TIE)
+    report["held_out_mean_loss_vs_exhaustive"] = float(np.mean(loss)) if loss else None
+    report["held_out_within_2pct_of_best"] = hits / max(1, len(loss))
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return report
+
+
+def _eval(nodes, xrow):
+    j = 0
+    while nodes[j][4] < 0:
+        f, thr, l, r, _ = nodes[j]
+        j = l if xrow[int(f)] <= thr else r
+    return int(nodes[j][4])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("--out", required=True)
+    s.add_argument("--reps", type=int, default=5)
+    s.add_argument("--quick", action="store_true")
+    t = sub.add_parser("train")
+    t.add_argument("data", nargs="+")
+    t.add_argument("--out", required=True)
+    t.add_argument("--all-features", action="store_true")
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        sweep(a.out, a.reps, a.quick)
+    else:
+        rep = train(a.data, a.out, a.all_features)
+        print(json.dumps(rep, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -51,7 +51,7 @@ def _vec_vals(v, kind, rng=None):
 
 def _plans(m, kind):
     out = []
-    for p in spx.all_plans(include_bucket=False):
+    for p in spx.all_plans():
         out.append(p)
     return out
 
@@ -175,7 +175,7 @@ def test_integer_valued_fp32_bitexact():
     for nnz_x in (5, 300, 3000):
         v = synth.sparse_vector(3000, nnz_x, nnz_x, dist="int")
         ref, S = reference(A, v.idx, v.val, "f32")
-        for p in spx.all_plans(include_bucket=False):
+        for p in spx.all_plans():
             try:
                 y = M.run_plan(dev_sparse(v, np.float32), p)
             except spx.SpxError as e:
@@ -213,7 +213,7 @@ def test_cfg3_poisson_closed_form(dt):
     npdt = np.float32 if dt == "f32" else np.float64
     ones = torch.ones(A.n, dtype=torch.float32 if dt == "f32" else torch.float64, device="cuda")
     all_idx = torch.arange(A.n, dtype=torch.int32, device="cuda")
-    for p in spx.all_plans(include_bucket=False):
+    for p in spx.all_plans():
         if p.writeback == spx.WB_LDS_ATOMIC:
             continue
         y = M.run_plan(ones, p)
@@ -229,7 +229,7 @@ def test_cfg3_dense_and_sparse(dt):
     A = cfg_matrix("cfg3" if dt == "f32" else "cfg3_f64")
     M = spx.Matrix.from_host(A)
     dense, sparse = synth.cfg3_vectors(dtype=npdt)
-    plans = [p for p in spx.all_plans(include_bucket=False) if p.writeback != spx.WB_LDS_ATOMIC]
+    plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     full = np.arange(A.n, dtype=np.int32)
     _run_and_check(M, A, full, dense, dt, plans, f"cfg3 {dt} dense", dense=True)
     _run_and_check(M, A, sparse.idx, sparse.val, dt, plans, f"cfg3 {dt} 1%")
@@ -243,7 +243,7 @@ def test_cfg2_rmat_sweep():
     A = cfg_matrix("cfg2")
     Mf = spx.Matrix.from_host(A)
     Mb = spx.Matrix.from_host(A, dtype=spx.BOOL)
-    plans = [p for p in spx.all_plans(include_bucket=False) if p.writeback != spx.WB_LDS_ATOMIC]
+    plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     for v in synth.cfg2_vectors():
         _run_and_check(Mf, A, v.idx, v.val, "f32", plans, f"cfg2 f32 nnz_x={v.nnz}")
         _run_and_check(Mb, A, v.idx, None, "bool", plans, f"cfg2 bool nnz_x={v.nnz}")
@@ -256,7 +256,7 @@ def test_bool_bfs_frontiers():
     A = cfg_matrix("rmat16")
     M = spx.Matrix.from_host(A, dtype=spx.BOOL)
     rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr)).astype(np.int32)
-    plans = [p for p in spx.all_plans(include_bucket=False) if p.writeback != spx.WB_LDS_ATOMIC]
+    plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     for fr in synth.bfs_frontiers(A, max_levels=12):
         nxt = oracle.bfs_step(A.col_idx, rows, A.n, A.m, fr.idx)
         x = (torch.as_tensor(fr.idx, device="cuda"), None)
@@ -277,7 +277,7 @@ def test_int_invariant_spmspv_equals_spmv():
     xd = np.zeros(A.n, np.int32)
     xd[v.idx] = val
     base = M.run_plan(torch.as_tensor(xd, device="cuda"), spx.plan("spmv")).cpu().numpy()
-    for p in spx.all_plans(include_bucket=False):
+    for p in spx.all_plans():
         if p.writeback == spx.WB_LDS_ATOMIC:
             continue
         y = M.run_plan((torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(val, device="cuda")), p)
