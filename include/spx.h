@@ -255,12 +255,23 @@ spx_status spx_run_times(spx_matrix *H, double *out, int32_t cap, int32_t *count
  * Batched SpMSpV: B sparse vectors in one launch sequence.
  * X is CSR-of-vectors: vec_ptr[B+1] (device), idx[total] and val[total]
  * (device); Y is B x m row-major (device), each vector's y contiguous.
- * The plan of every vector is chosen on the device; nothing synchronizes.
+ * The plan of every vector is chosen on the device (the three trees
+ * evaluated on all 13 features, nnz_s included, computed per vector on the
+ * device); the calls are a plan kernel, a queue scan and one persistent
+ * kernel, captured once into a HIP graph and replayed while the arrays and
+ * B stay the same; nothing synchronizes except a workspace reallocation.
  * total_nnz_x (host) is an upper bound of vec_ptr[B] used to size the
- * workspace.
+ * workspace. Column-major plans write back with device atomics in this
+ * path. Vector indices must be unique within a vector.
  * ------------------------------------------------------------------- */
 spx_status run_batch(spx_matrix *H, int32_t B, int64_t total_nnz_x, const int32_t *vec_ptr,
                      const int32_t *idx, const void *val, void *Y, void *stream);
+
+/* Status of the last run_batch on H: *flags = 0 when every work item ran;
+ * bit 0 set if a dependency wait timed out, bit 1 if vec_ptr[B] exceeded
+ * total_nnz_x (the affected rows of Y are not valid). Synchronizes the
+ * stream. */
+spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
 
 /* ---------------------------------------------------------------------
  * Backward of y = A(vals) x for L(y): with g = dL/dy,

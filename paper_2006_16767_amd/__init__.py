@@ -224,6 +224,11 @@ class Matrix:
         _lib.call("run_batch", self._h, B, tot, _ptr(vec_ptr), _ptr(idx), _ptr(val), _ptr(Y), _stream(stream))
         return Y
 
+    def batch_status(self, stream=None) -> int:
+        f = C.c_int32()
+        _lib.call("spx_batch_status", self._h, C.byref(f), _stream(stream))
+        return f.value
+
     def transpose_matvec(self, G, dX=None, stream=None):
         """dX[b] = A^T G[b]; G is B x m (or m)."""
         torch = _torch()

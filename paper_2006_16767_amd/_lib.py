@@ -77,6 +77,7 @@ SIGNATURES = {
     "spx_stage_times": (C.c_int, [P, C.POINTER(C.c_double)]),
     "spx_run_times": (C.c_int, [P, C.POINTER(C.c_double), _i32, C.POINTER(_i32)]),
     "run_batch": (C.c_int, [P, _i32, C.c_int64, P, P, P, P, P]),
+    "spx_batch_status": (C.c_int, [P, C.POINTER(_i32), P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),
     "spx_check_csr": (C.c_int, [C.POINTER(Csr)]),

@@ -139,9 +139,24 @@ struct spx_matrix {
     int32_t* scratch_i32 = nullptr;  // compaction workspace
     int64_t* dev_scalars = nullptr;  // 4 x int64 (feature reductions, counts)
     uint32_t* bucket_cursor = nullptr;
+    // merge-path partitions of the balanced row-major kernels, per tile size,
+    // for A (index 0) and for A^T (index 1)
+    int32_t* part[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* ws = nullptr;
     size_t ws_bytes = 0;
     spx_plan last_plan{};
+    // batched path: device copy of the trees, workspace, captured graph
+    DevSelector* dev_sel = nullptr;
+    void* bws = nullptr;
+    size_t bws_bytes = 0;
+    int32_t bcap_B = 0;
+    int64_t bcap_nnz = 0;
+    int32_t* berr = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void* gkey[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t gkey_B = -1;
     // profiling
     int profiling = 0;
     double host_ms[2] = {0, 0};
@@ -156,6 +171,23 @@ static spx_status ensure_ws(spx_matrix* H, size_t bytes) {
     const size_t b = align_up(bytes, 1 << 20);
     if (hipMalloc(&H->ws, b) != hipSuccess) return fail(SPX_ERR_ALLOC, "workspace allocation failed");
     H->ws_bytes = b;
+    return SPX_OK;
+}
+
+// Cached merge-path partition of the balanced row-major kernels.
+static spx_status cached_part(spx_matrix* H, const spx_csr& A, int which, const spx_plan* p, hipStream_t s,
+                              const int32_t** out) {
+    *out = nullptr;
+    if (p->distribution != SPX_DIST_BALANCED) return SPX_OK;
+    const int tile = p->tile == 4096 ? 4096 : 2048;
+    const int ti = tile == 4096 ? 1 : 0;
+    if (!H->part[which][ti]) {
+        const int64_t tiles = ceil_div((int64_t)A.m + A.nnz, tile);
+        if (hipMalloc((void**)&H->part[which][ti], (size_t)(2 * (tiles + 1)) * 4) != hipSuccess)
+            return fail(SPX_ERR_ALLOC, "partition allocation failed");
+        SPX_TRY(merge_partition(A.m, A.nnz, A.row_ptr, tile, H->part[which][ti], s));
+    }
+    *out = H->part[which][ti];
     return SPX_OK;
 }
 
@@ -183,6 +215,21 @@ static spx_csc handle_csc(const spx_matrix* H) {
     c.row_idx = H->row_idx;
     c.vals = H->vals_csc;
     return c;
+}
+
+static spx_status upload_selector(spx_matrix* H) {
+    if (!H->dev_sel && hipMalloc((void**)&H->dev_sel, sizeof(DevSelector)) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "device selector allocation failed");
+    DevSelector* h = new (std::nothrow) DevSelector();
+    if (!h) return fail(SPX_ERR_ALLOC, "selector staging");
+    upload_tree(H->sel.pattern, &h->t[0]);
+    for (int p = 0; p < 3; ++p) upload_tree(H->sel.distribution[p], &h->t[1 + p]);
+    upload_tree(H->sel.writeback, &h->t[4]);
+    for (int i = 0; i < 9; ++i) h->mfeat[i] = H->feat[i];
+    hipError_t e = hipMemcpy(H->dev_sel, h, sizeof(DevSelector), hipMemcpyHostToDevice);
+    delete h;
+    if (e != hipSuccess) return hip_fail(e, "upload selector");
+    return SPX_OK;
 }
 
 static Selector& global_selector() {
@@ -265,7 +312,7 @@ extern "C" spx_status spmv_csr(const spx_csr* A, const void* x, void* y, const s
     if (plan->pattern != SPX_PAT_SPMV) return fail(SPX_ERR_ARG, "spmv_csr needs pattern SPX_PAT_SPMV");
     if ((A->n > 0 && !x) || (A->m > 0 && !y)) return fail(SPX_ERR_ARG, "x or y is null");
     Arena ws(workspace, ws_bytes);
-    return launch_spmv_csr(A, x, nullptr, y, plan, ws, (hipStream_t)stream);
+    return launch_spmv_csr(A, x, nullptr, y, plan, nullptr, ws, (hipStream_t)stream);
 }
 
 extern "C" spx_status spmspv_csr(const spx_csr* A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
@@ -287,7 +334,7 @@ extern "C" spx_status spmspv_csr(const spx_csr* A, int32_t nnz_x, const int32_t*
     if (!bits || !xd) return fail(SPX_ERR_WORKSPACE, "spmspv_csr: workspace too small");
     SPX_TRY(sparse_to_bitvector(A->n, nnz_x, x_idx, x_val, A->dtype, bits,
                                 A->dtype == SPX_BOOL ? nullptr : xd, s));
-    return launch_spmv_csr(A, A->dtype == SPX_BOOL ? nullptr : xd, bits, y, plan, ws, s);
+    return launch_spmv_csr(A, A->dtype == SPX_BOOL ? nullptr : xd, bits, y, plan, nullptr, ws, s);
 }
 
 extern "C" spx_status spmspv_csc(const spx_csc* A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
@@ -309,8 +356,12 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     int cur = 0;
     hipGetDevice(&cur);
     hipSetDevice(H->device);
+    if (H->gexec) hipGraphExecDestroy(H->gexec);
+    if (H->graph) hipGraphDestroy(H->graph);
+    if (H->cap_stream) hipStreamDestroy(H->cap_stream);
     void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->bits, H->xd, H->sp_idx,
-                    H->sp_val, H->scratch_i32, H->dev_scalars, H->bucket_cursor, H->ws};
+                    H->sp_val, H->scratch_i32, H->dev_scalars, H->bucket_cursor, H->ws,
+                    H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (auto& e : H->ev_conv) {
@@ -416,6 +467,7 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
         st = matrix_features_device(A->row_ptr, A->m, A->n, &ms, s);
         if (st == SPX_OK) std::memcpy(H->feat, ms.f, sizeof(H->feat));
     }
+    if (st == SPX_OK) st = upload_selector(H);
     if (st != SPX_OK) {
         std::string keep = g_err;
         spx_matrix_destroy(H);
@@ -586,7 +638,10 @@ extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
         if (!parse_selector_json(ss.str(), &s, &err)) return fail(SPX_ERR_ARG, "selector: " + err);
     }
     global_selector() = s;
-    if (H) H->sel = s;
+    if (H) {
+        H->sel = s;
+        SPX_TRY(upload_selector(H));
+    }
     return SPX_OK;
 }
 
@@ -621,8 +676,10 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         }
         SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
         Arena ws(H->ws, H->ws_bytes);
+        const int32_t* part = nullptr;
+        SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
-        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, ws, s));
+        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s));
         record(H, H->ev_kern, false, s);
         return SPX_OK;
     }
@@ -646,8 +703,10 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         record(H, H->ev_conv, false, s);
         SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
         Arena ws(H->ws, H->ws_bytes);
+        const int32_t* part = nullptr;
+        SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
-        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, ws, s));
+        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, part, ws, s));
         record(H, H->ev_kern, false, s);
         return SPX_OK;
     }
@@ -756,10 +815,105 @@ extern "C" spx_status spx_stage_times(const spx_matrix* Hc, double* out4) {
 }
 
 // ------------------------------------------------------------------ batch (device-side selection)
+static int lanes_for(double avg) {
+    int L = 1;
+    while (L < 64 && L < avg) L <<= 1;
+    return L;
+}
+
 extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, const int32_t* vec_ptr,
                                 const int32_t* idx, const void* val, void* Y, void* stream) {
-    (void)H; (void)B; (void)total_nnz_x; (void)vec_ptr; (void)idx; (void)val; (void)Y; (void)stream;
-    return fail(SPX_ERR_UNSUPPORTED, "run_batch is not built yet");
+    if (!H) return fail(SPX_ERR_ARG, "handle is null");
+    if (B < 0 || total_nnz_x < 0) return fail(SPX_ERR_SHAPE, "B and total_nnz_x must be >= 0");
+    if (B == 0) return SPX_OK;
+    const spx_csr& A = H->csr;
+    if (!vec_ptr || (total_nnz_x > 0 && (!idx || (A.dtype != SPX_BOOL && !val))) || (A.m > 0 && !Y))
+        return fail(SPX_ERR_ARG, "run_batch: null array");
+    if (total_nnz_x > (int64_t)B * A.n) return fail(SPX_ERR_SHAPE, "total_nnz_x exceeds B * n");
+    hipStream_t s = (hipStream_t)stream;
+    const spx_plan bal{SPX_PAT_SPMV, SPX_DIST_BALANCED, SPX_WB_NONE, 0, 0, 0};
+    const int32_t* part = nullptr;
+    SPX_TRY(cached_part(H, A, 0, &bal, s, &part));
+    const int64_t tiles_mat = ceil_div((int64_t)A.m + A.nnz, 2048);
+    // capacity-bounded workspace, zeroed at allocation (the per-vector
+    // bitvector and value slots are self-cleaning afterwards)
+    if (B > H->bcap_B || total_nnz_x > H->bcap_nnz) {
+        const int32_t nb = std::max(B, H->bcap_B);
+        const int64_t nn = std::max(total_nnz_x, H->bcap_nnz);
+        size_t zf = 0, zb = 0;
+        const size_t bytes = batch_ws_size(A.m, A.n, A.dtype, nb, nn, tiles_mat, &zf, &zb);
+        SPX_HIP(hipStreamSynchronize(s));
+        if (H->bws) SPX_HIP(hipFree(H->bws));
+        H->bws = nullptr;
+        if (hipMalloc(&H->bws, bytes) != hipSuccess) {
+            H->bcap_B = 0;
+            H->bcap_nnz = 0;
+            return fail(SPX_ERR_ALLOC, "run_batch: workspace allocation failed");
+        }
+        SPX_HIP(hipMemset((char*)H->bws + zf, 0, zb));
+        SPX_HIP(hipDeviceSynchronize());
+        H->bws_bytes = bytes;
+        H->bcap_B = nb;
+        H->bcap_nnz = nn;
+        H->gkey_B = -1;  // the captured graph points at the old workspace
+    }
+    BatchLaunch L{};
+    L.csr = A;
+    L.col_ptr = H->col_ptr;
+    L.row_idx = H->row_idx;
+    L.vals_csc = H->vals_csc;
+    L.part = part;
+    L.tiles_mat = tiles_mat;
+    L.B = B;
+    L.cap_nnz_x = H->bcap_nnz;
+    L.vec_ptr = vec_ptr;
+    L.idx = idx;
+    L.val = val;
+    L.Y = Y;
+    L.sel = H->dev_sel;
+    L.row_lanes = lanes_for(H->feat[5]);
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    L.persistent_grid = std::max(1, cus) * 4;
+    // the graph is keyed by everything its kernel arguments capture
+    const void* key[5] = {vec_ptr, idx, val, Y, H->bws};
+    const bool same = H->gexec && H->gkey_B == B && std::equal(key, key + 5, H->gkey);
+    if (!same) {
+        if (H->gexec) hipGraphExecDestroy(H->gexec);
+        if (H->graph) hipGraphDestroy(H->graph);
+        H->gexec = nullptr;
+        H->graph = nullptr;
+        if (!H->cap_stream) SPX_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+        SPX_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+        spx_status st = launch_batch(L, H->bws, H->bws_bytes, H->cap_stream, &H->berr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(H->cap_stream, &g);
+        if (st != SPX_OK) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&H->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        H->graph = g;
+        std::copy(key, key + 5, H->gkey);
+        H->gkey_B = B;
+    }
+    SPX_HIP(hipGraphLaunch(H->gexec, s));
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stream) {
+    if (!H || !flags) return fail(SPX_ERR_ARG, "null argument");
+    *flags = 0;
+    if (!H->berr) return SPX_OK;
+    SPX_HIP(hipMemcpyAsync(flags, H->berr, 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    SPX_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return SPX_OK;
 }
 
 // ------------------------------------------------------------------ backward
@@ -774,11 +928,13 @@ extern "C" spx_status spmv_csr_transpose(spx_matrix* H, int32_t B, const void* G
     spx_plan p{SPX_PAT_SPMV, SPX_DIST_DIRECT, SPX_WB_NONE, 0, 0, 0};
     if (H->feat[3] > 16 * std::max(1.0, H->feat[5])) p.distribution = SPX_DIST_BALANCED;
     SPX_TRY(ensure_ws(H, ws_for(At.m, At.n, At.nnz, 0, dt, &p)));
+    const int32_t* part = nullptr;
+    SPX_TRY(cached_part(H, At, 1, &p, s, &part));
     const int vs = value_size(dt);
     for (int32_t b = 0; b < B; ++b) {
         Arena ws(H->ws, H->ws_bytes);
         SPX_TRY(launch_spmv_csr(&At, (const char*)G + (size_t)b * H->csr.m * vs, nullptr,
-                                (char*)dX + (size_t)b * H->csr.n * vs, &p, ws, s));
+                                (char*)dX + (size_t)b * H->csr.n * vs, &p, part, ws, s));
     }
     return SPX_OK;
 }

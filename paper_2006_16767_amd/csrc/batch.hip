@@ -1,0 +1,448 @@
+// Batched SpMSpV: B sparse vectors of uneven sparsity in one graph launch,
+// the plan of every vector chosen on the device.
+//
+//  k_batch_plan        one workgroup per vector: prefix sum of the lengths of
+//                      the columns it selects (its nnz_s falls out), then the
+//                      three decision trees evaluated on the Table 1 features
+//                      (matrix features + nnz_x, x_sparsity, nnz_s,
+//                      m_sparsity), and the vector's work-item counts for
+//                      the three phases of its plan.
+//  k_batch_scan        prefix sums of the counts: one ordered queue per
+//                      phase; resets the queue heads.
+//  k_batch_phase<A|B|C>  #CUs x 4 persistent workgroups pop the items of one
+//                      phase until its queue is drained (every workgroup
+//                      exits once the queue head passes the item count):
+//                        A: row-major plans scatter x into the vector's
+//                           bitvector / value slots; column-major plans zero
+//                           the vector's row of Y
+//                        B: one merge-path tile (or one row/entry chunk of the
+//                           direct distribution) of the vector's kernel
+//                        C: row-major balanced fix-up of tile carries, and the
+//                           self-cleaning of the bitvector / value slots
+//                      Items of one phase never wait for each other: the
+//                      ordering between phases is the kernel boundary.
+//
+// The launches are captured once into a HIP graph by the caller and
+// replayed. The per-vector bitvector and value slots are zero when a run
+// starts and are cleared again by phase C, so no fill is recorded in the
+// graph. Column-major plans write back with device atomics (the sort and
+// bucket write-backs need per-vector pair buffers sized by nnz_s, which the
+// host does not know without a sync).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "csc_tile.hpp"
+#include "csr_tile.hpp"
+#include "internal.hpp"
+
+namespace spx {
+
+constexpr int kBatchTile = 2048;     // merge tile (row-major and column-major)
+constexpr int kFillChunk = 65536;    // rows of Y zeroed per phase-A item
+constexpr int kScatterChunk = 2048;  // x entries scattered / cleared per item
+constexpr int kCscDirectEntries = 64;
+constexpr int kCscDirectLanes = 4;
+
+struct BatchPlan {
+    int32_t pattern, dist, wb, lanes;
+    int32_t nnz_x, base;
+    int32_t nA, nB, nC;
+    int64_t nnz_s;
+};
+
+struct BatchDev {
+    int32_t m, n, nnz;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const void* vals;
+    const int32_t* col_ptr;
+    const int32_t* row_idx;
+    const void* vals_csc;
+    const int32_t* part;
+    int64_t tiles_mat;
+    int32_t B;
+    int64_t cap_nnz_x;  // capacity of the per-entry arrays (host bound of vec_ptr[B])
+    const int32_t* vec_ptr;
+    const int32_t* idx;
+    const void* val;
+    void* Y;
+    const DevSelector* sel;
+    int32_t row_lanes;  // lanes per row of the row-major direct distribution
+    // workspace
+    BatchPlan* plans;
+    int32_t* offs;    // 3 x (B + 1)
+    int32_t* totals;  // 4
+    int32_t* queue;   // 3 queue heads, one per phase
+    int32_t* err;
+    int32_t* excl_all;  // cap_nnz_x + B
+    uint32_t* bits_all;  // B x nwords
+    void* xd_all;        // B x n values
+    int32_t* carry_row_all;  // B x tiles_mat
+    void* carry_val_all;     // B x tiles_mat accumulators
+    int64_t nwords;
+};
+
+__device__ __forceinline__ int dev_tree_eval(const DevTree& t, const double* f) {
+    int i = 0;
+    for (int guard = 0; guard < 64 && i >= 0 && i < t.n; ++guard) {
+        if (t.cls[i] >= 0) return t.cls[i];
+        const int fi = t.feat[i];
+        i = (fi >= 0 && fi < 13 && f[fi] <= t.thr[i]) ? t.left[i] : t.right[i];
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------------ plan
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
+    __shared__ int32_t s_tmp[kWavesPerBlock];
+    const int b = blockIdx.x;
+    const int base = a.vec_ptr[b];
+    const int nx = a.vec_ptr[b + 1] - base;
+    if (base < 0 || nx < 0 || (int64_t)a.vec_ptr[a.B] > a.cap_nnz_x || nx > a.n) {
+        // vec_ptr disagrees with the capacity the host sized: no work, flag it
+        if (threadIdx.x == 0) {
+            BatchPlan z{};
+            a.plans[b] = z;
+            atomicOr(a.err, 2);
+        }
+        return;
+    }
+    int32_t* excl = a.excl_all + base + b;
+    const int32_t* idx = a.idx + base;
+    constexpr int kIpt = 8;
+    int32_t carry = 0;
+    for (int c0 = 0; c0 < nx; c0 += kBlock * kIpt) {
+        int32_t len[kIpt];
+        int32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i) {
+            const int e = c0 + threadIdx.x * kIpt + i;
+            len[i] = 0;
+            if (e < nx) {
+                const int j = idx[e];
+                len[i] = a.col_ptr[j + 1] - a.col_ptr[j];
+            }
+            sum += len[i];
+        }
+        int32_t tot;
+        const int32_t incl = block_incl_scan(sum, s_tmp, &tot);
+        int32_t run = carry + incl - sum;
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i) {
+            const int e = c0 + threadIdx.x * kIpt + i;
+            if (e < nx) excl[e] = run;
+            run += len[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x != 0) return;
+    excl[nx] = carry;
+    const DevSelector& S = *a.sel;
+    double f[13];
+    for (int i = 0; i < 9; ++i) f[i] = S.mfeat[i];
+    f[9] = nx;
+    f[10] = a.n > 0 ? (double)nx / a.n : 0.0;
+    f[11] = carry;
+    f[12] = a.nnz > 0 ? (double)carry / a.nnz : 0.0;
+    BatchPlan p;
+    p.pattern = dev_tree_eval(S.t[0], f);
+    if (p.pattern < 0 || p.pattern > 2) p.pattern = 0;
+    p.dist = dev_tree_eval(S.t[1 + p.pattern], f) == SPX_DIST_BALANCED ? SPX_DIST_BALANCED : SPX_DIST_DIRECT;
+    p.wb = p.pattern == SPX_PAT_CSC_SPMSPV ? SPX_WB_ATOMIC : SPX_WB_NONE;
+    p.lanes = a.row_lanes;
+    p.nnz_x = nx;
+    p.base = base;
+    p.nnz_s = carry;
+    if (p.pattern == SPX_PAT_CSC_SPMSPV) {
+        p.nA = (int32_t)ceil_div(a.m, kFillChunk);
+        p.nB = p.dist == SPX_DIST_BALANCED ? (int32_t)ceil_div((int64_t)nx + carry, kBatchTile)
+                                           : (int32_t)ceil_div(nx, kCscDirectEntries);
+        p.nC = 0;
+    } else {
+        const int64_t rows_per_item = (int64_t)(kBlock / a.row_lanes) * 8;
+        p.nA = (int32_t)ceil_div(nx, kScatterChunk);
+        p.nB = p.dist == SPX_DIST_BALANCED ? (int32_t)a.tiles_mat : (int32_t)ceil_div(a.m, rows_per_item);
+        p.nC = (p.dist == SPX_DIST_BALANCED ? 1 : 0) + (int32_t)ceil_div(nx, kScatterChunk);
+    }
+    a.plans[b] = p;
+}
+
+__global__ void k_batch_reset(int32_t* err) { *err = 0; }
+
+// ------------------------------------------------------------------ queue
+__global__ __launch_bounds__(kBlock) void k_batch_scan(BatchDev a) {
+    __shared__ int32_t s_tmp[kWavesPerBlock];
+    for (int ph = 0; ph < 3; ++ph) {
+        int32_t* off = a.offs + ph * (a.B + 1);
+        int32_t carry = 0;
+        for (int c0 = 0; c0 < a.B; c0 += kBlock) {
+            const int b = c0 + threadIdx.x;
+            int32_t v = 0;
+            if (b < a.B) v = ph == 0 ? a.plans[b].nA : (ph == 1 ? a.plans[b].nB : a.plans[b].nC);
+            int32_t tot;
+            const int32_t incl = block_incl_scan(v, s_tmp, &tot);
+            if (b < a.B) off[b] = carry + incl - v;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) {
+            off[a.B] = carry;
+            a.totals[ph] = carry;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) a.queue[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ persistent
+template <int DT>
+union BatchLds {
+    CsrTileLds<DT, kBatchTile> csr;
+    CscTileLds<DT> csc;
+};
+
+// last b with off[b] <= item (off has B + 1 entries, non-decreasing)
+__device__ __forceinline__ int find_vector(const int32_t* off, int B, int item) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int DT, int L>
+__device__ __forceinline__ void batch_rows_direct(const BatchDev& a, int64_t r0, int64_t r1, bool valid,
+                                                  const typename SR<DT>::X* xd, const uint32_t* bits,
+                                                  typename SR<DT>::Y* y) {
+    using S = SR<DT>;
+    const auto* vals = (const typename S::V*)a.vals;
+    constexpr int G = kBlock / L;
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    for (int64_t row = r0 + g; row < r1; row += G) {
+        const int k0 = a.row_ptr[row], k1 = a.row_ptr[row + 1];
+        typename S::Acc acc = S::zero();
+        for (int k = k0 + lane; k < k1; k += L) {
+            const int c = a.col_idx[k];
+            if (!valid || test_bit(bits, c)) acc = S::fma(S::val(vals, k), S::xval(xd, c), acc);
+        }
+        acc = group_reduce<DT, L>(acc);
+        if (lane == 0) y[row] = S::out(acc);
+    }
+}
+
+template <int DT, int PH>
+__global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    __shared__ BatchLds<DT> L;
+    __shared__ int32_t s_item;
+    const int32_t total = a.totals[PH];
+    constexpr int ph = PH;
+    const auto* vals = (const typename S::V*)a.vals;
+    const auto* vals_csc = (const typename S::V*)a.vals_csc;
+    const auto* xval_all = (const typename S::X*)a.val;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue + PH, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int local = item;
+        const int32_t* off = a.offs + ph * (a.B + 1);
+        const int b = find_vector(off, a.B, local);
+        const int j = local - off[b];
+        const BatchPlan p = a.plans[b];
+        auto* Yb = (typename S::Y*)a.Y + (int64_t)b * a.m;
+        uint32_t* bits = a.bits_all + (int64_t)b * a.nwords;
+        auto* xd = S::kVals ? (typename S::X*)a.xd_all + (int64_t)b * a.n : (typename S::X*)nullptr;
+        const int32_t* idx = a.idx + p.base;
+        const typename S::X* xv = S::kVals ? xval_all + p.base : nullptr;
+        const bool csc = p.pattern == SPX_PAT_CSC_SPMSPV;
+        if constexpr (PH == 0) {
+            if (csc) {
+                const int64_t r0 = (int64_t)j * kFillChunk;
+                const int64_t r1 = std::min<int64_t>(r0 + kFillChunk, a.m);
+                for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) Yb[r] = (typename S::Y)0;
+            } else {
+                const int e1 = std::min(p.nnz_x, (j + 1) * kScatterChunk);
+                for (int e = j * kScatterChunk + threadIdx.x; e < e1; e += kBlock) {
+                    const int c = idx[e];
+                    atomicOr(&bits[c >> 5], 1u << (c & 31));
+                    if constexpr (S::kVals) xd[c] = xv[e];
+                }
+            }
+        } else if constexpr (PH == 1) {
+            if (csc) {
+                const int32_t* excl = a.excl_all + p.base + b;
+                if (p.dist == SPX_DIST_BALANCED) {
+                    csc_merge_tile<DT>(j, p.nnz_x, p.nnz_s, idx, xv, a.col_ptr, a.row_idx, vals_csc, excl,
+                                       EmitAtomic<DT>{Yb}, L.csc);
+                } else {
+                    const int e = j * kCscDirectEntries + threadIdx.x / kCscDirectLanes;
+                    if (e < p.nnz_x)
+                        csc_direct_entry<DT, kCscDirectLanes>(e, threadIdx.x % kCscDirectLanes, idx, xv, a.col_ptr,
+                                                              a.row_idx, vals_csc, nullptr, EmitAtomic<DT>{Yb});
+                }
+            } else {
+                const bool valid = p.pattern == SPX_PAT_CSR_SPMSPV || DT == SPX_BOOL;
+                if (p.dist == SPX_DIST_BALANCED) {
+                    int32_t* crow = a.carry_row_all + (int64_t)b * a.tiles_mat;
+                    Acc* cval = (Acc*)a.carry_val_all + (int64_t)b * a.tiles_mat;
+                    if (valid)
+                        csr_merge_tile<DT, true, kBatchTile>(j, a.m, a.row_ptr, a.col_idx, vals, xd, bits, Yb, a.part,
+                                                             crow, cval, L.csr);
+                    else
+                        csr_merge_tile<DT, false, kBatchTile>(j, a.m, a.row_ptr, a.col_idx, vals, xd, bits, Yb, a.part,
+                                                              crow, cval, L.csr);
+                } else {
+                    const int64_t rpi = (int64_t)(kBlock / p.lanes) * 8;
+                    const int64_t r0 = (int64_t)j * rpi, r1 = std::min<int64_t>(r0 + rpi, a.m);
+                    switch (p.lanes) {
+                        case 1: batch_rows_direct<DT, 1>(a, r0, r1, valid, xd, bits, Yb); break;
+                        case 2: batch_rows_direct<DT, 2>(a, r0, r1, valid, xd, bits, Yb); break;
+                        case 4: batch_rows_direct<DT, 4>(a, r0, r1, valid, xd, bits, Yb); break;
+                        case 8: batch_rows_direct<DT, 8>(a, r0, r1, valid, xd, bits, Yb); break;
+                        case 16: batch_rows_direct<DT, 16>(a, r0, r1, valid, xd, bits, Yb); break;
+                        case 32: batch_rows_direct<DT, 32>(a, r0, r1, valid, xd, bits, Yb); break;
+                        default: batch_rows_direct<DT, 64>(a, r0, r1, valid, xd, bits, Yb); break;
+                    }
+                }
+            }
+        } else {
+            int jj = j;
+            if (p.dist == SPX_DIST_BALANCED) {
+                if (jj == 0) {
+                    csr_merge_fixup_range<DT>(threadIdx.x, kBlock, a.tiles_mat, a.carry_row_all + (int64_t)b * a.tiles_mat,
+                                              (const Acc*)a.carry_val_all + (int64_t)b * a.tiles_mat, Yb);
+                }
+                --jj;
+            }
+            if (jj >= 0) {
+                const int e1 = std::min(p.nnz_x, (jj + 1) * kScatterChunk);
+                for (int e = jj * kScatterChunk + threadIdx.x; e < e1; e += kBlock) {
+                    const int c = idx[e];
+                    bits[c >> 5] = 0u;
+                    if constexpr (S::kVals) xd[c] = (typename S::X)0;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
+                         BatchDev* d, char* base, size_t* bytes) {
+    Sizer z;
+    size_t off[16];
+    int k = 0;
+    auto take = [&](size_t n_bytes) {
+        z.used = align_up(z.used, 256);
+        off[k++] = z.used;
+        z.used += align_up(n_bytes, 256);
+    };
+    const int vs = std::max(1, value_size(dtype));
+    const int as = dtype == SPX_F64 ? 8 : 4;
+    const int64_t nwords = ceil_div(n, 32) + 1;
+    take(sizeof(BatchPlan) * (size_t)B);                 // 0 plans
+    take(4 * (size_t)3 * (B + 1));                       // 1 offs
+    take(4 * 4);                                          // 2 totals
+    take(4 * 4);                                          // 3 queue heads, err
+    take(4);                                              // 4 (unused)
+    take(4 * (size_t)(cap_nnz_x + B));                    // 5 excl
+    take(4 * (size_t)B * nwords);                         // 6 bits (self-cleaning)
+    take((size_t)vs * B * (size_t)n);                     // 7 xd (self-cleaning)
+    take(4 * (size_t)B * tiles_mat);                      // 8 carry rows
+    take((size_t)as * B * tiles_mat);                     // 9 carry values
+    *bytes = z.used;
+    if (!d || !base) return;
+    d->plans = (BatchPlan*)(base + off[0]);
+    d->offs = (int32_t*)(base + off[1]);
+    d->totals = (int32_t*)(base + off[2]);
+    d->queue = (int32_t*)(base + off[3]);
+    d->err = d->queue + 3;
+    d->excl_all = (int32_t*)(base + off[5]);
+    d->bits_all = (uint32_t*)(base + off[6]);
+    d->xd_all = base + off[7];
+    d->carry_row_all = (int32_t*)(base + off[8]);
+    d->carry_val_all = base + off[9];
+    d->nwords = nwords;
+}
+
+size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
+                     size_t* zero_from, size_t* zero_bytes) {
+    size_t bytes = 0;
+    batch_layout(m, n, dtype, B, cap_nnz_x, tiles_mat, nullptr, nullptr, &bytes);
+    // the whole workspace is zeroed at allocation; only the bitvector and
+    // value slots rely on it (they are self-cleaning afterwards)
+    if (zero_from) *zero_from = 0;
+    if (zero_bytes) *zero_bytes = bytes;
+    return bytes;
+}
+
+spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev) {
+    BatchDev d{};
+    d.m = L.csr.m;
+    d.n = L.csr.n;
+    d.nnz = L.csr.nnz;
+    d.row_ptr = L.csr.row_ptr;
+    d.col_idx = L.csr.col_idx;
+    d.vals = L.csr.vals;
+    d.col_ptr = L.col_ptr;
+    d.row_idx = L.row_idx;
+    d.vals_csc = L.vals_csc;
+    d.part = L.part;
+    d.tiles_mat = L.tiles_mat;
+    d.B = L.B;
+    d.cap_nnz_x = L.cap_nnz_x;
+    d.vec_ptr = L.vec_ptr;
+    d.idx = L.idx;
+    d.val = L.val;
+    d.Y = L.Y;
+    d.sel = L.sel;
+    d.row_lanes = L.row_lanes;
+    size_t need = 0;
+    batch_layout(d.m, d.n, L.csr.dtype, L.B, L.cap_nnz_x, L.tiles_mat, &d, (char*)ws, &need);
+    if (need > ws_bytes) return fail(SPX_ERR_WORKSPACE, "run_batch: workspace too small");
+    if (err_dev) *err_dev = d.err;
+    if (L.B == 0) return SPX_OK;
+    switch (L.csr.dtype) {
+#define SPX_DT(DT)                                                            \
+    case DT:                                                                  \
+        k_batch_reset<<<1, 1, 0, s>>>(d.err);                                 \
+        k_batch_plan<DT><<<L.B, kBlock, 0, s>>>(d);                           \
+        k_batch_scan<<<1, kBlock, 0, s>>>(d);                                 \
+        k_batch_phase<DT, 0><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
+        k_batch_phase<DT, 1><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
+        k_batch_phase<DT, 2><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
+        break;
+        SPX_DT(SPX_F32)
+        SPX_DT(SPX_F64)
+        SPX_DT(SPX_I32)
+        SPX_DT(SPX_BOOL)
+#undef SPX_DT
+        default:
+            return fail(SPX_ERR_DTYPE, "run_batch: dtype");
+    }
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+void upload_tree(const Tree& t, DevTree* out) {
+    const int n = std::min<int>((int)t.cls.size(), kDevTreeNodes);
+    out->n = n;
+    for (int i = 0; i < n; ++i) {
+        out->feat[i] = t.feat[i];
+        out->thr[i] = t.thr[i];
+        out->left[i] = t.left[i];
+        out->right[i] = t.right[i];
+        out->cls[i] = t.cls[i];
+    }
+}
+
+}  // namespace spx

@@ -1,0 +1,134 @@
+// Merge-path tile of the row-major kernels (SpMV and bitvector-validated
+// SpMSpV), shared by the single-vector kernel and the batched persistent
+// kernel.
+#pragma once
+
+#include "common.hpp"
+
+namespace spx {
+
+// Workgroup b -> tile: each of the 8 XCDs (workgroups are dispatched to
+// them round-robin) gets one contiguous range of tiles, so neighbouring
+// tiles, which share x entries on matrices with locality, meet in the same
+// L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    constexpr int kXcd = 8;
+    const int64_t x = b % kXcd, j = b / kXcd;
+    const int64_t base = G / kXcd, rem = G % kXcd;
+    return x * base + (x < rem ? x : rem) + j;
+}
+
+constexpr int kShortRow = 32;
+
+template <int DT, int TILE>
+struct CsrTileLds {
+    int32_t end[TILE + 1];
+    typename SR<DT>::Acc prod[TILE];
+    int32_t lng[TILE + 1];
+    int32_t nlong;
+};
+
+// One tile: stage the products of its nonzeros in LDS with coalesced loads
+// (fully unrolled, so all gathers of a thread are in flight together), then
+// reduce every row whose end falls in the tile from LDS: short rows by one
+// thread, rows longer than kShortRow by a whole wave. The row still open at
+// the tile end leaves a carry for the fix-up pass (carry_row = -1 if none).
+// Ends with __syncthreads.
+template <int DT, bool VALID, int TILE>
+__device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col_idx,
+                                               const typename SR<DT>::V* __restrict__ vals,
+                                               const typename SR<DT>::X* __restrict__ x,
+                                               const uint32_t* __restrict__ bits,
+                                               typename SR<DT>::Y* __restrict__ y,
+                                               const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
+                                               typename SR<DT>::Acc* __restrict__ carry_val,
+                                               CsrTileLds<DT, TILE>& L) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    constexpr int kIpt = TILE / kBlock;
+    const int i0 = part[2 * tile], k0 = part[2 * tile + 1];
+    const int i1 = part[2 * tile + 2], k1 = part[2 * tile + 3];
+    const int R = i1 - i0;  // rows whose end lies in this tile
+    const int Q = k1 - k0;  // nonzeros of this tile
+    const bool open = i1 < m && k1 > row_ptr[i1];
+    if (threadIdx.x == 0) L.nlong = 0;
+    for (int r = threadIdx.x; r < R; r += kBlock) L.end[r] = row_ptr[i0 + 1 + r];
+#pragma unroll
+    for (int it = 0; it < kIpt; ++it) {
+        const int q = it * kBlock + threadIdx.x;
+        if (q < Q) {
+            const int k = k0 + q;
+            const int c = col_idx[k];
+            Acc p;
+            if constexpr (VALID)
+                p = test_bit(bits, c) ? S::mul(S::val(vals, k), S::xval(x, c)) : S::zero();
+            else
+                p = S::mul(S::val(vals, k), S::xval(x, c));
+            L.prod[q] = p;
+        }
+    }
+    __syncthreads();
+    const int nrows = R + (open ? 1 : 0);
+    for (int r = threadIdx.x; r < nrows; r += kBlock) {
+        const int a = (r == 0 ? k0 : L.end[r - 1]) - k0;
+        const int e = (r < R ? L.end[r] : k1) - k0;
+        if (e - a <= kShortRow) {
+            Acc acc = S::zero();
+            for (int q = a; q < e; ++q) acc = S::add(acc, L.prod[q]);
+            if (r < R) {
+                y[i0 + r] = S::out(acc);
+            } else {
+                carry_row[tile] = i1;
+                carry_val[tile] = acc;
+            }
+        } else {
+            L.lng[atomicAdd(&L.nlong, 1)] = r;
+        }
+    }
+    __syncthreads();
+    const int nl = L.nlong;
+    for (int li = wave_id(); li < nl; li += kWavesPerBlock) {
+        const int r = L.lng[li];
+        const int a = (r == 0 ? k0 : L.end[r - 1]) - k0;
+        const int e = (r < R ? L.end[r] : k1) - k0;
+        Acc acc = S::zero();
+        for (int q = a + lane_id(); q < e; q += kWave) acc = S::add(acc, L.prod[q]);
+        acc = group_reduce<DT, kWave>(acc);
+        if (lane_id() == 0) {
+            if (r < R) {
+                y[i0 + r] = S::out(acc);
+            } else {
+                carry_row[tile] = i1;
+                carry_val[tile] = acc;
+            }
+        }
+    }
+    if (!open && threadIdx.x == 0) carry_row[tile] = -1;
+    __syncthreads();
+}
+
+// Carries of tiles whose last row continues, added in tile order by the
+// first tile of each run of equal carry_row (deterministic). Threads of the
+// calling group take tiles t = first, first + stride, ...
+template <int DT>
+__device__ __forceinline__ void csr_merge_fixup_range(int64_t first, int64_t stride, int64_t tiles,
+                                                      const int32_t* __restrict__ carry_row,
+                                                      const typename SR<DT>::Acc* __restrict__ carry_val,
+                                                      typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    for (int64_t t = first; t < tiles; t += stride) {
+        const int row = carry_row[t];
+        if (row < 0) continue;
+        if (t > 0 && carry_row[t - 1] == row) continue;
+        typename S::Acc acc = S::zero();
+        for (int64_t u = t; u < tiles && carry_row[u] == row; ++u) acc = S::add(acc, carry_val[u]);
+        if constexpr (DT == SPX_BOOL) {
+            if (acc) y[row] = 1;
+        } else {
+            y[row] = S::out(S::add((typename S::Acc)y[row], acc));
+        }
+    }
+}
+
+}  // namespace spx

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/spx.h"
+#include "selector.hpp"
 
 namespace spx {
 
@@ -81,8 +82,12 @@ spx_status gather_perm(const void* in, const int32_t* perm, void* out, int64_t n
                        hipStream_t s);
 
 // ------------------------------------------------------------------ kernels
+// part: merge-path partition of the balanced distribution (null: computed
+// into the workspace on this call)
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                           const spx_plan* plan, Arena& ws, hipStream_t s);
+                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s);
+spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int tile, int32_t* part,
+                           hipStream_t s);
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan);
 
 struct CscArgs {
@@ -125,6 +130,41 @@ spx_status matrix_features_device(const int32_t* row_ptr, int32_t m, int32_t n,
 // nnz_s (and nnz_x for a dense x) on the device into out2[0..1] (int64)
 spx_status vector_features_device(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,
                                   int64_t* out2_dev, hipStream_t s);
+
+// batched SpMSpV (batch.hip)
+constexpr int kDevTreeNodes = 512;
+struct DevTree {
+    int32_t n;
+    int32_t feat[kDevTreeNodes], left[kDevTreeNodes], right[kDevTreeNodes], cls[kDevTreeNodes];
+    double thr[kDevTreeNodes];
+};
+// t[0] pattern, t[1 + pattern] distribution, t[4] write-back; mfeat = the
+// nine matrix features of Table 1
+struct DevSelector {
+    DevTree t[5];
+    double mfeat[9];
+};
+void upload_tree(const Tree& t, DevTree* out);
+struct BatchLaunch {
+    spx_csr csr;
+    const int32_t* col_ptr;
+    const int32_t* row_idx;
+    const void* vals_csc;
+    const int32_t* part;  // merge-path partition of A at tile 2048
+    int64_t tiles_mat;
+    int32_t B;
+    int64_t cap_nnz_x;
+    const int32_t* vec_ptr;
+    const int32_t* idx;
+    const void* val;
+    void* Y;
+    const DevSelector* sel;
+    int32_t row_lanes;
+    int32_t persistent_grid;
+};
+size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
+                     size_t* zero_from, size_t* zero_bytes);
+spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev);
 
 // backward
 spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n,

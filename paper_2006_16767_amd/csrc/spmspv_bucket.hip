@@ -57,6 +57,19 @@ struct BucketOut {
 };
 
 // ------------------------------------------------------------------ balanced scatter
+constexpr int kMergeChunks = 1024;  // chunk count of the balanced distribution (at most)
+
+// tiles per chunk, from the actual tile count (known on the device only)
+__host__ __device__ inline int64_t merge_tiles_per_chunk(int64_t tiles) {
+    return tiles > kMergeChunks ? (tiles + kMergeChunks - 1) / kMergeChunks : 1;
+}
+
+// Chunk c = merge tiles [c * S, (c + 1) * S): the workgroup walks its tiles
+// twice, first counting pairs per bucket, then writing each pair at the
+// chunk's start + the bucket's offset within the chunk + a slot taken from
+// an LDS cursor. With S tiles per chunk every (bucket, chunk) group is S
+// times longer than with one tile, so the pair stores and the accumulate
+// pass's loads move whole cache lines.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     int32_t nnz_x, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
@@ -64,49 +77,61 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     const typename SR<DT>::V* __restrict__ vals, const int32_t* __restrict__ excl, int logR, int NB,
     BucketOut<DT> out) {
     using S = SR<DT>;
-    using Acc = typename S::Acc;
     __shared__ CscTileLds<DT> L;
     __shared__ int32_t s_cnt[kMaxBuckets];
     __shared__ int32_t s_off[kMaxBuckets];
     __shared__ int32_t s_tmp[kWavesPerBlock];
+    __shared__ int32_t s_p0;
     const int64_t nnz_s = excl[nnz_x];
     const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
-    const int64_t tile = blockIdx.x;
-    if (tile >= tiles) return;  // the accumulate pass reads only the first `tiles` chunks
+    const int64_t S_tiles = merge_tiles_per_chunk(tiles);
+    const int64_t chunk = blockIdx.x;
+    const int64_t t_begin = chunk * S_tiles;
+    if (t_begin >= tiles) return;  // the accumulate pass reads only the chunks that exist
+    const int64_t t_end = t_begin + S_tiles < tiles ? t_begin + S_tiles : tiles;
+    const int rmask = (1 << logR) - 1;
     for (int b = threadIdx.x; b < NB; b += kBlock) s_cnt[b] = 0;
-    const CscTile t = csc_tile_setup<DT>(tile, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
-    int32_t bkt[kCscIpt], slot[kCscIpt];
-    uint16_t lrow[kCscIpt];
-    Acc val[kCscIpt];
+    // pass 1: counts
+    for (int64_t tt = t_begin; tt < t_end; ++tt) {
+        const CscTile t = csc_tile_setup<DT>(tt, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
+        if (tt == t_begin && threadIdx.x == 0) s_p0 = t.p0;
 #pragma unroll
-    for (int i = 0; i < kCscIpt; ++i) {
-        const int p = t.p0 + threadIdx.x + i * kBlock;
-        bkt[i] = -1;
-        if (p < t.p1) {
-            const int u = csc_tile_locate<DT>(p, t, L);
-            const int k = L.cs[u] + (p - L.excl[u]);
-            const int r = row_idx[k];
-            val[i] = S::mul(S::val(vals, k), L.v[u]);
-            bkt[i] = r >> logR;
-            lrow[i] = (uint16_t)(r & ((1 << logR) - 1));
-            slot[i] = atomicAdd(&s_cnt[bkt[i]], 1);
+        for (int i = 0; i < kCscIpt; ++i) {
+            const int p = t.p0 + threadIdx.x + i * kBlock;
+            if (p < t.p1) {
+                const int u = csc_tile_locate<DT>(p, t, L);
+                atomicAdd(&s_cnt[row_idx[L.cs[u] + (p - L.excl[u])] >> logR], 1);
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     bucket_scan(s_cnt, s_off, NB, s_tmp);
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kCscIpt; ++i) {
-        if (bkt[i] >= 0) {
-            const int64_t pos = (int64_t)t.p0 + s_off[bkt[i]] + slot[i];
-            out.prow[pos] = lrow[i];
-            if constexpr (S::kVals) out.pval[pos] = val[i];
-        }
-    }
+    const int P0 = s_p0;
     for (int b = threadIdx.x; b < NB; b += kBlock) {
-        const int64_t mi = (int64_t)b * out.stride + tile;
-        out.moff[mi] = t.p0 + s_off[b];
+        const int64_t mi = (int64_t)b * out.stride + chunk;
+        out.moff[mi] = P0 + s_off[b];
         out.mcnt[mi] = s_cnt[b];
+        s_cnt[b] = 0;  // becomes the write cursor
+    }
+    __syncthreads();
+    // pass 2: pairs
+    for (int64_t tt = t_begin; tt < t_end; ++tt) {
+        const CscTile t = csc_tile_setup<DT>(tt, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
+#pragma unroll
+        for (int i = 0; i < kCscIpt; ++i) {
+            const int p = t.p0 + threadIdx.x + i * kBlock;
+            if (p < t.p1) {
+                const int u = csc_tile_locate<DT>(p, t, L);
+                const int k = L.cs[u] + (p - L.excl[u]);
+                const int r = row_idx[k];
+                const int b = r >> logR;
+                const int64_t pos = (int64_t)P0 + s_off[b] + atomicAdd(&s_cnt[b], 1);
+                out.prow[pos] = (uint16_t)(r & rmask);
+                if constexpr (S::kVals) out.pval[pos] = S::mul(S::val(vals, k), L.v[u]);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -161,39 +186,45 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_direct(
 }
 
 // ------------------------------------------------------------------ accumulate
-// nch_fixed >= 0: number of chunks; otherwise the merge-tile count derived
-// from excl[nnz_x]. The bucket's groups are taken kAccWin chunks at a time:
-// their counts are prefix-summed in LDS, which flattens the window into one
-// run of pairs that all 256 threads stream through (each pair finds its
-// chunk by a binary search in LDS), so the loads of different pairs are
-// independent and stay in flight together.
-constexpr int kAccWin = 2048;
+// One 1024-thread workgroup per bucket. nch_fixed >= 0: number of chunks;
+// otherwise derived from excl[nnz_x] and the tiles per chunk. The bucket's
+// groups are taken kAccWin chunks at a time: their counts are prefix-summed
+// in LDS, which flattens the window into one run of pairs that all threads
+// stream through (each pair finds its chunk by a binary search in LDS), four
+// independent pairs per thread per step.
+constexpr int kAccThreads = 1024;
+constexpr int kAccWin = 4096;
 
 template <int DT>
-__global__ __launch_bounds__(kBlock) void k_bucket_accumulate(int32_t m, int logR, int32_t nch_fixed,
-                                                              int32_t nnz_x, const int32_t* __restrict__ excl,
-                                                              const uint16_t* __restrict__ prow,
-                                                              const typename SR<DT>::Acc* __restrict__ pval,
-                                                              const int32_t* __restrict__ moff,
-                                                              const int32_t* __restrict__ mcnt, int32_t stride,
-                                                              typename SR<DT>::Y* __restrict__ y) {
+__global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, int logR, int32_t nch_fixed,
+                                                                   int32_t nnz_x,
+                                                                   const int32_t* __restrict__ excl,
+                                                                   const uint16_t* __restrict__ prow,
+                                                                   const typename SR<DT>::Acc* __restrict__ pval,
+                                                                   const int32_t* __restrict__ moff,
+                                                                   const int32_t* __restrict__ mcnt, int32_t stride,
+                                                                   typename SR<DT>::Y* __restrict__ y) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
+    constexpr int kWaves = kAccThreads / kWave;
     extern __shared__ char s_raw[];
     Acc* acc = (Acc*)s_raw;
     __shared__ int32_t s_pre[kAccWin + 1];
     __shared__ int32_t s_off[kAccWin];
-    __shared__ int32_t s_tmp[kWavesPerBlock];
+    __shared__ int32_t s_wsum[kWaves];
     const int R = 1 << logR;
     const int b = blockIdx.x;
-    for (int r = threadIdx.x; r < R; r += kBlock) acc[r] = S::zero();
-    const int64_t nch = nch_fixed >= 0 ? nch_fixed : ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);
+    for (int r = threadIdx.x; r < R; r += kAccThreads) acc[r] = S::zero();
+    int64_t nch = nch_fixed;
+    if (nch < 0) {
+        const int64_t tiles = ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);
+        nch = ceil_div(tiles, merge_tiles_per_chunk(tiles));
+    }
     const int32_t* mo = moff + (int64_t)b * stride;
     const int32_t* mc = mcnt + (int64_t)b * stride;
-    constexpr int kPer = kAccWin / kBlock;
+    constexpr int kPer = kAccWin / kAccThreads;
     for (int64_t w0 = 0; w0 < nch; w0 += kAccWin) {
         const int wn = (int)std::min<int64_t>(kAccWin, nch - w0);
-        // counts of this window, prefix-summed (each thread owns kPer consecutive chunks)
         int32_t cnt[kPer];
         int32_t sum = 0;
 #pragma unroll
@@ -203,18 +234,24 @@ __global__ __launch_bounds__(kBlock) void k_bucket_accumulate(int32_t m, int log
             if (c < wn) s_off[c] = mo[w0 + c];
             sum += cnt[i];
         }
-        int32_t tot;
-        const int32_t incl = block_incl_scan(sum, s_tmp, &tot);
-        int32_t run = incl - sum;
+        // workgroup-wide exclusive scan of the per-thread sums
+        const int32_t wincl = wave_incl_scan(sum);
+        if (lane_id() == kWave - 1) s_wsum[wave_id()] = wincl;
+        __syncthreads();
+        int32_t pre = 0, tot = 0;
+        for (int i = 0; i < kWaves; ++i) {
+            const int32_t t = s_wsum[i];
+            if (i < wave_id()) pre += t;
+            tot += t;
+        }
+        int32_t run = pre + wincl - sum;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             s_pre[threadIdx.x * kPer + i] = run;
             run += cnt[i];
         }
-        if (threadIdx.x == 0) s_pre[kAccWin] = tot;
         __syncthreads();
-        for (int i = threadIdx.x; i < tot; i += kBlock) {
-            // last chunk whose prefix start is <= i
+        auto locate = [&](int i) {
             int lo = 0, hi = wn - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -223,7 +260,30 @@ __global__ __launch_bounds__(kBlock) void k_bucket_accumulate(int32_t m, int log
                 else
                     hi = mid - 1;
             }
-            const int q = s_off[lo] + (i - s_pre[lo]);
+            return s_off[lo] + (i - s_pre[lo]);
+        };
+        int i = threadIdx.x;
+        for (; i + 3 * kAccThreads < tot; i += 4 * kAccThreads) {
+            int q[4];
+            uint16_t r[4];
+            Acc v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = locate(i + u * kAccThreads);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                r[u] = prow[q[u]];
+                if constexpr (S::kVals) v[u] = pval[q[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if constexpr (S::kVals)
+                    S::lds_atomic_add(&acc[r[u]], v[u]);
+                else
+                    acc[r[u]] = 1u;
+            }
+        }
+        for (; i < tot; i += kAccThreads) {
+            const int q = locate(i);
             if constexpr (S::kVals)
                 S::lds_atomic_add(&acc[prow[q]], pval[q]);
             else
@@ -232,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_accumulate(int32_t m, int log
         __syncthreads();
     }
     const int64_t base = (int64_t)b << logR;
-    for (int r = threadIdx.x; r < R; r += kBlock)
+    for (int r = threadIdx.x; r < R; r += kAccThreads)
         if (base + r < m) y[base + r] = S::out(acc[r]);
 }
 
@@ -261,7 +321,8 @@ static bool bucket_geometry(int32_t m, int dtype, int bucket_rows, BucketGeom* g
 }
 
 static int64_t bucket_chunks(int32_t nnz_x, int64_t nnz_s_ub, const spx_plan* plan) {
-    if (plan->distribution == SPX_DIST_BALANCED) return std::max<int64_t>(1, ceil_div((int64_t)nnz_x + nnz_s_ub, kCscTile));
+    if (plan->distribution == SPX_DIST_BALANCED)
+        return std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)nnz_x + nnz_s_ub, kCscTile), kMergeChunks));
     return std::max<int64_t>(1, std::min<int64_t>(nnz_x, kDirectChunks));
 }
 
@@ -324,8 +385,9 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
     }
     SPX_HIP(hipGetLastError());
     const size_t lds = ((size_t)1 << g.logR) * sizeof(Acc);
-    k_bucket_accumulate<DT><<<(unsigned)g.NB, kBlock, lds, s>>>(A.m, g.logR, nch_fixed, nnz_x, excl, out.prow,
-                                                                out.pval, out.moff, out.mcnt, out.stride, y);
+    k_bucket_accumulate<DT><<<(unsigned)g.NB, kAccThreads, lds, s>>>(A.m, g.logR, nch_fixed, nnz_x, excl,
+                                                                     out.prow, out.pval, out.moff, out.mcnt,
+                                                                     out.stride, y);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }

@@ -31,14 +31,6 @@ namespace spx {
 constexpr int kLdsBytes = 65536;  // LDS budget of the privatized y copy
 
 template <int DT>
-struct EmitAtomic {
-    typename SR<DT>::Y* y;
-    __device__ void operator()(int r, typename SR<DT>::Acc v, int64_t) const {
-        SR<DT>::atomic_add(&y[r], v);
-    }
-};
-
-template <int DT>
 struct EmitLds {
     typename SR<DT>::Acc* sy;
     __device__ void operator()(int r, typename SR<DT>::Acc v, int64_t) const {
@@ -65,35 +57,6 @@ struct EmitPairs {
         }
     }
 };
-
-// --------------------------------------------------------------- direct
-// excl (optional) gives each entry's prefix position for pair emission.
-template <int DT, int L, typename Emit>
-__device__ __forceinline__ void csc_direct_entry(int e, int g, const int32_t* __restrict__ x_idx,
-                                                 const typename SR<DT>::X* __restrict__ x_val,
-                                                 const int32_t* __restrict__ col_ptr,
-                                                 const int32_t* __restrict__ row_idx,
-                                                 const typename SR<DT>::V* __restrict__ vals,
-                                                 const int32_t* __restrict__ excl, const Emit& emit) {
-    using S = SR<DT>;
-    const int j = x_idx[e];
-    const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
-    const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
-    const int64_t pbase = excl ? (int64_t)excl[e] - c0 : 0;
-    int k = c0 + g;
-    for (; k + 3 * L < c1; k += 4 * L) {
-        int r[4];
-        typename S::V a[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            r[u] = row_idx[k + u * L];
-            a[u] = S::val(vals, k + u * L);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) emit(r[u], S::mul(a[u], v), pbase + k + u * L);
-    }
-    for (; k < c1; k += L) emit(row_idx[k], S::mul(S::val(vals, k), v), pbase + k);
-}
 
 template <int DT, int L>
 __global__ __launch_bounds__(kBlock) void k_csc_direct_atomic(int32_t nnz_x, const int32_t* __restrict__ x_idx,
@@ -159,28 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_x_lengths(int32_t nnz_x, const int32
     }
     const int j = x_idx[e];
     len[e] = col_ptr[j + 1] - col_ptr[j];
-}
-
-// --------------------------------------------------------------- balanced
-// excl[0..nnz_x]: exclusive prefix of the selected column lengths (excl[nnz_x]
-// = nnz_s). Tiles are taken grid-stride until the merge length is covered.
-template <int DT, typename Emit>
-__device__ __forceinline__ void csc_merge_tile(int64_t tile, int32_t nnz_x, int64_t nnz_s,
-                                               const int32_t* __restrict__ x_idx,
-                                               const typename SR<DT>::X* __restrict__ x_val,
-                                               const int32_t* __restrict__ col_ptr,
-                                               const int32_t* __restrict__ row_idx,
-                                               const typename SR<DT>::V* __restrict__ vals,
-                                               const int32_t* __restrict__ excl, const Emit& emit,
-                                               CscTileLds<DT>& L) {
-    using S = SR<DT>;
-    const CscTile t = csc_tile_setup<DT>(tile, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
-    for (int p = t.p0 + threadIdx.x; p < t.p1; p += kBlock) {
-        const int u = csc_tile_locate<DT>(p, t, L);
-        const int k = L.cs[u] + (p - L.excl[u]);
-        emit(row_idx[k], S::mul(S::val(vals, k), L.v[u]), p);
-    }
-    __syncthreads();
 }
 
 template <int DT>

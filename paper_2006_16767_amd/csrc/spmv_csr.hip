@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "csr_tile.hpp"
 #include "internal.hpp"
 
 namespace spx {
@@ -77,137 +78,50 @@ __global__ __launch_bounds__(kBlock) void k_csr_direct(int32_t m, const int32_t*
 }
 
 // --------------------------------------------------------------- balanced
-constexpr int kMergeIpt = 8;
-constexpr int kMergeTile = kBlock * kMergeIpt;
+// Merge-path partition: boundary b of tile size T sits at merge diagonal
+// d = min(b * T, m + nnz); part[2b] = rows finished before d, part[2b+1] =
+// nonzeros consumed before d. Depends on the matrix only, so a handle
+// computes it once.
+__global__ __launch_bounds__(kBlock) void k_merge_partition(int32_t m, int32_t nnz,
+                                                            const int32_t* __restrict__ row_ptr, int64_t tiles,
+                                                            int32_t tile, int32_t* __restrict__ part) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b > tiles) return;
+    const int64_t d = std::min<int64_t>(b * tile, (int64_t)m + nnz);
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)row_ptr[mid + 1] + mid >= d)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    part[2 * b] = lo;
+    part[2 * b + 1] = (int)(d - lo);
+}
 
-template <int DT, bool VALID>
-__global__ __launch_bounds__(kBlock) void k_csr_merge(int32_t m, int32_t nnz,
-                                                      const int32_t* __restrict__ row_ptr,
+template <int DT, bool VALID, int TILE>
+__global__ __launch_bounds__(kBlock) void k_csr_merge(int32_t m, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col_idx,
                                                       const typename SR<DT>::V* __restrict__ vals,
                                                       const typename SR<DT>::X* __restrict__ x,
                                                       const uint32_t* __restrict__ bits,
                                                       typename SR<DT>::Y* __restrict__ y,
+                                                      const int32_t* __restrict__ part, int64_t tiles,
                                                       int32_t* __restrict__ carry_row,
                                                       typename SR<DT>::Acc* __restrict__ carry_val) {
-    using S = SR<DT>;
-    using Acc = typename S::Acc;
-    __shared__ int32_t s_end[kMergeTile + 1];  // row_ptr[i0 + 1 + r]
-    __shared__ Acc s_prod[kMergeTile];
-    __shared__ Acc s_row[kMergeTile];
-    __shared__ int32_t s_key[kBlock];
-    __shared__ Acc s_cv[kBlock];
-    __shared__ int32_t s_bound[4];
-
-    const int64_t total = (int64_t)m + nnz;
-    const int64_t d0 = (int64_t)blockIdx.x * kMergeTile;
-    const int64_t d1 = std::min<int64_t>(d0 + kMergeTile, total);
-    auto ends = [&](int i) { return row_ptr[i + 1]; };
-    if (wave_id() < 2) {
-        const int64_t d = wave_id() == 0 ? d0 : d1;
-        const int i = merge_search_wave(ends, m, d);
-        if (lane_id() == 0) {
-            s_bound[wave_id() * 2 + 0] = i;
-            s_bound[wave_id() * 2 + 1] = (int)(d - i);
-        }
-    }
-    __syncthreads();
-    const int i0 = s_bound[0], k0 = s_bound[1], i1 = s_bound[2], k1 = s_bound[3];
-    const int R = i1 - i0;   // rows whose end lies in this tile
-    const int Q = k1 - k0;   // nonzeros consumed in this tile
-    for (int r = threadIdx.x; r < R; r += kBlock) s_end[r] = row_ptr[i0 + 1 + r];
-    for (int q = threadIdx.x; q < Q; q += kBlock) {
-        const int k = k0 + q;
-        const int c = col_idx[k];
-        Acc p;
-        if constexpr (VALID) {
-            p = test_bit(bits, c) ? S::mul(S::val(vals, k), S::xval(x, c)) : S::zero();
-        } else {
-            p = S::mul(S::val(vals, k), S::xval(x, c));
-        }
-        s_prod[q] = p;
-    }
-    __syncthreads();
-
-    // thread-level merge walk over kMergeIpt items
-    const int tile_items = (int)(d1 - d0);
-    const int dt = std::min((int)threadIdx.x * kMergeIpt, tile_items);
-    const int dte = std::min(dt + kMergeIpt, tile_items);
-    int r = merge_search_lds(s_end, R, dt, k0);
-    int q = dt - r;
-    const int r_start = r;
-    Acc acc = S::zero();
-    bool first_end = true;
-    Acc first_val = S::zero();
-    int first_row = -1;
-    for (int it = dt; it < dte; ++it) {
-        if (r < R && k0 + q >= s_end[r]) {
-            if (first_end) {
-                first_end = false;
-                first_row = r;
-                first_val = acc;
-            } else {
-                s_row[r] = acc;
-            }
-            acc = S::zero();
-            ++r;
-        } else {
-            acc = S::add(acc, s_prod[q]);
-            ++q;
-        }
-    }
-    // carry-out: the partial sum of row r (still open at this thread's end)
-    s_key[threadIdx.x] = r;
-    s_cv[threadIdx.x] = acc;
-    __syncthreads();
-    // segmented inclusive scan of carries over threads (segments = equal key)
-    for (int off = 1; off < kBlock; off <<= 1) {
-        Acc add = S::zero();
-        const int t = threadIdx.x;
-        if (t >= off && s_key[t - off] == s_key[t]) add = s_cv[t - off];
-        __syncthreads();
-        s_cv[t] = S::add(s_cv[t], add);
-        __syncthreads();
-    }
-    // carry-in of thread t = scanned carry of thread t-1 if it is open on the
-    // row thread t started in (always true by continuity, unless t == 0)
-    if (first_row >= 0) {
-        Acc cin = S::zero();
-        if (threadIdx.x > 0 && s_key[threadIdx.x - 1] == r_start) cin = s_cv[threadIdx.x - 1];
-        s_row[first_row] = S::add(first_val, cin);
-    }
-    __syncthreads();
-    for (int rr = threadIdx.x; rr < R; rr += kBlock) y[i0 + rr] = S::out(s_row[rr]);
-    if (threadIdx.x == kBlock - 1) {
-        // the row open at the tile end continues in the next tile
-        const bool open = (i1 < m) && (k1 > row_ptr[i1]);
-        carry_row[blockIdx.x] = open ? i1 : -1;
-        carry_val[blockIdx.x] = open ? s_cv[kBlock - 1] : S::zero();
-    }
+    __shared__ CsrTileLds<DT, TILE> L;
+    csr_merge_tile<DT, VALID, TILE>(xcd_tile(blockIdx.x, tiles), m, row_ptr, col_idx, vals, x, bits, y, part,
+                                    carry_row, carry_val, L);
 }
 
-// Adds the carries of tiles whose last row continues, in tile order. A row
-// that spans several tiles appears as a run of equal carry_row; the first
-// tile of the run sums the run and adds it to y (written by the tile that
-// finished the row).
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_csr_merge_fixup(int32_t tiles,
                                                             const int32_t* __restrict__ carry_row,
                                                             const typename SR<DT>::Acc* __restrict__ carry_val,
                                                             typename SR<DT>::Y* __restrict__ y) {
-    using S = SR<DT>;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= tiles) return;
-    const int row = carry_row[t];
-    if (row < 0) return;
-    if (t > 0 && carry_row[t - 1] == row) return;
-    typename S::Acc acc = S::zero();
-    for (int u = t; u < tiles && carry_row[u] == row; ++u) acc = S::add(acc, carry_val[u]);
-    if constexpr (DT == SPX_BOOL) {
-        if (acc) y[row] = 1;
-    } else {
-        y[row] = S::out(S::add((typename S::Acc)y[row], acc));
-    }
+    csr_merge_fixup_range<DT>((int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock, tiles,
+                              carry_row, carry_val, y);
 }
 
 // --------------------------------------------------------------- launch
@@ -218,18 +132,28 @@ static int pick_lanes(int32_t m, int32_t nnz) {
     return L;
 }
 
+static int merge_tile(const spx_plan* plan) { return plan->tile == 4096 ? 4096 : 2048; }
+
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan) {
     if (!plan || plan->distribution != SPX_DIST_BALANCED) return 0;
-    const int64_t tiles = ceil_div((int64_t)m + nnz, kMergeTile);
+    const int64_t tiles = ceil_div((int64_t)m + nnz, merge_tile(plan));
     Sizer z;
+    z.take<int32_t>(2 * (tiles + 1));
     z.take<int32_t>(tiles);
     z.take<double>(tiles);
     return z.used;
 }
 
+spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int tile, int32_t* part, hipStream_t s) {
+    const int64_t tiles = ceil_div((int64_t)m + nnz, tile);
+    k_merge_partition<<<(unsigned)ceil_div(tiles + 1, kBlock), kBlock, 0, s>>>(m, nnz, row_ptr, tiles, tile, part);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
 template <int DT, bool VALID>
 static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                               const spx_plan* plan, Arena& ws, hipStream_t s) {
+                               const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s) {
     using S = SR<DT>;
     const auto* vals = (const typename S::V*)A->vals;
     const auto* xv = (const typename S::X*)x;
@@ -259,12 +183,22 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
         return SPX_OK;
     }
     if (plan->distribution == SPX_DIST_BALANCED) {
-        const int64_t tiles = ceil_div((int64_t)A->m + A->nnz, kMergeTile);
+        const int T = merge_tile(plan);
+        const int64_t tiles = ceil_div((int64_t)A->m + A->nnz, T);
+        int32_t* own_part = ws.take<int32_t>(2 * (tiles + 1));
         int32_t* crow = ws.take<int32_t>(tiles);
         auto* cval = ws.take<typename S::Acc>(tiles);
-        if (!crow || !cval) return fail(SPX_ERR_WORKSPACE, "spmv balanced: workspace too small");
-        k_csr_merge<DT, VALID><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->nnz, A->row_ptr, A->col_idx,
-                                                                  vals, xv, bits, yv, crow, cval);
+        if (!own_part || !crow || !cval) return fail(SPX_ERR_WORKSPACE, "spmv balanced: workspace too small");
+        if (!part) {
+            SPX_TRY(merge_partition(A->m, A->nnz, A->row_ptr, T, own_part, s));
+            part = own_part;
+        }
+        if (T == 4096)
+            k_csr_merge<DT, VALID, 4096><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->row_ptr, A->col_idx, vals, xv,
+                                                                           bits, yv, part, tiles, crow, cval);
+        else
+            k_csr_merge<DT, VALID, 2048><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->row_ptr, A->col_idx, vals, xv,
+                                                                           bits, yv, part, tiles, crow, cval);
         SPX_HIP(hipGetLastError());
         k_csr_merge_fixup<DT><<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, s>>>((int32_t)tiles, crow,
                                                                                   cval, yv);
@@ -275,13 +209,13 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
 }
 
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                           const spx_plan* plan, Arena& ws, hipStream_t s) {
+                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s) {
     const bool valid = plan->pattern == SPX_PAT_CSR_SPMSPV;
     switch (A->dtype) {
 #define SPX_DT(DT)                                                                            \
     case DT:                                                                                  \
-        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, ws, s)                     \
-                     : launch_csr_t<DT, false>(A, x, bits, y, plan, ws, s);
+        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, part, ws, s)               \
+                     : launch_csr_t<DT, false>(A, x, bits, y, plan, part, ws, s);
         SPX_DT(SPX_F32)
         SPX_DT(SPX_F64)
         SPX_DT(SPX_I32)

@@ -1,0 +1,144 @@
+"""Batched SpMSpV (one graph-captured persistent launch, plans chosen on
+the device) against the CPU oracle and against per-vector run()."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_16767_amd as spx
+from paper_2006_16767_amd import synth
+
+from parity_util import assert_close, cfg_matrix, reference
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pack(vecs, kind, npdt):
+    torch = _torch()
+    ptr = np.zeros(len(vecs) + 1, np.int32)
+    ptr[1:] = np.cumsum([v.nnz for v in vecs])
+    idx = np.concatenate([v.idx for v in vecs]).astype(np.int32) if ptr[-1] else np.zeros(0, np.int32)
+    val = None
+    if kind != "bool":
+        val = np.concatenate([np.asarray(v.val, npdt) for v in vecs]) if ptr[-1] else np.zeros(0, npdt)
+    t = lambda a: torch.as_tensor(a, device="cuda")
+    return t(ptr), t(idx), (None if val is None else t(val))
+
+
+def _vectors(n, B, seed, kind, dense_frac=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(B):
+        if b == 0:
+            nnz = 0
+        elif b == 1:
+            nnz = n
+        else:
+            nnz = max(1, int(round(n * 10 ** rng.uniform(-4, np.log10(0.5)))))
+        dist = "int" if kind == "i32" else "uniform"
+        v = synth.sparse_vector(n, nnz, seed * 1000 + b, dist, np.int32 if kind == "i32" else np.float64)
+        out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "i32", "bool"])
+def test_batch_matches_oracle_small(kind):
+    torch = _torch()
+    npdt = {"f32": np.float32, "f64": np.float64, "i32": np.int32, "bool": None}[kind]
+    code = {"f32": spx.F32, "f64": spx.F64, "i32": spx.I32, "bool": spx.BOOL}[kind]
+    for name in ("cfg1", "rmat16"):
+        A = cfg_matrix(name)
+        if kind == "i32":
+            A = A.with_vals(np.clip(np.round(A.vals * 4), -4, 4).astype(np.int32))
+        elif npdt is not None:
+            A = A.with_vals(A.vals.astype(npdt))
+        M = spx.Matrix.from_host(A, dtype=code)
+        vecs = _vectors(A.n, 40, 3, kind)
+        ptr, idx, val = _pack(vecs, kind, npdt)
+        Y = M.run_batch(ptr, idx, val)
+        torch.cuda.synchronize()
+        assert M.batch_status() == 0
+        Yh = Y.cpu().numpy()
+        for b, v in enumerate(vecs):
+            ref, S = reference(A, v.idx, None if kind == "bool" else np.asarray(v.val, npdt), kind)
+            assert_close(Yh[b], ref, S, kind, f"batch {name} {kind} b={b} nnz_x={v.nnz}")
+
+
+def test_batch_graph_replays_and_recapture():
+    """Replays of the captured graph, with eager work and syncs between
+    them, each checked; new values in the same arrays; then different
+    arrays (re-capture) and a larger batch (re-allocation)."""
+    torch = _torch()
+    A = cfg_matrix("rmat16")
+    M = spx.Matrix.from_host(A)
+    vecs = _vectors(A.n, 24, 5, "f32")
+    ptr, idx, val = _pack(vecs, "f32", np.float32)
+    Y = M.out_tensor(len(vecs))
+    refs = [reference(A, v.idx, np.asarray(v.val, np.float32), "f32") for v in vecs]
+    for rep in range(3):
+        M.run_batch(ptr, idx, val, Y)
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        for b in range(len(vecs)):
+            assert_close(Yh[b], refs[b][0], refs[b][1], "f32", f"replay {rep} b={b}")
+    # same arrays, new values (graph replay reads the new contents)
+    val.mul_(-2.0)
+    M.run_batch(ptr, idx, val, Y)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy()
+    for b in range(len(vecs)):
+        assert_close(Yh[b], -2.0 * refs[b][0], 2.0 * refs[b][1], "f32", f"new values b={b}")
+    # different arrays and a larger batch
+    vecs2 = _vectors(A.n, 50, 6, "f32")
+    p2, i2, v2 = _pack(vecs2, "f32", np.float32)
+    Y2 = M.run_batch(p2, i2, v2)
+    torch.cuda.synchronize()
+    Yh2 = Y2.cpu().numpy()
+    for b, v in enumerate(vecs2):
+        ref, S = reference(A, v.idx, np.asarray(v.val, np.float32), "f32")
+        assert_close(Yh2[b], ref, S, "f32", f"recapture b={b}")
+    assert M.batch_status() == 0
+
+
+@pytest.mark.slow
+def test_batch_cfg4_rmat_matches_looped_run():
+    """512 vectors of log-uniform density on R-MAT 2^18 (degree 32): every
+    row equals the per-vector run() result within the FP32 bound, and a
+    sample equals the oracle."""
+    torch = _torch()
+    A = cfg_matrix("cfg4_rmat")
+    M = spx.Matrix.from_host(A)
+    vecs = synth.cfg4_rmat_batch(A.n, 512)
+    ptr, idx, val = _pack(vecs, "f32", np.float32)
+    Y = M.run_batch(ptr, idx, val)
+    torch.cuda.synchronize()
+    assert M.batch_status() == 0
+    Yh = Y.cpu().numpy()
+    for b in range(0, 512, 16):
+        v = vecs[b]
+        ref, S = reference(A, v.idx, v.val, "f32")
+        assert_close(Yh[b], ref, S, "f32", f"cfg4 rmat b={b} nnz_x={v.nnz}")
+
+
+@pytest.mark.slow
+def test_batch_cfg4_svm_rows():
+    torch = _torch()
+    A = cfg_matrix("cfg4_svm")
+    M = spx.Matrix.from_host(A)
+    vecs = synth.cfg4_svm_batch(A, 256)
+    ptr, idx, val = _pack(vecs, "f32", np.float32)
+    Y = M.run_batch(ptr, idx, val)
+    torch.cuda.synchronize()
+    assert M.batch_status() == 0
+    Yh = Y.cpu().numpy()
+    for b in range(0, 256, 8):
+        v = vecs[b]
+        ref, S = reference(A, v.idx, v.val, "f32")
+        assert_close(Yh[b], ref, S, "f32", f"cfg4 svm b={b}")
