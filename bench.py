@@ -44,8 +44,12 @@ def kernel_names(p):
     profile cross-check)."""
     if p.pattern in (0, 1):
         return ["k_csr_direct"] if p.distribution == 0 else ["k_csr_merge", "k_csr_merge_fixup"]
-    stem = {1: "atomic", 3: "lds", 2: "pairs", 4: "bucket"}[p.writeback]
     dist = "direct" if p.distribution == 0 else "merge"
+    if p.writeback == 4:
+        return [f"k_bucket_scatter_{dist}", "k_bucket_accumulate"]
+    if p.writeback == 2:
+        return [f"k_csc_{dist}_pairs", "k_radix_hist", "k_radix_scatter", "k_reduce_by_key"]
+    stem = {1: "atomic", 3: "lds"}[p.writeback]
     return [f"k_csc_{dist}_{stem}"]
 
 
@@ -94,6 +98,104 @@ def cpu_baseline(A, vecs, min_seconds=10.0, max_rounds=50):
                       f"dense accumulator, float64 Neumaier sums), {tot_t:.1f} s on 1 host thread"}
 
 
+def _timer(torch):
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    return timeit
+
+
+def extra_poisson(torch, spx, synth, reps=50):
+    """7-point Poisson 128^3, FP32, dense x ~ N(0,1): the SpMV roofline case."""
+    import numpy as np
+    A = synth.cfg3_matrix()
+    M = spx.Matrix.from_host(A)
+    x = torch.as_tensor(synth.cfg3_vectors()[0], device="cuda")
+    y = M.out_tensor()
+    timeit = _timer(torch)
+    ms = timeit(lambda: M.run(x, y), reps)
+    plan = M.last_plan()
+    b = A.nnz * 8 + (A.m + 1) * 4 + A.n * 4 + A.m * 4
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"workload": "poisson3d_128_f32_dense_x", "plan": repr(plan), "ms": round(ms, 4),
+            "alg_bytes": b, "GB/s": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2)}
+
+
+def _pack(torch, vecs, np):
+    ptr = np.zeros(len(vecs) + 1, np.int32)
+    ptr[1:] = np.cumsum([v.nnz for v in vecs])
+    idx = np.concatenate([v.idx for v in vecs]).astype(np.int32)
+    val = np.concatenate([np.asarray(v.val, np.float32) for v in vecs])
+    return (torch.as_tensor(ptr, device="cuda"), torch.as_tensor(idx, device="cuda"),
+            torch.as_tensor(val, device="cuda"))
+
+
+def extra_batched(torch, spx, synth, reps=5):
+    """512 sparse vectors (densities log-uniform in [1e-4, 0.5]) on R-MAT
+    2^18 (degree 32): one graph launch of run_batch vs a loop of run()."""
+    import numpy as np
+    A = synth.cfg4_rmat()
+    M = spx.Matrix.from_host(A)
+    vecs = synth.cfg4_rmat_batch(A.n, 512)
+    ptr, idx, val = _pack(torch, vecs, np)
+    Y = M.out_tensor(len(vecs))
+    xs = [(idx[ptr[b]:ptr[b + 1]], val[ptr[b]:ptr[b + 1]]) for b in range(len(vecs))]
+    timeit = _timer(torch)
+    t_batch = timeit(lambda: M.run_batch(ptr, idx, val, Y), reps)
+    t_loop = timeit(lambda: [M.run(x, Y[b]) for b, x in enumerate(xs)], reps)
+    nnz_s = [int(M.vector_features(x)["nnz_s"]) for x in xs]
+    sum_b = sum(alg_bytes(A.m, A.n, A.nnz, v.nnz, ns)[0] for v, ns in zip(vecs, nnz_s))
+    uniq = A.nnz * 8 + (A.m + 1) * 4 + (A.n + 1) * 4 + int(ptr[-1]) * 8 + len(vecs) * A.m * 4
+    return {"workload": "rmat18_deg32_f32_batch512", "batched_ms": round(t_batch, 3), "looped_ms": round(t_loop, 3),
+            "speedup_batched_vs_looped": round(t_loop / t_batch, 2),
+            "GB/s_sum_per_vector_bytes": round(sum_b / (t_batch * 1e-3) / 1e9, 1),
+            "GB/s_unique_bytes": round(uniq / (t_batch * 1e-3) / 1e9, 1),
+            "status": M.batch_status()}
+
+
+def extra_fwd_bwd(torch, spx, synth, reps=10):
+    """Pruned FC layer 16384 x 4096 at 5%, batch 64 of post-ReLU activations
+    (50..95% zeros): forward vs forward + backward (dX and dvals)."""
+    import numpy as np
+    A = synth.cfg5_matrix()
+    M = spx.Matrix.from_host(A)
+    acts = synth.cfg5_activations()
+    Xh = np.zeros((64, A.n), np.float32)
+    for b, v in enumerate(acts):
+        Xh[b, v.idx] = v.val
+    X = torch.as_tensor(Xh, device="cuda")
+    G = torch.as_tensor(synth.cfg5_upstream(), device="cuda")
+    Y = M.out_tensor(64)
+    dX = torch.empty_like(X)
+    dv = torch.empty(A.nnz, dtype=torch.float32, device="cuda")
+    timeit = _timer(torch)
+    t_f = timeit(lambda: M.run_dense_batch(X, Y), reps)
+    t_dx = timeit(lambda: M.transpose_matvec(G, dX), reps)
+    t_dv = timeit(lambda: M.dvals(G, X, dv), reps)
+    B, m, n, nnz = 64, A.m, A.n, A.nnz
+    nnz_x = [v.nnz for v in acts]
+    # forward bytes: per vector min(CSC, SpMV) traffic, nnz_s from the handle
+    xs = [(torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda")) for v in acts]
+    nnz_s = [int(M.vector_features(x)["nnz_s"]) for x in xs]
+    b_fwd = sum(alg_bytes(m, n, nnz, nx, ns)[0] for nx, ns in zip(nnz_x, nnz_s)) + B * n * 4  # + reading dense X
+    b_dx = nnz * 8 + (n + 1) * 4 + B * (m * 4 + n * 4)
+    b_dv = nnz * 8 + (m + 1) * 4 + B * (m * 4 + n * 4) + nnz * 4
+    f_pct = b_fwd / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS
+    bw_pct = (b_dx + b_dv) / ((t_dx + t_dv) * 1e-3) / 1e9 / HBM_PEAK_GBS
+    return {"workload": "fc16384x4096_d0.05_batch64_f32", "fwd_ms": round(t_f, 3), "dx_ms": round(t_dx, 3),
+            "dvals_ms": round(t_dv, 3), "fwd_plus_bwd_over_fwd": round((t_f + t_dx + t_dv) / t_f, 2),
+            "fwd_pct_hbm_peak": round(100 * f_pct, 2), "bwd_pct_hbm_peak": round(100 * bw_pct, 2),
+            "bwd_over_fwd_frac_of_peak": round(bw_pct / f_pct, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +203,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the Poisson / batched / backward figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -207,6 +310,13 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("poisson_spmv", extra_poisson), ("batched_vs_looped", extra_batched),
+                         ("fwd_vs_fwd_bwd", extra_fwd_bwd)):
+            print(f"[bench] extra: {name}", file=sys.stderr, flush=True)
+            extras[name] = fn(torch, spx, synth)
+        rec["extras"] = extras
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(A, vecs, min_seconds=args.cpu_seconds)

@@ -274,12 +274,14 @@ spx_status run_batch(spx_matrix *H, int32_t B, int64_t total_nnz_x, const int32_
 spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
 
 /* ---------------------------------------------------------------------
- * Backward of y = A(vals) x for L(y): with g = dL/dy,
- *   dx = A^T g                       (spmv_csr_transpose: row-major over
- *                                     the CSC copy, i.e. a gather along
- *                                     columns, no atomics)
- *   dvals_k = sum_b g_b[row k] x_b[col k]   over the CSR pattern
- * F32 and F64 only.
+ * Backward of Y[b] = A(vals) X[b] for a loss L(Y), with G = dL/dY
+ * (B x m) and X (B x n), both dense, row-major, on the device:
+ *   dX[b] = A^T G[b]                       (spmv_csr_transpose: the CSC copy
+ *                                           read as rows of A^T, a gather
+ *                                           along columns, no atomics)
+ *   dvals_k = sum_b G[b, row k] X[b, col k]  over the CSR pattern
+ * Both read the matrix once for the whole batch. F32 and F64 only. The
+ * handle's workspace holds B-minor copies of G (and X).
  * ------------------------------------------------------------------- */
 
 /* dX[b] = A^T G[b] for b < B: G is B x m, dX is B x n (device, row-major). */
@@ -289,6 +291,14 @@ spx_status spmv_csr_transpose(spx_matrix *H, int32_t B, const void *G, void *dX,
  * G is B x m and X is B x n dense (device, row-major). */
 spx_status dvals_pattern(spx_matrix *H, int32_t B, const void *G, const void *X, void *dvals,
                          void *stream);
+
+/* Vector format conversion for a batch (Section 6.3): the B dense rows of
+ * X (B x n, matrix dtype; uint8 for BOOL) become sparse vectors in
+ * CSR-of-vectors form, ready for run_batch: vec_ptr[B+1], idx[], val[]
+ * (caller-owned device arrays with room for B * n entries). x != 0 marks a
+ * nonzero (-0.0 is zero, NaN is not). */
+spx_status spx_dense_rows_to_sparse(spx_matrix *H, int32_t B, const void *X, int32_t *vec_ptr,
+                                    int32_t *idx, void *val, void *stream);
 
 /* ---------------------------------------------------------------------
  * Host-only helpers.

@@ -74,7 +74,7 @@ int oracle_spmv(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col
 
 /* ---------------------------------------------------------------------
  * O2a: the oracle's own CSR -> CSC conversion (Section 2: CSC gives O(1)
- * access to a column; Section 5.1: both formats are stored up front).
+ * access to a column; Section 6.1: both formats are stored up front).
  * Counting sort by column, stable in row order, so row_idx is ascending
  * within each column. perm[p] is the CSR position of CSC position p.
  * vals / vals_csc may be NULL (pattern only).

@@ -22,7 +22,20 @@ from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F64, I32, NO_SYNC, PAT
 __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
            "F32", "F64", "BOOL", "I32", "all_plans"]
 
-_TORCH_DT = None
+_DEFAULT_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x.json")
+_selector_loaded = False
+
+
+def _ensure_default_selector():
+    """Loads the trees trained on MI355X timings (selector_mi355x.json) once,
+    before the first handle is created; spx_load_selector can replace them."""
+    global _selector_loaded
+    if _selector_loaded:
+        return
+    import os
+    if os.path.exists(_DEFAULT_SELECTOR):
+        _lib.call("spx_load_selector", None, _DEFAULT_SELECTOR.encode())
+    _selector_loaded = True
 
 
 def _torch():
@@ -99,10 +112,12 @@ class Matrix:
         assert self.row_ptr.dtype == torch.int32 and self.col_idx.dtype == torch.int32
         self._csr = _lib.Csr(self.m, self.n, self.nnz, dtype, _ptr(self.row_ptr), _ptr(self.col_idx),
                              _ptr(self.vals))
+        _ensure_default_selector()
         h = C.c_void_p()
         _lib.call("spx_matrix_create", C.byref(self._csr), VALIDATE if validate else 0, _stream(stream),
                   C.byref(h))
         self._h = h
+        self._vals_version = None if self.vals is None else self.vals._version
 
     @classmethod
     def from_host(cls, A, dtype=None, device="cuda", validate=False):
@@ -223,6 +238,33 @@ class Matrix:
         tot = int(idx.numel()) if total_nnz_x is None else int(total_nnz_x)
         _lib.call("run_batch", self._h, B, tot, _ptr(vec_ptr), _ptr(idx), _ptr(val), _ptr(Y), _stream(stream))
         return Y
+
+    def sync_values(self, vals=None, stream=None):
+        """Refreshes the CSC copy if the CSR value tensor changed in place
+        since the last refresh (tracked by the tensor's version counter)."""
+        v = self.vals if vals is None else vals
+        if v is None:
+            return
+        ver = v._version
+        if self._vals_version != ver:
+            self.values_updated(stream)
+            self._vals_version = ver
+
+    def run_dense_batch(self, X, Y=None, stream=None):
+        """Y[b] = A X[b] for the rows of a dense X (B x n): the rows become
+        sparse vectors on the device, then run_batch."""
+        torch = _torch()
+        B = int(X.shape[0])
+        key = (B, X.dtype)
+        if getattr(self, "_dense_bufs", (None,))[0] != key:
+            dev = X.device
+            self._dense_bufs = (key, torch.empty(B + 1, dtype=torch.int32, device=dev),
+                                torch.empty(max(1, B * self.n), dtype=torch.int32, device=dev),
+                                None if self.dtype == BOOL else torch.empty(max(1, B * self.n), dtype=X.dtype,
+                                                                            device=dev))
+        _, vp, idx, val = self._dense_bufs
+        _lib.call("spx_dense_rows_to_sparse", self._h, B, _ptr(X), _ptr(vp), _ptr(idx), _ptr(val), _stream(stream))
+        return self.run_batch(vp, idx, val, Y, total_nnz_x=B * self.n, stream=stream)
 
     def batch_status(self, stream=None) -> int:
         f = C.c_int32()

@@ -1,0 +1,47 @@
+"""Differentiable sparse layer: Y = X A(vals)^T, i.e. y_b = A(vals) x_b for
+each row x_b of a dense batch X (B x n), e.g. a pruned fully-connected
+layer applied to post-ReLU activations.
+
+Forward: the library converts each row of X to a sparse vector on the
+device and runs the batched SpMSpV (plans chosen per vector on the device).
+Backward (F32/F64): dX = G A (gather along the CSC columns, no atomics) and
+dvals_k = sum_b G[b, row k] X[b, col k] over the stored pattern; both
+kernels read the matrix once for the whole batch.
+
+The matrix handle borrows its CSR value tensor; pass that tensor as
+`vals` so autograd tracks it. After an in-place update of the values
+(an optimizer step), the next forward refreshes the CSC copy (gather
+through the CSC-to-CSR permutation) when the tensor's version changed.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import Matrix
+
+
+class SparseLinearFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, vals, X, M: Matrix):
+        if vals.data_ptr() != M.vals.data_ptr():
+            raise ValueError("vals must be the value tensor the matrix handle was built on")
+        M.sync_values(vals)
+        Xc = X.contiguous()
+        Y = M.run_dense_batch(Xc)
+        ctx.save_for_backward(Xc)
+        ctx.M = M
+        return Y
+
+    @staticmethod
+    def backward(ctx, G):
+        (X,) = ctx.saved_tensors
+        M = ctx.M
+        G = G.contiguous()
+        dvals = M.dvals(G, X) if ctx.needs_input_grad[0] else None
+        dX = M.transpose_matvec(G) if ctx.needs_input_grad[1] else None
+        return dvals, dX, None
+
+
+def sparse_linear(M: Matrix, X: torch.Tensor, vals: torch.Tensor | None = None) -> torch.Tensor:
+    """Y[b] = A(vals) X[b] for every row of X (B x n) -> (B x m)."""
+    return SparseLinearFunction.apply(M.vals if vals is None else vals, X, M)

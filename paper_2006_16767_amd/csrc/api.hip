@@ -573,7 +573,7 @@ struct LazyFeatures {
     void counts() {
         if (have_counts) return;
         have_counts = true;
-        if (no_sync) {
+        if (no_sync || x->kind == SPX_VEC_DENSE) {
             // host-known fallback: a dense x counts as full, nnz_s is
             // estimated from the average column length
             nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : H->csr.n;
@@ -586,11 +586,9 @@ struct LazyFeatures {
         }
         synced = true;
     }
-    int64_t nx() {
-        if (x->kind == SPX_VEC_SPARSE) return x->nnz_x;
-        counts();
-        return nnz_x;
-    }
+    // A vector handed over dense is taken as dense (nnz_x = n): counting its
+    // nonzeros would cost a device reduction and a sync on every call.
+    int64_t nx() { return x->kind == SPX_VEC_SPARSE ? x->nnz_x : H->csr.n; }
     int64_t ns() {
         counts();
         return nnz_s;
@@ -922,21 +920,10 @@ extern "C" spx_status spmv_csr_transpose(spx_matrix* H, int32_t B, const void* G
     if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
     const int dt = H->csr.dtype;
     if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "backward supports F32 and F64");
-    hipStream_t s = (hipStream_t)stream;
-    // A^T in CSR form is the handle's CSC: rows of A^T = columns of A
-    spx_csr At{H->csr.n, H->csr.m, H->csr.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc};
-    spx_plan p{SPX_PAT_SPMV, SPX_DIST_DIRECT, SPX_WB_NONE, 0, 0, 0};
-    if (H->feat[3] > 16 * std::max(1.0, H->feat[5])) p.distribution = SPX_DIST_BALANCED;
-    SPX_TRY(ensure_ws(H, ws_for(At.m, At.n, At.nnz, 0, dt, &p)));
-    const int32_t* part = nullptr;
-    SPX_TRY(cached_part(H, At, 1, &p, s, &part));
-    const int vs = value_size(dt);
-    for (int32_t b = 0; b < B; ++b) {
-        Arena ws(H->ws, H->ws_bytes);
-        SPX_TRY(launch_spmv_csr(&At, (const char*)G + (size_t)b * H->csr.m * vs, nullptr,
-                                (char*)dX + (size_t)b * H->csr.n * vs, &p, part, ws, s));
-    }
-    return SPX_OK;
+    SPX_TRY(ensure_ws(H, grad_ws_bytes(H->csr.m, H->csr.n, B, dt)));
+    Arena ws(H->ws, H->ws_bytes);
+    return launch_dx(H->col_ptr, H->row_idx, H->vals_csc, H->csr.m, H->csr.n, dt, B, G, dX, ws,
+                     (hipStream_t)stream);
 }
 
 extern "C" spx_status dvals_pattern(spx_matrix* H, int32_t B, const void* G, const void* X, void* dvals,
@@ -945,6 +932,18 @@ extern "C" spx_status dvals_pattern(spx_matrix* H, int32_t B, const void* G, con
     if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
     const int dt = H->csr.dtype;
     if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "backward supports F32 and F64");
-    return launch_dvals(H->csr.row_ptr, H->csr.col_idx, H->csr.m, H->csr.n, H->csr.nnz, dt, B, G, X, dvals,
+    SPX_TRY(ensure_ws(H, grad_ws_bytes(H->csr.m, H->csr.n, B, dt)));
+    Arena ws(H->ws, H->ws_bytes);
+    return launch_dvals(H->csr.row_ptr, H->csr.col_idx, H->csr.m, H->csr.n, H->csr.nnz, dt, B, G, X, dvals, ws,
                         (hipStream_t)stream);
+}
+
+extern "C" spx_status spx_dense_rows_to_sparse(spx_matrix* H, int32_t B, const void* X, int32_t* vec_ptr,
+                                               int32_t* idx, void* val, void* stream) {
+    if (!H || (B > 0 && (!X || !vec_ptr || !idx || (H->csr.dtype != SPX_BOOL && !val))))
+        return fail(SPX_ERR_ARG, "null argument");
+    if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    SPX_TRY(ensure_ws(H, scan_ws_elems((int64_t)B + 1) * 4 + 256));
+    return dense_rows_to_sparse(B, H->csr.n, H->csr.dtype, X, vec_ptr, idx, val, (int32_t*)H->ws,
+                                (hipStream_t)stream);
 }

@@ -166,9 +166,16 @@ size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz
                      size_t* zero_from, size_t* zero_bytes);
 spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev);
 
-// backward
+// backward (grad.hip): workspace grad_ws_bytes(m, n, B, dtype)
+size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype);
+spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m,
+                     int32_t n, int dtype, int32_t B, const void* G, void* dX, Arena& ws, hipStream_t s);
 spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n,
                         int32_t nnz, int dtype, int32_t B, const void* G, const void* X,
-                        void* dvals, hipStream_t s);
+                        void* dvals, Arena& ws, hipStream_t s);
+// B dense rows of length n -> CSR-of-vectors (vec_ptr[B+1], idx, val);
+// ws_i32: scan_ws_elems(B + 1) int32
+spx_status dense_rows_to_sparse(int32_t B, int32_t n, int dtype, const void* X, int32_t* vec_ptr,
+                                int32_t* idx, void* val, int32_t* ws_i32, hipStream_t s);
 
 }  // namespace spx
