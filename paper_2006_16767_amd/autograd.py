@@ -9,9 +9,10 @@ dvals_k = sum_b G[b, row k] X[b, col k] over the stored pattern; both
 kernels read the matrix once for the whole batch.
 
 The matrix handle borrows its CSR value tensor; pass that tensor as
-`vals` so autograd tracks it. After an in-place update of the values
-(an optimizer step), the next forward refreshes the CSC copy (gather
-through the CSC-to-CSR permutation) when the tensor's version changed.
+`vals` so autograd tracks it. Every forward re-derives the CSC copy of the
+values (one gather through the CSC-to-CSR permutation), because the values
+may have changed in place in ways the tensor's version counter does not
+record (writes through .data, as optimizers and gradcheck do).
 """
 from __future__ import annotations
 
@@ -25,7 +26,7 @@ class SparseLinearFunction(torch.autograd.Function):
     def forward(ctx, vals, X, M: Matrix):
         if vals.data_ptr() != M.vals.data_ptr():
             raise ValueError("vals must be the value tensor the matrix handle was built on")
-        M.sync_values(vals)
+        M.values_updated()
         Xc = X.contiguous()
         Y = M.run_dense_batch(Xc)
         ctx.save_for_backward(Xc)

@@ -20,6 +20,61 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
 
 constexpr int kShortRow = 32;
 
+// Products of the tile's nonzeros into LDS, written as straight-line phases
+// so that every load of a phase is in flight before the first is used: all
+// column indices, then (validation) all bitvector words, then the values
+// and x entries, then the LDS stores. Items past Q use a clamped, valid
+// index and are not stored.
+template <int DT, bool VALID, int IPT, int NT>
+__device__ __forceinline__ void csr_stage_products(int k0, int Q, const int32_t* __restrict__ col_idx,
+                                                   const typename SR<DT>::V* __restrict__ vals,
+                                                   const typename SR<DT>::X* __restrict__ x,
+                                                   const uint32_t* __restrict__ bits,
+                                                   typename SR<DT>::Acc* __restrict__ prod) {
+    using S = SR<DT>;
+    int kk[IPT], c[IPT];
+    bool on[IPT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int q = it * NT + threadIdx.x;
+        on[it] = q < Q;
+        kk[it] = k0 + (on[it] ? q : 0);
+    }
+    if (Q == 0) return;
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) c[it] = col_idx[kk[it]];
+    if constexpr (VALID) {
+        uint32_t w[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) w[it] = bits[c[it] >> 5];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) on[it] = on[it] && ((w[it] >> (c[it] & 31)) & 1u);
+        typename S::V a[IPT];
+        typename S::X b[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            a[it] = on[it] ? S::val(vals, kk[it]) : (typename S::V)0;
+            b[it] = on[it] ? S::xval(x, c[it]) : (typename S::X)0;
+        }
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int q = it * NT + threadIdx.x;
+            if (q < Q) prod[q] = on[it] ? S::mul(a[it], b[it]) : S::zero();
+        }
+    } else {
+        typename S::V a[IPT];
+        typename S::X b[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            a[it] = S::val(vals, kk[it]);
+            b[it] = S::xval(x, c[it]);
+        }
+#pragma unroll
+        for (int it = 0; it < IPT; ++it)
+            if (on[it]) prod[it * NT + threadIdx.x] = S::mul(a[it], b[it]);
+    }
+}
+
 template <int DT, int TILE>
 struct CsrTileLds {
     int32_t end[TILE + 1];
@@ -54,20 +109,7 @@ __device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const in
     const bool open = i1 < m && k1 > row_ptr[i1];
     if (threadIdx.x == 0) L.nlong = 0;
     for (int r = threadIdx.x; r < R; r += kBlock) L.end[r] = row_ptr[i0 + 1 + r];
-#pragma unroll
-    for (int it = 0; it < kIpt; ++it) {
-        const int q = it * kBlock + threadIdx.x;
-        if (q < Q) {
-            const int k = k0 + q;
-            const int c = col_idx[k];
-            Acc p;
-            if constexpr (VALID)
-                p = test_bit(bits, c) ? S::mul(S::val(vals, k), S::xval(x, c)) : S::zero();
-            else
-                p = S::mul(S::val(vals, k), S::xval(x, c));
-            L.prod[q] = p;
-        }
-    }
+    csr_stage_products<DT, VALID, kIpt, kBlock>(k0, Q, col_idx, vals, x, bits, L.prod);
     __syncthreads();
     const int nrows = R + (open ? 1 : 0);
     for (int r = threadIdx.x; r < nrows; r += kBlock) {

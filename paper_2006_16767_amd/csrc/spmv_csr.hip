@@ -124,6 +124,99 @@ __global__ __launch_bounds__(kBlock) void k_csr_merge_fixup(int32_t tiles,
                               carry_row, carry_val, y);
 }
 
+
+// --------------------------------------------------------------- LDS bitvector
+// Row-major SpMSpV with the bitvector of supp(x) held in LDS. One persistent
+// 1024-thread workgroup per CU copies the bitvector (n / 8 bytes, up to
+// kLdsBitsMax) into LDS once, then takes merge tiles in XCD-contiguous
+// order. The per-entry validation becomes an LDS read; only effective
+// entries touch vals and the scattered x values.
+constexpr int kBitThreads = 1024;
+constexpr int kBitTile = 2048;
+constexpr int kLdsTotal = 160 * 1024;  // LDS per workgroup on gfx950
+
+template <int DT>
+__global__ __launch_bounds__(kBitThreads) void k_csr_bitlds(int32_t m, int32_t n, const int32_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col_idx,
+                                                            const typename SR<DT>::V* __restrict__ vals,
+                                                            const typename SR<DT>::X* __restrict__ x,
+                                                            const uint32_t* __restrict__ bits,
+                                                            typename SR<DT>::Y* __restrict__ y,
+                                                            const int32_t* __restrict__ part, int64_t tiles,
+                                                            int32_t* __restrict__ carry_row,
+                                                            typename SR<DT>::Acc* __restrict__ carry_val) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    constexpr int kWaves = kBitThreads / kWave;
+    constexpr int kIpt = kBitTile / kBitThreads;
+    extern __shared__ uint32_t s_bits[];
+    __shared__ int32_t s_end[kBitTile + 1];
+    __shared__ Acc s_prod[kBitTile];
+    __shared__ int32_t s_lng[kBitTile + 1];
+    __shared__ int32_t s_nlong;
+    const int nwords = (n + 31) >> 5;
+    for (int w = threadIdx.x; w < nwords; w += kBitThreads) s_bits[w] = bits[w];
+    __syncthreads();
+    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x) {
+        // XCD-contiguous order over the persistent grid
+        const int64_t tile = xcd_tile(bt, tiles);
+        const int i0 = part[2 * tile], k0 = part[2 * tile + 1];
+        const int i1 = part[2 * tile + 2], k1 = part[2 * tile + 3];
+        const int R = i1 - i0, Q = k1 - k0;
+        const bool open = i1 < m && k1 > row_ptr[i1];
+        if (threadIdx.x == 0) s_nlong = 0;
+        for (int r = threadIdx.x; r < R; r += kBitThreads) s_end[r] = row_ptr[i0 + 1 + r];
+        csr_stage_products<DT, true, kIpt, kBitThreads>(k0, Q, col_idx, vals, x, s_bits, s_prod);
+        __syncthreads();
+        const int nrows = R + (open ? 1 : 0);
+        for (int r = threadIdx.x; r < nrows; r += kBitThreads) {
+            const int a = (r == 0 ? k0 : s_end[r - 1]) - k0;
+            const int e = (r < R ? s_end[r] : k1) - k0;
+            if (e - a <= kShortRow) {
+                Acc acc = S::zero();
+                for (int q = a; q < e; ++q) acc = S::add(acc, s_prod[q]);
+                if (r < R) {
+                    y[i0 + r] = S::out(acc);
+                } else {
+                    carry_row[tile] = i1;
+                    carry_val[tile] = acc;
+                }
+            } else {
+                s_lng[atomicAdd(&s_nlong, 1)] = r;
+            }
+        }
+        __syncthreads();
+        const int nl = s_nlong;
+        for (int li = wave_id(); li < nl; li += kWaves) {
+            const int r = s_lng[li];
+            const int a = (r == 0 ? k0 : s_end[r - 1]) - k0;
+            const int e = (r < R ? s_end[r] : k1) - k0;
+            Acc acc = S::zero();
+            for (int q = a + lane_id(); q < e; q += kWave) acc = S::add(acc, s_prod[q]);
+            acc = group_reduce<DT, kWave>(acc);
+            if (lane_id() == 0) {
+                if (r < R) {
+                    y[i0 + r] = S::out(acc);
+                } else {
+                    carry_row[tile] = i1;
+                    carry_val[tile] = acc;
+                }
+            }
+        }
+        if (!open && threadIdx.x == 0) carry_row[tile] = -1;
+        __syncthreads();
+    }
+}
+
+// static LDS of k_csr_bitlds plus the bitvector must fit one CU's LDS
+static size_t bitlds_static(int dtype) {
+    const size_t acc = dtype == SPX_F64 ? 8 : 4;
+    return (size_t)(kBitTile + 1) * 4 * 2 + (size_t)kBitTile * acc + 64;
+}
+bool bitlds_fits(int32_t n, int dtype) {
+    return (size_t)((n + 31) / 32) * 4 + bitlds_static(dtype) + 512 <= (size_t)kLdsTotal;
+}
+
 // --------------------------------------------------------------- launch
 static int pick_lanes(int32_t m, int32_t nnz) {
     const double avg = m > 0 ? (double)nnz / m : 0.0;
@@ -133,6 +226,12 @@ static int pick_lanes(int32_t m, int32_t nnz) {
 }
 
 static int merge_tile(const spx_plan* plan) { return plan->tile == 4096 ? 4096 : 2048; }
+// plan->tile = 1 asks the balanced row-major SpMSpV to keep the bitvector in
+// LDS (persistent workgroups, when n / 8 bytes fit next to the tile).
+static bool want_bitlds(const spx_plan* plan, int32_t n, int dtype) {
+    return plan->pattern == SPX_PAT_CSR_SPMSPV && plan->distribution == SPX_DIST_BALANCED && plan->tile == 1 &&
+           bitlds_fits(n, dtype);
+}
 
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan) {
     if (!plan || plan->distribution != SPX_DIST_BALANCED) return 0;
@@ -193,7 +292,17 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
             SPX_TRY(merge_partition(A->m, A->nnz, A->row_ptr, T, own_part, s));
             part = own_part;
         }
-        if (T == 4096)
+        if (VALID && want_bitlds(plan, A->n, DT)) {
+            int dev = 0, cus = 256;
+            hipGetDevice(&dev);
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            const int grid = (int)std::min<int64_t>(tiles, std::max(1, cus));
+            const size_t lds = (size_t)((A->n + 31) / 32) * 4;
+            SPX_HIP(hipFuncSetAttribute((const void*)k_csr_bitlds<DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+            k_csr_bitlds<DT><<<grid, kBitThreads, lds, s>>>(A->m, A->n, A->row_ptr, A->col_idx, vals, xv, bits, yv,
+                                                           part, tiles, crow, cval);
+        } else if (T == 4096)
             k_csr_merge<DT, VALID, 4096><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->row_ptr, A->col_idx, vals, xv,
                                                                            bits, yv, part, tiles, crow, cval);
         else
