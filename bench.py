@@ -19,7 +19,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -37,40 +36,6 @@ def alg_bytes(m, n, nnz, nnz_x, nnz_s, s_i=4, s_v=4, s_x=4, s_y=4):
     b_spmv = nnz * (s_i + s_v) + (m + 1) * s_i + n * s_x + m * s_y
     b_csc = nnz_x * (s_i + s_x) + 2 * nnz_x * s_i + nnz_s * (s_i + s_v) + m * s_y
     return min(b_spmv, b_csc), b_spmv, b_csc
-
-
-def kernel_names(p):
-    """rocprofv3 kernel-name stems of the launches a plan makes (for the
-    profile cross-check)."""
-    if p.pattern in (0, 1):
-        return ["k_csr_direct"] if p.distribution == 0 else ["k_csr_merge", "k_csr_merge_fixup"]
-    dist = "direct" if p.distribution == 0 else "merge"
-    if p.writeback == 4:
-        return [f"k_bucket_scatter_{dist}", "k_bucket_accumulate"]
-    if p.writeback == 2:
-        return [f"k_csc_{dist}_pairs", "k_radix_hist", "k_radix_scatter", "k_reduce_by_key"]
-    stem = {1: "atomic", 3: "lds"}[p.writeback]
-    return [f"k_csc_{dist}_{stem}"]
-
-
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, or None if
-    absent or if the kernel sources changed since the counters were taken."""
-    path = os.path.join(HERE, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    ent = rec.get(f"{workload}:{kernel}")
-    if not ent:
-        return None
-    src = os.path.join(HERE, "paper_2006_16767_amd", "csrc", ent["source"])
-    if not os.path.exists(src):
-        return None
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if h != ent["source_sha256"]:
-        return None
-    return ent["bytes_per_launch"]
 
 
 def cpu_baseline(A, vecs, min_seconds=10.0, max_rounds=50):
@@ -213,7 +178,7 @@ def main():
     import numpy as np
     import torch
     import paper_2006_16767_amd as spx
-    from paper_2006_16767_amd import synth
+    from paper_2006_16767_amd import prof, synth
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -264,9 +229,9 @@ def main():
     dom_bytes = bytes_v[dom]
     dom_ms = per_vec_ms[dom] if per_vec_ms else float("nan")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    workload = "rmat20_deg16_f32_sweep12"
-    names = kernel_names(dom_plan)
-    traffic = traffic_for(names[0], f"{workload}:v{dom}")
+    workload = prof.SWEEP_WORKLOAD
+    names = prof.kernel_names(dom_plan)
+    traffic = prof.traffic_for(os.path.join(HERE, "profiles", "traffic.json"), dom)
 
     rec = {
         "metric": "SpMV/SpMSpV eff. GB/s (% HBM peak); batched vs looped; fwd+bwd vs fwd",

@@ -188,19 +188,40 @@ spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, con
  * arrays (they must outlive it) and OWNS what it derives: the CSC copy
  * (stable counting-sort transpose on the device), the CSC-to-CSR
  * permutation, the matrix features and the workspace. Synchronizes the
- * stream once (to read the matrix features). Host-side checks only; pass
- * flags & SPX_VALIDATE to also check row_ptr monotonicity and index
- * ranges on the device (one extra sync). */
+ * stream (to read the column lengths and the matrix features). Host-side
+ * checks only; pass flags & SPX_VALIDATE to also check row_ptr
+ * monotonicity and index ranges on the device (one extra sync).
+ *
+ * Column renumbering (an implementation layout, not part of the paper's
+ * method): when the 16384 longest columns hold at least max(0.3, twice the
+ * uniform share) of the entries and n >= 65536, the handle also keeps a
+ * copy of A whose columns are ranked by descending length (stable), with
+ * the entries of each row ordered by rank; the row-major patterns run on
+ * that copy and read x through the same renumbering (one gather of n
+ * entries per call), so that the most-read x entries share cache lines.
+ * Results are those of A up to the summation order within a row.
+ * SPX_RENUMBER forces the copy, SPX_NO_RENUMBER forbids it. Memory:
+ * 4 + value size bytes per entry for the copy, 4 for its source positions,
+ * 8 per column. */
 #define SPX_VALIDATE 1u
+#define SPX_RENUMBER 4u
+#define SPX_NO_RENUMBER 8u
 spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
 spx_status spx_matrix_destroy(spx_matrix *H);
 
 /* The handle's CSC copy (device pointers owned by the handle). */
 spx_status spx_matrix_csc(const spx_matrix *H, spx_csc *out);
 
-/* Re-derives the CSC values from the borrowed CSR values (gather through
- * the permutation); call after the caller changed A's values in place. */
+/* Re-derives the CSC values (and those of the renumbered copy) from the
+ * borrowed CSR values (gathers through the permutations); call after the
+ * caller changed A's values in place. */
 spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
+
+/* *renumbered = 1 if the handle keeps the column-renumbered copy (see
+ * spx_matrix_create), else 0. If so and order is not NULL, copies the
+ * ranking to order (device, n int32: order[r] = the column of rank r),
+ * asynchronously on stream. */
+spx_status spx_matrix_column_order(const spx_matrix *H, int32_t *order, int32_t *renumbered, void *stream);
 
 /* Matrix features of Table 1, out[9] = {m, n, nnz, max_row, min_row,
  * avg_row, relative_range = (max_row - min_row) / n, var_nnz_row

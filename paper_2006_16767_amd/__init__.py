@@ -16,7 +16,7 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
-                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
+                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
                    WB_SORT, Plan, SpxError)
 
 __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
@@ -99,7 +99,7 @@ class Matrix:
     features and workspaces belong to the library handle."""
 
     def __init__(self, row_ptr, col_idx, vals, m: int, n: int, dtype: int | None = None,
-                 validate: bool = False, stream=None):
+                 validate: bool = False, renumber: bool | None = None, stream=None):
         torch = _torch()
         self.row_ptr = row_ptr.contiguous()
         self.col_idx = col_idx.contiguous()
@@ -114,13 +114,13 @@ class Matrix:
                              _ptr(self.vals))
         _ensure_default_selector()
         h = C.c_void_p()
-        _lib.call("spx_matrix_create", C.byref(self._csr), VALIDATE if validate else 0, _stream(stream),
-                  C.byref(h))
+        flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
+        _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         self._vals_version = None if self.vals is None else self.vals._version
 
     @classmethod
-    def from_host(cls, A, dtype=None, device="cuda", validate=False):
+    def from_host(cls, A, dtype=None, device="cuda", validate=False, renumber=None):
         """From an object with m, n, row_ptr, col_idx, vals (numpy)."""
         torch = _torch()
         rp = torch.as_tensor(A.row_ptr, dtype=torch.int32, device=device)
@@ -133,7 +133,7 @@ class Matrix:
             if dtype is not None:
                 v = v.to(torch_dtype(dtype))
             dt = dtype_code(v.dtype)
-        return cls(rp, ci, v, A.m, A.n, dt, validate=validate)
+        return cls(rp, ci, v, A.m, A.n, dt, validate=validate, renumber=renumber)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -228,6 +228,18 @@ class Matrix:
 
     def values_updated(self, stream=None):
         _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
+
+    def column_order(self, stream=None):
+        """The column ranking of the renumbered row-major copy (device int32
+        tensor, order[r] = column of rank r), or None if there is none."""
+        torch = _torch()
+        flag = C.c_int32(0)
+        _lib.call("spx_matrix_column_order", self._h, None, C.byref(flag), _stream(stream))
+        if not flag.value:
+            return None
+        out = torch.empty(self.n, dtype=torch.int32, device=self.row_ptr.device)
+        _lib.call("spx_matrix_column_order", self._h, _ptr(out), C.byref(flag), _stream(stream))
+        return out
 
     def load_selector(self, path: str | None):
         _lib.call("spx_load_selector", self._h, None if path is None else path.encode())

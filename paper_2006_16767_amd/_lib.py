@@ -22,7 +22,7 @@ PAT_SPMV, PAT_CSR_SPMSPV, PAT_CSC_SPMSPV = 0, 1, 2
 DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET = 0, 1, 2, 3, 4
 VEC_DENSE, VEC_SPARSE = 0, 1
-VALIDATE, NO_SYNC = 1, 2
+VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER = 1, 2, 4, 8
 
 
 class Plan(C.Structure):
@@ -66,6 +66,7 @@ SIGNATURES = {
     "spx_matrix_destroy": (C.c_int, [P]),
     "spx_matrix_csc": (C.c_int, [P, C.POINTER(Csc)]),
     "spx_matrix_values_updated": (C.c_int, [P, P]),
+    "spx_matrix_column_order": (C.c_int, [P, P, C.POINTER(C.c_int32), P]),
     "spx_matrix_features": (C.c_int, [P, C.POINTER(C.c_double)]),
     "spx_vector_features": (C.c_int, [P, C.POINTER(Vec), C.POINTER(C.c_double), P]),
     "spx_load_selector": (C.c_int, [P, C.c_char_p]),

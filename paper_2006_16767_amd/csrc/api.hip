@@ -103,6 +103,33 @@ __global__ __launch_bounds__(kBlock) void k_validate_csr(const int32_t* __restri
     }
 }
 
+// Entries of A listed column by column in rank order (rows ascending within
+// a column): key = row, value = CSR position. rq[q] is the rank owning
+// position q of that listing, gptr the prefix of column lengths by rank.
+__global__ __launch_bounds__(kBlock) void k_rank_major(int64_t nnz, const int32_t* __restrict__ rq,
+                                                       const int32_t* __restrict__ gptr,
+                                                       const int32_t* __restrict__ gorder,
+                                                       const int32_t* __restrict__ col_ptr,
+                                                       const int32_t* __restrict__ row_idx,
+                                                       const int32_t* __restrict__ perm,
+                                                       uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += stride) {
+        const int r = rq[q];
+        const int64_t p = col_ptr[gorder[r]] + (q - gptr[r]);
+        keys[q] = (uint32_t)row_idx[p];
+        vals[q] = (uint32_t)perm[p];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_renumber_cols(int64_t nnz, const int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ col_idx,
+                                                          const int32_t* __restrict__ grank,
+                                                          int32_t* __restrict__ gcol) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride) gcol[k] = grank[col_idx[src[k]]];
+}
+
 // dense x -> bitvector of its nonzeros (x != 0)
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_dense_bits(int32_t n, const typename SR<DT>::X* __restrict__ x,
@@ -129,6 +156,16 @@ struct spx_matrix {
     int32_t* row_idx = nullptr;
     int32_t* perm = nullptr;  // CSC position -> CSR position
     void* vals_csc = nullptr;
+    // column renumbering of the row-major kernels (null when not used):
+    // gorder[r] = original column of rank r, grank its inverse; gcsr is A
+    // with renumbered columns (rows unchanged, entries of a row by rank),
+    // gsrc[k] the CSR position of its entry k
+    int32_t* gorder = nullptr;
+    int32_t* grank = nullptr;
+    int32_t* gcol = nullptr;
+    int32_t* gsrc = nullptr;
+    void* gvals = nullptr;
+    spx_csr gcsr{};
     double feat[9] = {0};
     Selector sel;
     // conversion buffers (allocated on first use)
@@ -332,7 +369,7 @@ extern "C" spx_status spmspv_csr(const spx_csr* A, int32_t nnz_x, const int32_t*
     uint32_t* bits = probe.take<uint32_t>((size_t)ceil_div(A->n, 32) + 1);
     void* xd = probe.take<uint64_t>((size_t)A->n + 1);
     if (!bits || !xd) return fail(SPX_ERR_WORKSPACE, "spmspv_csr: workspace too small");
-    SPX_TRY(sparse_to_bitvector(A->n, nnz_x, x_idx, x_val, A->dtype, bits,
+    SPX_TRY(sparse_to_bitvector(A->n, nnz_x, x_idx, x_val, A->dtype, nullptr, bits,
                                 A->dtype == SPX_BOOL ? nullptr : xd, s));
     return launch_spmv_csr(A, A->dtype == SPX_BOOL ? nullptr : xd, bits, y, plan, nullptr, ws, s);
 }
@@ -359,7 +396,8 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     if (H->gexec) hipGraphExecDestroy(H->gexec);
     if (H->graph) hipGraphDestroy(H->graph);
     if (H->cap_stream) hipStreamDestroy(H->cap_stream);
-    void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->bits, H->xd, H->sp_idx,
+    void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->gorder, H->grank, H->gcol, H->gsrc,
+                    H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->bucket_cursor, H->ws,
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws};
     for (void* p : ptrs)
@@ -431,6 +469,89 @@ static spx_status build_csc(spx_matrix* H, hipStream_t s) {
     return st;
 }
 
+// Column renumbering for the row-major kernels. Their x (or bitvector)
+// reads are gathers that run at the rate of the cache level holding the
+// gathered lines; with columns ranked by descending length the most-read
+// entries share lines that stay in the per-CU cache. Used by default when
+// the kHotCols longest columns hold a share of the entries well above what
+// uniform lengths would give them.
+constexpr int32_t kHotCols = 16384;
+
+static spx_status build_gcsr(spx_matrix* H, uint32_t flags, hipStream_t s) {
+    const spx_csr& A = H->csr;
+    const int64_t nnz = A.nnz;
+    if ((flags & SPX_NO_RENUMBER) || A.n == 0 || nnz == 0) return SPX_OK;
+    std::vector<int32_t> cp((size_t)A.n + 1);
+    SPX_HIP(hipMemcpyAsync(cp.data(), H->col_ptr, cp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPX_HIP(hipStreamSynchronize(s));
+    int32_t maxlen = 0;
+    for (int32_t j = 0; j < A.n; ++j) maxlen = std::max(maxlen, cp[j + 1] - cp[j]);
+    // stable counting sort of the columns by descending length
+    std::vector<int64_t> start((size_t)maxlen + 2, 0);
+    for (int32_t j = 0; j < A.n; ++j) ++start[(size_t)(maxlen - (cp[j + 1] - cp[j])) + 1];
+    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+    std::vector<int32_t> order((size_t)A.n), rank((size_t)A.n), gptr((size_t)A.n + 1);
+    for (int32_t j = 0; j < A.n; ++j) order[(size_t)start[(size_t)(maxlen - (cp[j + 1] - cp[j]))]++] = j;
+    gptr[0] = 0;
+    for (int32_t r = 0; r < A.n; ++r) {
+        rank[(size_t)order[r]] = r;
+        gptr[(size_t)r + 1] = gptr[r] + (cp[order[r] + 1] - cp[order[r]]);
+    }
+    if (!(flags & SPX_RENUMBER)) {
+        const int32_t hot = std::min(kHotCols, A.n);
+        const double share = (double)gptr[hot] / (double)nnz;
+        const double uniform = (double)hot / A.n;
+        if (A.n < 4 * kHotCols || share < std::max(0.3, 2.0 * uniform)) return SPX_OK;
+    }
+    const int vs = value_size(A.dtype);
+    if (hipMalloc((void**)&H->gorder, (size_t)A.n * 4) != hipSuccess ||
+        hipMalloc((void**)&H->grank, (size_t)A.n * 4) != hipSuccess ||
+        hipMalloc((void**)&H->gcol, (size_t)nnz * 4) != hipSuccess ||
+        (vs > 0 && hipMalloc(&H->gvals, (size_t)nnz * vs) != hipSuccess))
+        return fail(SPX_ERR_ALLOC, "renumbered CSR allocation failed");
+    uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
+    int32_t *rws = nullptr, *rq = nullptr, *dptr = nullptr;
+    const size_t rw = radix_ws_elems(nnz);
+    spx_status st = SPX_OK;
+    do {
+        if (hipMalloc((void**)&keys, nnz * 4) != hipSuccess || hipMalloc((void**)&vals, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&keys2, nnz * 4) != hipSuccess || hipMalloc((void**)&vals2, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&rws, rw * 4) != hipSuccess || hipMalloc((void**)&rq, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&dptr, gptr.size() * 4) != hipSuccess) {
+            st = fail(SPX_ERR_ALLOC, "renumbering temporaries: allocation failed");
+            break;
+        }
+        if (hipMemcpyAsync(H->gorder, order.data(), order.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(H->grank, rank.data(), rank.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(dptr, gptr.data(), gptr.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "renumbering upload");
+            break;
+        }
+        if ((st = expand_rows(dptr, A.n, rq, s))) break;
+        const int grid = (int)std::min<int64_t>(ceil_div(nnz, kBlock), 8192);
+        k_rank_major<<<grid, kBlock, 0, s>>>(nnz, rq, dptr, H->gorder, H->col_ptr, H->row_idx, H->perm, keys, vals);
+        bool alt = false;
+        // stable by row: within a row the entries keep their rank order
+        if ((st = radix_sort_pairs(keys, vals, keys2, vals2, nnz, key_bits_for(A.m), rws, s, &alt))) break;
+        H->gsrc = (int32_t*)(alt ? vals2 : vals);
+        (alt ? vals2 : vals) = nullptr;
+        k_renumber_cols<<<grid, kBlock, 0, s>>>(nnz, H->gsrc, A.col_idx, H->grank, H->gcol);
+        if (hipGetLastError() != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "renumbering kernels");
+            break;
+        }
+        if (vs > 0 && (st = gather_perm(A.vals, H->gsrc, H->gvals, nnz, vs, s))) break;
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(SPX_ERR_HIP, "renumbering sync");
+    } while (0);
+    for (void* p : {(void*)keys, (void*)vals, (void*)keys2, (void*)vals2, (void*)rws, (void*)rq, (void*)dptr})
+        if (p) hipFree(p);
+    if (st != SPX_OK) return st;
+    H->gcsr = A;
+    H->gcsr.col_idx = H->gcol;
+    H->gcsr.vals = vs > 0 ? H->gvals : nullptr;
+    return SPX_OK;
+}
+
 extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* stream, spx_matrix** out) {
     if (!out) return fail(SPX_ERR_ARG, "out is null");
     *out = nullptr;
@@ -462,6 +583,7 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
         }
     }
     st = build_csc(H, s);
+    if (st == SPX_OK) st = build_gcsr(H, flags, s);
     if (st == SPX_OK) {
         MatrixStats ms;
         st = matrix_features_device(A->row_ptr, A->m, A->n, &ms, s);
@@ -488,7 +610,18 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     if (!H) return fail(SPX_ERR_ARG, "handle is null");
     const int vs = value_size(H->csr.dtype);
     if (vs == 0 || H->csr.nnz == 0) return SPX_OK;
-    return gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream);
+    SPX_TRY(gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream));
+    if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_column_order(const spx_matrix* H, int32_t* order, int32_t* renumbered,
+                                              void* stream) {
+    if (!H || !renumbered) return fail(SPX_ERR_ARG, "null argument");
+    *renumbered = H->gorder ? 1 : 0;
+    if (!H->gorder || !order || H->csr.n == 0) return SPX_OK;
+    SPX_HIP(hipMemcpyAsync(order, H->gorder, (size_t)H->csr.n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SPX_OK;
 }
 
 extern "C" spx_status spx_matrix_features(const spx_matrix* H, double* out9) {
@@ -660,7 +793,8 @@ static void record(spx_matrix* H, std::vector<std::pair<hipEvent_t, hipEvent_t>>
 // Executes plan p for x. nnz_s_hint: exact nnz_s if known (else -1).
 static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_plan* p, int64_t nnz_s_hint,
                             int64_t nnz_x_known, hipStream_t s) {
-    const spx_csr& A = H->csr;
+    // the row-major kernels read the renumbered copy when there is one
+    const spx_csr& A = H->gorder && p->pattern != SPX_PAT_CSC_SPMSPV ? H->gcsr : H->csr;
     const int dt = A.dtype;
     SPX_TRY(spx_check_plan(p, dt));
     SPX_TRY(ensure_conv(H));
@@ -668,7 +802,12 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         const void* xd = x->val;
         if (x->kind == SPX_VEC_SPARSE) {
             record(H, H->ev_conv, true, s);
-            SPX_TRY(sparse_to_dense(A.n, x->nnz_x, x->idx, x->val, dt, H->xd, s));
+            SPX_TRY(sparse_to_dense(A.n, x->nnz_x, x->idx, x->val, dt, H->grank, H->xd, s));
+            record(H, H->ev_conv, false, s);
+            xd = H->xd;
+        } else if (H->gorder) {
+            record(H, H->ev_conv, true, s);
+            SPX_TRY(permute_dense(A.n, x->val, dt, H->gorder, H->xd, nullptr, s));
             record(H, H->ev_conv, false, s);
             xd = H->xd;
         }
@@ -685,7 +824,11 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         const void* xd = nullptr;
         record(H, H->ev_conv, true, s);
         if (x->kind == SPX_VEC_SPARSE) {
-            SPX_TRY(sparse_to_bitvector(A.n, x->nnz_x, x->idx, x->val, dt, H->bits, dt == SPX_BOOL ? nullptr : H->xd, s));
+            SPX_TRY(sparse_to_bitvector(A.n, x->nnz_x, x->idx, x->val, dt, H->grank, H->bits,
+                                        dt == SPX_BOOL ? nullptr : H->xd, s));
+            xd = dt == SPX_BOOL ? nullptr : H->xd;
+        } else if (H->gorder) {
+            SPX_TRY(permute_dense(A.n, x->val, dt, H->gorder, H->xd, H->bits, s));
             xd = dt == SPX_BOOL ? nullptr : H->xd;
         } else {
             const unsigned g = (unsigned)std::max<int64_t>(1, ceil_div(ceil_div(A.n, 32), kBlock));

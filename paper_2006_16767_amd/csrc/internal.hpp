@@ -111,11 +111,15 @@ spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
 size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
 
 // sparse x -> bitvector of supp(x) (cleared first) + scattered values xd[n]
+// (map, if given, renumbers the columns: entry j lands at map[j])
 spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                               int dtype, uint32_t* bits, void* xd, hipStream_t s);
-// sparse x -> zero-filled dense x
+                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s);
+// sparse x -> zero-filled dense x (map as above)
 spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                           int dtype, void* xd, hipStream_t s);
+                           int dtype, const int32_t* map, void* xd, hipStream_t s);
+// dense x -> xg[r] = x[order[r]], plus the bitvector of xg's nonzeros if bits
+spx_status permute_dense(int32_t n, const void* x, int dtype, const int32_t* order, void* xg, uint32_t* bits,
+                         hipStream_t s);
 // dense x -> (idx, val) of its nonzeros in index order; count to *nnz_dev
 size_t compact_ws_elems(int32_t n);
 spx_status dense_to_sparse(int32_t n, const void* x, int dtype, int32_t* idx, void* val,

@@ -334,30 +334,31 @@ spx_status gather_perm(const void* in, const int32_t* perm, void* out, int64_t n
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter_bits(int32_t nnz_x, const int32_t* __restrict__ idx,
                                                          const T* __restrict__ val,
+                                                         const int32_t* __restrict__ map,
                                                          uint32_t* __restrict__ bits,
                                                          T* __restrict__ xd) {
     int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= nnz_x) return;
-    const int j = idx[e];
+    const int j = map ? map[idx[e]] : idx[e];
     atomicOr(&bits[j >> 5], 1u << (j & 31));
     if (xd) xd[j] = val[e];
 }
 
 spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                               int dtype, uint32_t* bits, void* xd, hipStream_t s) {
+                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s) {
     SPX_TRY(fill_u32(bits, 0u, (size_t)ceil_div(n, 32), s));
     if (nnz_x <= 0) return SPX_OK;
     const unsigned g = (unsigned)ceil_div(nnz_x, kBlock);
     switch (value_size(dtype)) {
         case 0:
-            k_scatter_bits<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, nullptr, bits, nullptr);
+            k_scatter_bits<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, nullptr, map, bits, nullptr);
             break;
         case 4:
-            k_scatter_bits<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint32_t*)x_val, bits,
+            k_scatter_bits<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint32_t*)x_val, map, bits,
                                                           (uint32_t*)xd);
             break;
         case 8:
-            k_scatter_bits<uint64_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint64_t*)x_val, bits,
+            k_scatter_bits<uint64_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint64_t*)x_val, map, bits,
                                                           (uint64_t*)xd);
             break;
     }
@@ -368,29 +369,74 @@ spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, c
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter_dense(int32_t nnz_x, const int32_t* __restrict__ idx,
                                                           const T* __restrict__ val, T one,
+                                                          const int32_t* __restrict__ map,
                                                           T* __restrict__ xd) {
     int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= nnz_x) return;
-    xd[idx[e]] = val ? val[e] : one;
+    xd[map ? map[idx[e]] : idx[e]] = val ? val[e] : one;
 }
 
 spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                           int dtype, void* xd, hipStream_t s) {
+                           int dtype, const int32_t* map, void* xd, hipStream_t s) {
     SPX_TRY(fill_bytes(xd, 0, (size_t)n * std::max(1, value_size(dtype)), s));
     if (nnz_x <= 0) return SPX_OK;
     const unsigned g = (unsigned)ceil_div(nnz_x, kBlock);
     switch (value_size(dtype)) {
         case 0:
-            k_scatter_dense<uint8_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, nullptr, (uint8_t)1, (uint8_t*)xd);
+            k_scatter_dense<uint8_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, nullptr, (uint8_t)1, map, (uint8_t*)xd);
             break;
         case 4:
-            k_scatter_dense<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint32_t*)x_val, 0u,
+            k_scatter_dense<uint32_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint32_t*)x_val, 0u, map,
                                                            (uint32_t*)xd);
             break;
         case 8:
-            k_scatter_dense<uint64_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint64_t*)x_val, 0ull,
+            k_scatter_dense<uint64_t><<<g, kBlock, 0, s>>>(nnz_x, x_idx, (const uint64_t*)x_val, 0ull, map,
                                                            (uint64_t*)xd);
             break;
+    }
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+// xg[r] = x[order[r]] (a dense x in the renumbered column order) and, if
+// bits is given, the bitvector of xg's nonzeros, one wave ballot per 64
+// entries.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute_dense(int32_t n, const T* __restrict__ x,
+                                                          const int32_t* __restrict__ order,
+                                                          T* __restrict__ xg, uint32_t* __restrict__ bits) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    T v = 0;
+    if (r < n) {
+        v = x[order[r]];
+        xg[r] = v;
+    }
+    if (!bits) return;
+    const uint64_t b = __ballot(r < n && v != (T)0);
+    const int64_t base = r - lane_id();
+    if (lane_id() == 0 && base < n) bits[base >> 5] = (uint32_t)b;
+    if (lane_id() == 32 && base + 32 < n) bits[(base >> 5) + 1] = (uint32_t)(b >> 32);
+}
+
+spx_status permute_dense(int32_t n, const void* x, int dtype, const int32_t* order, void* xg, uint32_t* bits,
+                         hipStream_t s) {
+    if (n <= 0) return SPX_OK;
+    const unsigned g = (unsigned)ceil_div(n, kBlock);
+    switch (dtype) {
+        case SPX_F32:
+            k_permute_dense<float><<<g, kBlock, 0, s>>>(n, (const float*)x, order, (float*)xg, bits);
+            break;
+        case SPX_F64:
+            k_permute_dense<double><<<g, kBlock, 0, s>>>(n, (const double*)x, order, (double*)xg, bits);
+            break;
+        case SPX_I32:
+            k_permute_dense<int32_t><<<g, kBlock, 0, s>>>(n, (const int32_t*)x, order, (int32_t*)xg, bits);
+            break;
+        case SPX_BOOL:
+            k_permute_dense<uint8_t><<<g, kBlock, 0, s>>>(n, (const uint8_t*)x, order, (uint8_t*)xg, bits);
+            break;
+        default:
+            return fail(SPX_ERR_DTYPE, "permute_dense: dtype");
     }
     SPX_HIP(hipGetLastError());
     return SPX_OK;

@@ -1,0 +1,224 @@
+"""Profiling drivers and rocprofv3 summaries.
+
+The drivers run one piece of work so that a counter pass
+(`rocprofv3 --pmc ...`) sees exactly the dispatches of interest; the
+summaries read the rocpd databases rocprofv3 writes (`*_results.db`).
+
+  python -m paper_2006_16767_amd.prof vector K [--reps R]
+      run() on vector K of the R-MAT 2^20 (degree 16) sweep, R times after
+      one warm-up call; prints the plan and its kernel-name stems.
+  python -m paper_2006_16767_amd.prof copy [--mib M] [--reps R]
+      a plain device-to-device copy of M MiB, R times (counter calibration:
+      it reads and writes exactly M MiB).
+  python -m paper_2006_16767_amd.prof kernels DB --title T --command C
+      kernel-trace summary (markdown) of a `--kernel-trace --stats` db.
+  python -m paper_2006_16767_amd.prof traffic --fetch DB --write DB
+        --copy-fetch DB --copy-write DB --mib M --vector K --out JSON
+      HBM bytes per launch of vector K's kernels: FETCH_SIZE and WRITE_SIZE
+      (KiB per dispatch) scaled by what the same counters read for the copy
+      of M MiB; written with the hash of the library sources, so the figure
+      is void once a kernel changes.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SWEEP_WORKLOAD = "rmat20_deg16_f32_sweep12"
+
+
+def library_source_hash() -> str:
+    """sha256 over the library's kernel and host sources, in name order."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if path.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def kernel_names(p) -> list[str]:
+    """Kernel-name stems of the launches a plan makes."""
+    if p.pattern in (0, 1):
+        if p.distribution == 0:
+            return ["k_csr_direct"]
+        return (["k_csr_bitlds"] if p.pattern == 1 and p.tile == 1 else ["k_csr_merge"]) + ["k_csr_merge_fixup"]
+    dist = "direct" if p.distribution == 0 else "merge"
+    if p.writeback == 4:
+        return [f"k_bucket_scatter_{dist}", "k_bucket_accumulate"]
+    if p.writeback == 2:
+        return [f"k_csc_{dist}_pairs", "k_radix_hist", "k_radix_scatter", "k_reduce_by_key"]
+    stem = {1: "atomic", 3: "lds"}[p.writeback]
+    return [f"k_csc_{dist}_{stem}"]
+
+
+def _stem(name: str) -> str:
+    """'void spx::k_csr_merge<0, false, 2048>(int, ...)' -> 'k_csr_merge'."""
+    n = name.replace("void ", "").replace("spx::", "")
+    for c in "<(":
+        i = n.find(c)
+        if i > 0:
+            n = n[:i]
+    return n.strip()
+
+
+def _db(path: str) -> str:
+    if os.path.isdir(path):
+        found = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+        if not found:
+            raise SystemExit(f"no *_results.db under {path}")
+        return found[-1]
+    return path
+
+
+def counter_per_dispatch(db: str, counter: str) -> list[tuple[int, str, float]]:
+    """(dispatch id, kernel name, counter value summed over its instances),
+    in dispatch order."""
+    con = sqlite3.connect(_db(db))
+    rows = con.execute(
+        "select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
+        "group by dispatch_id, kernel_name order by dispatch_id", (counter,)).fetchall()
+    con.close()
+    return [(int(d), k, float(v)) for d, k, v in rows]
+
+
+def _mean_by_stem(rows, stems):
+    """Mean per-dispatch value of each kernel stem, and its dispatch count."""
+    out = {}
+    for s in stems:
+        vals = [v for _, k, v in rows if _stem(k) == s]
+        out[s] = (sum(vals) / len(vals) if vals else None, len(vals))
+    return out
+
+
+def cmd_vector(args):
+    import torch
+    from . import Matrix
+    from . import synth
+    A = synth.cfg2_matrix()
+    vecs = synth.cfg2_vectors(A.n)
+    v = vecs[args.k]
+    M = Matrix.from_host(A)
+    x = (torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda"))
+    y = M.out_tensor()
+    M.run(x, y)
+    torch.cuda.synchronize()
+    p = M.last_plan()
+    print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p)}", flush=True)
+    for _ in range(args.reps):
+        M.run(x, y)
+    torch.cuda.synchronize()
+    print(f"[prof] {args.reps} runs done", flush=True)
+
+
+def cmd_copy(args):
+    import torch
+    n = args.mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[prof] copied {args.mib} MiB {args.reps} times", flush=True)
+
+
+def cmd_kernels(args):
+    con = sqlite3.connect(_db(args.db))
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    con.close()
+    scale = 1.0  # the top_kernels view reports microseconds
+    print(f"# {args.title}\n")
+    print(f"Command (run from the repository root on one MI355X):\n\n```\n{args.command}\n```\n")
+    print("Durations in microseconds (rocprofv3 kernel trace, `top_kernels` view).\n")
+    print("| kernel | calls | total us | avg us | % |")
+    print("|---|---:|---:|---:|---:|")
+    for n, c, t, a, p in rows[:args.top]:
+        short = n.replace("spx::", "")
+        i = short.find("(")
+        short = short[:i] if i > 0 else short
+        print(f"| `{short}` | {c} | {t * scale:.1f} | {a * scale:.3f} | {p:.1f} |")
+
+
+def cmd_traffic(args):
+    copy_bytes = args.mib * (1 << 20)
+    cf = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE")
+    cw = counter_per_dispatch(args.copy_write, "WRITE_SIZE")
+    # the copy is the largest dispatch of its run
+    f_copy = max(v for _, _, v in cf) * 1024.0
+    w_copy = max(v for _, _, v in cw) * 1024.0
+    k_fetch = copy_bytes / f_copy
+    k_write = copy_bytes / w_copy
+    stems = args.kernels.split(",")
+    fr = _mean_by_stem(counter_per_dispatch(args.fetch, "FETCH_SIZE"), stems)
+    wr = _mean_by_stem(counter_per_dispatch(args.write, "WRITE_SIZE"), stems)
+    fetch = sum((fr[s][0] or 0.0) for s in stems) * 1024.0 * k_fetch
+    write = sum((wr[s][0] or 0.0) for s in stems) * 1024.0 * k_write
+    rec = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            rec = json.load(f)
+    key = f"{SWEEP_WORKLOAD}:v{args.vector}"
+    rec[key] = {
+        "kernels": stems,
+        "dispatches": {s: [fr[s][1], wr[s][1]] for s in stems},
+        "fetch_bytes_per_launch": round(fetch),
+        "write_bytes_per_launch": round(write),
+        "bytes_per_launch": round(fetch + write),
+        "calibration": {"copy_bytes": copy_bytes, "fetch_factor": round(k_fetch, 4),
+                        "write_factor": round(k_write, 4)},
+        "library_sha256": library_source_hash(),
+        "commands": args.command or [],
+    }
+    with open(args.out, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(rec[key]))
+
+
+def traffic_for(path: str, vector: int):
+    """Committed HBM bytes per launch of the sweep vector's kernels, or None
+    if absent or taken on library sources other than the current ones."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(f"{SWEEP_WORKLOAD}:v{vector}")
+    if not rec or rec.get("library_sha256") != library_source_hash():
+        return None
+    return rec["bytes_per_launch"]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2006_16767_amd.prof")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("vector")
+    a.add_argument("k", type=int)
+    a.add_argument("--reps", type=int, default=5)
+    a = sub.add_parser("copy")
+    a.add_argument("--mib", type=int, default=512)
+    a.add_argument("--reps", type=int, default=3)
+    a = sub.add_parser("kernels")
+    a.add_argument("db")
+    a.add_argument("--title", required=True)
+    a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=30)
+    a = sub.add_parser("traffic")
+    for n in ("fetch", "write", "copy_fetch", "copy_write", "out", "kernels"):
+        a.add_argument("--" + n.replace("_", "-"), dest=n, required=True)
+    a.add_argument("--mib", type=int, required=True)
+    a.add_argument("--vector", type=int, required=True)
+    a.add_argument("--command", action="append")
+    args = ap.parse_args(argv)
+    {"vector": cmd_vector, "copy": cmd_copy, "kernels": cmd_kernels, "traffic": cmd_traffic}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -367,3 +367,32 @@ def test_backward_matches_oracle(dt):
     rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr))
     sdv = (np.abs(G[:, rows].astype(np.float64)) * np.abs(X[:, A.col_idx].astype(np.float64))).sum(0)
     assert_close(dv, dv_ref, sdv, dt, "dvals")
+
+
+# ------------------------------------------------------------------ launch parameters
+
+def _variant_plans():
+    out = []
+    for L in (1, 2, 4, 8, 16, 32, 64):
+        out += [spx.plan("spmv", "direct", lanes=L), spx.plan("csr_spmspv", "direct", lanes=L)]
+        for wb in ("atomic", "lds_atomic", "sort", "bucket"):
+            out.append(spx.plan("csc_spmspv", "direct", wb, lanes=L))
+    for T in (2048, 4096):
+        out += [spx.plan("spmv", "balanced", tile=T), spx.plan("csr_spmspv", "balanced", tile=T)]
+    out.append(spx.plan("csr_spmspv", "balanced", tile=1))
+    for R in (64, 256, 1024, 8192):
+        out += [spx.plan("csc_spmspv", "balanced", "bucket", bucket_rows=R),
+                spx.plan("csc_spmspv", "direct", "bucket", bucket_rows=R)]
+    return out
+
+
+@pytest.mark.parametrize("kind", ["f32", "i32"])
+@pytest.mark.parametrize("name", ["cfg1", "rmat16"])
+def test_launch_parameter_variants(name, kind):
+    """Every explicit lane count, merge tile and bucket height gives the
+    oracle's result (the automatic choices cover only one of each)."""
+    _torch()
+    A, M = _matrix(cfg_matrix(name), kind)
+    for nnz_x in (max(1, A.n // 100), A.n // 2):
+        v = synth.sparse_vector(A.n, nnz_x, 900 + nnz_x)
+        _run_and_check(M, A, v.idx, _vec_vals(v, kind), kind, _variant_plans(), f"{name} {kind} nnz_x={nnz_x}")
