@@ -59,9 +59,13 @@ def _ptr(t):
 
 
 def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream)
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:  # the current stream's handle without building a Stream object
+        return C.c_void_p(raw(torch._C._cuda_getDevice()))
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def plan(pattern="spmv", distribution="direct", writeback="none", lanes=0, tile=0, bucket_rows=0) -> Plan:

@@ -124,6 +124,42 @@ __global__ __launch_bounds__(kBlock) void k_x_lengths(int32_t nnz_x, const int32
     len[e] = col_ptr[j + 1] - col_ptr[j];
 }
 
+// Prologue of the column-major kernels for a short x, in one launch:
+// workgroup 0 writes excl (exclusive prefix of the selected column lengths,
+// nnz_x + 1 entries, each thread a run of kProIpt consecutive entries);
+// the other workgroups zero y (ywords 32-bit words, then ytail bytes).
+constexpr int kProIpt = 32;
+constexpr int kProMax = kBlock * kProIpt;  // nnz_x + 1 <= kProMax
+
+__global__ __launch_bounds__(kBlock) void k_csc_prologue(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                         const int32_t* __restrict__ col_ptr,
+                                                         int32_t* __restrict__ excl, uint32_t* __restrict__ y,
+                                                         int64_t ywords, int ytail) {
+    if (blockIdx.x == 0) {
+        __shared__ int32_t tmp[kWavesPerBlock];
+        const int e0 = threadIdx.x * kProIpt;
+        int j[kProIpt], len[kProIpt];
+#pragma unroll
+        for (int u = 0; u < kProIpt; ++u) j[u] = e0 + u < nnz_x ? x_idx[e0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kProIpt; ++u) len[u] = j[u] >= 0 ? col_ptr[j[u] + 1] - col_ptr[j[u]] : 0;
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < kProIpt; ++u) sum += len[u];
+        int total;
+        int run = block_incl_scan<int32_t>(sum, tmp, &total) - sum;
+#pragma unroll
+        for (int u = 0; u < kProIpt; ++u) {
+            if (e0 + u <= nnz_x) excl[e0 + u] = run;
+            run += len[u];
+        }
+        return;
+    }
+    const int64_t stride = (int64_t)(gridDim.x - 1) * kBlock;
+    for (int64_t i = (int64_t)(blockIdx.x - 1) * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = 0u;
+    if (blockIdx.x == 1 && (int)threadIdx.x < ytail) ((uint8_t*)(y + ywords))[threadIdx.x] = 0;
+}
+
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_csc_merge_atomic(int32_t nnz_x, const int32_t* __restrict__ x_idx,
                                                              const typename SR<DT>::X* __restrict__ x_val,
@@ -326,24 +362,35 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int dist = plan->distribution;
     const size_t ybytes = (size_t)A.m * sizeof(typename S::Y);
     if (A.m == 0) return SPX_OK;
-    // the bucket write-back writes every row itself
-    if (wb != SPX_WB_BUCKET || nnz_x == 0) SPX_TRY(fill_bytes(y, 0, ybytes, s));
-    if (nnz_x == 0) return SPX_OK;
     const int L = plan->lanes > 0 ? plan->lanes : pick_col_lanes(A.n, A.nnz);
     const bool lds_ok = (int64_t)A.m * (int64_t)sizeof(Acc) <= kLdsBytes;
-    if (wb == SPX_WB_LDS_ATOMIC && !lds_ok)
+    if (wb == SPX_WB_LDS_ATOMIC && !lds_ok && nnz_x > 0)
         return fail(SPX_ERR_UNSUPPORTED, "lds-atomic write-back needs m * sizeof(acc) <= 64 KiB");
-
+    // the bucket write-back writes every row itself
+    const bool fill_y = wb != SPX_WB_BUCKET || nnz_x == 0;
+    const bool need_excl = nnz_x > 0 && (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET);
     int32_t* excl = nullptr;
-    if (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET) {
+    if (need_excl) {
         excl = ws.take<int32_t>((size_t)nnz_x + 1);
         int32_t* sws = ws.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
         if (!excl || !sws) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
-        k_x_lengths<<<(unsigned)ceil_div((int64_t)nnz_x + 1, kBlock), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr,
-                                                                                       excl);
-        SPX_HIP(hipGetLastError());
-        SPX_TRY(scan_exclusive_i32(excl, excl, (int64_t)nnz_x + 1, nullptr, sws, s));
+        if (nnz_x + 1 <= kProMax && ((uintptr_t)y & 3) == 0) {
+            const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
+            const int fill_blocks = fill_y ? (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ywords, kBlock), 4096)) : 0;
+            k_csc_prologue<<<1 + fill_blocks, kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, (uint32_t*)y, ywords,
+                                                             fill_y ? (int)(ybytes & 3) : 0);
+            SPX_HIP(hipGetLastError());
+        } else {
+            if (fill_y) SPX_TRY(fill_bytes(y, 0, ybytes, s));
+            k_x_lengths<<<(unsigned)ceil_div((int64_t)nnz_x + 1, kBlock), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr,
+                                                                                           excl);
+            SPX_HIP(hipGetLastError());
+            SPX_TRY(scan_exclusive_i32(excl, excl, (int64_t)nnz_x + 1, nullptr, sws, s));
+        }
+    } else if (fill_y) {
+        SPX_TRY(fill_bytes(y, 0, ybytes, s));
     }
+    if (nnz_x == 0) return SPX_OK;
     // grid of the balanced kernels: enough tiles for the known or bounded work
     const int64_t ub = A.nnz_s_hint >= 0 ? A.nnz_s_hint : (int64_t)A.nnz;
     const int64_t merge_tiles = std::max<int64_t>(1, ceil_div((int64_t)nnz_x + ub, kCscTile));

@@ -4,9 +4,10 @@ The drivers run one piece of work so that a counter pass
 (`rocprofv3 --pmc ...`) sees exactly the dispatches of interest; the
 summaries read the rocpd databases rocprofv3 writes (`*_results.db`).
 
-  python -m paper_2006_16767_amd.prof vector K [--reps R]
-      run() on vector K of the R-MAT 2^20 (degree 16) sweep, R times after
-      one warm-up call; prints the plan and its kernel-name stems.
+  python -m paper_2006_16767_amd.prof vector K [--reps R] [--plan P,D[,W]]
+      run() (or run_plan with the given plan) on vector K of the R-MAT 2^20
+      (degree 16) sweep, R times after one warm-up call; prints the plan and
+      its kernel-name stems.
   python -m paper_2006_16767_amd.prof copy [--mib M] [--reps R]
       a plain device-to-device copy of M MiB, R times (counter calibration:
       it reads and writes exactly M MiB).
@@ -100,7 +101,7 @@ def _mean_by_stem(rows, stems):
 
 def cmd_vector(args):
     import torch
-    from . import Matrix
+    from . import Matrix, plan
     from . import synth
     A = synth.cfg2_matrix()
     vecs = synth.cfg2_vectors(A.n)
@@ -108,12 +109,17 @@ def cmd_vector(args):
     M = Matrix.from_host(A)
     x = (torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda"))
     y = M.out_tensor()
-    M.run(x, y)
+    if args.plan:
+        p = plan(*args.plan.split(","))
+        call = lambda: M.run_plan(x, p, y)  # noqa: E731
+    else:
+        call = lambda: M.run(x, y)  # noqa: E731
+    call()
     torch.cuda.synchronize()
     p = M.last_plan()
     print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p)}", flush=True)
     for _ in range(args.reps):
-        M.run(x, y)
+        call()
     torch.cuda.synchronize()
     print(f"[prof] {args.reps} runs done", flush=True)
 
@@ -202,6 +208,7 @@ def main(argv=None):
     a = sub.add_parser("vector")
     a.add_argument("k", type=int)
     a.add_argument("--reps", type=int, default=5)
+    a.add_argument("--plan", help="pattern,distribution[,writeback] instead of run()'s choice")
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=512)
     a.add_argument("--reps", type=int, default=3)

@@ -16,7 +16,8 @@ Workloads (the paper's own datasets are not available; these stand in):
               randomly relabelled; A[i, j] = 1 iff edge j -> i, so a column
               is a vertex's out-edges (push) and a row its in-edges (pull)
   * poisson3d: 7-point Laplacian on a k^3 grid, Dirichlet, x-fastest order
-  * powerlaw: rows with Pareto(1.5) lengths (SVM-like data matrix)
+  * powerlaw: rows with Pareto(1.5) lengths (SVM-like data matrix); the
+              column variant skews column lengths instead
   * bernoulli: each entry present with probability p (pruned FC layer)
 """
 from __future__ import annotations
@@ -225,6 +226,18 @@ def powerlaw_rows(m: int, n: int, mean_len: float, seed: int, alpha: float = 1.5
     return CSR(m, n, row_ptr.astype(np.int32), cols.astype(np.int32), vals,
                {"kind": "powerlaw", "alpha": alpha, "x_min": xm, "mean": float(L.mean()),
                 "seed": seed})
+
+
+def powerlaw_cols(m: int, n: int, mean_len: float, seed: int, alpha: float = 1.5,
+                  dtype=np.float32) -> CSR:
+    """Columns with Pareto(alpha) lengths of mean mean_len and uniformly
+    placed distinct rows (feature-popularity skew): the column draws of
+    powerlaw_rows with the roles of m and n swapped, stored as CSR."""
+    D = powerlaw_rows(n, m, mean_len, seed, alpha, dtype)
+    cols = np.repeat(np.arange(n, dtype=np.int64), np.diff(D.row_ptr))
+    A = _coo_to_csr(m, n, np.asarray(D.col_idx, np.int64), cols, D.vals)
+    A.meta = {"kind": "powerlaw_cols", "mean_len": mean_len, "alpha": alpha, "seed": seed}
+    return A
 
 
 def bernoulli(m: int, n: int, p: float, seed: int, std: float = 0.02,

@@ -3,8 +3,8 @@
     python -m paper_2006_16767_amd.tune sweep --out sweep.jsonl   # on the GPU
     python -m paper_2006_16767_amd.tune train sweep.jsonl --out selector.json
 
-sweep  builds a synthetic corpus (uniform, banded, R-MAT, Poisson, power-law
-       and Bernoulli matrices; for each, input vectors whose nnz_x grows from
+sweep  builds a synthetic corpus (uniform, R-MAT, Poisson stencil, power-law,
+       Bernoulli and SVM-like feature matrices; for each, input vectors whose nnz_x grows from
        1 to n on a log scale, uniformly placed), times every candidate kernel
        with HIP events (median of several runs, the result of each run
        discarded), and appends one JSON record per (matrix, vector): the 13
@@ -50,28 +50,43 @@ def corpus(quick: bool = False):
     """(name, generator) pairs of the synthetic training matrices."""
     from . import synth
     mats = [
+        ("uniform_4k_d16", lambda: synth.uniform_rows(4096, 4096, 16, 43)),
+        ("uniform_16k_d4", lambda: synth.uniform_rows(16384, 16384, 4, 44)),
         ("uniform_64k_d8", lambda: synth.uniform_rows(65536, 65536, 8, 11)),
+        ("uniform_128k_d64", lambda: synth.uniform_rows(131072, 131072, 64, 45)),
         ("uniform_256k_d32", lambda: synth.uniform_rows(262144, 262144, 32, 12)),
         ("uniform_1m_d16", lambda: synth.uniform_rows(1 << 20, 1 << 20, 16, 13)),
+        ("uniform_2m_d8", lambda: synth.uniform_rows(1 << 21, 1 << 21, 8, 46)),
         ("rmat14_d16", lambda: synth.rmat(14, 16, 21)),
+        ("rmat16_d4", lambda: synth.rmat(16, 4, 26)),
         ("rmat17_d8", lambda: synth.rmat(17, 8, 22)),
         ("rmat18_d32", lambda: synth.rmat(18, 32, 23)),
+        ("rmat19_d16", lambda: synth.rmat(19, 16, 27)),
+        ("rmat20_d4", lambda: synth.rmat(20, 4, 28)),
         ("rmat20_d16", lambda: synth.rmat(20, 16, 24)),
         ("rmat20_d16_nrl", lambda: synth.rmat(20, 16, 25, relabel=False)),
+        ("rmat21_d8", lambda: synth.rmat(21, 8, 29)),
+        ("poisson32", lambda: synth.poisson3d(32)),
         ("poisson64", lambda: synth.poisson3d(64)),
+        ("poisson100", lambda: synth.poisson3d(100)),
         ("poisson128", lambda: synth.poisson3d(128)),
         ("powerlaw_100k_50k", lambda: synth.powerlaw_rows(100_000, 50_000, 40.0, 31)),
         ("powerlaw_500k_500k", lambda: synth.powerlaw_rows(500_000, 500_000, 12.0, 32)),
+        ("powerlaw_1m_1m", lambda: synth.powerlaw_rows(1 << 20, 1 << 20, 6.0, 33)),
+        ("powerlaw_50k_200k_a2", lambda: synth.powerlaw_rows(50_000, 200_000, 20.0, 34, alpha=2.0)),
         ("bernoulli_16k_4k", lambda: synth.bernoulli(16384, 4096, 0.05, 41)),
         ("bernoulli_4k_16k", lambda: synth.bernoulli(4096, 16384, 0.02, 42)),
-        ("uniform_4k_d16", lambda: synth.uniform_rows(4096, 4096, 16, 43)),
+        ("bernoulli_32k_8k", lambda: synth.bernoulli(32768, 8192, 0.01, 47)),
+        ("bernoulli_8k_8k", lambda: synth.bernoulli(8192, 8192, 0.1, 48)),
+        ("powerlaw_200k_1m", lambda: synth.powerlaw_rows(200_000, 1 << 20, 8.0, 35)),
+        ("powerlaw_cols_1m_200k", lambda: synth.powerlaw_cols(1 << 20, 200_000, 8.0, 36)),
     ]
     if quick:
-        mats = [m for m in mats if m[0] in ("uniform_4k_d16", "rmat14_d16", "poisson64")]
+        mats = [m for m in mats if m[0] in ("uniform_4k_d16", "rmat14_d16", "poisson32")]
     return mats
 
 
-def densities(n: int, count: int = 16):
+def densities(n: int, count: int = 24):
     """nnz_x from 1 to n, log-spaced (the paper grows nnz_x from 1 to n)."""
     vals = np.unique(np.round(np.geomspace(1, n, count)).astype(np.int64))
     return [int(v) for v in vals]
