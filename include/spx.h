@@ -297,6 +297,15 @@ spx_status run_batch(spx_matrix *H, int32_t B, int64_t total_nnz_x, const int32_
  * stream. */
 spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
 
+/* Y[b] = A X[b] for the B rows of a dense X (B x n -> Y B x m, device,
+ * row-major): the row-major SpMV of Section 4.1 applied to all B vectors
+ * in one pass over A (a wave per row, lane = batch entry, entries of x
+ * gathered from a B-minor copy of X in the workspace). Reads A once where
+ * B separate calls read it B times; meant for dense batches such as layer
+ * activations. One wave walks a whole row, so rows far longer than the
+ * average (hub rows) serialize. F32 and F64 only. */
+spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void *stream);
+
 /* ---------------------------------------------------------------------
  * Backward of Y[b] = A(vals) X[b] for a loss L(Y), with G = dL/dY
  * (B x m) and X (B x n), both dense, row-major, on the device:

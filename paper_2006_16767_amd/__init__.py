@@ -282,6 +282,15 @@ class Matrix:
         _lib.call("spx_dense_rows_to_sparse", self._h, B, _ptr(X), _ptr(vp), _ptr(idx), _ptr(val), _stream(stream))
         return self.run_batch(vp, idx, val, Y, total_nnz_x=B * self.n, stream=stream)
 
+    def spmv_batch(self, X, Y=None, stream=None):
+        """Y[b] = A X[b] for the rows of a dense X (B x n) in one pass over
+        A (F32/F64)."""
+        X2 = X.reshape(-1, self.n).contiguous()
+        B = int(X2.shape[0])
+        Y = self.out_tensor(B) if Y is None else Y
+        _lib.call("spmv_csr_batch", self._h, B, _ptr(X2), _ptr(Y), _stream(stream))
+        return Y
+
     def batch_status(self, stream=None) -> int:
         f = C.c_int32()
         _lib.call("spx_batch_status", self._h, C.byref(f), _stream(stream))

@@ -2,8 +2,10 @@
 each row x_b of a dense batch X (B x n), e.g. a pruned fully-connected
 layer applied to post-ReLU activations.
 
-Forward: the library converts each row of X to a sparse vector on the
-device and runs the batched SpMSpV (plans chosen per vector on the device).
+Forward, two ways: "fused" (default) runs the row-major SpMV of every row
+of X in one pass over A (spmv_csr_batch); "sparse" converts each row of X
+to a sparse vector on the device and runs the batched SpMSpV, with the plan
+of each vector chosen on the device (run_batch).
 Backward (F32/F64): dX = G A (gather along the CSC columns, no atomics) and
 dvals_k = sum_b G[b, row k] X[b, col k] over the stored pattern; both
 kernels read the matrix once for the whole batch.
@@ -23,12 +25,17 @@ from . import Matrix
 
 class SparseLinearFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, vals, X, M: Matrix):
+    def forward(ctx, vals, X, M: Matrix, mode: str = "fused"):
         if vals.data_ptr() != M.vals.data_ptr():
             raise ValueError("vals must be the value tensor the matrix handle was built on")
         M.values_updated()
         Xc = X.contiguous()
-        Y = M.run_dense_batch(Xc)
+        if mode == "fused":
+            Y = M.spmv_batch(Xc)
+        elif mode == "sparse":
+            Y = M.run_dense_batch(Xc)
+        else:
+            raise ValueError(f"mode must be 'fused' or 'sparse', not {mode!r}")
         ctx.save_for_backward(Xc)
         ctx.M = M
         return Y
@@ -40,9 +47,10 @@ class SparseLinearFunction(torch.autograd.Function):
         G = G.contiguous()
         dvals = M.dvals(G, X) if ctx.needs_input_grad[0] else None
         dX = M.transpose_matvec(G) if ctx.needs_input_grad[1] else None
-        return dvals, dX, None
+        return dvals, dX, None, None
 
 
-def sparse_linear(M: Matrix, X: torch.Tensor, vals: torch.Tensor | None = None) -> torch.Tensor:
+def sparse_linear(M: Matrix, X: torch.Tensor, vals: torch.Tensor | None = None,
+                  mode: str = "fused") -> torch.Tensor:
     """Y[b] = A(vals) X[b] for every row of X (B x n) -> (B x m)."""
-    return SparseLinearFunction.apply(M.vals if vals is None else vals, X, M)
+    return SparseLinearFunction.apply(M.vals if vals is None else vals, X, M, mode)

@@ -1058,6 +1058,17 @@ extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stre
 }
 
 // ------------------------------------------------------------------ backward
+extern "C" spx_status spmv_csr_batch(spx_matrix* H, int32_t B, const void* X, void* Y, void* stream) {
+    if (!H || (B > 0 && (!X || !Y))) return fail(SPX_ERR_ARG, "null argument");
+    if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    const int dt = H->csr.dtype;
+    if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "the fused batch SpMV supports F32 and F64");
+    SPX_TRY(ensure_ws(H, grad_ws_bytes(H->csr.m, H->csr.n, B, dt)));
+    Arena ws(H->ws, H->ws_bytes);
+    return launch_spmv_batch(H->csr.row_ptr, H->csr.col_idx, H->csr.vals, H->csr.m, H->csr.n, dt, B, X, Y, ws,
+                             (hipStream_t)stream);
+}
+
 extern "C" spx_status spmv_csr_transpose(spx_matrix* H, int32_t B, const void* G, void* dX, void* stream) {
     if (!H || (B > 0 && (!G || !dX))) return fail(SPX_ERR_ARG, "null argument");
     if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");

@@ -8,12 +8,16 @@
 // copies of the dense operands (G^T is m x B, X^T is n x B), so that the B
 // values one stored entry needs are 4 * B contiguous bytes:
 //
-//  k_spmm_csc   one wave per column j of A (a row of A^T, read from the CSC
+//  k_seg_gather one wave per column j of A (a row of A^T, read from the CSC
 //               copy: a gather along the column, no atomics); lane b
-//               accumulates sum_k vals[k] * G^T[row_k, b].
-//  k_sddmm      a group of lanes per row i of A; G^T[i, :] is staged in LDS
-//               once per row; every lane takes one stored entry k and forms
-//               the B-long dot product of G^T[i, :] and X^T[col_k, :].
+//               accumulates sum_k vals[k] * G^T[row_k, b] (eight entries in
+//               flight) and stores dX^T[j, b] coalesced; one transpose gives
+//               dX.
+//  k_sddmm      one wave per row i of A, lane b = batch entry: sixteen stored
+//               entries at a time, each lane forms its sixteen products
+//               G^T[i, b] X^T[col_k, b] (coalesced 4B-per-lane rows), and a
+//               butterfly over the wave folds the sixteen B-long sums with
+//               17 shuffles.
 #include <algorithm>
 
 #include "common.hpp"
@@ -48,71 +52,96 @@ static spx_status transpose(int64_t rows, int64_t cols, const T* in, T* out, hip
     return SPX_OK;
 }
 
-// dX[b0 + lane, j] for lanes < nb; GT is m x B
+// Segment gather over a batch: outT[j, b0 + lane] = sum over the entries k
+// of segment j of vals[k] * inT[idx[k], b0 + lane], for lanes < nb. inT and
+// outT are B-minor (rows of B values). With the CSC (segments = columns,
+// idx = rows, inT = G^T) it is dX^T = (G A)^T; with the CSR (segments =
+// rows, idx = columns, inT = X^T) it is Y^T for y_b = A x_b.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmm_csc(int32_t n, int32_t B, int32_t b0, int32_t nb,
-                                                     const int32_t* __restrict__ col_ptr,
-                                                     const int32_t* __restrict__ row_idx,
-                                                     const T* __restrict__ vals, const T* __restrict__ GT,
-                                                     T* __restrict__ dX) {
-    const int64_t j = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
-    if (j >= n) return;
+__global__ __launch_bounds__(kBlock) void k_seg_gather(int32_t nseg, int32_t B, int32_t b0, int32_t nb,
+                                                       const int32_t* __restrict__ seg_ptr,
+                                                       const int32_t* __restrict__ idx,
+                                                       const T* __restrict__ vals, const T* __restrict__ inT,
+                                                       T* __restrict__ outT) {
+    const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave_id());
+    if (j >= nseg) return;
     const int lane = lane_id();
     const bool on = lane < nb;
-    const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
-    const T* g = GT + b0 + (on ? lane : 0);
-    T acc = 0;
+    const int c0 = seg_ptr[j], c1 = seg_ptr[j + 1];
+    const int32_t* row_idx = idx;
+    const T* g = inT + b0 + (on ? lane : 0);
+    T acc0 = 0, acc1 = 0;
     int k = c0;
-    for (; k + 3 < c1; k += 4) {
-        int r[4];
-        T v[4], gv[4];
+    for (; k + 7 < c1; k += 8) {
+        int r[8];
+        T v[8], gv[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             r[u] = row_idx[k + u];
             v[u] = vals[k + u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) gv[u] = g[(int64_t)r[u] * B];
+        for (int u = 0; u < 8; ++u) gv[u] = g[(int64_t)r[u] * B];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_fma(v[u], gv[u], acc);
+        for (int u = 0; u < 8; u += 2) {
+            acc0 = __builtin_fma(v[u], gv[u], acc0);
+            acc1 = __builtin_fma(v[u + 1], gv[u + 1], acc1);
+        }
     }
-    for (; k < c1; ++k) acc = __builtin_fma(vals[k], g[(int64_t)row_idx[k] * B], acc);
-    if (on) dX[(int64_t)(b0 + lane) * n + j] = acc;
+    for (; k < c1; ++k) acc0 = __builtin_fma(vals[k], g[(int64_t)row_idx[k] * B], acc0);
+    if (on) outT[(int64_t)j * B + b0 + lane] = acc0 + acc1;
 }
 
-// dvals[k] for the entries of row i; L lanes per row, B <= 64 per pass
-template <typename T, int L>
+// Folds p[0..15] over the 64 lanes of a wave: lane l ends with the full sum
+// of value (l >> 2) & 15. Each step halves the values a lane keeps and pairs
+// it with the lane across one bit of the lane index.
+template <typename T>
+__device__ __forceinline__ T wave_fold16(T (&p)[16]) {
+    const int lane = lane_id();
+    T q[8], r[4], t[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) q[v] = (h5 ? p[v + 8] : p[v]) + shfl_xor(h5 ? p[v] : p[v + 8], 32);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r[v] = (h4 ? q[v + 4] : q[v]) + shfl_xor(h4 ? q[v] : q[v + 4], 16);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) t[v] = (h3 ? r[v + 2] : r[v]) + shfl_xor(h3 ? r[v] : r[v + 2], 8);
+    T s = (h2 ? t[1] : t[0]) + shfl_xor(h2 ? t[0] : t[1], 4);
+    s += shfl_xor(s, 2);
+    s += shfl_xor(s, 1);
+    return s;
+}
+
+// dvals[k] for the entries of row i: a wave per row, lane = batch entry
+// (chunks of 64 for B > 64).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sddmm(int32_t m, int32_t B, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_idx, const T* __restrict__ GT,
                                                   const T* __restrict__ XT, T* __restrict__ dvals) {
-    constexpr int kRows = kBlock / L;
-    __shared__ T s_g[kRows][64];
-    const int lr = threadIdx.x / L, g = threadIdx.x % L;
-    const int64_t row = (int64_t)blockIdx.x * kRows + lr;
-    const bool live = row < m;
-    for (int b0 = 0; b0 < B; b0 += 64) {
-        const int nb = std::min(64, B - b0);
-        if (live)
-            for (int b = g; b < nb; b += L) s_g[lr][b] = GT[row * B + b0 + b];
-        __syncthreads();
-        if (live) {
-            const int k0 = row_ptr[row], k1 = row_ptr[row + 1];
-            for (int k = k0 + g; k < k1; k += L) {
-                const T* xr = XT + (int64_t)col_idx[k] * B + b0;
-                T acc = 0;
-                int b = 0;
-                for (; b + 3 < nb; b += 4) {
-                    const T x0 = xr[b], x1 = xr[b + 1], x2 = xr[b + 2], x3 = xr[b + 3];
-                    acc = __builtin_fma(s_g[lr][b], x0, acc);
-                    acc = __builtin_fma(s_g[lr][b + 1], x1, acc);
-                    acc = __builtin_fma(s_g[lr][b + 2], x2, acc);
-                    acc = __builtin_fma(s_g[lr][b + 3], x3, acc);
-                }
-                for (; b < nb; ++b) acc = __builtin_fma(s_g[lr][b], xr[b], acc);
-                dvals[k] = b0 == 0 ? acc : dvals[k] + acc;
-            }
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave_id());
+    if (i >= m) return;
+    const int lane = lane_id();
+    const int k0 = row_ptr[i], k1 = row_ptr[i + 1];
+    for (int k = k0; k < k1; k += 16) {
+        int c[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u] = col_idx[k + u < k1 ? k + u : k1 - 1];
+        T p[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) p[u] = 0;
+        for (int b0 = 0; b0 < B; b0 += 64) {
+            const bool on = b0 + lane < B;
+            const int b = b0 + (on ? lane : 0);
+            const T gv = on ? GT[(int64_t)i * B + b] : (T)0;
+            T xv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) xv[u] = XT[(int64_t)c[u] * B + b];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) p[u] = __builtin_fma(gv, xv[u], p[u]);
         }
-        __syncthreads();
+        const T s = wave_fold16(p);
+        const int v = (lane >> 2) & 15;
+        if ((lane & 3) == 0 && k + v < k1) dvals[k + v] = s;
     }
 }
 
@@ -128,15 +157,16 @@ template <typename T>
 static spx_status dx_t(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n,
                        int32_t B, const void* G, void* dX, Arena& ws, hipStream_t s) {
     T* GT = ws.take<T>((size_t)m * B);
-    if (!GT) return fail(SPX_ERR_WORKSPACE, "dx: workspace too small");
+    T* dXT = ws.take<T>((size_t)n * B);
+    if (!GT || !dXT) return fail(SPX_ERR_WORKSPACE, "dx: workspace too small");
     SPX_TRY(transpose<T>(B, m, (const T*)G, GT, s));
     for (int32_t b0 = 0; b0 < B; b0 += 64) {
         const int nb = std::min(64, B - b0);
-        k_spmm_csc<T><<<(unsigned)ceil_div(n, kWavesPerBlock), kBlock, 0, s>>>(n, B, b0, nb, col_ptr, row_idx,
-                                                                              (const T*)vals_csc, GT, (T*)dX);
+        k_seg_gather<T><<<(unsigned)ceil_div(n, kWavesPerBlock), kBlock, 0, s>>>(n, B, b0, nb, col_ptr, row_idx,
+                                                                                (const T*)vals_csc, GT, dXT);
         SPX_HIP(hipGetLastError());
     }
-    return SPX_OK;
+    return transpose<T>(n, B, dXT, (T*)dX, s);
 }
 
 spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n,
@@ -149,6 +179,31 @@ spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void*
 }
 
 template <typename T>
+static spx_status spmv_batch_t(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
+                               int32_t n, int32_t B, const void* X, void* Y, Arena& ws, hipStream_t s) {
+    T* XT = ws.take<T>((size_t)n * B);
+    T* YT = ws.take<T>((size_t)m * B);
+    if (!XT || !YT) return fail(SPX_ERR_WORKSPACE, "spmv batch: workspace too small");
+    SPX_TRY(transpose<T>(B, n, (const T*)X, XT, s));
+    for (int32_t b0 = 0; b0 < B; b0 += 64) {
+        const int nb = std::min(64, B - b0);
+        k_seg_gather<T><<<(unsigned)ceil_div(m, kWavesPerBlock), kBlock, 0, s>>>(m, B, b0, nb, row_ptr, col_idx,
+                                                                                (const T*)vals, XT, YT);
+        SPX_HIP(hipGetLastError());
+    }
+    return transpose<T>(m, B, YT, (T*)Y, s);
+}
+
+spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
+                             int32_t n, int dtype, int32_t B, const void* X, void* Y, Arena& ws, hipStream_t s) {
+    if (B == 0 || m == 0) return SPX_OK;
+    if (n == 0) return fill_bytes(Y, 0, (size_t)B * m * (dtype == SPX_F64 ? 8 : 4), s);
+    if (dtype == SPX_F32) return spmv_batch_t<float>(row_ptr, col_idx, vals, m, n, B, X, Y, ws, s);
+    if (dtype == SPX_F64) return spmv_batch_t<double>(row_ptr, col_idx, vals, m, n, B, X, Y, ws, s);
+    return fail(SPX_ERR_DTYPE, "spmv batch: F32 or F64 only");
+}
+
+template <typename T>
 static spx_status dvals_t(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n, int32_t nnz,
                           int32_t B, const void* G, const void* X, void* dvals, Arena& ws, hipStream_t s) {
     T* GT = ws.take<T>((size_t)m * B);
@@ -156,19 +211,9 @@ static spx_status dvals_t(const int32_t* row_ptr, const int32_t* col_idx, int32_
     if (!GT || !XT) return fail(SPX_ERR_WORKSPACE, "dvals: workspace too small");
     SPX_TRY(transpose<T>(B, m, (const T*)G, GT, s));
     SPX_TRY(transpose<T>(B, n, (const T*)X, XT, s));
-    // at least 4 lanes per row keeps the per-row LDS copies of G^T within 32 KiB
-    const double avg = (double)nnz / m;
-    int L = 4;
-    while (L < 64 && L < avg) L <<= 1;
-    const int64_t blocks = ceil_div(m, kBlock / L);
-    switch (L) {
-#define SPX_L(LL)                                                                                               \
-    case LL:                                                                                                    \
-        k_sddmm<T, LL><<<(unsigned)blocks, kBlock, 0, s>>>(m, B, row_ptr, col_idx, GT, XT, (T*)dvals);          \
-        break;
-        SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
-#undef SPX_L
-    }
+    (void)nnz;
+    k_sddmm<T><<<(unsigned)ceil_div(m, kWavesPerBlock), kBlock, 0, s>>>(m, B, row_ptr, col_idx, GT, XT,
+                                                                        (T*)dvals);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }

@@ -172,6 +172,8 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
 
 // backward (grad.hip): workspace grad_ws_bytes(m, n, B, dtype)
 size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype);
+spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
+                             int32_t n, int dtype, int32_t B, const void* X, void* Y, Arena& ws, hipStream_t s);
 spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m,
                      int32_t n, int dtype, int32_t B, const void* G, void* dX, Arena& ws, hipStream_t s);
 spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n,

@@ -27,7 +27,8 @@ def _relu_batch(n, B, seed, dtype):
     return np.abs(X).astype(dtype)
 
 
-def test_fd_exact_fp64_and_oracle():
+@pytest.mark.parametrize("mode", ["fused", "sparse"])
+def test_fd_exact_fp64_and_oracle(mode):
     torch = _torch()
     from paper_2006_16767_amd.autograd import sparse_linear
     A = synth.bernoulli(64, 32, 0.05, 12, std=1.0, dtype=np.float64)
@@ -35,7 +36,7 @@ def test_fd_exact_fp64_and_oracle():
     vals = M.vals.requires_grad_(True)
     X = torch.as_tensor(_relu_batch(32, 3, 1, np.float64), device="cuda").requires_grad_(True)
     G = torch.as_tensor(np.random.default_rng(2).standard_normal((3, 64)), device="cuda")
-    Y = sparse_linear(M, X, vals)
+    Y = sparse_linear(M, X, vals, mode)
     (Y * G).sum().backward()
     dvals = vals.grad.detach().cpu().numpy()
     dX = X.grad.detach().cpu().numpy()
@@ -47,7 +48,7 @@ def test_fd_exact_fp64_and_oracle():
     h = 2.0 ** -10
     with torch.no_grad():
         def L():
-            return float((sparse_linear(M, X.detach(), vals) * G).sum())
+            return float((sparse_linear(M, X.detach(), vals, mode) * G).sum())
         for k in range(A.nnz):
             vals[k] += h
             lp = L()
@@ -61,8 +62,8 @@ def test_fd_exact_fp64_and_oracle():
             for j in range(32):
                 Xp = Xd.clone(); Xp[b, j] += h
                 Xm = Xd.clone(); Xm[b, j] -= h
-                fd = (float((sparse_linear(M, Xp, vals) * G).sum()) -
-                      float((sparse_linear(M, Xm, vals) * G).sum())) / (2 * h)
+                fd = (float((sparse_linear(M, Xp, vals, mode) * G).sum()) -
+                      float((sparse_linear(M, Xm, vals, mode) * G).sum())) / (2 * h)
                 assert abs(fd - dX[b, j]) <= 1e-9 * max(1.0, abs(dX[b, j]))
 
 
@@ -77,16 +78,17 @@ def test_gradcheck_small():
                                     eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
-def test_values_refresh_after_inplace_update():
+@pytest.mark.parametrize("mode", ["fused", "sparse"])
+def test_values_refresh_after_inplace_update(mode):
     torch = _torch()
     from paper_2006_16767_amd.autograd import sparse_linear
     A = synth.bernoulli(200, 100, 0.1, 5, dtype=np.float32)
     M = spx.Matrix.from_host(A)
     X = torch.as_tensor(_relu_batch(100, 4, 6, np.float32), device="cuda")
     with torch.no_grad():
-        Y1 = sparse_linear(M, X).clone()
+        Y1 = sparse_linear(M, X, mode=mode).clone()
         M.vals.mul_(2.0)  # an optimizer-style in-place update
-        Y2 = sparse_linear(M, X)
+        Y2 = sparse_linear(M, X, mode=mode)
     torch.cuda.synchronize()
     # the forward may pick column-major plans, which read the CSC copy
     assert torch.allclose(Y2, 2.0 * Y1, rtol=1e-6, atol=1e-6)
@@ -110,11 +112,15 @@ def test_pruned_fc_layer_full_size():
     G = torch.as_tensor(Gh, device="cuda")
     Y = sparse_linear(M, X, vals)
     (Y * G).sum().backward()
+    with torch.no_grad():
+        Ys = sparse_linear(M, X.detach(), mode="sparse")
     torch.cuda.synchronize()
     Yh = Y.detach().cpu().numpy()
+    Ysh = Ys.cpu().numpy()
     for b in range(0, 64, 9):
         ref, S = oracle.spmv(A, Xh[b])
-        assert_close(Yh[b], ref, S, "f32", f"fc forward b={b}")
+        assert_close(Yh[b], ref, S, "f32", f"fc forward (fused) b={b}")
+        assert_close(Ysh[b], ref, S, "f32", f"fc forward (sparse) b={b}")
     dX_ref, sdX, dv_ref = oracle.grad(A, Gh, Xh)
     dX = X.grad.cpu().numpy()
     for b in range(64):
@@ -122,3 +128,21 @@ def test_pruned_fc_layer_full_size():
     rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr))
     sdv = (np.abs(Gh[:, rows].astype(np.float64)) * np.abs(Xh[:, A.col_idx].astype(np.float64))).sum(0)
     assert_close(vals.grad.cpu().numpy(), dv_ref, sdv, "f32", "fc dvals")
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+def test_fused_batch_spmv_matches_oracle(kind):
+    """spmv_csr_batch on ragged shapes: empty rows, rows shorter and longer
+    than the 8-entry unroll, B = 1, below, at and above 64 (chunks of 64)."""
+    torch = _torch()
+    npdt = np.float32 if kind == "f32" else np.float64
+    for ci, (m, n, dens) in enumerate([(37, 53, 0.1), (3001, 2503, 0.004), (700, 900, 0.05), (2, 1, 1.0)]):
+        A = synth.random_csr(m, n, dens, 500 + ci, empty_rows=0.2)
+        A = A.with_vals(np.asarray(A.vals).astype(npdt))
+        M = spx.Matrix.from_host(A)
+        for B in (1, 3, 64, 70, 130):
+            X = _relu_batch(n, B, 10 * ci + B, npdt)
+            Y = M.spmv_batch(torch.as_tensor(X, device="cuda")).cpu().numpy()
+            for b in sorted({0, B // 2, B - 1}):
+                ref, S = oracle.spmv(A, X[b].astype(np.float64))
+                assert_close(Y[b], ref, S, kind, f"{m}x{n} B={B} b={b}")

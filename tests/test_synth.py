@@ -56,6 +56,10 @@ def test_powerlaw_and_bernoulli():
     A = synth.powerlaw_rows(20000, 5000, 40.0, 3)
     _valid_csr(A)
     assert abs(np.diff(A.row_ptr).mean() - 40.0) <= 0.5
+    C = synth.powerlaw_cols(5000, 20000, 40.0, 3)
+    _valid_csr(C)
+    # the column lengths are the row lengths of the row generator, transposed
+    assert np.array_equal(np.sort(np.bincount(C.col_idx, minlength=C.n)), np.sort(np.diff(A.row_ptr)))
     W = synth.bernoulli(512, 256, 0.05, 4)
     _valid_csr(W)
     assert abs(W.nnz / (512 * 256) - 0.05) < 0.005
