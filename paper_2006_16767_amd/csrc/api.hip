@@ -175,7 +175,7 @@ struct spx_matrix {
     void* sp_val = nullptr;
     int32_t* scratch_i32 = nullptr;  // compaction workspace
     int64_t* dev_scalars = nullptr;  // 4 x int64 (feature reductions, counts)
-    uint32_t* bucket_cursor = nullptr;
+    uint32_t* scan_counter = nullptr;  // arrival counter of the one-launch length scan
     // merge-path partitions of the balanced row-major kernels, per tile size,
     // for A (index 0) and for A^T (index 1)
     int32_t* part[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -398,7 +398,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     if (H->cap_stream) hipStreamDestroy(H->cap_stream);
     void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->gorder, H->grank, H->gcol, H->gsrc,
                     H->gvals, H->bits, H->xd, H->sp_idx,
-                    H->sp_val, H->scratch_i32, H->dev_scalars, H->bucket_cursor, H->ws,
+                    H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws};
     for (void* p : ptrs)
         if (p) hipFree(p);
@@ -581,6 +581,10 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
             return fail(hbad & 1 ? SPX_ERR_SHAPE : SPX_ERR_INDEX,
                         hbad & 1 ? "row_ptr is not a valid CSR row pointer" : "a column index is out of range");
         }
+    }
+    if (hipMalloc((void**)&H->scan_counter, 256) != hipSuccess || hipMemset(H->scan_counter, 0, 256) != hipSuccess) {
+        spx_matrix_destroy(H);
+        return fail(SPX_ERR_ALLOC, "scan counter allocation failed");
     }
     st = build_csc(H, s);
     if (st == SPX_OK) st = build_gcsr(H, flags, s);
@@ -872,7 +876,7 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
     }
     SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, nnz_x, dt, p)));
     Arena ws(H->ws, H->ws_bytes);
-    CscArgs a{A.m, A.n, A.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc, A.row_ptr, H->bucket_cursor, nnz_s_hint};
+    CscArgs a{A.m, A.n, A.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc, A.row_ptr, H->scan_counter, nnz_s_hint};
     record(H, H->ev_kern, true, s);
     SPX_TRY(launch_spmspv_csc(a, nnz_x, idx, val, y, p, ws, s));
     record(H, H->ev_kern, false, s);

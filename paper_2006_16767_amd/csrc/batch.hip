@@ -281,13 +281,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
             if (csc) {
                 const int32_t* excl = a.excl_all + p.base + b;
                 if (p.dist == SPX_DIST_BALANCED) {
-                    csc_merge_tile<DT>(j, p.nnz_x, p.nnz_s, idx, xv, a.col_ptr, a.row_idx, vals_csc, excl,
+                    csc_merge_tile<DT>(j, p.nnz_x, p.nnz_s, idx, xv, a.col_ptr, a.row_idx, vals_csc, Excl{excl, nullptr},
                                        EmitAtomic<DT>{Yb}, L.csc);
                 } else {
                     const int e = j * kCscDirectEntries + threadIdx.x / kCscDirectLanes;
                     if (e < p.nnz_x)
                         csc_direct_entry<DT, kCscDirectLanes>(e, threadIdx.x % kCscDirectLanes, idx, xv, a.col_ptr,
-                                                              a.row_idx, vals_csc, nullptr, EmitAtomic<DT>{Yb});
+                                                              a.row_idx, vals_csc, Excl{nullptr, nullptr},
+                                                              EmitAtomic<DT>{Yb});
                 }
             } else {
                 const bool valid = p.pattern == SPX_PAT_CSR_SPMSPV || DT == SPX_BOOL;

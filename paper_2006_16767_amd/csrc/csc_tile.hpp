@@ -10,11 +10,13 @@
 #pragma once
 
 #include "common.hpp"
+#include "internal.hpp"
 
 namespace spx {
 
 constexpr int kCscIpt = 8;
 constexpr int kCscTile = kBlock * kCscIpt;
+
 
 template <int DT>
 struct CscTileLds {
@@ -34,7 +36,7 @@ __device__ __forceinline__ CscTile csc_tile_setup(int64_t tile, int32_t nnz_x, i
                                                   const int32_t* __restrict__ x_idx,
                                                   const typename SR<DT>::X* __restrict__ x_val,
                                                   const int32_t* __restrict__ col_ptr,
-                                                  const int32_t* __restrict__ excl, CscTileLds<DT>& L) {
+                                                  const Excl excl, CscTileLds<DT>& L) {
     using S = SR<DT>;
     const int64_t total = (int64_t)nnz_x + nnz_s;
     const int64_t d0 = tile * kCscTile;
@@ -97,8 +99,7 @@ __device__ __forceinline__ void csc_merge_tile(int64_t tile, int32_t nnz_x, int6
                                                const int32_t* __restrict__ col_ptr,
                                                const int32_t* __restrict__ row_idx,
                                                const typename SR<DT>::V* __restrict__ vals,
-                                               const int32_t* __restrict__ excl, const Emit& emit,
-                                               CscTileLds<DT>& L) {
+                                               const Excl excl, const Emit& emit, CscTileLds<DT>& L) {
     using S = SR<DT>;
     const CscTile t = csc_tile_setup<DT>(tile, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
     for (int p = t.p0 + threadIdx.x; p < t.p1; p += kBlock) {
@@ -117,7 +118,7 @@ __device__ __forceinline__ void csc_direct_entry(int e, int g, const int32_t* __
                                                  const int32_t* __restrict__ col_ptr,
                                                  const int32_t* __restrict__ row_idx,
                                                  const typename SR<DT>::V* __restrict__ vals,
-                                                 const int32_t* __restrict__ excl, const Emit& emit) {
+                                                 const Excl excl, const Emit& emit) {
     using S = SR<DT>;
     const int j = x_idx[e];
     const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;

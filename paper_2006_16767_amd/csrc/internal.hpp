@@ -90,13 +90,26 @@ spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int t
                            hipStream_t s);
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan);
 
+// Read-only view of excl[0..nnz_x]: either one array (off null), or the
+// exclusive prefix within each run of 256 entries (local) plus the
+// exclusive prefix of the run totals (off), as the one-launch length scan
+// leaves it.
+struct Excl {
+    const int32_t* local;
+    const int32_t* off;
+    __device__ __forceinline__ int32_t operator[](int64_t e) const {
+        return off ? local[e] + off[e >> 8] : local[e];
+    }
+    __host__ __device__ explicit operator bool() const { return local != nullptr; }
+};
+
 struct CscArgs {
     int32_t m, n, nnz, dtype;
     const int32_t* col_ptr;
     const int32_t* row_idx;
     const void* vals;
     const int32_t* row_ptr;  // CSR row pointer of the same matrix (bucket layout); may be null
-    uint32_t* bucket_cursor; // handle-owned, zero between calls; may be null
+    uint32_t* scan_counter;  // handle-owned, zero between calls (the scan resets it); may be null
     int64_t nnz_s_hint;      // exact nnz_s if the host knows it, else -1
 };
 spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx,
@@ -106,7 +119,7 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
                      const spx_plan* plan);
 // bucket write-back (spmspv_bucket.hip); excl = prefix of selected column lengths
 spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                             void* y, const spx_plan* plan, const int32_t* excl, Arena& ws,
+                             void* y, const spx_plan* plan, const Excl excl, Arena& ws,
                              hipStream_t s);
 size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
 

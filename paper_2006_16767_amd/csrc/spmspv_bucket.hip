@@ -74,7 +74,7 @@ template <int DT>
 __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     int32_t nnz_x, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
     const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
-    const typename SR<DT>::V* __restrict__ vals, const int32_t* __restrict__ excl, int logR, int NB,
+    const typename SR<DT>::V* __restrict__ vals, const Excl excl, int logR, int NB,
     BucketOut<DT> out) {
     using S = SR<DT>;
     __shared__ CscTileLds<DT> L;
@@ -142,7 +142,7 @@ template <int DT, int L>
 __global__ __launch_bounds__(kBlock) void k_bucket_scatter_direct(
     int32_t nnz_x, int32_t E, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
     const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
-    const typename SR<DT>::V* __restrict__ vals, const int32_t* __restrict__ excl, int logR, int NB,
+    const typename SR<DT>::V* __restrict__ vals, const Excl excl, int logR, int NB,
     BucketOut<DT> out) {
     using S = SR<DT>;
     __shared__ int32_t s_cnt[kMaxBuckets];
@@ -198,7 +198,7 @@ constexpr int kAccWin = 4096;
 template <int DT>
 __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, int logR, int32_t nch_fixed,
                                                                    int32_t nnz_x,
-                                                                   const int32_t* __restrict__ excl,
+                                                                   const Excl excl,
                                                                    const uint16_t* __restrict__ prow,
                                                                    const typename SR<DT>::Acc* __restrict__ pval,
                                                                    const int32_t* __restrict__ moff,
@@ -340,7 +340,7 @@ size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx
 
 template <int DT>
 static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val_v,
-                                  void* y_v, const spx_plan* plan, const int32_t* excl, Arena& ws, hipStream_t s) {
+                                  void* y_v, const spx_plan* plan, const Excl excl, Arena& ws, hipStream_t s) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
     BucketGeom g;
@@ -393,7 +393,7 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
 }
 
 spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
-                             const spx_plan* plan, const int32_t* excl, Arena& ws, hipStream_t s) {
+                             const spx_plan* plan, const Excl excl, Arena& ws, hipStream_t s) {
     switch (A.dtype) {
         case SPX_F32:
             return launch_bucket_t<SPX_F32>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_direct_atomic(int32_t nnz_x, con
                                                               typename SR<DT>::Y* __restrict__ y) {
     const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
     if (e >= nnz_x) return;
-    csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, nullptr,
+    csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, Excl{nullptr, nullptr},
                             EmitAtomic<DT>{y});
 }
 
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_direct_pairs(int32_t nnz_x, cons
                                                              const int32_t* __restrict__ col_ptr,
                                                              const int32_t* __restrict__ row_idx,
                                                              const typename SR<DT>::V* __restrict__ vals,
-                                                             const int32_t* __restrict__ excl,
+                                                             const Excl excl,
                                                              EmitPairs<DT> emit) {
     const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
     if (e >= nnz_x) return;
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_csc_direct_lds(int32_t m, int32_t nn
     const int groups = kBlock / L;
     for (int64_t e = (int64_t)blockIdx.x * groups + threadIdx.x / L; e < nnz_x;
          e += (int64_t)gridDim.x * groups)
-        csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals, nullptr,
-                                EmitLds<DT>{sy});
+        csc_direct_entry<DT, L>((int)e, threadIdx.x % L, x_idx, x_val, col_ptr, row_idx, vals,
+                                Excl{nullptr, nullptr}, EmitLds<DT>{sy});
     __syncthreads();
     for (int r = threadIdx.x; r < m; r += kBlock) {
         const typename S::Acc v = sy[r];
@@ -160,13 +160,80 @@ __global__ __launch_bounds__(kBlock) void k_csc_prologue(int32_t nnz_x, const in
     if (blockIdx.x == 1 && (int)threadIdx.x < ytail) ((uint8_t*)(y + ywords))[threadIdx.x] = 0;
 }
 
+// The prefix of the selected column lengths over many workgroups, for x up
+// to kLsMaxTiles runs of 256 entries, with the zero fill of y: workgroups
+// [0, F) zero y; each of the T others writes the exclusive prefix of the
+// lengths of its 256 entries (one per thread) to local and the run's total
+// to sums. The last of the T to arrive (atomicInc wraps the counter back to
+// 0, so it is zero again for the next call) writes the exclusive prefix of
+// the T totals to off; readers add off[e >> 8] to local[e] (Excl). No
+// workgroup waits for another: the thread that writes a run total fences it
+// before its workgroup arrives, and the last one fences before it reads the
+// totals.
+constexpr int kLsMaxTiles = 4096;  // nnz_x + 1 <= 2^20
+constexpr int kLsPer = kLsMaxTiles / kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_csc_lengths_scan(int32_t nnz_x, const int32_t* __restrict__ x_idx,
+                                                             const int32_t* __restrict__ col_ptr,
+                                                             int32_t* __restrict__ local, int32_t* __restrict__ sums,
+                                                             int32_t* __restrict__ off, uint32_t* __restrict__ counter,
+                                                             uint32_t* __restrict__ y, int64_t ywords, int ytail,
+                                                             int F) {
+    if ((int)blockIdx.x < F) {
+        const int64_t stride = (int64_t)F * kBlock;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = 0u;
+        if (blockIdx.x == 0 && (int)threadIdx.x < ytail) ((uint8_t*)(y + ywords))[threadIdx.x] = 0;
+        return;
+    }
+    __shared__ int32_t tmp[kWavesPerBlock];
+    __shared__ int last;
+    const int t = blockIdx.x - F;
+    const int T = gridDim.x - F;
+    const int e = t * kBlock + threadIdx.x;
+    int len = 0;
+    if (e < nnz_x) {
+        const int j = x_idx[e];
+        len = col_ptr[j + 1] - col_ptr[j];
+    }
+    int total;
+    const int incl = block_incl_scan<int32_t>(len, tmp, &total);
+    if (e <= nnz_x) local[e] = incl - len;
+    // only the run totals cross workgroups inside this kernel (local is read
+    // by the next launch), so thread 0, which writes its total, fences it
+    if (threadIdx.x == 0) {
+        sums[t] = total;
+        __threadfence();
+        const bool l = atomicInc(counter, (unsigned)(T - 1)) == (unsigned)(T - 1);
+        if (l) __threadfence();
+        last = l;
+    }
+    __syncthreads();
+    if (!last) return;
+    // exclusive prefix of sums[0..T): kLsPer consecutive totals per thread
+    const int i0 = threadIdx.x * kLsPer;
+    int v[kLsPer];
+    int run = 0;
+#pragma unroll
+    for (int u = 0; u < kLsPer; ++u) {
+        v[u] = i0 + u < T ? sums[i0 + u] : 0;
+        run += v[u];
+    }
+    int all;
+    run = block_incl_scan<int32_t>(run, tmp, &all) - run;
+#pragma unroll
+    for (int u = 0; u < kLsPer; ++u) {
+        if (i0 + u < T) off[i0 + u] = run;
+        run += v[u];
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_csc_merge_atomic(int32_t nnz_x, const int32_t* __restrict__ x_idx,
                                                              const typename SR<DT>::X* __restrict__ x_val,
                                                              const int32_t* __restrict__ col_ptr,
                                                              const int32_t* __restrict__ row_idx,
                                                              const typename SR<DT>::V* __restrict__ vals,
-                                                             const int32_t* __restrict__ excl,
+                                                             const Excl excl,
                                                              typename SR<DT>::Y* __restrict__ y) {
     __shared__ CscTileLds<DT> L;
     const int64_t nnz_s = excl[nnz_x];
@@ -181,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_pairs(int32_t nnz_x, const
                                                             const int32_t* __restrict__ col_ptr,
                                                             const int32_t* __restrict__ row_idx,
                                                             const typename SR<DT>::V* __restrict__ vals,
-                                                            const int32_t* __restrict__ excl,
+                                                            const Excl excl,
                                                             EmitPairs<DT> emit) {
     __shared__ CscTileLds<DT> L;
     const int64_t nnz_s = excl[nnz_x];
@@ -197,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz
                                                           const int32_t* __restrict__ col_ptr,
                                                           const int32_t* __restrict__ row_idx,
                                                           const typename SR<DT>::V* __restrict__ vals,
-                                                          const int32_t* __restrict__ excl,
+                                                          const Excl excl,
                                                           typename SR<DT>::Y* __restrict__ y) {
     using S = SR<DT>;
     __shared__ CscTileLds<DT> L;
@@ -331,6 +398,8 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
     if (need_excl) {
         z.take<int32_t>((size_t)nnz_x + 1);
         z.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
+        z.take<int32_t>(kLsMaxTiles);
+        z.take<int32_t>(kLsMaxTiles);
     }
     if (plan->writeback == SPX_WB_BUCKET) {
         const size_t b = csc_bucket_ws(m, nnz, nnz_x, dtype, plan);
@@ -370,11 +439,26 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const bool fill_y = wb != SPX_WB_BUCKET || nnz_x == 0;
     const bool need_excl = nnz_x > 0 && (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET);
     int32_t* excl = nullptr;
+    Excl ex{nullptr, nullptr};
     if (need_excl) {
         excl = ws.take<int32_t>((size_t)nnz_x + 1);
         int32_t* sws = ws.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
         if (!excl || !sws) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
-        if (nnz_x + 1 <= kProMax && ((uintptr_t)y & 3) == 0) {
+        ex.local = excl;
+        const int64_t T = ceil_div((int64_t)nnz_x + 1, kBlock);
+        // the sort write-back reads nnz_s = excl[nnz_x] on the host: plain array
+        if (A.scan_counter && T <= kLsMaxTiles && wb != SPX_WB_SORT && ((uintptr_t)y & 3) == 0) {
+            int32_t* sums = ws.take<int32_t>(kLsMaxTiles);
+            int32_t* off = ws.take<int32_t>(kLsMaxTiles);
+            if (!sums || !off) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
+            const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
+            const int F = fill_y ? (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ywords, kBlock), 2048)) : 0;
+            k_csc_lengths_scan<<<(unsigned)(F + T), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, sums, off,
+                                                                   A.scan_counter, (uint32_t*)y, ywords,
+                                                                   fill_y ? (int)(ybytes & 3) : 0, F);
+            SPX_HIP(hipGetLastError());
+            ex.off = off;
+        } else if (nnz_x + 1 <= kProMax && ((uintptr_t)y & 3) == 0) {
             const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
             const int fill_blocks = fill_y ? (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ywords, kBlock), 4096)) : 0;
             k_csc_prologue<<<1 + fill_blocks, kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, (uint32_t*)y, ywords,
@@ -395,7 +479,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int64_t ub = A.nnz_s_hint >= 0 ? A.nnz_s_hint : (int64_t)A.nnz;
     const int64_t merge_tiles = std::max<int64_t>(1, ceil_div((int64_t)nnz_x + ub, kCscTile));
 
-    if (wb == SPX_WB_BUCKET) return launch_csc_bucket(A, nnz_x, x_idx, x_val_v, y_v, plan, excl, ws, s);
+    if (wb == SPX_WB_BUCKET) return launch_csc_bucket(A, nnz_x, x_idx, x_val_v, y_v, plan, ex, ws, s);
 
     if (wb == SPX_WB_ATOMIC || wb == SPX_WB_LDS_ATOMIC) {
         if (dist == SPX_DIST_DIRECT) {
@@ -432,11 +516,11 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
             if (wb == SPX_WB_ATOMIC) {
                 const int grid = (int)std::min<int64_t>(merge_tiles, 8192);
                 k_csc_merge_atomic<DT><<<grid, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals,
-                                                              excl, y);
+                                                              ex, y);
             } else {
                 const int grid = (int)std::min<int64_t>(merge_tiles, 64);
                 k_csc_merge_lds<DT><<<grid, kBlock, (size_t)A.m * sizeof(Acc), s>>>(
-                    A.m, nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, excl, y);
+                    A.m, nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, ex, y);
             }
         }
         SPX_HIP(hipGetLastError());
@@ -470,7 +554,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
 #define SPX_L(LL)                                                                                         \
     case LL:                                                                                              \
         k_csc_direct_pairs<DT, LL><<<(unsigned)blocks, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr,    \
-                                                                       A.row_idx, vals, excl, emit);      \
+                                                                       A.row_idx, vals, ex, emit);        \
         break;
                 SPX_L(1) SPX_L(2) SPX_L(4) SPX_L(8) SPX_L(16) SPX_L(32) SPX_L(64)
 #undef SPX_L
@@ -479,7 +563,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
             }
         } else {
             const int grid = (int)std::min<int64_t>(ceil_div((int64_t)nnz_x + nnz_s, kCscTile), 8192);
-            k_csc_merge_pairs<DT><<<grid, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, excl,
+            k_csc_merge_pairs<DT><<<grid, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, ex,
                                                          emit);
         }
         SPX_HIP(hipGetLastError());

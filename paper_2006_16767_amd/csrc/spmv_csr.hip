@@ -43,35 +43,30 @@ __global__ __launch_bounds__(kBlock) void k_csr_direct(int32_t m, const int32_t*
     if (row >= m) return;  // whole groups leave together (L divides 64)
     const int k0 = row_ptr[row], k1 = row_ptr[row + 1];
     Acc acc = S::zero();
-    int k = k0 + g;
-    // four independent gathers in flight per lane
-    for (; k + 3 * L < k1; k += 4 * L) {
-        int c[4];
+    // eight loads in flight per lane, predicated on the row's end: a short
+    // row (up to 8 * L entries) costs one round trip
+    for (int k = k0 + g; k < k1; k += 8 * L) {
+        int c[8];
+        bool on[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = col_idx[k + u * L];
+        for (int u = 0; u < 8; ++u) {
+            on[u] = k + u * L < k1;
+            c[u] = on[u] ? col_idx[k + u * L] : 0;
+        }
         if constexpr (VALID) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (test_bit(bits, c[u])) acc = S::fma(S::val(vals, k + u * L), S::xval(x, c[u]), acc);
-        } else {
-            typename S::V a[4];
-            typename S::X b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = S::val(vals, k + u * L);
-                b[u] = S::xval(x, c[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc = S::fma(a[u], b[u], acc);
+            for (int u = 0; u < 8; ++u) on[u] = on[u] && test_bit(bits, c[u]);
         }
-    }
-    for (; k < k1; k += L) {
-        const int c = col_idx[k];
-        if constexpr (VALID) {
-            if (test_bit(bits, c)) acc = S::fma(S::val(vals, k), S::xval(x, c), acc);
-        } else {
-            acc = S::fma(S::val(vals, k), S::xval(x, c), acc);
+        typename S::V a[8];
+        typename S::X b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = on[u] ? S::val(vals, k + u * L) : (typename S::V)0;
+            b[u] = on[u] ? S::xval(x, c[u]) : (typename S::X)0;
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (on[u]) acc = S::fma(a[u], b[u], acc);
     }
     acc = group_reduce<DT, L>(acc);
     if (g == 0) y[row] = S::out(acc);
@@ -218,10 +213,14 @@ bool bitlds_fits(int32_t n, int dtype) {
 }
 
 // --------------------------------------------------------------- launch
+// Lanes per row of the direct distribution: the largest power of two up to
+// half the average row length, at most 32 (measured on MI355X over uniform
+// rows of 7 to 205 entries: 2, 8, 16, 32 and 32 lanes were fastest at
+// averages 7, 16, 32, 64 and 205).
 static int pick_lanes(int32_t m, int32_t nnz) {
     const double avg = m > 0 ? (double)nnz / m : 0.0;
     int L = 1;
-    while (L < 64 && L < avg) L <<= 1;
+    while (L < 32 && 4.0 * L <= avg) L <<= 1;
     return L;
 }
 
