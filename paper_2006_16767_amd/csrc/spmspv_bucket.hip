@@ -57,19 +57,12 @@ struct BucketOut {
 };
 
 // ------------------------------------------------------------------ balanced scatter
-constexpr int kMergeChunks = 1024;  // chunk count of the balanced distribution (at most)
-
-// tiles per chunk, from the actual tile count (known on the device only)
-__host__ __device__ inline int64_t merge_tiles_per_chunk(int64_t tiles) {
-    return tiles > kMergeChunks ? (tiles + kMergeChunks - 1) / kMergeChunks : 1;
-}
-
-// Chunk c = merge tiles [c * S, (c + 1) * S): the workgroup walks its tiles
-// twice, first counting pairs per bucket, then writing each pair at the
-// chunk's start + the bucket's offset within the chunk + a slot taken from
-// an LDS cursor. With S tiles per chunk every (bucket, chunk) group is S
-// times longer than with one tile, so the pair stores and the accumulate
-// pass's loads move whole cache lines.
+// Chunk c = merge tile c. One pass: every thread forms the pairs of its
+// kCscIpt positions in registers, takes each pair's rank within its bucket
+// from the LDS counting atomic, and after the workgroup scan of the counts
+// stores the pair at the chunk's start + the bucket's offset + that rank.
+// The chunk's pairs fill a contiguous range, which the L2 assembles into
+// whole lines.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     int32_t nnz_x, const int32_t* __restrict__ x_idx, const typename SR<DT>::X* __restrict__ x_val,
@@ -77,61 +70,51 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     const typename SR<DT>::V* __restrict__ vals, const Excl excl, int logR, int NB,
     BucketOut<DT> out) {
     using S = SR<DT>;
+    using Acc = typename S::Acc;
     __shared__ CscTileLds<DT> L;
-    __shared__ int32_t s_cnt[kMaxBuckets];
-    __shared__ int32_t s_off[kMaxBuckets];
     __shared__ int32_t s_tmp[kWavesPerBlock];
-    __shared__ int32_t s_p0;
+    extern __shared__ int32_t s_dyn[];  // counts and offsets, NB each
+    int32_t* s_cnt = s_dyn;
+    int32_t* s_off = s_dyn + NB;
     const int64_t nnz_s = excl[nnz_x];
     const int64_t tiles = ceil_div((int64_t)nnz_x + nnz_s, kCscTile);
-    const int64_t S_tiles = merge_tiles_per_chunk(tiles);
     const int64_t chunk = blockIdx.x;
-    const int64_t t_begin = chunk * S_tiles;
-    if (t_begin >= tiles) return;  // the accumulate pass reads only the chunks that exist
-    const int64_t t_end = t_begin + S_tiles < tiles ? t_begin + S_tiles : tiles;
+    if (chunk >= tiles) return;  // the accumulate pass reads only the chunks that exist
     const int rmask = (1 << logR) - 1;
     for (int b = threadIdx.x; b < NB; b += kBlock) s_cnt[b] = 0;
-    // pass 1: counts
-    for (int64_t tt = t_begin; tt < t_end; ++tt) {
-        const CscTile t = csc_tile_setup<DT>(tt, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
-        if (tt == t_begin && threadIdx.x == 0) s_p0 = t.p0;
+    const CscTile t = csc_tile_setup<DT>(chunk, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
+    int r[kCscIpt], slot[kCscIpt];
+    Acc v[kCscIpt];
 #pragma unroll
-        for (int i = 0; i < kCscIpt; ++i) {
-            const int p = t.p0 + threadIdx.x + i * kBlock;
-            if (p < t.p1) {
-                const int u = csc_tile_locate<DT>(p, t, L);
-                atomicAdd(&s_cnt[row_idx[L.cs[u] + (p - L.excl[u])] >> logR], 1);
-            }
+    for (int i = 0; i < kCscIpt; ++i) {
+        const int p = t.p0 + threadIdx.x + i * kBlock;
+        r[i] = -1;
+        if (p < t.p1) {
+            const int u = csc_tile_locate<DT>(p, t, L);
+            const int k = L.cs[u] + (p - L.excl[u]);
+            r[i] = row_idx[k];
+            if constexpr (S::kVals) v[i] = S::mul(S::val(vals, k), L.v[u]);
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < kCscIpt; ++i)
+        if (r[i] >= 0) slot[i] = atomicAdd(&s_cnt[r[i] >> logR], 1);
+    __syncthreads();
     bucket_scan(s_cnt, s_off, NB, s_tmp);
     __syncthreads();
-    const int P0 = s_p0;
+    const int P0 = t.p0;
     for (int b = threadIdx.x; b < NB; b += kBlock) {
         const int64_t mi = (int64_t)b * out.stride + chunk;
         out.moff[mi] = P0 + s_off[b];
         out.mcnt[mi] = s_cnt[b];
-        s_cnt[b] = 0;  // becomes the write cursor
     }
-    __syncthreads();
-    // pass 2: pairs
-    for (int64_t tt = t_begin; tt < t_end; ++tt) {
-        const CscTile t = csc_tile_setup<DT>(tt, nnz_x, nnz_s, x_idx, x_val, col_ptr, excl, L);
 #pragma unroll
-        for (int i = 0; i < kCscIpt; ++i) {
-            const int p = t.p0 + threadIdx.x + i * kBlock;
-            if (p < t.p1) {
-                const int u = csc_tile_locate<DT>(p, t, L);
-                const int k = L.cs[u] + (p - L.excl[u]);
-                const int r = row_idx[k];
-                const int b = r >> logR;
-                const int64_t pos = (int64_t)P0 + s_off[b] + atomicAdd(&s_cnt[b], 1);
-                out.prow[pos] = (uint16_t)(r & rmask);
-                if constexpr (S::kVals) out.pval[pos] = S::mul(S::val(vals, k), L.v[u]);
-            }
+    for (int i = 0; i < kCscIpt; ++i) {
+        if (r[i] >= 0) {
+            const int64_t pos = (int64_t)P0 + s_off[r[i] >> logR] + slot[i];
+            out.prow[pos] = (uint16_t)(r[i] & rmask);
+            if constexpr (S::kVals) out.pval[pos] = v[i];
         }
-        __syncthreads();
     }
 }
 
@@ -216,10 +199,7 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
     const int b = blockIdx.x;
     for (int r = threadIdx.x; r < R; r += kAccThreads) acc[r] = S::zero();
     int64_t nch = nch_fixed;
-    if (nch < 0) {
-        const int64_t tiles = ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);
-        nch = ceil_div(tiles, merge_tiles_per_chunk(tiles));
-    }
+    if (nch < 0) nch = ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);  // one chunk per merge tile
     const int32_t* mo = moff + (int64_t)b * stride;
     const int32_t* mc = mcnt + (int64_t)b * stride;
     constexpr int kPer = kAccWin / kAccThreads;
@@ -322,7 +302,7 @@ static bool bucket_geometry(int32_t m, int dtype, int bucket_rows, BucketGeom* g
 
 static int64_t bucket_chunks(int32_t nnz_x, int64_t nnz_s_ub, const spx_plan* plan) {
     if (plan->distribution == SPX_DIST_BALANCED)
-        return std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)nnz_x + nnz_s_ub, kCscTile), kMergeChunks));
+        return std::max<int64_t>(1, ceil_div((int64_t)nnz_x + nnz_s_ub, kCscTile));
     return std::max<int64_t>(1, std::min<int64_t>(nnz_x, kDirectChunks));
 }
 
@@ -361,8 +341,8 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
         return fail(SPX_ERR_WORKSPACE, "bucket write-back: workspace too small");
     int32_t nch_fixed = -1;
     if (plan->distribution == SPX_DIST_BALANCED) {
-        k_bucket_scatter_merge<DT><<<(unsigned)ch, kBlock, 0, s>>>(nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals,
-                                                                   excl, g.logR, g.NB, out);
+        k_bucket_scatter_merge<DT><<<(unsigned)ch, kBlock, (size_t)2 * g.NB * sizeof(int32_t), s>>>(
+            nnz_x, x_idx, x_val, A.col_ptr, A.row_idx, vals, excl, g.logR, g.NB, out);
     } else {
         const int32_t E = (int32_t)ceil_div(nnz_x, ch);
         nch_fixed = (int32_t)ceil_div(nnz_x, E);

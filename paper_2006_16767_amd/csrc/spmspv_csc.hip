@@ -164,14 +164,37 @@ __global__ __launch_bounds__(kBlock) void k_csc_prologue(int32_t nnz_x, const in
 // to kLsMaxTiles runs of 256 entries, with the zero fill of y: workgroups
 // [0, F) zero y; each of the T others writes the exclusive prefix of the
 // lengths of its 256 entries (one per thread) to local and the run's total
-// to sums. The last of the T to arrive (atomicInc wraps the counter back to
-// 0, so it is zero again for the next call) writes the exclusive prefix of
-// the T totals to off; readers add off[e >> 8] to local[e] (Excl). No
-// workgroup waits for another: the thread that writes a run total fences it
-// before its workgroup arrives, and the last one fences before it reads the
-// totals.
+// to sums. Readers add off[e >> 8], the exclusive prefix of the totals, to
+// local[e] (Excl). off comes from a second one-workgroup launch, or, for
+// up to kLsFenceTiles runs and a counter, from the last of the T workgroups
+// to arrive (atomicInc wraps the counter back to 0, so it is zero again for
+// the next call). No workgroup waits for another: the thread that writes a
+// run total fences it before its workgroup arrives, and the last one fences
+// before it reads the totals. Each fence writes back the XCD's L2, so the
+// one-launch form is kept for few runs.
 constexpr int kLsMaxTiles = 4096;  // nnz_x + 1 <= 2^20
+constexpr int kLsFenceTiles = 32;
 constexpr int kLsPer = kLsMaxTiles / kBlock;
+
+// off[0..T) = exclusive prefix of sums[0..T), by one 256-thread workgroup
+__device__ __forceinline__ void scan_run_totals(const int32_t* __restrict__ sums, int T, int32_t* __restrict__ off,
+                                                int32_t* tmp) {
+    const int i0 = threadIdx.x * kLsPer;
+    int v[kLsPer];
+    int run = 0;
+#pragma unroll
+    for (int u = 0; u < kLsPer; ++u) {
+        v[u] = i0 + u < T ? sums[i0 + u] : 0;
+        run += v[u];
+    }
+    int all;
+    run = block_incl_scan<int32_t>(run, tmp, &all) - run;
+#pragma unroll
+    for (int u = 0; u < kLsPer; ++u) {
+        if (i0 + u < T) off[i0 + u] = run;
+        run += v[u];
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_csc_lengths_scan(int32_t nnz_x, const int32_t* __restrict__ x_idx,
                                                              const int32_t* __restrict__ col_ptr,
@@ -198,6 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_csc_lengths_scan(int32_t nnz_x, cons
     int total;
     const int incl = block_incl_scan<int32_t>(len, tmp, &total);
     if (e <= nnz_x) local[e] = incl - len;
+    if (!counter) {
+        if (threadIdx.x == 0) sums[t] = total;
+        return;
+    }
     // only the run totals cross workgroups inside this kernel (local is read
     // by the next launch), so thread 0, which writes its total, fences it
     if (threadIdx.x == 0) {
@@ -209,22 +236,13 @@ __global__ __launch_bounds__(kBlock) void k_csc_lengths_scan(int32_t nnz_x, cons
     }
     __syncthreads();
     if (!last) return;
-    // exclusive prefix of sums[0..T): kLsPer consecutive totals per thread
-    const int i0 = threadIdx.x * kLsPer;
-    int v[kLsPer];
-    int run = 0;
-#pragma unroll
-    for (int u = 0; u < kLsPer; ++u) {
-        v[u] = i0 + u < T ? sums[i0 + u] : 0;
-        run += v[u];
-    }
-    int all;
-    run = block_incl_scan<int32_t>(run, tmp, &all) - run;
-#pragma unroll
-    for (int u = 0; u < kLsPer; ++u) {
-        if (i0 + u < T) off[i0 + u] = run;
-        run += v[u];
-    }
+    scan_run_totals(sums, T, off, tmp);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_run_totals(const int32_t* __restrict__ sums, int T,
+                                                            int32_t* __restrict__ off) {
+    __shared__ int32_t tmp[kWavesPerBlock];
+    scan_run_totals(sums, T, off, tmp);
 }
 
 template <int DT>
@@ -447,16 +465,21 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
         ex.local = excl;
         const int64_t T = ceil_div((int64_t)nnz_x + 1, kBlock);
         // the sort write-back reads nnz_s = excl[nnz_x] on the host: plain array
-        if (A.scan_counter && T <= kLsMaxTiles && wb != SPX_WB_SORT && ((uintptr_t)y & 3) == 0) {
+        if (T <= kLsMaxTiles && wb != SPX_WB_SORT && ((uintptr_t)y & 3) == 0) {
             int32_t* sums = ws.take<int32_t>(kLsMaxTiles);
             int32_t* off = ws.take<int32_t>(kLsMaxTiles);
             if (!sums || !off) return fail(SPX_ERR_WORKSPACE, "spmspv_csc: workspace too small");
             const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
             const int F = fill_y ? (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ywords, kBlock), 2048)) : 0;
+            uint32_t* counter = T <= kLsFenceTiles ? A.scan_counter : nullptr;
             k_csc_lengths_scan<<<(unsigned)(F + T), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, sums, off,
-                                                                   A.scan_counter, (uint32_t*)y, ywords,
+                                                                   counter, (uint32_t*)y, ywords,
                                                                    fill_y ? (int)(ybytes & 3) : 0, F);
             SPX_HIP(hipGetLastError());
+            if (!counter) {
+                k_scan_run_totals<<<1, kBlock, 0, s>>>(sums, (int)T, off);
+                SPX_HIP(hipGetLastError());
+            }
             ex.off = off;
         } else if (nnz_x + 1 <= kProMax && ((uintptr_t)y & 3) == 0) {
             const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
