@@ -189,6 +189,10 @@ struct spx_matrix {
     int32_t bcap_B = 0;
     int64_t bcap_nnz = 0;
     int32_t* berr = nullptr;
+    int32_t* units = nullptr;  // fused-group work units of A (4 ints each)
+    int32_t nunits = 0;
+    int32_t* split_rows = nullptr;
+    int32_t nsplit = 0;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -263,6 +267,12 @@ static spx_status upload_selector(spx_matrix* H) {
     for (int p = 0; p < 3; ++p) upload_tree(H->sel.distribution[p], &h->t[1 + p]);
     upload_tree(H->sel.writeback, &h->t[4]);
     for (int i = 0; i < 9; ++i) h->mfeat[i] = H->feat[i];
+    h->needs_nnz_s = 0;
+    const Tree* trees[5] = {&H->sel.pattern, &H->sel.distribution[0], &H->sel.distribution[1],
+                            &H->sel.distribution[2], &H->sel.writeback};
+    for (const Tree* t : trees)
+        for (size_t i = 0; i < t->cls.size(); ++i)
+            if (t->cls[i] < 0 && (t->feat[i] == F_NNZ_S || t->feat[i] == F_M_SPARSITY)) h->needs_nnz_s = 1;
     hipError_t e = hipMemcpy(H->dev_sel, h, sizeof(DevSelector), hipMemcpyHostToDevice);
     delete h;
     if (e != hipSuccess) return hip_fail(e, "upload selector");
@@ -399,7 +409,8 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->gorder, H->grank, H->gcol, H->gsrc,
                     H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
-                    H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws};
+                    H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
+                    H->units, H->split_rows};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (auto& e : H->ev_conv) {
@@ -966,6 +977,40 @@ static int lanes_for(double avg) {
     return L;
 }
 
+// Work units of the fused row-major groups of run_batch: consecutive whole
+// rows up to kFusedUnitNnz entries and kFusedUnitRows rows per unit; a longer
+// row becomes pieces of kFusedUnitNnz entries (a split row).
+static spx_status build_units(spx_matrix* H, hipStream_t s) {
+    const spx_csr& A = H->csr;
+    std::vector<int32_t> rp((size_t)A.m + 1);
+    SPX_HIP(hipMemcpyAsync(rp.data(), A.row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s));
+    SPX_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> u;
+    std::vector<int32_t> split;
+    int32_t r = 0;
+    while (r < A.m) {
+        const int32_t len = rp[r + 1] - rp[r];
+        if (len > kFusedUnitNnz) {
+            for (int32_t k = rp[r]; k < rp[r + 1]; k += kFusedUnitNnz)
+                u.insert(u.end(), {r, r + 1, k, std::min(k + kFusedUnitNnz, rp[r + 1])});
+            split.push_back(r);
+            ++r;
+            continue;
+        }
+        const int32_t r0 = r;
+        while (r < A.m && r - r0 < kFusedUnitRows && rp[r + 1] - rp[r0] <= kFusedUnitNnz) ++r;
+        u.insert(u.end(), {r0, r, rp[r0], rp[r]});
+    }
+    H->nunits = (int32_t)(u.size() / 4);
+    H->nsplit = (int32_t)split.size();
+    if (hipMalloc((void**)&H->units, u.size() * 4) != hipSuccess ||
+        hipMalloc((void**)&H->split_rows, std::max<size_t>(1, split.size()) * 4) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "run_batch: work units allocation failed");
+    SPX_HIP(hipMemcpy(H->units, u.data(), u.size() * 4, hipMemcpyHostToDevice));
+    if (!split.empty()) SPX_HIP(hipMemcpy(H->split_rows, split.data(), split.size() * 4, hipMemcpyHostToDevice));
+    return SPX_OK;
+}
+
 extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, const int32_t* vec_ptr,
                                 const int32_t* idx, const void* val, void* Y, void* stream) {
     if (!H) return fail(SPX_ERR_ARG, "handle is null");
@@ -980,8 +1025,10 @@ extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, c
     const int32_t* part = nullptr;
     SPX_TRY(cached_part(H, A, 0, &bal, s, &part));
     const int64_t tiles_mat = ceil_div((int64_t)A.m + A.nnz, 2048);
+    if (!H->units && A.dtype != SPX_BOOL && A.m > 0) SPX_TRY(build_units(H, s));
     // capacity-bounded workspace, zeroed at allocation (the per-vector
-    // bitvector and value slots are self-cleaning afterwards)
+    // bitvector and value slots and the group slabs are self-cleaning
+    // afterwards)
     if (B > H->bcap_B || total_nnz_x > H->bcap_nnz) {
         const int32_t nb = std::max(B, H->bcap_B);
         const int64_t nn = std::max(total_nnz_x, H->bcap_nnz);
@@ -1021,6 +1068,13 @@ extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, c
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     L.persistent_grid = std::max(1, cus) * 4;
+    L.fcol = H->gorder ? H->gcol : nullptr;
+    L.fvals = H->gorder ? H->gvals : nullptr;
+    L.fmap = H->gorder ? H->grank : nullptr;
+    L.units = H->units;
+    L.nunits = H->nunits;
+    L.split_rows = H->split_rows;
+    L.nsplit = H->nsplit;
     // the graph is keyed by everything its kernel arguments capture
     const void* key[5] = {vec_ptr, idx, val, Y, H->bws};
     const bool same = H->gexec && H->gkey_B == B && std::equal(key, key + 5, H->gkey);

@@ -22,6 +22,19 @@
 //                      Items of one phase never wait for each other: the
 //                      ordering between phases is the kernel boundary.
 //
+// Fused row-major groups: a vector whose plan is row-major (SpMV or CSR
+// SpMSpV, any value type but BOOL), or whose entries reach
+// kFusedMinXSparsity of n, joins a group of up to 64 such vectors that share
+// one pass over A. Its phase-A items scatter x into the group's dense slab
+// X^T (n x 64, lane = slot in the group), the phase-B items of the group walk
+// work units of A (at most kUnitNnz entries of at most kUnitRows whole rows,
+// or a piece of a longer row) with a wave per unit and lane = vector, and
+// its phase-C items clear the slab again. Pieces of split rows are added to
+// Y with atomics (their rows of Y are zeroed by a phase-A item of the
+// group); every other row is written once. Non-support entries meet zeros in
+// the slab, so the bitvector validation of CSR SpMSpV becomes a product with
+// zero.
+//
 // The launches are captured once into a HIP graph by the caller and
 // replayed. The per-vector bitvector and value slots are zero when a run
 // starts and are cleared again by phase C, so no fill is recorded in the
@@ -44,11 +57,14 @@ constexpr int kFillChunk = 65536;    // rows of Y zeroed per phase-A item
 constexpr int kScatterChunk = 2048;  // x entries scattered / cleared per item
 constexpr int kCscDirectEntries = 64;
 constexpr int kCscDirectLanes = 4;
+constexpr int kGroup = 64;                 // vectors per fused group (lanes of a wave)
+constexpr double kFusedMinXSparsity = 0.01;
 
 struct BatchPlan {
     int32_t pattern, dist, wb, lanes;
     int32_t nnz_x, base;
     int32_t nA, nB, nC;
+    int32_t gslot;  // slot in the fused row-major groups, or -1
     int64_t nnz_s;
 };
 
@@ -82,6 +98,17 @@ struct BatchDev {
     int32_t* carry_row_all;  // B x tiles_mat
     void* carry_val_all;     // B x tiles_mat accumulators
     int64_t nwords;
+    // fused row-major groups
+    const int4* units;        // {first row, end row, first entry, end entry}
+    int32_t nunits;
+    const int32_t* split_rows;  // rows cut into several units
+    int32_t nsplit;
+    int32_t* gcount;  // vectors in groups (reset per run)
+    int32_t* gvec;    // slot -> vector
+    void* xt_all;     // ceil(B / 64) slabs of n x 64 values (self-cleaning)
+    const int32_t* fcol;  // columns and values the fused units read (the
+    const void* fvals;    // column-renumbered copy when the handle has one)
+    const int32_t* fmap;  // column -> slab row (null: identity)
 };
 
 __device__ __forceinline__ int dev_tree_eval(const DevTree& t, const double* f) {
@@ -112,6 +139,44 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     }
     int32_t* excl = a.excl_all + base + b;
     const int32_t* idx = a.idx + base;
+    const DevSelector& S = *a.sel;
+    __shared__ int s_fuse;
+    // host-known features first: a vector that joins a fused group needs no
+    // prefix of its column lengths (unless the trees read nnz_s)
+    if (threadIdx.x == 0) {
+        int fuse = 0;
+        if (DT != SPX_BOOL && a.units != nullptr && nx > 0 && !S.needs_nnz_s) {
+            double f[13];
+            for (int i = 0; i < 9; ++i) f[i] = S.mfeat[i];
+            f[9] = nx;
+            f[10] = a.n > 0 ? (double)nx / a.n : 0.0;
+            f[11] = f[12] = 0.0;
+            int pat = dev_tree_eval(S.t[0], f);
+            if (pat < 0 || pat > 2) pat = 0;
+            fuse = pat != SPX_PAT_CSC_SPMSPV || f[10] >= kFusedMinXSparsity;
+        }
+        s_fuse = fuse;
+    }
+    __syncthreads();
+    if (s_fuse) {
+        if (threadIdx.x == 0) {
+            BatchPlan p{};
+            p.pattern = SPX_PAT_SPMV;
+            p.dist = SPX_DIST_BALANCED;
+            p.wb = SPX_WB_NONE;
+            p.lanes = a.row_lanes;
+            p.nnz_x = nx;
+            p.base = base;
+            p.nnz_s = -1;
+            p.gslot = atomicAdd(a.gcount, 1);
+            a.gvec[p.gslot] = b;
+            p.nA = (int32_t)ceil_div(nx, kScatterChunk);
+            p.nB = 0;
+            p.nC = (int32_t)ceil_div(nx, kScatterChunk);
+            a.plans[b] = p;
+        }
+        return;
+    }
     constexpr int kIpt = 8;
     int32_t carry = 0;
     for (int c0 = 0; c0 < nx; c0 += kBlock * kIpt) {
@@ -140,7 +205,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     }
     if (threadIdx.x != 0) return;
     excl[nx] = carry;
-    const DevSelector& S = *a.sel;
     double f[13];
     for (int i = 0; i < 9; ++i) f[i] = S.mfeat[i];
     f[9] = nx;
@@ -150,13 +214,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     BatchPlan p;
     p.pattern = dev_tree_eval(S.t[0], f);
     if (p.pattern < 0 || p.pattern > 2) p.pattern = 0;
+    p.gslot = -1;
+    const bool fusable = DT != SPX_BOOL && a.units != nullptr && nx > 0;
+    if (fusable && (p.pattern != SPX_PAT_CSC_SPMSPV || f[10] >= kFusedMinXSparsity)) {
+        if (p.pattern == SPX_PAT_CSC_SPMSPV) p.pattern = SPX_PAT_SPMV;
+        p.gslot = atomicAdd(a.gcount, 1);
+        a.gvec[p.gslot] = b;
+    }
     p.dist = dev_tree_eval(S.t[1 + p.pattern], f) == SPX_DIST_BALANCED ? SPX_DIST_BALANCED : SPX_DIST_DIRECT;
     p.wb = p.pattern == SPX_PAT_CSC_SPMSPV ? SPX_WB_ATOMIC : SPX_WB_NONE;
     p.lanes = a.row_lanes;
     p.nnz_x = nx;
     p.base = base;
     p.nnz_s = carry;
-    if (p.pattern == SPX_PAT_CSC_SPMSPV) {
+    if (p.gslot >= 0) {
+        p.nA = (int32_t)ceil_div(nx, kScatterChunk);
+        p.nB = 0;
+        p.nC = (int32_t)ceil_div(nx, kScatterChunk);
+    } else if (p.pattern == SPX_PAT_CSC_SPMSPV) {
         p.nA = (int32_t)ceil_div(a.m, kFillChunk);
         p.nB = p.dist == SPX_DIST_BALANCED ? (int32_t)ceil_div((int64_t)nx + carry, kBatchTile)
                                            : (int32_t)ceil_div(nx, kCscDirectEntries);
@@ -170,7 +245,17 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     a.plans[b] = p;
 }
 
-__global__ void k_batch_reset(int32_t* err) { *err = 0; }
+__global__ void k_batch_reset(int32_t* err, int32_t* gcount) {
+    *err = 0;
+    *gcount = 0;
+}
+
+// group items appended after the per-vector items of a phase
+__device__ __forceinline__ int32_t group_items(const BatchDev& a, int ph, int32_t G) {
+    if (ph == 0) return a.nsplit > 0 ? G : 0;
+    if (ph == 1) return G * (int32_t)ceil_div(a.nunits, kWavesPerBlock);
+    return 0;
+}
 
 // ------------------------------------------------------------------ queue
 __global__ __launch_bounds__(kBlock) void k_batch_scan(BatchDev a) {
@@ -189,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_scan(BatchDev a) {
         }
         if (threadIdx.x == 0) {
             off[a.B] = carry;
-            a.totals[ph] = carry;
+            const int32_t G = (int32_t)ceil_div(*a.gcount, kGroup);
+            a.totals[ph] = carry + group_items(a, ph, G);
         }
         __syncthreads();
     }
@@ -236,6 +322,65 @@ __device__ __forceinline__ void batch_rows_direct(const BatchDev& a, int64_t r0,
     }
 }
 
+// One work unit of A for the vectors of fused group g: lane = vector. The
+// unit's entries stream 32 at a time (each a 64-wide gather of the slab row
+// X^T[col]); a row's sum is flushed when the stream passes its end.
+template <int DT>
+__device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32_t unit) {
+    using S = SR<DT>;
+    using X = typename S::X;
+    using Acc = typename S::Acc;
+    const int4 u = a.units[unit];
+    const int r0 = u.x, nrows = u.y - u.x, k0 = u.z, k1 = u.w;
+    const int lane = lane_id();
+    const int nvec = min(kGroup, *a.gcount - g * kGroup);
+    const bool on = lane < nvec;
+    const int b = on ? a.gvec[g * kGroup + lane] : 0;
+    auto* y = (typename S::Y*)a.Y + (int64_t)b * a.m;
+    const X* xt = (const X*)a.xt_all + (int64_t)g * a.n * kGroup + lane;
+    const auto* vals = (const typename S::V*)a.fvals;
+    // lane i holds row_ptr[r0 + i], i <= nrows (nrows < 64)
+    const int rp = lane <= nrows ? a.row_ptr[r0 + lane] : 0;
+    const bool split = nrows == 1 && (k0 != __shfl(rp, 0) || k1 != __shfl(rp, 1));
+    auto flush = [&](int i, Acc v) {
+        if (!on) return;
+        if (split)
+            S::atomic_add(&y[r0 + i], v);
+        else
+            y[r0 + i] = S::out(v);
+    };
+    int i = 0;
+    int end = __shfl(rp, 1);
+    Acc acc = S::zero();
+    // kStep entries per step: lane q loads entry k + q (one coalesced load),
+    // then all kStep slab rows are gathered before the first is used
+    constexpr int kStep = 32;
+    for (int k = k0; k < k1; k += kStep) {
+        const int kk = k + (lane & (kStep - 1));
+        const bool in = kk < k1;
+        const int cl = in ? a.fcol[kk] : 0;
+        const typename S::V vl = in ? S::val(vals, kk) : (typename S::V)0;
+        X xv[kStep];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) xv[q] = xt[(int64_t)__shfl(cl, q) * kGroup];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) {
+            if (k + q >= k1) break;
+            while (k + q >= end) {
+                flush(i, acc);
+                acc = S::zero();
+                ++i;
+                end = __shfl(rp, i + 1);
+            }
+            acc = S::fma(__shfl(vl, q), xv[q], acc);
+        }
+    }
+    for (; i < nrows; ++i) {
+        flush(i, acc);
+        acc = S::zero();
+    }
+}
+
 template <int DT, int PH>
 __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
     using S = SR<DT>;
@@ -255,6 +400,25 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
         if (item >= total) break;
         const int local = item;
         const int32_t* off = a.offs + ph * (a.B + 1);
+        if (local >= off[a.B]) {
+            // a fused group item (phase A: zero the split rows of Y; phase B:
+            // one work unit per wave)
+            const int gi = local - off[a.B];
+            if constexpr (PH == 0) {
+                const int g = gi;
+                const int nvec = min(kGroup, *a.gcount - g * kGroup);
+                for (int t = threadIdx.x; t < a.nsplit * nvec; t += kBlock) {
+                    const int b = a.gvec[g * kGroup + t % nvec];
+                    ((typename S::Y*)a.Y)[(int64_t)b * a.m + a.split_rows[t / nvec]] = (typename S::Y)0;
+                }
+            } else if constexpr (PH == 1) {
+                const int per = (int)ceil_div(a.nunits, kWavesPerBlock);
+                const int g = gi / per;
+                const int32_t unit = (gi % per) * kWavesPerBlock + wave_id();
+                if (unit < a.nunits) batch_fused_unit<DT>(a, g, unit);
+            }
+            continue;
+        }
         const int b = find_vector(off, a.B, local);
         const int j = local - off[b];
         const BatchPlan p = a.plans[b];
@@ -264,6 +428,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
         const int32_t* idx = a.idx + p.base;
         const typename S::X* xv = S::kVals ? xval_all + p.base : nullptr;
         const bool csc = p.pattern == SPX_PAT_CSC_SPMSPV;
+        if (p.gslot >= 0) {
+            if constexpr (PH != 1) {
+                if constexpr (S::kVals) {
+                    auto* xt = (typename S::X*)a.xt_all + (int64_t)(p.gslot / kGroup) * a.n * kGroup + p.gslot % kGroup;
+                    const int e1 = std::min(p.nnz_x, (j + 1) * kScatterChunk);
+                    for (int e = j * kScatterChunk + threadIdx.x; e < e1; e += kBlock) {
+                        const int c = a.fmap ? a.fmap[idx[e]] : idx[e];
+                        xt[(int64_t)c * kGroup] = PH == 0 ? xv[e] : (typename S::X)0;
+                    }
+                }
+            }
+            continue;
+        }
         if constexpr (PH == 0) {
             if (csc) {
                 const int64_t r0 = (int64_t)j * kFillChunk;
@@ -354,12 +531,14 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     take(4 * (size_t)3 * (B + 1));                       // 1 offs
     take(4 * 4);                                          // 2 totals
     take(4 * 4);                                          // 3 queue heads, err
-    take(4);                                              // 4 (unused)
+    take(4);                                              // 4 group count
     take(4 * (size_t)(cap_nnz_x + B));                    // 5 excl
     take(4 * (size_t)B * nwords);                         // 6 bits (self-cleaning)
     take((size_t)vs * B * (size_t)n);                     // 7 xd (self-cleaning)
     take(4 * (size_t)B * tiles_mat);                      // 8 carry rows
     take((size_t)as * B * tiles_mat);                     // 9 carry values
+    take(4 * (size_t)B);                                  // 10 group slot -> vector
+    take((size_t)vs * ceil_div(B, kGroup) * kGroup * (size_t)n);  // 11 group slabs (self-cleaning)
     *bytes = z.used;
     if (!d || !base) return;
     d->plans = (BatchPlan*)(base + off[0]);
@@ -373,6 +552,9 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     d->carry_row_all = (int32_t*)(base + off[8]);
     d->carry_val_all = base + off[9];
     d->nwords = nwords;
+    d->gcount = (int32_t*)(base + off[4]);
+    d->gvec = (int32_t*)(base + off[10]);
+    d->xt_all = base + off[11];
 }
 
 size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
@@ -407,6 +589,13 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
     d.Y = L.Y;
     d.sel = L.sel;
     d.row_lanes = L.row_lanes;
+    d.fcol = L.fcol ? L.fcol : L.csr.col_idx;
+    d.fvals = L.fcol ? L.fvals : L.csr.vals;
+    d.fmap = L.fcol ? L.fmap : nullptr;
+    d.units = (const int4*)L.units;
+    d.nunits = L.nunits;
+    d.split_rows = L.split_rows;
+    d.nsplit = L.nsplit;
     size_t need = 0;
     batch_layout(d.m, d.n, L.csr.dtype, L.B, L.cap_nnz_x, L.tiles_mat, &d, (char*)ws, &need);
     if (need > ws_bytes) return fail(SPX_ERR_WORKSPACE, "run_batch: workspace too small");
@@ -415,7 +604,7 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
     switch (L.csr.dtype) {
 #define SPX_DT(DT)                                                            \
     case DT:                                                                  \
-        k_batch_reset<<<1, 1, 0, s>>>(d.err);                                 \
+        k_batch_reset<<<1, 1, 0, s>>>(d.err, d.gcount);                       \
         k_batch_plan<DT><<<L.B, kBlock, 0, s>>>(d);                           \
         k_batch_scan<<<1, kBlock, 0, s>>>(d);                                 \
         k_batch_phase<DT, 0><<<L.persistent_grid, kBlock, 0, s>>>(d);         \

@@ -160,6 +160,7 @@ struct DevTree {
 struct DevSelector {
     DevTree t[5];
     double mfeat[9];
+    int32_t needs_nnz_s;  // a tree reads nnz_s or m_sparsity
 };
 void upload_tree(const Tree& t, DevTree* out);
 struct BatchLaunch {
@@ -178,7 +179,20 @@ struct BatchLaunch {
     const DevSelector* sel;
     int32_t row_lanes;
     int32_t persistent_grid;
+    // work units of A for the fused row-major groups (null: no fusion): at
+    // most kFusedUnitNnz entries of at most kFusedUnitRows whole rows, or a
+    // piece of a row longer than kFusedUnitNnz
+    const int32_t* units;  // 4 ints per unit
+    int32_t nunits;
+    const int32_t* split_rows;
+    int32_t nsplit;
+    // the column-renumbered copy (null: none) for the fused units
+    const int32_t* fcol;
+    const void* fvals;
+    const int32_t* fmap;  // column -> rank
 };
+constexpr int kFusedUnitNnz = 512;
+constexpr int kFusedUnitRows = 63;
 size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
                      size_t* zero_from, size_t* zero_bytes);
 spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev);

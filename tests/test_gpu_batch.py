@@ -142,3 +142,43 @@ def test_batch_cfg4_svm_rows():
         v = vecs[b]
         ref, S = reference(A, v.idx, v.val, "f32")
         assert_close(Yh[b], ref, S, "f32", f"cfg4 svm b={b}")
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "i32"])
+def test_batch_fused_groups(kind):
+    """Dense-enough vectors share passes over A in groups of 64: three
+    groups (the last partial), hub rows cut into pieces (R-MAT), empty rows
+    and a ragged row count, next to sparse vectors on per-vector plans."""
+    torch = _torch()
+    npdt = {"f32": np.float32, "f64": np.float64, "i32": np.int32}[kind]
+    code = {"f32": spx.F32, "f64": spx.F64, "i32": spx.I32}[kind]
+    rng = np.random.default_rng(11)
+    for name, A in (("rmat16", cfg_matrix("rmat16")),
+                    ("ragged", synth.random_csr(3001, 2503, 0.01, 77, empty_rows=0.3))):
+        if kind == "i32":
+            A = A.with_vals(np.clip(np.round(np.asarray(A.vals) * 4), -4, 4).astype(np.int32))
+        else:
+            A = A.with_vals(np.asarray(A.vals).astype(npdt))
+        M = spx.Matrix.from_host(A, dtype=code)
+        dens = np.concatenate([10 ** rng.uniform(-1.7, 0, 150), 10 ** rng.uniform(-4, -2.5, 20)])
+        dens[0], dens[1] = 1.0, 0.5
+        vecs = []
+        for b, d in enumerate(dens):
+            nnz = max(1, int(round(A.n * d)))
+            dist = "int" if kind == "i32" else "uniform"
+            vecs.append(synth.sparse_vector(A.n, nnz, 7000 + b, dist, np.int32 if kind == "i32" else np.float64))
+        ptr, idx, val = _pack(vecs, kind, npdt)
+        Y = M.run_batch(ptr, idx, val)
+        torch.cuda.synchronize()
+        assert M.batch_status() == 0
+        Yh = Y.cpu().numpy()
+        for b in list(range(0, 170, 7)) + [63, 64, 127, 128, 149, 169]:
+            v = vecs[b]
+            ref, S = reference(A, v.idx, np.asarray(v.val, npdt), kind)
+            assert_close(Yh[b], ref, S, kind, f"fused {name} {kind} b={b} nnz_x={v.nnz}")
+        # a second run on the same arrays: the group slabs were cleared
+        Y2 = M.run_batch(ptr, idx, val).cpu().numpy()
+        for b in (0, 1, 64, 149):
+            v = vecs[b]
+            ref, S = reference(A, v.idx, np.asarray(v.val, npdt), kind)
+            assert_close(Y2[b], ref, S, kind, f"fused rerun {name} {kind} b={b}")
