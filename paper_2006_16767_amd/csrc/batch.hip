@@ -387,8 +387,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
     using Acc = typename S::Acc;
     __shared__ BatchLds<DT> L;
     __shared__ int32_t s_item;
+    // the phase's item offsets per vector, in LDS when they fit (the vector
+    // of an item is found by a binary search over them)
+    constexpr int kOffLds = 2048;
+    __shared__ int32_t s_voff[kOffLds];
     const int32_t total = a.totals[PH];
     constexpr int ph = PH;
+    const bool off_in_lds = a.B + 1 <= kOffLds;
+    if (off_in_lds)
+        for (int i = threadIdx.x; i <= a.B; i += kBlock) s_voff[i] = a.offs[ph * (a.B + 1) + i];
     const auto* vals = (const typename S::V*)a.vals;
     const auto* vals_csc = (const typename S::V*)a.vals_csc;
     const auto* xval_all = (const typename S::X*)a.val;
@@ -419,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
             }
             continue;
         }
-        const int b = find_vector(off, a.B, local);
+        const int b = find_vector(off_in_lds ? s_voff : off, a.B, local);
         const int j = local - off[b];
         const BatchPlan p = a.plans[b];
         auto* Yb = (typename S::Y*)a.Y + (int64_t)b * a.m;
@@ -431,12 +438,26 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
         if (p.gslot >= 0) {
             if constexpr (PH != 1) {
                 if constexpr (S::kVals) {
+                    // the chunk's kScatterChunk entries, eight per thread with
+                    // every load of a step in flight before the stores
                     auto* xt = (typename S::X*)a.xt_all + (int64_t)(p.gslot / kGroup) * a.n * kGroup + p.gslot % kGroup;
                     const int e1 = std::min(p.nnz_x, (j + 1) * kScatterChunk);
-                    for (int e = j * kScatterChunk + threadIdx.x; e < e1; e += kBlock) {
-                        const int c = a.fmap ? a.fmap[idx[e]] : idx[e];
-                        xt[(int64_t)c * kGroup] = PH == 0 ? xv[e] : (typename S::X)0;
+                    constexpr int kPer = kScatterChunk / kBlock;
+                    int c[kPer];
+                    typename S::X v[kPer];
+#pragma unroll
+                    for (int q = 0; q < kPer; ++q) {
+                        const int e = j * kScatterChunk + q * kBlock + threadIdx.x;
+                        c[q] = e < e1 ? idx[e] : -1;
+                        v[q] = (PH == 0 && e < e1) ? xv[e] : (typename S::X)0;
                     }
+                    if (a.fmap) {
+#pragma unroll
+                        for (int q = 0; q < kPer; ++q) c[q] = c[q] >= 0 ? a.fmap[c[q]] : -1;
+                    }
+#pragma unroll
+                    for (int q = 0; q < kPer; ++q)
+                        if (c[q] >= 0) xt[(int64_t)c[q] * kGroup] = v[q];
                 }
             }
             continue;

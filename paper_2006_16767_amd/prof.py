@@ -8,6 +8,10 @@ summaries read the rocpd databases rocprofv3 writes (`*_results.db`).
       run() (or run_plan with the given plan) on vector K of the R-MAT 2^20
       (degree 16) sweep, R times after one warm-up call; prints the plan and
       its kernel-name stems.
+  python -m paper_2006_16767_amd.prof batch [--B 512] [--reps R]
+      run_batch on the 512-vector R-MAT 2^18 (degree 32) batch.
+  python -m paper_2006_16767_amd.prof fc [--reps R]
+      the pruned FC layer 16384 x 4096: fused forward, dX and dvals.
   python -m paper_2006_16767_amd.prof copy [--mib M] [--reps R]
       a plain device-to-device copy of M MiB, R times (counter calibration:
       it reads and writes exactly M MiB).
@@ -124,6 +128,52 @@ def cmd_vector(args):
     print(f"[prof] {args.reps} runs done", flush=True)
 
 
+def cmd_batch(args):
+    import numpy as np
+    import torch
+    from . import Matrix
+    from . import synth
+    A = synth.cfg4_rmat()
+    M = Matrix.from_host(A)
+    vecs = synth.cfg4_rmat_batch(A.n, args.B)
+    ptr = np.zeros(len(vecs) + 1, np.int32)
+    ptr[1:] = np.cumsum([v.nnz for v in vecs])
+    dev = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
+    idx = dev(np.concatenate([v.idx for v in vecs]).astype(np.int32))
+    val = dev(np.concatenate([np.asarray(v.val, np.float32) for v in vecs]))
+    Y = M.out_tensor(len(vecs))
+    M.run_batch(dev(ptr), idx, val, Y)
+    torch.cuda.synchronize()
+    print(f"[prof] batch of {len(vecs)} on R-MAT 2^18 (degree 32), status {M.batch_status()}", flush=True)
+    for _ in range(args.reps):
+        M.run_batch(dev(ptr), idx, val, Y)
+    torch.cuda.synchronize()
+    print(f"[prof] {args.reps} runs done", flush=True)
+
+
+def cmd_fc(args):
+    import numpy as np
+    import torch
+    from . import Matrix
+    from . import synth
+    A = synth.cfg5_matrix()
+    M = Matrix.from_host(A)
+    Xh = np.zeros((64, A.n), np.float32)
+    for b, v in enumerate(synth.cfg5_activations()):
+        Xh[b, v.idx] = v.val
+    X = torch.as_tensor(Xh, device="cuda")
+    G = torch.as_tensor(synth.cfg5_upstream(), device="cuda")
+    Y = M.out_tensor(64)
+    dX = torch.empty_like(X)
+    dv = torch.empty(A.nnz, dtype=torch.float32, device="cuda")
+    for _ in range(args.reps + 1):
+        M.spmv_batch(X, Y)
+        M.transpose_matvec(G, dX)
+        M.dvals(G, X, dv)
+    torch.cuda.synchronize()
+    print(f"[prof] FC layer 16384 x 4096: {args.reps + 1} forward + backward passes done", flush=True)
+
+
 def cmd_copy(args):
     import torch
     n = args.mib * (1 << 20) // 4
@@ -209,6 +259,11 @@ def main(argv=None):
     a.add_argument("k", type=int)
     a.add_argument("--reps", type=int, default=5)
     a.add_argument("--plan", help="pattern,distribution[,writeback] instead of run()'s choice")
+    a = sub.add_parser("batch")
+    a.add_argument("--B", type=int, default=512)
+    a.add_argument("--reps", type=int, default=5)
+    a = sub.add_parser("fc")
+    a.add_argument("--reps", type=int, default=5)
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=512)
     a.add_argument("--reps", type=int, default=3)
@@ -224,7 +279,8 @@ def main(argv=None):
     a.add_argument("--vector", type=int, required=True)
     a.add_argument("--command", action="append")
     args = ap.parse_args(argv)
-    {"vector": cmd_vector, "copy": cmd_copy, "kernels": cmd_kernels, "traffic": cmd_traffic}[args.cmd](args)
+    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "copy": cmd_copy, "kernels": cmd_kernels,
+     "traffic": cmd_traffic}[args.cmd](args)
 
 
 if __name__ == "__main__":
