@@ -86,7 +86,7 @@ def corpus(quick: bool = False):
     return mats
 
 
-def densities(n: int, count: int = 24):
+def densities(n: int, count: int = 40):
     """nnz_x from 1 to n, log-spaced (the paper grows nnz_x from 1 to n)."""
     vals = np.unique(np.round(np.geomspace(1, n, count)).astype(np.int64))
     return [int(v) for v in vals]
