@@ -14,8 +14,10 @@ train  labels each record per factor (the pattern of the fastest kernel;
        the best distribution within that pattern; the best write-back within
        the column-major pattern and the chosen distribution; times within 2%
        go to the cheaper alternative), splits 7:3, and grid-searches a
-       project-written CART decision tree (max_depth 1..10, class weights
-       balanced or uniform, 3-fold cross-validation on the training part).
+       project-written CART decision tree (max_depth 1..10; sample weights
+       balanced by class, uniform, or by regret, i.e. the relative time the
+       worst alternative would lose; 3-fold cross-validation on the training
+       part, scored by accuracy).
        The three trees are written as the JSON the library loads
        (spx_load_selector).
 
@@ -268,33 +270,55 @@ class Cart:
         return out
 
 
-def _weights(y, mode):
+def _weights(y, mode, T=None):
+    """Sample weights: uniform, balanced classes, or regret (how much time
+    choosing the worst alternative would cost, relative to the best, from
+    the per-class times T; clipped to [0.02, 2])."""
     if mode == "uniform":
         return np.ones(len(y))
+    if mode == "regret":
+        fin = np.where(np.isfinite(T), T, np.nan)
+        best = np.nanmin(fin, axis=1)
+        worst = np.nanmax(fin, axis=1)
+        return np.clip((worst - best) / best, 0.02, 2.0)
     cls, cnt = np.unique(y, return_counts=True)
     wmap = {c: len(y) / (len(cls) * n) for c, n in zip(cls, cnt)}
     return np.array([wmap[c] for c in y])
 
 
-def grid_search(X, y, n_classes, seed=0):
-    """max_depth 1..10 x class weight {balanced, uniform}, 3-fold CV."""
+def _time_loss(T, pred):
+    """Mean relative time lost by choosing class pred[i] instead of the
+    fastest (an alternative with no timing counts as a loss of 1)."""
+    best = np.min(np.where(np.isfinite(T), T, np.inf), axis=1)
+    chosen = T[np.arange(len(pred)), pred]
+    loss = np.where(np.isfinite(chosen), chosen / best - 1.0, 1.0)
+    return float(np.mean(loss))
+
+
+def grid_search(X, y, n_classes, seed=0, T=None, score_time=False):
+    """max_depth 1..10 x sample weighting {balanced, uniform, and regret when
+    per-class times T are given}, 3-fold CV. The score is accuracy, or with
+    score_time 1 - the mean relative time lost against the fastest class."""
     rng = np.random.default_rng(seed)
     idx = rng.permutation(len(y))
     folds = np.array_split(idx, 3)
     best = None
+    modes = ("balanced", "uniform") + (("regret",) if T is not None else ())
     for depth in range(1, 11):
-        for cw in ("balanced", "uniform"):
-            accs = []
+        for cw in modes:
+            scores = []
             for k in range(3):
                 te = folds[k]
                 tr = np.concatenate([folds[j] for j in range(3) if j != k])
                 if len(tr) == 0 or len(te) == 0:
                     continue
-                t = Cart(depth).fit(X[tr], y[tr], _weights(y[tr], cw), n_classes)
-                accs.append((t.predict(X[te]) == y[te]).mean())
-            acc = float(np.mean(accs)) if accs else 0.0
-            if best is None or acc > best[0] + 1e-9:
-                best = (acc, depth, cw)
+                w = _weights(y[tr], cw, None if T is None else T[tr])
+                t = Cart(depth).fit(X[tr], y[tr], w, n_classes)
+                pred = t.predict(X[te])
+                scores.append((pred == y[te]).mean() if not score_time else 1.0 - _time_loss(T[te], pred))
+            sc = float(np.mean(scores)) if scores else 0.0
+            if best is None or sc > best[0] + 1e-9:
+                best = (sc, depth, cw)
     return best
 
 
@@ -320,24 +344,37 @@ def train(paths, out_path, all_features=False, seed=0):
     report = {"records": len(rows), "train": len(tr), "test": len(te), "features": list(feats)}
     trees = {}
 
-    def fit_tree(name, ysel, mask, n_classes):
+    def fit_tree(name, ysel, mask, n_classes, tsel=None):
         y = np.array([ysel(lab) for _, lab in rows])
+        T = None if tsel is None else np.array([tsel(lab) for _, lab in rows], np.float64)
         trm = tr[mask[tr]]
         tem = te[mask[te]]
         if len(trm) == 0:
             return None
-        acc, depth, cw = grid_search(Xs[trm], y[trm], n_classes, seed)
-        t = Cart(depth).fit(Xs[trm], y[trm], _weights(y[trm], cw), n_classes)
+        acc, depth, cw = grid_search(Xs[trm], y[trm], n_classes, seed, None if T is None else T[trm])
+        t = Cart(depth).fit(Xs[trm], y[trm], _weights(y[trm], cw, None if T is None else T[trm]), n_classes)
         test_acc = float((t.predict(Xs[tem]) == y[tem]).mean()) if len(tem) else float("nan")
-        report[name] = {"cv_acc": acc, "max_depth": depth, "class_weight": cw, "test_acc": test_acc,
+        report[name] = {"cv_score": acc, "max_depth": depth, "class_weight": cw, "test_acc": test_acc,
                         "n_train": int(len(trm)), "n_test": int(len(tem)),
                         "classes": np.bincount(y[trm], minlength=n_classes).tolist()}
         # map feature columns back to Table 1 ids for the library
         nodes = [[fidx[n[0]] if n[4] < 0 else 0, n[1], n[2], n[3], n[4]] for n in t.nodes]
         return {"nodes": nodes, "max_depth": depth, "class_weight": cw}
 
+    def class_times(l, factor, pat=None):
+        """Per-class times of one factor, the others at their best (inf
+        where a class has no timing)."""
+        t = l["times"]
+        if factor == "pattern":
+            return [min((ms for (p, d, w), ms in t.items() if p == c), default=np.inf) for c in PATTERNS]
+        if factor == "distribution":
+            return [min((ms for (p, d, w), ms in t.items() if p == pat and d == c), default=np.inf) for c in DISTS]
+        dist = DISTS[l["distribution"]]
+        return [min((ms for (p, d, w), ms in t.items() if p == "csc_spmspv" and d == dist and w == c),
+                    default=np.inf) for c in WBS]
+
     allm = np.ones(len(rows), bool)
-    trees["pattern"] = fit_tree("pattern", lambda l: l["pattern"], allm, 3)
+    trees["pattern"] = fit_tree("pattern", lambda l: l["pattern"], allm, 3, lambda l: class_times(l, "pattern"))
     trees["distribution"] = {}
     for pi, pn in enumerate(PATTERNS):
         # distribution labels of records whose best pattern is this one; fall
@@ -353,12 +390,13 @@ def train(paths, out_path, all_features=False, seed=0):
         mask = np.array([l["pattern"] == pi for _, l in rows])
         if mask.sum() < 10:
             mask = allm
-        t = fit_tree(f"distribution_{pn}", dsel, mask, 2)
+        t = fit_tree(f"distribution_{pn}", dsel, mask, 2, lambda l, pn=pn: class_times(l, "distribution", pn))
         trees["distribution"][pn] = t or {"nodes": [[0, 0, 0, 0, 0]]}
     mask = np.array([l["pattern"] == 2 for _, l in rows])
     if mask.sum() < 10:
         mask = allm
-    trees["writeback"] = fit_tree("writeback", lambda l: l["writeback"], mask, 5)
+    trees["writeback"] = fit_tree("writeback", lambda l: l["writeback"], mask, 5,
+                                  lambda l: class_times(l, "writeback"))
     # selection quality against exhaustive search on the held-out part:
     # time of the predicted kernel vs the fastest kernel
     out = {"format": "spx-selector-v1", "source": "tuned on MI355X timings", "report": report, **trees}
