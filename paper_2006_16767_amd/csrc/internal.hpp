@@ -118,6 +118,10 @@ spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
 size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype,
                      const spx_plan* plan);
 // bucket write-back (spmspv_bucket.hip); excl = prefix of selected column lengths
+// the direct bucket write-back for a short x: one launch, no prefix, no fill
+bool csc_bucket_walks(const CscArgs& A, int32_t nnz_x, const spx_plan* plan);
+spx_status launch_csc_bucket_walk(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
+                                  const spx_plan* plan, hipStream_t s);
 spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
                              void* y, const spx_plan* plan, const Excl excl, Arena& ws,
                              hipStream_t s);

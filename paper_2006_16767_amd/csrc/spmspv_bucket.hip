@@ -1,7 +1,9 @@
 // Bucket write-back of the column-major SpMSpV.
 //
 // The rows of y are cut into NB buckets of R rows (R a power of two, R * acc
-// size <= 64 KiB so a bucket's slice of y fits in LDS). Two kernels:
+// size <= 64 KiB so a bucket's slice of y fits in LDS). Two kernels (a short
+// x with the direct distribution takes the one-launch walk instead, see
+// k_bucket_walk):
 //
 //  scatter     each workgroup takes a chunk of effective positions (one
 //              merge-path tile for the balanced distribution, a contiguous
@@ -276,6 +278,68 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
         if (base + r < m) y[base + r] = S::out(acc[r]);
 }
 
+// ------------------------------------------------------------------ walk (short x)
+// The direct bucket write-back for a short x, in one launch: one 1024-thread
+// workgroup per bucket zeroes its R rows in LDS, every thread takes x
+// entries and adds the entries of their columns whose row falls in the
+// bucket (rows ascend within a CSC column, so a long column is cut to the
+// bucket's row range by two binary searches), then the workgroup writes its
+// rows of y once. No pair buffer, no prefix, no zero fill of y.
+constexpr int kWalkMaxX = 2048;       // x entries of a walk
+constexpr int64_t kWalkMaxS = 16384;  // estimated selected entries of a walk
+constexpr int kWalkScan = 32;         // columns up to this length are scanned
+
+template <int DT>
+__global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR, int32_t nnz_x,
+                                                             const int32_t* __restrict__ x_idx,
+                                                             const typename SR<DT>::X* __restrict__ x_val,
+                                                             const int32_t* __restrict__ col_ptr,
+                                                             const int32_t* __restrict__ row_idx,
+                                                             const typename SR<DT>::V* __restrict__ vals,
+                                                             typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    extern __shared__ char s_raw[];
+    Acc* acc = (Acc*)s_raw;
+    const int R = 1 << logR;
+    const int b = blockIdx.x;
+    const int lo = b << logR, hi = lo + R;
+    for (int r = threadIdx.x; r < R; r += kAccThreads) acc[r] = S::zero();
+    __syncthreads();
+    for (int e = threadIdx.x; e < nnz_x; e += kAccThreads) {
+        const int j = x_idx[e];
+        const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
+        int k0 = col_ptr[j], k1 = col_ptr[j + 1];
+        if (k1 - k0 > kWalkScan) {
+            // first position with row >= lo, then first with row >= hi
+            int a = k0, z = k1;
+            while (a < z) {
+                const int mid = (a + z) >> 1;
+                if (row_idx[mid] < lo) a = mid + 1; else z = mid;
+            }
+            int a2 = a, z2 = k1;
+            while (a2 < z2) {
+                const int mid = (a2 + z2) >> 1;
+                if (row_idx[mid] < hi) a2 = mid + 1; else z2 = mid;
+            }
+            k0 = a;
+            k1 = a2;
+        }
+        for (int k = k0; k < k1; ++k) {
+            const int r = row_idx[k];
+            if (r >= lo && r < hi) {
+                if constexpr (S::kVals)
+                    S::lds_atomic_add(&acc[r - lo], S::mul(S::val(vals, k), v));
+                else
+                    acc[r - lo] = 1u;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += kAccThreads)
+        if (lo + r < m) y[lo + r] = S::out(acc[r]);
+}
+
 // ------------------------------------------------------------------ launch
 struct BucketGeom {
     int logR, NB;
@@ -370,6 +434,39 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
                                                                      out.stride, y);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
+}
+
+bool csc_bucket_walks(const CscArgs& A, int32_t nnz_x, const spx_plan* plan) {
+    if (plan->writeback != SPX_WB_BUCKET || plan->distribution != SPX_DIST_DIRECT) return false;
+    const int64_t est = A.nnz_s_hint >= 0 ? A.nnz_s_hint
+                                           : (int64_t)((double)nnz_x * (A.n > 0 ? (double)A.nnz / A.n : 0.0));
+    return nnz_x <= kWalkMaxX && est <= kWalkMaxS;
+}
+
+template <int DT>
+static spx_status launch_walk_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
+                                const spx_plan* plan, hipStream_t s) {
+    using S = SR<DT>;
+    BucketGeom g;
+    if (!bucket_geometry(A.m, DT, plan->bucket_rows, &g))
+        return fail(SPX_ERR_UNSUPPORTED, "bucket write-back: rows per bucket must fit 64 KiB of LDS and at most 4096 buckets");
+    const size_t lds = ((size_t)1 << g.logR) * sizeof(typename S::Acc);
+    k_bucket_walk<DT><<<(unsigned)g.NB, kAccThreads, lds, s>>>(A.m, g.logR, nnz_x, x_idx,
+                                                              (const typename S::X*)x_val, A.col_ptr, A.row_idx,
+                                                              (const typename S::V*)A.vals, (typename S::Y*)y);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+spx_status launch_csc_bucket_walk(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
+                                  const spx_plan* plan, hipStream_t s) {
+    switch (A.dtype) {
+        case SPX_F32: return launch_walk_t<SPX_F32>(A, nnz_x, x_idx, x_val, y, plan, s);
+        case SPX_F64: return launch_walk_t<SPX_F64>(A, nnz_x, x_idx, x_val, y, plan, s);
+        case SPX_I32: return launch_walk_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, s);
+        case SPX_BOOL: return launch_walk_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, s);
+    }
+    return fail(SPX_ERR_DTYPE, "bucket: unknown dtype");
 }
 
 spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,

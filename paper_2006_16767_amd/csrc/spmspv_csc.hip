@@ -449,6 +449,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int dist = plan->distribution;
     const size_t ybytes = (size_t)A.m * sizeof(typename S::Y);
     if (A.m == 0) return SPX_OK;
+    if (nnz_x > 0 && csc_bucket_walks(A, nnz_x, plan)) return launch_csc_bucket_walk(A, nnz_x, x_idx, x_val_v, y_v, plan, s);
     const int L = plan->lanes > 0 ? plan->lanes : pick_col_lanes(A.n, A.nnz);
     const bool lds_ok = (int64_t)A.m * (int64_t)sizeof(Acc) <= kLdsBytes;
     if (wb == SPX_WB_LDS_ATOMIC && !lds_ok && nnz_x > 0)
