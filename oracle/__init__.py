@@ -46,6 +46,7 @@ def _load():
         "oracle_matrix_features": [i32, i32, _i32p, _f64p],
         "oracle_vector_features": [i32, i32, _i32p, i32, _i32p, _f64p],
         "oracle_bfs_step": [C.c_int64, _i32p, _i32p, i32, _u8p, i32, _u8p],
+        "oracle_bfs_levels": [C.c_int64, _i32p, _i32p, i32, i32, _i32p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -187,6 +188,17 @@ def vector_features(csc: CSC, x_idx) -> dict:
     _check(lib.oracle_vector_features(csc.n, int(csc.col_ptr[-1]), csc.col_ptr, x_idx.size, x_idx,
                                       out), "oracle_vector_features")
     return dict(zip(VECTOR_FEATURES, out.tolist()))
+
+
+def bfs_levels(src, dst, n, source):
+    """Breadth-first levels from source over the directed edges src -> dst
+    (-1 where unreachable)."""
+    lib = _load()
+    src = _i32(src)
+    dst = _i32(dst)
+    level = np.empty(n, np.int32)
+    _check(lib.oracle_bfs_levels(src.size, src, dst, n, source, level), "oracle_bfs_levels")
+    return level
 
 
 def bfs_step(src, dst, n, m, active_idx):

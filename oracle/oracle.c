@@ -366,3 +366,70 @@ int oracle_bfs_step(int64_t n_edges, const int32_t *src, const int32_t *dst, int
     }
     return OK;
 }
+
+/* ---------------------------------------------------------------------
+ * Breadth-first search levels over a directed edge list src[e] -> dst[e]
+ * of n vertices (the traversal the paper runs its kernels in, Section 7):
+ * level[v] = fewest edges on a path from source, -1 if v is unreachable.
+ * Textbook queue order: out-edges grouped by their source vertex, a FIFO of
+ * discovered vertices, each vertex labelled when first discovered.
+ * ------------------------------------------------------------------- */
+int oracle_bfs_levels(int64_t n_edges, const int32_t *src, const int32_t *dst, int32_t n, int32_t source,
+                      int32_t *level)
+{
+    if (n < 0 || (n > 0 && (source < 0 || source >= n)))
+        return ERR_ARG;
+    int64_t *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *out = (int32_t *)malloc((size_t)(n_edges > 0 ? n_edges : 1) * sizeof(int32_t));
+    int32_t *queue = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!start || !out || !queue) {
+        free(start);
+        free(out);
+        free(queue);
+        return ERR_ALLOC;
+    }
+    for (int64_t e = 0; e < n_edges; ++e) {
+        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) {
+            free(start);
+            free(out);
+            free(queue);
+            return ERR_ARG;
+        }
+        start[src[e] + 1] += 1;
+    }
+    for (int32_t v = 0; v < n; ++v)
+        start[v + 1] += start[v];
+    int64_t *fill = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!fill) {
+        free(start);
+        free(out);
+        free(queue);
+        return ERR_ALLOC;
+    }
+    for (int32_t v = 0; v < n; ++v)
+        fill[v] = start[v];
+    for (int64_t e = 0; e < n_edges; ++e)
+        out[fill[src[e]]++] = dst[e];
+    free(fill);
+    for (int32_t v = 0; v < n; ++v)
+        level[v] = -1;
+    if (n > 0) {
+        int32_t head = 0, tail = 0;
+        level[source] = 0;
+        queue[tail++] = source;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            for (int64_t e = start[u]; e < start[u + 1]; ++e) {
+                int32_t v = out[e];
+                if (level[v] < 0) {
+                    level[v] = level[u] + 1;
+                    queue[tail++] = v;
+                }
+            }
+        }
+    }
+    free(start);
+    free(out);
+    free(queue);
+    return OK;
+}

@@ -447,3 +447,33 @@ def test_pin_catches_wrong_gini():
     srt = np.sort(L)
     wrong = sum((2 * i - 6 - 1) * r for i, r in enumerate(srt)) / (6 * L.sum())
     assert wrong != pytest.approx(_gini_mean_abs_diff(L), rel=1e-6)
+
+
+def test_bfs_levels_hand_worked():
+    """Six vertices: 0 -> 1 -> 2 -> 3, 0 -> 2, 4 -> 0, and 5 alone.
+    From 0: levels 0, 1, 1, 2, unreachable, unreachable. From 4: one more
+    everywhere below it, 0 for itself."""
+    src = np.array([0, 1, 2, 0, 4], np.int32)
+    dst = np.array([1, 2, 3, 2, 0], np.int32)
+    assert oracle.bfs_levels(src, dst, 6, 0).tolist() == [0, 1, 1, 2, -1, -1]
+    assert oracle.bfs_levels(src, dst, 6, 4).tolist() == [1, 2, 2, 3, 0, -1]
+    assert oracle.bfs_levels(src, dst, 6, 5).tolist() == [-1, -1, -1, -1, -1, 0]
+
+
+def test_bfs_levels_vs_scipy_shortest_path():
+    """Levels equal the unweighted directed shortest-path lengths of scipy's
+    csgraph, on random graphs from dense enough to sparse enough to leave
+    vertices unreachable."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(17)
+    for n, deg in ((40, 0.5), (300, 1.2), (300, 4.0), (1000, 2.0)):
+        ne = int(n * deg)
+        src = rng.integers(0, n, ne).astype(np.int32)
+        dst = rng.integers(0, n, ne).astype(np.int32)
+        g = sp.csr_matrix((np.ones(ne), (src, dst)), shape=(n, n))
+        for s in (0, n // 2, n - 1):
+            want = shortest_path(g, directed=True, unweighted=True, indices=s)
+            want = np.where(np.isinf(want), -1, want).astype(np.int64)
+            got = oracle.bfs_levels(src, dst, n, s)
+            assert np.array_equal(got, want), (n, deg, s)
