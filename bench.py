@@ -177,6 +177,44 @@ def extra_fwd_bwd(torch, spx, synth, reps=10):
             "dx_pct_unique": round(pct(dx_u, t_dx), 2), "dvals_pct": round(pct(dv_b, t_dv), 2)}
 
 
+def extra_bfs(torch, spx, synth, reps=3):
+    """Breadth-first search on the R-MAT 2^20 graph (pattern), one adaptive
+    SpMSpV per level, against every level on one fixed kernel."""
+    import numpy as np
+    A = synth.cfg2_matrix()
+    M = spx.Matrix.from_host(A, dtype=spx.BOOL)
+    outdeg = np.bincount(A.col_idx, minlength=A.n)
+    src = 0 if outdeg[0] > 0 else int(np.nonzero(outdeg > 0)[0][0])
+
+    def timed(plan=None):
+        M.bfs(src, plan=plan)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            level, plans = M.bfs(src, plan=plan)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3, level, plans
+
+    ms, level, plans = timed()
+    reached = level.cpu().numpy() >= 0
+    edges = int(outdeg[reached].sum())  # edges leaving reached vertices
+    out = {"workload": "rmat20_deg16_bfs", "source": src, "levels": M.bfs_levels,
+           "edges_traversed": edges, "adaptive_ms": round(ms, 3),
+           "adaptive_GTEPS": round(edges / (ms * 1e-3) / 1e9, 2),
+           "plans_per_level": [f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/"
+                               f"{['direct', 'balanced'][p.distribution]}/"
+                               f"{['none', 'atomic', 'sort', 'lds_atomic', 'bucket'][p.writeback]}" for p in plans],
+           "fixed_ms": {}}
+    for name, p in (("spmv_balanced", spx.plan("spmv", "balanced")),
+                    ("csr_spmspv_balanced", spx.plan("csr_spmspv", "balanced")),
+                    ("csc_balanced_atomic", spx.plan("csc_spmspv", "balanced", "atomic")),
+                    ("csc_direct_atomic", spx.plan("csc_spmspv", "direct", "atomic"))):
+        out["fixed_ms"][name] = round(timed(p)[0], 3)
+    best = min(out["fixed_ms"].values())
+    out["adaptive_speedup_vs_best_fixed"] = round(best / ms, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +332,7 @@ def main():
     if not args.no_extras:
         extras = {}
         for name, fn in (("poisson_spmv", extra_poisson), ("batched_vs_looped", extra_batched),
-                         ("fwd_vs_fwd_bwd", extra_fwd_bwd)):
+                         ("fwd_vs_fwd_bwd", extra_fwd_bwd), ("bfs", extra_bfs)):
             print(f"[bench] extra: {name}", file=sys.stderr, flush=True)
             extras[name] = fn(torch, spx, synth)
         rec["extras"] = extras

@@ -239,8 +239,10 @@ spx_status spx_vector_features(spx_matrix *H, const spx_vec *x, double *out4, vo
  * ------------------------------------------------------------------- */
 
 /* Loads the three decision trees (pattern, distribution, write-back) from
- * a JSON file written by the tuner. NULL restores the built-in trees.
- * Applies to handles created afterwards and to H if H is not NULL. */
+ * a JSON file written by the tuner; json_path NULL means the built-in
+ * trees. With H NULL they become the default of handles created
+ * afterwards; otherwise they replace H's trees only (for example trees
+ * trained for the BOOL semiring on a BOOL handle). */
 spx_status spx_load_selector(spx_matrix *H, const char *json_path);
 
 /* Walks the cascade: pattern tree, then distribution tree, then (column-
@@ -305,6 +307,21 @@ spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
  * activations. One wave walks a whole row, so rows far longer than the
  * average (hub rows) serialize. F32 and F64 only. */
 spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void *stream);
+
+/* Breadth-first search over the graph of a square BOOL handle (stored entry
+ * (i, j) = edge j -> i, so a column lists a vertex's out-edges): level[v] =
+ * fewest edges from source, -1 if unreachable (level: device int32[n]).
+ * Every level is one (OR, AND) SpMSpV of the frontier, through run() (the
+ * kernel chosen per level, as the frontier's density changes; Section 7) or
+ * through run_plan() with the given plan, followed by a kernel that keeps
+ * the unvisited vertices, labels them and appends them to the next
+ * frontier. At most max_levels levels are labelled. *n_levels = the number
+ * of levels labelled (1 + the largest level). If plans is given, plans[l]
+ * receives the plan of expansion l for l < plans_cap. Synchronizes the
+ * stream once per level (the frontier size decides the next call). The
+ * frontier and product buffers belong to the handle. */
+spx_status spx_bfs(spx_matrix *H, int32_t source, int32_t *level, int32_t max_levels, const spx_plan *plan,
+                   int32_t *n_levels, spx_plan *plans, int32_t plans_cap, void *stream);
 
 /* ---------------------------------------------------------------------
  * Backward of Y[b] = A(vals) X[b] for a loss L(Y), with G = dL/dY

@@ -23,6 +23,8 @@ __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spms
            "F32", "F64", "BOOL", "I32", "all_plans"]
 
 _DEFAULT_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x.json")
+# trees trained on (OR, AND) timings, loaded into BOOL handles
+_BOOL_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_bool.json")
 _selector_loaded = False
 
 
@@ -121,6 +123,8 @@ class Matrix:
         flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
+        if dtype == BOOL and __import__("os").path.exists(_BOOL_SELECTOR):
+            _lib.call("spx_load_selector", self._h, _BOOL_SELECTOR.encode())
         self._vals_version = None if self.vals is None else self.vals._version
 
     @classmethod
@@ -290,6 +294,23 @@ class Matrix:
         Y = self.out_tensor(B) if Y is None else Y
         _lib.call("spmv_csr_batch", self._h, B, _ptr(X2), _ptr(Y), _stream(stream))
         return Y
+
+    def bfs(self, source: int, max_levels: int = 1 << 30, plan: Plan | None = None, stream=None):
+        """Breadth-first levels from source (BOOL handle; entry (i, j) is the
+        edge j -> i): returns (level tensor int32[n], the plan of every
+        expansion). A search that runs to completion makes one expansion per
+        level, the last of which finds no new vertex."""
+        torch = _torch()
+        level = torch.empty(self.n, dtype=torch.int32, device=self.row_ptr.device)
+        nl = C.c_int32(0)
+        cap = 4096
+        plans = (Plan * cap)()
+        for i in range(cap):
+            plans[i].pattern = -1  # entries the search does not reach stay -1
+        _lib.call("spx_bfs", self._h, int(source), _ptr(level), int(max_levels),
+                  None if plan is None else C.byref(plan), C.byref(nl), plans, cap, _stream(stream))
+        self.bfs_levels = nl.value
+        return level, [plans[i] for i in range(cap) if plans[i].pattern >= 0]
 
     def batch_status(self, stream=None) -> int:
         f = C.c_int32()

@@ -79,6 +79,7 @@ SIGNATURES = {
     "spx_run_times": (C.c_int, [P, C.POINTER(C.c_double), _i32, C.POINTER(_i32)]),
     "run_batch": (C.c_int, [P, _i32, C.c_int64, P, P, P, P, P]),
     "spx_batch_status": (C.c_int, [P, C.POINTER(_i32), P]),
+    "spx_bfs": (C.c_int, [P, _i32, P, _i32, C.POINTER(Plan), C.POINTER(C.c_int32), C.POINTER(Plan), _i32, P]),
     "spmv_csr_batch": (C.c_int, [P, _i32, P, P, P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),

@@ -193,6 +193,10 @@ struct spx_matrix {
     int32_t nunits = 0;
     int32_t* split_rows = nullptr;
     int32_t nsplit = 0;
+    // breadth-first search buffers (allocated on first use)
+    int32_t* bfs_front[2] = {nullptr, nullptr};
+    uint8_t* bfs_y = nullptr;
+    int32_t* bfs_count = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -410,7 +414,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
-                    H->units, H->split_rows};
+                    H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->bfs_count};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (auto& e : H->ev_conv) {
@@ -783,12 +787,12 @@ extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
         std::string err;
         if (!parse_selector_json(ss.str(), &s, &err)) return fail(SPX_ERR_ARG, "selector: " + err);
     }
-    global_selector() = s;
-    if (H) {
-        H->sel = s;
-        SPX_TRY(upload_selector(H));
+    if (!H) {
+        global_selector() = s;
+        return SPX_OK;
     }
-    return SPX_OK;
+    H->sel = s;
+    return upload_selector(H);
 }
 
 // ------------------------------------------------------------------ execution
@@ -1112,6 +1116,56 @@ extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stre
     if (!H->berr) return SPX_OK;
     SPX_HIP(hipMemcpyAsync(flags, H->berr, 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
     SPX_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ breadth-first search
+extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int32_t max_levels,
+                              const spx_plan* plan, int32_t* n_levels, spx_plan* plans, int32_t plans_cap,
+                              void* stream) {
+    if (!H || !n_levels || (plans_cap > 0 && !plans)) return fail(SPX_ERR_ARG, "null argument");
+    const spx_csr& A = H->csr;
+    if (A.m != A.n) return fail(SPX_ERR_SHAPE, "breadth-first search needs a square matrix");
+    if (A.dtype != SPX_BOOL) return fail(SPX_ERR_DTYPE, "breadth-first search runs on a BOOL (pattern) handle");
+    if (A.n == 0) {
+        *n_levels = 0;
+        return SPX_OK;
+    }
+    if (!level) return fail(SPX_ERR_ARG, "level is null");
+    if (source < 0 || source >= A.n) return fail(SPX_ERR_INDEX, "source out of range");
+    if (max_levels < 1) return fail(SPX_ERR_ARG, "max_levels must be >= 1");
+    if (plan) SPX_TRY(spx_check_plan(plan, A.dtype));
+    hipStream_t s = (hipStream_t)stream;
+    if (!H->bfs_count) {
+        if (hipMalloc((void**)&H->bfs_front[0], (size_t)A.n * 4) != hipSuccess ||
+            hipMalloc((void**)&H->bfs_front[1], (size_t)A.n * 4) != hipSuccess ||
+            hipMalloc((void**)&H->bfs_y, (size_t)A.m) != hipSuccess ||
+            hipMalloc((void**)&H->bfs_count, 256) != hipSuccess)
+            return fail(SPX_ERR_ALLOC, "breadth-first search buffers: allocation failed");
+    }
+    SPX_TRY(launch_bfs_seed(A.n, source, level, H->bfs_front[0], H->bfs_count, s));
+    int cur = 0;
+    int32_t nf = 1;
+    int32_t depth = 1;  // levels assigned so far
+    while (nf > 0 && depth < max_levels) {
+        spx_vec x{SPX_VEC_SPARSE, A.n, nf, H->bfs_front[cur], nullptr};
+        spx_plan p;
+        if (plan) {
+            SPX_TRY(run_plan(H, &x, H->bfs_y, plan, stream));
+            p = *plan;
+        } else {
+            SPX_TRY(run(H, &x, H->bfs_y, stream));
+            p = H->last_plan;
+        }
+        if (depth - 1 < plans_cap) plans[depth - 1] = p;
+        SPX_TRY(fill_u32((uint32_t*)H->bfs_count, 0u, 1, s));
+        SPX_TRY(launch_bfs_update(A.n, H->bfs_y, depth, level, H->bfs_front[cur ^ 1], H->bfs_count, s));
+        SPX_HIP(hipMemcpyAsync(&nf, H->bfs_count, 4, hipMemcpyDeviceToHost, s));
+        SPX_HIP(hipStreamSynchronize(s));
+        cur ^= 1;
+        if (nf > 0) ++depth;
+    }
+    *n_levels = depth;
     return SPX_OK;
 }
 

@@ -201,6 +201,12 @@ size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz
                      size_t* zero_from, size_t* zero_bytes);
 spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev);
 
+// breadth-first search (bfs.hip)
+spx_status launch_bfs_seed(int32_t n, int32_t source, int32_t* level, int32_t* frontier, int32_t* count,
+                           hipStream_t s);
+spx_status launch_bfs_update(int32_t n, const uint8_t* y, int32_t L, int32_t* level, int32_t* next, int32_t* count,
+                             hipStream_t s);
+
 // backward (grad.hip): workspace grad_ws_bytes(m, n, B, dtype)
 size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype);
 spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,

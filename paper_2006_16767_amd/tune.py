@@ -2,6 +2,8 @@
 
     python -m paper_2006_16767_amd.tune sweep --out sweep.jsonl   # on the GPU
     python -m paper_2006_16767_amd.tune train sweep.jsonl --out selector.json
+    (sweep --dtype bool times the (OR, AND) semiring, for the trees BOOL
+    handles load)
 
 sweep  builds a synthetic corpus (uniform, R-MAT, Poisson stencil, power-law,
        Bernoulli and SVM-like feature matrices; for each, input vectors whose nnz_x grows from
@@ -94,9 +96,11 @@ def densities(n: int, count: int = 40):
     return [int(v) for v in vals]
 
 
-def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None):
+def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None, dtype: str = "f32"):
+    """dtype "f32": FP32 values; "bool": the pattern and index-only vectors
+    in the (OR, AND) semiring."""
     import torch
-    from . import Matrix, all_plans, synth
+    from . import BOOL, Matrix, all_plans, synth
 
     done = set()
     if os.path.exists(out_path):
@@ -111,7 +115,7 @@ def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None):
         for name, gen in corpus(quick):
             t0 = time.time()
             A = gen()
-            M = Matrix.from_host(A)
+            M = Matrix.from_host(A, dtype=BOOL if dtype == "bool" else None)
             mf = M.features()
             print(f"[tune] {name}: m={A.m} n={A.n} nnz={A.nnz} gen {time.time() - t0:.1f}s", flush=True)
             y = M.out_tensor()
@@ -123,7 +127,7 @@ def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None):
                     continue
                 v = synth.sparse_vector(A.n, nx, 5000 + i, lo=0.0, hi=1.0)
                 x = (torch.as_tensor(v.idx, device="cuda"),
-                     torch.as_tensor(np.asarray(v.val, np.float32), device="cuda"))
+                     None if dtype == "bool" else torch.as_tensor(np.asarray(v.val, np.float32), device="cuda"))
                 vf = M.vector_features(x)
                 times = {}
                 for p in plans:
@@ -436,13 +440,14 @@ def main(argv=None):
     s.add_argument("--out", required=True)
     s.add_argument("--reps", type=int, default=5)
     s.add_argument("--quick", action="store_true")
+    s.add_argument("--dtype", choices=("f32", "bool"), default="f32")
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--all-features", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        sweep(a.out, a.reps, a.quick)
+        sweep(a.out, a.reps, a.quick, dtype=a.dtype)
     else:
         rep = train(a.data, a.out, a.all_features)
         print(json.dumps(rep, indent=1))
