@@ -178,20 +178,21 @@ def extra_fwd_bwd(torch, spx, synth, reps=10):
 
 
 def extra_bfs(torch, spx, synth, reps=3):
-    """Breadth-first search on the R-MAT 2^20 graph (pattern), one adaptive
-    SpMSpV per level, against every level on one fixed kernel."""
+    """Breadth-first search on the R-MAT 2^20 graph (pattern): one adaptive
+    SpMSpV per level (with and without the masked-pull levels) against
+    every level on one fixed kernel."""
     import numpy as np
     A = synth.cfg2_matrix()
     M = spx.Matrix.from_host(A, dtype=spx.BOOL)
     outdeg = np.bincount(A.col_idx, minlength=A.n)
     src = 0 if outdeg[0] > 0 else int(np.nonzero(outdeg > 0)[0][0])
 
-    def timed(plan=None):
-        M.bfs(src, plan=plan)  # warm-up
+    def timed(plan=None, push_only=False):
+        M.bfs(src, plan=plan, push_only=push_only)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            level, plans = M.bfs(src, plan=plan)
+            level, plans = M.bfs(src, plan=plan, push_only=push_only)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps * 1e3, level, plans
 
@@ -201,9 +202,11 @@ def extra_bfs(torch, spx, synth, reps=3):
     out = {"workload": "rmat20_deg16_bfs", "source": src, "levels": M.bfs_levels,
            "edges_traversed": edges, "adaptive_ms": round(ms, 3),
            "adaptive_GTEPS": round(edges / (ms * 1e-3) / 1e9, 2),
-           "plans_per_level": [f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/"
+           "plans_per_level": ["masked_pull" if p.lanes == -1 else
+                               f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/"
                                f"{['direct', 'balanced'][p.distribution]}/"
                                f"{['none', 'atomic', 'sort', 'lds_atomic', 'bucket'][p.writeback]}" for p in plans],
+           "adaptive_push_only_ms": round(timed(push_only=True)[0], 3),
            "fixed_ms": {}}
     for name, p in (("spmv_balanced", spx.plan("spmv", "balanced")),
                     ("csr_spmspv_balanced", spx.plan("csr_spmspv", "balanced")),

@@ -311,17 +311,25 @@ spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void
 /* Breadth-first search over the graph of a square BOOL handle (stored entry
  * (i, j) = edge j -> i, so a column lists a vertex's out-edges): level[v] =
  * fewest edges from source, -1 if unreachable (level: device int32[n]).
- * Every level is one (OR, AND) SpMSpV of the frontier, through run() (the
- * kernel chosen per level, as the frontier's density changes; Section 7) or
- * through run_plan() with the given plan, followed by a kernel that keeps
- * the unvisited vertices, labels them and appends them to the next
- * frontier. At most max_levels levels are labelled. *n_levels = the number
- * of levels labelled (1 + the largest level). If plans is given, plans[l]
- * receives the plan of expansion l for l < plans_cap. Synchronizes the
- * stream once per level (the frontier size decides the next call). The
- * frontier and product buffers belong to the handle. */
+ * A level is one (OR, AND) SpMSpV of the frontier, through run() (the
+ * kernel chosen per level, as the frontier's density changes; Section 7)
+ * or through run_plan() with the given plan, followed by a kernel that
+ * keeps the unvisited vertices, labels them and appends them to the next
+ * frontier. Without a plan and without SPX_BFS_PUSH_ONLY, a level whose
+ * frontier's out-edges exceed the unexplored ones / 14 runs instead as a
+ * masked pull (only the rows of unvisited vertices, each stopped at its
+ * first frontier neighbour), until the frontier falls below n / 24
+ * vertices (the direction-optimizing heuristic; not part of the paper).
+ * At most max_levels levels are labelled. *n_levels = the number of levels
+ * labelled (1 + the largest level). If plans is given, plans[l] receives
+ * the plan of expansion l for l < plans_cap; a masked pull is reported as
+ * {SPX_PAT_CSR_SPMSPV, SPX_DIST_DIRECT, SPX_WB_NONE, lanes = -1}.
+ * Synchronizes the stream once per level (the frontier size decides the
+ * next call). The frontier lists and bitvectors, the product buffer and
+ * a pinned counter belong to the handle (allocated on the first call). */
+#define SPX_BFS_PUSH_ONLY 1u
 spx_status spx_bfs(spx_matrix *H, int32_t source, int32_t *level, int32_t max_levels, const spx_plan *plan,
-                   int32_t *n_levels, spx_plan *plans, int32_t plans_cap, void *stream);
+                   uint32_t flags, int32_t *n_levels, spx_plan *plans, int32_t plans_cap, void *stream);
 
 /* ---------------------------------------------------------------------
  * Backward of Y[b] = A(vals) X[b] for a loss L(Y), with G = dL/dY

@@ -295,7 +295,8 @@ class Matrix:
         _lib.call("spmv_csr_batch", self._h, B, _ptr(X2), _ptr(Y), _stream(stream))
         return Y
 
-    def bfs(self, source: int, max_levels: int = 1 << 30, plan: Plan | None = None, stream=None):
+    def bfs(self, source: int, max_levels: int = 1 << 30, plan: Plan | None = None, push_only: bool = False,
+            stream=None):
         """Breadth-first levels from source (BOOL handle; entry (i, j) is the
         edge j -> i): returns (level tensor int32[n], the plan of every
         expansion). A search that runs to completion makes one expansion per
@@ -307,8 +308,10 @@ class Matrix:
         plans = (Plan * cap)()
         for i in range(cap):
             plans[i].pattern = -1  # entries the search does not reach stay -1
+        # a masked-pull level comes back with lanes = -1
         _lib.call("spx_bfs", self._h, int(source), _ptr(level), int(max_levels),
-                  None if plan is None else C.byref(plan), C.byref(nl), plans, cap, _stream(stream))
+                  None if plan is None else C.byref(plan), _lib.BFS_PUSH_ONLY if push_only else 0, C.byref(nl),
+                  plans, cap, _stream(stream))
         self.bfs_levels = nl.value
         return level, [plans[i] for i in range(cap) if plans[i].pattern >= 0]
 

@@ -23,6 +23,7 @@ DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET = 0, 1, 2, 3, 4
 VEC_DENSE, VEC_SPARSE = 0, 1
 VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER = 1, 2, 4, 8
+BFS_PUSH_ONLY = 1
 
 
 class Plan(C.Structure):
@@ -79,7 +80,8 @@ SIGNATURES = {
     "spx_run_times": (C.c_int, [P, C.POINTER(C.c_double), _i32, C.POINTER(_i32)]),
     "run_batch": (C.c_int, [P, _i32, C.c_int64, P, P, P, P, P]),
     "spx_batch_status": (C.c_int, [P, C.POINTER(_i32), P]),
-    "spx_bfs": (C.c_int, [P, _i32, P, _i32, C.POINTER(Plan), C.POINTER(C.c_int32), C.POINTER(Plan), _i32, P]),
+    "spx_bfs": (C.c_int, [P, _i32, P, _i32, C.POINTER(Plan), C.c_uint32, C.POINTER(C.c_int32), C.POINTER(Plan),
+                          _i32, P]),
     "spmv_csr_batch": (C.c_int, [P, _i32, P, P, P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),

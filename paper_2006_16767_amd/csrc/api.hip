@@ -196,7 +196,9 @@ struct spx_matrix {
     // breadth-first search buffers (allocated on first use)
     int32_t* bfs_front[2] = {nullptr, nullptr};
     uint8_t* bfs_y = nullptr;
-    int32_t* bfs_count = nullptr;
+    int32_t* bfs_count = nullptr;     // two packed frontier counters
+    uint32_t* bfs_bits[2] = {nullptr, nullptr};
+    int32_t* bfs_host = nullptr;      // pinned copy of one counter
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -414,9 +416,11 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
-                    H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->bfs_count};
+                    H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->bfs_count,
+                    H->bfs_bits[0], H->bfs_bits[1]};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    if (H->bfs_host) hipHostFree(H->bfs_host);
     for (auto& e : H->ev_conv) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
@@ -1120,9 +1124,16 @@ extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stre
 }
 
 // ------------------------------------------------------------------ breadth-first search
+// Direction switch of the search (the direction-optimizing heuristic of
+// breadth-first search, not part of the paper): pull once the frontier's
+// out-edges exceed the unexplored edges / kPullAlpha, push again once the
+// frontier holds fewer than n / kPushBeta vertices.
+constexpr double kPullAlpha = 14.0;
+constexpr double kPushBeta = 24.0;
+
 extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int32_t max_levels,
-                              const spx_plan* plan, int32_t* n_levels, spx_plan* plans, int32_t plans_cap,
-                              void* stream) {
+                              const spx_plan* plan, uint32_t flags, int32_t* n_levels, spx_plan* plans,
+                              int32_t plans_cap, void* stream) {
     if (!H || !n_levels || (plans_cap > 0 && !plans)) return fail(SPX_ERR_ARG, "null argument");
     const spx_csr& A = H->csr;
     if (A.m != A.n) return fail(SPX_ERR_SHAPE, "breadth-first search needs a square matrix");
@@ -1136,32 +1147,62 @@ extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int
     if (max_levels < 1) return fail(SPX_ERR_ARG, "max_levels must be >= 1");
     if (plan) SPX_TRY(spx_check_plan(plan, A.dtype));
     hipStream_t s = (hipStream_t)stream;
-    if (!H->bfs_count) {
+    SPX_TRY(ensure_conv(H));
+    if (!H->bfs_host) {
+        const size_t words = (size_t)ceil_div(A.n, 32) * 4;
         if (hipMalloc((void**)&H->bfs_front[0], (size_t)A.n * 4) != hipSuccess ||
             hipMalloc((void**)&H->bfs_front[1], (size_t)A.n * 4) != hipSuccess ||
             hipMalloc((void**)&H->bfs_y, (size_t)A.m) != hipSuccess ||
-            hipMalloc((void**)&H->bfs_count, 256) != hipSuccess)
+            hipMalloc((void**)&H->bfs_count, 256) != hipSuccess ||
+            hipMalloc((void**)&H->bfs_bits[0], words) != hipSuccess ||
+            hipMalloc((void**)&H->bfs_bits[1], words) != hipSuccess ||
+            hipHostMalloc((void**)&H->bfs_host, 64, hipHostMallocDefault) != hipSuccess)
             return fail(SPX_ERR_ALLOC, "breadth-first search buffers: allocation failed");
     }
-    SPX_TRY(launch_bfs_seed(A.n, source, level, H->bfs_front[0], H->bfs_count, s));
+    const bool may_pull = !plan && !(flags & SPX_BFS_PUSH_ONLY);
+    SPX_TRY(launch_bfs_seed(A.n, source, H->col_ptr, level, H->bfs_front[0], H->bfs_bits[0], H->bfs_count, s));
+    // the counter of the level just labelled, read back through pinned memory
+    auto read_count = [&](int32_t L) -> spx_status {
+        SPX_HIP(hipMemcpyAsync(H->bfs_host, H->bfs_count + 2 * (L & 1), 8, hipMemcpyDeviceToHost, s));
+        SPX_HIP(hipStreamSynchronize(s));
+        return SPX_OK;
+    };
+    SPX_TRY(read_count(0));
     int cur = 0;
-    int32_t nf = 1;
-    int32_t depth = 1;  // levels assigned so far
+    int32_t nf = H->bfs_host[0];
+    int64_t mf = H->bfs_host[1];          // out-edges of the frontier
+    int64_t mu = (int64_t)A.nnz - mf;     // out-edges of the unvisited vertices
+    bool pull = false;
+    int32_t depth = 1;  // levels labelled so far
     while (nf > 0 && depth < max_levels) {
-        spx_vec x{SPX_VEC_SPARSE, A.n, nf, H->bfs_front[cur], nullptr};
-        spx_plan p;
-        if (plan) {
-            SPX_TRY(run_plan(H, &x, H->bfs_y, plan, stream));
-            p = *plan;
+        if (may_pull) {
+            if (!pull && (double)mf > (double)mu / kPullAlpha)
+                pull = true;
+            else if (pull && (double)nf < (double)A.n / kPushBeta)
+                pull = false;
+        }
+        spx_plan p{};
+        if (pull) {
+            SPX_TRY(launch_bfs_pull(A.n, A.row_ptr, A.col_idx, H->bfs_bits[cur], depth, H->col_ptr, level,
+                                    H->bfs_front[cur ^ 1], H->bfs_bits[cur ^ 1], H->bfs_count, s));
+            p = spx_plan{SPX_PAT_CSR_SPMSPV, SPX_DIST_DIRECT, SPX_WB_NONE, -1, 0, 0};
         } else {
-            SPX_TRY(run(H, &x, H->bfs_y, stream));
-            p = H->last_plan;
+            spx_vec x{SPX_VEC_SPARSE, A.n, nf, H->bfs_front[cur], nullptr};
+            if (plan) {
+                SPX_TRY(run_plan(H, &x, H->bfs_y, plan, stream));
+                p = *plan;
+            } else {
+                SPX_TRY(run(H, &x, H->bfs_y, stream));
+                p = H->last_plan;
+            }
+            SPX_TRY(launch_bfs_update(A.n, H->bfs_y, depth, H->col_ptr, level, H->bfs_front[cur ^ 1],
+                                      H->bfs_bits[cur ^ 1], H->bfs_count, s));
         }
         if (depth - 1 < plans_cap) plans[depth - 1] = p;
-        SPX_TRY(fill_u32((uint32_t*)H->bfs_count, 0u, 1, s));
-        SPX_TRY(launch_bfs_update(A.n, H->bfs_y, depth, level, H->bfs_front[cur ^ 1], H->bfs_count, s));
-        SPX_HIP(hipMemcpyAsync(&nf, H->bfs_count, 4, hipMemcpyDeviceToHost, s));
-        SPX_HIP(hipStreamSynchronize(s));
+        SPX_TRY(read_count(depth));
+        nf = H->bfs_host[0];
+        mf = H->bfs_host[1];
+        mu -= mf;
         cur ^= 1;
         if (nf > 0) ++depth;
     }

@@ -201,11 +201,18 @@ size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz
                      size_t* zero_from, size_t* zero_bytes);
 spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStream_t s, int32_t** err_dev);
 
-// breadth-first search (bfs.hip)
-spx_status launch_bfs_seed(int32_t n, int32_t source, int32_t* level, int32_t* frontier, int32_t* count,
-                           hipStream_t s);
-spx_status launch_bfs_update(int32_t n, const uint8_t* y, int32_t L, int32_t* level, int32_t* next, int32_t* count,
-                             hipStream_t s);
+// breadth-first search (bfs.hip). count points at two packed 64-bit
+// frontier counters {vertices (low half), their out-degrees (high half)},
+// read on the host as two int32 words (little-endian); level L appends
+// into count[L & 1] and clears the other. The bitvectors hold
+// ceil(n / 32) words.
+spx_status launch_bfs_seed(int32_t n, int32_t source, const int32_t* col_ptr, int32_t* level, int32_t* frontier,
+                           uint32_t* bits, void* count, hipStream_t s);
+spx_status launch_bfs_update(int32_t n, const uint8_t* y, int32_t L, const int32_t* col_ptr, int32_t* level,
+                             int32_t* next, uint32_t* next_bits, void* count, hipStream_t s);
+spx_status launch_bfs_pull(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint32_t* bits,
+                           int32_t L, const int32_t* col_ptr, int32_t* level, int32_t* next, uint32_t* next_bits,
+                           void* count, hipStream_t s);
 
 // backward (grad.hip): workspace grad_ws_bytes(m, n, B, dtype)
 size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype);

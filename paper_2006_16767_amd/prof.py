@@ -174,6 +174,22 @@ def cmd_fc(args):
     print(f"[prof] FC layer 16384 x 4096: {args.reps + 1} forward + backward passes done", flush=True)
 
 
+def cmd_bfs(args):
+    import numpy as np
+    import torch
+    from . import BOOL, Matrix
+    from . import synth
+    A = synth.cfg2_matrix()
+    M = Matrix.from_host(A, dtype=BOOL)
+    outdeg = np.bincount(A.col_idx, minlength=A.n)
+    src = 0 if outdeg[0] > 0 else int(np.nonzero(outdeg > 0)[0][0])
+    for _ in range(args.reps + 1):
+        _, plans = M.bfs(src, push_only=args.push_only)
+    torch.cuda.synchronize()
+    print(f"[prof] breadth-first search on R-MAT 2^20 from {src}: {M.bfs_levels} levels, "
+          f"{sum(p.lanes == -1 for p in plans)} pull levels, {args.reps + 1} searches done", flush=True)
+
+
 def cmd_copy(args):
     import torch
     n = args.mib * (1 << 20) // 4
@@ -264,6 +280,9 @@ def main(argv=None):
     a.add_argument("--reps", type=int, default=5)
     a = sub.add_parser("fc")
     a.add_argument("--reps", type=int, default=5)
+    a = sub.add_parser("bfs")
+    a.add_argument("--reps", type=int, default=3)
+    a.add_argument("--push-only", action="store_true")
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=512)
     a.add_argument("--reps", type=int, default=3)
@@ -279,7 +298,7 @@ def main(argv=None):
     a.add_argument("--vector", type=int, required=True)
     a.add_argument("--command", action="append")
     args = ap.parse_args(argv)
-    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "copy": cmd_copy, "kernels": cmd_kernels,
+    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "bfs": cmd_bfs, "copy": cmd_copy, "kernels": cmd_kernels,
      "traffic": cmd_traffic}[args.cmd](args)
 
 

@@ -30,17 +30,42 @@ def _source(A):
     return 0 if outdeg[0] > 0 else int(np.nonzero(outdeg > 0)[0][0])
 
 
+@pytest.mark.parametrize("push_only", [False, True])
 @pytest.mark.parametrize("name", ["rmat16", "cfg2"])
-def test_bfs_adaptive_matches_oracle(name):
+def test_bfs_adaptive_matches_oracle(name, push_only):
     _torch()
     A = cfg_matrix(name)
     M = spx.Matrix.from_host(A, dtype=spx.BOOL)
     s = _source(A)
-    level, plans = M.bfs(s)
+    level, plans = M.bfs(s, push_only=push_only)
     want = oracle.bfs_levels(*_edges(A), A.n, s)
     assert np.array_equal(level.cpu().numpy(), want)
     assert M.bfs_levels == int(want.max()) + 1
     assert len(plans) == M.bfs_levels  # the last expansion finds no new vertex
+    pulls = sum(p.lanes == -1 for p in plans)
+    if push_only:
+        assert pulls == 0
+    elif name == "cfg2":
+        assert pulls > 0  # the dense middle levels of the R-MAT search pull
+
+
+def test_bfs_pull_on_graphs_with_unreachable_parts():
+    """Several components and sinks: the masked pull must leave every
+    vertex outside the source's reach at -1 and stop rows at the first
+    frontier neighbour without skipping any level."""
+    _torch()
+    rng = np.random.default_rng(3)
+    n = 20000
+    src = rng.integers(0, n // 2, 120000).astype(np.int32)  # edges only among the first half
+    dst = rng.integers(0, n // 2, 120000).astype(np.int32)
+    key = np.unique(dst.astype(np.int64) * n + src)
+    A = synth._coo_to_csr(n, n, key // n, key % n, None)
+    M = spx.Matrix.from_host(A, dtype=spx.BOOL)
+    s = int(src[0])
+    want = oracle.bfs_levels(A.col_idx, np.repeat(np.arange(n), np.diff(A.row_ptr)).astype(np.int32), n, s)
+    level, plans = M.bfs(s)
+    assert np.array_equal(level.cpu().numpy(), want)
+    assert any(p.lanes == -1 for p in plans)
 
 
 def test_bfs_every_fixed_plan_matches_oracle():
