@@ -8,6 +8,8 @@ Matrices are passed as any object with attributes m, n, row_ptr (int32),
 col_idx (int32) and vals (or as explicit arrays). Floating-point inputs
 are widened to float64 before the call; every sum is Neumaier-compensated
 in float64 and returned with S_i = sum |a_ij x_j| over the same terms.
+The PageRank driver (pagerank_incremental) is a numpy loop over the
+oracle's own product. Every function is pinned by the CPU tests.
 """
 from __future__ import annotations
 
@@ -212,3 +214,45 @@ def bfs_step(src, dst, n, m, active_idx):
     nxt = np.empty(m, np.uint8)
     _check(lib.oracle_bfs_step(src.size, src, dst, n, act, m, nxt), "oracle_bfs_step")
     return nxt
+
+
+def pagerank_incremental(A, damping, eps, max_iters):
+    """Incremental (residual-push) PageRank, the second application of the
+    paper's evaluation (Section 7), in float64.
+
+    Stored entry (i, j) is an edge j -> i of weight a_ij >= 0; a walk
+    leaves j along (i, j) with probability a_ij / W_j, W_j = the sum of
+    column j (W_j = 0: j is dangling and its mass leaves the graph). The
+    fixed point p solves p = (1 - d)/n * 1 + d * P p, P = A diag(1/W).
+
+    Residual form: r starts at (1 - d)/n everywhere and p at 0. Each
+    round, the active vertices (|r_v| > eps) move r_v into p_v; those that
+    are not dangling form the sparse input x_v = r_v / W_v of one product
+    y = A x; their residual is cleared and r += d * y. The rounds stop
+    when no active vertex can propagate or after max_iters products.
+
+    Returns (p, r, products). At any stop, p + (I - d P)^-1 r is the fixed
+    point, and when the loop ends by itself every |r_v| <= eps except on
+    vertices that are dangling, whose residual was moved (so they are 0)."""
+    n = A.n
+    assert A.m == n, "PageRank needs a square matrix"
+    d = float(damping)
+    vals = _f64(A.vals)
+    W = np.zeros(n)
+    np.add.at(W, _i32(A.col_idx), vals)
+    r = np.full(n, (1.0 - d) / n)
+    p = np.zeros(n)
+    products = 0
+    while products < max_iters:
+        active = np.abs(r) > eps
+        p[active] += r[active]
+        prop = active & (W > 0)
+        x = np.zeros(n)
+        x[prop] = r[prop] / W[prop]
+        r[active] = 0.0
+        if not prop.any():
+            break
+        y, _ = spmv(A, x)
+        r += d * y
+        products += 1
+    return p, r, products

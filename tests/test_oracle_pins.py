@@ -477,3 +477,96 @@ def test_bfs_levels_vs_scipy_shortest_path():
             want = np.where(np.isinf(want), -1, want).astype(np.int64)
             got = oracle.bfs_levels(src, dst, n, s)
             assert np.array_equal(got, want), (n, deg, s)
+
+
+# ---------------------------------------------------------------- PageRank
+def _pr_dense(A, d):
+    """I - d P as a dense matrix, P = A diag(1/W) (dangling columns zero)."""
+    n = A.n
+    D = np.zeros((n, n))
+    for i in range(A.m):
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            D[i, A.col_idx[k]] += A.vals[k]
+    W = D.sum(0)
+    P = np.divide(D, W, out=np.zeros_like(D), where=W > 0)
+    return np.eye(n) - d * P
+
+
+def test_pagerank_hand_worked():
+    d = 0.85
+    # one edge 0 -> 1, vertex 1 dangling: p0 = (1 - d)/2, p1 = (1 - d)/2 + d p0,
+    # reached after one product and a last round that only moves r1
+    A = _mat(2, 2, [0, 0, 1], [0], [0.5])
+    p, r, k = oracle.pagerank_incremental(A, d, 0.0, 100)
+    assert k == 1
+    assert np.allclose(p, [(1 - d) / 2, (1 - d) / 2 * (1 + d)], rtol=1e-15, atol=0)
+    assert np.all(r == 0)
+    # a directed 3-cycle: P is a permutation, so p = 1/3 everywhere
+    A = _mat(3, 3, [0, 1, 2, 3], [2, 0, 1], [1.0, 2.0, 3.0])
+    p, r, k = oracle.pagerank_incremental(A, d, 0.0, 400)
+    assert k == 400
+    assert np.allclose(p, 1 / 3, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pagerank_fixed_point_by_dense_solve(seed):
+    """eps = 0: after k products the error is at most d^k / (1 - d) * sum r0,
+    so 400 products reach the dense solve of (I - d P) p = (1 - d)/n to
+    rounding; weighted edges, dangling and isolated vertices included."""
+    A = synth.random_csr(60, 60, 0.06, 900 + seed, empty_rows=0.1)
+    A = A.with_vals(np.abs(np.asarray(A.vals, np.float64)) + 0.1)
+    d = 0.85
+    p, r, k = oracle.pagerank_incremental(A, d, 0.0, 400)
+    want = np.linalg.solve(_pr_dense(A, d), np.full(A.n, (1 - d) / A.n))
+    assert np.allclose(p, want, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("eps_scale", [1e-1, 1e-3])
+def test_pagerank_threshold_residual_identity(eps_scale):
+    """eps > 0: the loop stops with every |r_v| <= eps, p below the fixed
+    point, and p + (I - d P)^-1 r equal to it (the residual identity)."""
+    A = synth.random_csr(80, 80, 0.05, 77, empty_rows=0.05)
+    A = A.with_vals(np.abs(np.asarray(A.vals, np.float64)) + 0.05)
+    d = 0.85
+    eps = eps_scale * (1 - d) / A.n
+    p, r, k = oracle.pagerank_incremental(A, d, eps, 10 ** 6)
+    M = _pr_dense(A, d)
+    want = np.linalg.solve(M, np.full(A.n, (1 - d) / A.n))
+    assert k > 1
+    assert np.all(np.abs(r) <= eps)
+    assert np.all(p <= want + 1e-15)
+    assert np.allclose(p + np.linalg.solve(M, r), want, rtol=1e-12, atol=1e-15)
+    # and the unfinished state after a few products obeys the same identity
+    p3, r3, k3 = oracle.pagerank_incremental(A, d, eps, 3)
+    assert k3 == 3
+    assert np.allclose(p3 + np.linalg.solve(M, r3), want, rtol=1e-12, atol=1e-15)
+
+
+def test_pagerank_pins_catch_planted_mistakes(monkeypatch):
+    """Mistakes planted in the oracle: a transposed product, and weights
+    normalized by the out-degree instead of the column weight sum. The
+    dense-solve pin fails on each."""
+    A = synth.random_csr(40, 40, 0.1, 5, empty_rows=0.0)
+    A = A.with_vals(np.abs(np.asarray(A.vals, np.float64)) + 0.1)
+    d = 0.85
+    want = np.linalg.solve(_pr_dense(A, d), np.full(A.n, (1 - d) / A.n))
+    p, _, _ = oracle.pagerank_incremental(A, d, 0.0, 400)
+    assert np.allclose(p, want, rtol=1e-12)
+
+    good_spmv = oracle.spmv
+    T = synth._coo_to_csr(A.n, A.m, np.asarray(A.col_idx, np.int64),
+                          np.repeat(np.arange(A.m), np.diff(A.row_ptr)), np.asarray(A.vals, np.float64))
+    with monkeypatch.context() as mp:
+        mp.setattr(oracle, "spmv", lambda M, x: good_spmv(T, x))
+        p, _, _ = oracle.pagerank_incremental(A, d, 0.0, 400)
+    assert not np.allclose(p, want, rtol=1e-6)
+
+    class _Np:
+        def __getattr__(self, k):
+            return getattr(np, k)
+    shim = _Np()
+    shim.add = SimpleNamespace(at=lambda W, idx, v: np.add.at(W, idx, 1.0))
+    with monkeypatch.context() as mp:
+        mp.setattr(oracle, "np", shim)
+        p, _, _ = oracle.pagerank_incremental(A, d, 0.0, 400)
+    assert not np.allclose(p, want, rtol=1e-6)
