@@ -331,6 +331,30 @@ spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void
 spx_status spx_bfs(spx_matrix *H, int32_t source, int32_t *level, int32_t max_levels, const spx_plan *plan,
                    uint32_t flags, int32_t *n_levels, spx_plan *plans, int32_t plans_cap, void *stream);
 
+/* Incremental (residual-push) PageRank over the graph of a square F32 or
+ * F64 handle (the second application of Section 7): stored entry (i, j) is
+ * an edge j -> i of weight a_ij >= 0 (SPX_ERR_ARG on a negative weight);
+ * the walk leaves j along (i, j) with probability a_ij / W_j, W_j = sum of
+ * column j, and a vertex with W_j = 0 is dangling (its mass leaves the
+ * graph). The fixed point p solves p = (1 - d)/n + d A diag(1/W) p.
+ * Residual r starts at (1 - d)/n, p at 0. Each round moves every residual
+ * with |r_v| > eps into p_v and clears it; the active vertices that are not
+ * dangling form the sparse input x_v = r_v / W_v of one product y = A x
+ * (through run(), or run_plan() with the given plan), and r += d y. The
+ * rounds stop when no active vertex can propagate, or after max_iters
+ * products (then the last product is folded into r too). At any stop
+ * p + (I - d A diag(1/W))^-1 r is the fixed point.
+ * damping in [0, 1), eps >= 0, max_iters >= 0. rank (required) and
+ * residual (optional): device arrays of n values of the handle's type,
+ * written by the call. *n_iters = the number of products; plans[k]
+ * receives the plan of product k for k < plans_cap. Synchronizes the
+ * stream once per round. The column sums are computed on the first call
+ * and again after spx_matrix_values_updated; the work buffers belong to
+ * the handle. */
+spx_status spx_pagerank(spx_matrix *H, double damping, double eps, int32_t max_iters, const spx_plan *plan,
+                        void *rank, void *residual, int32_t *n_iters, spx_plan *plans, int32_t plans_cap,
+                        void *stream);
+
 /* ---------------------------------------------------------------------
  * Backward of Y[b] = A(vals) X[b] for a loss L(Y), with G = dL/dY
  * (B x m) and X (B x n), both dense, row-major, on the device:

@@ -315,6 +315,29 @@ class Matrix:
         self.bfs_levels = nl.value
         return level, [plans[i] for i in range(cap) if plans[i].pattern >= 0]
 
+    def pagerank(self, damping: float = 0.85, eps: float | None = None, max_iters: int = 10000,
+                 plan: Plan | None = None, want_residual: bool = False, stream=None):
+        """Incremental (residual-push) PageRank on an F32/F64 handle (entry
+        (i, j) = edge j -> i of weight a_ij >= 0). eps defaults to
+        1e-3 (1 - damping) / n. Returns (rank, plans) or, with want_residual,
+        (rank, residual, plans); self.pr_iters = the number of products."""
+        if eps is None:
+            eps = 1e-3 * (1.0 - damping) / max(1, self.n)
+        self.sync_values(stream=stream)
+        rank = self.out_tensor()
+        res = self.out_tensor() if want_residual else None
+        ni = C.c_int32(0)
+        cap = 4096
+        plans = (Plan * cap)()
+        for i in range(cap):
+            plans[i].pattern = -1
+        _lib.call("spx_pagerank", self._h, float(damping), float(eps), int(max_iters),
+                  None if plan is None else C.byref(plan), _ptr(rank), None if res is None else _ptr(res),
+                  C.byref(ni), plans, cap, _stream(stream))
+        self.pr_iters = ni.value
+        out = [plans[i] for i in range(cap) if plans[i].pattern >= 0]
+        return (rank, res, out) if want_residual else (rank, out)
+
     def batch_status(self, stream=None) -> int:
         f = C.c_int32()
         _lib.call("spx_batch_status", self._h, C.byref(f), _stream(stream))

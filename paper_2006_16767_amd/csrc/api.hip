@@ -196,9 +196,18 @@ struct spx_matrix {
     // breadth-first search buffers (allocated on first use)
     int32_t* bfs_front[2] = {nullptr, nullptr};
     uint8_t* bfs_y = nullptr;
-    int32_t* bfs_count = nullptr;     // two packed frontier counters
+    int32_t* drv_count = nullptr;     // two packed counters of the graph drivers
     uint32_t* bfs_bits[2] = {nullptr, nullptr};
-    int32_t* bfs_host = nullptr;      // pinned copy of one counter
+    int32_t* drv_host = nullptr;      // pinned copy of one counter
+    // incremental PageRank: column sums (valid for the current values),
+    // residual, product, sparse input, negative-weight flag
+    void* pr_W = nullptr;
+    void* pr_r = nullptr;
+    void* pr_y = nullptr;
+    int32_t* pr_xidx = nullptr;
+    void* pr_xval = nullptr;
+    uint32_t* pr_bad = nullptr;
+    bool pr_W_valid = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -416,11 +425,12 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
-                    H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->bfs_count,
-                    H->bfs_bits[0], H->bfs_bits[1]};
+                    H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->drv_count,
+                    H->bfs_bits[0], H->bfs_bits[1], H->pr_W, H->pr_r, H->pr_y, H->pr_xidx, H->pr_xval,
+                    H->pr_bad};
     for (void* p : ptrs)
         if (p) hipFree(p);
-    if (H->bfs_host) hipHostFree(H->bfs_host);
+    if (H->drv_host) hipHostFree(H->drv_host);
     for (auto& e : H->ev_conv) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
@@ -632,6 +642,7 @@ extern "C" spx_status spx_matrix_csc(const spx_matrix* H, spx_csc* out) {
 extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     if (!H) return fail(SPX_ERR_ARG, "handle is null");
     const int vs = value_size(H->csr.dtype);
+    H->pr_W_valid = false;
     if (vs == 0 || H->csr.nnz == 0) return SPX_OK;
     SPX_TRY(gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
@@ -1123,6 +1134,26 @@ extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stre
     return SPX_OK;
 }
 
+// ------------------------------------------------------------------ graph drivers
+static spx_status ensure_driver_counters(spx_matrix* H) {
+    if (H->drv_host) return SPX_OK;
+    if (!H->drv_count && hipMalloc((void**)&H->drv_count, 256) != hipSuccess)
+        return fail(SPX_ERR_ALLOC, "driver counters: allocation failed");
+    if (hipHostMalloc((void**)&H->drv_host, 64, hipHostMallocDefault) != hipSuccess) {
+        H->drv_host = nullptr;
+        return fail(SPX_ERR_ALLOC, "driver counters: pinned allocation failed");
+    }
+    return SPX_OK;
+}
+
+// Copies counter (round & 1) to the pinned host words drv_host[0..1] and
+// waits for it.
+static spx_status read_driver_counter(spx_matrix* H, int32_t round, hipStream_t s) {
+    SPX_HIP(hipMemcpyAsync(H->drv_host, H->drv_count + 2 * (round & 1), 8, hipMemcpyDeviceToHost, s));
+    SPX_HIP(hipStreamSynchronize(s));
+    return SPX_OK;
+}
+
 // ------------------------------------------------------------------ breadth-first search
 // Direction switch of the search (the direction-optimizing heuristic of
 // breadth-first search, not part of the paper): pull once the frontier's
@@ -1148,29 +1179,23 @@ extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int
     if (plan) SPX_TRY(spx_check_plan(plan, A.dtype));
     hipStream_t s = (hipStream_t)stream;
     SPX_TRY(ensure_conv(H));
-    if (!H->bfs_host) {
+    SPX_TRY(ensure_driver_counters(H));
+    if (!H->bfs_y) {
         const size_t words = (size_t)ceil_div(A.n, 32) * 4;
         if (hipMalloc((void**)&H->bfs_front[0], (size_t)A.n * 4) != hipSuccess ||
             hipMalloc((void**)&H->bfs_front[1], (size_t)A.n * 4) != hipSuccess ||
-            hipMalloc((void**)&H->bfs_y, (size_t)A.m) != hipSuccess ||
-            hipMalloc((void**)&H->bfs_count, 256) != hipSuccess ||
             hipMalloc((void**)&H->bfs_bits[0], words) != hipSuccess ||
             hipMalloc((void**)&H->bfs_bits[1], words) != hipSuccess ||
-            hipHostMalloc((void**)&H->bfs_host, 64, hipHostMallocDefault) != hipSuccess)
+            hipMalloc((void**)&H->bfs_y, (size_t)A.m) != hipSuccess)
             return fail(SPX_ERR_ALLOC, "breadth-first search buffers: allocation failed");
     }
     const bool may_pull = !plan && !(flags & SPX_BFS_PUSH_ONLY);
-    SPX_TRY(launch_bfs_seed(A.n, source, H->col_ptr, level, H->bfs_front[0], H->bfs_bits[0], H->bfs_count, s));
-    // the counter of the level just labelled, read back through pinned memory
-    auto read_count = [&](int32_t L) -> spx_status {
-        SPX_HIP(hipMemcpyAsync(H->bfs_host, H->bfs_count + 2 * (L & 1), 8, hipMemcpyDeviceToHost, s));
-        SPX_HIP(hipStreamSynchronize(s));
-        return SPX_OK;
-    };
+    SPX_TRY(launch_bfs_seed(A.n, source, H->col_ptr, level, H->bfs_front[0], H->bfs_bits[0], H->drv_count, s));
+    auto read_count = [&](int32_t L) { return read_driver_counter(H, L, s); };
     SPX_TRY(read_count(0));
     int cur = 0;
-    int32_t nf = H->bfs_host[0];
-    int64_t mf = H->bfs_host[1];          // out-edges of the frontier
+    int32_t nf = H->drv_host[0];
+    int64_t mf = H->drv_host[1];          // out-edges of the frontier
     int64_t mu = (int64_t)A.nnz - mf;     // out-edges of the unvisited vertices
     bool pull = false;
     int32_t depth = 1;  // levels labelled so far
@@ -1184,7 +1209,7 @@ extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int
         spx_plan p{};
         if (pull) {
             SPX_TRY(launch_bfs_pull(A.n, A.row_ptr, A.col_idx, H->bfs_bits[cur], depth, H->col_ptr, level,
-                                    H->bfs_front[cur ^ 1], H->bfs_bits[cur ^ 1], H->bfs_count, s));
+                                    H->bfs_front[cur ^ 1], H->bfs_bits[cur ^ 1], H->drv_count, s));
             p = spx_plan{SPX_PAT_CSR_SPMSPV, SPX_DIST_DIRECT, SPX_WB_NONE, -1, 0, 0};
         } else {
             spx_vec x{SPX_VEC_SPARSE, A.n, nf, H->bfs_front[cur], nullptr};
@@ -1196,17 +1221,105 @@ extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int
                 p = H->last_plan;
             }
             SPX_TRY(launch_bfs_update(A.n, H->bfs_y, depth, H->col_ptr, level, H->bfs_front[cur ^ 1],
-                                      H->bfs_bits[cur ^ 1], H->bfs_count, s));
+                                      H->bfs_bits[cur ^ 1], H->drv_count, s));
         }
         if (depth - 1 < plans_cap) plans[depth - 1] = p;
         SPX_TRY(read_count(depth));
-        nf = H->bfs_host[0];
-        mf = H->bfs_host[1];
+        nf = H->drv_host[0];
+        mf = H->drv_host[1];
         mu -= mf;
         cur ^= 1;
         if (nf > 0) ++depth;
     }
     *n_levels = depth;
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ incremental PageRank
+extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, int32_t max_iters,
+                                   const spx_plan* plan, void* rank, void* residual, int32_t* n_iters,
+                                   spx_plan* plans, int32_t plans_cap, void* stream) {
+    if (!H || !n_iters || (plans_cap > 0 && !plans)) return fail(SPX_ERR_ARG, "null argument");
+    const spx_csr& A = H->csr;
+    if (A.m != A.n) return fail(SPX_ERR_SHAPE, "PageRank needs a square matrix");
+    if (A.dtype != SPX_F32 && A.dtype != SPX_F64) return fail(SPX_ERR_DTYPE, "PageRank runs on an F32 or F64 handle");
+    if (!(damping >= 0.0 && damping < 1.0)) return fail(SPX_ERR_ARG, "damping must lie in [0, 1)");
+    if (!(eps >= 0.0)) return fail(SPX_ERR_ARG, "eps must be >= 0");
+    if (max_iters < 0) return fail(SPX_ERR_ARG, "max_iters must be >= 0");
+    *n_iters = 0;
+    if (A.n == 0) return SPX_OK;
+    if (!rank) return fail(SPX_ERR_ARG, "rank is null");
+    if (plan) SPX_TRY(spx_check_plan(plan, A.dtype));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t vbytes = (size_t)A.n * value_size(A.dtype);
+    SPX_TRY(ensure_conv(H));
+    SPX_TRY(ensure_driver_counters(H));
+    if (!H->pr_r) {
+        if (hipMalloc(&H->pr_W, vbytes) != hipSuccess || hipMalloc(&H->pr_r, vbytes) != hipSuccess ||
+            hipMalloc(&H->pr_y, vbytes) != hipSuccess ||
+            hipMalloc((void**)&H->pr_xidx, (size_t)A.n * 4) != hipSuccess ||
+            hipMalloc(&H->pr_xval, vbytes) != hipSuccess || hipMalloc((void**)&H->pr_bad, 4) != hipSuccess) {
+            H->pr_r = nullptr;
+            return fail(SPX_ERR_ALLOC, "PageRank buffers: allocation failed");
+        }
+    }
+    PrArgs a;
+    a.dtype = A.dtype;
+    a.n = A.n;
+    a.damping = damping;
+    a.eps = eps;
+    a.col_ptr = H->col_ptr;
+    a.vals_csc = H->vals_csc;
+    a.bad = H->pr_bad;
+    a.W = H->pr_W;
+    a.r = H->pr_r;
+    a.p = rank;
+    a.x_idx = H->pr_xidx;
+    a.x_val = H->pr_xval;
+    a.count = H->drv_count;
+    if (!H->pr_W_valid) {
+        SPX_TRY(fill_u32(H->pr_bad, 0u, 1, s));
+        a.stage = PR_COLSUM;
+        SPX_TRY(launch_pagerank(a, s));
+        SPX_HIP(hipMemcpyAsync(H->drv_host, H->pr_bad, 4, hipMemcpyDeviceToHost, s));
+        SPX_HIP(hipStreamSynchronize(s));
+        if (H->drv_host[0]) return fail(SPX_ERR_ARG, "PageRank needs nonnegative edge weights");
+        H->pr_W_valid = true;
+    }
+    a.stage = PR_INIT;
+    SPX_TRY(launch_pagerank(a, s));
+    SPX_TRY(fill_u32((uint32_t*)H->drv_count, 0u, 4, s));
+    int32_t it = 0;
+    bool pending = false;  // a product not yet folded into r
+    for (int32_t round = 0; it < max_iters; ++round) {
+        a.stage = PR_SELECT;
+        a.round = round;
+        a.y = round ? H->pr_y : nullptr;
+        SPX_TRY(launch_pagerank(a, s));
+        pending = false;
+        SPX_TRY(read_driver_counter(H, round, s));
+        const int32_t nx = H->drv_host[0];
+        if (nx == 0) break;
+        spx_vec x{SPX_VEC_SPARSE, A.n, nx, H->pr_xidx, H->pr_xval};
+        spx_plan p{};
+        if (plan) {
+            SPX_TRY(run_plan(H, &x, H->pr_y, plan, stream));
+            p = *plan;
+        } else {
+            SPX_TRY(run(H, &x, H->pr_y, stream));
+            p = H->last_plan;
+        }
+        if (it < plans_cap) plans[it] = p;
+        ++it;
+        pending = true;
+    }
+    if (pending) {
+        a.stage = PR_FOLD;
+        a.y = H->pr_y;
+        SPX_TRY(launch_pagerank(a, s));
+    }
+    if (residual) SPX_HIP(hipMemcpyAsync(residual, H->pr_r, vbytes, hipMemcpyDeviceToDevice, s));
+    *n_iters = it;
     return SPX_OK;
 }
 

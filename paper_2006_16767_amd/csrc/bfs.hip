@@ -12,15 +12,10 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "frontier.hpp"
 #include "internal.hpp"
 
 namespace spx {
-
-// The frontier counter is one 64-bit word: the low half counts the
-// vertices appended to the next frontier, the high half sums their
-// out-degrees (column lengths). Neither half can carry into the other
-// (both stay below 2^31), so one atomic add updates both.
-using Count = unsigned long long;
 
 // Two counters alternate between levels: level L appends into count[L & 1]
 // and clears the other one for level L + 1 (the host has read it before
@@ -43,43 +38,6 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed(int32_t n, int32_t source, 
         count[0] = ((Count)(uint32_t)(col_ptr[source + 1] - col_ptr[source]) << 32) | 1ull;
         count[1] = 0;
     }
-}
-
-// Vertices per thread of the update and pull kernels: a workgroup owns
-// kChunk consecutive vertices and appends the ones it labels with a single
-// atomic on the counter (one atomic per wave, on the same word, costs more
-// than the rest of a level on a large frontier).
-constexpr int kVpt = 8;
-constexpr int kChunk = kBlock * kVpt;
-
-// Thread t holds the candidates v0 + j for the set bits j of mask, with
-// their summed out-degree deg. The workgroup reserves one range of the
-// next frontier and writes its vertices there in ascending order.
-// Contains __syncthreads; every thread of the workgroup must call it.
-__device__ __forceinline__ void block_append(uint32_t mask, int64_t v0, uint32_t deg, int32_t* __restrict__ next,
-                                             Count* __restrict__ count, Count* tmp) {
-    const Count mine = ((Count)deg << 32) | (Count)__popc(mask);
-    Count total;
-    const Count incl = block_incl_scan<Count>(mine, tmp, &total);
-    __shared__ Count base;
-    if (threadIdx.x == 0) base = (uint32_t)total ? atomicAdd(count, total) : 0ull;
-    __syncthreads();
-    uint32_t slot = (uint32_t)base + (uint32_t)(incl - mine);
-    while (mask) {
-        const int j = __ffs(mask) - 1;
-        mask &= mask - 1;
-        next[slot++] = (int32_t)(v0 + j);
-    }
-    __syncthreads();  // base is reused by the next chunk
-}
-
-// Writes the next frontier's bitvector for the 8 consecutive vertices
-// v0.. of every thread (v0 a multiple of 8): the four threads of one
-// 32-bit word are neighbouring lanes. Every lane of the wave must call it.
-__device__ __forceinline__ void write_bits(uint32_t mask8, int64_t v0, int32_t n, uint32_t* __restrict__ bits) {
-    const uint32_t b1 = __shfl_down(mask8, 1, kWave), b2 = __shfl_down(mask8, 2, kWave),
-                   b3 = __shfl_down(mask8, 3, kWave);
-    if ((threadIdx.x & 3) == 0 && v0 < n) bits[v0 >> 5] = mask8 | b1 << 8 | b2 << 16 | b3 << 24;
 }
 
 // Vertices reached by the product and not labelled yet get level L and go

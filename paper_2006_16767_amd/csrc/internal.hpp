@@ -214,6 +214,29 @@ spx_status launch_bfs_pull(int32_t n, const int32_t* row_ptr, const int32_t* col
                            int32_t L, const int32_t* col_ptr, int32_t* level, int32_t* next, uint32_t* next_bits,
                            void* count, hipStream_t s);
 
+// incremental PageRank (pagerank.hip): one launch per stage. count: two
+// packed counters as for breadth-first search, {entries appended to x,
+// active vertices}; round s appends into count[s & 1], clears the other.
+enum PrStage { PR_COLSUM, PR_INIT, PR_SELECT, PR_FOLD };
+struct PrArgs {
+    int stage = PR_INIT;
+    int dtype = SPX_F32;
+    int32_t n = 0;
+    int32_t round = 0;
+    double damping = 0.85, eps = 0.0;
+    const int32_t* col_ptr = nullptr;  // COLSUM
+    const void* vals_csc = nullptr;    // COLSUM
+    uint32_t* bad = nullptr;           // COLSUM: bit 0 = negative weight
+    void* W = nullptr;                 // column sums
+    void* r = nullptr;                 // residual
+    void* p = nullptr;                 // rank
+    const void* y = nullptr;           // last product (nullptr on round 0)
+    int32_t* x_idx = nullptr;          // next product's input
+    void* x_val = nullptr;
+    void* count = nullptr;
+};
+spx_status launch_pagerank(const PrArgs& a, hipStream_t s);
+
 // backward (grad.hip): workspace grad_ws_bytes(m, n, B, dtype)
 size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype);
 spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
