@@ -177,6 +177,48 @@ def extra_fwd_bwd(torch, spx, synth, reps=10):
             "dx_pct_unique": round(pct(dx_u, t_dx), 2), "dvals_pct": round(pct(dv_b, t_dv), 2)}
 
 
+def _plan_str(p):
+    if p.lanes == -1:
+        return "masked_pull"
+    return (f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/{['direct', 'balanced'][p.distribution]}/"
+            f"{['none', 'atomic', 'sort', 'lds_atomic', 'bucket'][p.writeback]}")
+
+
+def extra_pagerank(torch, spx, synth, reps=3):
+    """Incremental PageRank on the R-MAT 2^20 graph (FP32 weights U[0, 1],
+    damping 0.85, eps = 1e-3 (1 - d) / n): one adaptive SpMSpV per round as
+    the active set thins out, against every round on one fixed kernel."""
+    A = synth.cfg2_matrix()
+    M = spx.Matrix.from_host(A)
+    d = 0.85
+    eps = 1e-3 * (1 - d) / A.n
+
+    def timed(plan=None):
+        M.pagerank(d, eps, plan=plan)  # warm-up (and the column sums)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, plans = M.pagerank(d, eps, plan=plan)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3, plans
+
+    ms, plans = timed()
+    used = {}
+    for p in plans:
+        used[_plan_str(p)] = used.get(_plan_str(p), 0) + 1
+    out = {"workload": "rmat20_deg16_pagerank", "damping": d, "eps": eps, "products": M.pr_iters,
+           "adaptive_ms": round(ms, 3), "ms_per_product": round(ms / max(1, M.pr_iters), 4),
+           "plans_used": used, "fixed_ms": {}}
+    for name, p in (("spmv_balanced", spx.plan("spmv", "balanced")),
+                    ("csr_spmspv_balanced", spx.plan("csr_spmspv", "balanced")),
+                    ("csc_balanced_atomic", spx.plan("csc_spmspv", "balanced", "atomic")),
+                    ("csc_direct_atomic", spx.plan("csc_spmspv", "direct", "atomic"))):
+        out["fixed_ms"][name] = round(timed(p)[0], 3)
+    best = min(out["fixed_ms"].values())
+    out["adaptive_speedup_vs_best_fixed"] = round(best / ms, 2)
+    return out
+
+
 def extra_bfs(torch, spx, synth, reps=3):
     """Breadth-first search on the R-MAT 2^20 graph (pattern): one adaptive
     SpMSpV per level (with and without the masked-pull levels) against
@@ -202,10 +244,7 @@ def extra_bfs(torch, spx, synth, reps=3):
     out = {"workload": "rmat20_deg16_bfs", "source": src, "levels": M.bfs_levels,
            "edges_traversed": edges, "adaptive_ms": round(ms, 3),
            "adaptive_GTEPS": round(edges / (ms * 1e-3) / 1e9, 2),
-           "plans_per_level": ["masked_pull" if p.lanes == -1 else
-                               f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/"
-                               f"{['direct', 'balanced'][p.distribution]}/"
-                               f"{['none', 'atomic', 'sort', 'lds_atomic', 'bucket'][p.writeback]}" for p in plans],
+           "plans_per_level": [_plan_str(p) for p in plans],
            "adaptive_push_only_ms": round(timed(push_only=True)[0], 3),
            "fixed_ms": {}}
     for name, p in (("spmv_balanced", spx.plan("spmv", "balanced")),
@@ -335,7 +374,8 @@ def main():
     if not args.no_extras:
         extras = {}
         for name, fn in (("poisson_spmv", extra_poisson), ("batched_vs_looped", extra_batched),
-                         ("fwd_vs_fwd_bwd", extra_fwd_bwd), ("bfs", extra_bfs)):
+                         ("fwd_vs_fwd_bwd", extra_fwd_bwd), ("bfs", extra_bfs),
+                         ("pagerank", extra_pagerank)):
             print(f"[bench] extra: {name}", file=sys.stderr, flush=True)
             extras[name] = fn(torch, spx, synth)
         rec["extras"] = extras

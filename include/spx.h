@@ -240,9 +240,19 @@ spx_status spx_vector_features(spx_matrix *H, const spx_vec *x, double *out4, vo
 
 /* Loads the three decision trees (pattern, distribution, write-back) from
  * a JSON file written by the tuner; json_path NULL means the built-in
- * trees. With H NULL they become the default of handles created
- * afterwards; otherwise they replace H's trees only (for example trees
- * trained for the BOOL semiring on a BOOL handle). */
+ * trees. A handle holds two sets of trees:
+ *  - the host-feature trees decide run() and select_kernel(); they should
+ *    not test nnz_s or m_sparsity, which cost a device round trip there;
+ *  - trees that test nnz_s serve the callers that know it for free: the
+ *    graph drivers (spx_bfs, spx_pagerank count it while building x) and
+ *    run_batch (computes it on the device). Until such trees are loaded,
+ *    these callers use the host-feature trees.
+ * A file whose trees test nnz_s or m_sparsity loads into the second set;
+ * any other file, or NULL (the built-in trees), loads into the first and
+ * drops the second (load trees that test nnz_s after it). With
+ * H NULL the trees become the default of handles created afterwards;
+ * otherwise they replace H's only (for example trees trained for the BOOL
+ * semiring on a BOOL handle). */
 spx_status spx_load_selector(spx_matrix *H, const char *json_path);
 
 /* Walks the cascade: pattern tree, then distribution tree, then (column-

@@ -23,20 +23,28 @@ __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spms
            "F32", "F64", "BOOL", "I32", "all_plans"]
 
 _DEFAULT_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x.json")
-# trees trained on (OR, AND) timings, loaded into BOOL handles
+# trees that also test nnz_s, for the callers that know it (graph drivers,
+# run_batch)
+_NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_nnz_s.json")
+# trees trained on (OR, AND) timings, loaded into BOOL handles (host
+# features, then with nnz_s)
 _BOOL_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_bool.json")
+_BOOL_NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__),
+                                                  "selector_mi355x_bool_nnz_s.json")
 _selector_loaded = False
 
 
 def _ensure_default_selector():
-    """Loads the trees trained on MI355X timings (selector_mi355x.json) once,
-    before the first handle is created; spx_load_selector can replace them."""
+    """Loads the trees trained on MI355X timings (selector_mi355x.json, then
+    selector_mi355x_nnz_s.json) once, before the first handle is created;
+    spx_load_selector can replace them."""
     global _selector_loaded
     if _selector_loaded:
         return
     import os
-    if os.path.exists(_DEFAULT_SELECTOR):
-        _lib.call("spx_load_selector", None, _DEFAULT_SELECTOR.encode())
+    for path in (_DEFAULT_SELECTOR, _NNZ_S_SELECTOR):
+        if os.path.exists(path):
+            _lib.call("spx_load_selector", None, path.encode())
     _selector_loaded = True
 
 
@@ -123,8 +131,10 @@ class Matrix:
         flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
-        if dtype == BOOL and __import__("os").path.exists(_BOOL_SELECTOR):
-            _lib.call("spx_load_selector", self._h, _BOOL_SELECTOR.encode())
+        if dtype == BOOL:
+            for path in (_BOOL_SELECTOR, _BOOL_NNZ_S_SELECTOR):
+                if __import__("os").path.exists(path):
+                    _lib.call("spx_load_selector", self._h, path.encode())
         self._vals_version = None if self.vals is None else self.vals._version
 
     @classmethod

@@ -201,6 +201,10 @@ struct spx_matrix {
     int32_t* drv_host = nullptr;      // pinned copy of one counter
     // incremental PageRank: column sums (valid for the current values),
     // residual, product, sparse input, negative-weight flag
+    // trees for callers that know nnz_s without a device round trip (the
+    // graph drivers, run_batch); the host-feature trees otherwise
+    Selector sel_known;
+    bool has_sel_known = false;
     void* pr_W = nullptr;
     void* pr_r = nullptr;
     void* pr_y = nullptr;
@@ -273,21 +277,22 @@ static spx_csc handle_csc(const spx_matrix* H) {
     return c;
 }
 
+// The trees of a caller that knows nnz_s.
+static const Selector& known_selector(const spx_matrix* H) { return H->has_sel_known ? H->sel_known : H->sel; }
+
+// run_batch evaluates the trees on the device with nnz_s computed there, so
+// it takes the trees that read nnz_s when the handle has them.
 static spx_status upload_selector(spx_matrix* H) {
     if (!H->dev_sel && hipMalloc((void**)&H->dev_sel, sizeof(DevSelector)) != hipSuccess)
         return fail(SPX_ERR_ALLOC, "device selector allocation failed");
     DevSelector* h = new (std::nothrow) DevSelector();
     if (!h) return fail(SPX_ERR_ALLOC, "selector staging");
-    upload_tree(H->sel.pattern, &h->t[0]);
-    for (int p = 0; p < 3; ++p) upload_tree(H->sel.distribution[p], &h->t[1 + p]);
-    upload_tree(H->sel.writeback, &h->t[4]);
+    const Selector& S = known_selector(H);
+    upload_tree(S.pattern, &h->t[0]);
+    for (int p = 0; p < 3; ++p) upload_tree(S.distribution[p], &h->t[1 + p]);
+    upload_tree(S.writeback, &h->t[4]);
     for (int i = 0; i < 9; ++i) h->mfeat[i] = H->feat[i];
-    h->needs_nnz_s = 0;
-    const Tree* trees[5] = {&H->sel.pattern, &H->sel.distribution[0], &H->sel.distribution[1],
-                            &H->sel.distribution[2], &H->sel.writeback};
-    for (const Tree* t : trees)
-        for (size_t i = 0; i < t->cls.size(); ++i)
-            if (t->cls[i] < 0 && (t->feat[i] == F_NNZ_S || t->feat[i] == F_M_SPARSITY)) h->needs_nnz_s = 1;
+    h->needs_nnz_s = S.reads_nnz_s() ? 1 : 0;
     hipError_t e = hipMemcpy(H->dev_sel, h, sizeof(DevSelector), hipMemcpyHostToDevice);
     delete h;
     if (e != hipSuccess) return hip_fail(e, "upload selector");
@@ -296,6 +301,12 @@ static spx_status upload_selector(spx_matrix* H) {
 
 static Selector& global_selector() {
     static Selector s = builtin_selector();
+    return s;
+}
+
+// Default trees that read nnz_s (first = loaded).
+static std::pair<bool, Selector>& global_selector_known() {
+    static std::pair<bool, Selector> s{false, Selector{}};
     return s;
 }
 
@@ -591,6 +602,8 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
     H->csr = *A;
     hipGetDevice(&H->device);
     H->sel = global_selector();
+    H->has_sel_known = global_selector_known().first;
+    if (H->has_sel_known) H->sel_known = global_selector_known().second;
     spx_status st = SPX_OK;
     if (flags & SPX_VALIDATE) {
         uint32_t* bad = nullptr;
@@ -762,8 +775,8 @@ struct LazyFeatures {
     }
 };
 
-static spx_status select_impl(spx_matrix* H, const spx_vec* x, uint32_t flags, spx_plan* out, LazyFeatures& lf) {
-    const Selector& S = H->sel;
+static spx_status select_impl(spx_matrix* H, const Selector& S, const spx_vec* x, uint32_t flags, spx_plan* out,
+                              LazyFeatures& lf) {
     auto f = [&](int id) { return lf.get(id); };
     spx_plan p{};
     p.pattern = S.pattern.eval(f);
@@ -787,7 +800,7 @@ extern "C" spx_status select_kernel(spx_matrix* H, const spx_vec* x, uint32_t fl
     if (!H || !out) return fail(SPX_ERR_ARG, "null argument");
     SPX_TRY(check_vec(H, x));
     LazyFeatures lf{H, x, (hipStream_t)stream, (flags & SPX_NO_SYNC) != 0};
-    return select_impl(H, x, flags, out, lf);
+    return select_impl(H, H->sel, x, flags, out, lf);
 }
 
 extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
@@ -802,11 +815,25 @@ extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
         std::string err;
         if (!parse_selector_json(ss.str(), &s, &err)) return fail(SPX_ERR_ARG, "selector: " + err);
     }
+    // host-feature trees replace both sets (the nnz_s trees, if any, load
+    // after them); trees that test nnz_s replace the second set only
+    const bool known = json_path && s.reads_nnz_s();
     if (!H) {
-        global_selector() = s;
+        if (known) {
+            global_selector_known() = {true, s};
+        } else {
+            global_selector() = s;
+            global_selector_known().first = false;
+        }
         return SPX_OK;
     }
-    H->sel = s;
+    if (known) {
+        H->sel_known = s;
+        H->has_sel_known = true;
+    } else {
+        H->sel = s;
+        H->has_sel_known = false;
+    }
     return upload_selector(H);
 }
 
@@ -921,12 +948,27 @@ extern "C" spx_status run(spx_matrix* H, const spx_vec* x, void* y, void* stream
     auto t0 = std::chrono::steady_clock::now();
     LazyFeatures lf{H, x, s, false};
     spx_plan p;
-    SPX_TRY(select_impl(H, x, 0, &p, lf));
+    SPX_TRY(select_impl(H, H->sel, x, 0, &p, lf));
     auto t1 = std::chrono::steady_clock::now();
     if (H->profiling) H->host_ms[1] += std::chrono::duration<double, std::milli>(t1 - t0).count();
     H->last_plan = p;
     return exec_plan(H, x, y, &p, lf.have_counts && lf.synced ? lf.nnz_s : -1,
                      lf.have_counts && lf.synced ? lf.nnz_x : -1, s);
+}
+
+// run() for a sparse x whose nnz_s the caller knows (the graph drivers
+// count it while they build x): the trees that read nnz_s decide, with no
+// device round trip, and the column-major kernels get the exact nnz_s.
+static spx_status run_counts(spx_matrix* H, const spx_vec* x, void* y, int64_t nnz_s, hipStream_t s) {
+    LazyFeatures lf{H, x, s, false};
+    lf.have_counts = true;
+    lf.synced = true;
+    lf.nnz_x = x->nnz_x;
+    lf.nnz_s = nnz_s;
+    spx_plan p;
+    SPX_TRY(select_impl(H, known_selector(H), x, 0, &p, lf));
+    H->last_plan = p;
+    return exec_plan(H, x, y, &p, nnz_s, x->nnz_x, s);
 }
 
 extern "C" spx_status run_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_plan* plan, void* stream) {
@@ -1217,7 +1259,7 @@ extern "C" spx_status spx_bfs(spx_matrix* H, int32_t source, int32_t* level, int
                 SPX_TRY(run_plan(H, &x, H->bfs_y, plan, stream));
                 p = *plan;
             } else {
-                SPX_TRY(run(H, &x, H->bfs_y, stream));
+                SPX_TRY(run_counts(H, &x, H->bfs_y, mf, s));
                 p = H->last_plan;
             }
             SPX_TRY(launch_bfs_update(A.n, H->bfs_y, depth, H->col_ptr, level, H->bfs_front[cur ^ 1],
@@ -1299,6 +1341,7 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
         pending = false;
         SPX_TRY(read_driver_counter(H, round, s));
         const int32_t nx = H->drv_host[0];
+        const int64_t ns = H->drv_host[1];  // column lengths of supp(x)
         if (nx == 0) break;
         spx_vec x{SPX_VEC_SPARSE, A.n, nx, H->pr_xidx, H->pr_xval};
         spx_plan p{};
@@ -1306,7 +1349,7 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
             SPX_TRY(run_plan(H, &x, H->pr_y, plan, stream));
             p = *plan;
         } else {
-            SPX_TRY(run(H, &x, H->pr_y, stream));
+            SPX_TRY(run_counts(H, &x, H->pr_y, ns, s));
             p = H->last_plan;
         }
         if (it < plans_cap) plans[it] = p;

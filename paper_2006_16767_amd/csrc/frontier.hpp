@@ -12,8 +12,8 @@ namespace spx {
 
 // A counter is one 64-bit word of two halves that are added together: the
 // low half counts the vertices appended to the list, the high half holds a
-// per-driver sum (breadth-first search: their out-degrees; PageRank: the
-// active vertices). Neither half can carry into the other (both stay below
+// per-driver sum (both drivers: the column lengths of the appended
+// vertices, i.e. nnz_s of the next product). Neither half can carry into the other (both stay below
 // 2^31), so one atomic add updates both.
 using Count = unsigned long long;
 

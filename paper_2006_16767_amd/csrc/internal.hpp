@@ -216,7 +216,8 @@ spx_status launch_bfs_pull(int32_t n, const int32_t* row_ptr, const int32_t* col
 
 // incremental PageRank (pagerank.hip): one launch per stage. count: two
 // packed counters as for breadth-first search, {entries appended to x,
-// active vertices}; round s appends into count[s & 1], clears the other.
+// their column lengths}; round s appends into count[s & 1], clears the
+// other.
 enum PrStage { PR_COLSUM, PR_INIT, PR_SELECT, PR_FOLD };
 struct PrArgs {
     int stage = PR_INIT;
@@ -224,7 +225,7 @@ struct PrArgs {
     int32_t n = 0;
     int32_t round = 0;
     double damping = 0.85, eps = 0.0;
-    const int32_t* col_ptr = nullptr;  // COLSUM
+    const int32_t* col_ptr = nullptr;  // CSC column pointers
     const void* vals_csc = nullptr;    // COLSUM
     uint32_t* bad = nullptr;           // COLSUM: bit 0 = negative weight
     void* W = nullptr;                 // column sums

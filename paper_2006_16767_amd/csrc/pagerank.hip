@@ -51,21 +51,22 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(int32_t n, T r0, T* __restri
 }
 
 // One round. y = nullptr on the first round (no product yet). The counter
-// gets {appended entries of x (low), active vertices (high)}; count_clear
-// is zeroed for the next round. r += d y is rounded as a product and then a
-// sum (no fused multiply-add), the order the definition states.
+// gets {appended entries of x (low), their column lengths (high), i.e. the
+// nnz_s of the next product}; count_clear is zeroed for the next round.
+// r += d y is rounded as a product and then a sum (no fused multiply-add),
+// the order the definition states.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pr_select(int32_t n, T d, T eps, const T* __restrict__ y,
                                                       T* __restrict__ r, T* __restrict__ p,
-                                                      const T* __restrict__ W, int32_t* __restrict__ x_idx,
-                                                      T* __restrict__ x_val, Count* __restrict__ count,
-                                                      Count* __restrict__ count_clear) {
+                                                      const T* __restrict__ W, const int32_t* __restrict__ col_ptr,
+                                                      int32_t* __restrict__ x_idx, T* __restrict__ x_val,
+                                                      Count* __restrict__ count, Count* __restrict__ count_clear) {
 #pragma clang fp contract(off)
     __shared__ Count tmp[kWavesPerBlock];
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_clear = 0;
     for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n; base += (int64_t)gridDim.x * kChunk) {
         const int64_t v0 = base + (int64_t)threadIdx.x * kVpt;
-        uint32_t mask = 0, active = 0;
+        uint32_t mask = 0, ns = 0;
         T xv[kVpt];
 #pragma unroll
         for (int j = 0; j < kVpt; ++j) {
@@ -80,18 +81,18 @@ __global__ __launch_bounds__(kBlock) void k_pr_select(int32_t n, T d, T eps, con
                 if (rv > eps || rv < -eps) {
                     p[v] = p[v] + rv;
                     r[v] = (T)0;
-                    ++active;
                     const T w = W[v];
                     if (w > (T)0) {
                         mask |= 1u << j;
                         xv[j] = rv / w;
+                        ns += (uint32_t)(col_ptr[v + 1] - col_ptr[v]);
                     }
                 } else if (y) {
                     r[v] = rv;
                 }
             }
         }
-        block_append(mask, active, count, tmp, [&](uint32_t slot, int j) {
+        block_append(mask, ns, count, tmp, [&](uint32_t slot, int j) {
             x_idx[slot] = (int32_t)(v0 + j);
             x_val[slot] = xv[j];
         });
@@ -125,7 +126,7 @@ static spx_status pr_t(const PrArgs& a, hipStream_t s) {
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.n, kChunk), 2048));
             Count* c = (Count*)a.count;
             k_pr_select<T><<<grid, kBlock, 0, s>>>(a.n, (T)a.damping, (T)a.eps, (const T*)a.y, (T*)a.r, (T*)a.p,
-                                                   (const T*)a.W, a.x_idx, (T*)a.x_val, c + (a.round & 1),
+                                                   (const T*)a.W, a.col_ptr, a.x_idx, (T*)a.x_val, c + (a.round & 1),
                                                    c + ((a.round - 1) & 1));
             break;
         }

@@ -57,6 +57,15 @@ struct Selector {
     Tree distribution[3];  // per pattern; classes: spx_distribution
     Tree writeback;        // classes: spx_writeback
     std::string source = "builtin";
+    // true when an internal node of any tree tests nnz_s or m_sparsity,
+    // the features that need the vector's column lengths
+    bool reads_nnz_s() const {
+        const Tree* ts[5] = {&pattern, &distribution[0], &distribution[1], &distribution[2], &writeback};
+        for (const Tree* t : ts)
+            for (size_t i = 0; i < t->cls.size(); ++i)
+                if (t->cls[i] < 0 && (t->feat[i] == F_NNZ_S || t->feat[i] == F_M_SPARSITY)) return true;
+        return false;
+    }
 };
 
 Selector builtin_selector();

@@ -436,10 +436,14 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
     return SPX_OK;
 }
 
+// Every bucket's workgroup scans the short columns of x whole and cuts the
+// long ones to its rows by binary search, so a walk's cost follows nnz_x
+// and the average column length, not nnz_s (a hub column costs two
+// searches per bucket). The test therefore uses nnz_x times the average
+// column length whether or not the caller knows nnz_s.
 bool csc_bucket_walks(const CscArgs& A, int32_t nnz_x, const spx_plan* plan) {
     if (plan->writeback != SPX_WB_BUCKET || plan->distribution != SPX_DIST_DIRECT) return false;
-    const int64_t est = A.nnz_s_hint >= 0 ? A.nnz_s_hint
-                                           : (int64_t)((double)nnz_x * (A.n > 0 ? (double)A.nnz / A.n : 0.0));
+    const int64_t est = (int64_t)((double)nnz_x * (A.n > 0 ? (double)A.nnz / A.n : 0.0));
     return nnz_x <= kWalkMaxX && est <= kWalkMaxS;
 }
 

@@ -280,6 +280,24 @@ def random_csr(m: int, n: int, density: float, seed: int, dtype=np.float32,
     return _coo_to_csr(m, n, rr.astype(np.int64), cc.astype(np.int64), vals)
 
 
+def weighted_sparse_vector(n: int, nnz: int, weights: np.ndarray, seed: int, lo=0.0, hi=1.0,
+                           dtype=np.float32) -> SparseVec:
+    """nnz distinct indices drawn without replacement with probability
+    proportional to weights (Efraimidis-Spirakis keys U^(1/w)); indices of
+    zero weight only once the positive ones run out. Sorted; values
+    U[lo, hi]. Used for supports shaped like graph frontiers: weights =
+    column lengths favours hubs, 1 / (length + 1) the low-degree tail."""
+    rng = np.random.default_rng(seed)
+    nnz = int(min(max(nnz, 0), n))
+    w = np.asarray(weights, np.float64)
+    u = rng.random(n)
+    with np.errstate(divide="ignore"):
+        key = np.where(w > 0, np.log(u) / np.where(w > 0, w, 1.0), -np.inf)
+    idx = np.sort(np.argpartition(-key, nnz - 1)[:nnz]) if 0 < nnz < n else np.arange(nnz)
+    val = rng.uniform(lo, hi, size=nnz).astype(dtype)
+    return SparseVec(n, idx.astype(np.int32), val)
+
+
 def sparse_vector(n: int, nnz: int, seed: int, dist: str = "uniform",
                   dtype=np.float32, lo=-1.0, hi=1.0) -> SparseVec:
     """nnz distinct uniform indices in [0, n), sorted; values drawn from

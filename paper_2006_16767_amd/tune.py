@@ -96,9 +96,31 @@ def densities(n: int, count: int = 40):
     return [int(v) for v in vals]
 
 
-def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None, dtype: str = "f32"):
+SUPPORTS = ("uniform", "hub", "low")
+
+
+def _vectors(A, kind: str):
+    """(key suffix, sparse vector) pairs of one support kind: "uniform"
+    places nnz_x indices uniformly (40 sizes from 1 to n); "hub" draws them
+    with probability proportional to the column length and "low" to
+    1 / (length + 1), as graph frontiers do (20 sizes up to n / 2), so that
+    nnz_s departs from nnz_x times the average column length."""
+    from . import synth
+    if kind == "uniform":
+        return [(f"{nx}", synth.sparse_vector(A.n, nx, 5000 + i, lo=0.0, hi=1.0))
+                for i, nx in enumerate(densities(A.n))]
+    clen = np.bincount(np.asarray(A.col_idx), minlength=A.n).astype(np.float64)
+    w = clen if kind == "hub" else 1.0 / (clen + 1.0)
+    cap = int(min(A.n // 2, (w > 0).sum()))
+    sizes = [nx for nx in densities(A.n, 20) if nx <= cap]
+    seed0 = 7000 if kind == "hub" else 9000
+    return [(f"{kind}:{nx}", synth.weighted_sparse_vector(A.n, nx, w, seed0 + i)) for i, nx in enumerate(sizes)]
+
+
+def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None, dtype: str = "f32",
+          supports=("uniform",)):
     """dtype "f32": FP32 values; "bool": the pattern and index-only vectors
-    in the (OR, AND) semiring."""
+    in the (OR, AND) semiring. supports: the vector kinds of _vectors."""
     import torch
     from . import BOOL, Matrix, all_plans, synth
 
@@ -121,11 +143,9 @@ def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None, dtype: 
             y = M.out_tensor()
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
-            for i, nx in enumerate(densities(A.n)):
-                key = f"{name}:{nx}"
-                if key in done:
-                    continue
-                v = synth.sparse_vector(A.n, nx, 5000 + i, lo=0.0, hi=1.0)
+            todo = [(f"{name}:{suffix}", kind, v) for kind in supports for suffix, v in _vectors(A, kind)
+                    if f"{name}:{suffix}" not in done]
+            for key, kind, v in todo:
                 x = (torch.as_tensor(v.idx, device="cuda"),
                      None if dtype == "bool" else torch.as_tensor(np.asarray(v.val, np.float32), device="cuda"))
                 vf = M.vector_features(x)
@@ -144,7 +164,7 @@ def sweep(out_path: str, reps: int = 5, quick: bool = False, plans=None, dtype: 
                         ev1.synchronize()
                         ts.append(ev0.elapsed_time(ev1))
                     times[label] = float(np.median(ts))
-                rec = {"key": key, "matrix": name, "features": {**mf, **vf}, "times_ms": times}
+                rec = {"key": key, "matrix": name, "support": kind, "features": {**mf, **vf}, "times_ms": times}
                 fout.write(json.dumps(rec) + "\n")
                 fout.flush()
             print(f"[tune] {name}: done in {time.time() - t0:.1f}s", flush=True)
@@ -441,13 +461,18 @@ def main(argv=None):
     s.add_argument("--reps", type=int, default=5)
     s.add_argument("--quick", action="store_true")
     s.add_argument("--dtype", choices=("f32", "bool"), default="f32")
+    s.add_argument("--supports", default="uniform",
+                   help="comma-separated vector kinds: " + ", ".join(SUPPORTS))
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--all-features", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        sweep(a.out, a.reps, a.quick, dtype=a.dtype)
+        kinds = tuple(k for k in a.supports.split(",") if k)
+        if any(k not in SUPPORTS for k in kinds):
+            ap.error(f"--supports: kinds are {', '.join(SUPPORTS)}")
+        sweep(a.out, a.reps, a.quick, dtype=a.dtype, supports=kinds)
     else:
         rep = train(a.data, a.out, a.all_features)
         print(json.dumps(rep, indent=1))
