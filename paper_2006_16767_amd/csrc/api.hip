@@ -130,19 +130,22 @@ __global__ __launch_bounds__(kBlock) void k_renumber_cols(int64_t nnz, const int
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride) gcol[k] = grank[col_idx[src[k]]];
 }
 
-// dense x -> bitvector of its nonzeros (x != 0)
+// dense x -> bitvector of its nonzeros (x != 0): one element per lane
+// (coalesced), the wave's ballot is its two words
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_dense_bits(int32_t n, const typename SR<DT>::X* __restrict__ x,
                                                        uint32_t* __restrict__ bits) {
-    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // one word per thread
-    const int64_t j0 = w * 32;
-    if (j0 >= n) return;
-    uint32_t word = 0;
-    const int cnt = (int)std::min<int64_t>(32, n - j0);
-    for (int b = 0; b < cnt; ++b)
-        if (x[j0 + b] != (typename SR<DT>::X)0) word |= 1u << b;
-    bits[w] = word;
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool nz = j < n && x[j] != (typename SR<DT>::X)0;
+    const uint64_t b = __ballot(nz);
+    const int64_t j0 = j - lane_id();  // first element of the wave, a multiple of 64
+    if (lane_id() == 0 && j0 < n) {
+        bits[j0 >> 5] = (uint32_t)b;
+        if (j0 + 32 < n) bits[(j0 >> 5) + 1] = (uint32_t)(b >> 32);
+    }
 }
+
+static unsigned dense_bits_grid(int32_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kBlock)); }
 
 }  // namespace spx
 
@@ -198,7 +201,8 @@ struct spx_matrix {
     uint8_t* bfs_y = nullptr;
     int32_t* drv_count = nullptr;     // two packed counters of the graph drivers
     uint32_t* bfs_bits[2] = {nullptr, nullptr};
-    int32_t* drv_host = nullptr;      // pinned copy of one counter
+    int32_t* drv_host = nullptr;      // pinned copies of the counters (two slots of 16 bytes)
+    hipEvent_t drv_ev[2] = {nullptr, nullptr};
     // incremental PageRank: column sums (valid for the current values),
     // residual, product, sparse input, negative-weight flag
     // trees for callers that know nnz_s without a device round trip (the
@@ -210,6 +214,8 @@ struct spx_matrix {
     void* pr_y = nullptr;
     int32_t* pr_xidx = nullptr;
     void* pr_xval = nullptr;
+    void* pr_xd[2] = {nullptr, nullptr};
+    void* pr_p = nullptr;  // rank, copied to the caller's array at the end
     uint32_t* pr_bad = nullptr;
     bool pr_W_valid = false;
     hipStream_t cap_stream = nullptr;
@@ -438,10 +444,12 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
                     H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->drv_count,
                     H->bfs_bits[0], H->bfs_bits[1], H->pr_W, H->pr_r, H->pr_y, H->pr_xidx, H->pr_xval,
-                    H->pr_bad};
+                    H->pr_xd[0], H->pr_xd[1], H->pr_p, H->pr_bad};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (H->drv_host) hipHostFree(H->drv_host);
+    for (auto& e : H->drv_ev)
+        if (e) hipEventDestroy(e);
     for (auto& e : H->ev_conv) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
@@ -747,6 +755,8 @@ struct LazyFeatures {
                 return (double)ns();
             case F_M_SPARSITY:
                 return H->csr.nnz > 0 ? (double)ns() / H->csr.nnz : 0.0;
+            case F_S_PER_X:
+                return (double)ns() / (double)std::max<int64_t>(1, nx());
         }
         return 0.0;
     }
@@ -892,7 +902,7 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
             SPX_TRY(permute_dense(A.n, x->val, dt, H->gorder, H->xd, H->bits, s));
             xd = dt == SPX_BOOL ? nullptr : H->xd;
         } else {
-            const unsigned g = (unsigned)std::max<int64_t>(1, ceil_div(ceil_div(A.n, 32), kBlock));
+            const unsigned g = dense_bits_grid(A.n);
             switch (dt) {
                 case SPX_F32: k_dense_bits<SPX_F32><<<g, kBlock, 0, s>>>(A.n, (const float*)x->val, H->bits); break;
                 case SPX_F64: k_dense_bits<SPX_F64><<<g, kBlock, 0, s>>>(A.n, (const double*)x->val, H->bits); break;
@@ -956,19 +966,61 @@ extern "C" spx_status run(spx_matrix* H, const spx_vec* x, void* y, void* stream
                      lf.have_counts && lf.synced ? lf.nnz_x : -1, s);
 }
 
-// run() for a sparse x whose nnz_s the caller knows (the graph drivers
+// Selection for a sparse x whose nnz_s the caller knows (the graph drivers
 // count it while they build x): the trees that read nnz_s decide, with no
-// device round trip, and the column-major kernels get the exact nnz_s.
-static spx_status run_counts(spx_matrix* H, const spx_vec* x, void* y, int64_t nnz_s, hipStream_t s) {
+// device round trip.
+static spx_status select_counts(spx_matrix* H, const spx_vec* x, int64_t nnz_s, hipStream_t s, spx_plan* p) {
     LazyFeatures lf{H, x, s, false};
     lf.have_counts = true;
     lf.synced = true;
     lf.nnz_x = x->nnz_x;
     lf.nnz_s = nnz_s;
+    SPX_TRY(select_impl(H, known_selector(H), x, 0, p, lf));
+    H->last_plan = *p;
+    return SPX_OK;
+}
+
+// run() for a sparse x with known nnz_s; the column-major kernels get the
+// exact nnz_s too.
+static spx_status run_counts(spx_matrix* H, const spx_vec* x, void* y, int64_t nnz_s, hipStream_t s) {
     spx_plan p;
-    SPX_TRY(select_impl(H, known_selector(H), x, 0, &p, lf));
-    H->last_plan = p;
+    SPX_TRY(select_counts(H, x, nnz_s, s, &p));
     return exec_plan(H, x, y, &p, nnz_s, x->nnz_x, s);
+}
+
+// Executes plan p for a sparse x (F32/F64) that the caller has also written
+// dense into xd, at grank[j] when the handle keeps the renumbered copy: the
+// row-major kernels read xd with no conversion (the CSR SpMSpV takes its
+// bitvector from the nonzeros of xd, which equals supp(x) up to entries
+// whose value is exactly 0 and contribute nothing), the column-major ones
+// read the list.
+static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd, void* y, const spx_plan* p,
+                                int64_t nnz_s, hipStream_t s) {
+    if (p->pattern == SPX_PAT_CSC_SPMSPV) return exec_plan(H, x, y, p, nnz_s, x->nnz_x, s);
+    const spx_csr& A = H->gorder ? H->gcsr : H->csr;
+    const int dt = A.dtype;
+    if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "prepared x: F32 or F64 only");
+    SPX_TRY(spx_check_plan(p, dt));
+    SPX_TRY(ensure_conv(H));
+    const uint32_t* bits = nullptr;
+    if (p->pattern == SPX_PAT_CSR_SPMSPV) {
+        record(H, H->ev_conv, true, s);
+        if (dt == SPX_F32)
+            k_dense_bits<SPX_F32><<<dense_bits_grid(A.n), kBlock, 0, s>>>(A.n, (const float*)xd, H->bits);
+        else
+            k_dense_bits<SPX_F64><<<dense_bits_grid(A.n), kBlock, 0, s>>>(A.n, (const double*)xd, H->bits);
+        SPX_HIP(hipGetLastError());
+        record(H, H->ev_conv, false, s);
+        bits = H->bits;
+    }
+    SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
+    Arena ws(H->ws, H->ws_bytes);
+    const int32_t* part = nullptr;
+    SPX_TRY(cached_part(H, A, 0, p, s, &part));
+    record(H, H->ev_kern, true, s);
+    SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s));
+    record(H, H->ev_kern, false, s);
+    return SPX_OK;
 }
 
 extern "C" spx_status run_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_plan* plan, void* stream) {
@@ -1181,6 +1233,11 @@ static spx_status ensure_driver_counters(spx_matrix* H) {
     if (H->drv_host) return SPX_OK;
     if (!H->drv_count && hipMalloc((void**)&H->drv_count, 256) != hipSuccess)
         return fail(SPX_ERR_ALLOC, "driver counters: allocation failed");
+    for (auto& e : H->drv_ev)
+        if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+            return fail(SPX_ERR_HIP, "driver events: creation failed");
+        }
     if (hipHostMalloc((void**)&H->drv_host, 64, hipHostMallocDefault) != hipSuccess) {
         H->drv_host = nullptr;
         return fail(SPX_ERR_ALLOC, "driver counters: pinned allocation failed");
@@ -1300,7 +1357,9 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
         if (hipMalloc(&H->pr_W, vbytes) != hipSuccess || hipMalloc(&H->pr_r, vbytes) != hipSuccess ||
             hipMalloc(&H->pr_y, vbytes) != hipSuccess ||
             hipMalloc((void**)&H->pr_xidx, (size_t)A.n * 4) != hipSuccess ||
-            hipMalloc(&H->pr_xval, vbytes) != hipSuccess || hipMalloc((void**)&H->pr_bad, 4) != hipSuccess) {
+            hipMalloc(&H->pr_xval, vbytes) != hipSuccess || hipMalloc(&H->pr_xd[0], vbytes) != hipSuccess ||
+            hipMalloc(&H->pr_xd[1], vbytes) != hipSuccess || hipMalloc(&H->pr_p, vbytes) != hipSuccess ||
+            hipMalloc((void**)&H->pr_bad, 4) != hipSuccess) {
             H->pr_r = nullptr;
             return fail(SPX_ERR_ALLOC, "PageRank buffers: allocation failed");
         }
@@ -1315,9 +1374,12 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
     a.bad = H->pr_bad;
     a.W = H->pr_W;
     a.r = H->pr_r;
-    a.p = rank;
+    a.p = H->pr_p;
     a.x_idx = H->pr_xidx;
     a.x_val = H->pr_xval;
+    a.xd[0] = H->pr_xd[0];
+    a.xd[1] = H->pr_xd[1];
+    a.map = H->gorder ? H->grank : nullptr;
     a.count = H->drv_count;
     if (!H->pr_W_valid) {
         SPX_TRY(fill_u32(H->pr_bad, 0u, 1, s));
@@ -1331,36 +1393,80 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
     a.stage = PR_INIT;
     SPX_TRY(launch_pagerank(a, s));
     SPX_TRY(fill_u32((uint32_t*)H->drv_count, 0u, 4, s));
-    int32_t it = 0;
-    bool pending = false;  // a product not yet folded into r
-    for (int32_t round = 0; it < max_iters; ++round) {
+    // Round k's counter is copied to pinned slot k & 1 and marked by an
+    // event, so the host can wait for a round's select without waiting for
+    // the product queued behind it.
+    auto enqueue_select = [&](int32_t round) -> spx_status {
         a.stage = PR_SELECT;
         a.round = round;
         a.y = round ? H->pr_y : nullptr;
         SPX_TRY(launch_pagerank(a, s));
-        pending = false;
-        SPX_TRY(read_driver_counter(H, round, s));
-        const int32_t nx = H->drv_host[0];
-        const int64_t ns = H->drv_host[1];  // column lengths of supp(x)
-        if (nx == 0) break;
-        spx_vec x{SPX_VEC_SPARSE, A.n, nx, H->pr_xidx, H->pr_xval};
-        spx_plan p{};
+        SPX_HIP(hipMemcpyAsync(H->drv_host + 4 * (round & 1), H->drv_count + 2 * (round & 1), 8,
+                               hipMemcpyDeviceToHost, s));
+        SPX_HIP(hipEventRecord(H->drv_ev[round & 1], s));
+        return SPX_OK;
+    };
+    auto choose = [&](int32_t nx, int64_t ns, spx_plan* q) -> spx_status {
         if (plan) {
-            SPX_TRY(run_plan(H, &x, H->pr_y, plan, stream));
-            p = *plan;
+            *q = *plan;
+            return SPX_OK;
+        }
+        spx_vec xs{SPX_VEC_SPARSE, A.n, nx, H->pr_xidx, H->pr_xval};
+        return select_counts(H, &xs, ns, s, q);
+    };
+    // A row-major product reads the dense x and needs no count on the host,
+    // so while the plans stay row-major the next round's product is queued
+    // right behind its select, on the plan the last count chose, and the
+    // GPU does not wait for the host between rounds. A column-major plan
+    // needs the exact count: such a round waits for its select first.
+    int32_t it = 0;
+    bool pending = false;  // a product not yet folded into r
+    bool spec = false;     // this round's product was queued before its count was read
+    spx_plan spec_plan{};
+    for (int32_t round = 0; it < max_iters;) {
+        if (round == 0) SPX_TRY(enqueue_select(0));
+        SPX_HIP(hipEventSynchronize(H->drv_ev[round & 1]));
+        const int32_t nx = H->drv_host[4 * (round & 1)];
+        const int64_t ns = H->drv_host[4 * (round & 1) + 1];  // column lengths of supp(x)
+        spx_plan p{};
+        if (spec) {
+            // an empty x gave y = 0: nothing to count and nothing to fold
+            if (nx == 0) {
+                pending = false;
+                break;
+            }
+            p = spec_plan;
         } else {
-            SPX_TRY(run_counts(H, &x, H->pr_y, ns, s));
-            p = H->last_plan;
+            pending = false;
+            if (nx == 0) break;
+            SPX_TRY(choose(nx, ns, &p));
+            spx_vec x{SPX_VEC_SPARSE, A.n, nx, H->pr_xidx, H->pr_xval};
+            SPX_TRY(exec_prepared(H, &x, H->pr_xd[round & 1], H->pr_y, &p, ns, s));
         }
         if (it < plans_cap) plans[it] = p;
         ++it;
         pending = true;
+        if (it >= max_iters) break;
+        ++round;
+        SPX_TRY(enqueue_select(round));
+        spec = false;
+        if (p.pattern != SPX_PAT_CSC_SPMSPV) {
+            spx_plan q{};
+            SPX_TRY(choose(nx, ns, &q));
+            if (q.pattern != SPX_PAT_CSC_SPMSPV) {
+                spx_vec xd_only{SPX_VEC_SPARSE, A.n, 0, H->pr_xidx, H->pr_xval};
+                SPX_TRY(exec_prepared(H, &xd_only, H->pr_xd[round & 1], H->pr_y, &q, -1, s));
+                spec = true;
+                spec_plan = q;
+            }
+        }
     }
     if (pending) {
         a.stage = PR_FOLD;
         a.y = H->pr_y;
         SPX_TRY(launch_pagerank(a, s));
     }
+    SPX_HIP(hipMemcpyAsync(rank, H->pr_p, vbytes, hipMemcpyDeviceToDevice, s));
     if (residual) SPX_HIP(hipMemcpyAsync(residual, H->pr_r, vbytes, hipMemcpyDeviceToDevice, s));
     *n_iters = it;
     return SPX_OK;

@@ -116,7 +116,7 @@ __device__ __forceinline__ int dev_tree_eval(const DevTree& t, const double* f) 
     for (int guard = 0; guard < 64 && i >= 0 && i < t.n; ++guard) {
         if (t.cls[i] >= 0) return t.cls[i];
         const int fi = t.feat[i];
-        i = (fi >= 0 && fi < 13 && f[fi] <= t.thr[i]) ? t.left[i] : t.right[i];
+        i = (fi >= 0 && fi < F_COUNT && f[fi] <= t.thr[i]) ? t.left[i] : t.right[i];
     }
     return 0;
 }
@@ -146,11 +146,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     if (threadIdx.x == 0) {
         int fuse = 0;
         if (DT != SPX_BOOL && a.units != nullptr && nx > 0 && !S.needs_nnz_s) {
-            double f[13];
+            double f[F_COUNT];
             for (int i = 0; i < 9; ++i) f[i] = S.mfeat[i];
             f[9] = nx;
             f[10] = a.n > 0 ? (double)nx / a.n : 0.0;
-            f[11] = f[12] = 0.0;
+            f[11] = f[12] = f[13] = 0.0;
             int pat = dev_tree_eval(S.t[0], f);
             if (pat < 0 || pat > 2) pat = 0;
             fuse = pat != SPX_PAT_CSC_SPMSPV || f[10] >= kFusedMinXSparsity;
@@ -205,12 +205,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     }
     if (threadIdx.x != 0) return;
     excl[nx] = carry;
-    double f[13];
+    double f[F_COUNT];
     for (int i = 0; i < 9; ++i) f[i] = S.mfeat[i];
     f[9] = nx;
     f[10] = a.n > 0 ? (double)nx / a.n : 0.0;
     f[11] = carry;
     f[12] = a.nnz > 0 ? (double)carry / a.nnz : 0.0;
+    f[13] = (double)carry / (double)(nx > 0 ? nx : 1);
     BatchPlan p;
     p.pattern = dev_tree_eval(S.t[0], f);
     if (p.pattern < 0 || p.pattern > 2) p.pattern = 0;

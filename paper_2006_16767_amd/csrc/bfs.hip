@@ -42,14 +42,14 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed(int32_t n, int32_t source, 
 
 // Vertices reached by the product and not labelled yet get level L and go
 // to the next frontier. Thread t of a chunk owns its 8 consecutive vertices.
-__global__ __launch_bounds__(kBlock) void k_bfs_update(int32_t n, const uint8_t* __restrict__ y, int32_t L,
+__global__ __launch_bounds__(kWideBlock) void k_bfs_update(int32_t n, const uint8_t* __restrict__ y, int32_t L,
                                                        const int32_t* __restrict__ col_ptr,
                                                        int32_t* __restrict__ level, int32_t* __restrict__ next,
                                                        uint32_t* __restrict__ next_bits,
                                                        Count* __restrict__ count, Count* __restrict__ count_clear) {
-    __shared__ Count tmp[kWavesPerBlock];
+    __shared__ Count tmp[kWideBlock / kWave];
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_clear = 0;
-    for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n; base += (int64_t)gridDim.x * kChunk) {
+    for (int64_t base = (int64_t)blockIdx.x * kWideChunk; base < n; base += (int64_t)gridDim.x * kWideChunk) {
         const int64_t v0 = base + (int64_t)threadIdx.x * kVpt;
         uint64_t yy = 0;
         if (v0 + kVpt <= n) {
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_update(int32_t n, const uint8_t*
             }
         }
         write_bits(mask, v0, n, next_bits);
-        block_append(mask, v0, deg, next, count, tmp);
+        block_append<kWideBlock>(mask, v0, deg, next, count, tmp);
     }
 }
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_pull(int32_t n, const int32_t* _
             }
         }
         write_bits(mask, v0, n, next_bits);
-        block_append(mask, v0, deg, next, count, tmp);
+        block_append<kBlock>(mask, v0, deg, next, count, tmp);
     }
 }
 
@@ -175,9 +175,9 @@ spx_status launch_bfs_seed(int32_t n, int32_t source, const int32_t* col_ptr, in
 spx_status launch_bfs_update(int32_t n, const uint8_t* y, int32_t L, const int32_t* col_ptr, int32_t* level,
                              int32_t* next, uint32_t* next_bits, void* count, hipStream_t s) {
     if ((uintptr_t)y % 8) return fail(SPX_ERR_ARG, "breadth-first search: product buffer must be 8-byte aligned");
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kChunk), 2048));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kWideChunk), 2048));
     Count* c = (Count*)count;
-    k_bfs_update<<<grid, kBlock, 0, s>>>(n, y, L, col_ptr, level, next, next_bits, c + (L & 1), c + ((L - 1) & 1));
+    k_bfs_update<<<grid, kWideBlock, 0, s>>>(n, y, L, col_ptr, level, next, next_bits, c + (L & 1), c + ((L - 1) & 1));
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }

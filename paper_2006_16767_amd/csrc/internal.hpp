@@ -164,7 +164,7 @@ struct DevTree {
 struct DevSelector {
     DevTree t[5];
     double mfeat[9];
-    int32_t needs_nnz_s;  // a tree reads nnz_s or m_sparsity
+    int32_t needs_nnz_s;  // a tree reads nnz_s, m_sparsity or s_per_x
 };
 void upload_tree(const Tree& t, DevTree* out);
 struct BatchLaunch {
@@ -232,8 +232,10 @@ struct PrArgs {
     void* r = nullptr;                 // residual
     void* p = nullptr;                 // rank
     const void* y = nullptr;           // last product (nullptr on round 0)
-    int32_t* x_idx = nullptr;          // next product's input
+    int32_t* x_idx = nullptr;          // next product's input: list,
     void* x_val = nullptr;
+    void* xd[2] = {nullptr, nullptr};  // dense (alternating, 16-byte aligned),
+    const int32_t* map = nullptr;      // at map[v] (nullptr: v)
     void* count = nullptr;
 };
 spx_status launch_pagerank(const PrArgs& a, hipStream_t s);

@@ -13,7 +13,7 @@ namespace spx {
 
 static const char* kNames[F_COUNT] = {"m",           "n",           "nnz",       "max_row", "min_row",
                                       "avg_row",     "relative_range", "var_nnz_row", "gini",    "nnz_x",
-                                      "x_sparsity", "nnz_s",       "m_sparsity"};
+                                      "x_sparsity", "nnz_s",       "m_sparsity", "s_per_x"};
 
 const char* feature_name(int f) { return (f >= 0 && f < F_COUNT) ? kNames[f] : "?"; }
 

@@ -29,6 +29,7 @@ enum Feature {
     F_X_SPARSITY,
     F_NNZ_S,
     F_M_SPARSITY,
+    F_S_PER_X,  // nnz_s / max(1, nnz_x): mean length of the selected columns (derived, not in Table 1)
     F_COUNT
 };
 
@@ -57,13 +58,15 @@ struct Selector {
     Tree distribution[3];  // per pattern; classes: spx_distribution
     Tree writeback;        // classes: spx_writeback
     std::string source = "builtin";
-    // true when an internal node of any tree tests nnz_s or m_sparsity,
-    // the features that need the vector's column lengths
+    // true when an internal node of any tree tests nnz_s, m_sparsity or
+    // s_per_x, the features that need the vector's column lengths
     bool reads_nnz_s() const {
         const Tree* ts[5] = {&pattern, &distribution[0], &distribution[1], &distribution[2], &writeback};
         for (const Tree* t : ts)
             for (size_t i = 0; i < t->cls.size(); ++i)
-                if (t->cls[i] < 0 && (t->feat[i] == F_NNZ_S || t->feat[i] == F_M_SPARSITY)) return true;
+                if (t->cls[i] < 0 &&
+                    (t->feat[i] == F_NNZ_S || t->feat[i] == F_M_SPARSITY || t->feat[i] == F_S_PER_X))
+                    return true;
         return false;
     }
 };

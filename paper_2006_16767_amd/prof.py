@@ -190,6 +190,21 @@ def cmd_bfs(args):
           f"{sum(p.lanes == -1 for p in plans)} pull levels, {args.reps + 1} searches done", flush=True)
 
 
+def cmd_pagerank(args):
+    import torch
+    from . import Matrix
+    from . import synth
+    A = synth.cfg2_matrix()
+    M = Matrix.from_host(A)
+    d = 0.85
+    eps = 1e-3 * (1 - d) / A.n
+    for _ in range(args.reps + 1):
+        _, plans = M.pagerank(d, eps)
+    torch.cuda.synchronize()
+    print(f"[prof] incremental PageRank on R-MAT 2^20 (FP32): {M.pr_iters} products, "
+          f"{args.reps + 1} runs done", flush=True)
+
+
 def cmd_copy(args):
     import torch
     n = args.mib * (1 << 20) // 4
@@ -283,6 +298,8 @@ def main(argv=None):
     a = sub.add_parser("bfs")
     a.add_argument("--reps", type=int, default=3)
     a.add_argument("--push-only", action="store_true")
+    a = sub.add_parser("pagerank")
+    a.add_argument("--reps", type=int, default=2)
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=512)
     a.add_argument("--reps", type=int, default=3)
@@ -298,7 +315,7 @@ def main(argv=None):
     a.add_argument("--vector", type=int, required=True)
     a.add_argument("--command", action="append")
     args = ap.parse_args(argv)
-    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "bfs": cmd_bfs, "copy": cmd_copy, "kernels": cmd_kernels,
+    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "bfs": cmd_bfs, "pagerank": cmd_pagerank, "copy": cmd_copy, "kernels": cmd_kernels,
      "traffic": cmd_traffic}[args.cmd](args)
 
 

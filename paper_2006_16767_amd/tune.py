@@ -24,7 +24,9 @@ train  labels each record per factor (the pattern of the fastest kernel;
        (spx_load_selector).
 
 By default the trees use only features the host knows without a device
-round trip (everything except nnz_s and m_sparsity); see --all-features.
+round trip (everything except nnz_s, m_sparsity and the derived s_per_x);
+--all-features trains the trees for callers that know nnz_s (the graph
+drivers, the batched path), which the library keeps apart from run()'s.
 """
 from __future__ import annotations
 
@@ -38,8 +40,18 @@ import time
 import numpy as np
 
 FEATURES = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini",
-            "nnz_x", "x_sparsity", "nnz_s", "m_sparsity")
-CHEAP = tuple(f for f in FEATURES if f not in ("nnz_s", "m_sparsity"))
+            "nnz_x", "x_sparsity", "nnz_s", "m_sparsity", "s_per_x")
+# s_per_x = nnz_s / max(1, nnz_x), the mean length of the selected columns,
+# is derived here (not in Table 1, not stored by the sweep): the trees
+# cannot form a ratio of two features, and it separates hub-heavy vectors,
+# on which the direct column-major distribution serializes on long columns.
+CHEAP = tuple(f for f in FEATURES if f not in ("nnz_s", "m_sparsity", "s_per_x"))
+
+
+def _feature_row(rec):
+    f = dict(rec["features"])
+    f["s_per_x"] = f["nnz_s"] / max(1.0, f["nnz_x"])
+    return [f[k] for k in FEATURES]
 PATTERNS = ("spmv", "csr_spmspv", "csc_spmspv")
 DISTS = ("direct", "balanced")
 WBS = ("none", "atomic", "sort", "lds_atomic", "bucket")
@@ -359,7 +371,7 @@ def train(paths, out_path, all_features=False, seed=0):
         rows.append((r, lab))
     feats = FEATURES if all_features else CHEAP
     fidx = [FEATURES.index(f) for f in feats]
-    X = np.array([[r["features"][f] for f in FEATURES] for r, _ in rows], np.float64)
+    X = np.array([_feature_row(r) for r, _ in rows], np.float64)
     Xs = X[:, fidx]
     rng = np.random.default_rng(seed)
     perm = rng.permutation(len(rows))
