@@ -244,9 +244,9 @@ spx_status spx_vector_features(spx_matrix *H, const spx_vec *x, double *out4, vo
  *  - the host-feature trees decide run() and select_kernel(); they should
  *    not test nnz_s or m_sparsity, which cost a device round trip there;
  *  - trees that test nnz_s serve the callers that know it for free: the
- *    graph drivers (spx_bfs, spx_pagerank count it while building x) and
- *    run_batch (computes it on the device). Until such trees are loaded,
- *    these callers use the host-feature trees.
+ *    graph drivers (spx_bfs, spx_pagerank count it while building x).
+ *    Until such trees are loaded, they use the host-feature trees.
+ * run_batch evaluates the host-feature trees on the device.
  * A file whose trees test nnz_s or m_sparsity loads into the second set;
  * any other file, or NULL (the built-in trees), loads into the first and
  * drops the second (load trees that test nnz_s after it). With

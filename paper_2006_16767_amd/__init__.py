@@ -23,8 +23,8 @@ __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spms
            "F32", "F64", "BOOL", "I32", "all_plans"]
 
 _DEFAULT_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x.json")
-# trees that also test nnz_s, for the callers that know it (graph drivers,
-# run_batch)
+# trees that also test nnz_s, for the callers that know it (the graph
+# drivers)
 _NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_nnz_s.json")
 # trees trained on (OR, AND) timings, loaded into BOOL handles (host
 # features, then with nnz_s)

@@ -203,12 +203,12 @@ struct spx_matrix {
     uint32_t* bfs_bits[2] = {nullptr, nullptr};
     int32_t* drv_host = nullptr;      // pinned copies of the counters (two slots of 16 bytes)
     hipEvent_t drv_ev[2] = {nullptr, nullptr};
-    // incremental PageRank: column sums (valid for the current values),
-    // residual, product, sparse input, negative-weight flag
     // trees for callers that know nnz_s without a device round trip (the
-    // graph drivers, run_batch); the host-feature trees otherwise
+    // graph drivers); the host-feature trees otherwise
     Selector sel_known;
     bool has_sel_known = false;
+    // incremental PageRank: column sums (valid for the current values),
+    // residual, product, sparse input, negative-weight flag
     void* pr_W = nullptr;
     void* pr_r = nullptr;
     void* pr_y = nullptr;
@@ -286,14 +286,16 @@ static spx_csc handle_csc(const spx_matrix* H) {
 // The trees of a caller that knows nnz_s.
 static const Selector& known_selector(const spx_matrix* H) { return H->has_sel_known ? H->sel_known : H->sel; }
 
-// run_batch evaluates the trees on the device with nnz_s computed there, so
-// it takes the trees that read nnz_s when the handle has them.
+// run_batch evaluates the host-feature trees on the device: with them a
+// vector whose plan is row-major joins a fused group before any prefix of
+// its column lengths is computed (trees that read nnz_s would need that
+// prefix for every vector, which measured slower on the 512-vector batch).
 static spx_status upload_selector(spx_matrix* H) {
     if (!H->dev_sel && hipMalloc((void**)&H->dev_sel, sizeof(DevSelector)) != hipSuccess)
         return fail(SPX_ERR_ALLOC, "device selector allocation failed");
     DevSelector* h = new (std::nothrow) DevSelector();
     if (!h) return fail(SPX_ERR_ALLOC, "selector staging");
-    const Selector& S = known_selector(H);
+    const Selector& S = H->sel;
     upload_tree(S.pattern, &h->t[0]);
     for (int p = 0; p < 3; ++p) upload_tree(S.distribution[p], &h->t[1 + p]);
     upload_tree(S.writeback, &h->t[4]);

@@ -26,7 +26,7 @@ train  labels each record per factor (the pattern of the fastest kernel;
 By default the trees use only features the host knows without a device
 round trip (everything except nnz_s, m_sparsity and the derived s_per_x);
 --all-features trains the trees for callers that know nnz_s (the graph
-drivers, the batched path), which the library keeps apart from run()'s.
+drivers), which the library keeps apart from run()'s.
 """
 from __future__ import annotations
 
