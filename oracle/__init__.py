@@ -256,3 +256,29 @@ def pagerank_incremental(A, damping, eps, max_iters):
         r += d * y
         products += 1
     return p, r, products
+
+
+def spmspv_sparse(A, x_idx, x_val=None, mask=None, kind="f64"):
+    """Sparse-output SpMSpV with a complement mask (the frontier form of
+    y = A x that the paper's BFS application chains, Section 7): the rows i
+    with at least one stored entry in a column of supp(x) (structural, so a
+    row whose products sum to 0 is still listed) and mask[i] false (mask:
+    bool[m] or None), ascending, with their values of y = A x.
+
+    kind: "f64" (compensated float64, values and S), "i32" ((+, x) mod 2^32)
+    or "bool" ((OR, AND): values all 1). Returns (rows, values, S) with S
+    None except for "f64". Built from the oracle's own dense products: the
+    pattern product decides which rows are listed, the value product
+    supplies their values."""
+    touched = bool_spmspv(A, x_idx).astype(bool)
+    keep = touched if mask is None else touched & ~np.asarray(mask, bool)
+    rows = np.nonzero(keep)[0].astype(np.int32)
+    if kind == "bool":
+        return rows, np.ones(rows.size, np.uint8), None
+    if kind == "i32":
+        csc = transpose(A, int_values=True)
+        y = int_spmspv(csc, x_idx, x_val)
+        return rows, y[rows], None
+    csc = transpose(A)
+    y, s = spmspv(csc, x_idx, x_val)
+    return rows, y[rows], s[rows]

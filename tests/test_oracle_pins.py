@@ -570,3 +570,59 @@ def test_pagerank_pins_catch_planted_mistakes(monkeypatch):
         mp.setattr(oracle, "np", shim)
         p, _, _ = oracle.pagerank_incremental(A, d, 0.0, 400)
     assert not np.allclose(p, want, rtol=1e-6)
+
+
+# ---------------------------------------------------------------- sparse output, complement mask
+def test_sparse_output_hand_worked():
+    """A (4 x 3): rows 0: (0, 2.0); 1: (1, -1.0), (2, 1.0); 2: (2, 3.0);
+    3: (0, 1.0), (2, -1.0). x = {0: 1.0, 2: 1.0}. y = [2, 1, 3, 0]: row 3 is
+    listed with value 0 (its products cancel), row 1 through column 2 only.
+    With row 2 masked the list is rows 0, 1, 3."""
+    A = _mat(4, 3, [0, 1, 3, 4, 6], [0, 1, 2, 2, 0, 2], [2.0, -1.0, 1.0, 3.0, 1.0, -1.0])
+    rows, vals, _ = oracle.spmspv_sparse(A, [0, 2], [1.0, 1.0])
+    assert rows.tolist() == [0, 1, 2, 3] and vals.tolist() == [2.0, 1.0, 3.0, 0.0]
+    rows, vals, _ = oracle.spmspv_sparse(A, [0, 2], [1.0, 1.0], mask=[False, False, True, False])
+    assert rows.tolist() == [0, 1, 3] and vals.tolist() == [2.0, 1.0, 0.0]
+    rows, vals, _ = oracle.spmspv_sparse(A, [1], [5.0], kind="bool")
+    assert rows.tolist() == [1] and vals.tolist() == [1]
+    rows, vals, _ = oracle.spmspv_sparse(A, [], [])
+    assert rows.size == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sparse_output_brute_force(seed):
+    """Against a dense matrix: listed rows = rows with a stored entry in a
+    selected column and no mask bit; values = the dense product."""
+    rng = np.random.default_rng(seed)
+    A = synth.random_csr(30, 25, 0.12, 40 + seed, empty_rows=0.2)
+    D = np.zeros((A.m, A.n))
+    P = np.zeros((A.m, A.n), bool)
+    for i in range(A.m):
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            D[i, A.col_idx[k]] += A.vals[k]
+            P[i, A.col_idx[k]] = True
+    x_idx = np.sort(rng.choice(A.n, 6, replace=False)).astype(np.int32)
+    x_val = rng.uniform(-1, 1, 6)
+    mask = rng.random(A.m) < 0.3
+    x = np.zeros(A.n)
+    x[x_idx] = x_val
+    sel = np.zeros(A.n, bool)
+    sel[x_idx] = True
+    want_rows = np.nonzero(P[:, sel].any(1) & ~mask)[0]
+    rows, vals, _ = oracle.spmspv_sparse(A, x_idx, x_val, mask=mask)
+    assert rows.tolist() == want_rows.tolist()
+    assert np.allclose(vals, (D @ x)[want_rows], rtol=1e-14, atol=1e-15)
+
+
+def test_sparse_output_pin_catches_numeric_listing(monkeypatch):
+    """A planted mistake: listing the rows whose value is nonzero instead of
+    the rows an effective entry reaches drops row 3 of the hand-worked case."""
+    A = _mat(4, 3, [0, 1, 3, 4, 6], [0, 1, 2, 2, 0, 2], [2.0, -1.0, 1.0, 3.0, 1.0, -1.0])
+
+    def numeric(M, xi):
+        y, _ = oracle.spmspv(oracle.transpose(M), xi, np.ones(len(xi)))
+        return (y != 0).astype(np.uint8)
+    with monkeypatch.context() as mp:
+        mp.setattr(oracle, "bool_spmspv", numeric)
+        rows, _, _ = oracle.spmspv_sparse(A, [0, 2], [1.0, 1.0])
+    assert rows.tolist() != [0, 1, 2, 3]
