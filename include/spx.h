@@ -318,6 +318,23 @@ spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
  * average (hub rows) serialize. F32 and F64 only. */
 spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void *stream);
 
+/* Sparse-output SpMSpV with a complement mask (the frontier form of the
+ * product, Section 7; the bucket write-back of Section 4.2.2 listing rows
+ * instead of writing a dense y): for a sparse x, the rows i that an
+ * effective entry reaches (a stored entry in a column of supp(x), however
+ * its products sum) and whose bit in mask is clear (mask: device bitvector
+ * of ceil(m / 32) words, bit i of word i / 32; NULL masks nothing) go to
+ * y_idx[k] (device int32) with y_val[k] = (A x)_i (device, the handle's
+ * value type; NULL to skip the values; for BOOL all 1), k < *nnz_y (host).
+ * Rows ascend within each bucket of rows; the buckets come in any order.
+ * y_idx / y_val must hold the rows that can be listed (m at most). No
+ * dense y is written, so the cost follows nnz_x and nnz_s, not m.
+ * plan: a column-major plan with the bucket write-back (its distribution,
+ * lanes and bucket rows are used), or NULL to let the column-major
+ * distribution tree choose. Synchronizes the stream (the count). */
+spx_status spmspv_sparse(spx_matrix *H, const spx_vec *x, const uint32_t *mask, const spx_plan *plan,
+                         int32_t *y_idx, void *y_val, int32_t *nnz_y, void *stream);
+
 /* Breadth-first search over the graph of a square BOOL handle (stored entry
  * (i, j) = edge j -> i, so a column lists a vertex's out-edges): level[v] =
  * fewest edges from source, -1 if unreachable (level: device int32[n]).

@@ -325,6 +325,36 @@ class Matrix:
         self.bfs_levels = nl.value
         return level, [plans[i] for i in range(cap) if plans[i].pattern >= 0]
 
+    def pack_mask(self, rows_mask):
+        """A bool / uint8 tensor of m entries as the bitvector (int32 words,
+        bit i of word i // 32) that spmspv_sparse takes."""
+        torch = _torch()
+        words = (self.m + 31) // 32
+        b = torch.zeros(words * 32, dtype=torch.int64, device=rows_mask.device)
+        b[:self.m] = (rows_mask.reshape(-1) != 0).to(torch.int64)
+        w = (b.view(words, 32) << torch.arange(32, device=b.device)).sum(1)
+        return w.to(torch.uint32).view(torch.int32) if hasattr(torch, "uint32") else \
+            torch.where(w >= 2 ** 31, w - 2 ** 32, w).to(torch.int32)
+
+    def spmspv_sparse(self, x, mask=None, plan: Plan | None = None, with_values: bool = True, stream=None):
+        """y = A x for a sparse x as a row list: (rows, values) of the rows an
+        effective entry reaches, minus those set in mask (a packed bitvector
+        from pack_mask, or a bool / uint8 tensor of m entries). Rows ascend
+        within each bucket of rows; buckets come in any order."""
+        torch = _torch()
+        v, keep = _vec(x, self.n)
+        if mask is not None and mask.dtype != torch.int32:
+            mask = self.pack_mask(mask)
+        self.sync_values(stream=stream)
+        idx = torch.empty(max(1, self.m), dtype=torch.int32, device=self.row_ptr.device)
+        val = torch.empty(max(1, self.m), dtype=torch_dtype(self.dtype),
+                          device=self.row_ptr.device) if with_values else None
+        cnt = C.c_int32(0)
+        _lib.call("spmspv_sparse", self._h, C.byref(v), _ptr(mask), None if plan is None else C.byref(plan),
+                  _ptr(idx), _ptr(val), C.byref(cnt), _stream(stream))
+        k = cnt.value
+        return idx[:k], (val[:k] if val is not None else None)
+
     def pagerank(self, damping: float = 0.85, eps: float | None = None, max_iters: int = 10000,
                  plan: Plan | None = None, want_residual: bool = False, stream=None):
         """Incremental (residual-push) PageRank on an F32/F64 handle (entry

@@ -82,6 +82,7 @@ SIGNATURES = {
     "spx_batch_status": (C.c_int, [P, C.POINTER(_i32), P]),
     "spx_bfs": (C.c_int, [P, _i32, P, _i32, C.POINTER(Plan), C.c_uint32, C.POINTER(C.c_int32), C.POINTER(Plan),
                           _i32, P]),
+    "spmspv_sparse": (C.c_int, [P, C.POINTER(Vec), P, C.POINTER(Plan), P, P, C.POINTER(C.c_int32), P]),
     "spx_pagerank": (C.c_int, [P, C.c_double, C.c_double, _i32, C.POINTER(Plan), P, P, C.POINTER(C.c_int32),
                                C.POINTER(Plan), _i32, P]),
     "spmv_csr_batch": (C.c_int, [P, _i32, P, P, P]),

@@ -1230,6 +1230,53 @@ extern "C" spx_status spx_batch_status(spx_matrix* H, int32_t* flags, void* stre
     return SPX_OK;
 }
 
+// ------------------------------------------------------------------ sparse output
+extern "C" spx_status spmspv_sparse(spx_matrix* H, const spx_vec* x, const uint32_t* mask, const spx_plan* plan,
+                                    int32_t* y_idx, void* y_val, int32_t* nnz_y, void* stream) {
+    if (!H || !x || !nnz_y) return fail(SPX_ERR_ARG, "null argument");
+    SPX_TRY(check_vec(H, x));
+    if (x->kind != SPX_VEC_SPARSE) return fail(SPX_ERR_ARG, "the sparse-output product takes a sparse x");
+    if (H->csr.m > 0 && !y_idx) return fail(SPX_ERR_ARG, "y_idx is null");
+    *nnz_y = 0;
+    const int dt = H->csr.dtype;
+    hipStream_t s = (hipStream_t)stream;
+    spx_plan p{};
+    if (plan) {
+        SPX_TRY(spx_check_plan(plan, dt));
+        if (plan->pattern != SPX_PAT_CSC_SPMSPV || plan->writeback != SPX_WB_BUCKET)
+            return fail(SPX_ERR_ARG, "the sparse-output product runs the column-major bucket plans");
+        p = *plan;
+    } else {
+        // the column-major distribution tree decides; the write-back is the
+        // bucket one, the only one that lists rows
+        LazyFeatures lf{H, x, s, false};
+        p.pattern = SPX_PAT_CSC_SPMSPV;
+        p.distribution = H->sel.distribution[SPX_PAT_CSC_SPMSPV].eval([&](int f) { return lf.get(f); }) ==
+                                 SPX_DIST_BALANCED
+                             ? SPX_DIST_BALANCED
+                             : SPX_DIST_DIRECT;
+        p.writeback = SPX_WB_BUCKET;
+    }
+    H->last_plan = p;
+    if (H->csr.m == 0 || x->nnz_x == 0) return SPX_OK;
+    SPX_TRY(ensure_conv(H));
+    int32_t* count = (int32_t*)(H->dev_scalars + 6);
+    SPX_TRY(fill_u32((uint32_t*)count, 0u, 1, s));
+    const SparseOut so{mask, y_idx, y_val, count};
+    const spx_csr& A = H->csr;
+    SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, x->nnz_x, dt, &p)));
+    Arena ws(H->ws, H->ws_bytes);
+    CscArgs a{A.m, A.n, A.nnz, dt, H->col_ptr, H->row_idx, H->vals_csc, A.row_ptr, H->scan_counter, -1, &so};
+    record(H, H->ev_kern, true, s);
+    SPX_TRY(launch_spmspv_csc(a, x->nnz_x, x->idx, x->val, nullptr, &p, ws, s));
+    record(H, H->ev_kern, false, s);
+    int32_t h = 0;
+    SPX_HIP(hipMemcpyAsync(&h, count, 4, hipMemcpyDeviceToHost, s));
+    SPX_HIP(hipStreamSynchronize(s));
+    *nnz_y = h;
+    return SPX_OK;
+}
+
 // ------------------------------------------------------------------ graph drivers
 static spx_status ensure_driver_counters(spx_matrix* H) {
     if (H->drv_host) return SPX_OK;

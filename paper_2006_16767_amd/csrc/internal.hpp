@@ -103,6 +103,17 @@ struct Excl {
     __host__ __device__ explicit operator bool() const { return local != nullptr; }
 };
 
+// Sparse output of the column-major SpMSpV (bucket write-back only): the
+// rows that an effective entry reaches and whose bit in mask is clear
+// (mask nullptr: none masked) go to idx / val (val may be nullptr;
+// capacity m), ascending within each bucket of rows, buckets in any order;
+// *count (device, zeroed by the caller) receives their number.
+struct SparseOut {
+    const uint32_t* mask;
+    int32_t* idx;
+    void* val;
+    int32_t* count;
+};
 struct CscArgs {
     int32_t m, n, nnz, dtype;
     const int32_t* col_ptr;
@@ -111,6 +122,7 @@ struct CscArgs {
     const int32_t* row_ptr;  // CSR row pointer of the same matrix (bucket layout); may be null
     uint32_t* scan_counter;  // handle-owned, zero between calls (the scan resets it); may be null
     int64_t nnz_s_hint;      // exact nnz_s if the host knows it, else -1
+    const SparseOut* sparse = nullptr;  // sparse output instead of a dense y
 };
 spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx,
                              const void* x_val, void* y, const spx_plan* plan, Arena& ws,

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     using Acc = typename S::Acc;
     __shared__ CscTileLds<DT> L;
     __shared__ int32_t s_tmp[kWavesPerBlock];
-    extern __shared__ int32_t s_dyn[];  // counts and offsets, NB each
+    extern __shared__ __align__(16) int32_t s_dyn[];  // counts and offsets, NB each
     int32_t* s_cnt = s_dyn;
     int32_t* s_off = s_dyn + NB;
     const int64_t nnz_s = excl[nnz_x];
@@ -180,7 +180,56 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_direct(
 constexpr int kAccThreads = 1024;
 constexpr int kAccWin = 4096;
 
+// Sparse output of one bucket (rows base .. base + R - 1): thread t lists
+// its R / kAccThreads consecutive rows that were reached (touched bit, or a
+// nonzero accumulator for the pattern semiring) and are not masked; one
+// atomic per workgroup reserves their slots. Contains __syncthreads.
 template <int DT>
+__device__ __forceinline__ void bucket_emit_sparse(const typename SR<DT>::Acc* acc, const uint32_t* touched,
+                                                   int64_t base, int R, int32_t m, const SparseOut& so) {
+    using S = SR<DT>;
+    constexpr int kWaves = kAccThreads / kWave;
+    __shared__ int32_t s_w[kWaves];
+    __shared__ int32_t s_base;
+    const int per = R >= kAccThreads ? R / kAccThreads : 1;  // at most 16
+    const int r0 = threadIdx.x * per;
+    uint32_t keep = 0;
+    if (r0 < R) {
+        for (int j = 0; j < per; ++j) {
+            const int r = r0 + j;
+            const int64_t row = base + r;
+            bool t;
+            if constexpr (S::kVals)
+                t = (touched[r >> 5] >> (r & 31)) & 1u;
+            else
+                t = acc[r] != 0u;
+            if (t && row < m && !(so.mask && ((so.mask[row >> 5] >> (row & 31)) & 1u))) keep |= 1u << j;
+        }
+    }
+    const int32_t cnt = __popc(keep);
+    const int32_t incl = wave_incl_scan(cnt);
+    if (lane_id() == kWave - 1) s_w[wave_id()] = incl;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int i = 0; i < kWaves; ++i) {
+        const int32_t t = s_w[i];
+        if (i < wave_id()) pre += t;
+        tot += t;
+    }
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(so.count, tot) : 0;
+    __syncthreads();
+    int32_t slot = s_base + pre + incl - cnt;
+    auto* val = (typename S::Y*)so.val;
+    while (keep) {
+        const int j = __ffs(keep) - 1;
+        keep &= keep - 1;
+        so.idx[slot] = (int32_t)(base + r0 + j);
+        if (val) val[slot] = S::out(acc[r0 + j]);
+        ++slot;
+    }
+}
+
+template <int DT, bool SPARSE>
 __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, int logR, int32_t nch_fixed,
                                                                    int32_t nnz_x,
                                                                    const Excl excl,
@@ -188,18 +237,23 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
                                                                    const typename SR<DT>::Acc* __restrict__ pval,
                                                                    const int32_t* __restrict__ moff,
                                                                    const int32_t* __restrict__ mcnt, int32_t stride,
-                                                                   typename SR<DT>::Y* __restrict__ y) {
+                                                                   typename SR<DT>::Y* __restrict__ y,
+                                                                   const SparseOut so) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
     constexpr int kWaves = kAccThreads / kWave;
-    extern __shared__ char s_raw[];
+    constexpr bool kTouch = SPARSE && S::kVals;  // a value can sum to 0: keep a touched bit per row
+    extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     Acc* acc = (Acc*)s_raw;
     __shared__ int32_t s_pre[kAccWin + 1];
     __shared__ int32_t s_off[kAccWin];
     __shared__ int32_t s_wsum[kWaves];
     const int R = 1 << logR;
+    uint32_t* touched = (uint32_t*)(acc + R);
     const int b = blockIdx.x;
     for (int r = threadIdx.x; r < R; r += kAccThreads) acc[r] = S::zero();
+    if constexpr (kTouch)
+        for (int w = threadIdx.x; w < (R + 31) / 32; w += kAccThreads) touched[w] = 0u;
     int64_t nch = nch_fixed;
     if (nch < 0) nch = ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);  // one chunk per merge tile
     const int32_t* mo = moff + (int64_t)b * stride;
@@ -262,20 +316,27 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
                     S::lds_atomic_add(&acc[r[u]], v[u]);
                 else
                     acc[r[u]] = 1u;
+                if constexpr (kTouch) atomicOr(&touched[r[u] >> 5], 1u << (r[u] & 31));
             }
         }
         for (; i < tot; i += kAccThreads) {
             const int q = locate(i);
+            const int rq = prow[q];
             if constexpr (S::kVals)
-                S::lds_atomic_add(&acc[prow[q]], pval[q]);
+                S::lds_atomic_add(&acc[rq], pval[q]);
             else
-                acc[prow[q]] = 1u;
+                acc[rq] = 1u;
+            if constexpr (kTouch) atomicOr(&touched[rq >> 5], 1u << (rq & 31));
         }
         __syncthreads();
     }
     const int64_t base = (int64_t)b << logR;
-    for (int r = threadIdx.x; r < R; r += kAccThreads)
-        if (base + r < m) y[base + r] = S::out(acc[r]);
+    if constexpr (SPARSE) {
+        bucket_emit_sparse<DT>(acc, touched, base, R, m, so);
+    } else {
+        for (int r = threadIdx.x; r < R; r += kAccThreads)
+            if (base + r < m) y[base + r] = S::out(acc[r]);
+    }
 }
 
 // ------------------------------------------------------------------ walk (short x)
@@ -289,22 +350,27 @@ constexpr int kWalkMaxX = 2048;       // x entries of a walk
 constexpr int64_t kWalkMaxS = 16384;  // estimated selected entries of a walk
 constexpr int kWalkScan = 32;         // columns up to this length are scanned
 
-template <int DT>
+template <int DT, bool SPARSE>
 __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR, int32_t nnz_x,
                                                              const int32_t* __restrict__ x_idx,
                                                              const typename SR<DT>::X* __restrict__ x_val,
                                                              const int32_t* __restrict__ col_ptr,
                                                              const int32_t* __restrict__ row_idx,
                                                              const typename SR<DT>::V* __restrict__ vals,
-                                                             typename SR<DT>::Y* __restrict__ y) {
+                                                             typename SR<DT>::Y* __restrict__ y,
+                                                             const SparseOut so) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
-    extern __shared__ char s_raw[];
+    constexpr bool kTouch = SPARSE && S::kVals;
+    extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     Acc* acc = (Acc*)s_raw;
     const int R = 1 << logR;
+    uint32_t* touched = (uint32_t*)(acc + R);
     const int b = blockIdx.x;
     const int lo = b << logR, hi = lo + R;
     for (int r = threadIdx.x; r < R; r += kAccThreads) acc[r] = S::zero();
+    if constexpr (kTouch)
+        for (int w = threadIdx.x; w < (R + 31) / 32; w += kAccThreads) touched[w] = 0u;
     __syncthreads();
     for (int e = threadIdx.x; e < nnz_x; e += kAccThreads) {
         const int j = x_idx[e];
@@ -332,12 +398,17 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
                     S::lds_atomic_add(&acc[r - lo], S::mul(S::val(vals, k), v));
                 else
                     acc[r - lo] = 1u;
+                if constexpr (kTouch) atomicOr(&touched[(r - lo) >> 5], 1u << ((r - lo) & 31));
             }
         }
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < R; r += kAccThreads)
-        if (lo + r < m) y[lo + r] = S::out(acc[r]);
+    if constexpr (SPARSE) {
+        bucket_emit_sparse<DT>(acc, touched, lo, R, m, so);
+    } else {
+        for (int r = threadIdx.x; r < R; r += kAccThreads)
+            if (lo + r < m) y[lo + r] = S::out(acc[r]);
+    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -428,10 +499,17 @@ static spx_status launch_bucket_t(const CscArgs& A, int32_t nnz_x, const int32_t
         }
     }
     SPX_HIP(hipGetLastError());
-    const size_t lds = ((size_t)1 << g.logR) * sizeof(Acc);
-    k_bucket_accumulate<DT><<<(unsigned)g.NB, kAccThreads, lds, s>>>(A.m, g.logR, nch_fixed, nnz_x, excl,
-                                                                     out.prow, out.pval, out.moff, out.mcnt,
-                                                                     out.stride, y);
+    const size_t R = (size_t)1 << g.logR;
+    if (A.sparse) {
+        const size_t lds = R * sizeof(Acc) + (S::kVals ? ceil_div(R, 32) * 4 : 0);
+        k_bucket_accumulate<DT, true><<<(unsigned)g.NB, kAccThreads, lds, s>>>(
+            A.m, g.logR, nch_fixed, nnz_x, excl, out.prow, out.pval, out.moff, out.mcnt, out.stride, nullptr,
+            *A.sparse);
+    } else {
+        k_bucket_accumulate<DT, false><<<(unsigned)g.NB, kAccThreads, R * sizeof(Acc), s>>>(
+            A.m, g.logR, nch_fixed, nnz_x, excl, out.prow, out.pval, out.moff, out.mcnt, out.stride, y,
+            SparseOut{});
+    }
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }
@@ -454,10 +532,17 @@ static spx_status launch_walk_t(const CscArgs& A, int32_t nnz_x, const int32_t* 
     BucketGeom g;
     if (!bucket_geometry(A.m, DT, plan->bucket_rows, &g))
         return fail(SPX_ERR_UNSUPPORTED, "bucket write-back: rows per bucket must fit 64 KiB of LDS and at most 4096 buckets");
-    const size_t lds = ((size_t)1 << g.logR) * sizeof(typename S::Acc);
-    k_bucket_walk<DT><<<(unsigned)g.NB, kAccThreads, lds, s>>>(A.m, g.logR, nnz_x, x_idx,
-                                                              (const typename S::X*)x_val, A.col_ptr, A.row_idx,
-                                                              (const typename S::V*)A.vals, (typename S::Y*)y);
+    const size_t R = (size_t)1 << g.logR;
+    if (A.sparse) {
+        const size_t lds = R * sizeof(typename S::Acc) + (S::kVals ? ceil_div(R, 32) * 4 : 0);
+        k_bucket_walk<DT, true><<<(unsigned)g.NB, kAccThreads, lds, s>>>(
+            A.m, g.logR, nnz_x, x_idx, (const typename S::X*)x_val, A.col_ptr, A.row_idx,
+            (const typename S::V*)A.vals, nullptr, *A.sparse);
+    } else {
+        k_bucket_walk<DT, false><<<(unsigned)g.NB, kAccThreads, R * sizeof(typename S::Acc), s>>>(
+            A.m, g.logR, nnz_x, x_idx, (const typename S::X*)x_val, A.col_ptr, A.row_idx,
+            (const typename S::V*)A.vals, (typename S::Y*)y, SparseOut{});
+    }
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_direct_lds(int32_t m, int32_t nn
                                                            const typename SR<DT>::V* __restrict__ vals,
                                                            typename SR<DT>::Y* __restrict__ y) {
     using S = SR<DT>;
-    extern __shared__ char s_raw[];
+    extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     auto* sy = (typename S::Acc*)s_raw;
     for (int r = threadIdx.x; r < m; r += kBlock) sy[r] = S::zero();
     __syncthreads();
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz
                                                           typename SR<DT>::Y* __restrict__ y) {
     using S = SR<DT>;
     __shared__ CscTileLds<DT> L;
-    extern __shared__ char s_raw[];
+    extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     auto* sy = (typename S::Acc*)s_raw;
     for (int r = threadIdx.x; r < m; r += kBlock) sy[r] = S::zero();
     __syncthreads();
@@ -449,13 +449,16 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int dist = plan->distribution;
     const size_t ybytes = (size_t)A.m * sizeof(typename S::Y);
     if (A.m == 0) return SPX_OK;
+    if (A.sparse && wb != SPX_WB_BUCKET) return fail(SPX_ERR_ARG, "sparse output needs the bucket write-back");
+    if (A.sparse && nnz_x == 0) return SPX_OK;  // nothing reached; the caller zeroed the count
     if (nnz_x > 0 && csc_bucket_walks(A, nnz_x, plan)) return launch_csc_bucket_walk(A, nnz_x, x_idx, x_val_v, y_v, plan, s);
     const int L = plan->lanes > 0 ? plan->lanes : pick_col_lanes(A.n, A.nnz);
     const bool lds_ok = (int64_t)A.m * (int64_t)sizeof(Acc) <= kLdsBytes;
     if (wb == SPX_WB_LDS_ATOMIC && !lds_ok && nnz_x > 0)
         return fail(SPX_ERR_UNSUPPORTED, "lds-atomic write-back needs m * sizeof(acc) <= 64 KiB");
-    // the bucket write-back writes every row itself
-    const bool fill_y = wb != SPX_WB_BUCKET || nnz_x == 0;
+    // the bucket write-back writes every row itself (or, for a sparse
+    // output, only the rows it lists)
+    const bool fill_y = !A.sparse && (wb != SPX_WB_BUCKET || nnz_x == 0);
     const bool need_excl = nnz_x > 0 && (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET);
     int32_t* excl = nullptr;
     Excl ex{nullptr, nullptr};

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBitThreads) void k_csr_bitlds(int32_t m, int32_t n
     using Acc = typename S::Acc;
     constexpr int kWaves = kBitThreads / kWave;
     constexpr int kIpt = kBitTile / kBitThreads;
-    extern __shared__ uint32_t s_bits[];
+    extern __shared__ __align__(16) uint32_t s_bits[];
     __shared__ int32_t s_end[kBitTile + 1];
     __shared__ Acc s_prod[kBitTile];
     __shared__ int32_t s_lng[kBitTile + 1];
