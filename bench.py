@@ -219,6 +219,41 @@ def extra_pagerank(torch, spx, synth, reps=3):
     return out
 
 
+def extra_sparse_output(torch, spx, synth, reps=20):
+    """Sparse-output SpMSpV (row list, no dense y) against run() with its
+    dense y, on the R-MAT 2^20 sweep vectors up to 1 % density: kernel time
+    from the library's HIP events around each call's launches (the dense
+    y's zero fill included on the dense side; on the sparse side the count
+    read-back is not a kernel)."""
+    A = synth.cfg2_matrix()
+    M = spx.Matrix.from_host(A)
+    vecs = synth.cfg2_vectors(A.n)
+    y = M.out_tensor()
+    out = {"workload": "rmat20_deg16_f32_sparse_output", "nnz_x": [], "dense_us": [], "sparse_us": [],
+           "rows_listed": []}
+    for v in vecs:
+        if v.nnz > A.n // 100:
+            break
+        x = (torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda"))
+        M.run(x, y)
+        rows, _ = M.spmspv_sparse(x)
+        torch.cuda.synchronize()
+        M.set_profiling(True)
+        M.run_times()
+        for _ in range(reps):
+            M.run(x, y)
+        dense = M.run_times()
+        for _ in range(reps):
+            M.spmspv_sparse(x)
+        sparse = M.run_times()
+        M.set_profiling(False)
+        out["nnz_x"].append(v.nnz)
+        out["dense_us"].append(round(1e3 * sorted(dense)[len(dense) // 2], 2))
+        out["sparse_us"].append(round(1e3 * sorted(sparse)[len(sparse) // 2], 2))
+        out["rows_listed"].append(int(rows.numel()))
+    return out
+
+
 def extra_bfs(torch, spx, synth, reps=3):
     """Breadth-first search on the R-MAT 2^20 graph (pattern): one adaptive
     SpMSpV per level (with and without the masked-pull levels) against
@@ -375,7 +410,7 @@ def main():
         extras = {}
         for name, fn in (("poisson_spmv", extra_poisson), ("batched_vs_looped", extra_batched),
                          ("fwd_vs_fwd_bwd", extra_fwd_bwd), ("bfs", extra_bfs),
-                         ("pagerank", extra_pagerank)):
+                         ("pagerank", extra_pagerank), ("sparse_output", extra_sparse_output)):
             print(f"[bench] extra: {name}", file=sys.stderr, flush=True)
             extras[name] = fn(torch, spx, synth)
         rec["extras"] = extras
