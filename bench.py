@@ -224,13 +224,38 @@ def extra_sparse_output(torch, spx, synth, reps=20):
     dense y, on the R-MAT 2^20 sweep vectors up to 1 % density: kernel time
     from the library's HIP events around each call's launches (the dense
     y's zero fill included on the dense side; on the sparse side the count
-    read-back is not a kernel)."""
+    read-back is not a kernel). A consumer that needs the list (frontier
+    chaining) must compact the dense y: the wall time of run() followed by
+    the library's dense-to-sparse conversion and the count read-back is
+    given beside the sparse call's wall time (both end with the count on
+    the host)."""
+    from paper_2006_16767_amd import _lib
     A = synth.cfg2_matrix()
     M = spx.Matrix.from_host(A)
     vecs = synth.cfg2_vectors(A.n)
     y = M.out_tensor()
+    vp = torch.empty(2, dtype=torch.int32, device="cuda")
+    li = torch.empty(A.m, dtype=torch.int32, device="cuda")
+    lv = torch.empty(A.m, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def dense_then_list(x):
+        M.run(x, y)
+        _lib.call("spx_dense_rows_to_sparse", M._h, 1, y.data_ptr(), vp.data_ptr(), li.data_ptr(),
+                  lv.data_ptr(), stream)
+        return int(vp[1].item())
+
+    def wall_us(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return round((time.perf_counter() - t0) / reps * 1e6, 1)
+
     out = {"workload": "rmat20_deg16_f32_sparse_output", "nnz_x": [], "dense_us": [], "sparse_us": [],
-           "rows_listed": []}
+           "dense_then_list_wall_us": [], "sparse_wall_us": [], "rows_listed": []}
     for v in vecs:
         if v.nnz > A.n // 100:
             break
@@ -247,6 +272,8 @@ def extra_sparse_output(torch, spx, synth, reps=20):
             M.spmspv_sparse(x)
         sparse = M.run_times()
         M.set_profiling(False)
+        out["dense_then_list_wall_us"].append(wall_us(lambda: dense_then_list(x)))
+        out["sparse_wall_us"].append(wall_us(lambda: M.spmspv_sparse(x)))
         out["nnz_x"].append(v.nnz)
         out["dense_us"].append(round(1e3 * sorted(dense)[len(dense) // 2], 2))
         out["sparse_us"].append(round(1e3 * sorted(sparse)[len(sparse) // 2], 2))

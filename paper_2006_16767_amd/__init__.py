@@ -280,6 +280,20 @@ class Matrix:
             self.values_updated(stream)
             self._vals_version = ver
 
+    def dense_rows_to_sparse(self, X, stream=None):
+        """The rows of a dense X (B x n, the matrix dtype) as CSR-of-vectors:
+        (vec_ptr int32[B+1], idx, val) on the device, trimmed to vec_ptr[B]."""
+        torch = _torch()
+        X2 = X.reshape(-1, self.n).contiguous()
+        B = int(X2.shape[0])
+        vp = torch.empty(B + 1, dtype=torch.int32, device=X.device)
+        idx = torch.empty(max(1, B * self.n), dtype=torch.int32, device=X.device)
+        val = None if self.dtype == BOOL else torch.empty(max(1, B * self.n), dtype=X.dtype, device=X.device)
+        _lib.call("spx_dense_rows_to_sparse", self._h, B, _ptr(X2), _ptr(vp), _ptr(idx), _ptr(val),
+                  _stream(stream))
+        k = int(vp[B].item())
+        return vp, idx[:k], (val[:k] if val is not None else None)
+
     def run_dense_batch(self, X, Y=None, stream=None):
         """Y[b] = A X[b] for the rows of a dense X (B x n): the rows become
         sparse vectors on the device, then run_batch."""

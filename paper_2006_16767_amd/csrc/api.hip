@@ -1257,6 +1257,15 @@ extern "C" spx_status spmspv_sparse(spx_matrix* H, const spx_vec* x, const uint3
                              : SPX_DIST_DIRECT;
         p.writeback = SPX_WB_BUCKET;
     }
+    // each bucket that lists rows takes one atomic on the shared count, and
+    // atomics on one word serialize: the fewest, largest buckets that fit
+    // LDS (a quarter of the default count at m = 2^20)
+    if (p.bucket_rows <= 0) {
+        const int asz = dt == SPX_F64 ? 8 : 4;
+        int R = 64;
+        while (R < 65536 / asz && R < H->csr.m) R <<= 1;
+        p.bucket_rows = R;
+    }
     H->last_plan = p;
     if (H->csr.m == 0 || x->nnz_x == 0) return SPX_OK;
     SPX_TRY(ensure_conv(H));
@@ -1561,7 +1570,7 @@ extern "C" spx_status spx_dense_rows_to_sparse(spx_matrix* H, int32_t B, const v
     if (!H || (B > 0 && (!X || !vec_ptr || !idx || (H->csr.dtype != SPX_BOOL && !val))))
         return fail(SPX_ERR_ARG, "null argument");
     if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
-    SPX_TRY(ensure_ws(H, scan_ws_elems((int64_t)B + 1) * 4 + 256));
-    return dense_rows_to_sparse(B, H->csr.n, H->csr.dtype, X, vec_ptr, idx, val, (int32_t*)H->ws,
-                                (hipStream_t)stream);
+    SPX_TRY(ensure_ws(H, dense_rows_ws_bytes(B, H->csr.n)));
+    Arena ws(H->ws, H->ws_bytes);
+    return dense_rows_to_sparse(B, H->csr.n, H->csr.dtype, X, vec_ptr, idx, val, ws, (hipStream_t)stream);
 }

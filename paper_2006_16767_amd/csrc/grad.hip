@@ -229,61 +229,102 @@ spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t 
 
 // ------------------------------------------------------------------ dense rows -> sparse vectors
 // B dense rows of length n (x != 0 is a nonzero: -0.0 is zero, NaN is not)
-// become CSR-of-vectors: counts per row, a prefix over rows, then each row
-// compacted in index order by one workgroup.
+// become CSR-of-vectors. Every row is cut into tiles of kRowTile entries so
+// that a long row spreads over many workgroups: a count per tile, one
+// exclusive scan over all tiles (row after row), then each tile compacts
+// its entries in index order at its offset; the first tile of a row writes
+// the row's start, the last tile of the last row the total.
+constexpr int kRowTile = kBlock * 8;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_row_nnz(int32_t n, const T* __restrict__ X, int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(kBlock) void k_tile_nnz(int32_t n, int32_t tpr, const T* __restrict__ X,
+                                                     int32_t* __restrict__ cnt) {
     __shared__ int32_t s_tmp[kWavesPerBlock];
-    const T* x = X + (int64_t)blockIdx.x * n;
+    const int64_t t = blockIdx.x;
+    const int64_t b = t / tpr;
+    const int64_t j0 = (t - b * tpr) * kRowTile;
+    const T* x = X + b * n;
     int32_t c = 0;
-    for (int j = threadIdx.x; j < n; j += kBlock) c += x[j] != (T)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + u * kBlock + threadIdx.x;
+        c += j < n && x[j] != (T)0;
+    }
     int32_t tot;
     block_incl_scan(c, s_tmp, &tot);
-    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+    if (threadIdx.x == 0) cnt[t] = tot;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_row_compact(int32_t n, const T* __restrict__ X,
-                                                        const int32_t* __restrict__ vec_ptr, int32_t* __restrict__ idx,
-                                                        T* __restrict__ val) {
+__global__ __launch_bounds__(kBlock) void k_tile_compact(int32_t B, int32_t n, int32_t tpr, const T* __restrict__ X,
+                                                         const int32_t* __restrict__ off,
+                                                         int32_t* __restrict__ vec_ptr, int32_t* __restrict__ idx,
+                                                         T* __restrict__ val) {
     __shared__ int32_t s_tmp[kWavesPerBlock];
-    const T* x = X + (int64_t)blockIdx.x * n;
-    int32_t carry = vec_ptr[blockIdx.x];
-    for (int j0 = 0; j0 < n; j0 += kBlock) {
-        const int j = j0 + threadIdx.x;
-        const T v = j < n ? x[j] : (T)0;
-        const int32_t f = (j < n && v != (T)0) ? 1 : 0;
-        int32_t tot;
-        const int32_t incl = block_incl_scan(f, s_tmp, &tot);
-        if (f) {
-            idx[carry + incl - 1] = j;
-            if (val) val[carry + incl - 1] = v;
-        }
-        carry += tot;
+    const int64_t t = blockIdx.x;
+    const int64_t b = t / tpr;
+    const int64_t tile = t - b * tpr;
+    const int64_t j0 = tile * kRowTile + (int64_t)threadIdx.x * 8;  // 8 consecutive entries per thread
+    const T* x = X + b * n;
+    T v[8];
+    uint32_t f = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + u;
+        v[u] = j < n ? x[j] : (T)0;
+        if (j < n && v[u] != (T)0) f |= 1u << u;
+    }
+    const int32_t c = __popc(f);
+    int32_t tot;
+    const int32_t incl = block_incl_scan(c, s_tmp, &tot);
+    int32_t slot = off[t] + incl - c;
+    while (f) {
+        const int u = __ffs(f) - 1;
+        f &= f - 1;
+        idx[slot] = (int32_t)(j0 + u);
+        if (val) val[slot] = v[u];
+        ++slot;
+    }
+    if (threadIdx.x == 0) {
+        if (tile == 0) vec_ptr[b] = off[t];
+        if (t == (int64_t)B * tpr - 1) vec_ptr[B] = off[t] + tot;
     }
 }
 
 template <typename T>
 static spx_status rows_to_sparse_t(int32_t B, int32_t n, const void* X, int32_t* vec_ptr, int32_t* idx, void* val,
-                                   int32_t* ws_i32, hipStream_t s) {
-    k_row_nnz<T><<<B, kBlock, 0, s>>>(n, (const T*)X, vec_ptr);
+                                   Arena& ws, hipStream_t s) {
+    const int32_t tpr = (int32_t)std::max<int64_t>(1, ceil_div(n, kRowTile));
+    const int64_t tiles = (int64_t)B * tpr;
+    int32_t* off = ws.take<int32_t>((size_t)tiles + 1);
+    int32_t* sws = ws.take<int32_t>(scan_ws_elems(tiles + 1));
+    if (!off || !sws) return fail(SPX_ERR_WORKSPACE, "dense rows: workspace too small");
+    SPX_TRY(fill_u32((uint32_t*)(off + tiles), 0u, 1, s));
+    k_tile_nnz<T><<<(unsigned)tiles, kBlock, 0, s>>>(n, tpr, (const T*)X, off);
     SPX_HIP(hipGetLastError());
-    SPX_TRY(scan_exclusive_i32(vec_ptr, vec_ptr, (int64_t)B + 1, nullptr, ws_i32, s));
-    k_row_compact<T><<<B, kBlock, 0, s>>>(n, (const T*)X, vec_ptr, idx, (T*)val);
+    SPX_TRY(scan_exclusive_i32(off, off, tiles + 1, nullptr, sws, s));
+    k_tile_compact<T><<<(unsigned)tiles, kBlock, 0, s>>>(B, n, tpr, (const T*)X, off, vec_ptr, idx, (T*)val);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }
 
+size_t dense_rows_ws_bytes(int32_t B, int32_t n) {
+    const int64_t tiles = (int64_t)B * std::max<int64_t>(1, ceil_div(n, kRowTile));
+    Sizer z;
+    z.take<int32_t>((size_t)tiles + 1);
+    z.take<int32_t>(scan_ws_elems(tiles + 1));
+    return z.used;
+}
+
 spx_status dense_rows_to_sparse(int32_t B, int32_t n, int dtype, const void* X, int32_t* vec_ptr, int32_t* idx,
-                                void* val, int32_t* ws_i32, hipStream_t s) {
+                                void* val, Arena& ws, hipStream_t s) {
     if (B == 0) return fill_u32((uint32_t*)vec_ptr, 0, 1, s);
-    // vec_ptr[B] must be 0 before the scan turns counts into offsets
-    SPX_TRY(fill_u32((uint32_t*)(vec_ptr + B), 0, 1, s));
+    if (n == 0) return fill_u32((uint32_t*)vec_ptr, 0, (size_t)B + 1, s);
     switch (dtype) {
-        case SPX_F32: return rows_to_sparse_t<float>(B, n, X, vec_ptr, idx, val, ws_i32, s);
-        case SPX_F64: return rows_to_sparse_t<double>(B, n, X, vec_ptr, idx, val, ws_i32, s);
-        case SPX_I32: return rows_to_sparse_t<int32_t>(B, n, X, vec_ptr, idx, val, ws_i32, s);
-        case SPX_BOOL: return rows_to_sparse_t<uint8_t>(B, n, X, vec_ptr, idx, nullptr, ws_i32, s);
+        case SPX_F32: return rows_to_sparse_t<float>(B, n, X, vec_ptr, idx, val, ws, s);
+        case SPX_F64: return rows_to_sparse_t<double>(B, n, X, vec_ptr, idx, val, ws, s);
+        case SPX_I32: return rows_to_sparse_t<int32_t>(B, n, X, vec_ptr, idx, val, ws, s);
+        case SPX_BOOL: return rows_to_sparse_t<uint8_t>(B, n, X, vec_ptr, idx, nullptr, ws, s);
     }
     return fail(SPX_ERR_DTYPE, "dense rows: dtype");
 }

@@ -264,6 +264,7 @@ spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t 
 // B dense rows of length n -> CSR-of-vectors (vec_ptr[B+1], idx, val);
 // ws_i32: scan_ws_elems(B + 1) int32
 spx_status dense_rows_to_sparse(int32_t B, int32_t n, int dtype, const void* X, int32_t* vec_ptr,
-                                int32_t* idx, void* val, int32_t* ws_i32, hipStream_t s);
+                                int32_t* idx, void* val, Arena& ws, hipStream_t s);
+size_t dense_rows_ws_bytes(int32_t B, int32_t n);
 
 }  // namespace spx

@@ -182,3 +182,30 @@ def test_batch_fused_groups(kind):
             v = vecs[b]
             ref, S = reference(A, v.idx, np.asarray(v.val, npdt), kind)
             assert_close(Y2[b], ref, S, kind, f"fused rerun {name} {kind} b={b}")
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (3, 100), (2, 2049), (64, 4096), (1, 1 << 20)])
+def test_dense_rows_to_sparse(B, n):
+    """Compaction of dense rows (long rows span many workgroups): indices in
+    order and values exactly as numpy's nonzero finds them; -0.0 is a zero,
+    NaN a nonzero; empty rows keep an empty range."""
+    torch = _torch()
+    rng = np.random.default_rng(B * 7 + n)
+    X = rng.standard_normal((B, n)).astype(np.float32)
+    X[rng.random((B, n)) < 0.7] = 0.0
+    X[0, :: max(1, n // 5)] = -0.0
+    if n > 3:
+        X[0, 3] = np.nan
+    if B > 1:
+        X[1] = 0.0
+    A = synth.random_csr(4, n, 0.5, 1)
+    M = spx.Matrix.from_host(A)
+    vp, idx, val = M.dense_rows_to_sparse(torch.as_tensor(X, device="cuda"))
+    vp, idx, val = vp.cpu().numpy(), idx.cpu().numpy(), val.cpu().numpy()
+    assert vp[0] == 0
+    for b in range(B):
+        nz = np.nonzero(X[b] != 0)[0]  # NaN != 0 holds, -0.0 != 0 does not
+        assert np.array_equal(idx[vp[b]:vp[b + 1]], nz)
+        got, want = val[vp[b]:vp[b + 1]], X[b, nz]
+        assert np.array_equal(np.isnan(got), np.isnan(want))
+        assert np.array_equal(got[~np.isnan(got)], want[~np.isnan(want)])
