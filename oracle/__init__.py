@@ -25,6 +25,7 @@ _lib = None
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 
 
 def _load():
@@ -42,6 +43,7 @@ def _load():
         "oracle_transpose": [i32, i32, _i32p, _i32p, vp, _i32p, _i32p, vp, vp],
         "oracle_spmspv_csc": [i32, i32, _i32p, _i32p, _f64p, i32, _i32p, _f64p, _f64p, vp],
         "oracle_bool_spmspv": [i32, i32, _i32p, _i32p, i32, _i32p, _u8p],
+        "oracle_minplus_spmv": [i32, i32, _i32p, _i32p, _f32p, _f32p, _f32p],
         "oracle_int_spmv": [i32, i32, _i32p, _i32p, _i32p, _i32p, _i32p],
         "oracle_int_spmspv_csc": [i32, i32, _i32p, _i32p, _i32p, i32, _i32p, _i32p, _i32p],
         "oracle_grad": [i32, i32, _i32p, _i32p, _f64p, i32, _f64p, _f64p, vp, vp, vp],
@@ -282,3 +284,25 @@ def spmspv_sparse(A, x_idx, x_val=None, mask=None, kind="f64"):
     csc = transpose(A)
     y, s = spmspv(csc, x_idx, x_val)
     return rows, y[rows], s[rows]
+
+
+def minplus_spmv(A, x):
+    """Min-plus product over float32: y_i = min over stored (i, j) of
+    (a_ij + x_j) with x_j = +inf meaning absent; +inf where nothing is
+    effective (shortest-path relaxation, the semiring extension of the
+    paper's closing section)."""
+    lib = _load()
+    y = np.empty(A.m, np.float32)
+    _check(lib.oracle_minplus_spmv(A.m, A.n, _i32(A.row_ptr), _i32(A.col_idx),
+                                   np.ascontiguousarray(A.vals, dtype=np.float32),
+                                   np.ascontiguousarray(x, dtype=np.float32), y), "oracle_minplus_spmv")
+    return y
+
+
+def minplus_spmspv(A, x_idx, x_val):
+    """The sparse-x form: SpMV with the absent entries at +inf (the semiring
+    zero), so SpMSpV equals SpMV with the zero-filled vector, as it does in
+    the other semirings."""
+    x = np.full(A.n, np.inf, np.float32)
+    x[np.asarray(x_idx, np.int64)] = np.asarray(x_val, np.float32)
+    return minplus_spmv(A, x)

@@ -176,6 +176,33 @@ int oracle_bool_spmspv(int32_t m, int32_t n, const int32_t *row_ptr, const int32
 }
 
 /* ---------------------------------------------------------------------
+ * Min-plus semiring over float32 (shortest-path relaxation):
+ * y_i = min over the stored entries (i, j) with x_j present of
+ * (a_ij + x_j), each sum one float32 addition (correctly rounded, so the
+ * result does not depend on the order of the minimum); +inf when no entry
+ * is effective. A dense x marks an absent entry by +inf; a sparse x lists
+ * the present ones (any other index is absent).
+ * ------------------------------------------------------------------- */
+int oracle_minplus_spmv(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        const float *vals, const float *x, float *y)
+{
+    (void)n;
+    for (int32_t i = 0; i < m; ++i) {
+        float best = INFINITY;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const float xj = x[col_idx[k]];
+            if (xj == INFINITY)
+                continue;
+            const volatile float sum = vals[k] + xj; /* one float32 rounding */
+            if (sum < best)
+                best = sum;
+        }
+        y[i] = best;
+    }
+    return OK;
+}
+
+/* ---------------------------------------------------------------------
  * O4: integer (+, x) semiring modulo 2^32, reinterpreted as int32.
  * Unsigned arithmetic, so wrap-around is defined.
  * SpMV over CSR, and SpMSpV as the column scatter of O2b.

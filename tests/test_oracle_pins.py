@@ -626,3 +626,90 @@ def test_sparse_output_pin_catches_numeric_listing(monkeypatch):
         mp.setattr(oracle, "bool_spmspv", numeric)
         rows, _, _ = oracle.spmspv_sparse(A, [0, 2], [1.0, 1.0])
     assert rows.tolist() != [0, 1, 2, 3]
+
+
+# ---------------------------------------------------------------- min-plus semiring
+def test_minplus_hand_worked():
+    """A (3 x 3): (0, 2) 1.5; (1, 0) 2.0, (1, 2) 0.25; (2, 1) 3.0; x = [0, inf, 1].
+    Row 0: 1.5 + 1 = 2.5. Row 1: min(2 + 0, 0.25 + 1) = 1.25. Row 2 reads only
+    the absent x_1: +inf."""
+    A = _mat(3, 3, [0, 1, 3, 4], [2, 0, 2, 1], [1.5, 2.0, 0.25, 3.0])
+    y = oracle.minplus_spmv(A, np.array([0.0, np.inf, 1.0], np.float32))
+    assert y.tolist() == [2.5, 1.25, np.inf]
+    y = oracle.minplus_spmspv(A, [0, 2], [0.0, 1.0])
+    assert y.tolist() == [2.5, 1.25, np.inf]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_minplus_brute_force_float32(seed):
+    """Against a dense table of float32 sums a_ij + x_j (numpy float32
+    adds, one rounding each) and their minimum: bit-exact."""
+    rng = np.random.default_rng(seed)
+    A = synth.random_csr(40, 30, 0.15, 70 + seed, empty_rows=0.2)
+    x = rng.uniform(-2, 2, A.n).astype(np.float32)
+    x[rng.random(A.n) < 0.3] = np.inf
+    want = np.full(A.m, np.inf, np.float32)
+    for i in range(A.m):
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            j = A.col_idx[k]
+            if np.isfinite(x[j]):
+                want[i] = min(want[i], np.float32(np.float32(A.vals[k]) + x[j]))
+    assert np.array_equal(oracle.minplus_spmv(A, x), want)
+
+
+def _bellman_ford(A, source, prod):
+    d = np.full(A.n, np.inf, np.float32)
+    d[source] = 0.0
+    for _ in range(A.n):
+        nd = np.minimum(d, prod(A, d))
+        if np.array_equal(nd, d):
+            break
+        d = nd
+    return d
+
+
+def test_minplus_relaxation_is_shortest_paths():
+    """Entry (i, j) is the edge j -> i, so repeated relaxation d = min(d, A (x) d)
+    from a source reaches scipy's Dijkstra distances on the graph A^T, exactly
+    (integer weights are exact in float32)."""
+    from scipy.sparse.csgraph import dijkstra
+    rng = np.random.default_rng(9)
+    n = 60
+    src = rng.integers(0, n, 300)
+    dst = rng.integers(0, n, 300)
+    key = np.unique(dst.astype(np.int64) * n + src)
+    w = rng.integers(1, 20, key.size).astype(np.float32)
+    A = synth._coo_to_csr(n, n, key // n, key % n, w)
+    G = sp.csr_matrix((np.asarray(A.vals, np.float64), A.col_idx, A.row_ptr), shape=(n, n)).T.tocsr()
+    for s0 in (0, 7, 33):
+        want = dijkstra(G, directed=True, indices=s0)
+        got = _bellman_ford(A, s0, oracle.minplus_spmv)
+        assert np.array_equal(got.astype(np.float64), want)
+
+
+def test_minplus_pins_catch_planted_mistakes(monkeypatch):
+    """A transposed product (edges read the wrong way) breaks the
+    shortest-path pin; a sum instead of the minimum breaks the hand-worked
+    one."""
+    from scipy.sparse.csgraph import dijkstra
+    A = _mat(3, 3, [0, 1, 3, 4], [2, 0, 2, 1], [1.5, 2.0, 0.25, 3.0])
+    T = _mat(3, 3, [0, 1, 2, 4], [1, 2, 0, 1], [2.0, 3.0, 1.5, 0.25])  # A^T
+    G = sp.csr_matrix((np.asarray(A.vals, np.float64), A.col_idx, A.row_ptr), shape=(3, 3)).T.tocsr()
+    want = dijkstra(G, directed=True, indices=0)
+    good = oracle.minplus_spmv
+    with monkeypatch.context() as mp:
+        mp.setattr(oracle, "minplus_spmv", lambda M, x: good(T, x))
+        got = _bellman_ford(A, 0, lambda M, d: oracle.minplus_spmv(M, d))
+    assert not np.array_equal(got.astype(np.float64), want)
+
+    def summed(M, x):
+        y = np.zeros(M.m, np.float32)
+        for i in range(M.m):
+            for k in range(M.row_ptr[i], M.row_ptr[i + 1]):
+                if np.isfinite(x[M.col_idx[k]]):
+                    y[i] += M.vals[k] + x[M.col_idx[k]]
+        return y
+    with monkeypatch.context() as mp:
+        mp.setattr(oracle, "minplus_spmv", summed)
+        got = oracle.minplus_spmv(A, np.array([0.0, np.inf, 1.0], np.float32))
+    assert got.tolist() != [2.5, 1.25, np.inf]
