@@ -70,7 +70,15 @@ typedef int spx_status;
 #define SPX_ERR_HIP (-7)          /* a HIP runtime call failed */
 #define SPX_ERR_WORKSPACE (-8)    /* workspace missing or smaller than required */
 
-typedef enum { SPX_F32 = 0, SPX_F64 = 1, SPX_BOOL = 2, SPX_I32 = 3 } spx_dtype;
+/* Value type and semiring of a handle. SPX_F32_MINPLUS is (min, +) over
+ * float32 (the shortest-path relaxation; a semiring beyond the paper's):
+ * y_i = min over the effective entries (i, j) of (a_ij + x_j), each sum one
+ * float32 addition, +inf where none is effective; a dense x marks an absent
+ * entry by +inf (the semiring's zero), a sparse x lists the present ones.
+ * It runs the row- and column-major kernels of run()/run_plan() and the
+ * sparse output; the batched path, the backward and the graph drivers
+ * refuse it (SPX_ERR_DTYPE). */
+typedef enum { SPX_F32 = 0, SPX_F64 = 1, SPX_BOOL = 2, SPX_I32 = 3, SPX_F32_MINPLUS = 4 } spx_dtype;
 
 /* Computing pattern (Section 4.1). */
 typedef enum {

@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
+from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F32_MINPLUS, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
                    PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
                    WB_SORT, Plan, SpxError)
 
@@ -61,7 +61,8 @@ def dtype_code(t) -> int:
 
 def torch_dtype(code: int):
     torch = _torch()
-    return {F32: torch.float32, F64: torch.float64, I32: torch.int32, BOOL: torch.uint8}[code]
+    return {F32: torch.float32, F64: torch.float64, I32: torch.int32, BOOL: torch.uint8,
+            F32_MINPLUS: torch.float32}[code]
 
 
 def _ptr(t):
@@ -150,7 +151,7 @@ class Matrix:
             v = torch.as_tensor(A.vals, device=device)
             if dtype is not None:
                 v = v.to(torch_dtype(dtype))
-            dt = dtype_code(v.dtype)
+            dt = dtype_code(v.dtype) if dtype is None else dtype  # F32_MINPLUS shares float32
         return cls(rp, ci, v, A.m, A.n, dt, validate=validate, renumber=renumber)
 
     def close(self):

@@ -17,7 +17,7 @@ ERRORS = {
     -5: "SPX_ERR_UNSUPPORTED", -6: "SPX_ERR_ALLOC", -7: "SPX_ERR_HIP", -8: "SPX_ERR_WORKSPACE",
 }
 
-F32, F64, BOOL, I32 = 0, 1, 2, 3
+F32, F64, BOOL, I32, F32_MINPLUS = 0, 1, 2, 3, 4
 PAT_SPMV, PAT_CSR_SPMSPV, PAT_CSC_SPMSPV = 0, 1, 2
 DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET = 0, 1, 2, 3, 4

@@ -38,6 +38,7 @@ int value_size(int dtype) {
     switch (dtype) {
         case SPX_F32:
         case SPX_I32:
+        case SPX_F32_MINPLUS:
             return 4;
         case SPX_F64:
             return 8;
@@ -50,6 +51,7 @@ int out_size(int dtype) {
     switch (dtype) {
         case SPX_F32:
         case SPX_I32:
+        case SPX_F32_MINPLUS:
             return 4;
         case SPX_F64:
             return 8;
@@ -60,7 +62,13 @@ int out_size(int dtype) {
     }
 }
 
-static bool valid_dtype(int dt) { return dt == SPX_F32 || dt == SPX_F64 || dt == SPX_I32 || dt == SPX_BOOL; }
+static bool valid_dtype(int dt) {
+    return dt == SPX_F32 || dt == SPX_F64 || dt == SPX_I32 || dt == SPX_BOOL || dt == SPX_F32_MINPLUS;
+}
+
+// 32-bit word of the semiring's zero (the fill of a y that atomics update,
+// and of an x that absent entries leave unwritten)
+uint32_t zero_word(int dtype) { return dtype == SPX_F32_MINPLUS ? 0x7f800000u : 0u; }
 
 static int key_bits_for(int32_t n) {
     int b = 0;
@@ -136,7 +144,7 @@ template <int DT>
 __global__ __launch_bounds__(kBlock) void k_dense_bits(int32_t n, const typename SR<DT>::X* __restrict__ x,
                                                        uint32_t* __restrict__ bits) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool nz = j < n && x[j] != (typename SR<DT>::X)0;
+    const bool nz = j < n && SR<DT>::present(x[j]);
     const uint64_t b = __ballot(nz);
     const int64_t j0 = j - lane_id();  // first element of the wave, a multiple of 64
     if (lane_id() == 0 && j0 < n) {
@@ -910,6 +918,9 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
                 case SPX_F64: k_dense_bits<SPX_F64><<<g, kBlock, 0, s>>>(A.n, (const double*)x->val, H->bits); break;
                 case SPX_I32: k_dense_bits<SPX_I32><<<g, kBlock, 0, s>>>(A.n, (const int32_t*)x->val, H->bits); break;
                 case SPX_BOOL: k_dense_bits<SPX_BOOL><<<g, kBlock, 0, s>>>(A.n, (const uint8_t*)x->val, H->bits); break;
+                case SPX_F32_MINPLUS:
+                    k_dense_bits<SPX_F32_MINPLUS><<<g, kBlock, 0, s>>>(A.n, (const float*)x->val, H->bits);
+                    break;
             }
             SPX_HIP(hipGetLastError());
             xd = dt == SPX_BOOL ? nullptr : x->val;
@@ -1130,6 +1141,7 @@ extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, c
                                 const int32_t* idx, const void* val, void* Y, void* stream) {
     if (!H) return fail(SPX_ERR_ARG, "handle is null");
     if (B < 0 || total_nnz_x < 0) return fail(SPX_ERR_SHAPE, "B and total_nnz_x must be >= 0");
+    if (H->csr.dtype == SPX_F32_MINPLUS) return fail(SPX_ERR_DTYPE, "the batched path has no min-plus kernels");
     if (B == 0) return SPX_OK;
     const spx_csr& A = H->csr;
     if (!vec_ptr || (total_nnz_x > 0 && (!idx || (A.dtype != SPX_BOOL && !val))) || (A.m > 0 && !Y))
@@ -1570,6 +1582,7 @@ extern "C" spx_status spx_dense_rows_to_sparse(spx_matrix* H, int32_t B, const v
     if (!H || (B > 0 && (!X || !vec_ptr || !idx || (H->csr.dtype != SPX_BOOL && !val))))
         return fail(SPX_ERR_ARG, "null argument");
     if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    if (H->csr.dtype == SPX_F32_MINPLUS) return fail(SPX_ERR_DTYPE, "dense rows: the batched path has no min-plus");
     SPX_TRY(ensure_ws(H, dense_rows_ws_bytes(B, H->csr.n)));
     Arena ws(H->ws, H->ws_bytes);
     return dense_rows_to_sparse(B, H->csr.n, H->csr.dtype, X, vec_ptr, idx, val, ws, (hipStream_t)stream);

@@ -21,6 +21,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 //   F32 / F64 : real (+, *)
 //   I32       : (+, *) modulo 2^32 (unsigned accumulation, int32 output)
 //   BOOL      : (OR, AND) over the pattern; x values and A values are not read
+//   F32_MINPLUS: (min, +) over float32; zero +inf, absent x entries +inf
 // ---------------------------------------------------------------------------
 template <int DT>
 struct SR;
@@ -40,8 +41,40 @@ struct SR<SPX_F32> {
     __device__ static Acc add(Acc a, Acc b) { return a + b; }
     __device__ static Y out(Acc a) { return a; }
     __device__ static bool nonzero(Acc a) { return a != 0.0f; }
+    __device__ static bool present(X x) { return x != 0.0f; }
     __device__ static void atomic_add(Y* p, Acc v) { unsafeAtomicAdd(p, v); }
     __device__ static void lds_atomic_add(Acc* p, Acc v) { atomicAdd(p, v); }
+};
+
+// float32 minimum as integer atomics: non-negative floats order like their
+// int bits, negative ones like their unsigned bits reversed.
+__device__ __forceinline__ void atomic_min_f32(float* p, float v) {
+    if (v >= 0.0f)
+        atomicMin((int*)p, __float_as_int(v));
+    else
+        atomicMax((unsigned int*)p, __float_as_uint(v));
+}
+
+// (min, +) over float32: the zero is +inf, a product is a sum (one float32
+// rounding), a sum is a minimum.
+template <>
+struct SR<SPX_F32_MINPLUS> {
+    using V = float;
+    using X = float;
+    using Acc = float;
+    using Y = float;
+    static constexpr bool kVals = true;
+    __device__ static Acc zero() { return __builtin_inff(); }
+    __device__ static V val(const V* __restrict__ v, int64_t k) { return v[k]; }
+    __device__ static X xval(const X* __restrict__ x, int64_t j) { return x[j]; }
+    __device__ static Acc mul(V a, X b) { return a + b; }
+    __device__ static Acc fma(V a, X b, Acc c) { return fminf(c, a + b); }
+    __device__ static Acc add(Acc a, Acc b) { return fminf(a, b); }
+    __device__ static Y out(Acc a) { return a; }
+    __device__ static bool nonzero(Acc a) { return a != __builtin_inff(); }
+    __device__ static bool present(X x) { return x != __builtin_inff(); }
+    __device__ static void atomic_add(Y* p, Acc v) { atomic_min_f32(p, v); }
+    __device__ static void lds_atomic_add(Acc* p, Acc v) { atomic_min_f32(p, v); }
 };
 
 template <>
@@ -59,6 +92,7 @@ struct SR<SPX_F64> {
     __device__ static Acc add(Acc a, Acc b) { return a + b; }
     __device__ static Y out(Acc a) { return a; }
     __device__ static bool nonzero(Acc a) { return a != 0.0; }
+    __device__ static bool present(X x) { return x != 0.0; }
     __device__ static void atomic_add(Y* p, Acc v) { unsafeAtomicAdd(p, v); }
     __device__ static void lds_atomic_add(Acc* p, Acc v) { atomicAdd(p, v); }
 };
@@ -78,6 +112,7 @@ struct SR<SPX_I32> {
     __device__ static Acc add(Acc a, Acc b) { return a + b; }
     __device__ static Y out(Acc a) { return (int32_t)a; }
     __device__ static bool nonzero(Acc a) { return a != 0u; }
+    __device__ static bool present(X x) { return x != 0; }
     __device__ static void atomic_add(Y* p, Acc v) { atomicAdd((uint32_t*)p, v); }
     __device__ static void lds_atomic_add(Acc* p, Acc v) { atomicAdd(p, v); }
 };
@@ -97,6 +132,7 @@ struct SR<SPX_BOOL> {
     __device__ static Acc add(Acc a, Acc b) { return a | b; }
     __device__ static Y out(Acc a) { return a ? 1 : 0; }
     __device__ static bool nonzero(Acc a) { return a != 0u; }
+    __device__ static bool present(X x) { return x != 0; }
     // OR is idempotent: racing writers store the same byte.
     __device__ static void atomic_add(Y* p, Acc v) {
         if (v) *p = 1;

@@ -32,6 +32,7 @@ spx_status hip_fail(hipError_t e, const char* what);
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int value_size(int dtype);  // bytes per A / x value (0 for BOOL)
+uint32_t zero_word(int dtype);  // the semiring's zero as a 32-bit word (+inf for min-plus, else 0)
 int out_size(int dtype);    // bytes per y element (1 for BOOL)
 
 // Bump allocator over a caller-provided workspace.

@@ -378,7 +378,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_dense(int32_t nnz_x, const i
 
 spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
                            int dtype, const int32_t* map, void* xd, hipStream_t s) {
-    SPX_TRY(fill_bytes(xd, 0, (size_t)n * std::max(1, value_size(dtype)), s));
+    // absent entries hold the semiring's zero (+inf for min-plus)
+    if (zero_word(dtype))
+        SPX_TRY(fill_u32((uint32_t*)xd, zero_word(dtype), (size_t)n, s));
+    else
+        SPX_TRY(fill_bytes(xd, 0, (size_t)n * std::max(1, value_size(dtype)), s));
     if (nnz_x <= 0) return SPX_OK;
     const unsigned g = (unsigned)ceil_div(nnz_x, kBlock);
     switch (value_size(dtype)) {
@@ -401,10 +405,12 @@ spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const
 // xg[r] = x[order[r]] (a dense x in the renumbered column order) and, if
 // bits is given, the bitvector of xg's nonzeros, one wave ballot per 64
 // entries.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_permute_dense(int32_t n, const T* __restrict__ x,
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_permute_dense(int32_t n, const typename SR<DT>::X* __restrict__ x,
                                                           const int32_t* __restrict__ order,
-                                                          T* __restrict__ xg, uint32_t* __restrict__ bits) {
+                                                          typename SR<DT>::X* __restrict__ xg,
+                                                          uint32_t* __restrict__ bits) {
+    using T = typename SR<DT>::X;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     T v = 0;
     if (r < n) {
@@ -412,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_permute_dense(int32_t n, const T* __
         xg[r] = v;
     }
     if (!bits) return;
-    const uint64_t b = __ballot(r < n && v != (T)0);
+    const uint64_t b = __ballot(r < n && SR<DT>::present(v));
     const int64_t base = r - lane_id();
     if (lane_id() == 0 && base < n) bits[base >> 5] = (uint32_t)b;
     if (lane_id() == 32 && base + 32 < n) bits[(base >> 5) + 1] = (uint32_t)(b >> 32);
@@ -424,16 +430,19 @@ spx_status permute_dense(int32_t n, const void* x, int dtype, const int32_t* ord
     const unsigned g = (unsigned)ceil_div(n, kBlock);
     switch (dtype) {
         case SPX_F32:
-            k_permute_dense<float><<<g, kBlock, 0, s>>>(n, (const float*)x, order, (float*)xg, bits);
+            k_permute_dense<SPX_F32><<<g, kBlock, 0, s>>>(n, (const float*)x, order, (float*)xg, bits);
             break;
         case SPX_F64:
-            k_permute_dense<double><<<g, kBlock, 0, s>>>(n, (const double*)x, order, (double*)xg, bits);
+            k_permute_dense<SPX_F64><<<g, kBlock, 0, s>>>(n, (const double*)x, order, (double*)xg, bits);
             break;
         case SPX_I32:
-            k_permute_dense<int32_t><<<g, kBlock, 0, s>>>(n, (const int32_t*)x, order, (int32_t*)xg, bits);
+            k_permute_dense<SPX_I32><<<g, kBlock, 0, s>>>(n, (const int32_t*)x, order, (int32_t*)xg, bits);
             break;
         case SPX_BOOL:
-            k_permute_dense<uint8_t><<<g, kBlock, 0, s>>>(n, (const uint8_t*)x, order, (uint8_t*)xg, bits);
+            k_permute_dense<SPX_BOOL><<<g, kBlock, 0, s>>>(n, (const uint8_t*)x, order, (uint8_t*)xg, bits);
+            break;
+        case SPX_F32_MINPLUS:
+            k_permute_dense<SPX_F32_MINPLUS><<<g, kBlock, 0, s>>>(n, (const float*)x, order, (float*)xg, bits);
             break;
         default:
             return fail(SPX_ERR_DTYPE, "permute_dense: dtype");
@@ -448,7 +457,7 @@ template <int DT>
 __global__ __launch_bounds__(kBlock) void k_flag_nonzero(int32_t n, const typename SR<DT>::X* __restrict__ x,
                                                          int32_t* __restrict__ flags) {
     int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j < n) flags[j] = x[j] != (typename SR<DT>::X)0 ? 1 : 0;
+    if (j < n) flags[j] = SR<DT>::present(x[j]) ? 1 : 0;
 }
 
 template <int DT>
@@ -459,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(int32_t n, const typename SR
     int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const typename SR<DT>::X v = x[j];
-    if (v != (typename SR<DT>::X)0) {
+    if (SR<DT>::present(v)) {
         const int p = pos[j];
         idx[p] = j;
         if (val) val[p] = v;
@@ -486,6 +495,7 @@ spx_status dense_to_sparse(int32_t n, const void* x, int dtype, int32_t* idx, vo
         SPX_CASE(SPX_F64)
         SPX_CASE(SPX_I32)
         SPX_CASE(SPX_BOOL)
+        SPX_CASE(SPX_F32_MINPLUS)
 #undef SPX_CASE
         default:
             return fail(SPX_ERR_DTYPE, "dense_to_sparse: dtype");
@@ -637,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_vec_feat_dense(const int32_t* __rest
     unsigned long long a = 0, c = 0;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * kBlock) {
-        if (x[j] != (typename SR<DT>::X)0) {
+        if (SR<DT>::present(x[j])) {
             a += (unsigned long long)(col_ptr[j + 1] - col_ptr[j]);
             c += 1;
         }
@@ -684,6 +694,9 @@ spx_status vector_features_device(const int32_t* col_ptr, int32_t n, const spx_v
                 break;
             case SPX_BOOL:
                 k_vec_feat_dense<SPX_BOOL><<<grid, kBlock, 0, s>>>(col_ptr, n, (const uint8_t*)x->val, o);
+                break;
+            case SPX_F32_MINPLUS:
+                k_vec_feat_dense<SPX_F32_MINPLUS><<<grid, kBlock, 0, s>>>(col_ptr, n, (const float*)x->val, o);
                 break;
             default:
                 return fail(SPX_ERR_DTYPE, "vector features: dtype");

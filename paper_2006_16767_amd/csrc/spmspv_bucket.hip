@@ -554,6 +554,7 @@ spx_status launch_csc_bucket_walk(const CscArgs& A, int32_t nnz_x, const int32_t
         case SPX_F64: return launch_walk_t<SPX_F64>(A, nnz_x, x_idx, x_val, y, plan, s);
         case SPX_I32: return launch_walk_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, s);
         case SPX_BOOL: return launch_walk_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, s);
+        case SPX_F32_MINPLUS: return launch_walk_t<SPX_F32_MINPLUS>(A, nnz_x, x_idx, x_val, y, plan, s);
     }
     return fail(SPX_ERR_DTYPE, "bucket: unknown dtype");
 }
@@ -569,6 +570,8 @@ spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
             return launch_bucket_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
         case SPX_BOOL:
             return launch_bucket_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
+        case SPX_F32_MINPLUS:
+            return launch_bucket_t<SPX_F32_MINPLUS>(A, nnz_x, x_idx, x_val, y, plan, excl, ws, s);
     }
     return fail(SPX_ERR_DTYPE, "bucket: unknown dtype");
 }

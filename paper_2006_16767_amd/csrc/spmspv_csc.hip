@@ -134,7 +134,7 @@ constexpr int kProMax = kBlock * kProIpt;  // nnz_x + 1 <= kProMax
 __global__ __launch_bounds__(kBlock) void k_csc_prologue(int32_t nnz_x, const int32_t* __restrict__ x_idx,
                                                          const int32_t* __restrict__ col_ptr,
                                                          int32_t* __restrict__ excl, uint32_t* __restrict__ y,
-                                                         int64_t ywords, int ytail) {
+                                                         int64_t ywords, int ytail, uint32_t yfill) {
     if (blockIdx.x == 0) {
         __shared__ int32_t tmp[kWavesPerBlock];
         const int e0 = threadIdx.x * kProIpt;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_prologue(int32_t nnz_x, const in
         return;
     }
     const int64_t stride = (int64_t)(gridDim.x - 1) * kBlock;
-    for (int64_t i = (int64_t)(blockIdx.x - 1) * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = 0u;
+    for (int64_t i = (int64_t)(blockIdx.x - 1) * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = yfill;
     if (blockIdx.x == 1 && (int)threadIdx.x < ytail) ((uint8_t*)(y + ywords))[threadIdx.x] = 0;
 }
 
@@ -201,10 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_csc_lengths_scan(int32_t nnz_x, cons
                                                              int32_t* __restrict__ local, int32_t* __restrict__ sums,
                                                              int32_t* __restrict__ off, uint32_t* __restrict__ counter,
                                                              uint32_t* __restrict__ y, int64_t ywords, int ytail,
-                                                             int F) {
+                                                             uint32_t yfill, int F) {
     if ((int)blockIdx.x < F) {
         const int64_t stride = (int64_t)F * kBlock;
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = 0u;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ywords; i += stride) y[i] = yfill;
         if (blockIdx.x == 0 && (int)threadIdx.x < ytail) ((uint8_t*)(y + ywords))[threadIdx.x] = 0;
         return;
     }
@@ -437,6 +437,12 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
     return z.used;
 }
 
+// y filled with the semiring's zero (0 bytes, or +inf words for min-plus)
+static spx_status fill_y_zero(void* y, int dtype, size_t ybytes, hipStream_t s) {
+    if (zero_word(dtype)) return fill_u32((uint32_t*)y, zero_word(dtype), ybytes / 4, s);
+    return fill_bytes(y, 0, ybytes, s);
+}
+
 template <int DT>
 static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val_v,
                                void* y_v, const spx_plan* plan, Arena& ws, hipStream_t s) {
@@ -478,7 +484,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
             uint32_t* counter = T <= kLsFenceTiles ? A.scan_counter : nullptr;
             k_csc_lengths_scan<<<(unsigned)(F + T), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, sums, off,
                                                                    counter, (uint32_t*)y, ywords,
-                                                                   fill_y ? (int)(ybytes & 3) : 0, F);
+                                                                   fill_y ? (int)(ybytes & 3) : 0, zero_word(DT), F);
             SPX_HIP(hipGetLastError());
             if (!counter) {
                 k_scan_run_totals<<<1, kBlock, 0, s>>>(sums, (int)T, off);
@@ -489,17 +495,17 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
             const int64_t ywords = fill_y ? (int64_t)(ybytes / 4) : 0;
             const int fill_blocks = fill_y ? (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ywords, kBlock), 4096)) : 0;
             k_csc_prologue<<<1 + fill_blocks, kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr, excl, (uint32_t*)y, ywords,
-                                                             fill_y ? (int)(ybytes & 3) : 0);
+                                                             fill_y ? (int)(ybytes & 3) : 0, zero_word(DT));
             SPX_HIP(hipGetLastError());
         } else {
-            if (fill_y) SPX_TRY(fill_bytes(y, 0, ybytes, s));
+            if (fill_y) SPX_TRY(fill_y_zero(y, DT, ybytes, s));
             k_x_lengths<<<(unsigned)ceil_div((int64_t)nnz_x + 1, kBlock), kBlock, 0, s>>>(nnz_x, x_idx, A.col_ptr,
                                                                                            excl);
             SPX_HIP(hipGetLastError());
             SPX_TRY(scan_exclusive_i32(excl, excl, (int64_t)nnz_x + 1, nullptr, sws, s));
         }
     } else if (fill_y) {
-        SPX_TRY(fill_bytes(y, 0, ybytes, s));
+        SPX_TRY(fill_y_zero(y, DT, ybytes, s));
     }
     if (nnz_x == 0) return SPX_OK;
     // grid of the balanced kernels: enough tiles for the known or bounded work
@@ -616,6 +622,8 @@ spx_status launch_spmspv_csc(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
             return launch_csc_t<SPX_I32>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
         case SPX_BOOL:
             return launch_csc_t<SPX_BOOL>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
+        case SPX_F32_MINPLUS:
+            return launch_csc_t<SPX_F32_MINPLUS>(A, nnz_x, x_idx, x_val, y, plan, ws, s);
     }
     return fail(SPX_ERR_DTYPE, "spmspv_csc: unknown dtype");
 }

@@ -328,6 +328,7 @@ spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits
         SPX_DT(SPX_F64)
         SPX_DT(SPX_I32)
         SPX_DT(SPX_BOOL)
+        SPX_DT(SPX_F32_MINPLUS)
 #undef SPX_DT
     }
     return fail(SPX_ERR_DTYPE, "spmv: unknown dtype");
