@@ -1453,8 +1453,22 @@ extern "C" spx_status spx_pagerank(spx_matrix* H, double damping, double eps, in
     a.count = H->drv_count;
     if (!H->pr_W_valid) {
         SPX_TRY(fill_u32(H->pr_bad, 0u, 1, s));
-        a.stage = PR_COLSUM;
+        a.stage = PR_NEGCHECK;
+        a.nnz = A.nnz;
         SPX_TRY(launch_pagerank(a, s));
+        // W = A^T 1: the balanced row-major SpMV over the CSC arrays read as
+        // the CSR of A^T (its merge partition cached as the handle's second
+        // one), x = ones in the second dense buffer (zeroed again by round 0)
+        a.stage = PR_ONES;
+        a.ones = H->pr_xd[1];
+        SPX_TRY(launch_pagerank(a, s));
+        const spx_csr At{A.n, A.m, A.nnz, A.dtype, H->col_ptr, H->row_idx, H->vals_csc};
+        const spx_plan bal{SPX_PAT_SPMV, SPX_DIST_BALANCED, SPX_WB_NONE, 0, 0, 0};
+        const int32_t* part = nullptr;
+        SPX_TRY(cached_part(H, At, 1, &bal, s, &part));
+        SPX_TRY(ensure_ws(H, ws_for(At.m, At.n, At.nnz, 0, A.dtype, &bal)));
+        Arena ws(H->ws, H->ws_bytes);
+        SPX_TRY(launch_spmv_csr(&At, H->pr_xd[1], nullptr, H->pr_W, &bal, part, ws, s));
         SPX_HIP(hipMemcpyAsync(H->drv_host, H->pr_bad, 4, hipMemcpyDeviceToHost, s));
         SPX_HIP(hipStreamSynchronize(s));
         if (H->drv_host[0]) return fail(SPX_ERR_ARG, "PageRank needs nonnegative edge weights");

@@ -231,16 +231,18 @@ spx_status launch_bfs_pull(int32_t n, const int32_t* row_ptr, const int32_t* col
 // packed counters as for breadth-first search, {entries appended to x,
 // their column lengths}; round s appends into count[s & 1], clears the
 // other.
-enum PrStage { PR_COLSUM, PR_INIT, PR_SELECT, PR_FOLD };
+enum PrStage { PR_NEGCHECK, PR_ONES, PR_INIT, PR_SELECT, PR_FOLD };
 struct PrArgs {
     int stage = PR_INIT;
     int dtype = SPX_F32;
     int32_t n = 0;
     int32_t round = 0;
     double damping = 0.85, eps = 0.0;
+    int64_t nnz = 0;
     const int32_t* col_ptr = nullptr;  // CSC column pointers
-    const void* vals_csc = nullptr;    // COLSUM
-    uint32_t* bad = nullptr;           // COLSUM: bit 0 = negative weight
+    const void* vals_csc = nullptr;    // NEGCHECK
+    uint32_t* bad = nullptr;           // NEGCHECK: bit 0 = negative weight
+    void* ones = nullptr;              // ONES: n values set to 1
     void* W = nullptr;                 // column sums
     void* r = nullptr;                 // residual
     void* p = nullptr;                 // rank

@@ -21,24 +21,22 @@
 
 namespace spx {
 
-// W_j = sum of column j over the CSC values; bad gets bit 0 if a weight is
-// negative. Run once per value version of the handle.
+// bad gets bit 0 if a stored weight is negative (one atomic per wave that
+// sees one). The column sums themselves are a product: W = A^T 1.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pr_colsum(int32_t n, const int32_t* __restrict__ col_ptr,
-                                                      const T* __restrict__ vals, T* __restrict__ W,
-                                                      uint32_t* __restrict__ bad) {
+__global__ __launch_bounds__(kBlock) void k_pr_negcheck(int64_t nnz, const T* __restrict__ vals,
+                                                        uint32_t* __restrict__ bad) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
-        T s = 0;
-        bool neg = false;
-        for (int32_t k = col_ptr[j]; k < col_ptr[j + 1]; ++k) {
-            const T a = vals[k];
-            neg |= a < (T)0;
-            s += a;
-        }
-        W[j] = s;
-        if (neg) atomicOr(bad, 1u);
-    }
+    bool neg = false;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride) neg |= vals[k] < (T)0;
+    if (__ballot(neg) && lane_id() == 0) atomicOr(bad, 1u);
+}
+
+// v = 1 everywhere (the x of W = A^T 1).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pr_ones(int32_t n, T* __restrict__ v) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) v[i] = (T)1;
 }
 
 // r = r0 everywhere, p = 0, and the dense x buffer of round 0 zeroed.
@@ -180,8 +178,13 @@ static int flat_grid(int32_t n) { return (int)std::max<int64_t>(1, std::min<int6
 template <typename T>
 static spx_status pr_t(const PrArgs& a, hipStream_t s) {
     switch (a.stage) {
-        case PR_COLSUM:
-            k_pr_colsum<T><<<flat_grid(a.n), kBlock, 0, s>>>(a.n, a.col_ptr, (const T*)a.vals_csc, (T*)a.W, a.bad);
+        case PR_NEGCHECK: {
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(a.nnz, kBlock), 4096));
+            k_pr_negcheck<T><<<grid, kBlock, 0, s>>>(a.nnz, (const T*)a.vals_csc, a.bad);
+            break;
+        }
+        case PR_ONES:
+            k_pr_ones<T><<<flat_grid(a.n), kBlock, 0, s>>>(a.n, (T*)a.ones);
             break;
         case PR_INIT:
             k_pr_init<T><<<flat_grid(a.n), kBlock, 0, s>>>(a.n, (T)((1.0 - a.damping) / a.n), (T*)a.r, (T*)a.p,
