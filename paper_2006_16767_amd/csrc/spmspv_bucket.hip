@@ -341,16 +341,45 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
 
 // ------------------------------------------------------------------ walk (short x)
 // The direct bucket write-back for a short x, in one launch: one 1024-thread
-// workgroup per bucket zeroes its R rows in LDS, every thread takes x
-// entries and adds the entries of their columns whose row falls in the
-// bucket (rows ascend within a CSC column, so a long column is cut to the
-// bucket's row range by two binary searches), then the workgroup writes its
-// rows of y once. No pair buffer, no prefix, no zero fill of y.
+// workgroup per bucket zeroes its R rows in LDS; groups of G lanes take x
+// entries (G = the plan's lanes, or the most that lets every entry of x go
+// out in one round) and add the entries of their columns whose row falls in
+// the bucket. Rows ascend within a CSC column, so a long column is cut to
+// the bucket's row range by two searches in which the group probes G
+// points per step; short columns are read whole, G entries per step. Then
+// the workgroup writes its rows of y once. No pair buffer, no prefix, no
+// zero fill of y.
 constexpr int kWalkMaxX = 2048;       // x entries of a walk
 constexpr int64_t kWalkMaxS = 16384;  // estimated selected entries of a walk
-constexpr int kWalkScan = 32;         // columns up to this length are scanned
+constexpr int kWalkScan = 32;         // a thread reads columns up to this length whole
 
-template <int DT, bool SPARSE>
+// First position in [a, b) whose row is >= key (b if none), rows ascending:
+// the G lanes of a group probe G interior points of the interval per step
+// (G = 1 is the binary search). Every lane of the group gets the result;
+// the group must be converged.
+template <int G>
+__device__ __forceinline__ int group_lower_bound(const int32_t* __restrict__ rows, int a, int b, int key) {
+    const int lane = threadIdx.x % G;
+    const int shift = (lane_id() / G) * G;  // the group's bits in the wave's ballot
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    int lo = a, hi = b;
+    while (lo < hi) {
+        const int64_t span = hi - lo;
+        const int p = lo + (int)((span * (lane + 1)) / (G + 1));  // in [lo, hi)
+        const uint64_t m = (__ballot(rows[p] >= key) >> shift) & gmask;
+        if (!m) {
+            lo += (int)((span * G) / (G + 1)) + 1;  // every probe is below key
+        } else {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            const int lo0 = lo;
+            hi = lo0 + (int)((span * (f + 1)) / (G + 1));
+            if (f > 0) lo = lo0 + (int)((span * f) / (G + 1)) + 1;
+        }
+    }
+    return lo;
+}
+
+template <int DT, bool SPARSE, int G>
 __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR, int32_t nnz_x,
                                                              const int32_t* __restrict__ x_idx,
                                                              const typename SR<DT>::X* __restrict__ x_val,
@@ -362,6 +391,7 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
     using S = SR<DT>;
     using Acc = typename S::Acc;
     constexpr bool kTouch = SPARSE && S::kVals;
+    constexpr int kScan = G == 1 ? kWalkScan : 4 * G;  // read whole up to this length
     extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     Acc* acc = (Acc*)s_raw;
     const int R = 1 << logR;
@@ -372,26 +402,17 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
     if constexpr (kTouch)
         for (int w = threadIdx.x; w < (R + 31) / 32; w += kAccThreads) touched[w] = 0u;
     __syncthreads();
-    for (int e = threadIdx.x; e < nnz_x; e += kAccThreads) {
+    const int lane = threadIdx.x % G;
+    // the loop is uniform across each group of G lanes
+    for (int e = threadIdx.x / G; e < nnz_x; e += kAccThreads / G) {
         const int j = x_idx[e];
         const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
         int k0 = col_ptr[j], k1 = col_ptr[j + 1];
-        if (k1 - k0 > kWalkScan) {
-            // first position with row >= lo, then first with row >= hi
-            int a = k0, z = k1;
-            while (a < z) {
-                const int mid = (a + z) >> 1;
-                if (row_idx[mid] < lo) a = mid + 1; else z = mid;
-            }
-            int a2 = a, z2 = k1;
-            while (a2 < z2) {
-                const int mid = (a2 + z2) >> 1;
-                if (row_idx[mid] < hi) a2 = mid + 1; else z2 = mid;
-            }
-            k0 = a;
-            k1 = a2;
+        if (k1 - k0 > kScan) {
+            k0 = group_lower_bound<G>(row_idx, k0, k1, lo);
+            k1 = group_lower_bound<G>(row_idx, k0, k1, hi);
         }
-        for (int k = k0; k < k1; ++k) {
+        for (int k = k0 + lane; k < k1; k += G) {
             const int r = row_idx[k];
             if (r >= lo && r < hi) {
                 if constexpr (S::kVals)
@@ -525,6 +546,22 @@ bool csc_bucket_walks(const CscArgs& A, int32_t nnz_x, const spx_plan* plan) {
     return nnz_x <= kWalkMaxX && est <= kWalkMaxS;
 }
 
+template <int DT, bool SPARSE>
+static void walk_launch(int G, unsigned grid, size_t lds, hipStream_t s, int32_t m, int logR, int32_t nnz_x,
+                        const int32_t* x_idx, const void* x_val, const CscArgs& A, void* y, const SparseOut& so) {
+    using S = SR<DT>;
+    switch (G) {
+#define SPX_G(GG)                                                                                          \
+    case GG:                                                                                               \
+        k_bucket_walk<DT, SPARSE, GG><<<grid, kAccThreads, lds, s>>>(                                     \
+            m, logR, nnz_x, x_idx, (const typename S::X*)x_val, A.col_ptr, A.row_idx,                      \
+            (const typename S::V*)A.vals, (typename S::Y*)y, so);                                          \
+        break;
+        SPX_G(1) SPX_G(2) SPX_G(4) SPX_G(8) SPX_G(16) SPX_G(32) SPX_G(64)
+#undef SPX_G
+    }
+}
+
 template <int DT>
 static spx_status launch_walk_t(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
                                 const spx_plan* plan, hipStream_t s) {
@@ -532,16 +569,21 @@ static spx_status launch_walk_t(const CscArgs& A, int32_t nnz_x, const int32_t* 
     BucketGeom g;
     if (!bucket_geometry(A.m, DT, plan->bucket_rows, &g))
         return fail(SPX_ERR_UNSUPPORTED, "bucket write-back: rows per bucket must fit 64 KiB of LDS and at most 4096 buckets");
+    // lanes per x entry: the plan's, else the most that send every entry
+    // out in one round of the workgroup
+    int G = plan->lanes;
+    if (G <= 0) {
+        G = 64;
+        while (G > 1 && (int64_t)nnz_x * G > kAccThreads) G >>= 1;
+    }
+    if (G > 64 || (G & (G - 1))) return fail(SPX_ERR_ARG, "lanes must be a power of two in [1, 64]");
     const size_t R = (size_t)1 << g.logR;
     if (A.sparse) {
         const size_t lds = R * sizeof(typename S::Acc) + (S::kVals ? ceil_div(R, 32) * 4 : 0);
-        k_bucket_walk<DT, true><<<(unsigned)g.NB, kAccThreads, lds, s>>>(
-            A.m, g.logR, nnz_x, x_idx, (const typename S::X*)x_val, A.col_ptr, A.row_idx,
-            (const typename S::V*)A.vals, nullptr, *A.sparse);
+        walk_launch<DT, true>(G, (unsigned)g.NB, lds, s, A.m, g.logR, nnz_x, x_idx, x_val, A, nullptr, *A.sparse);
     } else {
-        k_bucket_walk<DT, false><<<(unsigned)g.NB, kAccThreads, R * sizeof(typename S::Acc), s>>>(
-            A.m, g.logR, nnz_x, x_idx, (const typename S::X*)x_val, A.col_ptr, A.row_idx,
-            (const typename S::V*)A.vals, (typename S::Y*)y, SparseOut{});
+        walk_launch<DT, false>(G, (unsigned)g.NB, R * sizeof(typename S::Acc), s, A.m, g.logR, nnz_x, x_idx, x_val,
+                               A, y, SparseOut{});
     }
     SPX_HIP(hipGetLastError());
     return SPX_OK;
