@@ -24,11 +24,11 @@ constexpr int kShortRow = 32;
 // so that every load of a phase is in flight before the first is used: all
 // column indices, then (validation) all bitvector words, then the values
 // and x entries, then the LDS stores. Items past Q use a clamped, valid
-// index and are not stored.
-template <int DT, bool VALID, int IPT, int NT>
+// index and are not stored. xf(c) returns x_c (a global load, or an LDS
+// read for the columns a kernel keeps there).
+template <int DT, bool VALID, int IPT, int NT, typename XF>
 __device__ __forceinline__ void csr_stage_products(int k0, int Q, const int32_t* __restrict__ col_idx,
-                                                   const typename SR<DT>::V* __restrict__ vals,
-                                                   const typename SR<DT>::X* __restrict__ x,
+                                                   const typename SR<DT>::V* __restrict__ vals, XF xf,
                                                    const uint32_t* __restrict__ bits,
                                                    typename SR<DT>::Acc* __restrict__ prod) {
     using S = SR<DT>;
@@ -54,7 +54,7 @@ __device__ __forceinline__ void csr_stage_products(int k0, int Q, const int32_t*
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
             a[it] = on[it] ? S::val(vals, kk[it]) : (typename S::V)0;
-            b[it] = on[it] ? S::xval(x, c[it]) : (typename S::X)0;
+            b[it] = on[it] ? xf(c[it]) : (typename S::X)0;
         }
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void csr_stage_products(int k0, int Q, const int32_t*
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
             a[it] = S::val(vals, kk[it]);
-            b[it] = S::xval(x, c[it]);
+            b[it] = xf(c[it]);
         }
 #pragma unroll
         for (int it = 0; it < IPT; ++it)
@@ -83,36 +83,36 @@ struct CsrTileLds {
     int32_t nlong;
 };
 
-// One tile: stage the products of its nonzeros in LDS with coalesced loads
-// (fully unrolled, so all gathers of a thread are in flight together), then
-// reduce every row whose end falls in the tile from LDS: short rows by one
-// thread, rows longer than kShortRow by a whole wave. The row still open at
-// the tile end leaves a carry for the fix-up pass (carry_row = -1 if none).
-// Ends with __syncthreads.
-template <int DT, bool VALID, int TILE>
-__device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col_idx,
-                                               const typename SR<DT>::V* __restrict__ vals,
-                                               const typename SR<DT>::X* __restrict__ x,
-                                               const uint32_t* __restrict__ bits,
-                                               typename SR<DT>::Y* __restrict__ y,
-                                               const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
-                                               typename SR<DT>::Acc* __restrict__ carry_val,
-                                               CsrTileLds<DT, TILE>& L) {
+// One tile, NT threads: stage the products of its nonzeros in LDS with
+// coalesced loads (fully unrolled, so all gathers of a thread are in flight
+// together), then reduce every row whose end falls in the tile from LDS:
+// short rows by one thread, rows longer than kShortRow by a whole wave. The
+// row still open at the tile end leaves a carry for the fix-up pass
+// (carry_row = -1 if none). Ends with __syncthreads.
+template <int DT, bool VALID, int TILE, int NT, typename XF>
+__device__ __forceinline__ void csr_merge_tile_nt(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_idx,
+                                                  const typename SR<DT>::V* __restrict__ vals, XF xf,
+                                                  const uint32_t* __restrict__ bits,
+                                                  typename SR<DT>::Y* __restrict__ y,
+                                                  const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
+                                                  typename SR<DT>::Acc* __restrict__ carry_val,
+                                                  CsrTileLds<DT, TILE>& L) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
-    constexpr int kIpt = TILE / kBlock;
+    constexpr int kIpt = TILE / NT;
+    constexpr int kWaves = NT / kWave;
     const int i0 = part[2 * tile], k0 = part[2 * tile + 1];
     const int i1 = part[2 * tile + 2], k1 = part[2 * tile + 3];
     const int R = i1 - i0;  // rows whose end lies in this tile
     const int Q = k1 - k0;  // nonzeros of this tile
     const bool open = i1 < m && k1 > row_ptr[i1];
     if (threadIdx.x == 0) L.nlong = 0;
-    for (int r = threadIdx.x; r < R; r += kBlock) L.end[r] = row_ptr[i0 + 1 + r];
-    csr_stage_products<DT, VALID, kIpt, kBlock>(k0, Q, col_idx, vals, x, bits, L.prod);
+    for (int r = threadIdx.x; r < R; r += NT) L.end[r] = row_ptr[i0 + 1 + r];
+    csr_stage_products<DT, VALID, kIpt, NT>(k0, Q, col_idx, vals, xf, bits, L.prod);
     __syncthreads();
     const int nrows = R + (open ? 1 : 0);
-    for (int r = threadIdx.x; r < nrows; r += kBlock) {
+    for (int r = threadIdx.x; r < nrows; r += NT) {
         const int a = (r == 0 ? k0 : L.end[r - 1]) - k0;
         const int e = (r < R ? L.end[r] : k1) - k0;
         if (e - a <= kShortRow) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const in
     }
     __syncthreads();
     const int nl = L.nlong;
-    for (int li = wave_id(); li < nl; li += kWavesPerBlock) {
+    for (int li = wave_id(); li < nl; li += kWaves) {
         const int r = L.lng[li];
         const int a = (r == 0 ? k0 : L.end[r - 1]) - k0;
         const int e = (r < R ? L.end[r] : k1) - k0;
@@ -148,6 +148,22 @@ __device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const in
     }
     if (!open && threadIdx.x == 0) carry_row[tile] = -1;
     __syncthreads();
+}
+
+// The tile with kBlock threads and x read from global memory.
+template <int DT, bool VALID, int TILE>
+__device__ __forceinline__ void csr_merge_tile(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col_idx,
+                                               const typename SR<DT>::V* __restrict__ vals,
+                                               const typename SR<DT>::X* __restrict__ x,
+                                               const uint32_t* __restrict__ bits,
+                                               typename SR<DT>::Y* __restrict__ y,
+                                               const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
+                                               typename SR<DT>::Acc* __restrict__ carry_val,
+                                               CsrTileLds<DT, TILE>& L) {
+    csr_merge_tile_nt<DT, VALID, TILE, kBlock>(
+        tile, m, row_ptr, col_idx, vals, [x](int c) { return SR<DT>::xval(x, c); }, bits, y, part, carry_row,
+        carry_val, L);
 }
 
 // Carries of tiles whose last row continues, added in tile order by the

@@ -140,67 +140,16 @@ __global__ __launch_bounds__(kBitThreads) void k_csr_bitlds(int32_t m, int32_t n
                                                             const int32_t* __restrict__ part, int64_t tiles,
                                                             int32_t* __restrict__ carry_row,
                                                             typename SR<DT>::Acc* __restrict__ carry_val) {
-    using S = SR<DT>;
-    using Acc = typename S::Acc;
-    constexpr int kWaves = kBitThreads / kWave;
-    constexpr int kIpt = kBitTile / kBitThreads;
     extern __shared__ __align__(16) uint32_t s_bits[];
-    __shared__ int32_t s_end[kBitTile + 1];
-    __shared__ Acc s_prod[kBitTile];
-    __shared__ int32_t s_lng[kBitTile + 1];
-    __shared__ int32_t s_nlong;
+    __shared__ CsrTileLds<DT, kBitTile> L;
     const int nwords = (n + 31) >> 5;
     for (int w = threadIdx.x; w < nwords; w += kBitThreads) s_bits[w] = bits[w];
     __syncthreads();
-    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x) {
-        // XCD-contiguous order over the persistent grid
-        const int64_t tile = xcd_tile(bt, tiles);
-        const int i0 = part[2 * tile], k0 = part[2 * tile + 1];
-        const int i1 = part[2 * tile + 2], k1 = part[2 * tile + 3];
-        const int R = i1 - i0, Q = k1 - k0;
-        const bool open = i1 < m && k1 > row_ptr[i1];
-        if (threadIdx.x == 0) s_nlong = 0;
-        for (int r = threadIdx.x; r < R; r += kBitThreads) s_end[r] = row_ptr[i0 + 1 + r];
-        csr_stage_products<DT, true, kIpt, kBitThreads>(k0, Q, col_idx, vals, x, s_bits, s_prod);
-        __syncthreads();
-        const int nrows = R + (open ? 1 : 0);
-        for (int r = threadIdx.x; r < nrows; r += kBitThreads) {
-            const int a = (r == 0 ? k0 : s_end[r - 1]) - k0;
-            const int e = (r < R ? s_end[r] : k1) - k0;
-            if (e - a <= kShortRow) {
-                Acc acc = S::zero();
-                for (int q = a; q < e; ++q) acc = S::add(acc, s_prod[q]);
-                if (r < R) {
-                    y[i0 + r] = S::out(acc);
-                } else {
-                    carry_row[tile] = i1;
-                    carry_val[tile] = acc;
-                }
-            } else {
-                s_lng[atomicAdd(&s_nlong, 1)] = r;
-            }
-        }
-        __syncthreads();
-        const int nl = s_nlong;
-        for (int li = wave_id(); li < nl; li += kWaves) {
-            const int r = s_lng[li];
-            const int a = (r == 0 ? k0 : s_end[r - 1]) - k0;
-            const int e = (r < R ? s_end[r] : k1) - k0;
-            Acc acc = S::zero();
-            for (int q = a + lane_id(); q < e; q += kWave) acc = S::add(acc, s_prod[q]);
-            acc = group_reduce<DT, kWave>(acc);
-            if (lane_id() == 0) {
-                if (r < R) {
-                    y[i0 + r] = S::out(acc);
-                } else {
-                    carry_row[tile] = i1;
-                    carry_val[tile] = acc;
-                }
-            }
-        }
-        if (!open && threadIdx.x == 0) carry_row[tile] = -1;
-        __syncthreads();
-    }
+    // XCD-contiguous order over the persistent grid
+    for (int64_t bt = blockIdx.x; bt < tiles; bt += gridDim.x)
+        csr_merge_tile_nt<DT, true, kBitTile, kBitThreads>(
+            xcd_tile(bt, tiles), m, row_ptr, col_idx, vals, [x](int c) { return SR<DT>::xval(x, c); }, s_bits, y,
+            part, carry_row, carry_val, L);
 }
 
 // static LDS of k_csr_bitlds plus the bitvector must fit one CU's LDS
@@ -293,8 +242,8 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
         }
         if (VALID && want_bitlds(plan, A->n, DT)) {
             int dev = 0, cus = 256;
-            hipGetDevice(&dev);
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            SPX_HIP(hipGetDevice(&dev));
+            SPX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             const int grid = (int)std::min<int64_t>(tiles, std::max(1, cus));
             const size_t lds = (size_t)((A->n + 31) / 32) * 4;
             SPX_HIP(hipFuncSetAttribute((const void*)k_csr_bitlds<DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
