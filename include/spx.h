@@ -90,7 +90,8 @@ typedef enum {
 /* Workload distribution (Section 4.2.1). Balanced tiles hold 2048 merge
  * items (tile = 0 or 2048) or 4096 (tile = 4096). For the balanced row-major
  * SpMSpV, tile = 1 keeps the bitvector of supp(x) in LDS instead (persistent
- * workgroups; n up to about 1.1M for FP32, otherwise the 2048 kernel). */
+ * workgroups; n up to about 1.17M for FP32 or 1.1M for FP64, otherwise the
+ * 2048 kernel). */
 typedef enum {
     SPX_DIST_DIRECT = 0,  /* a fixed group of `lanes` threads per row (per column for CSC) */
     SPX_DIST_BALANCED = 1 /* merge-path tiles with equal (rows + entries) per workgroup */

@@ -75,11 +75,15 @@ __device__ __forceinline__ void csr_stage_products(int k0, int Q, const int32_t*
     }
 }
 
+// A tile's LDS. A row longer than kShortRow within the tile takes more than
+// kShortRow of its TILE items, so at most TILE / (kShortRow + 1) rows are
+// long: lng needs no more (which keeps the tile at 16.4 KB for TILE = 2048
+// and FP32, eight 256-thread workgroups per CU).
 template <int DT, int TILE>
 struct CsrTileLds {
     int32_t end[TILE + 1];
     typename SR<DT>::Acc prod[TILE];
-    int32_t lng[TILE + 1];
+    int32_t lng[TILE / (kShortRow + 1) + 1];
     int32_t nlong;
 };
 

@@ -154,8 +154,8 @@ __global__ __launch_bounds__(kBitThreads) void k_csr_bitlds(int32_t m, int32_t n
 
 // static LDS of k_csr_bitlds plus the bitvector must fit one CU's LDS
 static size_t bitlds_static(int dtype) {
-    const size_t acc = dtype == SPX_F64 ? 8 : 4;
-    return (size_t)(kBitTile + 1) * 4 * 2 + (size_t)kBitTile * acc + 64;
+    // every semiring's accumulator is at most 4 bytes except FP64's
+    return (dtype == SPX_F64 ? sizeof(CsrTileLds<SPX_F64, kBitTile>) : sizeof(CsrTileLds<SPX_F32, kBitTile>)) + 64;
 }
 bool bitlds_fits(int32_t n, int dtype) {
     return (size_t)((n + 31) / 32) * 4 + bitlds_static(dtype) + 512 <= (size_t)kLdsTotal;
