@@ -179,9 +179,15 @@ struct spx_matrix {
     spx_csr gcsr{};
     double feat[9] = {0};
     Selector sel;
-    // conversion buffers (allocated on first use)
+    // conversion buffers (allocated on first use). *_clean: the buffer is
+    // known to hold zeros (the semiring's zero for xd) once the work queued
+    // so far has run, because the last balanced row-major product cleared
+    // what its conversion scattered; the next sparse conversion then skips
+    // its fill. Calls on one handle are ordered on one stream.
     uint32_t* bits = nullptr;
     void* xd = nullptr;
+    bool bits_clean = false;
+    bool xd_clean = false;
     int32_t* sp_idx = nullptr;
     void* sp_val = nullptr;
     int32_t* scratch_i32 = nullptr;  // compaction workspace
@@ -881,13 +887,18 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
     SPX_TRY(ensure_conv(H));
     if (p->pattern == SPX_PAT_SPMV) {
         const void* xd = x->val;
+        Unscatter un;
         if (x->kind == SPX_VEC_SPARSE) {
             record(H, H->ev_conv, true, s);
-            SPX_TRY(sparse_to_dense(A.n, x->nnz_x, x->idx, x->val, dt, H->grank, H->xd, s));
+            const bool clean = H->xd_clean;
+            H->xd_clean = false;
+            SPX_TRY(sparse_to_dense(A.n, x->nnz_x, x->idx, x->val, dt, H->grank, H->xd, s, clean));
             record(H, H->ev_conv, false, s);
             xd = H->xd;
+            un = Unscatter{x->nnz_x, x->idx, H->grank, nullptr, H->xd, A.n};
         } else if (H->gorder) {
             record(H, H->ev_conv, true, s);
+            H->xd_clean = false;
             SPX_TRY(permute_dense(A.n, x->val, dt, H->gorder, H->xd, nullptr, s));
             record(H, H->ev_conv, false, s);
             xd = H->xd;
@@ -897,21 +908,33 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         const int32_t* part = nullptr;
         SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
-        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s));
+        bool cleared = false;
+        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared));
         record(H, H->ev_kern, false, s);
+        if (un.xd) H->xd_clean = cleared;
         return SPX_OK;
     }
     if (p->pattern == SPX_PAT_CSR_SPMSPV) {
         const void* xd = nullptr;
+        Unscatter un;
         record(H, H->ev_conv, true, s);
         if (x->kind == SPX_VEC_SPARSE) {
+            // the values land in xd unfilled (the bitvector decides which
+            // entries are read), so only the bitvector is cleared after
+            const bool clean = H->bits_clean;
+            H->bits_clean = false;
+            if (dt != SPX_BOOL) H->xd_clean = false;
             SPX_TRY(sparse_to_bitvector(A.n, x->nnz_x, x->idx, x->val, dt, H->grank, H->bits,
-                                        dt == SPX_BOOL ? nullptr : H->xd, s));
+                                        dt == SPX_BOOL ? nullptr : H->xd, s, clean));
             xd = dt == SPX_BOOL ? nullptr : H->xd;
+            un = Unscatter{x->nnz_x, x->idx, H->grank, H->bits, nullptr, A.n};
         } else if (H->gorder) {
+            H->bits_clean = false;
+            H->xd_clean = false;
             SPX_TRY(permute_dense(A.n, x->val, dt, H->gorder, H->xd, H->bits, s));
             xd = dt == SPX_BOOL ? nullptr : H->xd;
         } else {
+            H->bits_clean = false;
             const unsigned g = dense_bits_grid(A.n);
             switch (dt) {
                 case SPX_F32: k_dense_bits<SPX_F32><<<g, kBlock, 0, s>>>(A.n, (const float*)x->val, H->bits); break;
@@ -931,8 +954,10 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         const int32_t* part = nullptr;
         SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
-        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, part, ws, s));
+        bool cleared = false;
+        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, part, ws, s, un.bits ? &un : nullptr, &cleared));
         record(H, H->ev_kern, false, s);
+        if (un.bits) H->bits_clean = cleared;
         return SPX_OK;
     }
     // column-major: needs (idx, val)
@@ -1018,6 +1043,7 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
     const uint32_t* bits = nullptr;
     if (p->pattern == SPX_PAT_CSR_SPMSPV) {
         record(H, H->ev_conv, true, s);
+        H->bits_clean = false;
         if (dt == SPX_F32)
             k_dense_bits<SPX_F32><<<dense_bits_grid(A.n), kBlock, 0, s>>>(A.n, (const float*)xd, H->bits);
         else

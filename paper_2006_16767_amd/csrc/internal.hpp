@@ -83,10 +83,27 @@ spx_status gather_perm(const void* in, const int32_t* perm, void* out, int64_t n
                        hipStream_t s);
 
 // ------------------------------------------------------------------ kernels
+// Positions a sparse x was scattered to (map[idx[e]], or idx[e] when map is
+// null) in a bitvector and / or a dense x buffer. The balanced row-major
+// launch clears them again in its fix-up pass, after the product has read
+// them, so that the buffers are back at zero (the semiring's zero for xd)
+// for the next conversion, which then needs no fill.
+struct Unscatter {
+    int32_t nnz_x = 0;
+    const int32_t* idx = nullptr;
+    const int32_t* map = nullptr;
+    uint32_t* bits = nullptr;  // whole words are zeroed
+    void* xd = nullptr;
+    int32_t n = 0;  // length of x: past n / 16 entries the whole buffers are cleared with coalesced stores
+};
+
 // part: merge-path partition of the balanced distribution (null: computed
-// into the workspace on this call)
+// into the workspace on this call). un (optional): positions to clear after
+// the product; *cleared (optional) tells whether they were (only the
+// balanced distribution has the pass that does it).
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s);
+                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
+                           const Unscatter* un = nullptr, bool* cleared = nullptr);
 spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int tile, int32_t* part,
                            hipStream_t s);
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan);
@@ -140,13 +157,16 @@ spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
                              hipStream_t s);
 size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
 
-// sparse x -> bitvector of supp(x) (cleared first) + scattered values xd[n]
-// (map, if given, renumbers the columns: entry j lands at map[j])
+// sparse x -> bitvector of supp(x) (cleared first unless `clean` says it
+// is all zero already) + scattered values xd[n] (map, if given, renumbers
+// the columns: entry j lands at map[j])
 spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s);
-// sparse x -> zero-filled dense x (map as above)
+                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s,
+                               bool clean = false);
+// sparse x -> dense x filled with the semiring's zero (skipped when `clean`
+// says xd holds it already; map as above)
 spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                           int dtype, const int32_t* map, void* xd, hipStream_t s);
+                           int dtype, const int32_t* map, void* xd, hipStream_t s, bool clean = false);
 // dense x -> xg[r] = x[order[r]], plus the bitvector of xg's nonzeros if bits
 spx_status permute_dense(int32_t n, const void* x, int dtype, const int32_t* order, void* xg, uint32_t* bits,
                          hipStream_t s);

@@ -345,8 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_bits(int32_t nnz_x, const in
 }
 
 spx_status sparse_to_bitvector(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s) {
-    SPX_TRY(fill_u32(bits, 0u, (size_t)ceil_div(n, 32), s));
+                               int dtype, const int32_t* map, uint32_t* bits, void* xd, hipStream_t s,
+                               bool clean) {
+    if (!clean) SPX_TRY(fill_u32(bits, 0u, (size_t)ceil_div(n, 32), s));
     if (nnz_x <= 0) return SPX_OK;
     const unsigned g = (unsigned)ceil_div(nnz_x, kBlock);
     switch (value_size(dtype)) {
@@ -377,9 +378,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_dense(int32_t nnz_x, const i
 }
 
 spx_status sparse_to_dense(int32_t n, int32_t nnz_x, const int32_t* x_idx, const void* x_val,
-                           int dtype, const int32_t* map, void* xd, hipStream_t s) {
+                           int dtype, const int32_t* map, void* xd, hipStream_t s, bool clean) {
     // absent entries hold the semiring's zero (+inf for min-plus)
-    if (zero_word(dtype))
+    if (clean)
+        ;
+    else if (zero_word(dtype))
         SPX_TRY(fill_u32((uint32_t*)xd, zero_word(dtype), (size_t)n, s));
     else
         SPX_TRY(fill_bytes(xd, 0, (size_t)n * std::max(1, value_size(dtype)), s));

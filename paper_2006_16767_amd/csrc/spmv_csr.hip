@@ -114,9 +114,28 @@ template <int DT>
 __global__ __launch_bounds__(kBlock) void k_csr_merge_fixup(int32_t tiles,
                                                             const int32_t* __restrict__ carry_row,
                                                             const typename SR<DT>::Acc* __restrict__ carry_val,
-                                                            typename SR<DT>::Y* __restrict__ y) {
-    csr_merge_fixup_range<DT>((int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock, tiles,
-                              carry_row, carry_val, y);
+                                                            typename SR<DT>::Y* __restrict__ y, Unscatter un) {
+    using X = typename SR<DT>::X;
+    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x, stride = (int64_t)gridDim.x * kBlock;
+    csr_merge_fixup_range<DT>(first, stride, tiles, carry_row, carry_val, y);
+    // the scattered x back to zero (the product that read it has finished):
+    // entry by entry for a sparse x (several entries of one bitvector word
+    // store the same 0), the whole buffers with coalesced stores once x
+    // holds more than n / 16 entries (fewer bytes than the scattered lines)
+    X z = (X)0;
+    if constexpr (DT == SPX_F32_MINPLUS) z = __builtin_inff();
+    if ((int64_t)un.nnz_x * 16 > un.n) {
+        if (un.bits)
+            for (int64_t w = first; w < ((int64_t)un.n + 31) / 32; w += stride) un.bits[w] = 0u;
+        if (un.xd)
+            for (int64_t j = first; j < un.n; j += stride) ((X*)un.xd)[j] = z;
+        return;
+    }
+    for (int64_t e = first; e < un.nnz_x; e += stride) {
+        const int32_t j = un.map ? un.map[un.idx[e]] : un.idx[e];
+        if (un.bits) un.bits[j >> 5] = 0u;
+        if (un.xd) ((X*)un.xd)[j] = z;
+    }
 }
 
 
@@ -200,7 +219,8 @@ spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int t
 
 template <int DT, bool VALID>
 static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                               const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s) {
+                               const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
+                               const Unscatter* un, bool* cleared) {
     using S = SR<DT>;
     const auto* vals = (const typename S::V*)A->vals;
     const auto* xv = (const typename S::X*)x;
@@ -257,22 +277,27 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
             k_csr_merge<DT, VALID, 2048><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->row_ptr, A->col_idx, vals, xv,
                                                                            bits, yv, part, tiles, crow, cval);
         SPX_HIP(hipGetLastError());
-        k_csr_merge_fixup<DT><<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, s>>>((int32_t)tiles, crow,
-                                                                                  cval, yv);
+        const Unscatter u = un ? *un : Unscatter{};
+        const int64_t work = std::max<int64_t>(tiles, (int64_t)u.nnz_x * 16 > u.n ? u.n : u.nnz_x);
+        k_csr_merge_fixup<DT><<<(unsigned)std::min<int64_t>(ceil_div(work, kBlock), 8192), kBlock, 0, s>>>(
+            (int32_t)tiles, crow, cval, yv, u);
         SPX_HIP(hipGetLastError());
+        if (cleared) *cleared = un != nullptr;
         return SPX_OK;
     }
     return fail(SPX_ERR_ARG, "unknown distribution");
 }
 
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
-                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s) {
+                           const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
+                           const Unscatter* un, bool* cleared) {
+    if (cleared) *cleared = false;
     const bool valid = plan->pattern == SPX_PAT_CSR_SPMSPV;
     switch (A->dtype) {
 #define SPX_DT(DT)                                                                            \
     case DT:                                                                                  \
-        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, part, ws, s)               \
-                     : launch_csr_t<DT, false>(A, x, bits, y, plan, part, ws, s);
+        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, part, ws, s, un, cleared)  \
+                     : launch_csr_t<DT, false>(A, x, bits, y, plan, part, ws, s, un, cleared);
         SPX_DT(SPX_F32)
         SPX_DT(SPX_F64)
         SPX_DT(SPX_I32)
