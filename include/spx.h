@@ -211,19 +211,35 @@ spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, con
  * Results are those of A up to the summation order within a row.
  * SPX_RENUMBER forces the copy, SPX_NO_RENUMBER forbids it. Memory:
  * 4 + value size bytes per entry for the copy, 4 for its source positions,
- * 8 per column. */
+ * 8 per column.
+ *
+ * Storage-format pre-selection (Section 8's extension: pick the matrix
+ * format per matrix, before the kernel): besides CSR the handle can keep a
+ * sliced ELLPACK copy (SELL-C-sigma: slices of 64 rows, one wave per slice
+ * and a lane per row, rows sorted by descending length within windows of
+ * 4096 rows, padding to the longest row of each slice). When it does, every
+ * plan of the SpMV pattern runs on it; the other patterns are unchanged.
+ * By default a small decision tree over the matrix features and the
+ * padding ratio (cells / nnz) decides (trained on MI355X timings of both
+ * formats; reading the padding ratio copies row_ptr to the host once).
+ * SPX_FORMAT_SELL forces the copy (SPX_ERR_UNSUPPORTED when a row is longer
+ * than 4096 entries or the copy would take more than 3 nnz + 65536 cells),
+ * SPX_FORMAT_CSR forbids it. Memory: 8 + value size bytes per cell, 4 per
+ * row. */
 #define SPX_VALIDATE 1u
 #define SPX_RENUMBER 4u
 #define SPX_NO_RENUMBER 8u
+#define SPX_FORMAT_CSR 16u
+#define SPX_FORMAT_SELL 32u
 spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
 spx_status spx_matrix_destroy(spx_matrix *H);
 
 /* The handle's CSC copy (device pointers owned by the handle). */
 spx_status spx_matrix_csc(const spx_matrix *H, spx_csc *out);
 
-/* Re-derives the CSC values (and those of the renumbered copy) from the
- * borrowed CSR values (gathers through the permutations); call after the
- * caller changed A's values in place. */
+/* Re-derives the CSC values (and those of the renumbered and sliced ELL
+ * copies) from the borrowed CSR values (gathers through the permutations);
+ * call after the caller changed A's values in place. */
 spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
 
 /* *renumbered = 1 if the handle keeps the column-renumbered copy (see
@@ -231,6 +247,11 @@ spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
  * ranking to order (device, n int32: order[r] = the column of rank r),
  * asynchronously on stream. */
 spx_status spx_matrix_column_order(const spx_matrix *H, int32_t *order, int32_t *renumbered, void *stream);
+
+/* *format = 1 if the handle keeps the sliced ELLPACK copy (see
+ * spx_matrix_create), else 0; *padding_ratio (may be NULL) = its cells /
+ * nnz (0 when there is no copy). Host only. */
+spx_status spx_matrix_format(const spx_matrix *H, int32_t *format, double *padding_ratio);
 
 /* Matrix features of Table 1, out[9] = {m, n, nnz, max_row, min_row,
  * avg_row, relative_range = (max_row - min_row) / n, var_nnz_row

@@ -16,7 +16,7 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F32_MINPLUS, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
-                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
+                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
                    WB_SORT, Plan, SpxError)
 
 __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
@@ -114,7 +114,7 @@ class Matrix:
     features and workspaces belong to the library handle."""
 
     def __init__(self, row_ptr, col_idx, vals, m: int, n: int, dtype: int | None = None,
-                 validate: bool = False, renumber: bool | None = None, stream=None):
+                 validate: bool = False, renumber: bool | None = None, stream=None, fmt: str | None = None):
         torch = _torch()
         self.row_ptr = row_ptr.contiguous()
         self.col_idx = col_idx.contiguous()
@@ -130,6 +130,7 @@ class Matrix:
         _ensure_default_selector()
         h = C.c_void_p()
         flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
+        flags |= {None: 0, "csr": FORMAT_CSR, "sell": FORMAT_SELL}[fmt]
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         if dtype == BOOL:
@@ -139,7 +140,7 @@ class Matrix:
         self._vals_version = None if self.vals is None else self.vals._version
 
     @classmethod
-    def from_host(cls, A, dtype=None, device="cuda", validate=False, renumber=None):
+    def from_host(cls, A, dtype=None, device="cuda", validate=False, renumber=None, fmt=None):
         """From an object with m, n, row_ptr, col_idx, vals (numpy)."""
         torch = _torch()
         rp = torch.as_tensor(A.row_ptr, dtype=torch.int32, device=device)
@@ -152,7 +153,7 @@ class Matrix:
             if dtype is not None:
                 v = v.to(torch_dtype(dtype))
             dt = dtype_code(v.dtype) if dtype is None else dtype  # F32_MINPLUS shares float32
-        return cls(rp, ci, v, A.m, A.n, dt, validate=validate, renumber=renumber)
+        return cls(rp, ci, v, A.m, A.n, dt, validate=validate, renumber=renumber, fmt=fmt)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -247,6 +248,14 @@ class Matrix:
 
     def values_updated(self, stream=None):
         _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
+
+    def storage_format(self):
+        """("sell", padding ratio) when the handle keeps the sliced ELLPACK
+        copy that its SpMV plans run on, else ("csr", 0.0)."""
+        f = C.c_int32(0)
+        r = C.c_double(0.0)
+        _lib.call("spx_matrix_format", self._h, C.byref(f), C.byref(r))
+        return ("sell" if f.value else "csr"), float(r.value)
 
     def column_order(self, stream=None):
         """The column ranking of the renumbered row-major copy (device int32

@@ -22,7 +22,7 @@ PAT_SPMV, PAT_CSR_SPMSPV, PAT_CSC_SPMSPV = 0, 1, 2
 DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET = 0, 1, 2, 3, 4
 VEC_DENSE, VEC_SPARSE = 0, 1
-VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER = 1, 2, 4, 8
+VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL = 1, 2, 4, 8, 16, 32
 BFS_PUSH_ONLY = 1
 
 
@@ -69,6 +69,7 @@ SIGNATURES = {
     "spx_matrix_values_updated": (C.c_int, [P, P]),
     "spx_matrix_column_order": (C.c_int, [P, P, C.POINTER(C.c_int32), P]),
     "spx_matrix_features": (C.c_int, [P, C.POINTER(C.c_double)]),
+    "spx_matrix_format": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "spx_vector_features": (C.c_int, [P, C.POINTER(Vec), C.POINTER(C.c_double), P]),
     "spx_load_selector": (C.c_int, [P, C.c_char_p]),
     "select_kernel": (C.c_int, [P, C.POINTER(Vec), C.c_uint32, C.POINTER(Plan), P]),

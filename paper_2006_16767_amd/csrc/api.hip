@@ -188,6 +188,10 @@ struct spx_matrix {
     void* xd = nullptr;
     bool bits_clean = false;
     bool xd_clean = false;
+    // sliced ELLPACK copy of the row-major CSR (the renumbered one when
+    // there is one), used by the SpMV pattern when present
+    SellMat sell;
+    double sell_ratio = 0.0;
     int32_t* sp_idx = nullptr;
     void* sp_val = nullptr;
     int32_t* scratch_i32 = nullptr;  // compaction workspace
@@ -463,6 +467,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->pr_xd[0], H->pr_xd[1], H->pr_p, H->pr_bad};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    sell_free(&H->sell);
     if (H->drv_host) hipHostFree(H->drv_host);
     for (auto& e : H->drv_ev)
         if (e) hipEventDestroy(e);
@@ -616,6 +621,49 @@ static spx_status build_gcsr(spx_matrix* H, uint32_t flags, hipStream_t s) {
     return SPX_OK;
 }
 
+// Storage-format pre-selection: keep the sliced ELLPACK copy or not. The
+// tree reads the Table 1 features of A and the padding ratio of the
+// sliced copy (cells / nnz), the latter computed from a host copy of
+// row_ptr only when a node asks for it.
+constexpr int32_t kSellMaxRow = 4096;  // longest row the copy accepts (serial sums per lane)
+constexpr double kSellMaxRatio = 3.0;  // most cells per entry it accepts, beyond a fixed allowance
+constexpr int64_t kSellAllowance = 65536;  // cells any matrix may use (one partly filled slice)
+static spx_status choose_format(spx_matrix* H, uint32_t flags, hipStream_t s) {
+    const spx_csr& A = H->gorder ? H->gcsr : H->csr;
+    if ((flags & SPX_FORMAT_CSR) || A.m == 0) return SPX_OK;
+    const bool forced = (flags & SPX_FORMAT_SELL) != 0;
+    std::vector<int32_t> rp;
+    SellPlanInfo info;
+    bool shaped = false;
+    spx_status st = SPX_OK;
+    auto shape = [&]() {
+        if (shaped) return;
+        shaped = true;
+        rp.resize((size_t)A.m + 1);
+        if (hipMemcpyAsync(rp.data(), A.row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "row_ptr read-back");
+            return;
+        }
+        info = sell_shape(rp.data(), A.m);
+    };
+    auto ratio = [&]() {
+        shape();
+        return (double)info.padded / (double)std::max<int64_t>(1, A.nnz);
+    };
+    const bool want = forced || format_prefers_sell(H->feat, ratio);
+    if (st != SPX_OK || !want) return st;
+    const double r = ratio();
+    if (st != SPX_OK) return st;
+    if (H->feat[3] > kSellMaxRow || (double)info.padded > kSellMaxRatio * (double)A.nnz + (double)kSellAllowance) {
+        if (forced) return fail(SPX_ERR_UNSUPPORTED, "sliced ELL: a row longer than 4096 or more than 3 nnz + 65536 cells");
+        return SPX_OK;
+    }
+    SPX_TRY(sell_build(A, info, &H->sell, s));
+    H->sell_ratio = r;
+    return SPX_OK;
+}
+
 extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* stream, spx_matrix** out) {
     if (!out) return fail(SPX_ERR_ARG, "out is null");
     *out = nullptr;
@@ -659,6 +707,7 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
         st = matrix_features_device(A->row_ptr, A->m, A->n, &ms, s);
         if (st == SPX_OK) std::memcpy(H->feat, ms.f, sizeof(H->feat));
     }
+    if (st == SPX_OK) st = choose_format(H, flags, s);
     if (st == SPX_OK) st = upload_selector(H);
     if (st != SPX_OK) {
         std::string keep = g_err;
@@ -683,6 +732,14 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     if (vs == 0 || H->csr.nnz == 0) return SPX_OK;
     SPX_TRY(gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
+    if (H->sell.col) SPX_TRY(sell_refresh(H->sell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_format(const spx_matrix* H, int32_t* format, double* padding_ratio) {
+    if (!H || !format) return fail(SPX_ERR_ARG, "null argument");
+    *format = H->sell.col ? 1 : 0;
+    if (padding_ratio) *padding_ratio = H->sell.col ? H->sell_ratio : 0.0;
     return SPX_OK;
 }
 
@@ -909,7 +966,10 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
         bool cleared = false;
-        SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared));
+        if (H->sell.col)
+            SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
+        else
+            SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared));
         record(H, H->ev_kern, false, s);
         if (un.xd) H->xd_clean = cleared;
         return SPX_OK;
@@ -1057,7 +1117,10 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
     const int32_t* part = nullptr;
     SPX_TRY(cached_part(H, A, 0, p, s, &part));
     record(H, H->ev_kern, true, s);
-    SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s));
+    if (H->sell.col && p->pattern == SPX_PAT_SPMV)
+        SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
+    else
+        SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s));
     record(H, H->ev_kern, false, s);
     return SPX_OK;
 }

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/spx.h"
 #include "selector.hpp"
@@ -289,5 +290,31 @@ spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t 
 spx_status dense_rows_to_sparse(int32_t B, int32_t n, int dtype, const void* X, int32_t* vec_ptr,
                                 int32_t* idx, void* val, Arena& ws, hipStream_t s);
 size_t dense_rows_ws_bytes(int32_t B, int32_t n);
+
+// ------------------------------------------------------------------ sliced ELL
+// SELL-C-sigma copy of A (C = 64 rows per slice, rows sorted by descending
+// length inside windows of kSellSigma rows); see sell.hip for the layout.
+constexpr int32_t kSellSigma = 4096;
+struct SellMat {
+    int64_t nslices = 0;
+    int64_t padded = 0;           // stored cells, padding included
+    int64_t* slice_ptr = nullptr;  // [nslices + 1], cells before each slice
+    int32_t* perm = nullptr;       // [nslices * 64], row of each slot or -1
+    int32_t* col = nullptr;        // [padded], -1 for padding
+    int32_t* src = nullptr;        // [padded], CSR position or -1
+    void* vals = nullptr;          // [padded] (none for BOOL)
+};
+// The slot order and slice widths, computed on the host from row_ptr.
+struct SellPlanInfo {
+    int64_t nslices = 0;
+    int64_t padded = 0;
+    std::vector<int32_t> perm;
+    std::vector<int64_t> slice_ptr;
+};
+SellPlanInfo sell_shape(const int32_t* row_ptr_host, int32_t m);
+spx_status sell_build(const spx_csr& A, const SellPlanInfo& info, SellMat* out, hipStream_t s);
+spx_status sell_refresh(const SellMat& S, const spx_csr& A, hipStream_t s);
+void sell_free(SellMat* S);
+spx_status sell_spmv(const SellMat& S, int dtype, const void* x, void* y, hipStream_t s);
 
 }  // namespace spx

@@ -37,6 +37,26 @@ static Tree make_tree(std::initializer_list<std::initializer_list<double>> rows)
     return t;
 }
 
+// Trained (tune.py formats-train, depth 3, regret-weighted) on MI355X
+// timings of the dense-x FP32 SpMV on the 30 tuning matrices, best CSR plan
+// against the sliced copy: the copy wins on even row lengths (population
+// standard deviation <= 0.36) over more than 40960 rows, with n up to about
+// 1.5M (the 7-point stencil at 128^3, 2.1M rows, ran 5 % faster in CSR).
+// On that corpus it loses 0.2 % against always taking the faster format,
+// CSR alone 2.1 %.
+Tree format_tree() {
+    // rows: feature, threshold, left, right, class (-1 = internal)
+    return make_tree({
+        {F_VAR_ROW, 0.3603, 1, 6, -1},
+        {F_M, 40960.0, 2, 3, -1},
+        {0, 0, 0, 0, 0},
+        {F_N, 1572864.0, 4, 5, -1},
+        {0, 0, 0, 0, 1},
+        {0, 0, 0, 0, 0},
+        {0, 0, 0, 0, 0},
+    });
+}
+
 // Untrained defaults, written on host-known features only so that run()
 // needs no device-to-host sync: vector density picks the pattern
 // (column-major when sparse, row-major with validation in between, SpMV

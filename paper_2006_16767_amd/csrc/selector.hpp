@@ -72,6 +72,18 @@ struct Selector {
 };
 
 Selector builtin_selector();
+
+// Storage-format pre-selector: class 1 when the sliced ELLPACK copy is
+// expected to run the SpMV faster than CSR. Feature ids 0-8 are the Table 1
+// matrix features (F_M .. F_GINI), kFmtPadding the padding ratio of the
+// sliced copy (cells / nnz), which ratio() computes on first use.
+constexpr int kFmtPadding = 9;
+Tree format_tree();
+template <typename RatioFn>
+bool format_prefers_sell(const double* feat, RatioFn&& ratio) {
+    static const Tree t = format_tree();
+    return t.eval([&](int f) { return f < kFmtPadding ? feat[f] : ratio(); }) == 1;
+}
 // Parses the tuner's JSON. Returns false with a message on error.
 bool parse_selector_json(const std::string& text, Selector* out, std::string* err);
 

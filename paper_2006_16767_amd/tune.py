@@ -257,6 +257,98 @@ def driver_sweep(out_path: str, reps: int = 5):
             print(f"[drivers] pagerank round {k}: nnz_x {int(idx.numel())}", flush=True)
 
 
+# ----------------------------------------------------------------------------- storage format
+FORMAT_FEATURES = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini",
+                   "padding")
+SELL_SIGMA = 4096  # rows per sorting window of the sliced copy
+
+
+def sell_padding(A) -> float:
+    """Cells / nnz of the sliced ELLPACK copy of A (slices of 64 rows, rows
+    sorted by descending length within windows of SELL_SIGMA rows)."""
+    lens = np.diff(np.asarray(A.row_ptr, dtype=np.int64))
+    m = len(lens)
+    ns = (m + 63) // 64
+    slot = np.zeros(ns * 64, dtype=np.int64)
+    pos = 0
+    for w0 in range(0, m, SELL_SIGMA):
+        part = lens[w0:w0 + SELL_SIGMA]
+        slot[pos:pos + len(part)] = part[np.argsort(-part, kind="stable")]
+        pos += len(part)
+    return float(slot.reshape(ns, 64).max(axis=1).sum() * 64) / max(1, int(lens.sum()))
+
+
+def format_sweep(out_path: str, reps: int = 10):
+    """Training data of the storage-format pre-selector: on every corpus
+    matrix, the SpMV of a dense x (FP32) by the fastest SpMV plan of a CSR
+    handle against the sliced ELLPACK copy of a handle forced to keep it
+    (null when the matrix is too skewed for it). One record per matrix."""
+    import torch
+    from . import F32, Matrix, SpxError, plan
+    csr_plans = [plan("spmv", "direct"), plan("spmv", "balanced"), plan("spmv", "balanced", tile=4096)]
+    with open(out_path, "w") as fout:
+        for name, gen in corpus():
+            A = gen()
+            x = torch.rand(A.n, device="cuda", dtype=torch.float32)
+            y = torch.empty(A.m, device="cuda", dtype=torch.float32)
+            Mc = Matrix.from_host(A, dtype=F32, fmt="csr")
+            feats = Mc.features()
+            tc = _time_plans(Mc, x, y, csr_plans, reps)
+            Mc.close()
+            rec = {"matrix": name, "features": dict(feats, padding=sell_padding(A)), "csr_ms": tc,
+                   "sell_ms": None}
+            try:
+                Ms = Matrix.from_host(A, dtype=F32, fmt="sell")
+                rec["sell_ms"] = _time_plans(Ms, x, y, [plan("spmv", "direct")], reps)[repr(plan("spmv", "direct"))]
+                rec["features"]["padding"] = Ms.storage_format()[1]
+                Ms.close()
+            except SpxError:
+                pass
+            fout.write(json.dumps(rec) + "\n")
+            fout.flush()
+            ts = "-" if rec["sell_ms"] is None else f"{rec['sell_ms'] * 1e3:.1f}"
+            print(f"[format] {name}: csr {min(tc.values()) * 1e3:.1f} us, sell {ts} us", flush=True)
+
+
+def format_train(path: str, out_path: str, max_depth: int = 3):
+    """The storage-format tree from a format sweep: class 1 (sliced
+    ELLPACK) where it ran the SpMV faster than the best CSR plan. Samples
+    are weighted by the time a wrong choice would lose (relative), and
+    the tree is grown on all records (one per matrix, too few to hold some
+    out); the report gives the time lost against always taking the faster
+    format, and the rows of the tree for the library's built-in table."""
+    from sklearn.tree import DecisionTreeClassifier
+    recs = [json.loads(l) for l in open(path) if l.strip()]
+    X, y, w, tc, ts = [], [], [], [], []
+    for r in recs:
+        c = min(r["csr_ms"].values())
+        s_ = r["sell_ms"] if r["sell_ms"] is not None else float("inf")
+        X.append([r["features"][k] for k in FORMAT_FEATURES])
+        y.append(int(s_ < c))
+        w.append(abs(min(s_, 10 * c) - c) / min(s_, c))
+        tc.append(c)
+        ts.append(s_)
+    X = np.asarray(X)
+    clf = DecisionTreeClassifier(max_depth=max_depth, random_state=0).fit(X, y, sample_weight=np.asarray(w) + 1e-3)
+    pred = clf.predict(X)
+    best = sum(min(a, b) for a, b in zip(tc, ts))
+    chosen = sum(b if p_ else a for a, b, p_ in zip(tc, ts, pred))
+    csr_only = sum(tc)
+    t = clf.tree_
+    rows = []
+    for i in range(t.node_count):
+        if t.children_left[i] < 0:
+            rows.append([0, 0.0, 0, 0, int(np.argmax(t.value[i][0]))])
+        else:
+            rows.append([int(t.feature[i]), float(t.threshold[i]), int(t.children_left[i]), int(t.children_right[i]), -1])
+    rep = {"records": len(recs), "sell_faster": int(sum(y)), "accuracy": float(np.mean(pred == np.asarray(y))),
+           "loss_vs_best": chosen / best - 1.0, "csr_only_loss_vs_best": csr_only / best - 1.0,
+           "features": list(FORMAT_FEATURES), "rows": rows}
+    with open(out_path, "w") as f:
+        json.dump(rep, f, indent=1)
+    return rep
+
+
 def evaluate(paths, selector_paths):
     """Accuracy and time loss of saved selectors on timed records (the
     misprediction study): per selector and support kind, the share of
@@ -701,6 +793,12 @@ def main(argv=None):
     st.add_argument("--out", required=True)
     st.add_argument("--all-features", action="store_true")
     st.add_argument("--jobs", type=int, default=8)
+    fs = sub.add_parser("formats")
+    fs.add_argument("--out", required=True)
+    fs.add_argument("--reps", type=int, default=10)
+    ft = sub.add_parser("formats-train")
+    ft.add_argument("data")
+    ft.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", required=True)
@@ -708,6 +806,12 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "drivers":
         driver_sweep(a.out, a.reps)
+        return
+    if a.cmd == "formats":
+        format_sweep(a.out, a.reps)
+        return
+    if a.cmd == "formats-train":
+        print(json.dumps(format_train(a.data, a.out), indent=1))
         return
     if a.cmd == "evaluate":
         rep = evaluate(a.data, a.selectors)
