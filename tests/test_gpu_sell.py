@@ -151,3 +151,23 @@ def test_auto_format_follows_the_tree():
     assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "sell"
     assert spx.Matrix.from_host(cfg_matrix("cfg1")).storage_format()[0] == "csr"
     assert spx.Matrix.from_host(cfg_matrix("rmat16")).storage_format()[0] == "csr"
+
+
+def test_sell_full_size_uniform_rows():
+    """A full-size matrix the format tree sends to the sliced copy (2^20
+    rows of 16 entries): run() on dense and sparse x against the oracle."""
+    torch = _torch()
+    A = synth.uniform_rows(1 << 20, 1 << 20, 16, 13)
+    M = spx.Matrix.from_host(A)
+    assert M.storage_format()[0] == "sell"
+    x = synth.dense_vector(A.n, 14)
+    ref, S = oracle.spmv(A, x.astype(np.float64))
+    y = M.run(torch.as_tensor(x, device="cuda"))
+    torch.cuda.synchronize()
+    assert_close(y.cpu().numpy(), ref, S, "f32", "uniform 2^20 dense x")
+    v = synth.sparse_vector(A.n, A.n // 2, 15)
+    ref, S = reference(A, v.idx, np.asarray(v.val, np.float32), "f32")
+    y = M.run_plan((torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(np.asarray(v.val, np.float32), device="cuda")),
+                   spx.plan("spmv", "balanced"))
+    torch.cuda.synchronize()
+    assert_close(y.cpu().numpy(), ref, S, "f32", "uniform 2^20 sparse x")
