@@ -87,3 +87,55 @@ def test_train_writes_a_selector_the_library_loads(tmp_path):
     bad.write_text('{"pattern": {"nodes": [[99, 0, 1, 2, -1]]}}')
     assert lib.spx_load_selector(None, str(bad).encode()) == -1
     assert lib.spx_load_selector(None, None) == 0  # back to the built-in trees
+
+
+def _csr_rows(lens):
+    rp = np.zeros(len(lens) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    return type("A", (), {"row_ptr": rp})()
+
+
+def test_sell_padding_by_hand():
+    """Slices of 64 rows padded to their longest row, rows sorted by length
+    (descending) within windows of 4096 rows before slicing."""
+    # one slice: 64 rows, longest 5, 10 entries in all -> 64 * 5 cells
+    lens = [5, 1, 1, 3] + [0] * 60
+    assert tune.sell_padding(_csr_rows(lens)) == pytest.approx(64 * 5 / 10)
+    # 128 rows, even length 2: no padding
+    assert tune.sell_padding(_csr_rows([2] * 128)) == 1.0
+    # 128 rows, 64 of length 4 interleaved with 64 of length 1: the sort
+    # inside the window groups them, so the slices are 4 wide and 1 wide
+    lens = [4, 1] * 64
+    assert tune.sell_padding(_csr_rows(lens)) == pytest.approx((64 * 4 + 64 * 1) / (64 * 5))
+    # the same rows split by the window: 4096 one-entry rows first, then the
+    # pattern, which the sort cannot reach across the window boundary
+    lens = [1] * 4096 + [4, 1] * 64
+    cells = 4096 + 64 * 4 + 64 * 1
+    assert tune.sell_padding(_csr_rows(lens)) == pytest.approx(cells / (4096 + 64 * 5))
+    # 3 rows: one partly filled slice
+    assert tune.sell_padding(_csr_rows([2, 0, 1])) == pytest.approx(64 * 2 / 3)
+
+
+def test_format_train_separates_the_formats(tmp_path):
+    """Sliced copy faster exactly on the even-row, many-row records: the
+    tree learns it, loses nothing on its training set, and its rows are in
+    the library's table form."""
+    pytest.importorskip("sklearn.tree")
+    path = tmp_path / "formats.jsonl"
+    rng = np.random.default_rng(1)
+    with open(path, "w") as f:
+        for i in range(40):
+            m = float(rng.choice([4096, 65536, 1 << 20]))
+            var = float(rng.choice([0.0, 0.3, 5.0]))
+            sell_wins = m > 40000 and var < 1.0
+            feats = {k: 1.0 for k in tune.FORMAT_FEATURES}
+            feats.update(m=m, n=m, var_nnz_row=var, padding=1.0 + var)
+            csr = 10.0
+            rec = {"matrix": f"m{i}", "features": feats, "csr_ms": {"Plan(spmv)": csr},
+                   "sell_ms": 8.0 if sell_wins else (None if var > 1 else 12.0)}
+            f.write(json.dumps(rec) + "\n")
+    rep = tune.format_train(str(path), str(tmp_path / "tree.json"))
+    assert rep["accuracy"] == 1.0 and rep["loss_vs_best"] == pytest.approx(0.0)
+    assert rep["csr_only_loss_vs_best"] > 0
+    for row in rep["rows"]:
+        assert len(row) == 5 and (row[4] in (0, 1) or (row[4] == -1 and 0 <= row[0] < len(tune.FORMAT_FEATURES)))
