@@ -39,6 +39,11 @@
  *  - Every launch is enqueued on the caller's stream (a hipStream_t passed
  *    as void*; NULL is the default stream) and returns without waiting,
  *    except where a function says it synchronizes.
+ *  - A handle's scratch (conversion buffers, workspace, driver state) is
+ *    shared by all its calls, and it tracks what earlier calls left there
+ *    (e.g. a conversion buffer cleared by the last product): calls on one
+ *    handle must be ordered, on one stream or with the caller
+ *    synchronizing between streams. Different handles are independent.
  *  - Every function returns an spx_status (0 on success, negative on
  *    error); nothing aborts and no C++ exception crosses the boundary.
  *    spx_last_error() returns a thread-local message for the last error.
