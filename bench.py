@@ -41,7 +41,7 @@ def alg_bytes(m, n, nnz, nnz_x, nnz_s, s_i=4, s_v=4, s_x=4, s_y=4):
     return min(b_spmv, b_csc), b_spmv, b_csc
 
 
-def cpu_baseline(A, vecs, min_seconds=10.0, max_rounds=50):
+def cpu_baseline(A, vecs, min_seconds=10.0, max_rounds=200):
     """The oracle as it stands, single-threaded, over the same vectors until
     at least min_seconds of CPU time have accumulated."""
     import numpy as np
