@@ -278,27 +278,29 @@ def sell_padding(A) -> float:
     return float(slot.reshape(ns, 64).max(axis=1).sum() * 64) / max(1, int(lens.sum()))
 
 
-def format_sweep(out_path: str, reps: int = 10):
+def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
     """Training data of the storage-format pre-selector: on every corpus
-    matrix, the SpMV of a dense x (FP32) by the fastest SpMV plan of a CSR
-    handle against the sliced ELLPACK copy of a handle forced to keep it
-    (null when the matrix is too skewed for it). One record per matrix."""
+    matrix, the SpMV of a dense x (FP32, or FP64 to check the tree on the
+    other precision) by the fastest SpMV plan of a CSR handle against the
+    sliced ELLPACK copy of a handle forced to keep it (null when the matrix
+    is too skewed for it). One record per matrix."""
     import torch
-    from . import F32, Matrix, SpxError, plan
+    from . import F32, F64, Matrix, SpxError, plan
+    code, tdt = (F64, torch.float64) if dtype == "f64" else (F32, torch.float32)
     csr_plans = [plan("spmv", "direct"), plan("spmv", "balanced"), plan("spmv", "balanced", tile=4096)]
     with open(out_path, "w") as fout:
         for name, gen in corpus():
             A = gen()
-            x = torch.rand(A.n, device="cuda", dtype=torch.float32)
-            y = torch.empty(A.m, device="cuda", dtype=torch.float32)
-            Mc = Matrix.from_host(A, dtype=F32, fmt="csr")
+            x = torch.rand(A.n, device="cuda", dtype=tdt)
+            y = torch.empty(A.m, device="cuda", dtype=tdt)
+            Mc = Matrix.from_host(A, dtype=code, fmt="csr")
             feats = Mc.features()
             tc = _time_plans(Mc, x, y, csr_plans, reps)
             Mc.close()
             rec = {"matrix": name, "features": dict(feats, padding=sell_padding(A)), "csr_ms": tc,
                    "sell_ms": None}
             try:
-                Ms = Matrix.from_host(A, dtype=F32, fmt="sell")
+                Ms = Matrix.from_host(A, dtype=code, fmt="sell")
                 rec["sell_ms"] = _time_plans(Ms, x, y, [plan("spmv", "direct")], reps)[repr(plan("spmv", "direct"))]
                 rec["features"]["padding"] = Ms.storage_format()[1]
                 Ms.close()
@@ -347,6 +349,30 @@ def format_train(path: str, out_path: str, max_depth: int = 3):
     with open(out_path, "w") as f:
         json.dump(rep, f, indent=1)
     return rep
+
+
+def format_evaluate(path: str, tree_path: str):
+    """Time lost on a format sweep by a trained format tree (the rows of
+    format_train's report), against always taking the faster format and
+    against CSR alone."""
+    rows = json.load(open(tree_path))["rows"]
+    recs = [json.loads(l) for l in open(path) if l.strip()]
+    best = chosen = csr_only = 0.0
+    hits = 0
+    for r in recs:
+        x = [r["features"][k] for k in FORMAT_FEATURES]
+        i = 0
+        while rows[i][4] < 0:
+            i = rows[i][2] if x[rows[i][0]] <= rows[i][1] else rows[i][3]
+        c = min(r["csr_ms"].values())
+        s_ = r["sell_ms"] if r["sell_ms"] is not None else float("inf")
+        pick = s_ if rows[i][4] == 1 else c
+        best += min(c, s_)
+        chosen += pick
+        csr_only += c
+        hits += int(pick == min(c, s_))
+    return {"records": len(recs), "right_format": hits / len(recs), "loss_vs_best": chosen / best - 1.0,
+            "csr_only_loss_vs_best": csr_only / best - 1.0}
 
 
 def evaluate(paths, selector_paths):
@@ -796,6 +822,10 @@ def main(argv=None):
     fs = sub.add_parser("formats")
     fs.add_argument("--out", required=True)
     fs.add_argument("--reps", type=int, default=10)
+    fs.add_argument("--dtype", choices=("f32", "f64"), default="f32")
+    fe = sub.add_parser("formats-evaluate")
+    fe.add_argument("data")
+    fe.add_argument("--tree", required=True)
     ft = sub.add_parser("formats-train")
     ft.add_argument("data")
     ft.add_argument("--out", required=True)
@@ -808,7 +838,10 @@ def main(argv=None):
         driver_sweep(a.out, a.reps)
         return
     if a.cmd == "formats":
-        format_sweep(a.out, a.reps)
+        format_sweep(a.out, a.reps, a.dtype)
+        return
+    if a.cmd == "formats-evaluate":
+        print(json.dumps(format_evaluate(a.data, a.tree), indent=1))
         return
     if a.cmd == "formats-train":
         print(json.dumps(format_train(a.data, a.out), indent=1))
