@@ -214,9 +214,13 @@ spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, con
  * that copy and read x through the same renumbering (one gather of n
  * entries per call), so that the most-read x entries share cache lines.
  * Results are those of A up to the summation order within a row.
- * SPX_RENUMBER forces the copy, SPX_NO_RENUMBER forbids it. Memory:
- * 4 + value size bytes per entry for the copy, 4 for its source positions,
- * 8 per column.
+ * SPX_RENUMBER forces the copy, SPX_NO_RENUMBER forbids it. With it, for
+ * n <= 2^21, the handle also keeps the copy's entries reordered by column
+ * inside each 2048-item merge tile (each with its position in the tile),
+ * which the balanced row-major kernels read, so that a wave's gathers of x
+ * meet fewer cache lines; results are the same bits. Memory: 4 + value
+ * size bytes per entry for the copy, 4 for its source positions, 8 per
+ * column, and 8 + value size per entry for the reordered copy.
  *
  * Storage-format pre-selection (Section 8's extension: pick the matrix
  * format per matrix, before the kernel): besides CSR the handle can keep a

@@ -192,6 +192,9 @@ struct spx_matrix {
     // there is one), used by the SpMV pattern when present
     SellMat sell;
     double sell_ratio = 0.0;
+    // column-sorted copy of the renumbered CSR for the balanced SpMV with
+    // 2048-item tiles (kept with the renumbered copy when n <= 2^21)
+    TileSorted ts;
     int32_t* sp_idx = nullptr;
     void* sp_val = nullptr;
     int32_t* scratch_i32 = nullptr;  // compaction workspace
@@ -468,6 +471,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     sell_free(&H->sell);
+    tile_sorted_free(&H->ts);
     if (H->drv_host) hipHostFree(H->drv_host);
     for (auto& e : H->drv_ev)
         if (e) hipEventDestroy(e);
@@ -618,6 +622,13 @@ static spx_status build_gcsr(spx_matrix* H, uint32_t flags, hipStream_t s) {
     H->gcsr = A;
     H->gcsr.col_idx = H->gcol;
     H->gcsr.vals = vs > 0 ? H->gvals : nullptr;
+    // the column-sorted copy for the balanced SpMV (2048-item tiles)
+    if (A.n <= (1 << 21)) {
+        spx_plan bal{SPX_PAT_SPMV, SPX_DIST_BALANCED, SPX_WB_NONE, 0, 2048, 0};
+        const int32_t* part = nullptr;
+        SPX_TRY(cached_part(H, H->gcsr, 0, &bal, s, &part));
+        SPX_TRY(tile_sorted_build(H->gcsr, part, H->gsrc, &H->ts, s));
+    }
     return SPX_OK;
 }
 
@@ -733,6 +744,7 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     SPX_TRY(gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->sell.col) SPX_TRY(sell_refresh(H->sell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
+    if (H->ts.pk) SPX_TRY(gather_perm(H->csr.vals, H->ts.src, H->ts.vals, H->csr.nnz, vs, (hipStream_t)stream));
     return SPX_OK;
 }
 
@@ -969,7 +981,8 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         if (H->sell.col)
             SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
         else
-            SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared));
+            SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared,
+                                    H->gorder && H->ts.pk ? &H->ts : nullptr));
         record(H, H->ev_kern, false, s);
         if (un.xd) H->xd_clean = cleared;
         return SPX_OK;
@@ -1015,7 +1028,8 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
         bool cleared = false;
-        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, part, ws, s, un.bits ? &un : nullptr, &cleared));
+        SPX_TRY(launch_spmv_csr(&A, xd, H->bits, y, p, part, ws, s, un.bits ? &un : nullptr, &cleared,
+                                H->gorder && H->ts.pk ? &H->ts : nullptr));
         record(H, H->ev_kern, false, s);
         if (un.bits) H->bits_clean = cleared;
         return SPX_OK;
@@ -1120,7 +1134,8 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
     if (H->sell.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
     else
-        SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s));
+        SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s, nullptr, nullptr,
+                                H->gorder && H->ts.pk ? &H->ts : nullptr));
     record(H, H->ev_kern, false, s);
     return SPX_OK;
 }

@@ -87,24 +87,20 @@ struct CsrTileLds {
     int32_t nlong;
 };
 
-// One tile, NT threads: stage the products of its nonzeros in LDS with
-// coalesced loads (fully unrolled, so all gathers of a thread are in flight
-// together), then reduce every row whose end falls in the tile from LDS:
-// short rows by one thread, rows longer than kShortRow by a whole wave. The
-// row still open at the tile end leaves a carry for the fix-up pass
-// (carry_row = -1 if none). Ends with __syncthreads.
-template <int DT, bool VALID, int TILE, int NT, typename XF>
-__device__ __forceinline__ void csr_merge_tile_nt(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col_idx,
-                                                  const typename SR<DT>::V* __restrict__ vals, XF xf,
-                                                  const uint32_t* __restrict__ bits,
-                                                  typename SR<DT>::Y* __restrict__ y,
-                                                  const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
-                                                  typename SR<DT>::Acc* __restrict__ carry_val,
-                                                  CsrTileLds<DT, TILE>& L) {
+// One tile, NT threads: stage the products of its nonzeros in LDS (stage(k0,
+// Q, prod) writes prod[q] for the tile's items q < Q in row order), then
+// reduce every row whose end falls in the tile from LDS: short rows by one
+// thread, rows longer than kShortRow by a whole wave. The row still open
+// at the tile end leaves a carry for the fix-up pass (carry_row = -1 if
+// none). Ends with __syncthreads.
+template <int DT, int TILE, int NT, typename StageFn>
+__device__ __forceinline__ void csr_merge_tile_core(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
+                                                    typename SR<DT>::Y* __restrict__ y,
+                                                    const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
+                                                    typename SR<DT>::Acc* __restrict__ carry_val,
+                                                    CsrTileLds<DT, TILE>& L, StageFn stage) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
-    constexpr int kIpt = TILE / NT;
     constexpr int kWaves = NT / kWave;
     const int i0 = part[2 * tile], k0 = part[2 * tile + 1];
     const int i1 = part[2 * tile + 2], k1 = part[2 * tile + 3];
@@ -113,7 +109,7 @@ __device__ __forceinline__ void csr_merge_tile_nt(int64_t tile, int32_t m, const
     const bool open = i1 < m && k1 > row_ptr[i1];
     if (threadIdx.x == 0) L.nlong = 0;
     for (int r = threadIdx.x; r < R; r += NT) L.end[r] = row_ptr[i0 + 1 + r];
-    csr_stage_products<DT, VALID, kIpt, NT>(k0, Q, col_idx, vals, xf, bits, L.prod);
+    stage(k0, Q, L.prod);
     __syncthreads();
     const int nrows = R + (open ? 1 : 0);
     for (int r = threadIdx.x; r < nrows; r += NT) {
@@ -152,6 +148,72 @@ __device__ __forceinline__ void csr_merge_tile_nt(int64_t tile, int32_t m, const
     }
     if (!open && threadIdx.x == 0) carry_row[tile] = -1;
     __syncthreads();
+}
+
+// The tile over the row-ordered entries, x read through xf.
+template <int DT, bool VALID, int TILE, int NT, typename XF>
+__device__ __forceinline__ void csr_merge_tile_nt(int64_t tile, int32_t m, const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_idx,
+                                                  const typename SR<DT>::V* __restrict__ vals, XF xf,
+                                                  const uint32_t* __restrict__ bits,
+                                                  typename SR<DT>::Y* __restrict__ y,
+                                                  const int32_t* __restrict__ part, int32_t* __restrict__ carry_row,
+                                                  typename SR<DT>::Acc* __restrict__ carry_val,
+                                                  CsrTileLds<DT, TILE>& L) {
+    csr_merge_tile_core<DT, TILE, NT>(tile, m, row_ptr, y, part, carry_row, carry_val, L,
+                                      [&](int k0, int Q, typename SR<DT>::Acc* prod) {
+                                          csr_stage_products<DT, VALID, TILE / NT, NT>(k0, Q, col_idx, vals, xf,
+                                                                                       bits, prod);
+                                      });
+}
+
+// Column-sorted tiles: inside each 2048-item merge tile the entries are
+// ordered by column, so that the 64 gathers of a wave meet fewer cache
+// lines, and each entry's word holds its column (low kTsColBits bits) and
+// its position in the tile in row order (the bits above), where its product
+// goes. The reduction then runs on row-ordered products as above.
+constexpr int kTsColBits = 21;
+constexpr uint32_t kTsColMask = (1u << kTsColBits) - 1u;
+template <int DT, bool VALID, int IPT, int NT>
+__device__ __forceinline__ void csr_stage_sorted(int k0, int Q, const uint32_t* __restrict__ pk,
+                                                 const typename SR<DT>::V* __restrict__ vals,
+                                                 const typename SR<DT>::X* __restrict__ x,
+                                                 const uint32_t* __restrict__ bits,
+                                                 typename SR<DT>::Acc* __restrict__ prod) {
+    using S = SR<DT>;
+    if (Q == 0) return;
+    uint32_t w[IPT];
+    int kk[IPT];
+    bool on[IPT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int q = it * NT + threadIdx.x;
+        on[it] = q < Q;
+        kk[it] = k0 + (on[it] ? q : 0);
+    }
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) w[it] = pk[kk[it]];
+    bool ok[IPT];
+    if constexpr (VALID) {
+        uint32_t bw[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) bw[it] = bits[(w[it] & kTsColMask) >> 5];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) ok[it] = (bw[it] >> (w[it] & 31u)) & 1u;
+    } else {
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) ok[it] = true;
+    }
+    typename S::V a[IPT];
+    typename S::X b[IPT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        a[it] = ok[it] ? S::val(vals, kk[it]) : (typename S::V)0;
+        b[it] = ok[it] ? S::xval(x, (int64_t)(w[it] & kTsColMask)) : (typename S::X)0;
+    }
+#pragma unroll
+    for (int it = 0; it < IPT; ++it)
+        if (on[it]) prod[w[it] >> kTsColBits] = ok[it] ? S::mul(a[it], b[it]) : S::zero();
 }
 
 // The tile with kBlock threads and x read from global memory.

@@ -98,13 +98,31 @@ struct Unscatter {
     int32_t n = 0;  // length of x: past n / 16 entries the whole buffers are cleared with coalesced stores
 };
 
+// Column-sorted copy of a CSR for the balanced SpMV with 2048-item merge
+// tiles (csr_tile.hpp: inside each tile the entries ordered by column, each
+// word = column | position in the tile << 21; needs n <= 2^21).
+struct TileSorted {
+    uint32_t* pk = nullptr;  // [nnz]
+    void* vals = nullptr;    // [nnz] (none for BOOL)
+    int32_t* src = nullptr;  // [nnz] position in the original CSR (value refresh)
+};
+
 // part: merge-path partition of the balanced distribution (null: computed
 // into the workspace on this call). un (optional): positions to clear after
 // the product; *cleared (optional) tells whether they were (only the
-// balanced distribution has the pass that does it).
+// balanced distribution has the pass that does it). ts (optional): the
+// column-sorted copy of A, which the balanced row-major kernels with
+// 2048-item tiles (SpMV and the bitvector SpMSpV, LDS bitvector aside) then
+// read instead of A's column indices and values.
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
                            const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
-                           const Unscatter* un = nullptr, bool* cleared = nullptr);
+                           const Unscatter* un = nullptr, bool* cleared = nullptr,
+                           const TileSorted* ts = nullptr);
+// Builds ts for A (the partition of 2048-item tiles given); returns
+// SPX_ERR_UNSUPPORTED when n > 2^21. Synchronizes the stream.
+spx_status tile_sorted_build(const spx_csr& A, const int32_t* part, const int32_t* src_of_A, TileSorted* ts,
+                             hipStream_t s);
+void tile_sorted_free(TileSorted* ts);
 spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int tile, int32_t* part,
                            hipStream_t s);
 size_t spmv_csr_ws(int32_t m, int32_t nnz, const spx_plan* plan);

@@ -139,6 +139,27 @@ __global__ __launch_bounds__(kBlock) void k_csr_merge_fixup(int32_t tiles,
 }
 
 
+// Balanced SpMV / bitvector SpMSpV over the column-sorted copy (2048-item
+// tiles).
+template <int DT, bool VALID>
+__global__ __launch_bounds__(kBlock) void k_csr_merge_sorted(int32_t m, const int32_t* __restrict__ row_ptr,
+                                                             const uint32_t* __restrict__ pk,
+                                                             const typename SR<DT>::V* __restrict__ vals,
+                                                             const typename SR<DT>::X* __restrict__ x,
+                                                             const uint32_t* __restrict__ bits,
+                                                             typename SR<DT>::Y* __restrict__ y,
+                                                             const int32_t* __restrict__ part, int64_t tiles,
+                                                             int32_t* __restrict__ carry_row,
+                                                             typename SR<DT>::Acc* __restrict__ carry_val) {
+    constexpr int kTile = 2048;
+    __shared__ CsrTileLds<DT, kTile> L;
+    csr_merge_tile_core<DT, kTile, kBlock>(xcd_tile(blockIdx.x, tiles), m, row_ptr, y, part, carry_row, carry_val, L,
+                                           [&](int k0, int Q, typename SR<DT>::Acc* prod) {
+                                               csr_stage_sorted<DT, VALID, kTile / kBlock, kBlock>(k0, Q, pk, vals,
+                                                                                                   x, bits, prod);
+                                           });
+}
+
 // --------------------------------------------------------------- LDS bitvector
 // Row-major SpMSpV with the bitvector of supp(x) held in LDS. One persistent
 // 1024-thread workgroup per CU copies the bitvector (n / 8 bytes, up to
@@ -220,7 +241,7 @@ spx_status merge_partition(int32_t m, int32_t nnz, const int32_t* row_ptr, int t
 template <int DT, bool VALID>
 static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
                                const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
-                               const Unscatter* un, bool* cleared) {
+                               const Unscatter* un, bool* cleared, const TileSorted* ts) {
     using S = SR<DT>;
     const auto* vals = (const typename S::V*)A->vals;
     const auto* xv = (const typename S::X*)x;
@@ -270,6 +291,9 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
                                         (int)lds));
             k_csr_bitlds<DT><<<grid, kBitThreads, lds, s>>>(A->m, A->n, A->row_ptr, A->col_idx, vals, xv, bits, yv,
                                                            part, tiles, crow, cval);
+        } else if (ts && ts->pk && T == 2048) {
+            k_csr_merge_sorted<DT, VALID><<<(unsigned)tiles, kBlock, 0, s>>>(
+                A->m, A->row_ptr, ts->pk, (const typename S::V*)ts->vals, xv, bits, yv, part, tiles, crow, cval);
         } else if (T == 4096)
             k_csr_merge<DT, VALID, 4096><<<(unsigned)tiles, kBlock, 0, s>>>(A->m, A->row_ptr, A->col_idx, vals, xv,
                                                                            bits, yv, part, tiles, crow, cval);
@@ -290,14 +314,14 @@ static spx_status launch_csr_t(const spx_csr* A, const void* x, const uint32_t* 
 
 spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits, void* y,
                            const spx_plan* plan, const int32_t* part, Arena& ws, hipStream_t s,
-                           const Unscatter* un, bool* cleared) {
+                           const Unscatter* un, bool* cleared, const TileSorted* ts) {
     if (cleared) *cleared = false;
     const bool valid = plan->pattern == SPX_PAT_CSR_SPMSPV;
     switch (A->dtype) {
 #define SPX_DT(DT)                                                                            \
     case DT:                                                                                  \
-        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, part, ws, s, un, cleared)  \
-                     : launch_csr_t<DT, false>(A, x, bits, y, plan, part, ws, s, un, cleared);
+        return valid ? launch_csr_t<DT, true>(A, x, bits, y, plan, part, ws, s, un, cleared, ts)  \
+                     : launch_csr_t<DT, false>(A, x, bits, y, plan, part, ws, s, un, cleared, ts);
         SPX_DT(SPX_F32)
         SPX_DT(SPX_F64)
         SPX_DT(SPX_I32)
@@ -306,6 +330,126 @@ spx_status launch_spmv_csr(const spx_csr* A, const void* x, const uint32_t* bits
 #undef SPX_DT
     }
     return fail(SPX_ERR_DTYPE, "spmv: unknown dtype");
+}
+
+// --------------------------------------------------------------- column-sorted copy
+// tile_of[k] = the 2048-item tile holding entry k (a workgroup per tile)
+__global__ __launch_bounds__(kBlock) void k_ts_tile_of(const int32_t* __restrict__ part, int64_t tiles,
+                                                       int32_t* __restrict__ tile_of) {
+    const int64_t t = blockIdx.x;
+    if (t >= tiles) return;
+    const int k0 = part[2 * t + 1], k1 = part[2 * t + 3];
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) tile_of[k] = (int32_t)t;
+}
+
+// keys = column, vals = position (the first sort: by column)
+__global__ __launch_bounds__(kBlock) void k_ts_pairs(int64_t nnz, const int32_t* __restrict__ col,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride) {
+        keys[k] = (uint32_t)col[k];
+        vals[k] = (uint32_t)k;
+    }
+}
+
+// keys = tile of each position (the second, stable sort: by tile)
+__global__ __launch_bounds__(kBlock) void k_ts_tile_keys(int64_t nnz, const uint32_t* __restrict__ pos,
+                                                         const int32_t* __restrict__ tile_of,
+                                                         uint32_t* __restrict__ keys) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride)
+        keys[k] = (uint32_t)tile_of[pos[k]];
+}
+
+// Sorted position p holds entry src = pos[p], of the same tile (the tiles'
+// ranges are contiguous and the sort keeps their sizes): its word packs the
+// column with src's slot in the tile.
+__global__ __launch_bounds__(kBlock) void k_ts_fill(int64_t nnz, const uint32_t* __restrict__ pos,
+                                                    const int32_t* __restrict__ tile_of,
+                                                    const int32_t* __restrict__ part,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ src_of_A,
+                                                    uint32_t* __restrict__ pk, int32_t* __restrict__ src) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride) {
+        const uint32_t e = pos[p];
+        const int32_t k0 = part[2 * tile_of[p] + 1];
+        pk[p] = (uint32_t)col[e] | ((e - (uint32_t)k0) << kTsColBits);
+        src[p] = src_of_A ? src_of_A[e] : (int32_t)e;
+    }
+}
+
+void tile_sorted_free(TileSorted* ts) {
+    void* ptrs[] = {ts->pk, ts->vals, ts->src};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    *ts = TileSorted{};
+}
+
+static int bits_for(int64_t n) {
+    int b = 1;
+    while (b < 31 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+spx_status tile_sorted_build(const spx_csr& A, const int32_t* part, const int32_t* src_of_A, TileSorted* out,
+                             hipStream_t s) {
+    const int64_t nnz = A.nnz;
+    if (A.n > (1 << kTsColBits)) return fail(SPX_ERR_UNSUPPORTED, "column-sorted copy: n above 2^21");
+    if (nnz == 0 || A.m == 0) return SPX_OK;
+    const int64_t tiles = ceil_div((int64_t)A.m + nnz, 2048);
+    const int vs = value_size(A.dtype);
+    TileSorted ts;
+    uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
+    int32_t *rws = nullptr, *tile_of = nullptr;
+    spx_status st = SPX_OK;
+    do {
+        if (hipMalloc((void**)&ts.pk, nnz * 4) != hipSuccess || hipMalloc((void**)&ts.src, nnz * 4) != hipSuccess ||
+            (vs > 0 && hipMalloc(&ts.vals, nnz * vs) != hipSuccess) ||
+            hipMalloc((void**)&keys, nnz * 4) != hipSuccess || hipMalloc((void**)&vals, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&keys2, nnz * 4) != hipSuccess || hipMalloc((void**)&vals2, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&tile_of, nnz * 4) != hipSuccess ||
+            hipMalloc((void**)&rws, radix_ws_elems(nnz) * 4) != hipSuccess) {
+            st = fail(SPX_ERR_ALLOC, "column-sorted copy: allocation failed");
+            break;
+        }
+        const int grid = (int)std::min<int64_t>(ceil_div(nnz, kBlock), 8192);
+        k_ts_tile_of<<<(unsigned)tiles, kBlock, 0, s>>>(part, tiles, tile_of);
+        k_ts_pairs<<<grid, kBlock, 0, s>>>(nnz, A.col_idx, keys, vals);
+        if (hipGetLastError() != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "column-sorted copy: kernels");
+            break;
+        }
+        bool alt = false;
+        if ((st = radix_sort_pairs(keys, vals, keys2, vals2, nnz, bits_for(A.n), rws, s, &alt))) break;
+        uint32_t* pos = alt ? vals2 : vals;
+        uint32_t* k2 = alt ? keys2 : keys;
+        uint32_t* other_k = alt ? keys : keys2;
+        uint32_t* other_v = alt ? vals : vals2;
+        k_ts_tile_keys<<<grid, kBlock, 0, s>>>(nnz, pos, tile_of, k2);
+        if (hipGetLastError() != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "column-sorted copy: kernels");
+            break;
+        }
+        bool alt2 = false;
+        if ((st = radix_sort_pairs(k2, pos, other_k, other_v, nnz, bits_for(tiles), rws, s, &alt2))) break;
+        uint32_t* pos2 = alt2 ? other_v : pos;
+        k_ts_fill<<<grid, kBlock, 0, s>>>(nnz, pos2, tile_of, part, A.col_idx, src_of_A, ts.pk, ts.src);
+        if (hipGetLastError() != hipSuccess) {
+            st = fail(SPX_ERR_HIP, "column-sorted copy: kernels");
+            break;
+        }
+        if (vs > 0 && (st = gather_perm(A.vals, (const int32_t*)pos2, ts.vals, nnz, vs, s))) break;
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(SPX_ERR_HIP, "column-sorted copy: sync");
+    } while (0);
+    for (void* p : {(void*)keys, (void*)vals, (void*)keys2, (void*)vals2, (void*)rws, (void*)tile_of})
+        if (p) hipFree(p);
+    if (st != SPX_OK) {
+        tile_sorted_free(&ts);
+        return st;
+    }
+    *out = ts;
+    return SPX_OK;
 }
 
 }  // namespace spx
