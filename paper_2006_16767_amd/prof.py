@@ -49,12 +49,20 @@ def library_source_hash() -> str:
     return h.hexdigest()
 
 
-def kernel_names(p) -> list[str]:
-    """Kernel-name stems of the launches a plan makes."""
+def kernel_names(p, column_sorted: bool = False) -> list[str]:
+    """Kernel-name stems of the launches a plan makes. column_sorted: the
+    handle keeps the column-sorted tiles (renumbered, n <= 2^21), which the
+    balanced row-major plans with 2048-item tiles read."""
     if p.pattern in (0, 1):
         if p.distribution == 0:
             return ["k_csr_direct"]
-        return (["k_csr_bitlds"] if p.pattern == 1 and p.tile == 1 else ["k_csr_merge"]) + ["k_csr_merge_fixup"]
+        if p.pattern == 1 and p.tile == 1:
+            main = "k_csr_bitlds"
+        elif column_sorted and p.tile != 4096:
+            main = "k_csr_merge_sorted"
+        else:
+            main = "k_csr_merge"
+        return [main, "k_csr_merge_fixup"]
     dist = "direct" if p.distribution == 0 else "merge"
     if p.writeback == 4:
         return [f"k_bucket_scatter_{dist}", "k_bucket_accumulate"]
@@ -121,7 +129,8 @@ def cmd_vector(args):
     call()
     torch.cuda.synchronize()
     p = M.last_plan()
-    print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p)}", flush=True)
+    sorted_tiles = M.column_order() is not None and M.n <= (1 << 21)
+    print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p, sorted_tiles)}", flush=True)
     for _ in range(args.reps):
         call()
     torch.cuda.synchronize()
