@@ -332,8 +332,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the Poisson / batched / backward figures")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the path runs on one GPU (asked for --gpus {args.gpus}); "
+              "sharding it across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

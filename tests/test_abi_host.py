@@ -19,7 +19,7 @@ def _declared_functions():
     return sorted(set(names))
 
 
-def test_header_declares_north_star_names():
+def test_header_declares_the_entry_points():
     names = _declared_functions()
     for n in ("spmv_csr", "spmspv_csc", "select_kernel", "run", "run_batch", "spmv_csr_transpose",
               "dvals_pattern", "spx_matrix_create", "spx_last_error"):
