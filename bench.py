@@ -7,17 +7,28 @@ FP32 weights U[0,1]; nnz fractions log-spaced over [1e-5, 0.5]), run():
 lazy features, the decision-tree cascade, vector conversion if needed, and
 the chosen kernel(s). Inputs are resident in HBM before timing starts.
 
-value = sum over the vectors of the algorithmic bytes min(B_CSC, B_SpMV)
-        divided by the step time (GB/s). The roofline object reports the
-dominant kernel: the plan with the largest kernel time in an untimed pass
-that records HIP events around every call, then timed in the timed steps
-with HIP events around that vector's launches only (on the launch stream;
-an event pair costs a few microseconds of queue time, so the other calls
-run without them). cpu_baseline is
-the plain C oracle (column-scatter SpMSpV over a dense accumulator) timed
-on the host on a bounded sample of the same vectors.
+Timing protocol (the paper averages 10 runs; its measurement section):
+  * every timed repetition starts from cold caches: an untimed read of a
+    1 GiB scratch buffer (larger than the 256 MB Infinity Cache and the
+    8 x 4 MB L2s, and it leaves no dirty lines to write back inside the
+    timed region) comes before it;
+  * a repetition is timed with HIP events on the launch stream;
+  * warm figures (back-to-back repetitions, no flush) are reported beside
+    the flushed ones and labelled as such.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+value = sum over the vectors of the algorithmic bytes min(B_CSC, B_SpMV)
+        divided by the mean flushed step time (GB/s); the GFLOP/s figure
+        counts 2 flops per effective entry (2 nnz_s per vector).
+The roofline object reports the dominant kernel: the plan with the largest
+kernel time in an untimed pass, timed in the timed steps with HIP events
+around that vector's launches only (an event pair costs queue time, so the
+other calls run without them). The copy figure is the library's streaming
+copy of 1 GiB (the achievable-bandwidth reference beside the 8 TB/s
+published peak). cpu_baseline is the plain C oracle (column scatter into a
+dense accumulator) on a bounded sample of the same vectors: on all host
+cores (disjoint row ranges, OpenMP) as the value, and on one thread.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 from __future__ import annotations
 
@@ -31,6 +42,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FLUSH_BYTES = 1 << 30
 
 
 def alg_bytes(m, n, nnz, nnz_x, nnz_s, s_i=4, s_v=4, s_x=4, s_y=4):
@@ -41,60 +53,127 @@ def alg_bytes(m, n, nnz, nnz_x, nnz_s, s_i=4, s_v=4, s_x=4, s_y=4):
     return min(b_spmv, b_csc), b_spmv, b_csc
 
 
-def cpu_baseline(A, vecs, min_seconds=10.0, max_rounds=200):
-    """The oracle as it stands, single-threaded, over the same vectors until
-    at least min_seconds of CPU time have accumulated."""
-    import numpy as np
-    import oracle
-    csc = oracle.transpose(A)  # one-time matrix preparation, not timed
-    tot_bytes = 0
-    tot_t = 0.0
-    rounds = 0
-    nsum = []
-    for v in vecs:
-        vf = oracle.vector_features(csc, v.idx)
-        nsum.append(vf["nnz_s"])
-    while tot_t < min_seconds and rounds < max_rounds:
-        for v, ns in zip(vecs, nsum):
-            t0 = time.perf_counter()
-            oracle.spmspv(csc, v.idx, v.val)
-            tot_t += time.perf_counter() - t0
-            tot_bytes += alg_bytes(A.m, A.n, A.nnz, v.nnz, ns)[0]
-        rounds += 1
-    return {"value": tot_bytes / tot_t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rounds} passes over the 12 sweep vectors (oracle column-scatter SpMSpV into a "
-                      f"dense accumulator, float64 Neumaier sums), {tot_t:.1f} s on 1 host thread"}
+class Flusher:
+    """Cold caches before a timed repetition: reads a 1 GiB scratch buffer
+    (written once at allocation), untimed."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.buf = torch.ones(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+
+    def __call__(self):
+        self.sink = self.buf.sum()
 
 
-def _timer(torch):
-    def timeit(fn, reps):
-        fn()
-        torch.cuda.synchronize()
+def event_times(torch, fn, reps, flush=None):
+    """Per-repetition times (ms) with HIP events on the current stream; the
+    flush (if any) runs before each start event, untimed."""
+    fn()
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        if flush:
+            flush()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(reps):
-            fn()
+        fn()
         e1.record()
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
-    return timeit
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
 
 
-def extra_poisson(torch, spx, synth, reps=50):
-    """7-point Poisson 128^3, FP32, dense x ~ N(0,1): the SpMV roofline case."""
+def warm_ms(torch, fn, reps):
+    """Mean time (ms) of back-to-back repetitions, no flush."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _stats(ts):
+    s = sorted(ts)
+    return {"median_ms": round(s[len(s) // 2], 5), "mean_ms": round(sum(s) / len(s), 5), "reps": len(s)}
+
+
+def cpu_baseline(A, vecs, min_seconds=10.0, omp_seconds=5.0, max_rounds=200):
+    """The oracle as it stands over the same vectors: its column scatter on
+    all host cores (disjoint row ranges, OpenMP; the value) and on one
+    thread, each until its time budget has accumulated."""
+    import oracle
+    csc = oracle.transpose(A)  # one-time matrix preparation, not timed
+    nsum = [oracle.vector_features(csc, v.idx)["nnz_s"] for v in vecs]
+
+    def leg(fn, budget):
+        tot_bytes, tot_t, rounds = 0, 0.0, 0
+        while tot_t < budget and rounds < max_rounds:
+            for v, ns in zip(vecs, nsum):
+                t0 = time.perf_counter()
+                fn(csc, v.idx, v.val)
+                tot_t += time.perf_counter() - t0
+                tot_bytes += alg_bytes(A.m, A.n, A.nnz, v.nnz, ns)[0]
+            rounds += 1
+        return tot_bytes / tot_t / 1e9, rounds, tot_t
+
+    threads = oracle.omp_threads()
+    omp_v, omp_r, omp_t = leg(oracle.spmspv_omp, omp_seconds)
+    one_v, one_r, one_t = leg(oracle.spmspv, min_seconds)
+    return {"value": omp_v, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{omp_r} passes over the 12 sweep vectors ({omp_t:.1f} s): the oracle's column scatter "
+                      f"into a dense accumulator, float64 Neumaier sums, disjoint row ranges on {threads} "
+                      f"OpenMP threads",
+            "host_cores_affinity": len(os.sched_getaffinity(0)),
+            "single_thread": {"value": one_v, "unit": "GB/s", "cores": 1,
+                              "sample": f"{one_r} passes over the 12 sweep vectors, {one_t:.1f} s on 1 thread"}}
+
+
+def extra_copy(torch, spx, flush, reps=10):
+    """Achievable bandwidth: the library's streaming copy of 1 GiB."""
+    src = torch.ones(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ts = event_times(torch, lambda: spx.stream_copy(src, dst), reps, flush)
+    st = _stats(ts)
+    gbs = 2 * FLUSH_BYTES / (st["median_ms"] * 1e-3) / 1e9
+    return {"workload": "stream_copy_1GiB", **st, "bytes_moved": 2 * FLUSH_BYTES, "GB/s": round(gbs, 1),
+            "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2)}
+
+
+def extra_poisson(torch, spx, synth, flush, reps=20):
+    """7-point Poisson 128^3 (the SpMV roofline case): dense x ~ N(0,1) in
+    FP32 and FP64, and the 1 % sparse x in FP32, each through run()."""
     import numpy as np
-    A = synth.cfg3_matrix()
-    M = spx.Matrix.from_host(A)
-    x = torch.as_tensor(synth.cfg3_vectors()[0], device="cuda")
-    y = M.out_tensor()
-    timeit = _timer(torch)
-    ms = timeit(lambda: M.run(x, y), reps)
-    plan = M.last_plan()
-    b = A.nnz * 8 + (A.m + 1) * 4 + A.n * 4 + A.m * 4
-    gbs = b / (ms * 1e-3) / 1e9
-    return {"workload": "poisson3d_128_f32_dense_x", "plan": repr(plan), "ms": round(ms, 4),
-            "alg_bytes": b, "GB/s": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2)}
+    out = {}
+    for name, dt in (("f32", np.float32), ("f64", np.float64)):
+        A = synth.cfg3_matrix(dt)
+        M = spx.Matrix.from_host(A)
+        xd, xs = synth.cfg3_vectors(dtype=dt)
+        s = np.dtype(dt).itemsize
+        cases = [("dense_x", torch.as_tensor(xd, device="cuda"), A.n, A.nnz)]
+        if name == "f32":
+            cases.append(("sparse_x_1pct", (torch.as_tensor(xs.idx, device="cuda"),
+                                            torch.as_tensor(np.asarray(xs.val, dt), device="cuda")), xs.nnz, None))
+        y = M.out_tensor()
+        for case, x, nnz_x, nnz_s in cases:
+            if nnz_s is None:
+                nnz_s = int(M.vector_features(x)["nnz_s"])
+            b = alg_bytes(A.m, A.n, A.nnz, nnz_x, nnz_s, 4, s, s, s)[0]
+            ts = event_times(torch, lambda: M.run(x, y), reps, flush)
+            st = _stats(ts)
+            w = warm_ms(torch, lambda: M.run(x, y), reps)
+            gbs = b / (st["median_ms"] * 1e-3) / 1e9
+            out[f"{name}_{case}"] = {
+                "workload": f"poisson3d_128_{name}_{case}", "plan": repr(M.last_plan()), "alg_bytes": b, **st,
+                "GB/s": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                "GFLOP/s": round(2 * nnz_s / (st["median_ms"] * 1e-3) / 1e9, 1),
+                "warm_ms": round(w, 5), "warm_pct_hbm_peak": round(100 * b / (w * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)}
+    return out
 
 
 def _pack(torch, vecs, np):
@@ -103,36 +182,49 @@ def _pack(torch, vecs, np):
     idx = np.concatenate([v.idx for v in vecs]).astype(np.int32)
     val = np.concatenate([np.asarray(v.val, np.float32) for v in vecs])
     return (torch.as_tensor(ptr, device="cuda"), torch.as_tensor(idx, device="cuda"),
-            torch.as_tensor(val, device="cuda"))
+            torch.as_tensor(val, device="cuda")), ptr
 
 
-def extra_batched(torch, spx, synth, reps=5):
-    """512 sparse vectors (densities log-uniform in [1e-4, 0.5]) on R-MAT
-    2^18 (degree 32): one graph launch of run_batch vs a loop of run()."""
+def _batched(torch, spx, A, vecs, workload, flush, reps):
     import numpy as np
-    A = synth.cfg4_rmat()
     M = spx.Matrix.from_host(A)
-    vecs = synth.cfg4_rmat_batch(A.n, 512)
-    ptr, idx, val = _pack(torch, vecs, np)
+    (ptr, idx, val), hp = _pack(torch, vecs, np)
     Y = M.out_tensor(len(vecs))
-    xs = [(idx[ptr[b]:ptr[b + 1]], val[ptr[b]:ptr[b + 1]]) for b in range(len(vecs))]
-    timeit = _timer(torch)
-    t_batch = timeit(lambda: M.run_batch(ptr, idx, val, Y), reps)
-    t_loop = timeit(lambda: [M.run(x, Y[b]) for b, x in enumerate(xs)], reps)
+    xs = [(idx[hp[b]:hp[b + 1]], val[hp[b]:hp[b + 1]]) for b in range(len(vecs))]
+    tb = _stats(event_times(torch, lambda: M.run_batch(ptr, idx, val, Y), reps, flush))
+    tl = _stats(event_times(torch, lambda: [M.run(x, Y[b]) for b, x in enumerate(xs)], reps, flush))
+    wb = warm_ms(torch, lambda: M.run_batch(ptr, idx, val, Y), reps)
+    wl = warm_ms(torch, lambda: [M.run(x, Y[b]) for b, x in enumerate(xs)], reps)
     nnz_s = [int(M.vector_features(x)["nnz_s"]) for x in xs]
     sum_b = sum(alg_bytes(A.m, A.n, A.nnz, v.nnz, ns)[0] for v, ns in zip(vecs, nnz_s))
-    uniq = A.nnz * 8 + (A.m + 1) * 4 + (A.n + 1) * 4 + int(ptr[-1]) * 8 + len(vecs) * A.m * 4
-    return {"workload": "rmat18_deg32_f32_batch512", "batched_ms": round(t_batch, 3), "looped_ms": round(t_loop, 3),
-            "speedup_batched_vs_looped": round(t_loop / t_batch, 2),
-            "GB/s_sum_per_vector_bytes": round(sum_b / (t_batch * 1e-3) / 1e9, 1),
-            "GB/s_unique_bytes": round(uniq / (t_batch * 1e-3) / 1e9, 1),
+    uniq = A.nnz * 8 + (A.m + 1) * 4 + (A.n + 1) * 4 + int(hp[-1]) * 8 + len(vecs) * A.m * 4
+    t = tb["median_ms"] * 1e-3
+    return {"workload": workload, "batched": tb, "looped": tl,
+            "speedup_batched_vs_looped": round(tl["median_ms"] / tb["median_ms"], 2),
+            "GB/s_sum_per_vector_bytes": round(sum_b / t / 1e9, 1),
+            "GB/s_unique_bytes": round(uniq / t / 1e9, 1),
+            "pct_hbm_peak_unique_bytes": round(100 * uniq / t / 1e9 / HBM_PEAK_GBS, 2),
+            "GFLOP/s": round(2 * sum(nnz_s) / t / 1e9, 1),
+            "warm_batched_ms": round(wb, 4), "warm_looped_ms": round(wl, 4),
             "status": M.batch_status()}
 
 
-def extra_fwd_bwd(torch, spx, synth, reps=10):
+def extra_batched(torch, spx, synth, flush, reps=5):
+    """Batched vs looped, both halves of the batched workload: 512 sparse
+    vectors (densities log-uniform in [1e-4, 0.5]) on R-MAT 2^18 (degree
+    32), and 256 rows of a 100k x 50k power-law matrix as x against it.
+    One graph launch of run_batch vs a loop of run() on the same stream."""
+    A = synth.cfg4_rmat()
+    r = _batched(torch, spx, A, synth.cfg4_rmat_batch(A.n, 512), "rmat18_deg32_f32_batch512", flush, reps)
+    S = synth.cfg4_svm()
+    s = _batched(torch, spx, S, synth.cfg4_svm_batch(S, 256), "powerlaw_100kx50k_f32_batch256", flush, reps)
+    return {"rmat": r, "svm": s}
+
+
+def extra_fwd_bwd(torch, spx, synth, flush, reps=10):
     """Pruned FC layer 16384 x 4096 at 5%, batch 64 of post-ReLU activations
     (50..95% zeros): forward (fused batch SpMV; the per-vector SpMSpV mode
-    timed beside it) vs forward + backward (dX and dvals)."""
+    timed beside it) vs forward + backward (dX and dvals), each flushed."""
     import numpy as np
     A = synth.cfg5_matrix()
     M = spx.Matrix.from_host(A)
@@ -145,11 +237,11 @@ def extra_fwd_bwd(torch, spx, synth, reps=10):
     Y = M.out_tensor(64)
     dX = torch.empty_like(X)
     dv = torch.empty(A.nnz, dtype=torch.float32, device="cuda")
-    timeit = _timer(torch)
-    t_f = timeit(lambda: M.spmv_batch(X, Y), reps)  # the layer's default forward (one pass over A)
-    t_f_sparse = timeit(lambda: M.run_dense_batch(X, Y), reps)  # per-vector adaptive SpMSpV
-    t_dx = timeit(lambda: M.transpose_matvec(G, dX), reps)
-    t_dv = timeit(lambda: M.dvals(G, X, dv), reps)
+    med = lambda fn: _stats(event_times(torch, fn, reps, flush))["median_ms"]
+    t_f = med(lambda: M.spmv_batch(X, Y))  # the layer's default forward (one pass over A)
+    t_f_sparse = med(lambda: M.run_dense_batch(X, Y))  # per-vector adaptive SpMSpV
+    t_dx = med(lambda: M.transpose_matvec(G, dX))
+    t_dv = med(lambda: M.dvals(G, X, dv))
     B, m, n, nnz = 64, A.m, A.n, A.nnz
     nnz_x = [v.nnz for v in acts]
     xs = [(torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda")) for v in acts]
@@ -170,42 +262,52 @@ def extra_fwd_bwd(torch, spx, synth, reps=10):
     f_pv, f_u = pct(fwd_pv, t_f), pct(fwd_u, t_f)
     b_pv = 100 * (dx_pv + dv_b) / t_b / 1e9 / HBM_PEAK_GBS
     b_u = 100 * (dx_u + dv_b) / t_b / 1e9 / HBM_PEAK_GBS
-    return {"workload": "fc16384x4096_d0.05_batch64_f32", "fwd_ms": round(t_f, 3), "dx_ms": round(t_dx, 3),
-            "dvals_ms": round(t_dv, 3), "fwd_sparse_mode_ms": round(t_f_sparse, 3),
+    return {"workload": "fc16384x4096_d0.05_batch64_f32", "fwd_ms": round(t_f, 4), "dx_ms": round(t_dx, 4),
+            "dvals_ms": round(t_dv, 4), "fwd_sparse_mode_ms": round(t_f_sparse, 4),
             "fwd_plus_bwd_over_fwd": round((t_f + t_dx + t_dv) / t_f, 2),
             "per_vector_scale": {"fwd_pct_hbm_peak": round(f_pv, 2), "bwd_pct_hbm_peak": round(b_pv, 2),
                                  "bwd_over_fwd": round(b_pv / f_pv, 2)},
             "unique_scale": {"fwd_pct_hbm_peak": round(f_u, 2), "bwd_pct_hbm_peak": round(b_u, 2),
                              "bwd_over_fwd": round(b_u / f_u, 2)},
-            "dx_pct_unique": round(pct(dx_u, t_dx), 2), "dvals_pct": round(pct(dv_b, t_dv), 2)}
+            "dx_pct_unique": round(pct(dx_u, t_dx), 2), "dvals_pct": round(pct(dv_b, t_dv), 2),
+            "GFLOP/s": {"fwd": round(2 * B * nnz / (t_f * 1e-3) / 1e9, 1),
+                        "dx": round(2 * B * nnz / (t_dx * 1e-3) / 1e9, 1),
+                        "dvals": round(2 * B * nnz / (t_dv * 1e-3) / 1e9, 1)}}
 
 
 def _plan_str(p):
     if p.lanes == -1:
         return "masked_pull"
+    wbs = ["none", "atomic", "sort", "lds_atomic", "bucket", "merge"]
     return (f"{['spmv', 'csr_spmspv', 'csc_spmspv'][p.pattern]}/{['direct', 'balanced'][p.distribution]}/"
-            f"{['none', 'atomic', 'sort', 'lds_atomic', 'bucket'][p.writeback]}")
+            f"{wbs[p.writeback]}")
 
 
-def extra_pagerank(torch, spx, synth, reps=3):
+def _driver_ms(torch, fn, reps, flush):
+    fn()  # warm-up
+    torch.cuda.synchronize()
+    tot = 0.0
+    out = None
+    for _ in range(reps):
+        flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t0
+    return tot / reps * 1e3, out
+
+
+def extra_pagerank(torch, spx, synth, flush, reps=3):
     """Incremental PageRank on the R-MAT 2^20 graph (FP32 weights U[0, 1],
     damping 0.85, eps = 1e-3 (1 - d) / n): one adaptive SpMSpV per round as
-    the active set thins out, against every round on one fixed kernel."""
+    the active set thins out, against every round on one fixed kernel.
+    Wall time per run, flushed before each."""
     A = synth.cfg2_matrix()
     M = spx.Matrix.from_host(A)
     d = 0.85
     eps = 1e-3 * (1 - d) / A.n
-
-    def timed(plan=None):
-        M.pagerank(d, eps, plan=plan)  # warm-up (and the column sums)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            _, plans = M.pagerank(d, eps, plan=plan)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps * 1e3, plans
-
-    ms, plans = timed()
+    ms, (_, plans) = _driver_ms(torch, lambda: M.pagerank(d, eps), reps, flush)
     used = {}
     for p in plans:
         used[_plan_str(p)] = used.get(_plan_str(p), 0) + 1
@@ -216,7 +318,7 @@ def extra_pagerank(torch, spx, synth, reps=3):
                     ("csr_spmspv_balanced", spx.plan("csr_spmspv", "balanced")),
                     ("csc_balanced_atomic", spx.plan("csc_spmspv", "balanced", "atomic")),
                     ("csc_direct_atomic", spx.plan("csc_spmspv", "direct", "atomic"))):
-        out["fixed_ms"][name] = round(timed(p)[0], 3)
+        out["fixed_ms"][name] = round(_driver_ms(torch, lambda: M.pagerank(d, eps, plan=p), reps, flush)[0], 3)
     best = min(out["fixed_ms"].values())
     out["adaptive_speedup_vs_best_fixed"] = round(best / ms, 2)
     return out
@@ -224,14 +326,14 @@ def extra_pagerank(torch, spx, synth, reps=3):
 
 def extra_sparse_output(torch, spx, synth, reps=20):
     """Sparse-output SpMSpV (row list, no dense y) against run() with its
-    dense y, on the R-MAT 2^20 sweep vectors up to 1 % density: kernel time
-    from the library's HIP events around each call's launches (the dense
-    y's zero fill included on the dense side; on the sparse side the count
-    read-back is not a kernel). A consumer that needs the list (frontier
-    chaining) must compact the dense y: the wall time of run() followed by
-    the library's dense-to-sparse conversion and the count read-back is
-    given beside the sparse call's wall time (both end with the count on
-    the host)."""
+    dense y, on the R-MAT 2^20 sweep vectors up to 1 % density (warm: these
+    are launch-bound): kernel time from the library's HIP events around
+    each call's launches (the dense y's zero fill included on the dense
+    side; on the sparse side the count read-back is not a kernel). A
+    consumer that needs the list (frontier chaining) must compact the dense
+    y: the wall time of run() followed by the library's dense-to-sparse
+    conversion and the count read-back is given beside the sparse call's
+    wall time (both end with the count on the host)."""
     from paper_2006_16767_amd import _lib
     A = synth.cfg2_matrix()
     M = spx.Matrix.from_host(A)
@@ -257,8 +359,8 @@ def extra_sparse_output(torch, spx, synth, reps=20):
         torch.cuda.synchronize()
         return round((time.perf_counter() - t0) / reps * 1e6, 1)
 
-    out = {"workload": "rmat20_deg16_f32_sparse_output", "nnz_x": [], "dense_us": [], "sparse_us": [],
-           "dense_then_list_wall_us": [], "sparse_wall_us": [], "rows_listed": []}
+    out = {"workload": "rmat20_deg16_f32_sparse_output", "cache": "warm (back-to-back calls)", "nnz_x": [],
+           "dense_us": [], "sparse_us": [], "dense_then_list_wall_us": [], "sparse_wall_us": [], "rows_listed": []}
     for v in vecs:
         if v.nnz > A.n // 100:
             break
@@ -284,52 +386,65 @@ def extra_sparse_output(torch, spx, synth, reps=20):
     return out
 
 
-def extra_bfs(torch, spx, synth, reps=3):
+def extra_bfs(torch, spx, synth, flush, reps=3):
     """Breadth-first search on the R-MAT 2^20 graph (pattern): one adaptive
     SpMSpV per level (with and without the masked-pull levels) against
-    every level on one fixed kernel."""
+    every level on one fixed kernel. Wall time per run, flushed before each."""
     import numpy as np
     A = synth.cfg2_matrix()
     M = spx.Matrix.from_host(A, dtype=spx.BOOL)
     outdeg = np.bincount(A.col_idx, minlength=A.n)
     src = 0 if outdeg[0] > 0 else int(np.nonzero(outdeg > 0)[0][0])
-
-    def timed(plan=None, push_only=False):
-        M.bfs(src, plan=plan, push_only=push_only)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            level, plans = M.bfs(src, plan=plan, push_only=push_only)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps * 1e3, level, plans
-
-    ms, level, plans = timed()
+    ms, (level, plans) = _driver_ms(torch, lambda: M.bfs(src), reps, flush)
     reached = level.cpu().numpy() >= 0
     edges = int(outdeg[reached].sum())  # edges leaving reached vertices
     out = {"workload": "rmat20_deg16_bfs", "source": src, "levels": M.bfs_levels,
            "edges_traversed": edges, "adaptive_ms": round(ms, 3),
            "adaptive_GTEPS": round(edges / (ms * 1e-3) / 1e9, 2),
            "plans_per_level": [_plan_str(p) for p in plans],
-           "adaptive_push_only_ms": round(timed(push_only=True)[0], 3),
+           "adaptive_push_only_ms": round(_driver_ms(torch, lambda: M.bfs(src, push_only=True), reps, flush)[0], 3),
            "fixed_ms": {}}
     for name, p in (("spmv_balanced", spx.plan("spmv", "balanced")),
                     ("csr_spmspv_balanced", spx.plan("csr_spmspv", "balanced")),
                     ("csc_balanced_atomic", spx.plan("csc_spmspv", "balanced", "atomic")),
                     ("csc_direct_atomic", spx.plan("csc_spmspv", "direct", "atomic"))):
-        out["fixed_ms"][name] = round(timed(p)[0], 3)
+        out["fixed_ms"][name] = round(_driver_ms(torch, lambda: M.bfs(src, plan=p), reps, flush)[0], 3)
     best = min(out["fixed_ms"].values())
     out["adaptive_speedup_vs_best_fixed"] = round(best / ms, 2)
+    return out
+
+
+def extra_small(torch, spx, synth, flush, reps=20):
+    """The small plain case (4096 x 4096, 16 entries per row): run() on the
+    dense x and the four sparse x. L2-resident and launch-bound, reported,
+    not gated."""
+    import numpy as np
+    A = synth.cfg1_matrix()
+    M = spx.Matrix.from_host(A)
+    xd, sparse = synth.cfg1_vectors()
+    y = M.out_tensor()
+    out = {"workload": "uniform4096x4096_16perrow_f32", "cases": []}
+    cases = [("dense", torch.as_tensor(np.asarray(xd, np.float32), device="cuda"), A.n)]
+    cases += [(f"sparse_{v.nnz}", (torch.as_tensor(v.idx, device="cuda"),
+                                    torch.as_tensor(np.asarray(v.val, np.float32), device="cuda")), v.nnz)
+              for v in sparse]
+    for name, x, nx in cases:
+        ns = int(M.vector_features(x)["nnz_s"]) if isinstance(x, tuple) else A.nnz
+        b = alg_bytes(A.m, A.n, A.nnz, nx, ns)[0]
+        st = _stats(event_times(torch, lambda: M.run(x, y), reps, flush))
+        out["cases"].append({"x": name, "plan": _plan_str(M.last_plan()), **st,
+                             "GB/s": round(b / (st["median_ms"] * 1e-3) / 1e9, 1)})
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-extras", action="store_true", help="skip the Poisson / batched / backward figures")
+    ap.add_argument("--no-extras", action="store_true", help="skip the figures beyond the headline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the path runs on one GPU (asked for --gpus {args.gpus}); "
@@ -345,6 +460,7 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    flush = Flusher(torch)
     print("[bench] generating R-MAT 2^20 (degree 16) and the 12-vector sweep", file=sys.stderr, flush=True)
     A = synth.cfg2_matrix()
     vecs = synth.cfg2_vectors(A.n)
@@ -354,11 +470,15 @@ def main():
     nnz_s = [int(M.vector_features(x)["nnz_s"]) for x in xs]
     bytes_v = [alg_bytes(A.m, A.n, A.nnz, v.nnz, ns)[0] for v, ns in zip(vecs, nnz_s)]
     step_bytes = float(sum(bytes_v))
+    step_flops = float(sum(2 * ns for ns in nnz_s))
+
+    def step():
+        for x, y in zip(xs, ys):
+            M.run(x, y)
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        for x, y in zip(xs, ys):
-            M.run(x, y)
+        step()
     torch.cuda.synchronize()
     plans = []
     for x, y in zip(xs, ys):
@@ -366,28 +486,36 @@ def main():
         plans.append(M.last_plan())
     torch.cuda.synchronize()
 
-    # Per-vector kernel times, in an untimed pass: HIP events around every
-    # call's launches (each event pair adds a few microseconds of queue
-    # time, so the timed steps record them around the dominant kernel only)
+    # Per-vector kernel times and the per-stage split (features, model,
+    # conversion, kernels), in an untimed pass with HIP events around every
+    # call's launches, each call after a flush.
     nv = len(vecs)
     prof_steps = 3
     M.set_profiling(True)
-    M.run_times()
     M.stage_times()
+    M.run_times()
     for _ in range(prof_steps):
         for x, y in zip(xs, ys):
+            flush()
             M.run(x, y)
     torch.cuda.synchronize()
     M.set_profiling(False)
+    stages = M.stage_times()  # before run_times, which consumes the kernel events
     ktimes = M.run_times()
-    stages = M.stage_times()
+    assert stages["kernel_ms"] > 0, "no kernel time recorded"
     per_vec_ms = [float(np.mean(ktimes[i::nv])) for i in range(nv)] if len(ktimes) == nv * prof_steps else []
     dom = int(np.argmax(per_vec_ms)) if per_vec_ms else nv - 1
+    overhead = stages["features_ms"] + stages["model_ms"] + stages["conversion_ms"]
 
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] timing {args.steps} flushed steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    evs = []
     for _ in range(args.steps):
+        flush()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         for i, (x, y) in enumerate(zip(xs, ys)):
             if i == dom:
                 M.set_profiling(True)
@@ -395,11 +523,17 @@ def main():
                 M.set_profiling(False)
             else:
                 M.run(x, y)
+        e1.record()
+        evs.append((e0, e1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = [a.elapsed_time(b) for a, b in evs]
     dom_times = M.run_times()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = step_bytes / ((t1 - t0) / args.steps) / 1e9
+    ms_per_step = float(np.mean(step_ms))
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    print("[bench] warm steps (secondary)", file=sys.stderr, flush=True)
+    warm = warm_ms(torch, step, args.steps)
 
     dom_plan = plans[dom]
     dom_bytes = bytes_v[dom]
@@ -428,14 +562,24 @@ def main():
                       f"relabelled; m=n={A.m}, nnz={A.nnz}; FP32 weights U[0,1]",
             "vectors": "12 sparse x, nnz fraction geomspace(1e-5, 0.5, 12), uniform supports, values U[0,1]",
             "step": "run() per vector: lazy features + decision-tree cascade + conversion + kernel",
+            "cache": "flushed before every timed step (untimed read of a 1 GiB scratch buffer)",
             "bytes_per_step": int(step_bytes),
             "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+            "GFLOP/s": round(step_flops / (ms_per_step * 1e-3) / 1e9, 2),
+            "step_ms": {"median": round(sorted(step_ms)[len(step_ms) // 2], 4), "min": round(min(step_ms), 4),
+                        "max": round(max(step_ms), 4)},
+            "wall_s_timed_loop_incl_flushes": round(t1 - t0, 4),
+            "warm": {"ms_per_step": round(warm, 4), "GB/s": round(step_bytes / (warm * 1e-3) / 1e9, 2),
+                     "note": "back-to-back steps, no flush"},
             "plans": [repr(p) for p in plans],
             "per_vector_kernel_ms": [round(t, 5) for t in per_vec_ms],
-            "per_vector_kernel_ms_from": f"HIP events around every call, {prof_steps} untimed steps",
-            "stage_ms_total": {k: round(v, 3) for k, v in stages.items()},
-            "events_in_timed_steps": "around the dominant vector's launches only",
-            "cache": "inputs resident in HBM; no cache flush between steps",
+            "per_vector_pct_hbm_peak": [round(100 * b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)
+                                        for b, t in zip(bytes_v, per_vec_ms)],
+            "per_vector_kernel_ms_from": f"HIP events around every call, flushed before each, {prof_steps} untimed steps",
+            "stage_ms_total": {k: round(v, 4) for k, v in stages.items()},
+            "overhead_share": round(overhead / (overhead + stages["kernel_ms"]), 4),
+            "overhead_share_note": "(features + model + conversion) / (those + kernels) over the untimed pass",
+            "events_in_timed_steps": "around each step, and around the dominant vector's launches",
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -455,12 +599,20 @@ def main():
     }
     if not args.no_extras:
         extras = {}
-        for name, fn in (("poisson_spmv", extra_poisson), ("batched_vs_looped", extra_batched),
-                         ("fwd_vs_fwd_bwd", extra_fwd_bwd), ("bfs", extra_bfs),
-                         ("pagerank", extra_pagerank), ("sparse_output", extra_sparse_output)):
+        for name, fn in (("stream_copy", lambda: extra_copy(torch, spx, flush)),
+                         ("poisson_spmv", lambda: extra_poisson(torch, spx, synth, flush)),
+                         ("small_cfg", lambda: extra_small(torch, spx, synth, flush)),
+                         ("batched_vs_looped", lambda: extra_batched(torch, spx, synth, flush)),
+                         ("fwd_vs_fwd_bwd", lambda: extra_fwd_bwd(torch, spx, synth, flush)),
+                         ("bfs", lambda: extra_bfs(torch, spx, synth, flush)),
+                         ("pagerank", lambda: extra_pagerank(torch, spx, synth, flush)),
+                         ("sparse_output", lambda: extra_sparse_output(torch, spx, synth))):
             print(f"[bench] extra: {name}", file=sys.stderr, flush=True)
-            extras[name] = fn(torch, spx, synth)
+            extras[name] = fn()
         rec["extras"] = extras
+        copy_gbs = extras["stream_copy"]["GB/s"]
+        rec["roofline"]["achievable_copy_GB/s"] = copy_gbs
+        rec["roofline"]["frac_of_achievable"] = round(achieved / copy_gbs, 4)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(A, vecs, min_seconds=args.cpu_seconds)

@@ -312,9 +312,14 @@ spx_status run(spx_matrix *H, const spx_vec *x, void *y, void *stream);
 /* y = A x with a given plan through the handle (its CSC and workspace). */
 spx_status run_plan(spx_matrix *H, const spx_vec *x, void *y, const spx_plan *plan, void *stream);
 
-/* The plan the last run() chose, and per-stage times of the last run()
- * in milliseconds when profiling is on: out[0] features, out[1] model
- * evaluation, out[2] vector conversion, out[3] kernel(s). */
+/* The plan the last run() chose, and per-stage times in milliseconds of
+ * the run() calls since the last spx_stage_times, while profiling is on
+ * (Section 7's overhead breakdown): out[0] features (host time, including
+ * any device reduction and its synchronization), out[1] model evaluation
+ * (host time), out[2] vector conversion and out[3] kernel(s) (HIP events on
+ * the caller's stream; synchronizes on them). Resets the feature, model and
+ * conversion totals; the kernel events stay until spx_run_times reads
+ * them. */
 spx_status spx_last_plan(const spx_matrix *H, spx_plan *out);
 spx_status spx_set_profiling(spx_matrix *H, int32_t on);
 spx_status spx_stage_times(const spx_matrix *H, double *out4);
@@ -447,6 +452,13 @@ spx_status dvals_pattern(spx_matrix *H, int32_t B, const void *G, const void *X,
  * nonzero (-0.0 is zero, NaN is not). */
 spx_status spx_dense_rows_to_sparse(spx_matrix *H, int32_t B, const void *X, int32_t *vec_ptr,
                                     int32_t *idx, void *val, void *stream);
+
+/* Measurement helper: copies bytes from src to dst (device pointers, both
+ * 16-byte aligned, bytes a multiple of 16; SPX_ERR_ARG otherwise) with a
+ * plain streaming kernel (16-byte loads and stores). Its rate is the
+ * achievable HBM bandwidth that the kernels' effective bandwidth is set
+ * against, beside the published peak. */
+spx_status spx_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* ---------------------------------------------------------------------
  * Host-only helpers.

@@ -42,6 +42,9 @@ def _load():
         "oracle_spmv": [i32, i32, _i32p, _i32p, _f64p, _f64p, _f64p, vp],
         "oracle_transpose": [i32, i32, _i32p, _i32p, vp, _i32p, _i32p, vp, vp],
         "oracle_spmspv_csc": [i32, i32, _i32p, _i32p, _f64p, i32, _i32p, _f64p, _f64p, vp],
+        "oracle_spmspv_csc_rows": [i32, i32, _i32p, _i32p, _f64p, i32, _i32p, _f64p, i32, i32, _f64p, vp],
+        "oracle_spmspv_csc_omp": [i32, i32, _i32p, _i32p, _f64p, i32, _i32p, _f64p, _f64p, vp],
+        "oracle_omp_threads": [],
         "oracle_bool_spmspv": [i32, i32, _i32p, _i32p, i32, _i32p, _u8p],
         "oracle_minplus_spmv": [i32, i32, _i32p, _i32p, _f32p, _f32p, _f32p],
         "oracle_int_spmv": [i32, i32, _i32p, _i32p, _i32p, _i32p, _i32p],
@@ -125,6 +128,36 @@ def spmspv(csc: CSC, x_idx, x_val):
                                  x_idx.size, x_idx, _f64(x_val), y, _ptr(s)),
            "oracle_spmspv_csc")
     return y, s
+
+
+def spmspv_rows(csc: CSC, x_idx, x_val, r0: int, r1: int):
+    """The column scatter restricted to output rows [r0, r1) (equal to
+    spmspv's rows bit for bit); returns (y, S) over those rows only."""
+    lib = _load()
+    y = np.zeros(csc.m, np.float64)
+    s = np.zeros(csc.m, np.float64)
+    x_idx = _i32(x_idx)
+    _check(lib.oracle_spmspv_csc_rows(csc.m, csc.n, csc.col_ptr, csc.row_idx, _f64(csc.vals), x_idx.size,
+                                      x_idx, _f64(x_val), int(r0), int(r1), y, _ptr(s)),
+           "oracle_spmspv_csc_rows")
+    return y[r0:r1], s[r0:r1]
+
+
+def spmspv_omp(csc: CSC, x_idx, x_val):
+    """spmspv with disjoint row ranges on the host's cores (OpenMP); the
+    same bits as spmspv. Returns (y, S)."""
+    lib = _load()
+    y = np.empty(csc.m, np.float64)
+    s = np.empty(csc.m, np.float64)
+    x_idx = _i32(x_idx)
+    _check(lib.oracle_spmspv_csc_omp(csc.m, csc.n, csc.col_ptr, csc.row_idx, _f64(csc.vals), x_idx.size,
+                                     x_idx, _f64(x_val), y, _ptr(s)), "oracle_spmspv_csc_omp")
+    return y, s
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP leg uses (OMP_NUM_THREADS, else the host's cores)."""
+    return int(_load().oracle_omp_threads())
 
 
 def bool_spmspv(A, x_idx):

@@ -29,6 +29,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OK 0
 #define ERR_ALLOC (-1)
@@ -145,6 +148,90 @@ int oracle_spmspv_csc(int32_t m, int32_t n, const int32_t *col_ptr, const int32_
         y[i] += cor[i];
     free(cor);
     return OK;
+}
+
+/* ---------------------------------------------------------------------
+ * O2c: the same column scatter, restricted to the output rows [r0, r1).
+ * Row i of y receives exactly the terms O2b adds to it, in the same order
+ * (x entries in order, each column top to bottom), so the result equals
+ * O2b's bit for bit. Rows ascend within a column of the oracle's own
+ * transpose (O2a is a stable counting sort), so a column's entries in
+ * [r0, r1) form one contiguous run, found by two binary searches.
+ * O2d runs disjoint row ranges of O2c on the host's cores (OpenMP); it is
+ * the multi-core leg of the CPU baseline, pinned equal to O2b.
+ * ------------------------------------------------------------------- */
+static int32_t lower_row(const int32_t *row_idx, int32_t a, int32_t b, int32_t key)
+{
+    while (a < b) {
+        int32_t mid = a + (b - a) / 2;
+        if (row_idx[mid] < key)
+            a = mid + 1;
+        else
+            b = mid;
+    }
+    return a;
+}
+
+int oracle_spmspv_csc_rows(int32_t m, int32_t n, const int32_t *col_ptr, const int32_t *row_idx,
+                           const double *vals_csc, int32_t nnz_x, const int32_t *x_idx,
+                           const double *x_val, int32_t r0, int32_t r1, double *y, double *s)
+{
+    if (r0 < 0 || r1 > m || r0 > r1)
+        return ERR_ARG;
+    double *cor = (double *)calloc((size_t)(r1 - r0) + 1, sizeof(double));
+    if (!cor)
+        return ERR_ALLOC;
+    for (int32_t i = r0; i < r1; ++i) {
+        y[i] = 0.0;
+        if (s)
+            s[i] = 0.0;
+    }
+    for (int32_t t = 0; t < nnz_x; ++t) {
+        int32_t j = x_idx[t];
+        if (j < 0 || j >= n) {
+            free(cor);
+            return ERR_ARG;
+        }
+        double v = x_val[t];
+        int32_t k0 = lower_row(row_idx, col_ptr[j], col_ptr[j + 1], r0);
+        int32_t k1 = lower_row(row_idx, k0, col_ptr[j + 1], r1);
+        for (int32_t k = k0; k < k1; ++k) {
+            int32_t i = row_idx[k];
+            double p = vals_csc[k] * v;
+            nadd(&y[i], &cor[i - r0], p);
+            if (s)
+                s[i] += fabs(p);
+        }
+    }
+    for (int32_t i = r0; i < r1; ++i)
+        y[i] += cor[i - r0];
+    free(cor);
+    return OK;
+}
+
+int oracle_spmspv_csc_omp(int32_t m, int32_t n, const int32_t *col_ptr, const int32_t *row_idx,
+                          const double *vals_csc, int32_t nnz_x, const int32_t *x_idx,
+                          const double *x_val, double *y, double *s)
+{
+    const int32_t blocks = 256;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|: bad)
+    for (int32_t b = 0; b < blocks; ++b) {
+        int32_t r0 = (int32_t)((int64_t)m * b / blocks), r1 = (int32_t)((int64_t)m * (b + 1) / blocks);
+        if (oracle_spmspv_csc_rows(m, n, col_ptr, row_idx, vals_csc, nnz_x, x_idx, x_val, r0, r1, y, s) != OK)
+            bad = 1;
+    }
+    return bad ? ERR_ARG : OK;
+}
+
+/* threads the OpenMP leg runs on */
+int oracle_omp_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ---------------------------------------------------------------------

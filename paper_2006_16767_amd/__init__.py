@@ -486,3 +486,13 @@ def spmspv_csc(A: Matrix, idx, val, p: Plan, y=None, stream=None):
     _lib.call("spmspv_csc", C.byref(c), int(idx.numel()), _ptr(idx), _ptr(val), _ptr(y), C.byref(p),
               _ptr(ws), ws.numel(), _stream(stream))
     return y
+
+
+def stream_copy(src, dst, stream=None):
+    """dst <- src with the library's streaming copy kernel (the achievable
+    bandwidth reference); both contiguous device tensors of equal byte size,
+    16-byte aligned."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _lib.call("spx_stream_copy", _ptr(src), _ptr(dst), nbytes, _stream(stream))
+    return dst

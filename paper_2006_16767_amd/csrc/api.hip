@@ -870,6 +870,11 @@ struct LazyFeatures {
     }
 };
 
+// Longest row (entries) for which run() still picks a write-back that sums a
+// row in one serial FP32 chain: a serial chain over 2^17 products of one sign
+// already comes within a factor two of the 1e-5 relative bound.
+constexpr double kAtomicChainMax = 65536.0;
+
 static spx_status select_impl(spx_matrix* H, const Selector& S, const spx_vec* x, uint32_t flags, spx_plan* out,
                               LazyFeatures& lf) {
     auto f = [&](int id) { return lf.get(id); };
@@ -884,6 +889,13 @@ static spx_status select_impl(spx_matrix* H, const Selector& S, const spx_vec* x
         if (p.writeback < SPX_WB_ATOMIC || p.writeback > SPX_WB_BUCKET) p.writeback = SPX_WB_ATOMIC;
         if (p.writeback == SPX_WB_LDS_ATOMIC &&
             (int64_t)H->csr.m * std::max(4, value_size(H->csr.dtype)) > 65536)
+            p.writeback = SPX_WB_SORT;
+        // the atomic, LDS-atomic and bucket write-backs add a row's products
+        // one at a time into one FP32 value; past kAtomicChainMax entries in
+        // a row that chain can miss the FP32 error bound, so the row's sum
+        // goes through the sort write-back's per-tile trees instead
+        if (H->csr.dtype == SPX_F32 && H->feat[3] > kAtomicChainMax &&
+            (p.writeback == SPX_WB_ATOMIC || p.writeback == SPX_WB_LDS_ATOMIC || p.writeback == SPX_WB_BUCKET))
             p.writeback = SPX_WB_SORT;
     }
     (void)flags;
@@ -1180,22 +1192,26 @@ extern "C" spx_status spx_run_times(spx_matrix* H, double* out, int32_t cap, int
 extern "C" spx_status spx_stage_times(const spx_matrix* Hc, double* out4) {
     if (!Hc || !out4) return fail(SPX_ERR_ARG, "null argument");
     spx_matrix* H = const_cast<spx_matrix*>(Hc);
-    auto sum = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+    // conversion events are consumed here; kernel events stay for
+    // spx_run_times, which consumes them
+    auto sum = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, bool consume) {
         double t = 0;
         for (auto& e : v) {
             float ms = 0;
             hipEventSynchronize(e.second);
             if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) t += ms;
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            if (consume) {
+                hipEventDestroy(e.first);
+                hipEventDestroy(e.second);
+            }
         }
-        v.clear();
+        if (consume) v.clear();
         return t;
     };
     out4[0] = H->host_ms[0];
     out4[1] = H->host_ms[1];
-    out4[2] = sum(H->ev_conv);
-    out4[3] = sum(H->ev_kern);
+    out4[2] = sum(H->ev_conv, true);
+    out4[3] = sum(H->ev_kern, false);
     H->host_ms[0] = H->host_ms[1] = 0;
     return SPX_OK;
 }

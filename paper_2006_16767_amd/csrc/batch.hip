@@ -313,13 +313,28 @@ __device__ __forceinline__ void batch_rows_direct(const BatchDev& a, int64_t r0,
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     for (int64_t row = r0 + g; row < r1; row += G) {
         const int k0 = a.row_ptr[row], k1 = a.row_ptr[row + 1];
-        typename S::Acc acc = S::zero();
-        for (int k = k0 + lane; k < k1; k += L) {
-            const int c = a.col_idx[k];
-            if (!valid || test_bit(bits, c)) acc = S::fma(S::val(vals, k), S::xval(xd, c), acc);
+        ChunkedAcc<DT, 4> acc;  // a partial sum per load slot: bounded chains on hub rows
+        int k = k0 + lane;
+        for (; k + 3 * L < k1; k += 4 * L) {
+            int c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = a.col_idx[k + u * L];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (!valid || test_bit(bits, c[u]))
+                    acc.part[u] = S::fma(S::val(vals, k + u * L), S::xval(xd, c[u]), acc.part[u]);
+            acc.end_round();
         }
-        acc = group_reduce<DT, L>(acc);
-        if (lane == 0) y[row] = S::out(acc);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int kk = k + u * L;
+            if (kk < k1) {
+                const int c = a.col_idx[kk];
+                if (!valid || test_bit(bits, c)) acc.part[u] = S::fma(S::val(vals, kk), S::xval(xd, c), acc.part[u]);
+            }
+        }
+        const typename S::Acc sum = group_reduce<DT, L>(acc.total());
+        if (lane == 0) y[row] = S::out(sum);
     }
 }
 

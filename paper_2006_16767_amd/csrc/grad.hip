@@ -70,7 +70,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(int32_t nseg, int32_t B, 
     const int c0 = seg_ptr[j], c1 = seg_ptr[j + 1];
     const int32_t* row_idx = idx;
     const T* g = inT + b0 + (on ? lane : 0);
-    T acc0 = 0, acc1 = 0;
+    // a partial sum per load slot, folded every kFoldRounds rounds (bounded
+    // chains on long segments)
+    ChunkedAcc<sizeof(T) == 8 ? SPX_F64 : SPX_F32, 8> acc;
     int k = c0;
     for (; k + 7 < c1; k += 8) {
         int r[8];
@@ -83,13 +85,13 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(int32_t nseg, int32_t B, 
 #pragma unroll
         for (int u = 0; u < 8; ++u) gv[u] = g[(int64_t)r[u] * B];
 #pragma unroll
-        for (int u = 0; u < 8; u += 2) {
-            acc0 = __builtin_fma(v[u], gv[u], acc0);
-            acc1 = __builtin_fma(v[u + 1], gv[u + 1], acc1);
-        }
+        for (int u = 0; u < 8; ++u) acc.part[u] = __builtin_fma(v[u], gv[u], acc.part[u]);
+        acc.end_round();
     }
-    for (; k < c1; ++k) acc0 = __builtin_fma(vals[k], g[(int64_t)row_idx[k] * B], acc0);
-    if (on) outT[(int64_t)j * B + b0 + lane] = acc0 + acc1;
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+        if (k + u < c1) acc.part[u] = __builtin_fma(vals[k + u], g[(int64_t)row_idx[k + u] * B], acc.part[u]);
+    if (on) outT[(int64_t)j * B + b0 + lane] = acc.total();
 }
 
 // Folds p[0..15] over the 64 lanes of a wave: lane l ends with the full sum

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(int64_t nslices, const int
     const int w = (int)((slice_ptr[s + 1] - base) / kSliceRows);
     const int32_t* cp = col + base + lane;
     const int64_t vb = base + lane;
-    typename S::Acc acc = S::zero();
+    ChunkedAcc<DT, U> acc;  // a partial sum per load slot: bounded chains on long rows
     for (int j = 0; j < w; j += U) {
         int c[U];
         typename S::V a[U];
@@ -93,10 +93,11 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv(int64_t nslices, const int
         for (int u = 0; u < U; ++u) b[u] = c[u] >= 0 ? S::xval(x, c[u]) : (typename S::X)0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (c[u] >= 0) acc = S::fma(a[u], b[u], acc);
+            if (c[u] >= 0) acc.part[u] = S::fma(a[u], b[u], acc.part[u]);
+        acc.end_round();
     }
     const int row = perm[s * kSliceRows + lane];
-    if (row >= 0) y[row] = S::out(acc);
+    if (row >= 0) y[row] = S::out(acc.total());
 }
 
 SellPlanInfo sell_shape(const int32_t* row_ptr_host, int32_t m) {

@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "csc_tile.hpp"
+#include "csr_tile.hpp"
 #include "internal.hpp"
 
 namespace spx {
@@ -304,13 +305,18 @@ __global__ __launch_bounds__(kBlock) void k_csc_merge_lds(int32_t m, int32_t nnz
 // --------------------------------------------------------------- reduce by key
 // Sorted (row, value) pairs -> y. Tiles of kCscTile pairs; each thread sums
 // kCscIpt consecutive pairs by run, a segmented scan over threads joins
-// runs that cross threads, and each run is stored once. Runs that continue
-// into a neighbouring tile are added atomically (y was zero-filled).
+// runs that cross threads, and each run is stored once. A run that
+// continues into the next tile leaves its partial sum as the tile's carry
+// instead; the tile where the run ends stores its own part, and a fix-up
+// pass adds the carries in tile order (the same scheme as the balanced
+// row-major kernels), so the result does not depend on scheduling.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_reduce_by_key(int64_t n, const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ vbits,
                                                           const typename SR<DT>::Acc* __restrict__ vwide,
-                                                          typename SR<DT>::Y* __restrict__ y) {
+                                                          typename SR<DT>::Y* __restrict__ y,
+                                                          int32_t* __restrict__ carry_row,
+                                                          typename SR<DT>::Acc* __restrict__ carry_val) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
     __shared__ uint32_t s_k[kCscTile + 2];
@@ -381,17 +387,24 @@ __global__ __launch_bounds__(kBlock) void k_reduce_by_key(int64_t n, const uint3
         const bool tail = (i == cnt - 1) || (s_k[2 + i] != s_k[1 + i]);
         if (tail) {
             const uint32_t r = s_k[1 + i];
-            // does the run extend beyond the tile on either side?
-            int j = i;
-            const bool touches_start = (s_k[1] == r);  // run includes tile item 0
-            const bool cross = (touches_start && s_k[0] == r) || (i == cnt - 1 && s_k[1 + cnt] == r);
-            (void)j;
-            if (cross)
-                S::atomic_add(&y[r], run);
-            else
+            const bool continues = i == cnt - 1 && s_k[1 + cnt] == r;
+            if (continues) {
+                carry_row[blockIdx.x] = (int32_t)r;
+                carry_val[blockIdx.x] = run;
+            } else {
                 y[r] = S::out(run);
+                if (i == cnt - 1) carry_row[blockIdx.x] = -1;
+            }
         }
     }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_rbk_fixup(int64_t tiles, const int32_t* __restrict__ carry_row,
+                                                      const typename SR<DT>::Acc* __restrict__ carry_val,
+                                                      typename SR<DT>::Y* __restrict__ y) {
+    csr_merge_fixup_range<DT>((int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock, tiles,
+                              carry_row, carry_val, y);
 }
 
 // --------------------------------------------------------------- launch
@@ -433,6 +446,8 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
         if (value_size(dtype) == 8) z.take<double>(np);
         z.take<int32_t>(radix_ws_elems(np));
         z.take<int32_t>(4);
+        z.take<int32_t>(ceil_div(np, kCscTile));  // carries of the reduce-by-key tiles
+        z.take<double>(ceil_div(np, kCscTile));
     }
     return z.used;
 }
@@ -578,7 +593,10 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
         Acc* vw = nullptr;
         if (sizeof(Acc) == 8) vw = ws.take<Acc>(np);
         int32_t* rws = ws.take<int32_t>(radix_ws_elems(np));
-        if (!keys || !vb || !keys2 || !vb2 || !rws || (sizeof(Acc) == 8 && !vw))
+        ws.take<int32_t>(4);
+        int32_t* crow = ws.take<int32_t>(ceil_div(np, kCscTile));
+        Acc* cval = (Acc*)ws.take<double>(ceil_div(np, kCscTile));
+        if (!keys || !vb || !keys2 || !vb2 || !rws || !crow || !cval || (sizeof(Acc) == 8 && !vw))
             return fail(SPX_ERR_WORKSPACE, "spmspv_csc sort: workspace too small");
         EmitPairs<DT> emit{keys, vb, vw};
         if (dist == SPX_DIST_DIRECT) {
@@ -604,7 +622,10 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
         SPX_TRY(radix_sort_pairs(keys, vb, keys2, vb2, nnz_s, key_bits(A.m), rws, s, &in_alt));
         const uint32_t* sk = in_alt ? keys2 : keys;
         const uint32_t* sv = in_alt ? vb2 : vb;
-        k_reduce_by_key<DT><<<(unsigned)ceil_div(nnz_s, kCscTile), kBlock, 0, s>>>(nnz_s, sk, sv, vw, y);
+        const int64_t rtiles = ceil_div(nnz_s, kCscTile);
+        k_reduce_by_key<DT><<<(unsigned)rtiles, kBlock, 0, s>>>(nnz_s, sk, sv, vw, y, crow, cval);
+        SPX_HIP(hipGetLastError());
+        k_rbk_fixup<DT><<<(unsigned)ceil_div(rtiles, kBlock), kBlock, 0, s>>>(rtiles, crow, cval, y);
         SPX_HIP(hipGetLastError());
         return SPX_OK;
     }

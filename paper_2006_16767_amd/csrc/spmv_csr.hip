@@ -42,9 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_csr_direct(int32_t m, const int32_t*
     const int g = threadIdx.x % L;
     if (row >= m) return;  // whole groups leave together (L divides 64)
     const int k0 = row_ptr[row], k1 = row_ptr[row + 1];
-    Acc acc = S::zero();
     // eight loads in flight per lane, predicated on the row's end: a short
-    // row (up to 8 * L entries) costs one round trip
+    // row (up to 8 * L entries) costs one round trip; each load slot keeps
+    // its own partial sum (bounded chains on hub rows)
+    ChunkedAcc<DT, 8> acc;
     for (int k = k0 + g; k < k1; k += 8 * L) {
         int c[8];
         bool on[8];
@@ -66,10 +67,11 @@ __global__ __launch_bounds__(kBlock) void k_csr_direct(int32_t m, const int32_t*
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (on[u]) acc = S::fma(a[u], b[u], acc);
+            if (on[u]) acc.part[u] = S::fma(a[u], b[u], acc.part[u]);
+        acc.end_round();
     }
-    acc = group_reduce<DT, L>(acc);
-    if (g == 0) y[row] = S::out(acc);
+    const Acc sum = group_reduce<DT, L>(acc.total());
+    if (g == 0) y[row] = S::out(sum);
 }
 
 // --------------------------------------------------------------- balanced

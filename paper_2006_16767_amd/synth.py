@@ -280,6 +280,28 @@ def random_csr(m: int, n: int, density: float, seed: int, dtype=np.float32,
     return _coo_to_csr(m, n, rr.astype(np.int64), cc.astype(np.int64), vals)
 
 
+def hub_matrix(n: int, hub_len: int, per_row: int, seed: int, dtype=np.float32) -> CSR:
+    """Square n x n matrix with one hub row and one hub column for the
+    accumulation-length checks: row 0 holds columns 0 .. hub_len - 1,
+    column 1 holds rows 1 .. hub_len, and every other row gets per_row
+    distinct uniform columns (a row's draw may hit column 1 again only as
+    that row's hub entry). Values U[0, 1] (one sign, so rounding errors do
+    not cancel)."""
+    rng = np.random.default_rng(seed)
+    rows = [np.zeros(hub_len, np.int64), np.arange(1, hub_len + 1, dtype=np.int64)]
+    cols = [np.arange(hub_len, dtype=np.int64), np.ones(hub_len, np.int64)]
+    r = np.repeat(np.arange(1, n, dtype=np.int64), per_row)
+    c = rng.integers(0, n, size=r.size, dtype=np.int64)
+    rows.append(r)
+    cols.append(c)
+    rr = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    key = np.unique(rr * n + cc)  # distinct entries
+    rr, cc = key // n, key % n
+    vals = rng.uniform(0.0, 1.0, size=rr.size).astype(dtype)
+    return _coo_to_csr(n, n, rr, cc, vals)
+
+
 def weighted_sparse_vector(n: int, nnz: int, weights: np.ndarray, seed: int, lo=0.0, hi=1.0,
                            dtype=np.float32) -> SparseVec:
     """nnz distinct indices drawn without replacement with probability

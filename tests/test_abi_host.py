@@ -98,3 +98,21 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.run(None, None, None, None) == -1
     assert lib.select_kernel(None, None, 0, None, None) == -1
     assert lib.spx_matrix_destroy(None) == 0
+
+
+def test_dynamic_lds_declarations_are_aligned():
+    """Every dynamic LDS array in the kernel sources is declared 16-byte
+    aligned. Dynamic LDS starts right after a kernel's static LDS with no
+    rounding, so an unaligned declaration can put 8-byte accumulators at a
+    misaligned address (8-byte LDS operations then fault)."""
+    csrc = os.path.join(ROOT, "paper_2006_16767_amd", "csrc")
+    found = 0
+    for name in sorted(os.listdir(csrc)):
+        if not name.endswith((".hip", ".hpp", ".h", ".cpp")):
+            continue
+        for lineno, line in enumerate(open(os.path.join(csrc, name)), 1):
+            code = line.split("//")[0]
+            if "extern" in code and "__shared__" in code:
+                found += 1
+                assert "__align__(16)" in code, f"{name}:{lineno}: dynamic LDS without __align__(16)"
+    assert found > 0

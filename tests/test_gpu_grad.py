@@ -117,7 +117,7 @@ def test_pruned_fc_layer_full_size():
     torch.cuda.synchronize()
     Yh = Y.detach().cpu().numpy()
     Ysh = Ys.cpu().numpy()
-    for b in range(0, 64, 9):
+    for b in range(64):
         ref, S = oracle.spmv(A, Xh[b])
         assert_close(Yh[b], ref, S, "f32", f"fc forward (fused) b={b}")
         assert_close(Ysh[b], ref, S, "f32", f"fc forward (sparse) b={b}")
@@ -143,6 +143,6 @@ def test_fused_batch_spmv_matches_oracle(kind):
         for B in (1, 3, 64, 70, 130):
             X = _relu_batch(n, B, 10 * ci + B, npdt)
             Y = M.spmv_batch(torch.as_tensor(X, device="cuda")).cpu().numpy()
-            for b in sorted({0, B // 2, B - 1}):
+            for b in range(B):
                 ref, S = oracle.spmv(A, X[b].astype(np.float64))
                 assert_close(Y[b], ref, S, kind, f"{m}x{n} B={B} b={b}")

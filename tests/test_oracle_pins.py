@@ -713,3 +713,24 @@ def test_minplus_pins_catch_planted_mistakes(monkeypatch):
         mp.setattr(oracle, "minplus_spmv", summed)
         got = oracle.minplus_spmv(A, np.array([0.0, np.inf, 1.0], np.float32))
     assert got.tolist() != [2.5, 1.25, np.inf]
+
+
+def test_row_range_and_openmp_scatter_equal_the_column_scatter():
+    """The row-range scatter (binary searches cut each column to the range)
+    and its OpenMP driver give the column scatter's bits: every row receives
+    the same terms in the same order. Ranges: empty, one row, the first and
+    last rows, ragged splits; matrices with empty rows and columns, and
+    R-MAT with hub columns."""
+    from paper_2006_16767_amd import synth
+    mats = [synth.random_csr(97, 61, 0.08, 5, empty_rows=0.2), synth.rmat(14, 8, 99)]
+    for A in mats:
+        csc = oracle.transpose(A)
+        for nnz in (0, 1, A.n // 7, A.n):
+            v = synth.sparse_vector(A.n, nnz, 40 + nnz)
+            y, s = oracle.spmspv(csc, v.idx, v.val)
+            yo, so = oracle.spmspv_omp(csc, v.idx, v.val)
+            assert np.array_equal(y, yo) and np.array_equal(s, so)
+            for r0, r1 in ((0, 0), (0, 1), (A.m - 1, A.m), (3, 3), (0, A.m), (A.m // 3, 2 * A.m // 3 + 1)):
+                yr, sr = oracle.spmspv_rows(csc, v.idx, v.val, r0, r1)
+                assert np.array_equal(yr, y[r0:r1]) and np.array_equal(sr, s[r0:r1])
+    assert oracle.omp_threads() >= 1
