@@ -51,8 +51,13 @@
  *    SPX_ERR_HIP.
  *  - Floating-point results: FP32 kernels satisfy
  *    |y_i - exact_i| <= 1e-5 * sum_j |a_ij x_j|, FP64 kernels
- *    1e-12 * sum_j |a_ij x_j|; the order of accumulation is unspecified
- *    and atomic write-backs are not run-to-run deterministic.
+ *    1e-12 * sum_j |a_ij x_j|; the order of accumulation is unspecified.
+ *    The row-major patterns and the sort and merge write-backs give the
+ *    same bits on every call; the atomic, LDS-atomic and bucket
+ *    write-backs add a row's products in the order the hardware serves
+ *    the atomics, so their last bits can differ between calls. Those three
+ *    also sum a row in one serial FP32 chain: the bound holds for rows of
+ *    up to about 2^16 entries (run() avoids them in FP32 beyond that).
  */
 #ifndef SPX_H
 #define SPX_H
@@ -108,7 +113,9 @@ typedef enum {
     SPX_WB_ATOMIC = 1,     /* zero y, then hardware atomic add per effective entry */
     SPX_WB_SORT = 2,       /* write (row, value) pairs, radix-sort by row, reduce by key */
     SPX_WB_LDS_ATOMIC = 3, /* per-workgroup copy of y in LDS, flushed with atomics (small m) */
-    SPX_WB_BUCKET = 4      /* bin pairs by row range, one workgroup per bucket sums in LDS */
+    SPX_WB_BUCKET = 4,     /* bin pairs by row range, one workgroup per bucket sums in LDS */
+    SPX_WB_MERGE = 5       /* sort each tile's pairs in LDS and sum them by row, then merge the
+                              tiles' sorted runs per range of rows (no atomics: repeatable bits) */
 } spx_writeback;
 
 /* One candidate kernel plus its launch parameters. Zero parameters mean

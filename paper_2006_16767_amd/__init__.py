@@ -17,7 +17,7 @@ import ctypes as C
 from . import _lib
 from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F32_MINPLUS, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
                    PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
-                   WB_SORT, Plan, SpxError)
+                   WB_MERGE, WB_SORT, Plan, SpxError)
 
 __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
            "F32", "F64", "BOOL", "I32", "all_plans"]
@@ -83,7 +83,7 @@ def plan(pattern="spmv", distribution="direct", writeback="none", lanes=0, tile=
     pat = {"spmv": PAT_SPMV, "csr_spmspv": PAT_CSR_SPMSPV, "csc_spmspv": PAT_CSC_SPMSPV}[pattern]
     dist = {"direct": DIST_DIRECT, "balanced": DIST_BALANCED}[distribution]
     wb = {"none": WB_NONE, "atomic": WB_ATOMIC, "sort": WB_SORT, "lds_atomic": WB_LDS_ATOMIC,
-          "bucket": WB_BUCKET}[writeback]
+          "bucket": WB_BUCKET, "merge": WB_MERGE}[writeback]
     return Plan(pat, dist, wb, lanes, tile, bucket_rows)
 
 
@@ -93,7 +93,7 @@ def all_plans(include_bucket=True):
     for d in ("direct", "balanced"):
         out.append(plan("spmv", d))
         out.append(plan("csr_spmspv", d))
-        for wb in ("atomic", "lds_atomic", "sort") + (("bucket",) if include_bucket else ()):
+        for wb in ("atomic", "lds_atomic", "sort", "merge") + (("bucket",) if include_bucket else ()):
             out.append(plan("csc_spmspv", d, wb))
     return out
 
@@ -496,3 +496,4 @@ def stream_copy(src, dst, stream=None):
     assert dst.numel() * dst.element_size() == nbytes
     _lib.call("spx_stream_copy", _ptr(src), _ptr(dst), nbytes, _stream(stream))
     return dst
+

@@ -20,7 +20,7 @@ ERRORS = {
 F32, F64, BOOL, I32, F32_MINPLUS = 0, 1, 2, 3, 4
 PAT_SPMV, PAT_CSR_SPMSPV, PAT_CSC_SPMSPV = 0, 1, 2
 DIST_DIRECT, DIST_BALANCED = 0, 1
-WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET = 0, 1, 2, 3, 4
+WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET, WB_MERGE = 0, 1, 2, 3, 4, 5
 VEC_DENSE, VEC_SPARSE = 0, 1
 VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL = 1, 2, 4, 8, 16, 32
 BFS_PUSH_ONLY = 1
@@ -36,7 +36,8 @@ class Plan(C.Structure):
     def __repr__(self):
         pat = ["spmv", "csr_spmspv", "csc_spmspv"][self.pattern] if 0 <= self.pattern < 3 else "?"
         dist = ["direct", "balanced"][self.distribution] if 0 <= self.distribution < 2 else "?"
-        wb = ["none", "atomic", "sort", "lds_atomic", "bucket"][self.writeback] if 0 <= self.writeback < 5 else "?"
+        wb = (["none", "atomic", "sort", "lds_atomic", "bucket", "merge"][self.writeback]
+              if 0 <= self.writeback < 6 else "?")
         return f"Plan({pat}, {dist}, {wb}, lanes={self.lanes}, tile={self.tile}, bucket_rows={self.bucket_rows})"
 
 

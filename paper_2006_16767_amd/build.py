@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["prim.hip", "spmv_csr.hip", "spmspv_csc.hip", "spmspv_bucket.hip", "grad.hip", "batch.hip",
+SOURCES = ["prim.hip", "spmv_csr.hip", "spmspv_csc.hip", "spmspv_bucket.hip", "spmspv_merge.hip", "grad.hip",
+           "batch.hip",
            "bfs.hip", "pagerank.hip", "sell.hip", "api.hip", "selector.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -367,7 +367,7 @@ extern "C" spx_status spx_check_plan(const spx_plan* p, int32_t dtype) {
     if (p->distribution != SPX_DIST_DIRECT && p->distribution != SPX_DIST_BALANCED)
         return fail(SPX_ERR_ARG, "bad distribution");
     if (p->pattern == SPX_PAT_CSC_SPMSPV) {
-        if (p->writeback < SPX_WB_ATOMIC || p->writeback > SPX_WB_BUCKET)
+        if (p->writeback < SPX_WB_ATOMIC || p->writeback > SPX_WB_MERGE)
             return fail(SPX_ERR_ARG, "column-major pattern needs a write-back");
     } else if (p->writeback != SPX_WB_NONE) {
         return fail(SPX_ERR_ARG, "row-major patterns take no write-back");
@@ -886,7 +886,7 @@ static spx_status select_impl(spx_matrix* H, const Selector& S, const spx_vec* x
     p.writeback = SPX_WB_NONE;
     if (p.pattern == SPX_PAT_CSC_SPMSPV) {
         p.writeback = S.writeback.eval(f);
-        if (p.writeback < SPX_WB_ATOMIC || p.writeback > SPX_WB_BUCKET) p.writeback = SPX_WB_ATOMIC;
+        if (p.writeback < SPX_WB_ATOMIC || p.writeback > SPX_WB_MERGE) p.writeback = SPX_WB_ATOMIC;
         if (p.writeback == SPX_WB_LDS_ATOMIC &&
             (int64_t)H->csr.m * std::max(4, value_size(H->csr.dtype)) > 65536)
             p.writeback = SPX_WB_SORT;

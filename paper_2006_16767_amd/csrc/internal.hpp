@@ -175,6 +175,10 @@ spx_status launch_csc_bucket(const CscArgs& A, int32_t nnz_x, const int32_t* x_i
                              void* y, const spx_plan* plan, const Excl excl, Arena& ws,
                              hipStream_t s);
 size_t csc_bucket_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
+// merge write-back (spmspv_merge.hip); excl as for the bucket
+spx_status launch_csc_merge(const CscArgs& A, int32_t nnz_x, const int32_t* x_idx, const void* x_val, void* y,
+                            const spx_plan* plan, const Excl excl, Arena& ws, hipStream_t s);
+size_t csc_merge_ws(int32_t m, int32_t nnz, int32_t nnz_x, int dtype, const spx_plan* plan);
 
 // sparse x -> bitvector of supp(x) (cleared first unless `clean` says it
 // is all zero already) + scattered values xd[n] (map, if given, renumbers

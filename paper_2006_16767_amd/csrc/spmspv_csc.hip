@@ -425,7 +425,7 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
     (void)n;
     Sizer z;
     const bool need_excl = plan->distribution == SPX_DIST_BALANCED || plan->writeback == SPX_WB_SORT ||
-                           plan->writeback == SPX_WB_BUCKET;
+                           plan->writeback == SPX_WB_BUCKET || plan->writeback == SPX_WB_MERGE;
     if (need_excl) {
         z.take<int32_t>((size_t)nnz_x + 1);
         z.take<int32_t>(scan_ws_elems((int64_t)nnz_x + 1));
@@ -434,6 +434,11 @@ size_t spmspv_csc_ws(int32_t m, int32_t n, int32_t nnz, int32_t nnz_x, int dtype
     }
     if (plan->writeback == SPX_WB_BUCKET) {
         const size_t b = csc_bucket_ws(m, nnz, nnz_x, dtype, plan);
+        if (b == 0) return 0;
+        z.used = align_up(z.used, 256) + b;
+    }
+    if (plan->writeback == SPX_WB_MERGE) {
+        const size_t b = csc_merge_ws(m, nnz, nnz_x, dtype, plan);
         if (b == 0) return 0;
         z.used = align_up(z.used, 256) + b;
     }
@@ -479,8 +484,10 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
         return fail(SPX_ERR_UNSUPPORTED, "lds-atomic write-back needs m * sizeof(acc) <= 64 KiB");
     // the bucket write-back writes every row itself (or, for a sparse
     // output, only the rows it lists)
-    const bool fill_y = !A.sparse && (wb != SPX_WB_BUCKET || nnz_x == 0);
-    const bool need_excl = nnz_x > 0 && (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET);
+    const bool writes_all_rows = wb == SPX_WB_BUCKET || wb == SPX_WB_MERGE;
+    const bool fill_y = !A.sparse && (!writes_all_rows || nnz_x == 0);
+    const bool need_excl =
+        nnz_x > 0 && (dist == SPX_DIST_BALANCED || wb == SPX_WB_SORT || wb == SPX_WB_BUCKET || wb == SPX_WB_MERGE);
     int32_t* excl = nullptr;
     Excl ex{nullptr, nullptr};
     if (need_excl) {
@@ -528,6 +535,7 @@ static spx_status launch_csc_t(const CscArgs& A, int32_t nnz_x, const int32_t* x
     const int64_t merge_tiles = std::max<int64_t>(1, ceil_div((int64_t)nnz_x + ub, kCscTile));
 
     if (wb == SPX_WB_BUCKET) return launch_csc_bucket(A, nnz_x, x_idx, x_val_v, y_v, plan, ex, ws, s);
+    if (wb == SPX_WB_MERGE) return launch_csc_merge(A, nnz_x, x_idx, x_val_v, y_v, plan, ex, ws, s);
 
     if (wb == SPX_WB_ATOMIC || wb == SPX_WB_LDS_ATOMIC) {
         if (dist == SPX_DIST_DIRECT) {
