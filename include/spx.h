@@ -286,27 +286,33 @@ spx_status spx_vector_features(spx_matrix *H, const spx_vec *x, double *out4, vo
 
 /* Loads the three decision trees (pattern, distribution, write-back) from
  * a JSON file written by the tuner; json_path NULL means the built-in
- * trees. A handle holds two sets of trees:
- *  - the host-feature trees decide run() and select_kernel(); they should
- *    not test nnz_s or m_sparsity, which cost a device round trip there;
- *  - trees that test nnz_s serve the callers that know it for free: the
- *    graph drivers (spx_bfs, spx_pagerank count it while building x).
- *    Until such trees are loaded, they use the host-feature trees.
- * run_batch evaluates the host-feature trees on the device.
- * A file whose trees test nnz_s or m_sparsity loads into the second set;
- * any other file, or NULL (the built-in trees), loads into the first and
- * drops the second (load trees that test nnz_s after it). With
- * H NULL the trees become the default of handles created afterwards;
- * otherwise they replace H's only (for example trees trained for the BOOL
- * semiring on a BOOL handle). */
+ * trees. A handle holds three sets of trees:
+ *  - the host-feature trees, which test only features the host knows
+ *    (Table 1 minus nnz_s and m_sparsity); run_batch evaluates them on the
+ *    device, and run() and select_kernel() use them until lazy trees load;
+ *  - lazy trees (the file has "lazy": true) decide run() and
+ *    select_kernel(): they may test nnz_s, m_sparsity or s_per_x (nnz_s /
+ *    max(1, nnz_x)), which are computed on the device, with one stream
+ *    synchronization, only when the walk reaches such a node (Section 6.3:
+ *    features evaluated lazily, cheap rules first; the tuner trains them
+ *    with that round trip charged to every vector that takes it);
+ *  - trees that test nnz_s without "lazy" serve the callers that know it
+ *    for free: the graph drivers (spx_bfs, spx_pagerank count it while
+ *    building x). Until such trees are loaded, they use the host-feature
+ *    trees.
+ * Host-feature trees (a file that tests no count feature, or NULL) replace
+ * all three sets; load the others after them. With H NULL the trees become
+ * the default of handles created afterwards; otherwise they replace H's
+ * only (for example trees trained for the BOOL semiring on a BOOL
+ * handle). */
 spx_status spx_load_selector(spx_matrix *H, const char *json_path);
 
-/* Walks the cascade: pattern tree, then distribution tree, then (column-
- * major only) write-back tree (Section 6.2). Features are evaluated
- * lazily, host-known ones first (Section 6.3); the only device work is the
- * nnz_s / dense nnz_x reduction, which synchronizes the stream, and which
- * flags & SPX_NO_SYNC forbids (rules needing it then take their
- * host-feature fallback). */
+/* Walks the cascade of run()'s trees: pattern tree, then distribution
+ * tree, then (column-major only) write-back tree (Section 6.2). Features
+ * are evaluated lazily (Section 6.3): the only device work is the nnz_s
+ * reduction, made when a node tests nnz_s, m_sparsity or s_per_x; it
+ * synchronizes the stream, and flags & SPX_NO_SYNC forbids it (such nodes
+ * then read nnz_s as nnz_x times the average column length). */
 #define SPX_NO_SYNC 2u
 spx_status select_kernel(spx_matrix *H, const spx_vec *x, uint32_t flags, spx_plan *out,
                          void *stream);
@@ -342,11 +348,14 @@ spx_status spx_run_times(spx_matrix *H, double *out, int32_t cap, int32_t *count
  * Batched SpMSpV: B sparse vectors in one launch sequence.
  * X is CSR-of-vectors: vec_ptr[B+1] (device), idx[total] and val[total]
  * (device); Y is B x m row-major (device), each vector's y contiguous.
- * The plan of every vector is chosen on the device (the three trees
- * evaluated on all 13 features, nnz_s included, computed per vector on the
- * device); the calls are a plan kernel, a queue scan and one persistent
- * kernel, captured once into a HIP graph and replayed while the arrays and
- * B stay the same; nothing synchronizes except a workspace reallocation.
+ * The plan of every vector is chosen on the device: the trees run() uses
+ * (see spx_load_selector), evaluated by a device kernel on the matrix
+ * features and the vector's nnz_x; a vector's nnz_s (the prefix of its
+ * column lengths) is computed on the device when its plan is column-major,
+ * or for every vector when the loaded trees test nnz_s. The calls are a
+ * plan kernel, a queue scan and one persistent kernel, captured once into
+ * a HIP graph and replayed while the arrays and B stay the same; nothing
+ * synchronizes except a workspace reallocation.
  * total_nnz_x (host) is an upper bound of vec_ptr[B] used to size the
  * workspace. Column-major plans write back with device atomics in this
  * path. Vector indices must be unique within a vector.
@@ -355,9 +364,10 @@ spx_status run_batch(spx_matrix *H, int32_t B, int64_t total_nnz_x, const int32_
                      const int32_t *idx, const void *val, void *Y, void *stream);
 
 /* Status of the last run_batch on H: *flags = 0 when every work item ran;
- * bit 0 set if a dependency wait timed out, bit 1 if vec_ptr[B] exceeded
- * total_nnz_x (the affected rows of Y are not valid). Synchronizes the
- * stream. */
+ * bit 1 (value 2) is set when vec_ptr disagreed with the capacity the host
+ * sized (vec_ptr[B] above total_nnz_x, a negative or decreasing entry, or a
+ * vector longer than n): such vectors are skipped and their rows of Y are
+ * not valid. No other bit is used. Synchronizes the stream. */
 spx_status spx_batch_status(spx_matrix *H, int32_t *flags, void *stream);
 
 /* Y[b] = A X[b] for the B rows of a dense X (B x n -> Y B x m, device,
@@ -385,6 +395,12 @@ spx_status spmv_csr_batch(spx_matrix *H, int32_t B, const void *X, void *Y, void
  * distribution tree choose. Synchronizes the stream (the count). */
 spx_status spmspv_sparse(spx_matrix *H, const spx_vec *x, const uint32_t *mask, const spx_plan *plan,
                          int32_t *y_idx, void *y_val, int32_t *nnz_y, void *stream);
+
+/* The complement mask of spmspv_sparse from one byte per row: bit i of
+ * words[i / 32] = (rows[i] != 0) for i < m; the unused high bits of the last
+ * word are cleared. rows: device, m bytes; words: device, ceil(m / 32)
+ * words, written. One wave ballot per 64 rows. */
+spx_status spx_pack_mask(int32_t m, const uint8_t *rows, uint32_t *words, void *stream);
 
 /* Breadth-first search over the graph of a square BOOL handle (stored entry
  * (i, j) = edge j -> i, so a column lists a vertex's out-edges): level[v] =

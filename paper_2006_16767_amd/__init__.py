@@ -31,18 +31,23 @@ _NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__fil
 _BOOL_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_bool.json")
 _BOOL_NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__),
                                                   "selector_mi355x_bool_nnz_s.json")
+# lazy trees of run(): they may ask for nnz_s (a device count and a stream
+# synchronization) where that pays for itself
+_LAZY_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_lazy.json")
+_BOOL_LAZY_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__),
+                                                 "selector_mi355x_bool_lazy.json")
 _selector_loaded = False
 
 
 def _ensure_default_selector():
     """Loads the trees trained on MI355X timings (selector_mi355x.json, then
-    selector_mi355x_nnz_s.json) once, before the first handle is created;
-    spx_load_selector can replace them."""
+    selector_mi355x_nnz_s.json and selector_mi355x_lazy.json) once, before
+    the first handle is created; spx_load_selector can replace them."""
     global _selector_loaded
     if _selector_loaded:
         return
     import os
-    for path in (_DEFAULT_SELECTOR, _NNZ_S_SELECTOR):
+    for path in (_DEFAULT_SELECTOR, _NNZ_S_SELECTOR, _LAZY_SELECTOR):
         if os.path.exists(path):
             _lib.call("spx_load_selector", None, path.encode())
     _selector_loaded = True
@@ -134,7 +139,7 @@ class Matrix:
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         if dtype == BOOL:
-            for path in (_BOOL_SELECTOR, _BOOL_NNZ_S_SELECTOR):
+            for path in (_BOOL_SELECTOR, _BOOL_NNZ_S_SELECTOR, _BOOL_LAZY_SELECTOR):
                 if __import__("os").path.exists(path):
                     _lib.call("spx_load_selector", self._h, path.encode())
         self._vals_version = None if self.vals is None else self.vals._version
@@ -349,16 +354,19 @@ class Matrix:
         self.bfs_levels = nl.value
         return level, [plans[i] for i in range(cap) if plans[i].pattern >= 0]
 
-    def pack_mask(self, rows_mask):
+    def pack_mask(self, rows_mask, stream=None):
         """A bool / uint8 tensor of m entries as the bitvector (int32 words,
-        bit i of word i // 32) that spmspv_sparse takes."""
+        bit i of word i // 32) that spmspv_sparse takes (spx_pack_mask)."""
         torch = _torch()
-        words = (self.m + 31) // 32
-        b = torch.zeros(words * 32, dtype=torch.int64, device=rows_mask.device)
-        b[:self.m] = (rows_mask.reshape(-1) != 0).to(torch.int64)
-        w = (b.view(words, 32) << torch.arange(32, device=b.device)).sum(1)
-        return w.to(torch.uint32).view(torch.int32) if hasattr(torch, "uint32") else \
-            torch.where(w >= 2 ** 31, w - 2 ** 32, w).to(torch.int32)
+        rows = rows_mask.reshape(-1)
+        if rows.dtype not in (torch.bool, torch.uint8):
+            raise TypeError("pack_mask: rows_mask must be bool or uint8")
+        if rows.numel() != self.m:
+            raise ValueError(f"pack_mask: {rows.numel()} entries for {self.m} rows")
+        rows = rows.contiguous()
+        words = torch.empty(max(1, (self.m + 31) // 32), dtype=torch.int32, device=rows.device)
+        _lib.call("spx_pack_mask", int(self.m), _ptr(rows), _ptr(words), _stream(stream))
+        return words
 
     def spmspv_sparse(self, x, mask=None, plan: Plan | None = None, with_values: bool = True, stream=None):
         """y = A x for a sparse x as a row list: (rows, values) of the rows an

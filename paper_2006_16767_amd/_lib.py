@@ -90,6 +90,7 @@ SIGNATURES = {
     "spmv_csr_batch": (C.c_int, [P, _i32, P, P, P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),
+    "spx_pack_mask": (C.c_int, [_i32, P, P, P]),
     "spx_dense_rows_to_sparse": (C.c_int, [P, _i32, P, P, P, P, P]),
     "spx_stream_copy": (C.c_int, [P, P, C.c_size_t, P]),
     "spx_check_csr": (C.c_int, [C.POINTER(Csr)]),

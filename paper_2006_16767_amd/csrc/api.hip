@@ -228,6 +228,10 @@ struct spx_matrix {
     // graph drivers); the host-feature trees otherwise
     Selector sel_known;
     bool has_sel_known = false;
+    // lazy trees of run() and select_kernel() (they may test nnz_s at a
+    // device round trip); the host-feature trees otherwise
+    Selector sel_run;
+    bool has_sel_run = false;
     // incremental PageRank: column sums (valid for the current values),
     // residual, product, sparse input, negative-weight flag
     void* pr_W = nullptr;
@@ -306,6 +310,8 @@ static spx_csc handle_csc(const spx_matrix* H) {
 
 // The trees of a caller that knows nnz_s.
 static const Selector& known_selector(const spx_matrix* H) { return H->has_sel_known ? H->sel_known : H->sel; }
+// The trees of run() and select_kernel().
+static const Selector& run_selector(const spx_matrix* H) { return H->has_sel_run ? H->sel_run : H->sel; }
 
 // run_batch evaluates the host-feature trees on the device: with them a
 // vector whose plan is row-major joins a fused group before any prefix of
@@ -339,6 +345,12 @@ static std::pair<bool, Selector>& global_selector_known() {
     return s;
 }
 
+// Default lazy trees of run() (first = loaded).
+static std::pair<bool, Selector>& global_selector_run() {
+    static std::pair<bool, Selector> s{false, Selector{}};
+    return s;
+}
+
 // ------------------------------------------------------------------ checks
 extern "C" spx_status spx_check_csr(const spx_csr* A) {
     if (!A) return fail(SPX_ERR_ARG, "matrix descriptor is null");
@@ -350,7 +362,7 @@ extern "C" spx_status spx_check_csr(const spx_csr* A) {
     return SPX_OK;
 }
 
-static spx_status check_csc(const spx_csc* A) {
+spx_status spx::check_csc(const spx_csc* A) {
     if (!A) return fail(SPX_ERR_ARG, "matrix descriptor is null");
     if (!valid_dtype(A->dtype)) return fail(SPX_ERR_DTYPE, "unknown dtype");
     if (A->m < 0 || A->n < 0 || A->nnz < 0) return fail(SPX_ERR_SHAPE, "negative matrix size");
@@ -687,6 +699,8 @@ extern "C" spx_status spx_matrix_create(const spx_csr* A, uint32_t flags, void* 
     H->sel = global_selector();
     H->has_sel_known = global_selector_known().first;
     if (H->has_sel_known) H->sel_known = global_selector_known().second;
+    H->has_sel_run = global_selector_run().first;
+    if (H->has_sel_run) H->sel_run = global_selector_run().second;
     spx_status st = SPX_OK;
     if (flags & SPX_VALIDATE) {
         uint32_t* bad = nullptr;
@@ -819,6 +833,7 @@ struct LazyFeatures {
     bool have_counts = false;
     int64_t nnz_s = -1, nnz_x = -1;
     bool synced = false;
+    double count_ms = 0.0;  // host time spent on the device count and its round trip
     double get(int f) {
         const double* mf = H->feat;
         switch (f) {
@@ -855,10 +870,12 @@ struct LazyFeatures {
             nnz_s = H->csr.n > 0 ? (int64_t)((double)H->csr.nnz / H->csr.n * nnz_x) : 0;
             return;
         }
+        const auto t0 = std::chrono::steady_clock::now();
         if (device_vector_counts(H, x, s, &nnz_s, &nnz_x) != SPX_OK) {
             nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : H->csr.n;
             nnz_s = H->csr.nnz;
         }
+        count_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         synced = true;
     }
     // A vector handed over dense is taken as dense (nnz_x = n): counting its
@@ -907,7 +924,7 @@ extern "C" spx_status select_kernel(spx_matrix* H, const spx_vec* x, uint32_t fl
     if (!H || !out) return fail(SPX_ERR_ARG, "null argument");
     SPX_TRY(check_vec(H, x));
     LazyFeatures lf{H, x, (hipStream_t)stream, (flags & SPX_NO_SYNC) != 0};
-    return select_impl(H, H->sel, x, flags, out, lf);
+    return select_impl(H, run_selector(H), x, flags, out, lf);
 }
 
 extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
@@ -922,25 +939,36 @@ extern "C" spx_status spx_load_selector(spx_matrix* H, const char* json_path) {
         std::string err;
         if (!parse_selector_json(ss.str(), &s, &err)) return fail(SPX_ERR_ARG, "selector: " + err);
     }
-    // host-feature trees replace both sets (the nnz_s trees, if any, load
-    // after them); trees that test nnz_s replace the second set only
-    const bool known = json_path && s.reads_nnz_s();
+    // host-feature trees replace every set (trees that test nnz_s, lazy or
+    // not, load after them); lazy trees replace run()'s set only, other
+    // trees that test nnz_s the drivers' set only
+    const bool lazy = json_path && s.lazy;
+    const bool known = json_path && !lazy && s.reads_nnz_s();
     if (!H) {
-        if (known) {
+        if (lazy) {
+            global_selector_run() = {true, s};
+        } else if (known) {
             global_selector_known() = {true, s};
         } else {
             global_selector() = s;
             global_selector_known().first = false;
+            global_selector_run().first = false;
         }
+        return SPX_OK;
+    }
+    if (lazy) {
+        H->sel_run = s;
+        H->has_sel_run = true;
         return SPX_OK;
     }
     if (known) {
         H->sel_known = s;
         H->has_sel_known = true;
-    } else {
-        H->sel = s;
-        H->has_sel_known = false;
+        return SPX_OK;
     }
+    H->sel = s;
+    H->has_sel_known = false;
+    H->has_sel_run = false;
     return upload_selector(H);
 }
 
@@ -1082,9 +1110,14 @@ extern "C" spx_status run(spx_matrix* H, const spx_vec* x, void* y, void* stream
     auto t0 = std::chrono::steady_clock::now();
     LazyFeatures lf{H, x, s, false};
     spx_plan p;
-    SPX_TRY(select_impl(H, H->sel, x, 0, &p, lf));
+    SPX_TRY(select_impl(H, run_selector(H), x, 0, &p, lf));
     auto t1 = std::chrono::steady_clock::now();
-    if (H->profiling) H->host_ms[1] += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (H->profiling) {
+        // features: the device count and its round trip when a tree asked
+        // for nnz_s; model: the rest of the walk
+        H->host_ms[0] += lf.count_ms;
+        H->host_ms[1] += std::chrono::duration<double, std::milli>(t1 - t0).count() - lf.count_ms;
+    }
     H->last_plan = p;
     return exec_plan(H, x, y, &p, lf.have_counts && lf.synced ? lf.nnz_s : -1,
                      lf.have_counts && lf.synced ? lf.nnz_x : -1, s);
@@ -1709,6 +1742,15 @@ extern "C" spx_status dvals_pattern(spx_matrix* H, int32_t B, const void* G, con
     Arena ws(H->ws, H->ws_bytes);
     return launch_dvals(H->csr.row_ptr, H->csr.col_idx, H->csr.m, H->csr.n, H->csr.nnz, dt, B, G, X, dvals, ws,
                         (hipStream_t)stream);
+}
+
+extern "C" spx_status spx_pack_mask(int32_t m, const uint8_t* rows, uint32_t* words, void* stream) {
+    if (m < 0) return fail(SPX_ERR_SHAPE, "m must be >= 0");
+    if (m == 0) return SPX_OK;
+    if (!rows || !words) return fail(SPX_ERR_ARG, "null argument");
+    k_dense_bits<SPX_BOOL><<<dense_bits_grid(m), kBlock, 0, (hipStream_t)stream>>>(m, rows, words);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
 }
 
 extern "C" spx_status spx_dense_rows_to_sparse(spx_matrix* H, int32_t B, const void* X, int32_t* vec_ptr,

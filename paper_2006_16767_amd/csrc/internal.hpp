@@ -151,6 +151,8 @@ struct SparseOut {
     void* val;
     int32_t* count;
 };
+// host-side checks of a CSC descriptor (api.hip)
+spx_status check_csc(const spx_csc* A);
 struct CscArgs {
     int32_t m, n, nnz, dtype;
     const int32_t* col_ptr;

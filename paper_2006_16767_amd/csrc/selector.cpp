@@ -37,20 +37,20 @@ static Tree make_tree(std::initializer_list<std::initializer_list<double>> rows)
     return t;
 }
 
-// Trained (tune.py formats-train, depth 3, regret-weighted) on MI355X
-// timings of the dense-x FP32 SpMV on the 30 tuning matrices, best CSR plan
-// against the sliced copy: the copy wins on even row lengths (population
-// standard deviation <= 0.36) over more than 40960 rows, with n up to about
-// 1.5M (the 7-point stencil at 128^3, 2.1M rows, ran 5 % faster in CSR).
-// On that corpus it loses 0.2 % against always taking the faster format,
-// CSR alone 2.1 %.
+// Trained (tune.py formats-train: the project CART, depth 3, regret-weighted)
+// on MI355X timings of the dense-x FP32 SpMV on the 30 tuning matrices, best
+// CSR plan against the sliced copy: the copy wins on even row lengths
+// ((max_row - min_row) / n <= 3.07e-5, i.e. a spread of at most 32 entries
+// at n = 2^20) over more than 40960 rows, up to about 1.5M rows (the 7-point
+// stencil at 128^3, 2.1M rows, ran 5 % faster in CSR). On that corpus it
+// loses 0.2 % against always taking the faster format, CSR alone 2.1 %.
 Tree format_tree() {
     // rows: feature, threshold, left, right, class (-1 = internal)
     return make_tree({
-        {F_VAR_ROW, 0.3603, 1, 6, -1},
+        {F_REL_RANGE, 3.07220458984375e-05, 1, 6, -1},
         {F_M, 40960.0, 2, 3, -1},
         {0, 0, 0, 0, 0},
-        {F_N, 1572864.0, 4, 5, -1},
+        {F_M, 1572864.0, 4, 5, -1},
         {0, 0, 0, 0, 1},
         {0, 0, 0, 0, 0},
         {0, 0, 0, 0, 0},
@@ -286,7 +286,9 @@ bool parse_selector_json(const std::string& text, Selector* out, std::string* er
     const char* pn[3] = {"spmv", "csr_spmspv", "csc_spmspv"};
     for (int i = 0; i < 3; ++i)
         if (!tree_from_json(d->get(pn[i]), &s.distribution[i], 2, err)) return false;
-    if (!tree_from_json(root->get("writeback"), &s.writeback, 5, err)) return false;
+    if (!tree_from_json(root->get("writeback"), &s.writeback, 6, err)) return false;
+    const JVal* lz = root->get("lazy");
+    s.lazy = lz && lz->kind == JVal::BOOL && lz->b;
     const JVal* src = root->get("source");
     s.source = (src && src->kind == JVal::STR) ? src->str : "json";
     *out = s;

@@ -58,6 +58,10 @@ struct Selector {
     Tree distribution[3];  // per pattern; classes: spx_distribution
     Tree writeback;        // classes: spx_writeback
     std::string source = "builtin";
+    // lazy trees decide run() and select_kernel(): they may test nnz_s (or
+    // m_sparsity, s_per_x), computed on the device only when the walk reaches
+    // such a node (the tuner charges that round trip in training)
+    bool lazy = false;
     // true when an internal node of any tree tests nnz_s, m_sparsity or
     // s_per_x, the features that need the vector's column lengths
     bool reads_nnz_s() const {

@@ -54,10 +54,12 @@ def _feature_row(rec):
     return [f[k] for k in FEATURES]
 PATTERNS = ("spmv", "csr_spmspv", "csc_spmspv")
 DISTS = ("direct", "balanced")
-WBS = ("none", "atomic", "sort", "lds_atomic", "bucket")
+WBS = ("none", "atomic", "sort", "lds_atomic", "bucket", "merge")
 # cheaper-first order used to break near-ties (within 2%)
 COST_ORDER = {("spmv",): 0, ("csr_spmspv",): 1, ("csc_spmspv", "atomic"): 2, ("csc_spmspv", "lds_atomic"): 3,
-              ("csc_spmspv", "bucket"): 4, ("csc_spmspv", "sort"): 5}
+              ("csc_spmspv", "bucket"): 4, ("csc_spmspv", "merge"): 5, ("csc_spmspv", "sort"): 6}
+# features that cost run() a device count and a stream synchronization
+COUNT_FEATURES = ("nnz_s", "m_sparsity", "s_per_x")
 TIE = 1.02
 
 
@@ -319,7 +321,6 @@ def format_train(path: str, out_path: str, max_depth: int = 3):
     the tree is grown on all records (one per matrix, too few to hold some
     out); the report gives the time lost against always taking the faster
     format, and the rows of the tree for the library's built-in table."""
-    from sklearn.tree import DecisionTreeClassifier
     recs = [json.loads(l) for l in open(path) if l.strip()]
     X, y, w, tc, ts = [], [], [], [], []
     for r in recs:
@@ -331,18 +332,13 @@ def format_train(path: str, out_path: str, max_depth: int = 3):
         tc.append(c)
         ts.append(s_)
     X = np.asarray(X)
-    clf = DecisionTreeClassifier(max_depth=max_depth, random_state=0).fit(X, y, sample_weight=np.asarray(w) + 1e-3)
-    pred = clf.predict(X)
+    tree = Cart(max_depth).fit(X, np.asarray(y), np.asarray(w) + 1e-3, 2)
+    pred = tree.predict(X)
     best = sum(min(a, b) for a, b in zip(tc, ts))
     chosen = sum(b if p_ else a for a, b, p_ in zip(tc, ts, pred))
     csr_only = sum(tc)
-    t = clf.tree_
-    rows = []
-    for i in range(t.node_count):
-        if t.children_left[i] < 0:
-            rows.append([0, 0.0, 0, 0, int(np.argmax(t.value[i][0]))])
-        else:
-            rows.append([int(t.feature[i]), float(t.threshold[i]), int(t.children_left[i]), int(t.children_right[i]), -1])
+    # library rows: feature, threshold, left, right, class (-1 = internal)
+    rows = [[int(n[0]), float(n[1]), int(n[2]), int(n[3]), int(n[4])] for n in tree.nodes]
     rep = {"records": len(recs), "sell_faster": int(sum(y)), "accuracy": float(np.mean(pred == np.asarray(y))),
            "loss_vs_best": chosen / best - 1.0, "csr_only_loss_vs_best": csr_only / best - 1.0,
            "features": list(FORMAT_FEATURES), "rows": rows}
@@ -662,7 +658,7 @@ def train(paths, out_path, all_features=False, seed=0):
     mask = np.array([l["pattern"] == 2 for _, l in rows])
     if mask.sum() < 10:
         mask = allm
-    trees["writeback"] = fit_tree("writeback", lambda l: l["writeback"], mask, 5,
+    trees["writeback"] = fit_tree("writeback", lambda l: l["writeback"], mask, len(WBS),
                                   lambda l: class_times(l, "writeback"))
     # selection quality against exhaustive search on the held-out part:
     # time of the predicted kernel vs the fastest kernel
@@ -686,6 +682,240 @@ def train(paths, out_path, all_features=False, seed=0):
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return report
+
+
+# ----------------------------------------------------------------------------- lazy trees
+class TimeCart:
+    """Decision tree grown on per-class times instead of labels, with a
+    price on the count features (the lazy evaluation of Section 6.3).
+
+    T[i, c] is the time of class c on sample i relative to that sample's
+    fastest plan (so every sample weighs the same); a leaf takes the class
+    with the least summed time. sync[i] is the cost, on the same scale, of
+    the device count and stream synchronization that nnz_s needs: a split
+    on a count feature charges it once to every sample at the node that has
+    not paid it on its path (paid[i]), and is taken only where the time it
+    saves exceeds that. Cheap splits therefore come first and the count is
+    asked for only in the regions of the feature space where it pays."""
+
+    def __init__(self, max_depth: int, min_leaf: int = 1):
+        self.max_depth = max_depth
+        self.min_leaf = min_leaf
+        self.nodes = []  # [feature, threshold, left, right, class]
+
+    def fit(self, X, T, sync, paid, costly):
+        X = np.asarray(X, np.float64)
+        T = np.asarray(T, np.float64)
+        self.costly = set(int(c) for c in costly)
+        self.nodes = []
+        self._grow(X, T, np.asarray(sync, np.float64), np.asarray(paid, bool), 0)
+        return self
+
+    def _leaf(self, T):
+        self.nodes.append([0, 0.0, 0, 0, int(np.argmin(T.sum(0)))])
+        return len(self.nodes) - 1
+
+    def _grow(self, X, T, sync, paid, depth):
+        n = len(T)
+        tot = T.sum(0)
+        loss = tot.min()
+        if depth >= self.max_depth or n < 2 * self.min_leaf:
+            return self._leaf(T)
+        unpaid = float(sync[~paid].sum())
+        best = None
+        for f in range(X.shape[1]):
+            order = np.argsort(X[:, f], kind="stable")
+            xs = X[order, f]
+            cum = np.cumsum(T[order], axis=0)[:-1]
+            split_loss = cum.min(1) + (tot[None, :] - cum).min(1)
+            k = np.arange(1, n)
+            valid = (xs[1:] > xs[:-1]) & (k >= self.min_leaf) & (n - k >= self.min_leaf)
+            if not valid.any():
+                continue
+            gain = loss - split_loss - (unpaid if f in self.costly else 0.0)
+            gain[~valid] = -np.inf
+            i = int(np.argmax(gain))
+            if best is None or gain[i] > best[0]:
+                best = (gain[i], f, 0.5 * (xs[i] + xs[i + 1]))
+        if best is None or best[0] <= 1e-9 * n:
+            return self._leaf(T)
+        _, f, thr = best
+        if f in self.costly:
+            paid = np.ones(n, bool)
+        me = len(self.nodes)
+        self.nodes.append([f, float(thr), -1, -1, -1])
+        mask = X[:, f] <= thr
+        l = self._grow(X[mask], T[mask], sync[mask], paid[mask], depth + 1)
+        r = self._grow(X[~mask], T[~mask], sync[~mask], paid[~mask], depth + 1)
+        self.nodes[me][2] = l
+        self.nodes[me][3] = r
+        return me
+
+    def walk(self, xrow):
+        """(class, whether the path tested a count feature)."""
+        j, asked = 0, False
+        while self.nodes[j][4] < 0:
+            f, thr, l, r, _ = self.nodes[j]
+            asked |= f in self.costly
+            j = l if xrow[f] <= thr else r
+        return int(self.nodes[j][4]), asked
+
+
+def _rel_times(rows, factor, pat_of=None, dist_of=None):
+    """Per-class times of one factor relative to each record's fastest plan
+    (the factors decided before it fixed by pat_of / dist_of, the ones after
+    it at their best); a class with no timing costs 4x the best."""
+    out = np.empty((len(rows), {"pattern": 3, "distribution": 2, "writeback": len(WBS)}[factor]))
+    for i, (_, lab) in enumerate(rows):
+        t, best = lab["times"], lab["best_ms"]
+        if factor == "pattern":
+            v = [min((ms for (p, d, w), ms in t.items() if p == c), default=np.inf) for c in PATTERNS]
+        elif factor == "distribution":
+            pat = PATTERNS[pat_of[i]]
+            v = [min((ms for (p, d, w), ms in t.items() if p == pat and d == c), default=np.inf) for c in DISTS]
+        else:
+            dist = DISTS[dist_of[i]]
+            v = [t.get(("csc_spmspv", dist, c), np.inf) for c in WBS]
+        v = np.asarray(v, np.float64) / best
+        out[i] = np.where(np.isfinite(v), v, 4.0)
+    return out
+
+
+def _fit_time_tree(X, T, sync, paid, costly, seed):
+    """Depth 1..10 by 3-fold cross-validation on the mean relative time
+    (plan time plus any count the path asks for); then fit on all rows."""
+    rng = np.random.default_rng(seed)
+    folds = np.array_split(rng.permutation(len(T)), 3)
+    best = None
+    for depth in range(1, 11):
+        for min_leaf in (1, 4):
+            sc = []
+            for k in range(3):
+                te = folds[k]
+                tr = np.concatenate([folds[j] for j in range(3) if j != k])
+                t = TimeCart(depth, min_leaf).fit(X[tr], T[tr], sync[tr], paid[tr], costly)
+                tot = 0.0
+                for i in te:
+                    c, asked = t.walk(X[i])
+                    tot += T[i, c] + (sync[i] if asked and not paid[i] else 0.0)
+                sc.append(tot / len(te))
+            m = float(np.mean(sc))
+            if best is None or m < best[0] - 1e-9:
+                best = (m, depth, min_leaf)
+    return TimeCart(best[1], best[2]).fit(X, T, sync, paid, costly), best
+
+
+def train_lazy(paths, out_path, sync_us: float, seed=0):
+    """Trees for run() that may ask for nnz_s: every Table 1 feature plus
+    s_per_x is available, but a path through a count feature pays sync_us
+    (the measured cost of the device count and stream synchronization in a
+    pipelined run() loop) on each vector that takes it. Cascade as in
+    train(): pattern, then the distribution of that pattern, then the
+    column-major write-back; a vector that paid in an earlier tree reads
+    the counts for free in the later ones. 7:3 split; the report gives the
+    held-out time lost against exhaustive search with the counts charged,
+    beside what the vectors would lose with no count at all."""
+    recs = []
+    for p in paths:
+        with open(p) as f:
+            recs += [json.loads(l) for l in f if l.strip()]
+    rows = [(r, lab) for r in recs for lab in [labels(r)] if lab is not None]
+    X = np.array([_feature_row(r) for r, _ in rows], np.float64)
+    best_ms = np.array([lab["best_ms"] for _, lab in rows])
+    sync = (sync_us * 1e-3) / best_ms
+    costly = [FEATURES.index(f) for f in COUNT_FEATURES]
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(len(rows))
+    ntr = int(round(0.7 * len(rows)))
+    tr, te = perm[:ntr], perm[ntr:]
+    report = {"records": len(rows), "train": int(len(tr)), "test": int(len(te)), "sync_us": sync_us,
+              "features": list(FEATURES), "costly": list(COUNT_FEATURES)}
+    no_paid = np.zeros(len(rows), bool)
+    Tp = _rel_times(rows, "pattern")
+    tp, sc = _fit_time_tree(X[tr], Tp[tr], sync[tr], no_paid[tr], costly, seed)
+    report["pattern"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2], "nodes": len(tp.nodes)}
+    walks = [tp.walk(x) for x in X]
+    pat = np.array([w[0] for w in walks])
+    paid = np.array([w[1] for w in walks])
+    trees = {"pattern": tp, "distribution": {}}
+    Td = _rel_times(rows, "distribution", pat_of=pat)
+    dist = np.zeros(len(rows), np.int64)
+    for pi, pn in enumerate(PATTERNS):
+        m = pat == pi
+        mtr = tr[m[tr]]
+        if len(mtr) < 10:
+            t = TimeCart(0).fit(X[:1], Td[:1], sync[:1], paid[:1], costly)
+        else:
+            t, sc = _fit_time_tree(X[mtr], Td[mtr], sync[mtr], paid[mtr], costly, seed)
+            report[f"distribution_{pn}"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2],
+                                           "nodes": len(t.nodes)}
+        trees["distribution"][pn] = t
+        for i in np.nonzero(m)[0]:
+            c, asked = t.walk(X[i])
+            dist[i] = c
+            paid[i] |= asked
+    Tw = _rel_times(rows, "writeback", dist_of=dist)
+    Tw[:, 0] = 4.0  # "none" is not a column-major write-back
+    m = pat == 2
+    mtr = tr[m[tr]]
+    tw, sc = _fit_time_tree(X[mtr], Tw[mtr], sync[mtr], paid[mtr], costly, seed)
+    report["writeback"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2], "nodes": len(tw.nodes)}
+    trees["writeback"] = tw
+    out = {"format": "spx-selector-v1", "source": "tuned on MI355X timings (lazy counts)", "lazy": True,
+           "sync_us": sync_us, "report": report,
+           "pattern": {"nodes": tp.nodes},
+           "distribution": {pn: {"nodes": t.nodes} for pn, t in trees["distribution"].items()},
+           "writeback": {"nodes": tw.nodes}}
+    ev = evaluate_lazy(rows, out, sync_us, subset=te)
+    report["held_out"] = ev
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return report
+
+
+def _walk_cascade(sel, x):
+    """(pattern, distribution, write-back, whether a count was asked for)."""
+    asked = False
+
+    def ev(nodes):
+        nonlocal asked
+        j = 0
+        while nodes[j][4] < 0:
+            f = nodes[j][0]
+            f = FEATURES.index(f) if isinstance(f, str) else int(f)
+            asked |= FEATURES[f] in COUNT_FEATURES
+            j = nodes[j][2] if x[f] <= nodes[j][1] else nodes[j][3]
+        return int(nodes[j][4])
+
+    pat = ev(sel["pattern"]["nodes"])
+    dist = ev(sel["distribution"][PATTERNS[pat]]["nodes"])
+    wb = ev(sel["writeback"]["nodes"]) if pat == 2 else 0
+    return pat, dist, wb, asked
+
+
+def evaluate_lazy(rows, sel, sync_us, subset=None):
+    """Per support kind: total and mean time over exhaustive search of a
+    selector's plans, with sync_us added to every vector whose walk asked
+    for a count, and the share of vectors that asked."""
+    per = {}
+    idx = range(len(rows)) if subset is None else subset
+    for i in idx:
+        r, lab = rows[i]
+        x = _feature_row(r)
+        pat, dist, wb, asked = _walk_cascade(sel, x)
+        t = lab["times"].get((PATTERNS[pat], DISTS[dist], WBS[wb]), 2 * lab["best_ms"])
+        t += sync_us * 1e-3 if asked else 0.0
+        o = per.setdefault(r.get("support", "uniform"), {"n": 0, "asked": 0, "best": 0.0, "chosen": 0.0,
+                                                        "loss": [], "hit": 0})
+        o["n"] += 1
+        o["asked"] += int(asked)
+        o["best"] += lab["best_ms"]
+        o["chosen"] += t
+        o["loss"].append(t / lab["best_ms"] - 1.0)
+        o["hit"] += int(t <= lab["best_ms"] * TIE)
+    return {k: {"vectors": o["n"], "asked_for_counts": o["asked"] / o["n"], "total_loss": o["chosen"] / o["best"] - 1.0,
+                "mean_loss": float(np.mean(o["loss"])), "within_2pct_of_best": o["hit"] / o["n"]}
+            for k, o in per.items()}
 
 
 # ----------------------------------------------------------------------------- model study
@@ -829,11 +1059,36 @@ def main(argv=None):
     ft = sub.add_parser("formats-train")
     ft.add_argument("data")
     ft.add_argument("--out", required=True)
+    tl = sub.add_parser("train-lazy")
+    tl.add_argument("data", nargs="+")
+    tl.add_argument("--out", required=True)
+    tl.add_argument("--sync-us", type=float, required=True,
+                    help="measured cost of run()'s device count and stream synchronization")
+    el = sub.add_parser("evaluate-lazy")
+    el.add_argument("data", nargs="+")
+    el.add_argument("--selectors", nargs="+", required=True)
+    el.add_argument("--sync-us", type=float, required=True)
+    el.add_argument("--out")
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--all-features", action="store_true")
     a = ap.parse_args(argv)
+    if a.cmd == "train-lazy":
+        print(json.dumps(train_lazy(a.data, a.out, a.sync_us), indent=1))
+        return
+    if a.cmd == "evaluate-lazy":
+        recs = []
+        for p in a.data:
+            with open(p) as f:
+                recs += [json.loads(l) for l in f if l.strip()]
+        rows = [(r, lab) for r in recs for lab in [labels(r)] if lab is not None]
+        rep = {os.path.basename(sp): evaluate_lazy(rows, json.load(open(sp)), a.sync_us) for sp in a.selectors}
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(rep, f, indent=1)
+        print(json.dumps(rep, indent=1))
+        return
     if a.cmd == "drivers":
         driver_sweep(a.out, a.reps)
         return

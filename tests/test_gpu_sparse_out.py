@@ -126,3 +126,19 @@ def test_sparse_output_full_size_rmat20():
             mask[prev] = True
         listed = _check(M, A, "f32", v.idx, np.asarray(v.val, np.float32), mask, None)
         prev = listed if mask is None else np.union1d(listed, prev)
+
+
+@pytest.mark.parametrize("m", [1, 31, 32, 33, 64, 65, 1000, 4097])
+def test_pack_mask_matches_bit_definition(m):
+    """spx_pack_mask: bit i of word i // 32 is rows[i] != 0, high bits of the
+    last word clear (numpy's little-endian bit packing as the definition)."""
+    torch = _torch()
+    rng = np.random.default_rng(16767 + m)
+    A = synth.uniform_rows(m, 8, 1, 3)
+    M = spx.Matrix.from_host(A.with_vals(np.asarray(A.vals).astype(np.float32)))
+    rows = rng.integers(0, 4, m).astype(np.uint8)  # any nonzero byte sets the bit
+    want = np.packbits(rows != 0, bitorder="little")
+    want = np.concatenate([want, np.zeros((-len(want)) % 4, np.uint8)]).view("<u4")
+    for t in (torch.as_tensor(rows, device="cuda"), torch.as_tensor(rows != 0, device="cuda")):
+        got = M.pack_mask(t).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got[:len(want)], want[:(m + 31) // 32])

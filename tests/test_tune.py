@@ -119,8 +119,7 @@ def test_sell_padding_by_hand():
 def test_format_train_separates_the_formats(tmp_path):
     """Sliced copy faster exactly on the even-row, many-row records: the
     tree learns it, loses nothing on its training set, and its rows are in
-    the library's table form."""
-    pytest.importorskip("sklearn.tree")
+    the library's table form (the project CART, no scikit-learn)."""
     path = tmp_path / "formats.jsonl"
     rng = np.random.default_rng(1)
     with open(path, "w") as f:
