@@ -200,6 +200,22 @@ spx_status spmspv_csc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, con
                       void *y, const spx_plan *plan, void *workspace, size_t ws_bytes,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * spmspv_csc with the workspace taken from a fixed scratch array inside the
+ * library (64 MiB per device, reserved on every GPU the library runs on
+ * until the process ends; spmspv_csc_noalloc_capacity() returns its size).
+ * Same arguments and results as spmspv_csc minus the workspace; the calls
+ * allocate nothing (no hipMalloc, no hipFree). Returns SPX_ERR_WORKSPACE
+ * when spx_workspace_size(A->m, A->n, A->nnz, nnz_x, A->dtype, plan) is
+ * larger than the scratch. The scratch is shared by every call on one GPU:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller. The sort write-back reads a count on the
+ * host and synchronizes the stream, as it does in spmspv_csc. */
+spx_status spmspv_csc_noalloc(const spx_csc *A, int32_t nnz_x, const int32_t *x_idx, const void *x_val,
+                              void *y, const spx_plan *plan, void *stream);
+size_t spmspv_csc_noalloc_capacity(void);
+
 /* ---------------------------------------------------------------------
  * Matrix handle: the dual CSR + CSC storage kept for the life of the
  * matrix (Section 6.1) and the matrix features computed once (Section 6.3).

@@ -496,6 +496,20 @@ def spmspv_csc(A: Matrix, idx, val, p: Plan, y=None, stream=None):
     return y
 
 
+def spmspv_csc_noalloc(A: Matrix, idx, val, p: Plan, y, stream=None):
+    """spmspv_csc without a workspace argument: the library's fixed device
+    scratch serves instead (nothing is allocated; y must be given)."""
+    c = A.csc_pointers()
+    _lib.call("spmspv_csc_noalloc", C.byref(c), int(idx.numel()), _ptr(idx), _ptr(val), _ptr(y), C.byref(p),
+              _stream(stream))
+    return y
+
+
+def noalloc_capacity() -> int:
+    """Bytes of the fixed device scratch behind spmspv_csc_noalloc."""
+    return int(_lib.load().spmspv_csc_noalloc_capacity())
+
+
 def stream_copy(src, dst, stream=None):
     """dst <- src with the library's streaming copy kernel (the achievable
     bandwidth reference); both contiguous device tensors of equal byte size,

@@ -64,6 +64,8 @@ SIGNATURES = {
     "spmv_csr": (C.c_int, [C.POINTER(Csr), P, P, C.POINTER(Plan), P, C.c_size_t, P]),
     "spmspv_csr": (C.c_int, [C.POINTER(Csr), _i32, P, P, P, C.POINTER(Plan), P, C.c_size_t, P]),
     "spmspv_csc": (C.c_int, [C.POINTER(Csc), _i32, P, P, P, C.POINTER(Plan), P, C.c_size_t, P]),
+    "spmspv_csc_noalloc": (C.c_int, [C.POINTER(Csc), _i32, P, P, P, C.POINTER(Plan), P]),
+    "spmspv_csc_noalloc_capacity": (C.c_size_t, []),
     "spx_matrix_create": (C.c_int, [C.POINTER(Csr), C.c_uint32, P, C.POINTER(P)]),
     "spx_matrix_destroy": (C.c_int, [P]),
     "spx_matrix_csc": (C.c_int, [P, C.POINTER(Csc)]),

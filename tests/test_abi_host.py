@@ -116,3 +116,20 @@ def test_dynamic_lds_declarations_are_aligned():
                 found += 1
                 assert "__align__(16)" in code, f"{name}:{lineno}: dynamic LDS without __align__(16)"
     assert found > 0
+
+
+def test_noalloc_entry_rejects_oversized_plans_on_the_host():
+    """spmspv_csc_noalloc refuses a plan whose workspace exceeds its fixed
+    scratch before touching the device (fake pointers, never dereferenced)."""
+    lib = _lib.load()
+    cap = lib.spmspv_csc_noalloc_capacity()
+    assert cap == 64 << 20
+    big = _lib.Csc(1 << 20, 1 << 20, 1 << 26, _lib.F32, C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000))
+    sort = _lib.Plan(_lib.PAT_CSC_SPMSPV, _lib.DIST_BALANCED, _lib.WB_SORT, 0, 0, 0)
+    assert lib.spx_workspace_size(big.m, big.n, big.nnz, 16, _lib.F32, C.byref(sort)) > cap
+    rc = lib.spmspv_csc_noalloc(C.byref(big), 16, C.c_void_p(0x4000), C.c_void_p(0x5000), C.c_void_p(0x6000),
+                                C.byref(sort), None)
+    assert rc == -8 and b"scratch" in lib.spx_last_error()
+    rowmajor = _lib.Plan(_lib.PAT_SPMV, _lib.DIST_DIRECT, _lib.WB_NONE, 0, 0, 0)
+    assert lib.spmspv_csc_noalloc(C.byref(big), 16, C.c_void_p(0x4000), C.c_void_p(0x5000), C.c_void_p(0x6000),
+                                  C.byref(rowmajor), None) == -1
