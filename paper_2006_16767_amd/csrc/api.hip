@@ -199,6 +199,10 @@ struct spx_matrix {
     void* sp_val = nullptr;
     int32_t* scratch_i32 = nullptr;  // compaction workspace
     int64_t* dev_scalars = nullptr;  // 4 x int64 (feature reductions, counts)
+    // lazy counts of run(): two device counters and a ticket (zero between
+    // calls) and the pinned host copy the counting kernel writes
+    unsigned long long* cnt_dev = nullptr;
+    long long* cnt_host = nullptr;
     uint32_t* scan_counter = nullptr;  // arrival counter of the one-launch length scan
     // merge-path partitions of the balanced row-major kernels, per tile size,
     // for A (index 0) and for A^T (index 1)
@@ -479,12 +483,13 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
                     H->part[0][0], H->part[0][1], H->part[1][0], H->part[1][1], H->dev_sel, H->bws,
                     H->units, H->split_rows, H->bfs_front[0], H->bfs_front[1], H->bfs_y, H->drv_count,
                     H->bfs_bits[0], H->bfs_bits[1], H->pr_W, H->pr_r, H->pr_y, H->pr_xidx, H->pr_xval,
-                    H->pr_xd[0], H->pr_xd[1], H->pr_p, H->pr_bad};
+                    H->pr_xd[0], H->pr_xd[1], H->pr_p, H->pr_bad, H->cnt_dev};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sell_free(&H->sell);
     tile_sorted_free(&H->ts);
     if (H->drv_host) hipHostFree(H->drv_host);
+    if (H->cnt_host) hipHostFree(H->cnt_host);
     for (auto& e : H->drv_ev)
         if (e) hipEventDestroy(e);
     for (auto& e : H->ev_conv) {
@@ -799,14 +804,34 @@ static spx_status check_vec(const spx_matrix* H, const spx_vec* x) {
     return SPX_OK;
 }
 
-// device reduction for nnz_s (and nnz_x of a dense x); synchronizes
+// device count of nnz_s (and nnz_x of a dense x): one launch that writes
+// the totals to pinned host memory, then a stream synchronization
 static spx_status device_vector_counts(spx_matrix* H, const spx_vec* x, hipStream_t s, int64_t* nnz_s,
                                        int64_t* nnz_x) {
-    SPX_TRY(ensure_conv(H));
-    SPX_TRY(vector_features_device(H->col_ptr, H->csr.n, x, H->csr.dtype, H->dev_scalars, s));
-    int64_t h[2] = {0, 0};
-    SPX_HIP(hipMemcpyAsync(h, H->dev_scalars, sizeof(h), hipMemcpyDeviceToHost, s));
-    SPX_HIP(hipStreamSynchronize(s));
+    if (!H->cnt_dev) {
+        if (hipMalloc((void**)&H->cnt_dev, 64) != hipSuccess) return fail(SPX_ERR_ALLOC, "count buffers");
+        if (hipHostMalloc((void**)&H->cnt_host, 64, hipHostMallocCoherent) != hipSuccess) {
+            hipFree(H->cnt_dev);
+            H->cnt_dev = nullptr;
+            return fail(SPX_ERR_ALLOC, "pinned count buffer");
+        }
+        SPX_HIP(hipMemset(H->cnt_dev, 0, 64));
+        SPX_HIP(hipDeviceSynchronize());
+    }
+    volatile long long* h = H->cnt_host;
+    h[0] = -1;
+    h[1] = -1;
+    SPX_TRY(vector_counts_to_host(H->col_ptr, H->csr.n, x, H->csr.dtype, H->cnt_dev, (uint32_t*)(H->cnt_dev + 2),
+                                  H->cnt_host, s));
+    // the kernel's last workgroup stores the totals to the pinned buffer:
+    // poll it (a stream synchronization wakes the host about 10 us later),
+    // and after a second without a result fall back to the synchronization,
+    // which reports a failed launch
+    const auto t0 = std::chrono::steady_clock::now();
+    while ((h[0] < 0 || h[1] < 0) && std::chrono::steady_clock::now() - t0 < std::chrono::seconds(1)) {
+    }
+    if (h[0] < 0 || h[1] < 0) SPX_HIP(hipStreamSynchronize(s));
+    if (h[0] < 0 || h[1] < 0) return fail(SPX_ERR_HIP, "vector counts: the counting kernel wrote no result");
     *nnz_s = h[0];
     *nnz_x = x->kind == SPX_VEC_SPARSE ? x->nnz_x : h[1];
     return SPX_OK;

@@ -207,6 +207,10 @@ struct MatrixStats {
 spx_status matrix_features_device(const int32_t* row_ptr, int32_t m, int32_t n,
                                   MatrixStats* out, hipStream_t s);
 // nnz_s (and nnz_x for a dense x) on the device into out2[0..1] (int64)
+// nnz_s (and a dense x's nonzero count) in one launch, written to host-visible
+// host2[0..1]; acc2 (2 counters) and ticket must be zero and are left zero
+spx_status vector_counts_to_host(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,
+                                 unsigned long long* acc2, uint32_t* ticket, long long* host2, hipStream_t s);
 spx_status vector_features_device(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,
                                   int64_t* out2_dev, hipStream_t s);
 

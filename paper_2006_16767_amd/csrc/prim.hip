@@ -51,19 +51,22 @@ spx_status fill_bytes(void* p, uint8_t v, size_t bytes, hipStream_t s) {
 
 // ------------------------------------------------------------------ streaming copy
 // The achievable-bandwidth reference of the measurements: a plain copy with
-// 16-byte loads and stores, four of each in flight per thread, grid-stride.
+// 16-byte loads and stores in which every workgroup copies its own
+// contiguous 16 KiB (four loads in flight per thread, then four stores).
+// On MI355X this one-chunk-per-workgroup shape streamed a 1 GiB copy at
+// 5.8 TB/s, against 4.4-4.7 TB/s for grid-stride loops of the same loads
+// (and 5.3 TB/s for the runtime's device-to-device copy).
+constexpr int kCopyU = 4;
 __global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                         int64_t n16) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        uint4 a[4];
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kCopyU + threadIdx.x;
+    uint4 a[kCopyU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = src[i + u * stride];
+    for (int u = 0; u < kCopyU; ++u)
+        if (base + u * kBlock < n16) a[u] = src[base + u * kBlock];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dst[i + u * stride] = a[u];
-    }
-    for (; i < n16; i += stride) dst[i] = src[i];
+    for (int u = 0; u < kCopyU; ++u)
+        if (base + u * kBlock < n16) dst[base + u * kBlock] = a[u];
 }
 
 }  // namespace spx
@@ -74,12 +77,10 @@ extern "C" spx_status spx_stream_copy(const void* src, void* dst, size_t bytes, 
     if (!src || !dst) return fail(SPX_ERR_ARG, "stream copy: null pointer");
     if ((((uintptr_t)src | (uintptr_t)dst | bytes) & 15) != 0)
         return fail(SPX_ERR_ARG, "stream copy: pointers and size must be multiples of 16 bytes");
-    int dev = 0, cus = 256;
-    SPX_HIP(hipGetDevice(&dev));
-    SPX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t n16 = (int64_t)(bytes / 16);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n16, kBlock), (int64_t)cus * 16));
-    k_stream_copy<<<grid, kBlock, 0, (hipStream_t)stream>>>((const uint4*)src, (uint4*)dst, n16);
+    const int64_t blocks = ceil_div(n16, (int64_t)kBlock * kCopyU);
+    if (blocks > 0x7fffffff) return fail(SPX_ERR_ARG, "stream copy: more than 2^31 chunks of 16 KiB");
+    k_stream_copy<<<(unsigned)blocks, kBlock, 0, (hipStream_t)stream>>>((const uint4*)src, (uint4*)dst, n16);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }
@@ -709,6 +710,82 @@ __global__ __launch_bounds__(kBlock) void k_vec_feat_dense(const int32_t* __rest
         atomicAdd(&out[0], a);
         atomicAdd(&out[1], c);
     }
+}
+
+// The counts of run()'s lazy features in one launch: nnz_s (the column
+// lengths summed over supp(x)) and, for a dense x, the number of its present
+// entries. Every workgroup adds its partial sums into two device counters;
+// the last to arrive (atomicInc wraps the ticket back to 0) takes the totals
+// out of the counters (clearing them for the next call) and stores them to
+// host-visible memory, so the host needs no copy command, only the stream
+// synchronization. Counters and ticket are zero between calls.
+template <int DT, bool DENSE>
+__global__ __launch_bounds__(kBlock) void k_vec_counts(const int32_t* __restrict__ col_ptr, int32_t count,
+                                                       const int32_t* __restrict__ idx,
+                                                       const typename SR<DT>::X* __restrict__ x,
+                                                       unsigned long long* __restrict__ acc2,
+                                                       uint32_t* __restrict__ ticket, long long* __restrict__ host2) {
+    __shared__ unsigned long long s_red[2][kWavesPerBlock];
+    unsigned long long a = 0, c = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < count; e += (int64_t)gridDim.x * kBlock) {
+        if constexpr (DENSE) {
+            if (SR<DT>::present(x[e])) {
+                a += (unsigned long long)(col_ptr[e + 1] - col_ptr[e]);
+                c += 1;
+            }
+        } else {
+            const int j = idx[e];
+            a += (unsigned long long)(col_ptr[j + 1] - col_ptr[j]);
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, kWave);
+        c += __shfl_xor(c, off, kWave);
+    }
+    if (lane_id() == 0) {
+        s_red[0][wave_id()] = a;
+        s_red[1][wave_id()] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < kWavesPerBlock; ++i) {
+        a += s_red[0][i];
+        c += s_red[1][i];
+    }
+    if (a) atomicAdd(&acc2[0], a);
+    if (c) atomicAdd(&acc2[1], c);
+    __threadfence();
+    if (atomicInc(ticket, gridDim.x - 1) != gridDim.x - 1) return;
+    __threadfence();
+    const unsigned long long ta = atomicExch(&acc2[0], 0ull);
+    const unsigned long long tc = atomicExch(&acc2[1], 0ull);
+    __hip_atomic_store(&host2[0], (long long)ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host2[1], DENSE ? (long long)tc : (long long)count, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+spx_status vector_counts_to_host(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,
+                                 unsigned long long* acc2, uint32_t* ticket, long long* host2, hipStream_t s) {
+    const bool dense = x->kind != SPX_VEC_SPARSE;
+    const int32_t count = dense ? n : x->nnz_x;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, kBlock * 4), 256));
+    if (!dense) {
+        k_vec_counts<SPX_F32, false><<<grid, kBlock, 0, s>>>(col_ptr, count, x->idx, nullptr, acc2, ticket, host2);
+    } else {
+        switch (dtype) {
+#define SPX_DT(DT)                                                                                           \
+    case DT:                                                                                                 \
+        k_vec_counts<DT, true><<<grid, kBlock, 0, s>>>(col_ptr, count, nullptr,                              \
+                                                       (const typename SR<DT>::X*)x->val, acc2, ticket, host2); \
+        break;
+            SPX_DT(SPX_F32) SPX_DT(SPX_F64) SPX_DT(SPX_I32) SPX_DT(SPX_BOOL) SPX_DT(SPX_F32_MINPLUS)
+#undef SPX_DT
+            default:
+                return fail(SPX_ERR_DTYPE, "vector counts: dtype");
+        }
+    }
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
 }
 
 spx_status vector_features_device(const int32_t* col_ptr, int32_t n, const spx_vec* x, int dtype,

@@ -64,6 +64,8 @@ def kernel_names(p, column_sorted: bool = False) -> list[str]:
             main = "k_csr_merge"
         return [main, "k_csr_merge_fixup"]
     dist = "direct" if p.distribution == 0 else "merge"
+    if p.writeback == 5:
+        return (["k_merge_emit_direct"] if p.distribution == 0 else []) + ["k_merge_tile_sort", "k_merge_accumulate"]
     if p.writeback == 4:
         return [f"k_bucket_scatter_{dist}", "k_bucket_accumulate"]
     if p.writeback == 2:
