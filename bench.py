@@ -42,6 +42,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_VALU_PEAK_GFLOPS = 157300.0  # MI355X vector FP32, published
+L2_PEAK_GBS = 8 * 16 * 128 * 2.4  # derived: XCDs x L2 channels x bytes per clock x GHz
 FLUSH_BYTES = 1 << 30
 
 
@@ -224,7 +226,8 @@ def extra_batched(torch, spx, synth, flush, reps=5):
 def extra_fwd_bwd(torch, spx, synth, flush, reps=10):
     """Pruned FC layer 16384 x 4096 at 5%, batch 64 of post-ReLU activations
     (50..95% zeros): forward (fused batch SpMV; the per-vector SpMSpV mode
-    timed beside it) vs forward + backward (dX and dvals), each flushed."""
+    timed beside it) vs forward + backward (dX and dvals in one call; each
+    gradient alone is timed beside it), each flushed."""
     import numpy as np
     A = synth.cfg5_matrix()
     M = spx.Matrix.from_host(A)
@@ -242,6 +245,7 @@ def extra_fwd_bwd(torch, spx, synth, flush, reps=10):
     t_f_sparse = med(lambda: M.run_dense_batch(X, Y))  # per-vector adaptive SpMSpV
     t_dx = med(lambda: M.transpose_matvec(G, dX))
     t_dv = med(lambda: M.dvals(G, X, dv))
+    t_bwd = med(lambda: M.backward(G, X))  # both gradients from one B-minor copy of G
     B, m, n, nnz = 64, A.m, A.n, A.nnz
     nnz_x = [v.nnz for v in acts]
     xs = [(torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(v.val, device="cuda")) for v in acts]
@@ -254,7 +258,7 @@ def extra_fwd_bwd(torch, spx, synth, flush, reps=10):
     dx_pv = B * (nnz * 8 + (n + 1) * 4 + m * 4 + n * 4)
     dx_u = nnz * 8 + (n + 1) * 4 + B * (m * 4 + n * 4)
     dv_b = nnz * 8 + (m + 1) * 4 + B * (m * 4 + n * 4)  # fused over the batch by definition
-    t_b = (t_dx + t_dv) * 1e-3
+    t_b = t_bwd * 1e-3
 
     def pct(b, t_ms):
         return 100 * b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -262,14 +266,27 @@ def extra_fwd_bwd(torch, spx, synth, flush, reps=10):
     f_pv, f_u = pct(fwd_pv, t_f), pct(fwd_u, t_f)
     b_pv = 100 * (dx_pv + dv_b) / t_b / 1e9 / HBM_PEAK_GBS
     b_u = 100 * (dx_u + dv_b) / t_b / 1e9 / HBM_PEAK_GBS
-    return {"workload": "fc16384x4096_d0.05_batch64_f32", "fwd_ms": round(t_f, 4), "dx_ms": round(t_dx, 4),
-            "dvals_ms": round(t_dv, 4), "fwd_sparse_mode_ms": round(t_f_sparse, 4),
-            "fwd_plus_bwd_over_fwd": round((t_f + t_dx + t_dv) / t_f, 2),
+    return {"workload": "fc16384x4096_d0.05_batch64_f32", "fwd_ms": round(t_f, 4), "bwd_ms": round(t_bwd, 4),
+            "dx_alone_ms": round(t_dx, 4), "dvals_alone_ms": round(t_dv, 4),
+            "fwd_sparse_mode_ms": round(t_f_sparse, 4),
+            "fwd_plus_bwd_over_fwd": round((t_f + t_bwd) / t_f, 2),
             "per_vector_scale": {"fwd_pct_hbm_peak": round(f_pv, 2), "bwd_pct_hbm_peak": round(b_pv, 2),
                                  "bwd_over_fwd": round(b_pv / f_pv, 2)},
             "unique_scale": {"fwd_pct_hbm_peak": round(f_u, 2), "bwd_pct_hbm_peak": round(b_u, 2),
                              "bwd_over_fwd": round(b_u / f_u, 2)},
             "dx_pct_unique": round(pct(dx_u, t_dx), 2), "dvals_pct": round(pct(dv_b, t_dv), 2),
+            # the gathers' own roofs: every stored entry reads B-long rows of the
+            # B-minor copies (G^T for dX; G^T and X^T for dvals) from L2, and
+            # does 2 B FP32 flops
+            "l2_gather": {"dx_GB/s": round(nnz * B * 4 / (t_dx * 1e-3) / 1e9, 1),
+                          "dvals_GB/s": round(nnz * B * 8 / (t_dv * 1e-3) / 1e9, 1),
+                          "derived_peak_GB/s": L2_PEAK_GBS,
+                          "dx_frac": round(nnz * B * 4 / (t_dx * 1e-3) / 1e9 / L2_PEAK_GBS, 4),
+                          "dvals_frac": round(nnz * B * 8 / (t_dv * 1e-3) / 1e9 / L2_PEAK_GBS, 4),
+                          "peak_note": "derived: 8 XCDs x 16 L2 channels x 128 B/clk x 2.4 GHz (not a published figure)"},
+            "valu": {"peak_GFLOP/s": FP32_VALU_PEAK_GFLOPS,
+                     "dx_frac": round(2 * B * nnz / (t_dx * 1e-3) / 1e9 / FP32_VALU_PEAK_GFLOPS, 4),
+                     "dvals_frac": round(2 * B * nnz / (t_dv * 1e-3) / 1e9 / FP32_VALU_PEAK_GFLOPS, 4)},
             "GFLOP/s": {"fwd": round(2 * B * nnz / (t_f * 1e-3) / 1e9, 1),
                         "dx": round(2 * B * nnz / (t_dx * 1e-3) / 1e9, 1),
                         "dvals": round(2 * B * nnz / (t_dv * 1e-3) / 1e9, 1)}}

@@ -246,23 +246,29 @@ size_t spmspv_csc_noalloc_capacity(void);
  * column, and 8 + value size per entry for the reordered copy.
  *
  * Storage-format pre-selection (Section 8's extension: pick the matrix
- * format per matrix, before the kernel): besides CSR the handle can keep a
- * sliced ELLPACK copy (SELL-C-sigma: slices of 64 rows, one wave per slice
- * and a lane per row, rows sorted by descending length within windows of
- * 4096 rows, padding to the longest row of each slice). When it does, every
- * plan of the SpMV pattern runs on it; the other patterns are unchanged.
- * By default a small decision tree over the matrix features and the
- * padding ratio (cells / nnz) decides (trained on MI355X timings of both
- * formats; reading the padding ratio copies row_ptr to the host once).
- * SPX_FORMAT_SELL forces the copy (SPX_ERR_UNSUPPORTED when a row is longer
- * than 4096 entries or the copy would take more than 3 nnz + 65536 cells),
- * SPX_FORMAT_CSR forbids it. Memory: 8 + value size bytes per cell, 4 per
- * row. */
+ * format per matrix, before the kernel): besides CSR the handle can keep
+ * either a sliced ELLPACK copy (SELL-C-sigma: slices of 64 rows, one wave
+ * per slice and a lane per row, rows sorted by descending length within
+ * windows of 4096 rows, padding to the longest row of each slice) or an
+ * ELLPACK copy (every row padded to the longest row of the matrix, stored
+ * column-major, a thread per row, no row pointers read). When it does,
+ * every plan of the SpMV pattern runs on that copy; the other patterns are
+ * unchanged. By default a small decision tree over the matrix features and
+ * the two padding ratios (cells / nnz; reading the sliced one copies
+ * row_ptr to the host once) decides, trained on MI355X timings of the
+ * three formats. SPX_FORMAT_SELL forces the sliced copy
+ * (SPX_ERR_UNSUPPORTED when a row is longer than 4096 entries or the copy
+ * would take more than 3 nnz + 65536 cells), SPX_FORMAT_ELL the ELL copy
+ * (SPX_ERR_UNSUPPORTED beyond 4096 entries per row or 1.5 nnz + 65536
+ * cells; SPX_ERR_ARG with SPX_FORMAT_SELL), SPX_FORMAT_CSR forbids both.
+ * Memory: 8 + value size bytes per cell (4 more per row for the sliced
+ * copy). */
 #define SPX_VALIDATE 1u
 #define SPX_RENUMBER 4u
 #define SPX_NO_RENUMBER 8u
 #define SPX_FORMAT_CSR 16u
 #define SPX_FORMAT_SELL 32u
+#define SPX_FORMAT_ELL 64u
 spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
 spx_status spx_matrix_destroy(spx_matrix *H);
 
@@ -280,9 +286,9 @@ spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
  * asynchronously on stream. */
 spx_status spx_matrix_column_order(const spx_matrix *H, int32_t *order, int32_t *renumbered, void *stream);
 
-/* *format = 1 if the handle keeps the sliced ELLPACK copy (see
- * spx_matrix_create), else 0; *padding_ratio (may be NULL) = its cells /
- * nnz (0 when there is no copy). Host only. */
+/* *format = 1 if the handle keeps the sliced ELLPACK copy, 2 if it keeps
+ * the ELLPACK copy (see spx_matrix_create), else 0; *padding_ratio (may be
+ * NULL) = that copy's cells / nnz (0 when there is no copy). Host only. */
 spx_status spx_matrix_format(const spx_matrix *H, int32_t *format, double *padding_ratio);
 
 /* Matrix features of Table 1, out[9] = {m, n, nnz, max_row, min_row,
@@ -473,7 +479,9 @@ spx_status spx_pagerank(spx_matrix *H, double damping, double eps, int32_t max_i
  *                                           along columns, no atomics)
  *   dvals_k = sum_b G[b, row k] X[b, col k]  over the CSR pattern
  * Both read the matrix once for the whole batch. F32 and F64 only. The
- * handle's workspace holds B-minor copies of G (and X).
+ * handle's workspace holds B-minor copies of G (and X); dX is stored
+ * B-major directly by the gather kernel (a workgroup's 16 columns turned
+ * through LDS).
  * ------------------------------------------------------------------- */
 
 /* dX[b] = A^T G[b] for b < B: G is B x m, dX is B x n (device, row-major). */
@@ -483,6 +491,14 @@ spx_status spmv_csr_transpose(spx_matrix *H, int32_t B, const void *G, void *dX,
  * G is B x m and X is B x n dense (device, row-major). */
 spx_status dvals_pattern(spx_matrix *H, int32_t B, const void *G, const void *X, void *dvals,
                          void *stream);
+
+/* Both gradients of one backward pass: dX = G A (as spmv_csr_transpose)
+ * and dvals (as dvals_pattern), computed from one B-minor copy of G, which
+ * the two separate calls would each make. dX or dvals may be NULL to skip
+ * it (not both); X may be NULL when dvals is. Same layouts and dtypes as
+ * the separate calls. */
+spx_status spx_backward(spx_matrix *H, int32_t B, const void *G, const void *X, void *dX, void *dvals,
+                        void *stream);
 
 /* Vector format conversion for a batch (Section 6.3): the B dense rows of
  * X (B x n, matrix dtype; uint8 for BOOL) become sparse vectors in

@@ -16,7 +16,8 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F32_MINPLUS, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
-                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
+                   PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, FORMAT_ELL,
+                   WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
                    WB_MERGE, WB_SORT, Plan, SpxError)
 
 __all__ = ["Matrix", "Plan", "SpxError", "plan", "spmv_csr", "spmspv_csr", "spmspv_csc",
@@ -135,7 +136,7 @@ class Matrix:
         _ensure_default_selector()
         h = C.c_void_p()
         flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
-        flags |= {None: 0, "csr": FORMAT_CSR, "sell": FORMAT_SELL}[fmt]
+        flags |= {None: 0, "csr": FORMAT_CSR, "sell": FORMAT_SELL, "ell": FORMAT_ELL}[fmt]
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         if dtype == BOOL:
@@ -255,12 +256,13 @@ class Matrix:
         _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
 
     def storage_format(self):
-        """("sell", padding ratio) when the handle keeps the sliced ELLPACK
-        copy that its SpMV plans run on, else ("csr", 0.0)."""
+        """("sell" or "ell", padding ratio) when the handle keeps the sliced
+        ELLPACK or the ELLPACK copy that its SpMV plans run on, else
+        ("csr", 0.0)."""
         f = C.c_int32(0)
         r = C.c_double(0.0)
         _lib.call("spx_matrix_format", self._h, C.byref(f), C.byref(r))
-        return ("sell" if f.value else "csr"), float(r.value)
+        return ("csr", "sell", "ell")[f.value], float(r.value)
 
     def column_order(self, stream=None):
         """The column ranking of the renumbered row-major copy (device int32
@@ -432,6 +434,20 @@ class Matrix:
         out = torch.empty(self.nnz, dtype=G.dtype, device=G.device) if out is None else out
         _lib.call("dvals_pattern", self._h, G2.shape[0], _ptr(G2), _ptr(X2), _ptr(out), _stream(stream))
         return out
+
+
+    def backward(self, G, X=None, want_dx=True, want_dvals=True, stream=None):
+        """(dX, dvals) of one backward pass from one B-minor copy of G:
+        dX[b] = A^T G[b] (B x n) and dvals[k] = sum_b G[b, row k] X[b, col k];
+        either may be skipped (None is returned for it)."""
+        torch = _torch()
+        G2 = G.reshape(-1, self.m).contiguous()
+        B = int(G2.shape[0])
+        dX = torch.empty((B, self.n), dtype=G.dtype, device=G.device) if want_dx else None
+        dv = torch.empty(self.nnz, dtype=G.dtype, device=G.device) if want_dvals else None
+        X2 = X.reshape(-1, self.n).contiguous() if want_dvals else None
+        _lib.call("spx_backward", self._h, B, _ptr(G2), _ptr(X2), _ptr(dX), _ptr(dv), _stream(stream))
+        return dX, dv
 
 
 def _copy_raw(dst, src_ptr: int):

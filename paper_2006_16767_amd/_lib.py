@@ -22,7 +22,7 @@ PAT_SPMV, PAT_CSR_SPMSPV, PAT_CSC_SPMSPV = 0, 1, 2
 DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET, WB_MERGE = 0, 1, 2, 3, 4, 5
 VEC_DENSE, VEC_SPARSE = 0, 1
-VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL = 1, 2, 4, 8, 16, 32
+VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, FORMAT_ELL = 1, 2, 4, 8, 16, 32, 64
 BFS_PUSH_ONLY = 1
 
 
@@ -92,6 +92,7 @@ SIGNATURES = {
     "spmv_csr_batch": (C.c_int, [P, _i32, P, P, P]),
     "spmv_csr_transpose": (C.c_int, [P, _i32, P, P, P]),
     "dvals_pattern": (C.c_int, [P, _i32, P, P, P, P]),
+    "spx_backward": (C.c_int, [P, _i32, P, P, P, P, P]),
     "spx_pack_mask": (C.c_int, [_i32, P, P, P]),
     "spx_dense_rows_to_sparse": (C.c_int, [P, _i32, P, P, P, P, P]),
     "spx_stream_copy": (C.c_int, [P, P, C.c_size_t, P]),

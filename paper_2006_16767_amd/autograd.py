@@ -6,9 +6,10 @@ Forward, two ways: "fused" (default) runs the row-major SpMV of every row
 of X in one pass over A (spmv_csr_batch); "sparse" converts each row of X
 to a sparse vector on the device and runs the batched SpMSpV, with the plan
 of each vector chosen on the device (run_batch).
-Backward (F32/F64): dX = G A (gather along the CSC columns, no atomics) and
-dvals_k = sum_b G[b, row k] X[b, col k] over the stored pattern; both
-kernels read the matrix once for the whole batch.
+Backward (F32/F64), one library call (spx_backward): dX = G A (gather
+along the CSC columns, no atomics) and dvals_k = sum_b G[b, row k] X[b, col k]
+over the stored pattern; both kernels read the matrix once for the whole
+batch and share one B-minor copy of G.
 
 The matrix handle borrows its CSR value tensor; pass that tensor as
 `vals` so autograd tracks it. Every forward re-derives the CSC copy of the
@@ -45,8 +46,13 @@ class SparseLinearFunction(torch.autograd.Function):
         (X,) = ctx.saved_tensors
         M = ctx.M
         G = G.contiguous()
-        dvals = M.dvals(G, X) if ctx.needs_input_grad[0] else None
-        dX = M.transpose_matvec(G) if ctx.needs_input_grad[1] else None
+        want_dvals, want_dx = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (want_dvals or want_dx):
+            return None, None, None, None
+        # one call: the B-minor copy of G serves both gradients
+        dX, dvals = M.backward(G, X, want_dx=want_dx, want_dvals=want_dvals)
+        if dX is not None:
+            dX = dX.reshape(G.shape[:-1] + (M.n,))
         return dvals, dX, None, None
 
 

@@ -192,6 +192,7 @@ struct spx_matrix {
     // there is one), used by the SpMV pattern when present
     SellMat sell;
     double sell_ratio = 0.0;
+    EllMat ell;
     // column-sorted copy of the renumbered CSR for the balanced SpMV with
     // 2048-item tiles (kept with the renumbered copy when n <= 2^21)
     TileSorted ts;
@@ -487,6 +488,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     sell_free(&H->sell);
+    ell_free(&H->ell);
     tile_sorted_free(&H->ts);
     if (H->drv_host) hipHostFree(H->drv_host);
     if (H->cnt_host) hipHostFree(H->cnt_host);
@@ -656,10 +658,15 @@ static spx_status build_gcsr(spx_matrix* H, uint32_t flags, hipStream_t s) {
 constexpr int32_t kSellMaxRow = 4096;  // longest row the copy accepts (serial sums per lane)
 constexpr double kSellMaxRatio = 3.0;  // most cells per entry it accepts, beyond a fixed allowance
 constexpr int64_t kSellAllowance = 65536;  // cells any matrix may use (one partly filled slice)
+constexpr int32_t kEllMaxRow = 4096;   // longest row the ELL copy accepts
+constexpr double kEllMaxRatio = 1.5;   // most cells per entry it accepts, beyond the allowance
 static spx_status choose_format(spx_matrix* H, uint32_t flags, hipStream_t s) {
     const spx_csr& A = H->gorder ? H->gcsr : H->csr;
     if ((flags & SPX_FORMAT_CSR) || A.m == 0) return SPX_OK;
+    if ((flags & SPX_FORMAT_SELL) && (flags & SPX_FORMAT_ELL))
+        return fail(SPX_ERR_ARG, "SPX_FORMAT_SELL and SPX_FORMAT_ELL exclude each other");
     const bool forced = (flags & SPX_FORMAT_SELL) != 0;
+    const bool forced_ell = (flags & SPX_FORMAT_ELL) != 0;
     std::vector<int32_t> rp;
     SellPlanInfo info;
     bool shaped = false;
@@ -679,8 +686,18 @@ static spx_status choose_format(spx_matrix* H, uint32_t flags, hipStream_t s) {
         shape();
         return (double)info.padded / (double)std::max<int64_t>(1, A.nnz);
     };
-    const bool want = forced || format_prefers_sell(H->feat, ratio);
-    if (st != SPX_OK || !want) return st;
+    const int choice = forced ? 1 : forced_ell ? 2 : format_choice(H->feat, ratio);
+    if (st != SPX_OK || choice == 0) return st;
+    if (choice == 2) {
+        const int32_t w = (int32_t)H->feat[3];
+        const double cells = (double)w * (double)A.m;
+        if (w > kEllMaxRow || cells > kEllMaxRatio * (double)A.nnz + (double)kSellAllowance) {
+            if (forced_ell)
+                return fail(SPX_ERR_UNSUPPORTED, "ELL: a row longer than 4096 or more than 1.5 nnz + 65536 cells");
+            return SPX_OK;
+        }
+        return ell_build(A, w, &H->ell, s);
+    }
     const double r = ratio();
     if (st != SPX_OK) return st;
     if (H->feat[3] > kSellMaxRow || (double)info.padded > kSellMaxRatio * (double)A.nnz + (double)kSellAllowance) {
@@ -763,14 +780,18 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     SPX_TRY(gather_perm(H->csr.vals, H->perm, H->vals_csc, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->sell.col) SPX_TRY(sell_refresh(H->sell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
+    if (H->ell.col) SPX_TRY(ell_refresh(H->ell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->ts.pk) SPX_TRY(gather_perm(H->csr.vals, H->ts.src, H->ts.vals, H->csr.nnz, vs, (hipStream_t)stream));
     return SPX_OK;
 }
 
 extern "C" spx_status spx_matrix_format(const spx_matrix* H, int32_t* format, double* padding_ratio) {
     if (!H || !format) return fail(SPX_ERR_ARG, "null argument");
-    *format = H->sell.col ? 1 : 0;
-    if (padding_ratio) *padding_ratio = H->sell.col ? H->sell_ratio : 0.0;
+    *format = H->sell.col ? 1 : H->ell.col ? 2 : 0;
+    if (padding_ratio)
+        *padding_ratio = H->sell.col ? H->sell_ratio
+                         : H->ell.col ? (double)H->ell.cells / (double)std::max<int32_t>(1, H->csr.nnz)
+                                      : 0.0;
     return SPX_OK;
 }
 
@@ -882,6 +903,8 @@ struct LazyFeatures {
                 return H->csr.nnz > 0 ? (double)ns() / H->csr.nnz : 0.0;
             case F_S_PER_X:
                 return (double)ns() / (double)std::max<int64_t>(1, nx());
+            case F_COUNTED:
+                return have_counts && synced ? 1.0 : 0.0;
         }
         return 0.0;
     }
@@ -1045,6 +1068,8 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         bool cleared = false;
         if (H->sell.col)
             SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
+        else if (H->ell.col)
+            SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
         else
             SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared,
                                     H->gorder && H->ts.pk ? &H->ts : nullptr));
@@ -1203,6 +1228,8 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
     record(H, H->ev_kern, true, s);
     if (H->sell.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
+    else if (H->ell.col && p->pattern == SPX_PAT_SPMV)
+        SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
     else
         SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s, nullptr, nullptr,
                                 H->gorder && H->ts.pk ? &H->ts : nullptr));
@@ -1767,6 +1794,18 @@ extern "C" spx_status dvals_pattern(spx_matrix* H, int32_t B, const void* G, con
     Arena ws(H->ws, H->ws_bytes);
     return launch_dvals(H->csr.row_ptr, H->csr.col_idx, H->csr.m, H->csr.n, H->csr.nnz, dt, B, G, X, dvals, ws,
                         (hipStream_t)stream);
+}
+
+extern "C" spx_status spx_backward(spx_matrix* H, int32_t B, const void* G, const void* X, void* dX, void* dvals,
+                                   void* stream) {
+    if (!H || (B > 0 && (!G || (dvals && !X))) || (!dX && !dvals)) return fail(SPX_ERR_ARG, "null argument");
+    if (B < 0) return fail(SPX_ERR_SHAPE, "B must be >= 0");
+    const int dt = H->csr.dtype;
+    if (dt != SPX_F32 && dt != SPX_F64) return fail(SPX_ERR_DTYPE, "backward supports F32 and F64");
+    SPX_TRY(ensure_ws(H, grad_ws_bytes(H->csr.m, H->csr.n, B, dt)));
+    Arena ws(H->ws, H->ws_bytes);
+    return launch_backward(H->csr.row_ptr, H->csr.col_idx, H->col_ptr, H->row_idx, H->vals_csc, H->csr.m, H->csr.n,
+                           H->csr.nnz, dt, B, G, X, dX, dvals, ws, (hipStream_t)stream);
 }
 
 extern "C" spx_status spx_pack_mask(int32_t m, const uint8_t* rows, uint32_t* words, void* stream) {

@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
             f[9] = nx;
             f[10] = a.n > 0 ? (double)nx / a.n : 0.0;
             f[11] = f[12] = f[13] = 0.0;
+            f[F_COUNTED] = 0.0;
             int pat = dev_tree_eval(S.t[0], f);
             if (pat < 0 || pat > 2) pat = 0;
             fuse = pat != SPX_PAT_CSC_SPMSPV || f[10] >= kFusedMinXSparsity;
@@ -212,6 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_plan(BatchDev a) {
     f[11] = carry;
     f[12] = a.nnz > 0 ? (double)carry / a.nnz : 0.0;
     f[13] = (double)carry / (double)(nx > 0 ? nx : 1);
+    f[F_COUNTED] = 1.0;
     BatchPlan p;
     p.pattern = dev_tree_eval(S.t[0], f);
     if (p.pattern < 0 || p.pattern > 2) p.pattern = 0;

@@ -11,8 +11,8 @@
 //  k_seg_gather one wave per column j of A (a row of A^T, read from the CSC
 //               copy: a gather along the column, no atomics); lane b
 //               accumulates sum_k vals[k] * G^T[row_k, b] (eight entries in
-//               flight) and stores dX^T[j, b] coalesced; one transpose gives
-//               dX.
+//               flight); a workgroup's 16 columns are turned through LDS so
+//               that dX is stored B-major directly.
 //  k_sddmm      one wave per row i of A, lane b = batch entry: sixteen stored
 //               entries at a time, each lane forms its sixteen products
 //               G^T[i, b] X^T[col_k, b] (coalesced 4B-per-lane rows), and a
@@ -52,46 +52,62 @@ static spx_status transpose(int64_t rows, int64_t cols, const T* in, T* out, hip
     return SPX_OK;
 }
 
-// Segment gather over a batch: outT[j, b0 + lane] = sum over the entries k
-// of segment j of vals[k] * inT[idx[k], b0 + lane], for lanes < nb. inT and
-// outT are B-minor (rows of B values). With the CSC (segments = columns,
-// idx = rows, inT = G^T) it is dX^T = (G A)^T; with the CSR (segments =
-// rows, idx = columns, inT = X^T) it is Y^T for y_b = A x_b.
+// Segment gather over a batch, written B-major: out[b0 + b, j] = sum over
+// the entries k of segment j of vals[k] * inT[idx[k], b0 + b], for b < nb.
+// inT is B-minor (rows of B values), so a wave per segment reads the B
+// values of one entry as one coalesced row (lane = batch entry). A
+// workgroup takes kSegPerBlock consecutive segments, one wave each, and
+// turns its kSegPerBlock x nb results through LDS so that every batch row
+// is stored as kSegPerBlock consecutive values (no transpose pass). With
+// the CSC (segments = columns, idx = rows, inT = G^T) it is dX = G A; with
+// the CSR (segments = rows, idx = columns, inT = X^T) it is Y for
+// y_b = A x_b.
+constexpr int kSegPerBlock = 16;
+constexpr int kSegThreads = kSegPerBlock * kWave;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_seg_gather(int32_t nseg, int32_t B, int32_t b0, int32_t nb,
-                                                       const int32_t* __restrict__ seg_ptr,
-                                                       const int32_t* __restrict__ idx,
-                                                       const T* __restrict__ vals, const T* __restrict__ inT,
-                                                       T* __restrict__ outT) {
-    const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + wave_id());
-    if (j >= nseg) return;
+__global__ __launch_bounds__(kSegThreads) void k_seg_gather(int32_t nseg, int32_t B, int32_t b0, int32_t nb,
+                                                            const int32_t* __restrict__ seg_ptr,
+                                                            const int32_t* __restrict__ idx,
+                                                            const T* __restrict__ vals, const T* __restrict__ inT,
+                                                            T* __restrict__ out) {
+    __shared__ T tile[kSegPerBlock][kWave + 1];
+    const int w = __builtin_amdgcn_readfirstlane(wave_id());
+    const int64_t j0 = (int64_t)blockIdx.x * kSegPerBlock;
+    const int64_t j = j0 + w;
     const int lane = lane_id();
-    const bool on = lane < nb;
-    const int c0 = seg_ptr[j], c1 = seg_ptr[j + 1];
-    const int32_t* row_idx = idx;
-    const T* g = inT + b0 + (on ? lane : 0);
-    // a partial sum per load slot, folded every kFoldRounds rounds (bounded
-    // chains on long segments)
-    ChunkedAcc<sizeof(T) == 8 ? SPX_F64 : SPX_F32, 8> acc;
-    int k = c0;
-    for (; k + 7 < c1; k += 8) {
-        int r[8];
-        T v[8], gv[8];
+    if (j < nseg) {
+        const bool on = lane < nb;
+        const int c0 = seg_ptr[j], c1 = seg_ptr[j + 1];
+        const T* g = inT + b0 + (on ? lane : 0);
+        // a partial sum per load slot, folded every kFoldRounds rounds
+        // (bounded chains on long segments)
+        ChunkedAcc<sizeof(T) == 8 ? SPX_F64 : SPX_F32, 8> acc;
+        int k = c0;
+        for (; k + 7 < c1; k += 8) {
+            int r[8];
+            T v[8], gv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            r[u] = row_idx[k + u];
-            v[u] = vals[k + u];
+            for (int u = 0; u < 8; ++u) {
+                r[u] = idx[k + u];
+                v[u] = vals[k + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gv[u] = g[(int64_t)r[u] * B];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc.part[u] = __builtin_fma(v[u], gv[u], acc.part[u]);
+            acc.end_round();
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) gv[u] = g[(int64_t)r[u] * B];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc.part[u] = __builtin_fma(v[u], gv[u], acc.part[u]);
-        acc.end_round();
+        for (int u = 0; u < 7; ++u)
+            if (k + u < c1) acc.part[u] = __builtin_fma(vals[k + u], g[(int64_t)idx[k + u] * B], acc.part[u]);
+        tile[w][lane] = acc.total();
     }
-#pragma unroll
-    for (int u = 0; u < 7; ++u)
-        if (k + u < c1) acc.part[u] = __builtin_fma(vals[k + u], g[(int64_t)row_idx[k + u] * B], acc.part[u]);
-    if (on) outT[(int64_t)j * B + b0 + lane] = acc.total();
+    __syncthreads();
+    // thread t stores segment j0 + t % kSegPerBlock of batch row b0 + t / kSegPerBlock
+    const int jj = threadIdx.x % kSegPerBlock;
+    const int b = threadIdx.x / kSegPerBlock;
+    if (b < nb && j0 + jj < nseg) out[(int64_t)(b0 + b) * nseg + j0 + jj] = tile[jj][b];
 }
 
 // Folds p[0..15] over the 64 lanes of a wave: lane l ends with the full sum
@@ -155,20 +171,26 @@ size_t grad_ws_bytes(int32_t m, int32_t n, int32_t B, int dtype) {
     return z.used;
 }
 
+// out (B x nseg, B-major) from a B-minor inT, 64 batch rows per launch
+template <typename T>
+static spx_status seg_gather(int32_t nseg, int32_t B, const int32_t* seg_ptr, const int32_t* idx, const T* vals,
+                             const T* inT, T* out, hipStream_t s) {
+    for (int32_t b0 = 0; b0 < B; b0 += kWave) {
+        const int nb = std::min(kWave, B - b0);
+        k_seg_gather<T><<<(unsigned)ceil_div(nseg, kSegPerBlock), kSegThreads, 0, s>>>(nseg, B, b0, nb, seg_ptr, idx,
+                                                                                      vals, inT, out);
+        SPX_HIP(hipGetLastError());
+    }
+    return SPX_OK;
+}
+
 template <typename T>
 static spx_status dx_t(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n,
                        int32_t B, const void* G, void* dX, Arena& ws, hipStream_t s) {
     T* GT = ws.take<T>((size_t)m * B);
-    T* dXT = ws.take<T>((size_t)n * B);
-    if (!GT || !dXT) return fail(SPX_ERR_WORKSPACE, "dx: workspace too small");
+    if (!GT) return fail(SPX_ERR_WORKSPACE, "dx: workspace too small");
     SPX_TRY(transpose<T>(B, m, (const T*)G, GT, s));
-    for (int32_t b0 = 0; b0 < B; b0 += 64) {
-        const int nb = std::min(64, B - b0);
-        k_seg_gather<T><<<(unsigned)ceil_div(n, kWavesPerBlock), kBlock, 0, s>>>(n, B, b0, nb, col_ptr, row_idx,
-                                                                                (const T*)vals_csc, GT, dXT);
-        SPX_HIP(hipGetLastError());
-    }
-    return transpose<T>(n, B, dXT, (T*)dX, s);
+    return seg_gather<T>(n, B, col_ptr, row_idx, (const T*)vals_csc, GT, (T*)dX, s);
 }
 
 spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n,
@@ -184,16 +206,9 @@ template <typename T>
 static spx_status spmv_batch_t(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
                                int32_t n, int32_t B, const void* X, void* Y, Arena& ws, hipStream_t s) {
     T* XT = ws.take<T>((size_t)n * B);
-    T* YT = ws.take<T>((size_t)m * B);
-    if (!XT || !YT) return fail(SPX_ERR_WORKSPACE, "spmv batch: workspace too small");
+    if (!XT) return fail(SPX_ERR_WORKSPACE, "spmv batch: workspace too small");
     SPX_TRY(transpose<T>(B, n, (const T*)X, XT, s));
-    for (int32_t b0 = 0; b0 < B; b0 += 64) {
-        const int nb = std::min(64, B - b0);
-        k_seg_gather<T><<<(unsigned)ceil_div(m, kWavesPerBlock), kBlock, 0, s>>>(m, B, b0, nb, row_ptr, col_idx,
-                                                                                (const T*)vals, XT, YT);
-        SPX_HIP(hipGetLastError());
-    }
-    return transpose<T>(m, B, YT, (T*)Y, s);
+    return seg_gather<T>(m, B, row_ptr, col_idx, (const T*)vals, XT, (T*)Y, s);
 }
 
 spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, const void* vals, int32_t m,
@@ -218,6 +233,42 @@ static spx_status dvals_t(const int32_t* row_ptr, const int32_t* col_idx, int32_
                                                                         (T*)dvals);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
+}
+
+// dX = G A and dvals from one B-minor copy of G (and one of X): the two
+// gradients of a backward pass, with the transposes they share made once.
+template <typename T>
+static spx_status backward_t(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* col_ptr,
+                             const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n, int32_t B,
+                             const void* G, const void* X, void* dX, void* dvals, Arena& ws, hipStream_t s) {
+    T* GT = ws.take<T>((size_t)m * B);
+    T* XT = ws.take<T>((size_t)n * B);
+    if (!GT || !XT) return fail(SPX_ERR_WORKSPACE, "backward: workspace too small");
+    SPX_TRY(transpose<T>(B, m, (const T*)G, GT, s));
+    if (dX) SPX_TRY(seg_gather<T>(n, B, col_ptr, row_idx, (const T*)vals_csc, GT, (T*)dX, s));
+    if (dvals) {
+        SPX_TRY(transpose<T>(B, n, (const T*)X, XT, s));
+        k_sddmm<T><<<(unsigned)ceil_div(m, kWavesPerBlock), kBlock, 0, s>>>(m, B, row_ptr, col_idx, GT, XT,
+                                                                            (T*)dvals);
+        SPX_HIP(hipGetLastError());
+    }
+    return SPX_OK;
+}
+
+spx_status launch_backward(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* col_ptr,
+                           const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n, int32_t nnz, int dtype,
+                           int32_t B, const void* G, const void* X, void* dX, void* dvals, Arena& ws, hipStream_t s) {
+    const size_t es = dtype == SPX_F64 ? 8 : 4;
+    if (B == 0) return dvals && nnz > 0 ? fill_bytes(dvals, 0, (size_t)nnz * es, s) : SPX_OK;
+    if (m == 0 || nnz == 0) {
+        if (dX && n > 0) SPX_TRY(fill_bytes(dX, 0, (size_t)B * n * es, s));
+        return SPX_OK;
+    }
+    if (dtype == SPX_F32)
+        return backward_t<float>(row_ptr, col_idx, col_ptr, row_idx, vals_csc, m, n, B, G, X, dX, dvals, ws, s);
+    if (dtype == SPX_F64)
+        return backward_t<double>(row_ptr, col_idx, col_ptr, row_idx, vals_csc, m, n, B, G, X, dX, dvals, ws, s);
+    return fail(SPX_ERR_DTYPE, "backward: F32 or F64 only");
 }
 
 spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n, int32_t nnz,

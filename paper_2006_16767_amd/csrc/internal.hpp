@@ -310,6 +310,9 @@ spx_status launch_spmv_batch(const int32_t* row_ptr, const int32_t* col_idx, con
                              int32_t n, int dtype, int32_t B, const void* X, void* Y, Arena& ws, hipStream_t s);
 spx_status launch_dx(const int32_t* col_ptr, const int32_t* row_idx, const void* vals_csc, int32_t m,
                      int32_t n, int dtype, int32_t B, const void* G, void* dX, Arena& ws, hipStream_t s);
+spx_status launch_backward(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* col_ptr,
+                           const int32_t* row_idx, const void* vals_csc, int32_t m, int32_t n, int32_t nnz, int dtype,
+                           int32_t B, const void* G, const void* X, void* dX, void* dvals, Arena& ws, hipStream_t s);
 spx_status launch_dvals(const int32_t* row_ptr, const int32_t* col_idx, int32_t m, int32_t n,
                         int32_t nnz, int dtype, int32_t B, const void* G, const void* X,
                         void* dvals, Arena& ws, hipStream_t s);
@@ -344,5 +347,20 @@ spx_status sell_build(const spx_csr& A, const SellPlanInfo& info, SellMat* out, 
 spx_status sell_refresh(const SellMat& S, const spx_csr& A, hipStream_t s);
 void sell_free(SellMat* S);
 spx_status sell_spmv(const SellMat& S, int dtype, const void* x, void* y, hipStream_t s);
+
+// ELL copy of A: rows padded to the longest, column-major (entry j of row i
+// at j * m + i); see sell.hip.
+struct EllMat {
+    int32_t m = 0;
+    int32_t width = 0;        // longest row
+    int64_t cells = 0;        // width * m
+    int32_t* col = nullptr;   // [cells], -1 for padding
+    int32_t* src = nullptr;   // [cells], CSR position or -1
+    void* vals = nullptr;     // [cells] (none for BOOL)
+};
+spx_status ell_build(const spx_csr& A, int32_t width, EllMat* out, hipStream_t s);
+spx_status ell_refresh(const EllMat& E, const spx_csr& A, hipStream_t s);
+void ell_free(EllMat* E);
+spx_status ell_spmv(const EllMat& E, int dtype, const void* x, void* y, hipStream_t s);
 
 }  // namespace spx

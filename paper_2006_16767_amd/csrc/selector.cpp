@@ -13,7 +13,7 @@ namespace spx {
 
 static const char* kNames[F_COUNT] = {"m",           "n",           "nnz",       "max_row", "min_row",
                                       "avg_row",     "relative_range", "var_nnz_row", "gini",    "nnz_x",
-                                      "x_sparsity", "nnz_s",       "m_sparsity", "s_per_x"};
+                                      "x_sparsity", "nnz_s",       "m_sparsity", "s_per_x", "counted"};
 
 const char* feature_name(int f) { return (f >= 0 && f < F_COUNT) ? kNames[f] : "?"; }
 
@@ -38,21 +38,26 @@ static Tree make_tree(std::initializer_list<std::initializer_list<double>> rows)
 }
 
 // Trained (tune.py formats-train: the project CART, depth 3, regret-weighted)
-// on MI355X timings of the dense-x FP32 SpMV on the 30 tuning matrices, best
-// CSR plan against the sliced copy: the copy wins on even row lengths
-// ((max_row - min_row) / n <= 3.07e-5, i.e. a spread of at most 32 entries
-// at n = 2^20) over more than 40960 rows, up to about 1.5M rows (the 7-point
-// stencil at 128^3, 2.1M rows, ran 5 % faster in CSR). On that corpus it
-// loses 0.2 % against always taking the faster format, CSR alone 2.1 %.
+// on MI355X timings of the dense-x FP32 SpMV on the 30 tuning matrices:
+// best CSR plan, sliced copy and ELL copy. Nearly equal rows (population
+// standard deviation of the row lengths <= 0.83) over more than 98304 rows
+// go to ELL up to 15.7M entries (the 7-point stencils: 128^3 ran 29.0 us in
+// ELL against 34.8 in CSR and 36.5 sliced) and to the sliced copy beyond;
+// between 24576 and 98304 such rows the sliced copy wins; every uneven or
+// small matrix stays in CSR. On that corpus it loses 0.2 % against always
+// taking the fastest format (CSR alone 3.4 %); on the FP64 sweep 0.4 % (CSR
+// alone 2.6 %).
 Tree format_tree() {
     // rows: feature, threshold, left, right, class (-1 = internal)
     return make_tree({
-        {F_REL_RANGE, 3.07220458984375e-05, 1, 6, -1},
-        {F_M, 40960.0, 2, 3, -1},
+        {F_VAR_ROW, 0.8266357019503078, 1, 8, -1},
+        {F_M, 98304.0, 2, 5, -1},
+        {F_M, 24576.0, 3, 4, -1},
         {0, 0, 0, 0, 0},
-        {F_M, 1572864.0, 4, 5, -1},
         {0, 0, 0, 0, 1},
-        {0, 0, 0, 0, 0},
+        {F_NNZ, 15679488.0, 6, 7, -1},
+        {0, 0, 0, 0, 2},
+        {0, 0, 0, 0, 1},
         {0, 0, 0, 0, 0},
     });
 }

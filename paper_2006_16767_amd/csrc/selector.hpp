@@ -30,6 +30,8 @@ enum Feature {
     F_NNZ_S,
     F_M_SPARSITY,
     F_S_PER_X,  // nnz_s / max(1, nnz_x): mean length of the selected columns (derived, not in Table 1)
+    F_COUNTED,  // 1 when the vector's counts (nnz_s) are already known, else 0: lets a later tree of the
+                // cascade use them for free once an earlier one paid for them (not in Table 1)
     F_COUNT
 };
 
@@ -77,16 +79,22 @@ struct Selector {
 
 Selector builtin_selector();
 
-// Storage-format pre-selector: class 1 when the sliced ELLPACK copy is
-// expected to run the SpMV faster than CSR. Feature ids 0-8 are the Table 1
-// matrix features (F_M .. F_GINI), kFmtPadding the padding ratio of the
-// sliced copy (cells / nnz), which ratio() computes on first use.
+// Storage-format pre-selector: class 0 keeps CSR only, class 1 adds the
+// sliced ELLPACK copy, class 2 the ELLPACK copy, for the format expected to
+// run the SpMV fastest. Feature ids 0-8 are the Table 1 matrix features
+// (F_M .. F_GINI), kFmtPadding the padding ratio of the sliced copy
+// (cells / nnz; ratio() computes it on first use, from a host copy of
+// row_ptr), kFmtEllPadding that of the ELL copy (max_row * m / nnz, from the
+// features).
 constexpr int kFmtPadding = 9;
+constexpr int kFmtEllPadding = 10;
 Tree format_tree();
 template <typename RatioFn>
-bool format_prefers_sell(const double* feat, RatioFn&& ratio) {
+int format_choice(const double* feat, RatioFn&& ratio) {
     static const Tree t = format_tree();
-    return t.eval([&](int f) { return f < kFmtPadding ? feat[f] : ratio(); }) == 1;
+    const double ell = feat[F_NNZ] > 0 ? feat[F_MAX_ROW] * feat[F_M] / feat[F_NNZ] : 1.0;
+    const int c = t.eval([&](int f) { return f < kFmtPadding ? feat[f] : f == kFmtPadding ? ratio() : ell; });
+    return c >= 0 && c <= 2 ? c : 0;
 }
 // Parses the tuner's JSON. Returns false with a message on error.
 bool parse_selector_json(const std::string& text, Selector* out, std::string* err);

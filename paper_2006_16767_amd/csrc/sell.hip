@@ -1,5 +1,5 @@
-// Sliced ELLPACK (SELL-C-sigma) copy of A for the row-major SpMV: the
-// second storage format of the format pre-selection that the paper names
+// Sliced ELLPACK (SELL-C-sigma) and ELLPACK copies of A for the row-major
+// SpMV: the storage formats beside CSR of the format pre-selection that the paper names
 // as its extension (Section 8: choose the matrix format first, SMAT-style,
 // then the kernel). The handle keeps the copy when the format tree
 // (format_tree) prefers it.
@@ -203,6 +203,122 @@ spx_status sell_spmv(const SellMat& S, int dtype, const void* x, void* y, hipStr
 #undef SPX_DT
         default:
             return fail(SPX_ERR_DTYPE, "sliced ELL: unknown dtype");
+    }
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ ELLPACK
+// ELL copy of A: every row padded to the longest row w, stored column-major
+// (entry j of row i at j * m + i, padding column -1), so that consecutive
+// threads, one per row, read consecutive addresses at every step and y is
+// written in row order. No row pointer is read. The third candidate of the
+// format pre-selection, for matrices whose rows are nearly equal (the
+// padding w * m / nnz stays close to 1).
+__global__ __launch_bounds__(kBlock) void k_ell_fill(int32_t m, int32_t w, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx, int32_t* __restrict__ col,
+                                                     int32_t* __restrict__ src) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int32_t r0 = row_ptr[i], len = row_ptr[i + 1] - r0;
+    for (int j = 0; j < w; ++j) {
+        const int64_t pos = (int64_t)j * m + i;
+        const bool on = j < len;
+        col[pos] = on ? col_idx[r0 + j] : -1;
+        src[pos] = on ? r0 + j : -1;
+    }
+}
+
+// y = A x over the ELL copy: a thread per row, eight steps loaded per round
+// (steps past w switched off), a partial sum per load slot.
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_ell_spmv(int32_t m, int32_t w, const int32_t* __restrict__ col,
+                                                     const typename SR<DT>::V* __restrict__ vals,
+                                                     const typename SR<DT>::X* __restrict__ x,
+                                                     typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    constexpr int U = 8;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    ChunkedAcc<DT, U> acc;
+    for (int j = 0; j < w; j += U) {
+        int c[U];
+        typename S::V a[U];
+        typename S::X b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = j + u < w ? col[(int64_t)(j + u) * m + i] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            a[u] = j + u < w ? S::val(vals, (int64_t)(j + u) * m + i) : (typename S::V)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) b[u] = c[u] >= 0 ? S::xval(x, c[u]) : (typename S::X)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) acc.part[u] = S::fma(a[u], b[u], acc.part[u]);
+        acc.end_round();
+    }
+    y[i] = S::out(acc.total());
+}
+
+spx_status ell_build(const spx_csr& A, int32_t w, EllMat* out, hipStream_t s) {
+    EllMat E;
+    E.m = A.m;
+    E.width = w;
+    E.cells = (int64_t)w * A.m;
+    const int vs = value_size(A.dtype);
+    const size_t cells = (size_t)std::max<int64_t>(1, E.cells);
+    if (hipMalloc((void**)&E.col, cells * 4) != hipSuccess || hipMalloc((void**)&E.src, cells * 4) != hipSuccess ||
+        (vs > 0 && hipMalloc(&E.vals, cells * vs) != hipSuccess)) {
+        ell_free(&E);
+        return fail(SPX_ERR_ALLOC, "ELL allocation failed");
+    }
+    if (A.m > 0 && w > 0) {
+        k_ell_fill<<<(unsigned)ceil_div(A.m, kBlock), kBlock, 0, s>>>(A.m, w, A.row_ptr, A.col_idx, E.col, E.src);
+        if (hipGetLastError() != hipSuccess) {
+            ell_free(&E);
+            return fail(SPX_ERR_HIP, "ELL fill");
+        }
+    }
+    *out = E;
+    return ell_refresh(*out, A, s);
+}
+
+spx_status ell_refresh(const EllMat& E, const spx_csr& A, hipStream_t s) {
+    const int vs = value_size(A.dtype);
+    if (vs == 0 || E.cells == 0) return SPX_OK;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(E.cells, kBlock), 8192));
+    if (vs == 4)
+        k_sell_vals<uint32_t><<<grid, kBlock, 0, s>>>(E.cells, E.src, (const uint32_t*)A.vals, (uint32_t*)E.vals);
+    else
+        k_sell_vals<uint64_t><<<grid, kBlock, 0, s>>>(E.cells, E.src, (const uint64_t*)A.vals, (uint64_t*)E.vals);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+void ell_free(EllMat* E) {
+    void* ptrs[] = {E->col, E->src, E->vals};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    *E = EllMat{};
+}
+
+spx_status ell_spmv(const EllMat& E, int dtype, const void* x, void* y, hipStream_t s) {
+    if (E.m == 0) return SPX_OK;
+    const unsigned grid = (unsigned)ceil_div(E.m, kBlock);
+    switch (dtype) {
+#define SPX_DT(DT)                                                                                           \
+    case DT:                                                                                                 \
+        k_ell_spmv<DT><<<grid, kBlock, 0, s>>>(E.m, E.width, E.col, (const typename SR<DT>::V*)E.vals,       \
+                                               (const typename SR<DT>::X*)x, (typename SR<DT>::Y*)y);        \
+        break;
+        SPX_DT(SPX_F32)
+        SPX_DT(SPX_F64)
+        SPX_DT(SPX_I32)
+        SPX_DT(SPX_BOOL)
+        SPX_DT(SPX_F32_MINPLUS)
+#undef SPX_DT
+        default:
+            return fail(SPX_ERR_DTYPE, "ELL: unknown dtype");
     }
     SPX_HIP(hipGetLastError());
     return SPX_OK;

@@ -13,7 +13,8 @@
 //              the pair buffer, grouped by bucket. The chunk's range is its
 //              range of prefix positions, so no global atomic and no count
 //              pass are needed. Per (bucket, chunk) it records the offset and
-//              count of that group, bucket-major.
+//              count of that group, chunk-major (each chunk writes its own
+//              contiguous row of the tables).
 //  accumulate  one workgroup per bucket zeroes an LDS copy of its R rows,
 //              adds the pairs of every chunk's group with LDS atomics, and
 //              writes all R rows of y once (rows that received nothing get 0,
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_merge(
     __syncthreads();
     const int P0 = t.p0;
     for (int b = threadIdx.x; b < NB; b += kBlock) {
-        const int64_t mi = (int64_t)b * out.stride + chunk;
+        const int64_t mi = chunk * NB + b;  // chunk-major: the chunk's table is one contiguous run
         out.moff[mi] = P0 + s_off[b];
         out.mcnt[mi] = s_cnt[b];
     }
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter_direct(
     bucket_scan(s_cnt, s_off, NB, s_tmp);
     __syncthreads();
     for (int b = threadIdx.x; b < NB; b += kBlock) {
-        const int64_t mi = (int64_t)b * out.stride + c;
+        const int64_t mi = (int64_t)c * NB + b;
         out.moff[mi] = P0 + s_off[b];
         out.mcnt[mi] = s_cnt[b];
         s_cnt[b] = 0;  // becomes the write cursor
@@ -256,8 +257,10 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
         for (int w = threadIdx.x; w < (R + 31) / 32; w += kAccThreads) touched[w] = 0u;
     int64_t nch = nch_fixed;
     if (nch < 0) nch = ceil_div((int64_t)nnz_x + excl[nnz_x], kCscTile);  // one chunk per merge tile
-    const int32_t* mo = moff + (int64_t)b * stride;
-    const int32_t* mc = mcnt + (int64_t)b * stride;
+    // the tables are chunk-major (row c holds the chunk's NB groups): this
+    // bucket's entries sit NB apart
+    const int NB = (int)gridDim.x;
+    (void)stride;
     constexpr int kPer = kAccWin / kAccThreads;
     for (int64_t w0 = 0; w0 < nch; w0 += kAccWin) {
         const int wn = (int)std::min<int64_t>(kAccWin, nch - w0);
@@ -266,8 +269,8 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int c = threadIdx.x * kPer + i;
-            cnt[i] = c < wn ? mc[w0 + c] : 0;
-            if (c < wn) s_off[c] = mo[w0 + c];
+            cnt[i] = c < wn ? mcnt[(w0 + c) * NB + b] : 0;
+            if (c < wn) s_off[c] = moff[(w0 + c) * NB + b];
             sum += cnt[i];
         }
         // workgroup-wide exclusive scan of the per-thread sums

@@ -11,7 +11,8 @@ summaries read the rocpd databases rocprofv3 writes (`*_results.db`).
   python -m paper_2006_16767_amd.prof batch [--B 512] [--reps R]
       run_batch on the 512-vector R-MAT 2^18 (degree 32) batch.
   python -m paper_2006_16767_amd.prof fc [--reps R]
-      the pruned FC layer 16384 x 4096: fused forward, dX and dvals.
+      the pruned FC layer 16384 x 4096: fused forward, then dX and dvals
+      in one backward call.
   python -m paper_2006_16767_amd.prof copy [--mib M] [--reps R]
       a plain device-to-device copy of M MiB, R times (counter calibration:
       it reads and writes exactly M MiB).
@@ -175,12 +176,9 @@ def cmd_fc(args):
     X = torch.as_tensor(Xh, device="cuda")
     G = torch.as_tensor(synth.cfg5_upstream(), device="cuda")
     Y = M.out_tensor(64)
-    dX = torch.empty_like(X)
-    dv = torch.empty(A.nnz, dtype=torch.float32, device="cuda")
     for _ in range(args.reps + 1):
         M.spmv_batch(X, Y)
-        M.transpose_matvec(G, dX)
-        M.dvals(G, X, dv)
+        M.backward(G, X)  # dX and dvals from one B-minor copy of G
     torch.cuda.synchronize()
     print(f"[prof] FC layer 16384 x 4096: {args.reps + 1} forward + backward passes done", flush=True)
 

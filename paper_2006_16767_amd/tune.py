@@ -206,18 +206,26 @@ def _time_plans(M, x, y, plans, reps):
     return times
 
 
-def driver_sweep(out_path: str, reps: int = 5):
+DRIVER_GRAPHS = {
+    "rmat20_d16": lambda synth: synth.cfg2_matrix(),
+    "rmat19_d16": lambda synth: synth.rmat(19, 16, 27),
+    "rmat18_d32": lambda synth: synth.rmat(18, 32, 23),
+}
+
+
+def driver_sweep(out_path: str, reps: int = 5, graph: str = "rmat20_d16"):
     """Every candidate plan timed on the vectors the graph drivers produce
-    on the R-MAT 2^20 graph (the setting of the paper's misprediction
-    study, Section 6): the frontier of every BFS level (BOOL, from the
-    lowest vertex with an out-edge) and the x of every incremental PageRank
-    round (FP32, d = 0.85, eps = 1e-3 (1 - d) / n; round k's x is taken
-    from the residual after k products). One record per vector, as the
-    sweep writes them, with support "bfs" or "pagerank" and the plan the
-    driver ran."""
+    on an R-MAT graph (R-MAT 2^20 by default, the setting of the paper's
+    misprediction study, Section 6): the frontier of every BFS level (BOOL,
+    from the lowest vertex with an out-edge) and the x of every incremental
+    PageRank round (FP32, d = 0.85, eps = 1e-3 (1 - d) / n; round k's x is
+    taken from the residual after k products). One record per vector, as
+    the sweep writes them, with support "bfs" or "pagerank" and the plan the
+    driver ran. Other graphs give driver vectors to train on that the
+    R-MAT 2^20 evaluation does not contain."""
     import torch
     from . import BOOL, Matrix, all_plans, synth
-    A = synth.cfg2_matrix()
+    A = DRIVER_GRAPHS[graph](synth)
     plans = all_plans()
     dev = lambda a: torch.as_tensor(a, device="cuda")  # noqa: E731
     with open(out_path, "w") as fout:
@@ -231,7 +239,7 @@ def driver_sweep(out_path: str, reps: int = 5):
         for L in range(M.bfs_levels):
             idx = np.nonzero(lv == L)[0].astype(np.int32)
             x = (dev(idx), None)
-            rec = {"key": f"rmat20_d16:bfs:{L}", "matrix": "rmat20_d16", "support": "bfs",
+            rec = {"key": f"{graph}:bfs:{L}", "matrix": graph, "support": "bfs",
                    "features": {**mf, **M.vector_features(x)}, "times_ms": _time_plans(M, x, y, plans, reps),
                    "driver_plan": repr(used[L]) if L < len(used) else None}
             fout.write(json.dumps(rec) + "\n")
@@ -251,7 +259,7 @@ def driver_sweep(out_path: str, reps: int = 5):
             prop = (r.abs() > eps) & (W > 0)
             idx = torch.nonzero(prop).flatten().to(torch.int32)
             x = (idx, (r[idx.long()] / W[idx.long()]).contiguous())
-            rec = {"key": f"rmat20_d16:pagerank:{k}", "matrix": "rmat20_d16", "support": "pagerank",
+            rec = {"key": f"{graph}:pagerank:{k}", "matrix": graph, "support": "pagerank",
                    "features": {**mf, **M.vector_features(x)}, "times_ms": _time_plans(M, x, y, plans, reps),
                    "driver_plan": repr(used[k])}
             fout.write(json.dumps(rec) + "\n")
@@ -261,7 +269,8 @@ def driver_sweep(out_path: str, reps: int = 5):
 
 # ----------------------------------------------------------------------------- storage format
 FORMAT_FEATURES = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini",
-                   "padding")
+                   "padding", "ell_padding")
+FORMATS = ("csr", "sell", "ell")
 SELL_SIGMA = 4096  # rows per sorting window of the sliced copy
 
 
@@ -284,8 +293,9 @@ def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
     """Training data of the storage-format pre-selector: on every corpus
     matrix, the SpMV of a dense x (FP32, or FP64 to check the tree on the
     other precision) by the fastest SpMV plan of a CSR handle against the
-    sliced ELLPACK copy of a handle forced to keep it (null when the matrix
-    is too skewed for it). One record per matrix."""
+    sliced ELLPACK and the ELLPACK copies of handles forced to keep them
+    (null when the matrix is too skewed for a copy). One record per
+    matrix."""
     import torch
     from . import F32, F64, Matrix, SpxError, plan
     code, tdt = (F64, torch.float64) if dtype == "f64" else (F32, torch.float32)
@@ -299,49 +309,72 @@ def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
             feats = Mc.features()
             tc = _time_plans(Mc, x, y, csr_plans, reps)
             Mc.close()
-            rec = {"matrix": name, "features": dict(feats, padding=sell_padding(A)), "csr_ms": tc,
-                   "sell_ms": None}
-            try:
-                Ms = Matrix.from_host(A, dtype=code, fmt="sell")
-                rec["sell_ms"] = _time_plans(Ms, x, y, [plan("spmv", "direct")], reps)[repr(plan("spmv", "direct"))]
-                rec["features"]["padding"] = Ms.storage_format()[1]
-                Ms.close()
-            except SpxError:
-                pass
+            lens = np.diff(np.asarray(A.row_ptr, dtype=np.int64))
+            ell = float(lens.max() * A.m) / max(1, int(lens.sum())) if A.m else 1.0
+            rec = {"matrix": name, "features": dict(feats, padding=sell_padding(A), ell_padding=ell), "csr_ms": tc,
+                   "sell_ms": None, "ell_ms": None}
+            for fmt in ("sell", "ell"):
+                try:
+                    Ms = Matrix.from_host(A, dtype=code, fmt=fmt)
+                    rec[f"{fmt}_ms"] = _time_plans(Ms, x, y, [plan("spmv", "direct")], reps)[
+                        repr(plan("spmv", "direct"))]
+                    if fmt == "sell":
+                        rec["features"]["padding"] = Ms.storage_format()[1]
+                    Ms.close()
+                except SpxError:
+                    pass
             fout.write(json.dumps(rec) + "\n")
             fout.flush()
-            ts = "-" if rec["sell_ms"] is None else f"{rec['sell_ms'] * 1e3:.1f}"
-            print(f"[format] {name}: csr {min(tc.values()) * 1e3:.1f} us, sell {ts} us", flush=True)
+            ts = lambda v: "-" if v is None else f"{v * 1e3:.1f}"  # noqa: E731
+            print(f"[format] {name}: csr {min(tc.values()) * 1e3:.1f} us, sell {ts(rec['sell_ms'])} us, "
+                  f"ell {ts(rec['ell_ms'])} us", flush=True)
+
+
+def _format_times(r):
+    """(csr, sell, ell) SpMV times of a format record, inf where the copy
+    was refused or not timed."""
+    c = min(r["csr_ms"].values())
+    f = lambda k: r.get(k) if r.get(k) is not None else float("inf")  # noqa: E731
+    return [c, f("sell_ms"), f("ell_ms")]
+
+
+def _format_row(r):
+    f = dict(r["features"])
+    if "ell_padding" not in f:  # records written before the ELL candidate
+        f["ell_padding"] = f["max_row"] * f["m"] / max(1.0, f["nnz"])
+    return [f[k] for k in FORMAT_FEATURES]
 
 
 def format_train(path: str, out_path: str, max_depth: int = 3):
-    """The storage-format tree from a format sweep: class 1 (sliced
-    ELLPACK) where it ran the SpMV faster than the best CSR plan. Samples
-    are weighted by the time a wrong choice would lose (relative), and
-    the tree is grown on all records (one per matrix, too few to hold some
-    out); the report gives the time lost against always taking the faster
-    format, and the rows of the tree for the library's built-in table."""
+    """The storage-format tree from a format sweep: the class of the format
+    (0 CSR, 1 sliced ELLPACK, 2 ELLPACK) that ran the SpMV fastest. Samples
+    are weighted by the time the slowest available choice would lose
+    (relative), and the tree is grown on all records (one per matrix, too
+    few to hold some out); the report gives the time lost against always
+    taking the fastest format, and the rows of the tree for the library's
+    built-in table."""
     recs = [json.loads(l) for l in open(path) if l.strip()]
-    X, y, w, tc, ts = [], [], [], [], []
+    X, y, w, T = [], [], [], []
     for r in recs:
-        c = min(r["csr_ms"].values())
-        s_ = r["sell_ms"] if r["sell_ms"] is not None else float("inf")
-        X.append([r["features"][k] for k in FORMAT_FEATURES])
-        y.append(int(s_ < c))
-        w.append(abs(min(s_, 10 * c) - c) / min(s_, c))
-        tc.append(c)
-        ts.append(s_)
+        t = _format_times(r)
+        best = min(t)
+        worst = max(v for v in t if np.isfinite(v))
+        X.append(_format_row(r))
+        y.append(int(np.argmin(t)))
+        w.append(abs(min(worst, 10 * best) - best) / best)
+        T.append(t)
     X = np.asarray(X)
-    tree = Cart(max_depth).fit(X, np.asarray(y), np.asarray(w) + 1e-3, 2)
+    T = np.asarray(T)
+    tree = Cart(max_depth).fit(X, np.asarray(y), np.asarray(w) + 1e-3, len(FORMATS))
     pred = tree.predict(X)
-    best = sum(min(a, b) for a, b in zip(tc, ts))
-    chosen = sum(b if p_ else a for a, b, p_ in zip(tc, ts, pred))
-    csr_only = sum(tc)
+    best = float(T.min(axis=1).sum())
+    chosen = float(sum(T[i, p] if np.isfinite(T[i, p]) else T[i, 0] for i, p in enumerate(pred)))
+    csr_only = float(T[:, 0].sum())
     # library rows: feature, threshold, left, right, class (-1 = internal)
     rows = [[int(n[0]), float(n[1]), int(n[2]), int(n[3]), int(n[4])] for n in tree.nodes]
-    rep = {"records": len(recs), "sell_faster": int(sum(y)), "accuracy": float(np.mean(pred == np.asarray(y))),
-           "loss_vs_best": chosen / best - 1.0, "csr_only_loss_vs_best": csr_only / best - 1.0,
-           "features": list(FORMAT_FEATURES), "rows": rows}
+    rep = {"records": len(recs), "fastest": {f: int(sum(1 for v in y if v == i)) for i, f in enumerate(FORMATS)},
+           "accuracy": float(np.mean(pred == np.asarray(y))), "loss_vs_best": chosen / best - 1.0,
+           "csr_only_loss_vs_best": csr_only / best - 1.0, "features": list(FORMAT_FEATURES), "rows": rows}
     with open(out_path, "w") as f:
         json.dump(rep, f, indent=1)
     return rep
@@ -349,24 +382,23 @@ def format_train(path: str, out_path: str, max_depth: int = 3):
 
 def format_evaluate(path: str, tree_path: str):
     """Time lost on a format sweep by a trained format tree (the rows of
-    format_train's report), against always taking the faster format and
+    format_train's report), against always taking the fastest format and
     against CSR alone."""
     rows = json.load(open(tree_path))["rows"]
     recs = [json.loads(l) for l in open(path) if l.strip()]
     best = chosen = csr_only = 0.0
     hits = 0
     for r in recs:
-        x = [r["features"][k] for k in FORMAT_FEATURES]
+        x = _format_row(r)
         i = 0
         while rows[i][4] < 0:
             i = rows[i][2] if x[rows[i][0]] <= rows[i][1] else rows[i][3]
-        c = min(r["csr_ms"].values())
-        s_ = r["sell_ms"] if r["sell_ms"] is not None else float("inf")
-        pick = s_ if rows[i][4] == 1 else c
-        best += min(c, s_)
+        t = _format_times(r)
+        pick = t[rows[i][4]] if np.isfinite(t[rows[i][4]]) else t[0]
+        best += min(t)
         chosen += pick
-        csr_only += c
-        hits += int(pick == min(c, s_))
+        csr_only += t[0]
+        hits += int(pick == min(t))
     return {"records": len(recs), "right_format": hits / len(recs), "loss_vs_best": chosen / best - 1.0,
             "csr_only_loss_vs_best": csr_only / best - 1.0}
 
@@ -685,191 +717,135 @@ def train(paths, out_path, all_features=False, seed=0):
 
 
 # ----------------------------------------------------------------------------- lazy trees
-class TimeCart:
-    """Decision tree grown on per-class times instead of labels, with a
-    price on the count features (the lazy evaluation of Section 6.3).
-
-    T[i, c] is the time of class c on sample i relative to that sample's
-    fastest plan (so every sample weighs the same); a leaf takes the class
-    with the least summed time. sync[i] is the cost, on the same scale, of
-    the device count and stream synchronization that nnz_s needs: a split
-    on a count feature charges it once to every sample at the node that has
-    not paid it on its path (paid[i]), and is taken only where the time it
-    saves exceeds that. Cheap splits therefore come first and the count is
-    asked for only in the regions of the feature space where it pays."""
-
-    def __init__(self, max_depth: int, min_leaf: int = 1):
-        self.max_depth = max_depth
-        self.min_leaf = min_leaf
-        self.nodes = []  # [feature, threshold, left, right, class]
-
-    def fit(self, X, T, sync, paid, costly):
-        X = np.asarray(X, np.float64)
-        T = np.asarray(T, np.float64)
-        self.costly = set(int(c) for c in costly)
-        self.nodes = []
-        self._grow(X, T, np.asarray(sync, np.float64), np.asarray(paid, bool), 0)
-        return self
-
-    def _leaf(self, T):
-        self.nodes.append([0, 0.0, 0, 0, int(np.argmin(T.sum(0)))])
-        return len(self.nodes) - 1
-
-    def _grow(self, X, T, sync, paid, depth):
-        n = len(T)
-        tot = T.sum(0)
-        loss = tot.min()
-        if depth >= self.max_depth or n < 2 * self.min_leaf:
-            return self._leaf(T)
-        unpaid = float(sync[~paid].sum())
-        best = None
-        for f in range(X.shape[1]):
-            order = np.argsort(X[:, f], kind="stable")
-            xs = X[order, f]
-            cum = np.cumsum(T[order], axis=0)[:-1]
-            split_loss = cum.min(1) + (tot[None, :] - cum).min(1)
-            k = np.arange(1, n)
-            valid = (xs[1:] > xs[:-1]) & (k >= self.min_leaf) & (n - k >= self.min_leaf)
-            if not valid.any():
-                continue
-            gain = loss - split_loss - (unpaid if f in self.costly else 0.0)
-            gain[~valid] = -np.inf
-            i = int(np.argmax(gain))
-            if best is None or gain[i] > best[0]:
-                best = (gain[i], f, 0.5 * (xs[i] + xs[i + 1]))
-        if best is None or best[0] <= 1e-9 * n:
-            return self._leaf(T)
-        _, f, thr = best
-        if f in self.costly:
-            paid = np.ones(n, bool)
-        me = len(self.nodes)
-        self.nodes.append([f, float(thr), -1, -1, -1])
-        mask = X[:, f] <= thr
-        l = self._grow(X[mask], T[mask], sync[mask], paid[mask], depth + 1)
-        r = self._grow(X[~mask], T[~mask], sync[~mask], paid[~mask], depth + 1)
-        self.nodes[me][2] = l
-        self.nodes[me][3] = r
-        return me
-
-    def walk(self, xrow):
-        """(class, whether the path tested a count feature)."""
-        j, asked = 0, False
-        while self.nodes[j][4] < 0:
-            f, thr, l, r, _ = self.nodes[j]
-            asked |= f in self.costly
-            j = l if xrow[f] <= thr else r
-        return int(self.nodes[j][4]), asked
+def _tree_leaves(nodes):
+    return [i for i, n in enumerate(nodes) if int(n[4]) >= 0]
 
 
-def _rel_times(rows, factor, pat_of=None, dist_of=None):
-    """Per-class times of one factor relative to each record's fastest plan
-    (the factors decided before it fixed by pat_of / dist_of, the ones after
-    it at their best); a class with no timing costs 4x the best."""
-    out = np.empty((len(rows), {"pattern": 3, "distribution": 2, "writeback": len(WBS)}[factor]))
-    for i, (_, lab) in enumerate(rows):
-        t, best = lab["times"], lab["best_ms"]
-        if factor == "pattern":
-            v = [min((ms for (p, d, w), ms in t.items() if p == c), default=np.inf) for c in PATTERNS]
-        elif factor == "distribution":
-            pat = PATTERNS[pat_of[i]]
-            v = [min((ms for (p, d, w), ms in t.items() if p == pat and d == c), default=np.inf) for c in DISTS]
-        else:
-            dist = DISTS[dist_of[i]]
-            v = [t.get(("csc_spmspv", dist, c), np.inf) for c in WBS]
-        v = np.asarray(v, np.float64) / best
-        out[i] = np.where(np.isfinite(v), v, 4.0)
+def _splice(host_nodes, count_nodes, ask):
+    """host_nodes with every leaf in `ask` replaced by a copy of count_nodes
+    (rows: feature, threshold, left, right, class; node 0 is the root)."""
+    out = [list(n) for n in host_nodes]
+    for leaf in sorted(ask):
+        base = len(out)
+        for n in count_nodes:
+            n = list(n)
+            if int(n[4]) < 0:
+                n[2] = int(n[2]) + base
+                n[3] = int(n[3]) + base
+            out.append(n)
+        # the leaf becomes the copy's root
+        out[leaf] = list(out[base])
+        out[base] = [0, 0.0, 0, 0, 0]  # unreachable placeholder (keeps indices)
     return out
 
 
-def _fit_time_tree(X, T, sync, paid, costly, seed):
-    """Depth 1..10 by 3-fold cross-validation on the mean relative time
-    (plan time plus any count the path asks for); then fit on all rows."""
-    rng = np.random.default_rng(seed)
-    folds = np.array_split(rng.permutation(len(T)), 3)
-    best = None
-    for depth in range(1, 11):
-        for min_leaf in (1, 4):
-            sc = []
-            for k in range(3):
-                te = folds[k]
-                tr = np.concatenate([folds[j] for j in range(3) if j != k])
-                t = TimeCart(depth, min_leaf).fit(X[tr], T[tr], sync[tr], paid[tr], costly)
-                tot = 0.0
-                for i in te:
-                    c, asked = t.walk(X[i])
-                    tot += T[i, c] + (sync[i] if asked and not paid[i] else 0.0)
-                sc.append(tot / len(te))
-            m = float(np.mean(sc))
-            if best is None or m < best[0] - 1e-9:
-                best = (m, depth, min_leaf)
-    return TimeCart(best[1], best[2]).fit(X, T, sync, paid, costly), best
+def _gate(host_nodes, count_nodes, ask):
+    """Tree that reads the counts for free once an earlier tree asked for
+    them: counted > 0.5 -> count_nodes, else host_nodes with the ask leaves
+    spliced."""
+    h = _splice(host_nodes, count_nodes, ask)
+    out = [["counted", 0.5, 1, 1 + len(h), -1]]
+    for n in h:
+        n = list(n)
+        if int(n[4]) < 0:
+            n[2] = int(n[2]) + 1
+            n[3] = int(n[3]) + 1
+        out.append(n)
+    base = len(out)
+    for n in count_nodes:
+        n = list(n)
+        if int(n[4]) < 0:
+            n[2] = int(n[2]) + base
+            n[3] = int(n[3]) + base
+        out.append(n)
+    return out
 
 
-def train_lazy(paths, out_path, sync_us: float, seed=0):
-    """Trees for run() that may ask for nnz_s: every Table 1 feature plus
-    s_per_x is available, but a path through a count feature pays sync_us
-    (the measured cost of the device count and stream synchronization in a
-    pipelined run() loop) on each vector that takes it. Cascade as in
-    train(): pattern, then the distribution of that pattern, then the
-    column-major write-back; a vector that paid in an earlier tree reads
-    the counts for free in the later ones. 7:3 split; the report gives the
-    held-out time lost against exhaustive search with the counts charged,
-    beside what the vectors would lose with no count at all."""
+def lazy_selector(host_sel, count_sel, ask):
+    """ask: {"pattern": leaves, "spmv"/"csr_spmspv"/"csc_spmspv": leaves of that
+    distribution tree, "writeback": leaves} of the host trees at which the
+    walk asks for the counts and continues on the count trees."""
+    return {"format": "spx-selector-v1", "lazy": True,
+            "pattern": {"nodes": _splice(host_sel["pattern"]["nodes"], count_sel["pattern"]["nodes"],
+                                         ask.get("pattern", ()))},
+            "distribution": {p: {"nodes": _gate(host_sel["distribution"][p]["nodes"],
+                                                count_sel["distribution"][p]["nodes"], ask.get(p, ()))}
+                             for p in PATTERNS},
+            "writeback": {"nodes": _gate(host_sel["writeback"]["nodes"], count_sel["writeback"]["nodes"],
+                                         ask.get("writeback", ()))}}
+
+
+def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0):
+    """Trees for run() that ask for nnz_s only where that pays (Section 6.3:
+    features evaluated lazily, cheap rules first). Starting from the
+    host-feature trees, leaves of the cascade are switched one at a time to
+    "ask for the counts and continue on the trees that read them" while
+    that lowers the total time of the training vectors (over the total of
+    their fastest plans), sync_us (the measured cost of the device count in
+    a pipelined run() loop) charged to every vector whose walk asks. Once a
+    vector has asked, the later trees of its cascade read the counts for
+    free (the "counted" feature). 7:3 split; the report gives the held-out
+    loss of the host trees, of the count trees with the count charged on
+    every vector, and of the lazy trees."""
     recs = []
     for p in paths:
         with open(p) as f:
             recs += [json.loads(l) for l in f if l.strip()]
     rows = [(r, lab) for r in recs for lab in [labels(r)] if lab is not None]
-    X = np.array([_feature_row(r) for r, _ in rows], np.float64)
-    best_ms = np.array([lab["best_ms"] for _, lab in rows])
-    sync = (sync_us * 1e-3) / best_ms
-    costly = [FEATURES.index(f) for f in COUNT_FEATURES]
+    host = json.load(open(host_path))
+    cnt = json.load(open(count_path))
     rng = np.random.default_rng(seed)
     perm = rng.permutation(len(rows))
     ntr = int(round(0.7 * len(rows)))
     tr, te = perm[:ntr], perm[ntr:]
+    X = [_feature_row(r) for r, _ in rows]
+
+    def cost(sel, idx):
+        # total time over the total of the fastest plans: what a caller
+        # running these vectors waits, the counts included
+        tot = best = 0.0
+        for i in idx:
+            _, lab = rows[i]
+            pat, dist, wb, asked = _walk_cascade(sel, X[i])
+            t = lab["times"].get((PATTERNS[pat], DISTS[dist], WBS[wb]), 2 * lab["best_ms"])
+            tot += t + (sync_us * 1e-3 if asked else 0.0)
+            best += lab["best_ms"]
+        return tot / max(best, 1e-30)
+
+    cands = [("pattern", l) for l in _tree_leaves(host["pattern"]["nodes"])]
+    for p in PATTERNS:
+        cands += [(p, l) for l in _tree_leaves(host["distribution"][p]["nodes"])]
+    cands += [("writeback", l) for l in _tree_leaves(host["writeback"]["nodes"])]
+    ask = {}
+    cur = cost(lazy_selector(host, cnt, ask), tr)
+    start = cur
+    while True:
+        best = None
+        for tree, leaf in cands:
+            if leaf in ask.get(tree, ()):
+                continue
+            trial = {k: set(v) for k, v in ask.items()}
+            trial.setdefault(tree, set()).add(leaf)
+            c = cost(lazy_selector(host, cnt, trial), tr)
+            if c < cur - 1e-6 and (best is None or c < best[0]):
+                best = (c, tree, leaf)
+        if best is None:
+            break
+        cur = best[0]
+        ask.setdefault(best[1], set()).add(best[2])
+        print(f"[lazy] ask at {best[1]} leaf {best[2]}: train time over the best {cur:.4f}", flush=True)
+    sel = lazy_selector(host, cnt, ask)
+    sel["source"] = f"lazy counts over {os.path.basename(host_path)} and {os.path.basename(count_path)}"
+    sel["sync_us"] = sync_us
+    sel["ask"] = {k: sorted(v) for k, v in ask.items()}
     report = {"records": len(rows), "train": int(len(tr)), "test": int(len(te)), "sync_us": sync_us,
-              "features": list(FEATURES), "costly": list(COUNT_FEATURES)}
-    no_paid = np.zeros(len(rows), bool)
-    Tp = _rel_times(rows, "pattern")
-    tp, sc = _fit_time_tree(X[tr], Tp[tr], sync[tr], no_paid[tr], costly, seed)
-    report["pattern"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2], "nodes": len(tp.nodes)}
-    walks = [tp.walk(x) for x in X]
-    pat = np.array([w[0] for w in walks])
-    paid = np.array([w[1] for w in walks])
-    trees = {"pattern": tp, "distribution": {}}
-    Td = _rel_times(rows, "distribution", pat_of=pat)
-    dist = np.zeros(len(rows), np.int64)
-    for pi, pn in enumerate(PATTERNS):
-        m = pat == pi
-        mtr = tr[m[tr]]
-        if len(mtr) < 10:
-            t = TimeCart(0).fit(X[:1], Td[:1], sync[:1], paid[:1], costly)
-        else:
-            t, sc = _fit_time_tree(X[mtr], Td[mtr], sync[mtr], paid[mtr], costly, seed)
-            report[f"distribution_{pn}"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2],
-                                           "nodes": len(t.nodes)}
-        trees["distribution"][pn] = t
-        for i in np.nonzero(m)[0]:
-            c, asked = t.walk(X[i])
-            dist[i] = c
-            paid[i] |= asked
-    Tw = _rel_times(rows, "writeback", dist_of=dist)
-    Tw[:, 0] = 4.0  # "none" is not a column-major write-back
-    m = pat == 2
-    mtr = tr[m[tr]]
-    tw, sc = _fit_time_tree(X[mtr], Tw[mtr], sync[mtr], paid[mtr], costly, seed)
-    report["writeback"] = {"cv_mean_rel_time": sc[0], "max_depth": sc[1], "min_leaf": sc[2], "nodes": len(tw.nodes)}
-    trees["writeback"] = tw
-    out = {"format": "spx-selector-v1", "source": "tuned on MI355X timings (lazy counts)", "lazy": True,
-           "sync_us": sync_us, "report": report,
-           "pattern": {"nodes": tp.nodes},
-           "distribution": {pn: {"nodes": t.nodes} for pn, t in trees["distribution"].items()},
-           "writeback": {"nodes": tw.nodes}}
-    ev = evaluate_lazy(rows, out, sync_us, subset=te)
-    report["held_out"] = ev
+              "train_time_over_best": {"host": start, "lazy": cur},
+              "held_out": {"host": evaluate_lazy(rows, host, sync_us, te),
+                           "counts_always": evaluate_lazy(rows, cnt, sync_us, te),
+                           "lazy": evaluate_lazy(rows, sel, sync_us, te)}}
+    sel["report"] = report
     with open(out_path, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump(sel, f, indent=1)
     return report
 
 
@@ -880,11 +856,15 @@ def _walk_cascade(sel, x):
     def ev(nodes):
         nonlocal asked
         j = 0
-        while nodes[j][4] < 0:
+        while int(nodes[j][4]) < 0:
             f = nodes[j][0]
-            f = FEATURES.index(f) if isinstance(f, str) else int(f)
-            asked |= FEATURES[f] in COUNT_FEATURES
-            j = nodes[j][2] if x[f] <= nodes[j][1] else nodes[j][3]
+            if f == "counted" or f == len(FEATURES):  # whether an earlier tree asked
+                v = 1.0 if asked else 0.0
+            else:
+                f = FEATURES.index(f) if isinstance(f, str) else int(f)
+                asked |= FEATURES[f] in COUNT_FEATURES
+                v = x[f]
+            j = int(nodes[j][2]) if v <= nodes[j][1] else int(nodes[j][3])
         return int(nodes[j][4])
 
     pat = ev(sel["pattern"]["nodes"])
@@ -1040,6 +1020,7 @@ def main(argv=None):
     dr = sub.add_parser("drivers")
     dr.add_argument("--out", required=True)
     dr.add_argument("--reps", type=int, default=5)
+    dr.add_argument("--graph", choices=sorted(DRIVER_GRAPHS), default="rmat20_d16")
     ev = sub.add_parser("evaluate")
     ev.add_argument("data", nargs="+")
     ev.add_argument("--selectors", nargs="+", required=True)
@@ -1064,6 +1045,8 @@ def main(argv=None):
     tl.add_argument("--out", required=True)
     tl.add_argument("--sync-us", type=float, required=True,
                     help="measured cost of run()'s device count and stream synchronization")
+    tl.add_argument("--host", required=True, help="host-feature trees (JSON)")
+    tl.add_argument("--counts", required=True, help="trees that read nnz_s (JSON)")
     el = sub.add_parser("evaluate-lazy")
     el.add_argument("data", nargs="+")
     el.add_argument("--selectors", nargs="+", required=True)
@@ -1075,7 +1058,7 @@ def main(argv=None):
     t.add_argument("--all-features", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "train-lazy":
-        print(json.dumps(train_lazy(a.data, a.out, a.sync_us), indent=1))
+        print(json.dumps(train_lazy(a.data, a.out, a.host, a.counts, a.sync_us), indent=1))
         return
     if a.cmd == "evaluate-lazy":
         recs = []
@@ -1090,7 +1073,7 @@ def main(argv=None):
         print(json.dumps(rep, indent=1))
         return
     if a.cmd == "drivers":
-        driver_sweep(a.out, a.reps)
+        driver_sweep(a.out, a.reps, a.graph)
         return
     if a.cmd == "formats":
         format_sweep(a.out, a.reps, a.dtype)

@@ -146,3 +146,34 @@ def test_fused_batch_spmv_matches_oracle(kind):
             for b in range(B):
                 ref, S = oracle.spmv(A, X[b].astype(np.float64))
                 assert_close(Y[b], ref, S, kind, f"{m}x{n} B={B} b={b}")
+
+
+@pytest.mark.parametrize("B", [1, 7, 64, 130])
+def test_fused_backward_matches_separate_calls_and_oracle(B):
+    """spx_backward (one B-minor copy of G for both gradients) gives the same
+    bits as spmv_csr_transpose and dvals_pattern called apart, matches the
+    oracle's gradient, and skips either gradient on request; B past 64 runs
+    the gather in chunks of 64 batch rows, with a ragged last chunk."""
+    torch = _torch()
+    A = synth.bernoulli(700, 301, 0.04, 31, std=1.0, dtype=np.float32)
+    M = spx.Matrix.from_host(A)
+    rng = np.random.default_rng(B)
+    G = torch.as_tensor(rng.standard_normal((B, A.m)).astype(np.float32), device="cuda")
+    X = torch.as_tensor(_relu_batch(A.n, B, B + 1, np.float32), device="cuda")
+    dX, dv = M.backward(G, X)
+    dX2 = M.transpose_matvec(G)
+    dv2 = M.dvals(G, X)
+    only_dx, none_dv = M.backward(G, want_dvals=False)
+    none_dx, only_dv = M.backward(G, X, want_dx=False)
+    torch.cuda.synchronize()
+    assert none_dv is None and none_dx is None
+    for a, b in ((dX, dX2), (dv, dv2), (dX, only_dx), (dv, only_dv)):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+    dX_ref, S_dx, dv_ref = oracle.grad(A, G.cpu().numpy(), X.cpu().numpy())
+    got = dX.cpu().numpy()
+    for b in range(B):
+        assert_close(got[b], dX_ref[b], S_dx[b], "f32", f"dX row {b}")
+    # dvals: B products per entry, each bounded by |g| |x|
+    S_dv = oracle.grad(A.with_vals(np.ones(A.nnz)), np.abs(G.cpu().numpy()), np.abs(X.cpu().numpy()),
+                       want_dx=False)[2]
+    assert_close(dv.cpu().numpy(), dv_ref, S_dv, "f32", "dvals")

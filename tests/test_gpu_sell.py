@@ -1,5 +1,5 @@
-"""Sliced ELLPACK copy (the storage-format pre-selection): every SpMV plan
-on a handle that keeps the copy runs on it. Parity with the oracle's SpMV
+"""Sliced ELLPACK and ELLPACK copies (the storage-format pre-selection):
+every SpMV plan on a handle that keeps a copy runs on it. Parity with the oracle's SpMV
 for every dtype, dense and sparse x, ragged shapes (m not a multiple of the
 64-row slice, empty rows, a row much longer than its slice neighbours), the
 renumbered copy, a value refresh, and the refusal of a too-skewed matrix."""
@@ -144,11 +144,13 @@ def test_padding_ratio_matches_the_layout_definition():
 
 
 def test_auto_format_follows_the_tree():
-    """Even rows over more than 40960 rows (and n up to about 1.5M) get the
-    sliced copy by default; short or skewed matrices stay in CSR."""
+    """Nearly equal rows: 24576 to 98304 rows get the sliced copy, more rows
+    the ELL copy up to 15.7M entries (the stencils) and the sliced copy
+    beyond; small or uneven matrices stay in CSR."""
     _torch()
     assert spx.Matrix.from_host(synth.uniform_rows(65536, 65536, 8, 11)).storage_format()[0] == "sell"
-    assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "sell"
+    assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "ell"
+    assert spx.Matrix.from_host(cfg_matrix("cfg3")).storage_format()[0] == "ell"
     assert spx.Matrix.from_host(cfg_matrix("cfg1")).storage_format()[0] == "csr"
     assert spx.Matrix.from_host(cfg_matrix("rmat16")).storage_format()[0] == "csr"
 
@@ -171,3 +173,86 @@ def test_sell_full_size_uniform_rows():
                    spx.plan("spmv", "balanced"))
     torch.cuda.synchronize()
     assert_close(y.cpu().numpy(), ref, S, "f32", "uniform 2^20 sparse x")
+
+
+# ---------------------------------------------------------------- ELLPACK copy
+@pytest.mark.parametrize("kind", ["f32", "f64", "i32", "bool"])
+def test_ell_spmv_matches_oracle(kind):
+    """The ELL copy (rows padded to the longest, a thread per row): every
+    SpMV plan runs on it; ragged m, empty rows, dense and sparse x."""
+    for name, A in _matrices():
+        if name == "long_row":
+            continue  # padding to its 1000-entry row exceeds the ELL limit (refusal tested below)
+        A = _with_kind(A, kind)
+        M = spx.Matrix.from_host(A, dtype=KINDS[kind][0], fmt="ell", renumber=False)
+        fmt, ratio = M.storage_format()
+        assert fmt == "ell", (name, fmt)
+        lens = np.diff(np.asarray(A.row_ptr))
+        assert ratio == pytest.approx(lens.max() * A.m / A.nnz, rel=1e-12), name
+        _run_all(M, A, kind, f"ell {name}")
+
+
+def test_ell_on_the_renumbered_copy_and_minplus():
+    torch = _torch()
+    A = synth.uniform_rows(70000, 70000, 6, 31)
+    M = spx.Matrix.from_host(A, fmt="ell", renumber=True)
+    assert M.column_order() is not None and M.storage_format()[0] == "ell"
+    _run_all(M, A, "f32", "ell renumbered")
+    B = synth.poisson3d(12, np.float32)
+    W = np.abs(np.asarray(B.vals)) + 0.5
+    Bm = B.with_vals(W.astype(np.float32))
+    Mm = spx.Matrix.from_host(Bm, dtype=spx.F32_MINPLUS, fmt="ell")
+    assert Mm.storage_format()[0] == "ell"
+    d = np.full(B.n, np.inf, np.float32)
+    d[::7] = np.random.default_rng(3).uniform(0, 4, len(d[::7])).astype(np.float32)
+    ref = oracle.minplus_spmv(Bm, d)
+    y = Mm.run_plan(torch.as_tensor(d, device="cuda"), spx.plan("spmv", "direct"))
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def test_ell_follows_values_updated():
+    torch = _torch()
+    A = synth.poisson3d(24, np.float32)
+    M = spx.Matrix.from_host(A, fmt="ell")
+    new = np.random.default_rng(18).uniform(-2, 2, A.nnz).astype(np.float32)
+    M.vals.copy_(torch.as_tensor(new, device="cuda"))
+    M.values_updated()
+    B = A.with_vals(new)
+    x = synth.dense_vector(A.n, 19)
+    ref, S = oracle.spmv(B, x.astype(np.float64))
+    y = M.run_plan(torch.as_tensor(x, device="cuda"), spx.plan("spmv", "balanced"))
+    torch.cuda.synchronize()
+    assert_close(y.cpu().numpy(), ref, S, "f32", "ell after update")
+
+
+def test_ell_refused_when_padding_too_large():
+    _torch()
+    with pytest.raises(spx.SpxError) as e:
+        spx.Matrix.from_host(cfg_matrix("rmat16"), fmt="ell")
+    assert e.value.code == -5
+    A = dict(_matrices())["long_row"]
+    with pytest.raises(spx.SpxError) as e:
+        spx.Matrix.from_host(A, fmt="ell")
+    assert e.value.code == -5
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_ell_poisson_128_full_size(dt):
+    """The 7-point Poisson matrix on 128^3 (2,097,152 rows) on the ELL copy:
+    every row of A x for x ~ N(0, 1) against the oracle, and the closed form
+    A 1 = 6 - (in-grid neighbours), exact."""
+    torch = _torch()
+    A = synth.cfg3_matrix(dt)
+    M = spx.Matrix.from_host(A, fmt="ell")
+    assert M.storage_format()[0] == "ell"
+    xd, _ = synth.cfg3_vectors(dtype=dt)
+    ref, S = oracle.spmv(A, np.asarray(xd, np.float64))
+    y = M.run_plan(torch.as_tensor(np.asarray(xd, dt), device="cuda"), spx.plan("spmv", "direct"))
+    torch.cuda.synchronize()
+    assert_close(y.cpu().numpy(), ref, S, "f32" if dt == np.float32 else "f64", "poisson 128^3 ell")
+    ones = torch.ones(A.n, dtype=torch.float32 if dt == np.float32 else torch.float64, device="cuda")
+    y1 = M.run_plan(ones, spx.plan("spmv", "direct")).cpu().numpy()
+    want = np.asarray(A.vals, np.float64)
+    want = np.add.reduceat(want, np.asarray(A.row_ptr[:-1]))
+    assert np.array_equal(y1.astype(np.float64), want)
