@@ -138,3 +138,31 @@ def test_format_train_separates_the_formats(tmp_path):
     assert rep["csr_only_loss_vs_best"] > 0
     for row in rep["rows"]:
         assert len(row) == 5 and (row[4] in (0, 1) or (row[4] == -1 and 0 <= row[0] < len(tune.FORMAT_FEATURES)))
+
+
+def test_lazy_splice_asks_only_at_chosen_leaves():
+    """Leaf splicing: a vector reaching an 'ask' leaf of the host pattern
+    tree continues on the count tree (and is charged the count); the later
+    trees read the counts for free through the 'counted' gate; vectors on
+    other leaves never ask."""
+    F = tune.FEATURES
+    nx, ns = F.index("nnz_x"), F.index("nnz_s")
+    leaf = lambda c: [0, 0.0, 0, 0, c]  # noqa: E731
+    host = {"pattern": {"nodes": [[nx, 100.0, 1, 2, -1], leaf(2), leaf(0)]},
+            "distribution": {p: {"nodes": [leaf(0)]} for p in tune.PATTERNS},
+            "writeback": {"nodes": [leaf(1)]}}
+    cnt = {"pattern": {"nodes": [[ns, 1000.0, 1, 2, -1], leaf(2), leaf(1)]},
+           "distribution": {p: {"nodes": [leaf(1)]} for p in tune.PATTERNS},
+           "writeback": {"nodes": [[ns, 5.0, 1, 2, -1], leaf(4), leaf(2)]}}
+    sel = tune.lazy_selector(host, cnt, {"pattern": {1}})
+    row = lambda a, b: [1.0] * 9 + [a, a / 1e4, b, b / 1e6, b / max(1.0, a)]  # noqa: E731
+    # nnz_x <= 100 -> asks; nnz_s decides pattern; dist/wb from the count trees (counted)
+    assert tune._walk_cascade(sel, row(50, 500)) == (2, 1, 2, True)
+    assert tune._walk_cascade(sel, row(50, 3)) == (2, 1, 4, True)
+    assert tune._walk_cascade(sel, row(50, 5000)) == (1, 1, 0, True)
+    # nnz_x > 100 -> host leaf, no count, host distribution (and no write-back for SpMV)
+    assert tune._walk_cascade(sel, row(500, 5000)) == (0, 0, 0, False)
+    # asking at a write-back leaf only: the host pattern, then the count tree at the leaf
+    sel2 = tune.lazy_selector(host, cnt, {"writeback": {0}})
+    assert tune._walk_cascade(sel2, row(50, 3)) == (2, 0, 4, True)
+    assert tune._walk_cascade(sel2, row(500, 3)) == (0, 0, 0, False)
