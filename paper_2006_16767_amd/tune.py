@@ -403,15 +403,19 @@ def format_evaluate(path: str, tree_path: str):
             "csr_only_loss_vs_best": csr_only / best - 1.0}
 
 
-def evaluate(paths, selector_paths):
+def evaluate(paths, selector_paths, kinds=None):
     """Accuracy and time loss of saved selectors on timed records (the
     misprediction study): per selector and support kind, the share of
     vectors whose predicted plan is within 2 % of the fastest, the share
-    with the right pattern, and the total and mean time over the best."""
+    with the right pattern, and the total and mean time over the best.
+    kinds: the support kinds to keep (the BFS levels are timed in the BOOL
+    semiring, the PageRank rounds in FP32)."""
     recs = []
     for p in paths:
         with open(p) as f:
             recs += [json.loads(l) for l in f if l.strip()]
+    if kinds:
+        recs = [r for r in recs if r.get("support", "uniform") in kinds]
     out = {}
     for sp in selector_paths:
         with open(sp) as f:
@@ -775,22 +779,49 @@ def lazy_selector(host_sel, count_sel, ask):
                                          ask.get("writeback", ()))}}
 
 
-def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0):
+def _lazy_leaves(sel):
+    """(tree, leaf index, number of classes) of every leaf of a selector."""
+    out = [("pattern", i, len(PATTERNS)) for i in _tree_leaves(sel["pattern"]["nodes"])]
+    for p in PATTERNS:
+        out += [(p, i, len(DISTS)) for i in _tree_leaves(sel["distribution"][p]["nodes"])]
+    out += [("writeback", i, len(WBS)) for i in _tree_leaves(sel["writeback"]["nodes"])]
+    return out
+
+
+def _tree_nodes(sel, tree):
+    if tree == "pattern" or tree == "writeback":
+        return sel[tree]["nodes"]
+    return sel["distribution"][tree]["nodes"]
+
+
+def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0, give_back=0.02, kinds=None):
     """Trees for run() that ask for nnz_s only where that pays (Section 6.3:
     features evaluated lazily, cheap rules first). Starting from the
     host-feature trees, leaves of the cascade are switched one at a time to
     "ask for the counts and continue on the trees that read them" while
-    that lowers the total time of the training vectors (over the total of
-    their fastest plans), sync_us (the measured cost of the device count in
-    a pipelined run() loop) charged to every vector whose walk asks. Once a
-    vector has asked, the later trees of its cascade read the counts for
-    free (the "counted" feature). 7:3 split; the report gives the held-out
-    loss of the host trees, of the count trees with the count charged on
-    every vector, and of the lazy trees."""
+    that lowers the training time; then every leaf of the resulting
+    cascade takes the class that lowers it most (cost-sensitive leaf
+    labels: the host trees were grown for accuracy, and a leaf that holds
+    vectors the host features cannot tell apart, such as hub and uniform
+    supports of one size, should hold the plan that is fastest over all of
+    them). sync_us (the measured cost of the device count in a pipelined
+    run() loop) is charged to every vector whose walk asks; once a vector
+    has asked, the later trees of its cascade read the counts for free (the
+    "counted" feature). The training time is the mean over support kinds of
+    (total time / total of the fastest plans), so that no kind outweighs
+    the others by its number of vectors, and a change is taken only while
+    the uniform supports lose at most give_back more than under the host
+    trees. kinds: the support kinds to keep (the driver files hold BFS
+    levels timed in the BOOL semiring and PageRank rounds in FP32). 7:3
+    split; the report gives the held-out loss of the host trees, of the
+    count trees with the count charged on every vector, and of the lazy
+    trees."""
     recs = []
     for p in paths:
         with open(p) as f:
             recs += [json.loads(l) for l in f if l.strip()]
+    if kinds:
+        recs = [r for r in recs if r.get("support", "uniform") in kinds]
     rows = [(r, lab) for r in recs for lab in [labels(r)] if lab is not None]
     host = json.load(open(host_path))
     cnt = json.load(open(count_path))
@@ -799,25 +830,31 @@ def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0):
     ntr = int(round(0.7 * len(rows)))
     tr, te = perm[:ntr], perm[ntr:]
     X = [_feature_row(r) for r, _ in rows]
+    kind = [r.get("support", "uniform") for r, _ in rows]
 
-    def cost(sel, idx):
-        # total time over the total of the fastest plans: what a caller
-        # running these vectors waits, the counts included
-        tot = best = 0.0
+    def per_kind(sel, idx):
+        tot, best = {}, {}
         for i in idx:
             _, lab = rows[i]
             pat, dist, wb, asked = _walk_cascade(sel, X[i])
             t = lab["times"].get((PATTERNS[pat], DISTS[dist], WBS[wb]), 2 * lab["best_ms"])
-            tot += t + (sync_us * 1e-3 if asked else 0.0)
-            best += lab["best_ms"]
-        return tot / max(best, 1e-30)
+            k = kind[i]
+            tot[k] = tot.get(k, 0.0) + t + (sync_us * 1e-3 if asked else 0.0)
+            best[k] = best.get(k, 0.0) + lab["best_ms"]
+        return {k: tot[k] / max(best[k], 1e-30) for k in tot}
 
-    cands = [("pattern", l) for l in _tree_leaves(host["pattern"]["nodes"])]
-    for p in PATTERNS:
-        cands += [(p, l) for l in _tree_leaves(host["distribution"][p]["nodes"])]
-    cands += [("writeback", l) for l in _tree_leaves(host["writeback"]["nodes"])]
+    base = per_kind(host, tr)
+    cap = base.get("uniform", np.inf) + give_back
+
+    def cost(sel):
+        r = per_kind(sel, tr)
+        if r.get("uniform", 0.0) > cap:
+            return np.inf
+        return float(np.mean(list(r.values())))
+
+    cands = [(t, l) for t, l, _ in _lazy_leaves(host)]
     ask = {}
-    cur = cost(lazy_selector(host, cnt, ask), tr)
+    cur = cost(lazy_selector(host, cnt, ask))
     start = cur
     while True:
         best = None
@@ -826,7 +863,7 @@ def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0):
                 continue
             trial = {k: set(v) for k, v in ask.items()}
             trial.setdefault(tree, set()).add(leaf)
-            c = cost(lazy_selector(host, cnt, trial), tr)
+            c = cost(lazy_selector(host, cnt, trial))
             if c < cur - 1e-6 and (best is None or c < best[0]):
                 best = (c, tree, leaf)
         if best is None:
@@ -835,11 +872,33 @@ def train_lazy(paths, out_path, host_path, count_path, sync_us: float, seed=0):
         ask.setdefault(best[1], set()).add(best[2])
         print(f"[lazy] ask at {best[1]} leaf {best[2]}: train time over the best {cur:.4f}", flush=True)
     sel = lazy_selector(host, cnt, ask)
+    after_ask = cur
+    relabeled = 0
+    for _ in range(3):
+        changed = False
+        for tree, leaf, k in _lazy_leaves(sel):
+            nodes = _tree_nodes(sel, tree)
+            keep = int(nodes[leaf][4])
+            for c in range(k):
+                if c == keep:
+                    continue
+                nodes[leaf][4] = c
+                v = cost(sel)
+                if v < cur - 1e-6:
+                    cur, keep, changed = v, c, True
+                    relabeled += 1
+            nodes[leaf][4] = keep
+        if not changed:
+            break
+    print(f"[lazy] {relabeled} leaf labels changed: train time over the best {cur:.4f}", flush=True)
     sel["source"] = f"lazy counts over {os.path.basename(host_path)} and {os.path.basename(count_path)}"
     sel["sync_us"] = sync_us
     sel["ask"] = {k: sorted(v) for k, v in ask.items()}
     report = {"records": len(rows), "train": int(len(tr)), "test": int(len(te)), "sync_us": sync_us,
-              "train_time_over_best": {"host": start, "lazy": cur},
+              "give_back": give_back,
+              "train_time_over_best": {"host": start, "asks": after_ask, "lazy": cur,
+                                       "per_kind": per_kind(sel, tr), "per_kind_host": base},
+              "leaf_labels_changed": relabeled,
               "held_out": {"host": evaluate_lazy(rows, host, sync_us, te),
                            "counts_always": evaluate_lazy(rows, cnt, sync_us, te),
                            "lazy": evaluate_lazy(rows, sel, sync_us, te)}}
@@ -1025,6 +1084,7 @@ def main(argv=None):
     ev.add_argument("data", nargs="+")
     ev.add_argument("--selectors", nargs="+", required=True)
     ev.add_argument("--out")
+    ev.add_argument("--kinds", default="", help="support kinds to keep, comma-separated (default: all)")
     st = sub.add_parser("study")
     st.add_argument("data", nargs="+")
     st.add_argument("--out", required=True)
@@ -1047,6 +1107,9 @@ def main(argv=None):
                     help="measured cost of run()'s device count and stream synchronization")
     tl.add_argument("--host", required=True, help="host-feature trees (JSON)")
     tl.add_argument("--counts", required=True, help="trees that read nnz_s (JSON)")
+    tl.add_argument("--give-back", type=float, default=0.02,
+                    help="largest loss over the host trees allowed on uniform supports")
+    tl.add_argument("--kinds", default="", help="support kinds to keep, comma-separated (default: all)")
     el = sub.add_parser("evaluate-lazy")
     el.add_argument("data", nargs="+")
     el.add_argument("--selectors", nargs="+", required=True)
@@ -1058,7 +1121,9 @@ def main(argv=None):
     t.add_argument("--all-features", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "train-lazy":
-        print(json.dumps(train_lazy(a.data, a.out, a.host, a.counts, a.sync_us), indent=1))
+        kinds = tuple(k for k in a.kinds.split(",") if k) or None
+        print(json.dumps(train_lazy(a.data, a.out, a.host, a.counts, a.sync_us, give_back=a.give_back, kinds=kinds),
+                         indent=1))
         return
     if a.cmd == "evaluate-lazy":
         recs = []
@@ -1085,7 +1150,7 @@ def main(argv=None):
         print(json.dumps(format_train(a.data, a.out), indent=1))
         return
     if a.cmd == "evaluate":
-        rep = evaluate(a.data, a.selectors)
+        rep = evaluate(a.data, a.selectors, tuple(k for k in a.kinds.split(",") if k) or None)
         if a.out:
             with open(a.out, "w") as f:
                 json.dump(rep, f, indent=1)

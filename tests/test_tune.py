@@ -87,6 +87,18 @@ def test_train_writes_a_selector_the_library_loads(tmp_path):
     bad.write_text('{"pattern": {"nodes": [[99, 0, 1, 2, -1]]}}')
     assert lib.spx_load_selector(None, str(bad).encode()) == -1
     assert lib.spx_load_selector(None, None) == 0  # back to the built-in trees
+    _restore_shipped(lib)
+
+
+def _restore_shipped(lib):
+    """The package's default trees, as the binding loads them, so that
+    later tests in the process see the usual defaults."""
+    import os
+    pkg = os.path.dirname(tune.__file__)
+    for name in ("selector_mi355x.json", "selector_mi355x_nnz_s.json", "selector_mi355x_lazy.json"):
+        path = os.path.join(pkg, name)
+        if os.path.exists(path):
+            assert lib.spx_load_selector(None, path.encode()) == 0, lib.spx_last_error()
 
 
 def _csr_rows(lens):
@@ -166,3 +178,21 @@ def test_lazy_splice_asks_only_at_chosen_leaves():
     sel2 = tune.lazy_selector(host, cnt, {"writeback": {0}})
     assert tune._walk_cascade(sel2, row(50, 3)) == (2, 0, 4, True)
     assert tune._walk_cascade(sel2, row(500, 3)) == (0, 0, 0, False)
+
+
+def test_shipped_selectors_load():
+    """Every tree file the package ships parses in the library (host only:
+    with no handle the trees become the defaults), the lazy trees with
+    their "counted" gate nodes included."""
+    import glob
+    import os
+    lib = _lib.load()
+    pkg = os.path.dirname(tune.__file__)
+    files = sorted(glob.glob(os.path.join(pkg, "selector_mi355x*.json")))
+    assert any(f.endswith("_lazy.json") for f in files)
+    try:
+        for f in files:
+            assert lib.spx_load_selector(None, f.encode()) == 0, (f, lib.spx_last_error())
+    finally:
+        assert lib.spx_load_selector(None, None) == 0
+        _restore_shipped(lib)
