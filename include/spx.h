@@ -247,28 +247,34 @@ size_t spmspv_csc_noalloc_capacity(void);
  *
  * Storage-format pre-selection (Section 8's extension: pick the matrix
  * format per matrix, before the kernel): besides CSR the handle can keep
- * either a sliced ELLPACK copy (SELL-C-sigma: slices of 64 rows, one wave
- * per slice and a lane per row, rows sorted by descending length within
- * windows of 4096 rows, padding to the longest row of each slice) or an
- * ELLPACK copy (every row padded to the longest row of the matrix, stored
- * column-major, a thread per row, no row pointers read). When it does,
- * every plan of the SpMV pattern runs on that copy; the other patterns are
- * unchanged. By default a small decision tree over the matrix features and
- * the two padding ratios (cells / nnz; reading the sliced one copies
- * row_ptr to the host once) decides, trained on MI355X timings of the
- * three formats. SPX_FORMAT_SELL forces the sliced copy
- * (SPX_ERR_UNSUPPORTED when a row is longer than 4096 entries or the copy
- * would take more than 3 nnz + 65536 cells), SPX_FORMAT_ELL the ELL copy
- * (SPX_ERR_UNSUPPORTED beyond 4096 entries per row or 1.5 nnz + 65536
- * cells; SPX_ERR_ARG with SPX_FORMAT_SELL), SPX_FORMAT_CSR forbids both.
- * Memory: 8 + value size bytes per cell (4 more per row for the sliced
- * copy). */
+ * one of three copies: a sliced ELLPACK copy (SELL-C-sigma: slices of 64
+ * rows, one wave per slice and a lane per row, rows sorted by descending
+ * length within windows of 4096 rows, padding to the longest row of each
+ * slice), an ELLPACK copy (every row padded to the longest row of the
+ * matrix, stored column-major, a thread per row, no row pointers read), or
+ * a CSR5 copy (tiles of 64 lanes x 16 consecutive entries stored
+ * transposed, a wave per tile, row starts marked by bits, rows that cross
+ * lanes or tiles joined by segmented sums in a fixed order; no padding
+ * beyond the last tile). When it does, every plan of the SpMV pattern runs
+ * on that copy; the other patterns are unchanged. By default a small
+ * decision tree over the matrix features and the padding ratios (cells /
+ * nnz; reading the sliced one copies row_ptr to the host once) decides,
+ * trained on MI355X timings of the four formats. SPX_FORMAT_SELL forces the
+ * sliced copy (SPX_ERR_UNSUPPORTED when a row is longer than 4096 entries or
+ * the copy would take more than 3 nnz + 65536 cells), SPX_FORMAT_ELL the ELL
+ * copy (SPX_ERR_UNSUPPORTED beyond 4096 entries per row or 1.5 nnz + 65536
+ * cells), SPX_FORMAT_CSR5 the CSR5 copy (any matrix; building it copies
+ * row_ptr to the host and synchronizes the stream); two of these flags
+ * together are SPX_ERR_ARG. SPX_FORMAT_CSR forbids every copy. Memory: 8 +
+ * value size bytes per cell (4 more per row for the sliced copy; for CSR5,
+ * 4 per row and 4 + 16 per tile of 1024 cells). */
 #define SPX_VALIDATE 1u
 #define SPX_RENUMBER 4u
 #define SPX_NO_RENUMBER 8u
 #define SPX_FORMAT_CSR 16u
 #define SPX_FORMAT_SELL 32u
 #define SPX_FORMAT_ELL 64u
+#define SPX_FORMAT_CSR5 128u
 spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
 spx_status spx_matrix_destroy(spx_matrix *H);
 
@@ -287,8 +293,9 @@ spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
 spx_status spx_matrix_column_order(const spx_matrix *H, int32_t *order, int32_t *renumbered, void *stream);
 
 /* *format = 1 if the handle keeps the sliced ELLPACK copy, 2 if it keeps
- * the ELLPACK copy (see spx_matrix_create), else 0; *padding_ratio (may be
- * NULL) = that copy's cells / nnz (0 when there is no copy). Host only. */
+ * the ELLPACK copy, 3 if it keeps the CSR5 copy (see spx_matrix_create),
+ * else 0; *padding_ratio (may be NULL) = that copy's cells / nnz (0 when
+ * there is no copy). Host only. */
 spx_status spx_matrix_format(const spx_matrix *H, int32_t *format, double *padding_ratio);
 
 /* Matrix features of Table 1, out[9] = {m, n, nnz, max_row, min_row,
@@ -334,7 +341,10 @@ spx_status spx_load_selector(spx_matrix *H, const char *json_path);
  * are evaluated lazily (Section 6.3): the only device work is the nnz_s
  * reduction, made when a node tests nnz_s, m_sparsity or s_per_x; it
  * synchronizes the stream, and flags & SPX_NO_SYNC forbids it (such nodes
- * then read nnz_s as nnz_x times the average column length). */
+ * then read nnz_s as nnz_x times the average column length). A vector
+ * handed over dense counts as dense (nnz_x = n) and never takes the
+ * column-major pattern (it would need a compaction and a host round trip
+ * first): where the pattern tree says column-major, it takes SpMV. */
 #define SPX_NO_SYNC 2u
 spx_status select_kernel(spx_matrix *H, const spx_vec *x, uint32_t flags, spx_plan *out,
                          void *stream);

@@ -193,6 +193,7 @@ struct spx_matrix {
     SellMat sell;
     double sell_ratio = 0.0;
     EllMat ell;
+    Csr5Mat c5;
     // column-sorted copy of the renumbered CSR for the balanced SpMV with
     // 2048-item tiles (kept with the renumbered copy when n <= 2^21)
     TileSorted ts;
@@ -489,6 +490,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
         if (p) hipFree(p);
     sell_free(&H->sell);
     ell_free(&H->ell);
+    csr5_free(&H->c5);
     tile_sorted_free(&H->ts);
     if (H->drv_host) hipHostFree(H->drv_host);
     if (H->cnt_host) hipHostFree(H->cnt_host);
@@ -651,10 +653,11 @@ static spx_status build_gcsr(spx_matrix* H, uint32_t flags, hipStream_t s) {
     return SPX_OK;
 }
 
-// Storage-format pre-selection: keep the sliced ELLPACK copy or not. The
-// tree reads the Table 1 features of A and the padding ratio of the
-// sliced copy (cells / nnz), the latter computed from a host copy of
-// row_ptr only when a node asks for it.
+// Storage-format pre-selection: which copy beside CSR the SpMV pattern
+// runs on (none, sliced ELLPACK, ELLPACK or CSR5). The tree reads the
+// Table 1 features of A and the padding ratios (cells / nnz): the sliced
+// copy's is computed from a host copy of row_ptr only when a node asks for
+// it; the CSR5 copy is built from that host copy too.
 constexpr int32_t kSellMaxRow = 4096;  // longest row the copy accepts (serial sums per lane)
 constexpr double kSellMaxRatio = 3.0;  // most cells per entry it accepts, beyond a fixed allowance
 constexpr int64_t kSellAllowance = 65536;  // cells any matrix may use (one partly filled slice)
@@ -663,31 +666,41 @@ constexpr double kEllMaxRatio = 1.5;   // most cells per entry it accepts, beyon
 static spx_status choose_format(spx_matrix* H, uint32_t flags, hipStream_t s) {
     const spx_csr& A = H->gorder ? H->gcsr : H->csr;
     if ((flags & SPX_FORMAT_CSR) || A.m == 0) return SPX_OK;
-    if ((flags & SPX_FORMAT_SELL) && (flags & SPX_FORMAT_ELL))
-        return fail(SPX_ERR_ARG, "SPX_FORMAT_SELL and SPX_FORMAT_ELL exclude each other");
+    const int nforced = ((flags & SPX_FORMAT_SELL) ? 1 : 0) + ((flags & SPX_FORMAT_ELL) ? 1 : 0) +
+                        ((flags & SPX_FORMAT_CSR5) ? 1 : 0);
+    if (nforced > 1) return fail(SPX_ERR_ARG, "SPX_FORMAT_SELL, SPX_FORMAT_ELL and SPX_FORMAT_CSR5 exclude each other");
     const bool forced = (flags & SPX_FORMAT_SELL) != 0;
     const bool forced_ell = (flags & SPX_FORMAT_ELL) != 0;
+    const bool forced_c5 = (flags & SPX_FORMAT_CSR5) != 0;
     std::vector<int32_t> rp;
     SellPlanInfo info;
-    bool shaped = false;
+    bool fetched = false, shaped = false;
     spx_status st = SPX_OK;
+    auto fetch = [&]() {
+        if (fetched) return;
+        fetched = true;
+        rp.resize((size_t)A.m + 1);
+        if (hipMemcpyAsync(rp.data(), A.row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = fail(SPX_ERR_HIP, "row_ptr read-back");
+    };
     auto shape = [&]() {
         if (shaped) return;
         shaped = true;
-        rp.resize((size_t)A.m + 1);
-        if (hipMemcpyAsync(rp.data(), A.row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            st = fail(SPX_ERR_HIP, "row_ptr read-back");
-            return;
-        }
-        info = sell_shape(rp.data(), A.m);
+        fetch();
+        if (st == SPX_OK) info = sell_shape(rp.data(), A.m);
     };
     auto ratio = [&]() {
         shape();
         return (double)info.padded / (double)std::max<int64_t>(1, A.nnz);
     };
-    const int choice = forced ? 1 : forced_ell ? 2 : format_choice(H->feat, ratio);
+    const int choice = forced ? 1 : forced_ell ? 2 : forced_c5 ? 3 : format_choice(H->feat, ratio);
     if (st != SPX_OK || choice == 0) return st;
+    if (choice == 3) {
+        fetch();
+        if (st != SPX_OK) return st;
+        return csr5_build(A, rp.data(), &H->c5, s);
+    }
     if (choice == 2) {
         const int32_t w = (int32_t)H->feat[3];
         const double cells = (double)w * (double)A.m;
@@ -781,16 +794,18 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->sell.col) SPX_TRY(sell_refresh(H->sell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->ell.col) SPX_TRY(ell_refresh(H->ell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
+    if (H->c5.col) SPX_TRY(csr5_refresh(H->c5, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->ts.pk) SPX_TRY(gather_perm(H->csr.vals, H->ts.src, H->ts.vals, H->csr.nnz, vs, (hipStream_t)stream));
     return SPX_OK;
 }
 
 extern "C" spx_status spx_matrix_format(const spx_matrix* H, int32_t* format, double* padding_ratio) {
     if (!H || !format) return fail(SPX_ERR_ARG, "null argument");
-    *format = H->sell.col ? 1 : H->ell.col ? 2 : 0;
+    *format = H->sell.col ? 1 : H->ell.col ? 2 : H->c5.col ? 3 : 0;
     if (padding_ratio)
-        *padding_ratio = H->sell.col ? H->sell_ratio
+        *padding_ratio = H->sell.col  ? H->sell_ratio
                          : H->ell.col ? (double)H->ell.cells / (double)std::max<int32_t>(1, H->csr.nnz)
+                         : H->c5.col  ? (double)H->c5.cells / (double)std::max<int32_t>(1, H->csr.nnz)
                                       : 0.0;
     return SPX_OK;
 }
@@ -946,6 +961,12 @@ static spx_status select_impl(spx_matrix* H, const Selector& S, const spx_vec* x
     spx_plan p{};
     p.pattern = S.pattern.eval(f);
     if (p.pattern < 0 || p.pattern > 2) p.pattern = SPX_PAT_SPMV;
+    // A vector handed over dense is taken as dense (nnz_x = n): the trees
+    // were trained on vectors handed over as lists, for which a row-major
+    // plan pays the scatter into a dense x; here the row-major plans read x
+    // as it is, while a column-major plan would first compact it, with a
+    // host round trip for its length. Such a vector takes the SpMV pattern.
+    if (x->kind == SPX_VEC_DENSE && p.pattern == SPX_PAT_CSC_SPMSPV) p.pattern = SPX_PAT_SPMV;
     p.distribution = S.distribution[p.pattern].eval(f);
     if (p.distribution != SPX_DIST_BALANCED) p.distribution = SPX_DIST_DIRECT;
     p.writeback = SPX_WB_NONE;
@@ -1070,6 +1091,8 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
             SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
         else if (H->ell.col)
             SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
+        else if (H->c5.col)
+            SPX_TRY(csr5_spmv(H->c5, dt, xd, y, s));
         else
             SPX_TRY(launch_spmv_csr(&A, xd, nullptr, y, p, part, ws, s, un.xd ? &un : nullptr, &cleared,
                                     H->gorder && H->ts.pk ? &H->ts : nullptr));
@@ -1230,6 +1253,8 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
         SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
     else if (H->ell.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
+    else if (H->c5.col && p->pattern == SPX_PAT_SPMV)
+        SPX_TRY(csr5_spmv(H->c5, dt, xd, y, s));
     else
         SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s, nullptr, nullptr,
                                 H->gorder && H->ts.pk ? &H->ts : nullptr));

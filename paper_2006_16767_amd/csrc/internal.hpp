@@ -363,4 +363,27 @@ spx_status ell_refresh(const EllMat& E, const spx_csr& A, hipStream_t s);
 void ell_free(EllMat* E);
 spx_status ell_spmv(const EllMat& E, int dtype, const void* x, void* y, hipStream_t s);
 
+// CSR5-style copy of A: tiles of 64 lanes x 16 consecutive entries stored
+// transposed, with row-start bits per lane and the non-empty rows listed;
+// see csr5.hip.
+struct Csr5Mat {
+    int32_t m = 0, nnz = 0;
+    int64_t ntiles = 0;
+    int64_t cells = 0;             // ntiles * tile size (the last tile padded)
+    int32_t nonempty = 0, nempty = 0;
+    int32_t* col = nullptr;        // [cells]
+    void* vals = nullptr;          // [cells] (none for BOOL)
+    uint32_t* flags = nullptr;     // [ntiles * 64] row-start bits per lane
+    int32_t* tile_start = nullptr; // [ntiles + 1] ordinal of the tile's first row start
+    int32_t* nz_rows = nullptr;    // [nonempty] ordinal -> row
+    int32_t* empty_rows = nullptr; // [nempty]
+    void* lead = nullptr;          // [ntiles] accumulators written by each call
+    void* trail = nullptr;         // [ntiles]
+};
+int64_t csr5_cells(int32_t nnz);
+spx_status csr5_build(const spx_csr& A, const int32_t* row_ptr_host, Csr5Mat* out, hipStream_t s);
+spx_status csr5_refresh(const Csr5Mat& C, const spx_csr& A, hipStream_t s);
+void csr5_free(Csr5Mat* C);
+spx_status csr5_spmv(const Csr5Mat& C, int dtype, const void* x, void* y, hipStream_t s);
+
 }  // namespace spx

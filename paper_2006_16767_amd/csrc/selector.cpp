@@ -39,26 +39,32 @@ static Tree make_tree(std::initializer_list<std::initializer_list<double>> rows)
 
 // Trained (tune.py formats-train: the project CART, depth 3, regret-weighted)
 // on MI355X timings of the dense-x FP32 SpMV on the 30 tuning matrices:
-// best CSR plan, sliced copy and ELL copy. Nearly equal rows (population
-// standard deviation of the row lengths <= 0.83) over more than 98304 rows
-// go to ELL up to 15.7M entries (the 7-point stencils: 128^3 ran 29.0 us in
-// ELL against 34.8 in CSR and 36.5 sliced) and to the sliced copy beyond;
-// between 24576 and 98304 such rows the sliced copy wins; every uneven or
-// small matrix stays in CSR. On that corpus it loses 0.2 % against always
-// taking the fastest format (CSR alone 3.4 %); on the FP64 sweep 0.4 % (CSR
-// alone 2.6 %).
+// best CSR plan, sliced copy, ELL copy and CSR5 copy. Up to 1.17M entries:
+// rows of at most 7 entries go to ELL, rows up to 1158 to the sliced copy,
+// longer (skewed) rows to CSR5 (R-MAT 2^14 to 2^17 and the small power-law
+// matrices, about 10 % under CSR). Beyond: nearly equal rows (relative range
+// <= 3.1e-5) to ELL up to 15.7M entries (the 7-point stencils: 128^3 ran
+// 25.7 us in ELL against 32.4 in CSR) and to the sliced copy beyond; rows
+// whose longest exceeds 17 % of n to CSR5; the rest (the large R-MAT graphs,
+// whose CSR kernels read the column-sorted tiles) stay in CSR. On that corpus
+// it loses 0.1 % against always taking the fastest format (CSR alone 4.5 %);
+// on the FP64 sweep 1.4 % (CSR alone 3.7 %).
 Tree format_tree() {
     // rows: feature, threshold, left, right, class (-1 = internal)
     return make_tree({
-        {F_VAR_ROW, 0.8266357019503078, 1, 8, -1},
-        {F_M, 98304.0, 2, 5, -1},
-        {F_M, 24576.0, 3, 4, -1},
-        {0, 0, 0, 0, 0},
-        {0, 0, 0, 0, 1},
-        {F_NNZ, 15679488.0, 6, 7, -1},
+        {F_NNZ, 1171495.0, 1, 6, -1},
+        {F_MAX_ROW, 1158.5, 2, 5, -1},
+        {F_MAX_ROW, 7.5, 3, 4, -1},
         {0, 0, 0, 0, 2},
         {0, 0, 0, 0, 1},
+        {0, 0, 0, 0, 3},
+        {F_REL_RANGE, 3.07220458984375e-05, 7, 10, -1},
+        {F_NNZ, 15679488.0, 8, 9, -1},
+        {0, 0, 0, 0, 2},
+        {0, 0, 0, 0, 1},
+        {F_REL_RANGE, 0.17117210571289063, 11, 12, -1},
         {0, 0, 0, 0, 0},
+        {0, 0, 0, 0, 3},
     });
 }
 

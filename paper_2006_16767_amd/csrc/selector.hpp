@@ -80,8 +80,8 @@ struct Selector {
 Selector builtin_selector();
 
 // Storage-format pre-selector: class 0 keeps CSR only, class 1 adds the
-// sliced ELLPACK copy, class 2 the ELLPACK copy, for the format expected to
-// run the SpMV fastest. Feature ids 0-8 are the Table 1 matrix features
+// sliced ELLPACK copy, class 2 the ELLPACK copy, class 3 the CSR5 copy, for
+// the format expected to run the SpMV fastest. Feature ids 0-8 are the Table 1 matrix features
 // (F_M .. F_GINI), kFmtPadding the padding ratio of the sliced copy
 // (cells / nnz; ratio() computes it on first use, from a host copy of
 // row_ptr), kFmtEllPadding that of the ELL copy (max_row * m / nnz, from the
@@ -94,7 +94,7 @@ int format_choice(const double* feat, RatioFn&& ratio) {
     static const Tree t = format_tree();
     const double ell = feat[F_NNZ] > 0 ? feat[F_MAX_ROW] * feat[F_M] / feat[F_NNZ] : 1.0;
     const int c = t.eval([&](int f) { return f < kFmtPadding ? feat[f] : f == kFmtPadding ? ratio() : ell; });
-    return c >= 0 && c <= 2 ? c : 0;
+    return c >= 0 && c <= 3 ? c : 0;
 }
 // Parses the tuner's JSON. Returns false with a message on error.
 bool parse_selector_json(const std::string& text, Selector* out, std::string* err);

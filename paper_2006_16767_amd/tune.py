@@ -270,7 +270,7 @@ def driver_sweep(out_path: str, reps: int = 5, graph: str = "rmat20_d16"):
 # ----------------------------------------------------------------------------- storage format
 FORMAT_FEATURES = ("m", "n", "nnz", "max_row", "min_row", "avg_row", "relative_range", "var_nnz_row", "gini",
                    "padding", "ell_padding")
-FORMATS = ("csr", "sell", "ell")
+FORMATS = ("csr", "sell", "ell", "csr5")
 SELL_SIGMA = 4096  # rows per sorting window of the sliced copy
 
 
@@ -293,9 +293,9 @@ def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
     """Training data of the storage-format pre-selector: on every corpus
     matrix, the SpMV of a dense x (FP32, or FP64 to check the tree on the
     other precision) by the fastest SpMV plan of a CSR handle against the
-    sliced ELLPACK and the ELLPACK copies of handles forced to keep them
-    (null when the matrix is too skewed for a copy). One record per
-    matrix."""
+    sliced ELLPACK, the ELLPACK and the CSR5 copies of handles forced to
+    keep them (null when the matrix is too skewed for a copy). One record
+    per matrix."""
     import torch
     from . import F32, F64, Matrix, SpxError, plan
     code, tdt = (F64, torch.float64) if dtype == "f64" else (F32, torch.float32)
@@ -312,8 +312,8 @@ def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
             lens = np.diff(np.asarray(A.row_ptr, dtype=np.int64))
             ell = float(lens.max() * A.m) / max(1, int(lens.sum())) if A.m else 1.0
             rec = {"matrix": name, "features": dict(feats, padding=sell_padding(A), ell_padding=ell), "csr_ms": tc,
-                   "sell_ms": None, "ell_ms": None}
-            for fmt in ("sell", "ell"):
+                   "sell_ms": None, "ell_ms": None, "csr5_ms": None}
+            for fmt in ("sell", "ell", "csr5"):
                 try:
                     Ms = Matrix.from_host(A, dtype=code, fmt=fmt)
                     rec[f"{fmt}_ms"] = _time_plans(Ms, x, y, [plan("spmv", "direct")], reps)[
@@ -327,15 +327,15 @@ def format_sweep(out_path: str, reps: int = 10, dtype: str = "f32"):
             fout.flush()
             ts = lambda v: "-" if v is None else f"{v * 1e3:.1f}"  # noqa: E731
             print(f"[format] {name}: csr {min(tc.values()) * 1e3:.1f} us, sell {ts(rec['sell_ms'])} us, "
-                  f"ell {ts(rec['ell_ms'])} us", flush=True)
+                  f"ell {ts(rec['ell_ms'])} us, csr5 {ts(rec['csr5_ms'])} us", flush=True)
 
 
 def _format_times(r):
-    """(csr, sell, ell) SpMV times of a format record, inf where the copy
-    was refused or not timed."""
+    """(csr, sell, ell, csr5) SpMV times of a format record, inf where the
+    copy was refused or not timed."""
     c = min(r["csr_ms"].values())
     f = lambda k: r.get(k) if r.get(k) is not None else float("inf")  # noqa: E731
-    return [c, f("sell_ms"), f("ell_ms")]
+    return [c, f("sell_ms"), f("ell_ms"), f("csr5_ms")]
 
 
 def _format_row(r):
@@ -347,7 +347,7 @@ def _format_row(r):
 
 def format_train(path: str, out_path: str, max_depth: int = 3):
     """The storage-format tree from a format sweep: the class of the format
-    (0 CSR, 1 sliced ELLPACK, 2 ELLPACK) that ran the SpMV fastest. Samples
+    (0 CSR, 1 sliced ELLPACK, 2 ELLPACK, 3 CSR5) that ran the SpMV fastest. Samples
     are weighted by the time the slowest available choice would lose
     (relative), and the tree is grown on all records (one per matrix, too
     few to hold some out); the report gives the time lost against always
@@ -1100,6 +1100,7 @@ def main(argv=None):
     ft = sub.add_parser("formats-train")
     ft.add_argument("data")
     ft.add_argument("--out", required=True)
+    ft.add_argument("--max-depth", type=int, default=3)
     tl = sub.add_parser("train-lazy")
     tl.add_argument("data", nargs="+")
     tl.add_argument("--out", required=True)
@@ -1147,7 +1148,7 @@ def main(argv=None):
         print(json.dumps(format_evaluate(a.data, a.tree), indent=1))
         return
     if a.cmd == "formats-train":
-        print(json.dumps(format_train(a.data, a.out), indent=1))
+        print(json.dumps(format_train(a.data, a.out, a.max_depth), indent=1))
         return
     if a.cmd == "evaluate":
         rep = evaluate(a.data, a.selectors, tuple(k for k in a.kinds.split(",") if k) or None)

@@ -54,7 +54,7 @@ def test_mixed_call_sequence(kind, renumber):
     torch = _torch()
     code, npdt = KINDS[kind]
     A = _with_kind(cfg_matrix("rmat16"), kind)
-    M = spx.Matrix.from_host(A, dtype=code, renumber=renumber)
+    M = spx.Matrix.from_host(A, dtype=code, renumber=renumber, fmt="csr")
     rng = np.random.default_rng(17)
     sizes = [A.n // 8, 5, A.n // 2, 1, 0, 300, -(A.n // 3), A.n // 8, 2, -7, A.n]
     for i in range(3 * len(PLANS)):
@@ -86,7 +86,7 @@ def test_minplus_sequence_keeps_infinity():
     torch = _torch()
     A = cfg_matrix("rmat16")
     A = A.with_vals(np.asarray(A.vals, np.float32))
-    M = spx.Matrix.from_host(A, dtype=spx.F32_MINPLUS, renumber=True)
+    M = spx.Matrix.from_host(A, dtype=spx.F32_MINPLUS, renumber=True, fmt="csr")
     plans = [spx.plan("spmv", "balanced"), spx.plan("csr_spmspv", "balanced"), spx.plan("spmv", "direct")]
     for i, nnz in enumerate([A.n // 4, 3, A.n // 2, 0, 40, A.n // 16, 1]):
         v = synth.sparse_vector(A.n, nnz, 700 + i)

@@ -46,7 +46,7 @@ def test_sweep_bitwise_repeatable(kind):
     torch = _torch()
     A = cfg_matrix("cfg2")
     npdt = np.float32 if kind == "f32" else np.float64
-    M = spx.Matrix.from_host(A.with_vals(A.vals.astype(npdt)))
+    M = spx.Matrix.from_host(A.with_vals(A.vals.astype(npdt)), fmt="csr")
     vecs = synth.cfg2_vectors(A.n)
     for v in vecs[::2] + [vecs[-1]]:
         x = (torch.as_tensor(v.idx, device="cuda"), torch.as_tensor(np.asarray(v.val, npdt), device="cuda"))

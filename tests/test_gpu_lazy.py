@@ -51,6 +51,18 @@ def _expected(sel, mf, A, col_len, idx):
     return (pat, dist, wb), asked
 
 
+def _rerun_report(M, x, plan, ref, S):
+    """On a mismatch: whether the same call and the same plan given
+    explicitly reproduce it (tells a wrong plan from a wrong execution)."""
+    out = []
+    for label, fn in (("run", lambda: M.run(x)), ("run_plan", lambda: M.run_plan(x, plan))):
+        for _ in range(3):
+            y = fn().cpu().numpy().astype(np.float64)
+            bad = int(np.count_nonzero(np.abs(y - ref) > 1e-5 * S))
+            out.append(f"{label}: {bad} rows off")
+    return "; ".join(out)
+
+
 @pytest.mark.gpu
 def test_lazy_trees_pick_what_the_tuner_walks_and_match_the_oracle():
     _torch()
@@ -76,9 +88,12 @@ def test_lazy_trees_pick_what_the_tuner_walks_and_match_the_oracle():
             # run() on every vector that asked and on every fourth other one
             if ask or checked % 4 == 0:
                 y = M.run(x)
-                ref, S = reference(A, v.idx, v.val, "f32")
-                assert_close(y.cpu().numpy(), ref, S, "f32", f"run {kind} {key} plan={M.last_plan()}")
                 lp = M.last_plan()
+                ref, S = reference(A, v.idx, v.val, "f32")
+                try:
+                    assert_close(y.cpu().numpy(), ref, S, "f32", f"run {kind} {key} plan={lp}")
+                except AssertionError as err:
+                    raise AssertionError(f"{err}\n{_rerun_report(M, x, lp, ref, S)}") from None
                 assert (lp.pattern, lp.distribution, lp.writeback) == want, f"{kind} {key}: run() took {lp}"
             checked += 1
     assert asked >= 2 and not_asked >= 2, (asked, not_asked)

@@ -60,7 +60,7 @@ def test_hub_row_row_major_and_tree_write_backs(renumber):
     torch = _torch()
     A, x = _inputs()
     ref, S = oracle.spmv(A, x.astype(np.float64))
-    M = spx.Matrix.from_host(A, renumber=renumber)
+    M = spx.Matrix.from_host(A, renumber=renumber, fmt="csr")
     xd = torch.as_tensor(x, device="cuda")
     idx = torch.arange(A.n, dtype=torch.int32, device="cuda")
     for p in _row_major_plans():

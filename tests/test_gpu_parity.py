@@ -35,7 +35,7 @@ def _matrix(A, kind):
         A = A.with_vals(vals)
     elif kind in ("f32", "f64"):
         A = A.with_vals(np.asarray(A.vals).astype(npdt))
-    return A, spx.Matrix.from_host(A, dtype=code)
+    return A, spx.Matrix.from_host(A, dtype=code, fmt="csr")
 
 
 def _vec_vals(v, kind, rng=None):
@@ -86,7 +86,7 @@ def _run_and_check(M, A, v_idx, v_val, kind, plans, what, dense=False):
 def test_transpose_matches_oracle(name):
     torch = _torch()
     A = cfg_matrix(name)
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     col_ptr, row_idx, vals = M.csc()
     ref = oracle.transpose(A)
     assert np.array_equal(col_ptr.cpu().numpy(), ref.col_ptr)
@@ -98,14 +98,14 @@ def test_transpose_ragged_and_empty():
     torch = _torch()
     for m, n, dens, seed in [(37, 53, 0.1, 1), (1, 1, 1.0, 2), (300, 7, 0.5, 3), (5, 400, 0.01, 4)]:
         A = synth.random_csr(m, n, dens, seed, empty_rows=0.3)
-        M = spx.Matrix.from_host(A)
+        M = spx.Matrix.from_host(A, fmt="csr")
         col_ptr, row_idx, vals = M.csc()
         ref = oracle.transpose(A)
         assert np.array_equal(col_ptr.cpu().numpy(), ref.col_ptr)
         assert np.array_equal(row_idx.cpu().numpy(), ref.row_idx)
     # a matrix with no entries at all
     A0 = synth.CSR(6, 9, np.zeros(7, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
-    M0 = spx.Matrix.from_host(A0)
+    M0 = spx.Matrix.from_host(A0, fmt="csr")
     assert np.array_equal(M0.csc()[0].cpu().numpy(), np.zeros(10, np.int32))
     y = M0.run((torch.as_tensor(np.array([1, 4], np.int32), device="cuda"),
                 torch.ones(2, dtype=torch.float32, device="cuda")))
@@ -116,7 +116,7 @@ def test_transpose_ragged_and_empty():
 def test_features_match_oracle(name):
     _torch()
     A = cfg_matrix(name)
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     f = M.features()
     ref = oracle.matrix_features(A)
     for k, v in ref.items():
@@ -171,7 +171,7 @@ def test_integer_valued_fp32_bitexact():
     every kernel must match the oracle bit for bit."""
     torch = _torch()
     A = synth.random_csr(4000, 3000, 0.003, 9, dtype=np.float32, int_values=True, empty_rows=0.1)
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     for nnz_x in (5, 300, 3000):
         v = synth.sparse_vector(3000, nnz_x, nnz_x, dist="int")
         ref, S = reference(A, v.idx, v.val, "f32")
@@ -206,7 +206,7 @@ def test_cfg3_poisson_closed_form(dt):
     exact in any order, so bit-exact."""
     torch = _torch()
     A = cfg_matrix("cfg3" if dt == "f32" else "cfg3_f64")
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     k = 128
     idx = np.arange(A.n)
     onb = sum(((c == 0) | (c == k - 1)).astype(np.int64) for c in (idx % k, (idx // k) % k, idx // (k * k)))
@@ -227,7 +227,7 @@ def test_cfg3_dense_and_sparse(dt):
     _torch()
     npdt = np.float32 if dt == "f32" else np.float64
     A = cfg_matrix("cfg3" if dt == "f32" else "cfg3_f64")
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     dense, sparse = synth.cfg3_vectors(dtype=npdt)
     plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     full = np.arange(A.n, dtype=np.int32)
@@ -241,8 +241,8 @@ def test_cfg2_rmat_sweep():
     boolean pattern (bit-exact)."""
     _torch()
     A = cfg_matrix("cfg2")
-    Mf = spx.Matrix.from_host(A)
-    Mb = spx.Matrix.from_host(A, dtype=spx.BOOL)
+    Mf = spx.Matrix.from_host(A, fmt="csr")
+    Mb = spx.Matrix.from_host(A, dtype=spx.BOOL, fmt="csr")
     plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     for v in synth.cfg2_vectors():
         _run_and_check(Mf, A, v.idx, v.val, "f32", plans, f"cfg2 f32 nnz_x={v.nnz}")
@@ -254,7 +254,7 @@ def test_bool_bfs_frontiers():
     edge-list expansion of each frontier."""
     torch = _torch()
     A = cfg_matrix("rmat16")
-    M = spx.Matrix.from_host(A, dtype=spx.BOOL)
+    M = spx.Matrix.from_host(A, dtype=spx.BOOL, fmt="csr")
     rows = np.repeat(np.arange(A.m), np.diff(A.row_ptr)).astype(np.int32)
     plans = [p for p in spx.all_plans() if p.writeback != spx.WB_LDS_ATOMIC]
     for fr in synth.bfs_frontiers(A, max_levels=12):
@@ -288,7 +288,7 @@ def test_direct_entry_points():
     """spmv_csr / spmspv_csr / spmspv_csc called directly with a workspace."""
     torch = _torch()
     A = cfg_matrix("cfg1")
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     dense, sparse = synth.cfg1_vectors()
     x = torch.as_tensor(dense, device="cuda")
     ref, S = reference(A, np.arange(A.n), dense, "f32")
@@ -325,7 +325,7 @@ def test_adaptive_run_cfg1_and_rmat16():
 def test_errors_on_device():
     torch = _torch()
     A = cfg_matrix("cfg1")
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     with pytest.raises(spx.SpxError) as e:
         M.run(torch.zeros(A.n + 1, device="cuda"))
     # the binding passes n of the matrix; a wrong-length sparse index set is
@@ -352,7 +352,7 @@ def test_backward_matches_oracle(dt):
     npdt = np.float32 if dt == "f32" else np.float64
     tdt = torch.float32 if dt == "f32" else torch.float64
     A = synth.bernoulli(3000, 1200, 0.03, 21, std=0.5, dtype=npdt)
-    M = spx.Matrix.from_host(A)
+    M = spx.Matrix.from_host(A, fmt="csr")
     B = 5
     G = np.random.default_rng(1).standard_normal((B, A.m)).astype(npdt)
     X = np.zeros((B, A.n), npdt)
@@ -396,3 +396,22 @@ def test_launch_parameter_variants(name, kind):
     for nnz_x in (max(1, A.n // 100), A.n // 2):
         v = synth.sparse_vector(A.n, nnz_x, 900 + nnz_x)
         _run_and_check(M, A, v.idx, _vec_vals(v, kind), kind, _variant_plans(), f"{name} {kind} nnz_x={nnz_x}")
+
+
+def test_dense_x_never_takes_the_column_major_pattern():
+    """A vector handed over dense counts as dense and is read as it is: the
+    selection keeps it off the column-major pattern, which would first
+    compact it with a host round trip."""
+    torch = _torch()
+    for name in ("cfg1", "rmat16"):
+        A = cfg_matrix(name)
+        M = spx.Matrix.from_host(A)
+        x = synth.dense_vector(A.n, 3)
+        xt = torch.as_tensor(x, device="cuda")
+        p = M.select(xt)
+        assert p.pattern != spx.PAT_CSC_SPMSPV, (name, p)
+        y = M.run(xt)
+        torch.cuda.synchronize()
+        assert M.last_plan().pattern == p.pattern
+        ref, S = oracle.spmv(A, x.astype(np.float64))
+        assert_close(y.cpu().numpy(), ref, S, "f32", f"run {name} dense x {M.last_plan()}")

@@ -65,7 +65,7 @@ def _check(M, A, kind, nnz_x, seed, dense):
 def test_column_order_is_the_stable_length_ranking():
     _torch()
     A = cfg_matrix("rmat16")
-    M = spx.Matrix.from_host(A, renumber=True)
+    M = spx.Matrix.from_host(A, renumber=True, fmt="csr")
     order = M.column_order()
     assert order is not None
     lens = np.diff(oracle.transpose(A, with_values=False).col_ptr)
@@ -87,7 +87,7 @@ def test_default_choice():
 def test_renumbered_plans_match_oracle(kind):
     _torch()
     A = _with_kind(cfg_matrix("rmat16"), kind)
-    M = spx.Matrix.from_host(A, dtype=KINDS[kind][0], renumber=True)
+    M = spx.Matrix.from_host(A, dtype=KINDS[kind][0], renumber=True, fmt="csr")
     for nnz_x in (0, 1, 300, A.n // 8, A.n):
         _check(M, A, kind, nnz_x, 40 + nnz_x, dense=False)
     for nnz_x in (1, A.n // 3):
@@ -101,7 +101,7 @@ def test_renumbered_ragged(kind):
     _torch()
     for ci, (m, n, dens) in enumerate([(37, 53, 0.1), (3001, 2503, 0.004), (700, 9000, 0.002), (2, 1, 1.0)]):
         A = _with_kind(synth.random_csr(m, n, dens, 300 + ci, empty_rows=0.2), kind)
-        M = spx.Matrix.from_host(A, dtype=KINDS[kind][0], renumber=True)
+        M = spx.Matrix.from_host(A, dtype=KINDS[kind][0], renumber=True, fmt="csr")
         for nnz_x in sorted({1, max(1, n // 7), n}):
             _check(M, A, kind, nnz_x, 60 + ci, dense=False)
             _check(M, A, kind, nnz_x, 70 + ci, dense=True)
@@ -110,7 +110,7 @@ def test_renumbered_ragged(kind):
 def test_renumbered_copy_follows_values_updated():
     torch = _torch()
     A = cfg_matrix("rmat16")
-    M = spx.Matrix.from_host(A, renumber=True)
+    M = spx.Matrix.from_host(A, renumber=True, fmt="csr")
     new = np.random.default_rng(8).uniform(-2, 2, A.nnz).astype(np.float32)
     M.vals.copy_(torch.as_tensor(new, device="cuda"))
     M.values_updated()

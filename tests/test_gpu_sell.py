@@ -128,7 +128,7 @@ def test_sell_refused_when_too_skewed():
     with pytest.raises(spx.SpxError) as e:
         spx.Matrix.from_host(A, fmt="sell")
     assert e.value.code == -5
-    assert spx.Matrix.from_host(A).storage_format()[0] == "csr"
+    assert spx.Matrix.from_host(A, fmt="csr").storage_format()[0] == "csr"
     assert spx.Matrix.from_host(synth.poisson3d(16, np.float32), fmt="csr").storage_format() == ("csr", 0.0)
 
 
@@ -144,15 +144,19 @@ def test_padding_ratio_matches_the_layout_definition():
 
 
 def test_auto_format_follows_the_tree():
-    """Nearly equal rows: 24576 to 98304 rows get the sliced copy, more rows
-    the ELL copy up to 15.7M entries (the stencils) and the sliced copy
-    beyond; small or uneven matrices stay in CSR."""
+    """Up to 1.17M entries: rows of at most 7 entries go to ELL, up to 1158 to
+    the sliced copy, longer to CSR5. Beyond: nearly equal rows to ELL up to
+    15.7M entries (the stencils) and to the sliced copy past that, rows
+    longer than 17 % of n to CSR5, the large R-MAT graphs stay in CSR."""
     _torch()
     assert spx.Matrix.from_host(synth.uniform_rows(65536, 65536, 8, 11)).storage_format()[0] == "sell"
+    assert spx.Matrix.from_host(synth.uniform_rows(16384, 16384, 4, 44)).storage_format()[0] == "ell"
+    assert spx.Matrix.from_host(cfg_matrix("cfg1")).storage_format()[0] == "sell"
+    assert spx.Matrix.from_host(cfg_matrix("rmat16")).storage_format()[0] == "csr5"
     assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "ell"
     assert spx.Matrix.from_host(cfg_matrix("cfg3")).storage_format()[0] == "ell"
-    assert spx.Matrix.from_host(cfg_matrix("cfg1")).storage_format()[0] == "csr"
-    assert spx.Matrix.from_host(cfg_matrix("rmat16")).storage_format()[0] == "csr"
+    assert spx.Matrix.from_host(synth.powerlaw_rows(100_000, 50_000, 40.0, 31)).storage_format()[0] == "csr5"
+    assert spx.Matrix.from_host(synth.rmat(18, 8, 5)).storage_format()[0] == "csr"
 
 
 def test_sell_full_size_uniform_rows():
