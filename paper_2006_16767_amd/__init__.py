@@ -33,23 +33,23 @@ _NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__fil
 _BOOL_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_bool.json")
 _BOOL_NNZ_S_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__),
                                                   "selector_mi355x_bool_nnz_s.json")
-# lazy trees of run(): they may ask for nnz_s (a device count and a stream
-# synchronization) where that pays for itself
-_LAZY_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_lazy.json")
-_BOOL_LAZY_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__),
-                                                 "selector_mi355x_bool_lazy.json")
+# lazy trees for run(): they may ask for nnz_s (a device count and a round
+# trip to the host) at the leaves where the training vectors gained by it.
+# Not loaded by default: on the uniform sweep the round trip costs more than
+# it saves (Matrix.load_selector(LAZY_SELECTOR) opts in).
+LAZY_SELECTOR = __import__("os").path.join(__import__("os").path.dirname(__file__), "selector_mi355x_lazy.json")
 _selector_loaded = False
 
 
 def _ensure_default_selector():
     """Loads the trees trained on MI355X timings (selector_mi355x.json, then
-    selector_mi355x_nnz_s.json and selector_mi355x_lazy.json) once, before
-    the first handle is created; spx_load_selector can replace them."""
+    selector_mi355x_nnz_s.json) once, before the first handle is created;
+    spx_load_selector can replace them."""
     global _selector_loaded
     if _selector_loaded:
         return
     import os
-    for path in (_DEFAULT_SELECTOR, _NNZ_S_SELECTOR, _LAZY_SELECTOR):
+    for path in (_DEFAULT_SELECTOR, _NNZ_S_SELECTOR):
         if os.path.exists(path):
             _lib.call("spx_load_selector", None, path.encode())
     _selector_loaded = True
@@ -141,7 +141,7 @@ class Matrix:
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         if dtype == BOOL:
-            for path in (_BOOL_SELECTOR, _BOOL_NNZ_S_SELECTOR, _BOOL_LAZY_SELECTOR):
+            for path in (_BOOL_SELECTOR, _BOOL_NNZ_S_SELECTOR):
                 if __import__("os").path.exists(path):
                     _lib.call("spx_load_selector", self._h, path.encode())
         self._vals_version = None if self.vals is None else self.vals._version

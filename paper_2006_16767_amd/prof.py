@@ -13,14 +13,18 @@ summaries read the rocpd databases rocprofv3 writes (`*_results.db`).
   python -m paper_2006_16767_amd.prof fc [--reps R]
       the pruned FC layer 16384 x 4096: fused forward, then dX and dvals
       in one backward call.
+  python -m paper_2006_16767_amd.prof poisson [--k K] [--dtype f32|f64] [--reps R]
+      run() on a dense x over the 7-point Poisson matrix on K^3 (128 by
+      default; the format tree keeps the ELL copy for it).
   python -m paper_2006_16767_amd.prof copy [--mib M] [--reps R]
       a plain device-to-device copy of M MiB, R times (counter calibration:
       it reads and writes exactly M MiB).
   python -m paper_2006_16767_amd.prof kernels DB --title T --command C
       kernel-trace summary (markdown) of a `--kernel-trace --stats` db.
   python -m paper_2006_16767_amd.prof traffic --fetch DB --write DB
-        --copy-fetch DB --copy-write DB --mib M --vector K --out JSON
-      HBM bytes per launch of vector K's kernels: FETCH_SIZE and WRITE_SIZE
+        --copy-fetch DB --copy-write DB --mib M (--vector K | --workload W) --out JSON
+      HBM bytes per launch of vector K's kernels (or of workload W's, keyed
+      by its name): FETCH_SIZE and WRITE_SIZE
       (KiB per dispatch) scaled by what the same counters read for the copy
       of M MiB; written with the hash of the library sources, so the figure
       is void once a kernel changes.
@@ -47,6 +51,46 @@ def library_source_hash() -> str:
             h.update(os.path.basename(path).encode())
             with open(path, "rb") as f:
                 h.update(f.read())
+    return h.hexdigest()
+
+
+def _local_includes(path: str) -> list[str]:
+    out = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith('#include "'):
+                inc = os.path.normpath(os.path.join(os.path.dirname(path), line.split('"')[1]))
+                if os.path.exists(inc):
+                    out.append(inc)
+    return out
+
+
+def kernel_source_hash(stems) -> str:
+    """sha256 over the sources that define the given kernels (the files with
+    a __global__ definition of each stem) and every local header they
+    include, transitively: the figure measured on those kernels stays valid
+    while these files are unchanged."""
+    import re
+    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    files = set()
+    for stem in stems:
+        pat = re.compile(r"__global__[^;{]*?\b" + re.escape(stem) + r"\s*\(", re.S)
+        for path in srcs:
+            with open(path) as f:
+                if pat.search(f.read()):
+                    files.add(path)
+    todo = list(files)
+    while todo:
+        for inc in _local_includes(todo.pop()):
+            if inc not in files:
+                files.add(inc)
+                todo.append(inc)
+    h = hashlib.sha256()
+    for path in sorted(files):
+        h.update(os.path.relpath(path, HERE).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
@@ -214,6 +258,26 @@ def cmd_pagerank(args):
           f"{args.reps + 1} runs done", flush=True)
 
 
+def cmd_poisson(args):
+    import numpy as np
+    import torch
+    from . import F32, F64, Matrix
+    from . import synth
+    dt = np.float64 if args.dtype == "f64" else np.float32
+    A = synth.cfg3_matrix(dt, k=args.k)
+    M = Matrix.from_host(A, dtype=F64 if args.dtype == "f64" else F32)
+    x = torch.as_tensor(synth.dense_vector(A.n, 3).astype(dt), device="cuda")
+    y = M.out_tensor()
+    M.run(x, y)
+    torch.cuda.synchronize()
+    print(f"[prof] Poisson {args.k}^3 {args.dtype}: format {M.storage_format()[0]}, plan {M.last_plan()}",
+          flush=True)
+    for _ in range(args.reps):
+        M.run(x, y)
+    torch.cuda.synchronize()
+    print(f"[prof] {args.reps} runs done", flush=True)
+
+
 def cmd_copy(args):
     import torch
     n = args.mib * (1 << 20) // 4
@@ -262,7 +326,7 @@ def cmd_traffic(args):
     if os.path.exists(args.out):
         with open(args.out) as f:
             rec = json.load(f)
-    key = f"{SWEEP_WORKLOAD}:v{args.vector}"
+    key = args.workload or f"{SWEEP_WORKLOAD}:v{args.vector}"
     rec[key] = {
         "kernels": stems,
         "dispatches": {s: [fr[s][1], wr[s][1]] for s in stems},
@@ -271,7 +335,7 @@ def cmd_traffic(args):
         "bytes_per_launch": round(fetch + write),
         "calibration": {"copy_bytes": copy_bytes, "fetch_factor": round(k_fetch, 4),
                         "write_factor": round(k_write, 4)},
-        "library_sha256": library_source_hash(),
+        "kernel_sources_sha256": kernel_source_hash(stems),
         "commands": args.command or [],
     }
     with open(args.out, "w") as f:
@@ -282,12 +346,13 @@ def cmd_traffic(args):
 
 def traffic_for(path: str, vector: int):
     """Committed HBM bytes per launch of the sweep vector's kernels, or None
-    if absent or taken on library sources other than the current ones."""
+    if absent or taken on other sources of those kernels than the current
+    ones."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f).get(f"{SWEEP_WORKLOAD}:v{vector}")
-    if not rec or rec.get("library_sha256") != library_source_hash():
+    if not rec or rec.get("kernel_sources_sha256") != kernel_source_hash(rec["kernels"]):
         return None
     return rec["bytes_per_launch"]
 
@@ -309,6 +374,10 @@ def main(argv=None):
     a.add_argument("--push-only", action="store_true")
     a = sub.add_parser("pagerank")
     a.add_argument("--reps", type=int, default=2)
+    a = sub.add_parser("poisson")
+    a.add_argument("--k", type=int, default=128)
+    a.add_argument("--dtype", choices=("f32", "f64"), default="f32")
+    a.add_argument("--reps", type=int, default=5)
     a = sub.add_parser("copy")
     a.add_argument("--mib", type=int, default=512)
     a.add_argument("--reps", type=int, default=3)
@@ -321,10 +390,13 @@ def main(argv=None):
     for n in ("fetch", "write", "copy_fetch", "copy_write", "out", "kernels"):
         a.add_argument("--" + n.replace("_", "-"), dest=n, required=True)
     a.add_argument("--mib", type=int, required=True)
-    a.add_argument("--vector", type=int, required=True)
+    g = a.add_mutually_exclusive_group(required=True)
+    g.add_argument("--vector", type=int)
+    g.add_argument("--workload")
     a.add_argument("--command", action="append")
     args = ap.parse_args(argv)
-    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "bfs": cmd_bfs, "pagerank": cmd_pagerank, "copy": cmd_copy, "kernels": cmd_kernels,
+    {"vector": cmd_vector, "batch": cmd_batch, "fc": cmd_fc, "bfs": cmd_bfs, "pagerank": cmd_pagerank,
+     "poisson": cmd_poisson, "copy": cmd_copy, "kernels": cmd_kernels,
      "traffic": cmd_traffic}[args.cmd](args)
 
 

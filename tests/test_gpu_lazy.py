@@ -10,7 +10,6 @@ length 40) with its uniform, hub-weighted and low-degree supports: on this
 matrix the shipped trees ask on some vectors and not on others.
 """
 import json
-import os
 
 import numpy as np
 import pytest
@@ -20,7 +19,7 @@ from paper_2006_16767_amd import synth, tune
 
 from parity_util import assert_close, dev_sparse, reference
 
-LAZY = os.path.join(os.path.dirname(spx.__file__), "selector_mi355x_lazy.json")
+LAZY = spx.LAZY_SELECTOR
 K_ATOMIC_CHAIN_MAX = 1 << 16  # longest FP32 row the one-at-a-time write-backs may sum
 
 

@@ -95,7 +95,7 @@ def _restore_shipped(lib):
     later tests in the process see the usual defaults."""
     import os
     pkg = os.path.dirname(tune.__file__)
-    for name in ("selector_mi355x.json", "selector_mi355x_nnz_s.json", "selector_mi355x_lazy.json"):
+    for name in ("selector_mi355x.json", "selector_mi355x_nnz_s.json"):
         path = os.path.join(pkg, name)
         if os.path.exists(path):
             assert lib.spx_load_selector(None, path.encode()) == 0, lib.spx_last_error()
