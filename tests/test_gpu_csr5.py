@@ -1,5 +1,6 @@
 """The CSR5 copy (the fourth storage format of the pre-selection): every
-SpMV plan on a handle that keeps it runs on it. Parity with the oracle's
+SpMV plan on a handle that keeps it runs on it (the other patterns keep
+their kernels, checked here on the same handles). Parity with the oracle's
 SpMV for every dtype on dense and sparse x, over shapes that stress the tile
 logic: rows that cross lanes and tiles, rows of exactly a lane or a tile,
 empty rows first, last and in runs, a row spanning hundreds of tiles, no
@@ -19,6 +20,9 @@ pytestmark = pytest.mark.gpu
 KINDS = {"f32": (spx.F32, np.float32), "f64": (spx.F64, np.float64), "i32": (spx.I32, np.int32),
          "bool": (spx.BOOL, None)}
 SPMV_PLANS = [spx.plan("spmv", "direct"), spx.plan("spmv", "balanced")]
+# the bitvector SpMSpV on the same handles: consecutive calls with other
+# supports check the bitvector and value buffers left clean between calls
+PLANS = SPMV_PLANS + [spx.plan("csr_spmspv", "balanced"), spx.plan("csr_spmspv", "direct")]
 TILE = 1024  # 64 lanes x 16 entries
 
 
@@ -79,7 +83,7 @@ def _run_all(M, A, kind, tag):
         xs = [torch.as_tensor(xd, device="cuda"),
               (torch.as_tensor(v.idx, device="cuda"), None if kind == "bool" else torch.as_tensor(val, device="cuda"))]
         for x in xs:
-            for p in SPMV_PLANS:
+            for p in PLANS:
                 y = M.run_plan(x, p)
                 torch.cuda.synchronize()
                 assert_close(y.cpu().numpy(), ref, S, kind, f"{tag} {kind} nnz_x={nnz_x} {p}")
