@@ -564,7 +564,7 @@ def main():
     dom_ms = float(np.mean(dom_times)) if len(dom_times) == args.steps else float("nan")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     workload = prof.SWEEP_WORKLOAD
-    names = prof.kernel_names(dom_plan, M.column_order() is not None and M.n <= (1 << 21))
+    names = prof.kernel_names(dom_plan, M.column_order() is not None and M.n <= (1 << 21), prof.csr5_bitvector(M))
     traffic = prof.traffic_for(os.path.join(HERE, "profiles", "traffic.json"), dom)
 
     rec = {

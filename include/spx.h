@@ -101,7 +101,11 @@ typedef enum {
  * items (tile = 0 or 2048) or 4096 (tile = 4096). For the balanced row-major
  * SpMSpV, tile = 1 keeps the bitvector of supp(x) in LDS instead (persistent
  * workgroups; n up to about 1.17M for FP32 or 1.1M for FP64, otherwise the
- * 2048 kernel). */
+ * 2048 kernel); and through a handle whose SpMV format is CSR5 (n <=
+ * 2^20), tile = 0 runs over the CSR5 tiles of 64 x 16 entries with the
+ * bitvector in LDS, every wave of a persistent workgroup on its own tiles
+ * with the next tile's indices in flight (tile = 2048 keeps the merge
+ * tiles). */
 typedef enum {
     SPX_DIST_DIRECT = 0,  /* a fixed group of `lanes` threads per row (per column for CSC) */
     SPX_DIST_BALANCED = 1 /* merge-path tiles with equal (rows + entries) per workgroup */

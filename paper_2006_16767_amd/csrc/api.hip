@@ -1135,6 +1135,15 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
             xd = dt == SPX_BOOL ? nullptr : x->val;
         }
         record(H, H->ev_conv, false, s);
+        if (H->c5.col && p->distribution == SPX_DIST_BALANCED && p->tile == 0 && csr5_lds_fits(A.n)) {
+            // the balanced bitvector SpMSpV over the CSR5 tiles the SpMV
+            // reads, bitvector in LDS; it leaves the whole bitvector clean
+            record(H, H->ev_kern, true, s);
+            SPX_TRY(csr5_spmspv(H->c5, dt, A.n, xd, H->bits, y, s));
+            record(H, H->ev_kern, false, s);
+            H->bits_clean = true;
+            return SPX_OK;
+        }
         SPX_TRY(ensure_ws(H, ws_for(A.m, A.n, A.nnz, 0, dt, p)));
         Arena ws(H->ws, H->ws_bytes);
         const int32_t* part = nullptr;
@@ -1255,7 +1264,11 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
         SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
     else if (H->c5.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(csr5_spmv(H->c5, dt, xd, y, s));
-    else
+    else if (p->pattern == SPX_PAT_CSR_SPMSPV && p->distribution == SPX_DIST_BALANCED && p->tile == 0 && H->c5.col &&
+             csr5_lds_fits(A.n)) {
+        SPX_TRY(csr5_spmspv(H->c5, dt, A.n, xd, H->bits, y, s));
+        H->bits_clean = true;
+    } else
         SPX_TRY(launch_spmv_csr(&A, xd, bits, y, p, part, ws, s, nullptr, nullptr,
                                 H->gorder && H->ts.pk ? &H->ts : nullptr));
     record(H, H->ev_kern, false, s);

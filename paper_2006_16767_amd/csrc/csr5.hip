@@ -31,7 +31,8 @@
 //              tile with a start, 64 tiles a step, written to that row; and
 //              the empty rows are zeroed.
 // Every sum has a fixed order (in-lane, then a fixed scan tree, then tile
-// order), so a call repeats its bits.
+// order), so a call repeats its bits. The same tiles serve the bitvector
+// SpMSpV (k_c5_spmspv_lds), with the bitvector of supp(x) held in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -149,18 +150,133 @@ __global__ __launch_bounds__(kBlock) void k_c5_spmv(int64_t ntiles, int32_t nnz,
     if (lane == 0) lead[t] = v;
 }
 
+// ------------------------------------------------------------------ bitvector SpMSpV
+// The bitvector SpMSpV over the same tiles, with the bitvector of supp(x) in
+// LDS: one persistent 1024-thread workgroup per CU copies it (n / 8 bytes, at
+// most kC5LdsWords words) once; then each of its 16 waves walks its own tiles
+// (no barrier), and while it sums tile t the column indices, row-start bits
+// and first ordinal of its next tile are already in flight. Per tile the
+// validation is an LDS read; only effective entries load their value and
+// gather x, and the row of every start in the lane is fetched together with
+// them (the ordinal map).
+constexpr int kC5LdsThreads = 1024;
+constexpr int kC5LdsWords = 32768;  // 128 KiB: n up to 2^20
+
+template <int DT>
+__global__ __launch_bounds__(kC5LdsThreads) void k_c5_spmspv_lds(
+    int64_t ntiles, int32_t nnz, int32_t nwords, const int32_t* __restrict__ col,
+    const typename SR<DT>::V* __restrict__ vals, const uint32_t* __restrict__ flags,
+    const int32_t* __restrict__ tile_start, const int32_t* __restrict__ nz_rows,
+    const typename SR<DT>::X* __restrict__ x, const uint32_t* __restrict__ bits, typename SR<DT>::Y* __restrict__ y,
+    typename SR<DT>::Acc* __restrict__ lead, typename SR<DT>::Acc* __restrict__ trail) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    extern __shared__ __align__(16) uint32_t s_bits[];
+    const int nvec = nwords >> 2;
+    for (int w = threadIdx.x; w < nvec; w += kC5LdsThreads)
+        reinterpret_cast<uint4*>(s_bits)[w] = reinterpret_cast<const uint4*>(bits)[w];
+    for (int w = (nvec << 2) + (int)threadIdx.x; w < nwords; w += kC5LdsThreads) s_bits[w] = bits[w];
+    __syncthreads();
+    constexpr int kWaves = kC5LdsThreads / kWave;
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    int64_t t = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;  // uniform over the wave
+    int cn[kC5Sigma];
+    uint32_t fln = 0;
+    int32_t tsn = 0;
+    if (t < ntiles) {
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j) cn[j] = col[t * kC5Tile + j * kWave + lane];
+        fln = flags[t * kWave + lane];
+        tsn = tile_start[t];
+    }
+    for (; t < ntiles; t += stride) {
+        int c[kC5Sigma];
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j) c[j] = cn[j];
+        const uint32_t fl = fln;
+        const int64_t base = t * kC5Tile;
+        const int64_t first = base + (int64_t)lane * kC5Sigma;
+        const int nfl = __popc(fl);
+        const int ord0 = tsn + wave_incl_scan(nfl) - nfl;  // ordinal of the lane's first row start
+        bool on[kC5Sigma];
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j)
+            on[j] = first + j < nnz && ((s_bits[c[j] >> 5] >> (c[j] & 31)) & 1u);
+        typename S::V a[kC5Sigma];
+        typename S::X b[kC5Sigma];
+        int32_t row[kC5Sigma];  // the row that starts at the lane's entry j
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j) a[j] = on[j] ? S::val(vals, base + j * kWave + lane) : (typename S::V)0;
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j) b[j] = on[j] ? S::xval(x, c[j]) : (typename S::X)0;
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j)
+            row[j] = ((fl >> j) & 1u) ? nz_rows[ord0 + __popc(fl & ((1u << j) - 1u))] : 0;
+        // the next tile's indices go out before this tile's sums wait
+        const int64_t tn = t + stride;
+        if (tn < ntiles) {
+#pragma unroll
+            for (int j = 0; j < kC5Sigma; ++j) cn[j] = col[tn * kC5Tile + j * kWave + lane];
+            fln = flags[tn * kWave + lane];
+            tsn = tile_start[tn];
+        }
+        Acc run = S::zero(), head = S::zero();
+        bool seen = false;
+        int32_t cur = 0;  // the row of the lane's latest start
+#pragma unroll
+        for (int j = 0; j < kC5Sigma; ++j) {
+            if ((fl >> j) & 1u) {
+                if (seen)
+                    y[cur] = S::out(run);  // a row that starts and ends in this lane
+                else
+                    head = run;
+                seen = true;
+                cur = row[j];
+                run = S::zero();
+            }
+            if (on[j]) run = S::fma(a[j], b[j], run);
+        }
+        if (!seen) head = run;
+        Acc v = head;
+        int f = seen ? 1 : 0;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const Acc vo = shfl_down(v, d);
+            const int fo = shfl_down(f, d);
+            if (lane + d < kWave && !f) {
+                v = S::add(v, vo);
+                f = fo;
+            }
+        }
+        const Acc vn = shfl_down(v, 1);
+        const int fn = shfl_down(f, 1);
+        if (seen) {
+            const Acc tot = lane + 1 < kWave ? S::add(run, vn) : run;
+            if (lane + 1 < kWave && fn)
+                y[cur] = S::out(tot);
+            else
+                trail[t] = tot;  // the tile's last start: the row is still open
+        }
+        if (lane == 0) lead[t] = v;
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(kBlock) void k_c5_fixup(int64_t ntiles, const int32_t* __restrict__ tile_start,
                                                      const int32_t* __restrict__ nz_rows,
                                                      const typename SR<DT>::Acc* __restrict__ lead,
                                                      const typename SR<DT>::Acc* __restrict__ trail, int32_t nempty,
                                                      const int32_t* __restrict__ empty_rows,
-                                                     typename SR<DT>::Y* __restrict__ y) {
+                                                     typename SR<DT>::Y* __restrict__ y,
+                                                     uint32_t* __restrict__ clear_bits, int32_t clear_words) {
     using S = SR<DT>;
     using Acc = typename S::Acc;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nempty; i += stride)
         y[empty_rows[i]] = S::out(S::zero());
+    // the bitvector SpMSpV leaves the bitvector it read clean for the next call
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < clear_words; i += stride) clear_bits[i] = 0u;
     const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (t >= ntiles) return;
     const int32_t s1 = tile_start[t + 1];
@@ -281,9 +397,60 @@ static spx_status csr5_spmv_t(const Csr5Mat& C, const void* x, void* y, hipStrea
     const int64_t blocks = std::max<int64_t>(
         {(int64_t)1, ceil_div(C.ntiles, kWavesPerBlock), std::min<int64_t>(ceil_div(C.nempty, kBlock), 4096)});
     k_c5_fixup<DT><<<(unsigned)blocks, kBlock, 0, s>>>(C.ntiles, C.tile_start, C.nz_rows, (const Acc*)C.lead,
-                                                       (const Acc*)C.trail, C.nempty, C.empty_rows, yv);
+                                                       (const Acc*)C.trail, C.nempty, C.empty_rows, yv, nullptr, 0);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
+}
+
+bool csr5_lds_fits(int32_t n) { return n >= 0 && (int64_t)(n + 31) / 32 <= kC5LdsWords; }
+
+template <int DT>
+static spx_status csr5_spmspv_t(const Csr5Mat& C, int32_t n, const void* x, uint32_t* bits, void* y,
+                                hipStream_t s) {
+    using S = SR<DT>;
+    using Acc = typename S::Acc;
+    auto* yv = (typename S::Y*)y;
+    const int32_t nwords = (n + 31) / 32;
+    if (C.ntiles > 0) {
+        static int cus = 0;
+        if (!cus) {
+            int dev = 0;
+            SPX_HIP(hipGetDevice(&dev));
+            SPX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            cus = std::max(cus, 1);
+        }
+        const size_t lds = (size_t)std::max(nwords, 4) * 4;
+        SPX_HIP(hipFuncSetAttribute((const void*)k_c5_spmspv_lds<DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        const unsigned grid = (unsigned)std::min<int64_t>(cus, ceil_div(C.ntiles, kC5LdsThreads / kWave));
+        k_c5_spmspv_lds<DT><<<grid, kC5LdsThreads, lds, s>>>(C.ntiles, C.nnz, nwords, C.col,
+                                                             (const typename S::V*)C.vals, C.flags, C.tile_start,
+                                                             C.nz_rows, (const typename S::X*)x, bits, yv,
+                                                             (Acc*)C.lead, (Acc*)C.trail);
+        SPX_HIP(hipGetLastError());
+    }
+    const int64_t blocks = std::max<int64_t>({(int64_t)1, ceil_div(C.ntiles, kWavesPerBlock),
+                                              std::min<int64_t>(ceil_div(C.nempty, kBlock), 4096),
+                                              std::min<int64_t>(ceil_div(nwords, kBlock), 4096)});
+    k_c5_fixup<DT><<<(unsigned)blocks, kBlock, 0, s>>>(C.ntiles, C.tile_start, C.nz_rows, (const Acc*)C.lead,
+                                                       (const Acc*)C.trail, C.nempty, C.empty_rows, yv, bits, nwords);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+spx_status csr5_spmspv(const Csr5Mat& C, int dtype, int32_t n, const void* x, uint32_t* bits, void* y,
+                       hipStream_t s) {
+    if (C.m == 0) return SPX_OK;
+    if (!csr5_lds_fits(n)) return fail(SPX_ERR_UNSUPPORTED, "CSR5 SpMSpV: n above 2^20");
+    if (((uintptr_t)bits & 15) != 0) return fail(SPX_ERR_ARG, "CSR5 SpMSpV: bitvector not 16-byte aligned");
+    switch (dtype) {
+        case SPX_F32: return csr5_spmspv_t<SPX_F32>(C, n, x, bits, y, s);
+        case SPX_F64: return csr5_spmspv_t<SPX_F64>(C, n, x, bits, y, s);
+        case SPX_I32: return csr5_spmspv_t<SPX_I32>(C, n, x, bits, y, s);
+        case SPX_BOOL: return csr5_spmspv_t<SPX_BOOL>(C, n, x, bits, y, s);
+        case SPX_F32_MINPLUS: return csr5_spmspv_t<SPX_F32_MINPLUS>(C, n, x, bits, y, s);
+    }
+    return fail(SPX_ERR_DTYPE, "CSR5 SpMSpV: unknown dtype");
 }
 
 spx_status csr5_spmv(const Csr5Mat& C, int dtype, const void* x, void* y, hipStream_t s) {

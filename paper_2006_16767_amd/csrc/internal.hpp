@@ -385,5 +385,11 @@ spx_status csr5_build(const spx_csr& A, const int32_t* row_ptr_host, Csr5Mat* ou
 spx_status csr5_refresh(const Csr5Mat& C, const spx_csr& A, hipStream_t s);
 void csr5_free(Csr5Mat* C);
 spx_status csr5_spmv(const Csr5Mat& C, int dtype, const void* x, void* y, hipStream_t s);
+// The bitvector SpMSpV over the CSR5 tiles with the bitvector in LDS (n <=
+// 2^20): x dense (read only where the bit is set), bits 16-byte aligned; the
+// bitvector is all zero again after the call.
+bool csr5_lds_fits(int32_t n);
+spx_status csr5_spmspv(const Csr5Mat& C, int dtype, int32_t n, const void* x, uint32_t* bits, void* y,
+                       hipStream_t s);
 
 }  // namespace spx

@@ -94,13 +94,23 @@ def kernel_source_hash(stems) -> str:
     return h.hexdigest()
 
 
-def kernel_names(p, column_sorted: bool = False) -> list[str]:
+def csr5_bitvector(M) -> bool:
+    """Whether M's balanced bitvector SpMSpV (tile 0) runs over CSR5 tiles
+    with the bitvector in LDS: the handle's SpMV format is CSR5 and n <=
+    2^20."""
+    return M.n <= (1 << 20) and M.storage_format()[0] == "csr5"
+
+
+def kernel_names(p, column_sorted: bool = False, csr5_bits: bool = False) -> list[str]:
     """Kernel-name stems of the launches a plan makes. column_sorted: the
     handle keeps the column-sorted tiles (renumbered, n <= 2^21), which the
-    balanced row-major plans with 2048-item tiles read."""
+    balanced row-major plans with 2048-item tiles read; csr5_bits: see
+    csr5_bitvector."""
     if p.pattern in (0, 1):
         if p.distribution == 0:
             return ["k_csr_direct"]
+        if p.pattern == 1 and p.tile == 0 and csr5_bits:
+            return ["k_c5_spmspv_lds", "k_c5_fixup"]
         if p.pattern == 1 and p.tile == 1:
             main = "k_csr_bitlds"
         elif column_sorted and p.tile != 4096:
@@ -177,7 +187,8 @@ def cmd_vector(args):
     torch.cuda.synchronize()
     p = M.last_plan()
     sorted_tiles = M.column_order() is not None and M.n <= (1 << 21)
-    print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p, sorted_tiles)}", flush=True)
+    print(f"[prof] vector {args.k}: nnz_x={v.nnz} plan={p} kernels={kernel_names(p, sorted_tiles, csr5_bitvector(M))}",
+          flush=True)
     for _ in range(args.reps):
         call()
     torch.cuda.synchronize()

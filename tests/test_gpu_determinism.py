@@ -32,6 +32,8 @@ def _deterministic_plans():
     for d in ("direct", "balanced"):
         out.append(spx.plan("spmv", d))
         out.append(spx.plan("csr_spmspv", d))
+        if d == "balanced":
+            out.append(spx.plan("csr_spmspv", d, tile=2048))
         out.append(spx.plan("csc_spmspv", d, "sort"))
         if hasattr(spx, "WB_MERGE"):
             out.append(spx.plan("csc_spmspv", d, "merge"))

@@ -27,6 +27,7 @@ def _torch():
 def _row_major_plans():
     return [p for p in spx.all_plans() if p.pattern != spx.PAT_CSC_SPMSPV] + [
         spx.plan("spmv", "balanced", tile=4096), spx.plan("csr_spmspv", "balanced", tile=4096),
+        spx.plan("csr_spmspv", "balanced", tile=2048),
         spx.plan("csr_spmspv", "balanced", tile=1), spx.plan("spmv", "direct", lanes=1),
         spx.plan("csr_spmspv", "direct", lanes=64)]
 
