@@ -355,6 +355,7 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
 constexpr int kWalkMaxX = 2048;       // x entries of a walk
 constexpr int64_t kWalkMaxS = 16384;  // estimated selected entries of a walk
 constexpr int kWalkScan = 32;         // a thread reads columns up to this length whole
+constexpr int kWalkU = 8;             // row indices a lane has in flight while it reads a column
 
 // First position in [a, b) whose row is >= key (b if none), rows ascending:
 // the G lanes of a group probe G interior points of the interval per step
@@ -415,14 +416,23 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
             k0 = group_lower_bound<G>(row_idx, k0, k1, lo);
             k1 = group_lower_bound<G>(row_idx, k0, k1, hi);
         }
-        for (int k = k0 + lane; k < k1; k += G) {
-            const int r = row_idx[k];
-            if (r >= lo && r < hi) {
-                if constexpr (S::kVals)
-                    S::lds_atomic_add(&acc[r - lo], S::mul(S::val(vals, k), v));
-                else
-                    acc[r - lo] = 1u;
-                if constexpr (kTouch) atomicOr(&touched[(r - lo) >> 5], 1u << ((r - lo) & 31));
+        // kWalkU row indices of a lane in flight at once (a lane's positions
+        // past k1 read the column's last entry and are dropped), so a column
+        // costs len / (G * kWalkU) round trips, not len / G
+        for (int kb = k0 + lane; kb < k1; kb += G * kWalkU) {
+            int r[kWalkU];
+#pragma unroll
+            for (int u = 0; u < kWalkU; ++u) r[u] = row_idx[min(kb + u * G, k1 - 1)];
+#pragma unroll
+            for (int u = 0; u < kWalkU; ++u) {
+                const int k = kb + u * G;
+                if (k < k1 && r[u] >= lo && r[u] < hi) {
+                    if constexpr (S::kVals)
+                        S::lds_atomic_add(&acc[r[u] - lo], S::mul(S::val(vals, k), v));
+                    else
+                        acc[r[u] - lo] = 1u;
+                    if constexpr (kTouch) atomicOr(&touched[(r[u] - lo) >> 5], 1u << ((r[u] - lo) & 31));
+                }
             }
         }
     }
