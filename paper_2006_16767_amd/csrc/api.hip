@@ -250,6 +250,8 @@ struct spx_matrix {
     uint32_t* pr_bad = nullptr;
     bool pr_W_valid = false;
     hipStream_t cap_stream = nullptr;
+    hipStream_t cap_side = nullptr;  // a second branch of the captured graph (the fused walk)
+    hipEvent_t cap_fork = nullptr, cap_join = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     const void* gkey[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -479,6 +481,9 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
     if (H->gexec) hipGraphExecDestroy(H->gexec);
     if (H->graph) hipGraphDestroy(H->graph);
     if (H->cap_stream) hipStreamDestroy(H->cap_stream);
+    if (H->cap_side) hipStreamDestroy(H->cap_side);
+    if (H->cap_fork) hipEventDestroy(H->cap_fork);
+    if (H->cap_join) hipEventDestroy(H->cap_join);
     void* ptrs[] = {H->col_ptr, H->row_idx, H->perm, H->vals_csc, H->gorder, H->grank, H->gcol, H->gsrc,
                     H->gvals, H->bits, H->xd, H->sp_idx,
                     H->sp_val, H->scratch_i32, H->dev_scalars, H->scan_counter, H->ws,
@@ -1438,9 +1443,6 @@ extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, c
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     L.persistent_grid = std::max(1, cus) * 4;
-    L.fcol = H->gorder ? H->gcol : nullptr;
-    L.fvals = H->gorder ? H->gvals : nullptr;
-    L.fmap = H->gorder ? H->grank : nullptr;
     L.units = H->units;
     L.nunits = H->nunits;
     L.split_rows = H->split_rows;
@@ -1454,6 +1456,12 @@ extern "C" spx_status run_batch(spx_matrix* H, int32_t B, int64_t total_nnz_x, c
         H->gexec = nullptr;
         H->graph = nullptr;
         if (!H->cap_stream) SPX_HIP(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+        if (!H->cap_side) SPX_HIP(hipStreamCreateWithFlags(&H->cap_side, hipStreamNonBlocking));
+        if (!H->cap_fork) SPX_HIP(hipEventCreateWithFlags(&H->cap_fork, hipEventDisableTiming));
+        if (!H->cap_join) SPX_HIP(hipEventCreateWithFlags(&H->cap_join, hipEventDisableTiming));
+        L.side = H->cap_side;
+        L.fork = H->cap_fork;
+        L.join = H->cap_join;
         SPX_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
         spx_status st = launch_batch(L, H->bws, H->bws_bytes, H->cap_stream, &H->berr);
         hipGraph_t g = nullptr;

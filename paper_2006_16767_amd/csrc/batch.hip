@@ -11,7 +11,10 @@
 //                      phase; resets the queue heads.
 //  k_batch_phase<A|B|C>  #CUs x 4 persistent workgroups pop the items of one
 //                      phase until its queue is drained (every workgroup
-//                      exits once the queue head passes the item count):
+//                      exits once the queue head passes the item count);
+//                      beside B, on a branch of the graph of its own,
+//                      k_batch_fused walks the work units of the fused
+//                      groups (a queue of its own, a wave per unit):
 //                        A: row-major plans scatter x into the vector's
 //                           bitvector / value slots; column-major plans zero
 //                           the vector's row of Y
@@ -26,12 +29,14 @@
 // SpMSpV, any value type but BOOL), or whose entries reach
 // kFusedMinXSparsity of n, joins a group of up to 64 such vectors that share
 // one pass over A. Its phase-A items scatter x into the group's dense slab
-// X^T (n x 64, lane = slot in the group), the phase-B items of the group walk
-// work units of A (at most kUnitNnz entries of at most kUnitRows whole rows,
-// or a piece of a longer row) with a wave per unit and lane = vector, and
-// its phase-C items clear the slab again. Pieces of split rows are added to
-// Y with atomics (their rows of Y are zeroed by a phase-A item of the
-// group); every other row is written once. Non-support entries meet zeros in
+// X^T (n x 64, row = column of A, lane = slot in the group) and its phase-C
+// items clear it again. k_batch_fused walks work units of A for each group
+// (at most kFusedUnitNnz entries of at most kFusedUnitRows whole rows, or a
+// piece of a longer row) with a wave per unit and lane = vector; it is a
+// kernel of its own so that its registers (a handful besides the 32 slab
+// values in flight) set its occupancy, not those of the tile kernels.
+// Pieces of split rows are added to Y with atomics (their rows of Y are
+// zeroed by phase-A items of the group); every other row is written once. Non-support entries meet zeros in
 // the slab, so the bitvector validation of CSR SpMSpV becomes a product with
 // zero.
 //
@@ -59,6 +64,7 @@ constexpr int kCscDirectEntries = 64;
 constexpr int kCscDirectLanes = 4;
 constexpr int kGroup = 64;                 // vectors per fused group (lanes of a wave)
 constexpr double kFusedMinXSparsity = 0.01;
+constexpr int kSplitZeroRows = 64;  // split rows of Y zeroed per phase-A group item
 
 struct BatchPlan {
     int32_t pattern, dist, wb, lanes;
@@ -90,7 +96,7 @@ struct BatchDev {
     BatchPlan* plans;
     int32_t* offs;    // 3 x (B + 1)
     int32_t* totals;  // 4
-    int32_t* queue;   // 3 queue heads, one per phase
+    int32_t* queue;   // queue heads: one per phase, [3] = err, [4, 5] = the fused walk's (64-bit)
     int32_t* err;
     int32_t* excl_all;  // cap_nnz_x + B
     uint32_t* bits_all;  // B x nwords
@@ -106,9 +112,6 @@ struct BatchDev {
     int32_t* gcount;  // vectors in groups (reset per run)
     int32_t* gvec;    // slot -> vector
     void* xt_all;     // ceil(B / 64) slabs of n x 64 values (self-cleaning)
-    const int32_t* fcol;  // columns and values the fused units read (the
-    const void* fvals;    // column-renumbered copy when the handle has one)
-    const int32_t* fmap;  // column -> slab row (null: identity)
 };
 
 __device__ __forceinline__ int dev_tree_eval(const DevTree& t, const double* f) {
@@ -253,10 +256,12 @@ __global__ void k_batch_reset(int32_t* err, int32_t* gcount) {
     *gcount = 0;
 }
 
-// group items appended after the per-vector items of a phase
+// group items appended after the per-vector items of a phase (the groups'
+// walk of A is k_batch_fused): phase A zeroes the split rows of the groups'
+// vectors in Y, kSplitZeroRows rows per item (one item for all of them left
+// a single workgroup with some 10^5 scattered stores, the tail of the phase)
 __device__ __forceinline__ int32_t group_items(const BatchDev& a, int ph, int32_t G) {
-    if (ph == 0) return a.nsplit > 0 ? G : 0;
-    if (ph == 1) return G * (int32_t)ceil_div(a.nunits, kWavesPerBlock);
+    if (ph == 0) return G * (int32_t)ceil_div(a.nsplit, kSplitZeroRows);
     return 0;
 }
 
@@ -282,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_scan(BatchDev a) {
         }
         __syncthreads();
     }
-    if (threadIdx.x < 3) a.queue[threadIdx.x] = 0;
+    if (threadIdx.x < 3 || threadIdx.x == 4 || threadIdx.x == 5) a.queue[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ persistent
@@ -340,11 +345,56 @@ __device__ __forceinline__ void batch_rows_direct(const BatchDev& a, int64_t r0,
     }
 }
 
+// Lane q's value, read into a scalar register (q uniform).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int q) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), q));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)u, q);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(u >> 32), q);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Slab row `row` of a group, this lane's slot. BUF: a buffer load with the
+// row's byte offset in a scalar register and the lane's in a vector one
+// (no 64-bit address per load); the group's slab is below 4 GiB then.
+template <typename X, bool BUF>
+struct SlabRows {
+    const X* base;  // the group's slab
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ SlabRows(const X* b, int64_t n) : base(b) {
+        if constexpr (BUF)
+            rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)b, (short)0, (int)(n * kGroup * (int64_t)sizeof(X)),
+                                                     0x00020000);
+    }
+    __device__ __forceinline__ X load(int row, int lane) const {
+        if constexpr (!BUF) {
+            return base[(int64_t)row * kGroup + lane];
+        } else if constexpr (sizeof(X) == 4) {
+            return __builtin_bit_cast(
+                X, __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, row * (kGroup * 4), 0));
+        } else {
+            return __builtin_bit_cast(
+                X, __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane * 8, row * (kGroup * 8), 0));
+        }
+    }
+};
+
+constexpr int kStageRows = 16;  // rows of a fused unit staged in LDS before they are stored
+
 // One work unit of A for the vectors of fused group g: lane = vector. The
 // unit's entries stream 32 at a time (each a 64-wide gather of the slab row
-// X^T[col]); a row's sum is flushed when the stream passes its end.
-template <int DT>
-__device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32_t unit) {
+// X^T[col]); a row's sums are staged when the stream passes its end, and
+// every kStageRows rows the stage goes out as one run of consecutive rows
+// per vector (a store of lanes = 16 rows x 4 vectors), not as 64 scattered
+// values per row. A piece of a split row adds its sums with atomics.
+// st: the wave's kStageRows x 64 stage, sb: its 64 vector ids (LDS).
+template <int DT, bool BUF>
+__device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32_t unit, typename SR<DT>::Acc* st,
+                                                 int32_t* sb) {
     using S = SR<DT>;
     using X = typename S::X;
     using Acc = typename S::Acc;
@@ -355,20 +405,34 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
     const bool on = lane < nvec;
     const int b = on ? a.gvec[g * kGroup + lane] : 0;
     auto* y = (typename S::Y*)a.Y + (int64_t)b * a.m;
-    const X* xt = (const X*)a.xt_all + (int64_t)g * a.n * kGroup + lane;
-    const auto* vals = (const typename S::V*)a.fvals;
+    const SlabRows<X, BUF> xt((const X*)a.xt_all + (int64_t)g * a.n * kGroup, a.n);
+    const auto* vals = (const typename S::V*)a.vals;
     // lane i holds row_ptr[r0 + i], i <= nrows (nrows < 64)
     const int rp = lane <= nrows ? a.row_ptr[r0 + lane] : 0;
-    const bool split = nrows == 1 && (k0 != __shfl(rp, 0) || k1 != __shfl(rp, 1));
+    const bool split = nrows == 1 && (k0 != lane_value(rp, 0) || k1 != lane_value(rp, 1));
+    sb[lane] = b;
+    // rows [c0, c0 + cnt) of the stage to Y: lane = (row rr, vector t * 4 + lane / 16)
+    auto store_stage = [&](int c0, int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        const int rr = lane & (kStageRows - 1);
+#pragma unroll 4
+        for (int t = 0; t < kGroup / 4; ++t) {
+            const int v = t * 4 + (lane >> 4);
+            if (rr < cnt && v < nvec)
+                ((typename S::Y*)a.Y)[(int64_t)sb[v] * a.m + r0 + c0 + rr] = S::out(st[rr * kGroup + v]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
     auto flush = [&](int i, Acc v) {
-        if (!on) return;
-        if (split)
-            S::atomic_add(&y[r0 + i], v);
-        else
-            y[r0 + i] = S::out(v);
+        if (split) {
+            if (on) S::atomic_add(&y[r0 + i], v);
+            return;
+        }
+        st[(i & (kStageRows - 1)) * kGroup + lane] = v;
+        if ((i & (kStageRows - 1)) == kStageRows - 1) store_stage(i - (kStageRows - 1), kStageRows);
     };
     int i = 0;
-    int end = __shfl(rp, 1);
+    int end = lane_value(rp, 1);
     Acc acc = S::zero();
     // kStep entries per step: lane q loads entry k + q (one coalesced load),
     // then all kStep slab rows are gathered before the first is used
@@ -376,11 +440,11 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
     for (int k = k0; k < k1; k += kStep) {
         const int kk = k + (lane & (kStep - 1));
         const bool in = kk < k1;
-        const int cl = in ? a.fcol[kk] : 0;
+        const int cl = in ? a.col_idx[kk] : 0;
         const typename S::V vl = in ? S::val(vals, kk) : (typename S::V)0;
         X xv[kStep];
 #pragma unroll
-        for (int q = 0; q < kStep; ++q) xv[q] = xt[(int64_t)__shfl(cl, q) * kGroup];
+        for (int q = 0; q < kStep; ++q) xv[q] = xt.load(lane_value(cl, q), lane);
 #pragma unroll
         for (int q = 0; q < kStep; ++q) {
             if (k + q >= k1) break;
@@ -388,14 +452,44 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
                 flush(i, acc);
                 acc = S::zero();
                 ++i;
-                end = __shfl(rp, i + 1);
+                end = lane_value(rp, i + 1);
             }
-            acc = S::fma(__shfl(vl, q), xv[q], acc);
+            acc = S::fma(lane_value(vl, q), xv[q], acc);
         }
     }
     for (; i < nrows; ++i) {
         flush(i, acc);
         acc = S::zero();
+    }
+    if (!split && (nrows & (kStageRows - 1))) store_stage(nrows & ~(kStageRows - 1), nrows & (kStageRows - 1));
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The fused groups' work: item = group x unit, a wave per item, popped in
+// order from a queue of its own (the kernel runs beside the phase-B tiles,
+// so its workgroups become resident as the tiles' leave; every wave exits
+// once the head passes the item count).
+template <int DT, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_batch_fused(BatchDev a) {
+    if constexpr (DT != SPX_BOOL) {  // BOOL vectors never join a group
+        using Acc = typename SR<DT>::Acc;
+        __shared__ Acc s_stage[kWavesPerBlock][kStageRows * kGroup];
+        __shared__ int32_t s_vec[kWavesPerBlock][kGroup];
+        const int64_t G = ceil_div(*a.gcount, kGroup);
+        const int64_t total = G * a.nunits;
+        auto* head = (unsigned long long*)(a.queue + 4);
+        for (;;) {
+            unsigned long long got = 0;
+            if (lane_id() == 0) got = atomicAdd(head, 1ull);
+            // lane 0's value through scalar registers: the item (and so the
+            // group's slab descriptor) is then known to be wave-uniform
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)got);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(got >> 32));
+            const int64_t item = (int64_t)(((uint64_t)hi << 32) | lo);
+            if (item >= total) break;
+            batch_fused_unit<DT, BUF>(a, (int)(item / a.nunits), (int32_t)(item % a.nunits), s_stage[wave_id()],
+                                      s_vec[wave_id()]);
+        }
     }
 }
 
@@ -426,21 +520,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
         const int local = item;
         const int32_t* off = a.offs + ph * (a.B + 1);
         if (local >= off[a.B]) {
-            // a fused group item (phase A: zero the split rows of Y; phase B:
-            // one work unit per wave)
-            const int gi = local - off[a.B];
+            // a fused group item (phase A: zero kSplitZeroRows split rows of
+            // Y for the group's vectors)
             if constexpr (PH == 0) {
-                const int g = gi;
-                const int nvec = min(kGroup, *a.gcount - g * kGroup);
-                for (int t = threadIdx.x; t < a.nsplit * nvec; t += kBlock) {
-                    const int b = a.gvec[g * kGroup + t % nvec];
-                    ((typename S::Y*)a.Y)[(int64_t)b * a.m + a.split_rows[t / nvec]] = (typename S::Y)0;
-                }
-            } else if constexpr (PH == 1) {
-                const int per = (int)ceil_div(a.nunits, kWavesPerBlock);
+                const int gi = local - off[a.B];
+                const int per = (int)ceil_div(a.nsplit, kSplitZeroRows);
                 const int g = gi / per;
-                const int32_t unit = (gi % per) * kWavesPerBlock + wave_id();
-                if (unit < a.nunits) batch_fused_unit<DT>(a, g, unit);
+                const int s0 = (gi % per) * kSplitZeroRows;
+                const int ns = min(kSplitZeroRows, a.nsplit - s0);
+                const int nvec = min(kGroup, *a.gcount - g * kGroup);
+                for (int t = threadIdx.x; t < ns * nvec; t += kBlock) {
+                    const int b = a.gvec[g * kGroup + t % nvec];
+                    ((typename S::Y*)a.Y)[(int64_t)b * a.m + a.split_rows[s0 + t / nvec]] = (typename S::Y)0;
+                }
             }
             continue;
         }
@@ -468,10 +560,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
                         const int e = j * kScatterChunk + q * kBlock + threadIdx.x;
                         c[q] = e < e1 ? idx[e] : -1;
                         v[q] = (PH == 0 && e < e1) ? xv[e] : (typename S::X)0;
-                    }
-                    if (a.fmap) {
-#pragma unroll
-                        for (int q = 0; q < kPer; ++q) c[q] = c[q] >= 0 ? a.fmap[c[q]] : -1;
                     }
 #pragma unroll
                     for (int q = 0; q < kPer; ++q)
@@ -569,7 +657,7 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     take(sizeof(BatchPlan) * (size_t)B);                 // 0 plans
     take(4 * (size_t)3 * (B + 1));                       // 1 offs
     take(4 * 4);                                          // 2 totals
-    take(4 * 4);                                          // 3 queue heads, err
+    take(4 * 8);                                          // 3 queue heads, err, fused walk head
     take(4);                                              // 4 group count
     take(4 * (size_t)(cap_nnz_x + B));                    // 5 excl
     take(4 * (size_t)B * nwords);                         // 6 bits (self-cleaning)
@@ -628,9 +716,6 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
     d.Y = L.Y;
     d.sel = L.sel;
     d.row_lanes = L.row_lanes;
-    d.fcol = L.fcol ? L.fcol : L.csr.col_idx;
-    d.fvals = L.fcol ? L.fvals : L.csr.vals;
-    d.fmap = L.fcol ? L.fmap : nullptr;
     d.units = (const int4*)L.units;
     d.nunits = L.nunits;
     d.split_rows = L.split_rows;
@@ -640,6 +725,34 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
     if (need > ws_bytes) return fail(SPX_ERR_WORKSPACE, "run_batch: workspace too small");
     if (err_dev) *err_dev = d.err;
     if (L.B == 0) return SPX_OK;
+    // a group's slab addressed by 32-bit buffer offsets when it fits
+    const int vsz = std::max(1, value_size(L.csr.dtype));
+    const bool slab_buf = (int64_t)d.n * kGroup * vsz < ((int64_t)1 << 31);
+    // the fused walk's items are dealt out by a grid stride, so its grid is
+    // what stays resident at once (no late workgroup forms a tail)
+    auto resident = [&](const void* fn) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        return (unsigned)std::max(1, L.persistent_grid / 4) * (unsigned)per_cu;
+    };
+    unsigned fused_grid = 1;
+    const bool fused = L.csr.dtype != SPX_BOOL && d.units && d.nunits > 0;
+    const bool branch = L.side && L.fork && L.join;
+    hipStream_t fs = branch ? L.side : s;
+    switch (L.csr.dtype) {
+#define SPX_DT(DT)                                                                                      \
+    case DT:                                                                                            \
+        fused_grid = slab_buf ? resident((const void*)k_batch_fused<DT, true>)                          \
+                              : resident((const void*)k_batch_fused<DT, false>);                        \
+        break;
+        SPX_DT(SPX_F32)
+        SPX_DT(SPX_F64)
+        SPX_DT(SPX_I32)
+#undef SPX_DT
+        default:
+            break;
+    }
     switch (L.csr.dtype) {
 #define SPX_DT(DT)                                                            \
     case DT:                                                                  \
@@ -647,7 +760,19 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
         k_batch_plan<DT><<<L.B, kBlock, 0, s>>>(d);                           \
         k_batch_scan<<<1, kBlock, 0, s>>>(d);                                 \
         k_batch_phase<DT, 0><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
+        if (fused) {                                                          \
+            if (branch) {                                                     \
+                SPX_HIP(hipEventRecord(L.fork, s));                           \
+                SPX_HIP(hipStreamWaitEvent(L.side, L.fork, 0));               \
+            }                                                                 \
+            if (slab_buf)                                                     \
+                k_batch_fused<DT, true><<<fused_grid, kBlock, 0, fs>>>(d);    \
+            else                                                              \
+                k_batch_fused<DT, false><<<fused_grid, kBlock, 0, fs>>>(d);   \
+            if (branch) SPX_HIP(hipEventRecord(L.join, L.side));              \
+        }                                                                     \
         k_batch_phase<DT, 1><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
+        if (fused && branch) SPX_HIP(hipStreamWaitEvent(s, L.join, 0));       \
         k_batch_phase<DT, 2><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
         break;
         SPX_DT(SPX_F32)

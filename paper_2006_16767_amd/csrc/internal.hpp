@@ -252,10 +252,11 @@ struct BatchLaunch {
     int32_t nunits;
     const int32_t* split_rows;
     int32_t nsplit;
-    // the column-renumbered copy (null: none) for the fused units
-    const int32_t* fcol;
-    const void* fvals;
-    const int32_t* fmap;  // column -> rank
+    // while the launches are captured: a second stream and two events that
+    // put the fused groups' walk on a branch of its own, beside the
+    // per-vector tiles (null: one stream)
+    hipStream_t side;
+    hipEvent_t fork, join;
 };
 constexpr int kFusedUnitNnz = 512;
 constexpr int kFusedUnitRows = 63;

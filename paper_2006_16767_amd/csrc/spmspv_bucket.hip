@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "csc_tile.hpp"
+#include "csc_walk.hpp"
 #include "internal.hpp"
 
 namespace spx {
@@ -344,44 +345,13 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_accumulate(int32_t m, in
 
 // ------------------------------------------------------------------ walk (short x)
 // The direct bucket write-back for a short x, in one launch: one 1024-thread
-// workgroup per bucket zeroes its R rows in LDS; groups of G lanes take x
-// entries (G = the plan's lanes, or the most that lets every entry of x go
-// out in one round) and add the entries of their columns whose row falls in
-// the bucket. Rows ascend within a CSC column, so a long column is cut to
-// the bucket's row range by two searches in which the group probes G
-// points per step; short columns are read whole, G entries per step. Then
-// the workgroup writes its rows of y once. No pair buffer, no prefix, no
-// zero fill of y.
+// workgroup per bucket zeroes its R rows in LDS and walks the columns of x
+// restricted to them (csc_walk.hpp: groups of G lanes per x entry, G = the
+// plan's lanes, or the most that lets every entry of x go out in one
+// round). Then the workgroup writes its rows of y once. No pair buffer, no
+// prefix, no zero fill of y.
 constexpr int kWalkMaxX = 2048;       // x entries of a walk
 constexpr int64_t kWalkMaxS = 16384;  // estimated selected entries of a walk
-constexpr int kWalkScan = 32;         // a thread reads columns up to this length whole
-constexpr int kWalkU = 8;             // row indices a lane has in flight while it reads a column
-
-// First position in [a, b) whose row is >= key (b if none), rows ascending:
-// the G lanes of a group probe G interior points of the interval per step
-// (G = 1 is the binary search). Every lane of the group gets the result;
-// the group must be converged.
-template <int G>
-__device__ __forceinline__ int group_lower_bound(const int32_t* __restrict__ rows, int a, int b, int key) {
-    const int lane = threadIdx.x % G;
-    const int shift = (lane_id() / G) * G;  // the group's bits in the wave's ballot
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
-    int lo = a, hi = b;
-    while (lo < hi) {
-        const int64_t span = hi - lo;
-        const int p = lo + (int)((span * (lane + 1)) / (G + 1));  // in [lo, hi)
-        const uint64_t m = (__ballot(rows[p] >= key) >> shift) & gmask;
-        if (!m) {
-            lo += (int)((span * G) / (G + 1)) + 1;  // every probe is below key
-        } else {
-            const int f = __ffsll((unsigned long long)m) - 1;
-            const int lo0 = lo;
-            hi = lo0 + (int)((span * (f + 1)) / (G + 1));
-            if (f > 0) lo = lo0 + (int)((span * f) / (G + 1)) + 1;
-        }
-    }
-    return lo;
-}
 
 template <int DT, bool SPARSE, int G>
 __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR, int32_t nnz_x,
@@ -395,7 +365,6 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
     using S = SR<DT>;
     using Acc = typename S::Acc;
     constexpr bool kTouch = SPARSE && S::kVals;
-    constexpr int kScan = G == 1 ? kWalkScan : 4 * G;  // read whole up to this length
     extern __shared__ __align__(16) char s_raw[];  // typed as the accumulator: 8-byte LDS ops need the alignment
     Acc* acc = (Acc*)s_raw;
     const int R = 1 << logR;
@@ -406,36 +375,14 @@ __global__ __launch_bounds__(kAccThreads) void k_bucket_walk(int32_t m, int logR
     if constexpr (kTouch)
         for (int w = threadIdx.x; w < (R + 31) / 32; w += kAccThreads) touched[w] = 0u;
     __syncthreads();
-    const int lane = threadIdx.x % G;
-    // the loop is uniform across each group of G lanes
-    for (int e = threadIdx.x / G; e < nnz_x; e += kAccThreads / G) {
-        const int j = x_idx[e];
-        const typename S::X v = S::kVals ? x_val[e] : (typename S::X)1;
-        int k0 = col_ptr[j], k1 = col_ptr[j + 1];
-        if (k1 - k0 > kScan) {
-            k0 = group_lower_bound<G>(row_idx, k0, k1, lo);
-            k1 = group_lower_bound<G>(row_idx, k0, k1, hi);
-        }
-        // kWalkU row indices of a lane in flight at once (a lane's positions
-        // past k1 read the column's last entry and are dropped), so a column
-        // costs len / (G * kWalkU) round trips, not len / G
-        for (int kb = k0 + lane; kb < k1; kb += G * kWalkU) {
-            int r[kWalkU];
-#pragma unroll
-            for (int u = 0; u < kWalkU; ++u) r[u] = row_idx[min(kb + u * G, k1 - 1)];
-#pragma unroll
-            for (int u = 0; u < kWalkU; ++u) {
-                const int k = kb + u * G;
-                if (k < k1 && r[u] >= lo && r[u] < hi) {
-                    if constexpr (S::kVals)
-                        S::lds_atomic_add(&acc[r[u] - lo], S::mul(S::val(vals, k), v));
-                    else
-                        acc[r[u] - lo] = 1u;
-                    if constexpr (kTouch) atomicOr(&touched[(r[u] - lo) >> 5], 1u << ((r[u] - lo) & 31));
-                }
-            }
-        }
-    }
+    walk_columns<DT, G>(kAccThreads, nnz_x, x_idx, x_val, col_ptr, row_idx, lo, hi,
+                        [&](int r, int k, typename S::X v) {
+                            if constexpr (S::kVals)
+                                S::lds_atomic_add(&acc[r], S::mul(S::val(vals, k), v));
+                            else
+                                acc[r] = 1u;
+                            if constexpr (kTouch) atomicOr(&touched[r >> 5], 1u << (r & 31));
+                        });
     __syncthreads();
     if constexpr (SPARSE) {
         bucket_emit_sparse<DT>(acc, touched, lo, R, m, so);

@@ -204,6 +204,94 @@ def test_batch_fused_groups(kind):
             assert_close(Y2[b], ref, S, kind, f"fused rerun {name} {kind} b={b}")
 
 
+@pytest.mark.parametrize("kind", ["f32", "f64", "i32"])
+def test_batch_fused_groups_with_unsorted_members(kind):
+    """Fused groups take their members' entries in any order. Three runs
+    on the same arrays (one captured graph): all ascending, one vector's
+    entries shuffled in place, ascending again; every row checked on every
+    run, so a slab or a split row of Y left dirty by one run shows up in the
+    next."""
+    torch = _torch()
+    npdt = {"f32": np.float32, "f64": np.float64, "i32": np.int32}[kind]
+    code = {"f32": spx.F32, "f64": spx.F64, "i32": spx.I32}[kind]
+    A = cfg_matrix("rmat16")
+    if kind == "i32":
+        A = A.with_vals(np.clip(np.round(np.asarray(A.vals) * 4), -4, 4).astype(np.int32))
+    else:
+        A = A.with_vals(np.asarray(A.vals).astype(npdt))
+    M = spx.Matrix.from_host(A, dtype=code)
+    rng = np.random.default_rng(13)
+    dist = "int" if kind == "i32" else "uniform"
+    vecs = [synth.sparse_vector(A.n, max(1, int(round(A.n * d))), 8000 + b, dist,
+                                np.int32 if kind == "i32" else np.float64)
+            for b, d in enumerate(10 ** rng.uniform(-1.5, -0.3, 130))]
+    ptr, idx, val = _pack(vecs, kind, npdt)
+    hp = ptr.cpu().numpy()
+    idx_sorted, val_sorted = idx.clone(), val.clone()
+    refs = [reference(A, v.idx, np.asarray(v.val, npdt), kind) for v in vecs]
+    for run in range(3):
+        if run == 1:
+            s0, s1 = int(hp[70]), int(hp[71])
+            perm = torch.as_tensor(np.random.default_rng(14).permutation(s1 - s0), device="cuda")
+            idx[s0:s1] = idx_sorted[s0:s1][perm]
+            val[s0:s1] = val_sorted[s0:s1][perm]
+        elif run == 2:
+            idx.copy_(idx_sorted)
+            val.copy_(val_sorted)
+        Y = M.run_batch(ptr, idx, val)
+        torch.cuda.synchronize()
+        assert M.batch_status() == 0
+        Yh = Y.cpu().numpy()
+        for b, (ref, S) in enumerate(refs):
+            assert_close(Yh[b], ref, S, kind, f"unsorted members run {run} {kind} b={b} nnz_x={vecs[b].nnz}")
+
+
+def _one_per_row(m, n, seed):
+    """m rows of one entry each in a random column: columns average m / n
+    entries, many are empty."""
+    rng = np.random.default_rng(seed)
+    rp = np.arange(m + 1, dtype=np.int32)
+    ci = rng.integers(0, n, m).astype(np.int32)
+    return synth.CSR(m, n, rp, ci, rng.uniform(-1, 1, m).astype(np.float32))
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64", "i32", "bool"])
+def test_batch_column_major_write_backs(kind):
+    """Sparse vectors (below the fused-group density) on column-major plans,
+    where the columns are long (R-MAT 2^15, hub columns) and where they are
+    short (200,000 rows of one entry, two per column on average, many
+    columns empty). Empty vectors and a support of empty columns included;
+    every row is checked, on two runs (the second reuses the zero fill of
+    Y and the queue heads)."""
+    torch = _torch()
+    npdt = {"f32": np.float32, "f64": np.float64, "i32": np.int32, "bool": None}[kind]
+    code = {"f32": spx.F32, "f64": spx.F64, "i32": spx.I32, "bool": spx.BOOL}[kind]
+    rng = np.random.default_rng(12)
+    for name, A in (("rmat15", synth.rmat(15, 16, 23)), ("one_per_row", _one_per_row(200_000, 100_000, 24))):
+        if kind == "i32":
+            A = A.with_vals(np.clip(np.round(np.asarray(A.vals) * 4), -4, 4).astype(np.int32))
+        elif npdt is not None:
+            A = A.with_vals(np.asarray(A.vals).astype(npdt))
+        M = spx.Matrix.from_host(A, dtype=code)
+        dist = "int" if kind == "i32" else "uniform"
+        vecs = [synth.SparseVec(A.n, np.zeros(0, np.int32), np.zeros(0, np.float64))]
+        empty_cols = np.nonzero(np.bincount(A.col_idx, minlength=A.n) == 0)[0]
+        if empty_cols.size:
+            vecs.append(synth.SparseVec(A.n, empty_cols[:5].astype(np.int32), np.ones(min(5, empty_cols.size))))
+        for b, d in enumerate(10 ** rng.uniform(-4, -2.2, 40)):
+            nnz = max(1, int(round(A.n * d)))
+            vecs.append(synth.sparse_vector(A.n, nnz, 9000 + b, dist, np.int32 if kind == "i32" else np.float64))
+        ptr, idx, val = _pack(vecs, kind, npdt)
+        for rep in range(2):
+            Y = M.run_batch(ptr, idx, val)
+            torch.cuda.synchronize()
+            assert M.batch_status() == 0
+            Yh = Y.cpu().numpy()
+            for b, v in enumerate(vecs):
+                ref, S = reference(A, v.idx, None if kind == "bool" else np.asarray(v.val, npdt), kind)
+                assert_close(Yh[b], ref, S, kind, f"column-major {name} {kind} run {rep} b={b} nnz_x={v.nnz}")
+
+
 @pytest.mark.parametrize("B,n", [(1, 1), (3, 100), (2, 2049), (64, 4096), (1, 1 << 20)])
 def test_dense_rows_to_sparse(B, n):
     """Compaction of dense rows (long rows span many workgroups): indices in
