@@ -111,7 +111,11 @@ typedef enum {
     SPX_DIST_BALANCED = 1 /* merge-path tiles with equal (rows + entries) per workgroup */
 } spx_distribution;
 
-/* Write-back of the column-major pattern (Section 4.2.2). */
+/* Write-back of the column-major pattern (Section 4.2.2). NONE, SORT and
+ * MERGE add each row's products in a fixed order, so a floating-point y
+ * repeats bit for bit from call to call; ATOMIC, LDS_ATOMIC and BUCKET add
+ * them in the order the hardware serves the atomics, so its last bits may
+ * differ between calls (integer and Boolean results never do). */
 typedef enum {
     SPX_WB_NONE = 0,       /* row-major patterns: each row written once, no conflict */
     SPX_WB_ATOMIC = 1,     /* zero y, then hardware atomic add per effective entry */
@@ -119,7 +123,7 @@ typedef enum {
     SPX_WB_LDS_ATOMIC = 3, /* per-workgroup copy of y in LDS, flushed with atomics (small m) */
     SPX_WB_BUCKET = 4,     /* bin pairs by row range, one workgroup per bucket sums in LDS */
     SPX_WB_MERGE = 5       /* sort each tile's pairs in LDS and sum them by row, then merge the
-                              tiles' sorted runs per range of rows (no atomics: repeatable bits) */
+                              tiles' sorted runs per range of rows (no atomics) */
 } spx_writeback;
 
 /* One candidate kernel plus its launch parameters. Zero parameters mean
@@ -388,10 +392,13 @@ spx_status spx_run_times(spx_matrix *H, double *out, int32_t cap, int32_t *count
  * (see spx_load_selector), evaluated by a device kernel on the matrix
  * features and the vector's nnz_x; a vector's nnz_s (the prefix of its
  * column lengths) is computed on the device when its plan is column-major,
- * or for every vector when the loaded trees test nnz_s. The calls are a
- * plan kernel, a queue scan and one persistent kernel, captured once into
- * a HIP graph and replayed while the arrays and B stay the same; nothing
- * synchronizes except a workspace reallocation.
+ * or for every vector when the loaded trees test nnz_s. Vectors whose plan
+ * is row-major, or that hold at least 1 % of n, share passes over A in
+ * groups of 64 (not for BOOL). The calls are a plan kernel, a queue scan,
+ * three persistent phase kernels and, on a parallel branch beside the
+ * second, the groups' walk of A, captured once into a HIP graph and
+ * replayed while the arrays and B stay the same; nothing synchronizes
+ * except a workspace reallocation.
  * total_nnz_x (host) is an upper bound of vec_ptr[B] used to size the
  * workspace. Column-major plans write back with device atomics in this
  * path. Vector indices must be unique within a vector.

@@ -419,7 +419,8 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
         for (int t = 0; t < kGroup / 4; ++t) {
             const int v = t * 4 + (lane >> 4);
             if (rr < cnt && v < nvec)
-                ((typename S::Y*)a.Y)[(int64_t)sb[v] * a.m + r0 + c0 + rr] = S::out(st[rr * kGroup + v]);
+                __builtin_nontemporal_store(S::out(st[rr * kGroup + v]),
+                                            (typename S::Y*)a.Y + (int64_t)sb[v] * a.m + r0 + c0 + rr);
         }
         __builtin_amdgcn_wave_barrier();
     };
@@ -440,11 +441,24 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
     for (int k = k0; k < k1; k += kStep) {
         const int kk = k + (lane & (kStep - 1));
         const bool in = kk < k1;
-        const int cl = in ? a.col_idx[kk] : 0;
-        const typename S::V vl = in ? S::val(vals, kk) : (typename S::V)0;
-        X xv[kStep];
+        // A streams through once per group: non-temporal, so that L2 keeps
+        // the slab rows the gathers re-read
+        const int cl = in ? __builtin_nontemporal_load(a.col_idx + kk) : 0;
+        const typename S::V vl = in ? __builtin_nontemporal_load(vals + kk) : (typename S::V)0;
+        // the step's slab rows into scalars first, with the whole wave
+        // active; then only the group's lanes gather (a partial group moves
+        // only its own bytes)
+        int row[kStep];
 #pragma unroll
-        for (int q = 0; q < kStep; ++q) xv[q] = xt.load(lane_value(cl, q), lane);
+        for (int q = 0; q < kStep; ++q) row[q] = lane_value(cl, q);
+        X xv[kStep];
+        if (on) {
+#pragma unroll
+            for (int q = 0; q < kStep; ++q) xv[q] = xt.load(row[q], lane);
+        } else {
+#pragma unroll
+            for (int q = 0; q < kStep; ++q) xv[q] = (X)0;
+        }
 #pragma unroll
         for (int q = 0; q < kStep; ++q) {
             if (k + q >= k1) break;
@@ -477,6 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(BatchDev a) {
         __shared__ int32_t s_vec[kWavesPerBlock][kGroup];
         const int64_t G = ceil_div(*a.gcount, kGroup);
         const int64_t total = G * a.nunits;
+        if (total == 0) return;  // no group this run: no atomic on the head
         auto* head = (unsigned long long*)(a.queue + 4);
         for (;;) {
             unsigned long long got = 0;
