@@ -62,7 +62,17 @@ constexpr int kFillChunk = 65536;    // rows of Y zeroed per phase-A item
 constexpr int kScatterChunk = 2048;  // x entries scattered / cleared per item
 constexpr int kCscDirectEntries = 64;
 constexpr int kCscDirectLanes = 4;
-constexpr int kGroup = 64;                 // vectors per fused group (lanes of a wave)
+constexpr int kGroup = 64;                 // lanes of a fused group's wave
+
+// vectors per lane of a full fused group: two 4-byte values (an 8-byte slab
+// load per lane, 128 vectors per group and slab rows of 128 slots), one
+// 8-byte value (64 per group). A last group of at most 64 vectors is walked
+// one value per lane (32 entries per step instead of 16) over the first half
+// of its slab rows.
+template <int DT>
+constexpr int group_vpl() {
+    return sizeof(typename SR<DT>::X) == 4 ? 2 : 1;
+}
 constexpr double kFusedMinXSparsity = 0.01;
 constexpr int kSplitZeroRows = 64;  // split rows of Y zeroed per phase-A group item
 
@@ -96,7 +106,7 @@ struct BatchDev {
     BatchPlan* plans;
     int32_t* offs;    // 3 x (B + 1)
     int32_t* totals;  // 4
-    int32_t* queue;   // queue heads: one per phase, [3] = err, [4, 5] = the fused walk's (64-bit)
+    int32_t* queue;   // queue heads: one per phase, [3] = err, [4, 5] and [6, 7] = the two fused walks' (64-bit)
     int32_t* err;
     int32_t* excl_all;  // cap_nnz_x + B
     uint32_t* bits_all;  // B x nwords
@@ -111,7 +121,8 @@ struct BatchDev {
     int32_t nsplit;
     int32_t* gcount;  // vectors in groups (reset per run)
     int32_t* gvec;    // slot -> vector
-    void* xt_all;     // ceil(B / 64) slabs of n x 64 values (self-cleaning)
+    void* xt_all;     // ceil(B / gsize) slabs of n x gsize values (self-cleaning)
+    int32_t gsize;    // vectors per fused group and slots per slab row: 64 x group_vpl
 };
 
 __device__ __forceinline__ int dev_tree_eval(const DevTree& t, const double* f) {
@@ -282,12 +293,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_scan(BatchDev a) {
         }
         if (threadIdx.x == 0) {
             off[a.B] = carry;
-            const int32_t G = (int32_t)ceil_div(*a.gcount, kGroup);
+            const int32_t G = (int32_t)ceil_div(*a.gcount, a.gsize);
             a.totals[ph] = carry + group_items(a, ph, G);
         }
         __syncthreads();
     }
-    if (threadIdx.x < 3 || threadIdx.x == 4 || threadIdx.x == 5) a.queue[threadIdx.x] = 0;
+    if (threadIdx.x < 3 || (threadIdx.x >= 4 && threadIdx.x < 8)) a.queue[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ persistent
@@ -358,86 +369,110 @@ __device__ __forceinline__ T lane_value(T v, int q) {
     }
 }
 
-// Slab row `row` of a group, this lane's slot. BUF: a buffer load with the
-// row's byte offset in a scalar register and the lane's in a vector one
-// (no 64-bit address per load); the group's slab is below 4 GiB then.
-template <typename X, bool BUF>
+// Slab row `row` of a group (kSlots values), this lane's V slots (V
+// consecutive values: one 4- or 8-byte load per lane). BUF: a buffer load with the row's byte
+// offset in a scalar register and the lane's in a vector one (no 64-bit
+// address per load); the group's slab is below 2 GiB then.
+template <typename X, int V>
+struct SlotVals {
+    X v[V];
+};
+
+template <typename X, bool BUF, int V, int kSlots>
 struct SlabRows {
     const X* base;  // the group's slab
     __amdgpu_buffer_rsrc_t rsrc;
     __device__ SlabRows(const X* b, int64_t n) : base(b) {
         if constexpr (BUF)
-            rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)b, (short)0, (int)(n * kGroup * (int64_t)sizeof(X)),
+            rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)b, (short)0, (int)(n * kSlots * (int64_t)sizeof(X)),
                                                      0x00020000);
     }
-    __device__ __forceinline__ X load(int row, int lane) const {
+    __device__ __forceinline__ SlotVals<X, V> load(int row, int lane) const {
+        static_assert(sizeof(X) * V == 4 || sizeof(X) * V == 8, "a lane loads 4 or 8 bytes");
         if constexpr (!BUF) {
-            return base[(int64_t)row * kGroup + lane];
-        } else if constexpr (sizeof(X) == 4) {
-            return __builtin_bit_cast(
-                X, __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, row * (kGroup * 4), 0));
+            return *(const SlotVals<X, V>*)(base + (int64_t)row * kSlots + lane * V);
+        } else if constexpr (sizeof(X) * V == 4) {
+            return __builtin_bit_cast(SlotVals<X, V>, __builtin_amdgcn_raw_buffer_load_b32(
+                                                          rsrc, lane * 4, row * (kSlots * (int)sizeof(X)), 0));
         } else {
-            return __builtin_bit_cast(
-                X, __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane * 8, row * (kGroup * 8), 0));
+            return __builtin_bit_cast(SlotVals<X, V>, __builtin_amdgcn_raw_buffer_load_b64(
+                                                          rsrc, lane * 8, row * (kSlots * (int)sizeof(X)), 0));
         }
     }
 };
 
 constexpr int kStageRows = 16;  // rows of a fused unit staged in LDS before they are stored
 
-// One work unit of A for the vectors of fused group g: lane = vector. The
-// unit's entries stream 32 at a time (each a 64-wide gather of the slab row
-// X^T[col]); a row's sums are staged when the stream passes its end, and
-// every kStageRows rows the stage goes out as one run of consecutive rows
-// per vector (a store of lanes = 16 rows x 4 vectors), not as 64 scattered
-// values per row. A piece of a split row adds its sums with atomics.
-// st: the wave's kStageRows x 64 stage, sb: its 64 vector ids (LDS).
-template <int DT, bool BUF>
+// One work unit of A for the vectors of fused group g (at most 64 V of
+// them; the group's slab rows hold kGroup x group_vpl slots): lane l holds
+// slots V l .. V l + V - 1. The unit's entries stream 32 / V at a time (each a
+// gather of the slab row X^T[col], V values per lane); a row's sums are
+// staged when the stream passes its end, and every kStageRows / V rows the
+// stage goes out as one run of consecutive rows per vector, not as 64 V
+// scattered values per row. A piece of a split row adds its sums with
+// atomics. st: the wave's kStageRows x 64 stage, sb: its 64 V vector ids
+// (LDS).
+template <int DT, bool BUF, int V>
 __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32_t unit, typename SR<DT>::Acc* st,
                                                  int32_t* sb) {
     using S = SR<DT>;
     using X = typename S::X;
     using Acc = typename S::Acc;
+    constexpr int SLOTS = kGroup * group_vpl<DT>();  // vectors per group, slots per slab row
+    constexpr int GS = kGroup * V;                  // slots this walk covers
+    constexpr int kRows = kStageRows / V;           // rows per stage
+    constexpr int kPer = kWave / kRows;     // vectors per store of the stage
     const int4 u = a.units[unit];
     const int r0 = u.x, nrows = u.y - u.x, k0 = u.z, k1 = u.w;
     const int lane = lane_id();
-    const int nvec = min(kGroup, *a.gcount - g * kGroup);
-    const bool on = lane < nvec;
-    const int b = on ? a.gvec[g * kGroup + lane] : 0;
-    auto* y = (typename S::Y*)a.Y + (int64_t)b * a.m;
-    const SlabRows<X, BUF> xt((const X*)a.xt_all + (int64_t)g * a.n * kGroup, a.n);
+    const int nvec = min(GS, *a.gcount - g * SLOTS);
+    bool on[V];
+    typename S::Y* y[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int slot = lane * V + v;
+        on[v] = slot < nvec;
+        const int b = on[v] ? a.gvec[g * SLOTS + slot] : 0;
+        y[v] = (typename S::Y*)a.Y + (int64_t)b * a.m;
+        sb[slot] = b;
+    }
+    const SlabRows<X, BUF, V, SLOTS> xt((const X*)a.xt_all + (int64_t)g * a.n * SLOTS, a.n);
     const auto* vals = (const typename S::V*)a.vals;
     // lane i holds row_ptr[r0 + i], i <= nrows (nrows < 64)
     const int rp = lane <= nrows ? a.row_ptr[r0 + lane] : 0;
     const bool split = nrows == 1 && (k0 != lane_value(rp, 0) || k1 != lane_value(rp, 1));
-    sb[lane] = b;
-    // rows [c0, c0 + cnt) of the stage to Y: lane = (row rr, vector t * 4 + lane / 16)
+    // rows [c0, c0 + cnt) of the stage to Y: lane = (row rr, vector t * kPer + lane / kRows)
     auto store_stage = [&](int c0, int cnt) {
         __builtin_amdgcn_wave_barrier();
-        const int rr = lane & (kStageRows - 1);
+        const int rr = lane & (kRows - 1);
 #pragma unroll 4
-        for (int t = 0; t < kGroup / 4; ++t) {
-            const int v = t * 4 + (lane >> 4);
-            if (rr < cnt && v < nvec)
-                __builtin_nontemporal_store(S::out(st[rr * kGroup + v]),
-                                            (typename S::Y*)a.Y + (int64_t)sb[v] * a.m + r0 + c0 + rr);
+        for (int t = 0; t < GS / kPer; ++t) {
+            const int vs = t * kPer + lane / kRows;
+            if (rr < cnt && vs < nvec)
+                __builtin_nontemporal_store(S::out(st[rr * GS + vs]),
+                                            (typename S::Y*)a.Y + (int64_t)sb[vs] * a.m + r0 + c0 + rr);
         }
         __builtin_amdgcn_wave_barrier();
     };
-    auto flush = [&](int i, Acc v) {
+    Acc acc[V];
+    auto flush = [&](int i) {
         if (split) {
-            if (on) S::atomic_add(&y[r0 + i], v);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (on[v]) S::atomic_add(&y[v][r0 + i], acc[v]);
             return;
         }
-        st[(i & (kStageRows - 1)) * kGroup + lane] = v;
-        if ((i & (kStageRows - 1)) == kStageRows - 1) store_stage(i - (kStageRows - 1), kStageRows);
+#pragma unroll
+        for (int v = 0; v < V; ++v) st[(i & (kRows - 1)) * GS + lane * V + v] = acc[v];
+        if ((i & (kRows - 1)) == kRows - 1) store_stage(i - (kRows - 1), kRows);
     };
     int i = 0;
     int end = lane_value(rp, 1);
-    Acc acc = S::zero();
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = S::zero();
     // kStep entries per step: lane q loads entry k + q (one coalesced load),
     // then all kStep slab rows are gathered before the first is used
-    constexpr int kStep = 32;
+    constexpr int kStep = 32 / V;
     for (int k = k0; k < k1; k += kStep) {
         const int kk = k + (lane & (kStep - 1));
         const bool in = kk < k1;
@@ -451,31 +486,37 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
         int row[kStep];
 #pragma unroll
         for (int q = 0; q < kStep; ++q) row[q] = lane_value(cl, q);
-        X xv[kStep];
-        if (on) {
+        SlotVals<X, V> xv[kStep];
+        if (on[0]) {
 #pragma unroll
             for (int q = 0; q < kStep; ++q) xv[q] = xt.load(row[q], lane);
         } else {
 #pragma unroll
-            for (int q = 0; q < kStep; ++q) xv[q] = (X)0;
+            for (int q = 0; q < kStep; ++q)
+#pragma unroll
+                for (int v = 0; v < V; ++v) xv[q].v[v] = (X)0;
         }
 #pragma unroll
         for (int q = 0; q < kStep; ++q) {
             if (k + q >= k1) break;
             while (k + q >= end) {
-                flush(i, acc);
-                acc = S::zero();
+                flush(i);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = S::zero();
                 ++i;
                 end = lane_value(rp, i + 1);
             }
-            acc = S::fma(lane_value(vl, q), xv[q], acc);
+            const typename S::V aq = lane_value(vl, q);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = S::fma(aq, xv[q].v[v], acc[v]);
         }
     }
     for (; i < nrows; ++i) {
-        flush(i, acc);
-        acc = S::zero();
+        flush(i);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = S::zero();
     }
-    if (!split && (nrows & (kStageRows - 1))) store_stage(nrows & ~(kStageRows - 1), nrows & (kStageRows - 1));
+    if (!split && (nrows & (kRows - 1))) store_stage(nrows & ~(kRows - 1), nrows & (kRows - 1));
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -483,16 +524,27 @@ __device__ __forceinline__ void batch_fused_unit(const BatchDev& a, int g, int32
 // order from a queue of its own (the kernel runs beside the phase-B tiles,
 // so its workgroups become resident as the tiles' leave; every wave exits
 // once the head passes the item count).
-template <int DT, bool BUF>
+template <int DT, bool BUF, int V>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(BatchDev a) {
     if constexpr (DT != SPX_BOOL) {  // BOOL vectors never join a group
         using Acc = typename SR<DT>::Acc;
+        constexpr int SLOTS = kGroup * group_vpl<DT>();
         __shared__ Acc s_stage[kWavesPerBlock][kStageRows * kGroup];
-        __shared__ int32_t s_vec[kWavesPerBlock][kGroup];
-        const int64_t G = ceil_div(*a.gcount, kGroup);
-        const int64_t total = G * a.nunits;
-        if (total == 0) return;  // no group this run: no atomic on the head
-        auto* head = (unsigned long long*)(a.queue + 4);
+        __shared__ int32_t s_vec[kWavesPerBlock][kGroup * V];
+        // groups of this walk: the two-wide one takes every group of more
+        // than 64 vectors, the one-wide one the rest (a last partial group,
+        // or all groups of 8-byte values); one kernel per width, so that
+        // each has its own registers
+        const int gcount = *a.gcount;
+        const int64_t G = ceil_div(gcount, SLOTS);
+        const int last = G > 0 ? gcount - (int)(G - 1) * SLOTS : 0;
+        // groups 0 .. g_wide - 1 are wide
+        const int64_t g_wide = (SLOTS > kGroup && G > 0) ? (last > kGroup ? G : G - 1) : 0;
+        const int64_t g0 = V == 1 ? g_wide : 0;
+        const int64_t ng = V == 1 ? G - g_wide : g_wide;
+        const int64_t total = ng * a.nunits;
+        if (total <= 0) return;  // nothing for this walk: no atomic on the head
+        auto* head = (unsigned long long*)(a.queue + (V == 1 ? 6 : 4));
         for (;;) {
             unsigned long long got = 0;
             if (lane_id() == 0) got = atomicAdd(head, 1ull);
@@ -502,8 +554,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(BatchDev a) {
             const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(got >> 32));
             const int64_t item = (int64_t)(((uint64_t)hi << 32) | lo);
             if (item >= total) break;
-            batch_fused_unit<DT, BUF>(a, (int)(item / a.nunits), (int32_t)(item % a.nunits), s_stage[wave_id()],
-                                      s_vec[wave_id()]);
+            batch_fused_unit<DT, BUF, V>(a, (int)(g0 + item / a.nunits), (int32_t)(item % a.nunits),
+                                         s_stage[wave_id()], s_vec[wave_id()]);
         }
     }
 }
@@ -543,9 +595,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
                 const int g = gi / per;
                 const int s0 = (gi % per) * kSplitZeroRows;
                 const int ns = min(kSplitZeroRows, a.nsplit - s0);
-                const int nvec = min(kGroup, *a.gcount - g * kGroup);
+                const int gs = a.gsize;
+                const int nvec = min(gs, *a.gcount - g * gs);
                 for (int t = threadIdx.x; t < ns * nvec; t += kBlock) {
-                    const int b = a.gvec[g * kGroup + t % nvec];
+                    const int b = a.gvec[g * gs + t % nvec];
                     ((typename S::Y*)a.Y)[(int64_t)b * a.m + a.split_rows[s0 + t / nvec]] = (typename S::Y)0;
                 }
             }
@@ -565,7 +618,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
                 if constexpr (S::kVals) {
                     // the chunk's kScatterChunk entries, eight per thread with
                     // every load of a step in flight before the stores
-                    auto* xt = (typename S::X*)a.xt_all + (int64_t)(p.gslot / kGroup) * a.n * kGroup + p.gslot % kGroup;
+                    const int gs = a.gsize;
+                    auto* xt = (typename S::X*)a.xt_all + (int64_t)(p.gslot / gs) * a.n * gs + p.gslot % gs;
                     const int e1 = std::min(p.nnz_x, (j + 1) * kScatterChunk);
                     constexpr int kPer = kScatterChunk / kBlock;
                     int c[kPer];
@@ -578,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_phase(BatchDev a) {
                     }
 #pragma unroll
                     for (int q = 0; q < kPer; ++q)
-                        if (c[q] >= 0) xt[(int64_t)c[q] * kGroup] = v[q];
+                        if (c[q] >= 0) xt[(int64_t)c[q] * gs] = v[q];
                 }
             }
             continue;
@@ -672,7 +726,7 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     take(sizeof(BatchPlan) * (size_t)B);                 // 0 plans
     take(4 * (size_t)3 * (B + 1));                       // 1 offs
     take(4 * 4);                                          // 2 totals
-    take(4 * 8);                                          // 3 queue heads, err, fused walk head
+    take(4 * 8);                                          // 3 queue heads, err, two fused walk heads
     take(4);                                              // 4 group count
     take(4 * (size_t)(cap_nnz_x + B));                    // 5 excl
     take(4 * (size_t)B * nwords);                         // 6 bits (self-cleaning)
@@ -680,7 +734,8 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     take(4 * (size_t)B * tiles_mat);                      // 8 carry rows
     take((size_t)as * B * tiles_mat);                     // 9 carry values
     take(4 * (size_t)B);                                  // 10 group slot -> vector
-    take((size_t)vs * ceil_div(B, kGroup) * kGroup * (size_t)n);  // 11 group slabs (self-cleaning)
+    const int64_t gsize = (int64_t)kGroup * (vs == 4 ? 2 : 1);
+    take((size_t)vs * ceil_div(B, gsize) * gsize * (size_t)n);  // 11 group slabs (self-cleaning)
     *bytes = z.used;
     if (!d || !base) return;
     d->plans = (BatchPlan*)(base + off[0]);
@@ -697,6 +752,7 @@ static void batch_layout(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap
     d->gcount = (int32_t*)(base + off[4]);
     d->gvec = (int32_t*)(base + off[10]);
     d->xt_all = base + off[11];
+    d->gsize = (int32_t)gsize;
 }
 
 size_t batch_ws_size(int32_t m, int32_t n, int dtype, int32_t B, int64_t cap_nnz_x, int64_t tiles_mat,
@@ -742,7 +798,7 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
     if (L.B == 0) return SPX_OK;
     // a group's slab addressed by 32-bit buffer offsets when it fits
     const int vsz = std::max(1, value_size(L.csr.dtype));
-    const bool slab_buf = (int64_t)d.n * kGroup * vsz < ((int64_t)1 << 31);
+    const bool slab_buf = (int64_t)d.n * d.gsize * vsz < ((int64_t)1 << 31);
     // the fused walk's items are dealt out by a grid stride, so its grid is
     // what stays resident at once (no late workgroup forms a tail)
     auto resident = [&](const void* fn) {
@@ -751,15 +807,17 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
             per_cu = 1;
         return (unsigned)std::max(1, L.persistent_grid / 4) * (unsigned)per_cu;
     };
-    unsigned fused_grid = 1;
+    unsigned fused_grid = 1, fused_grid2 = 1;
     const bool fused = L.csr.dtype != SPX_BOOL && d.units && d.nunits > 0;
     const bool branch = L.side && L.fork && L.join;
     hipStream_t fs = branch ? L.side : s;
     switch (L.csr.dtype) {
 #define SPX_DT(DT)                                                                                      \
     case DT:                                                                                            \
-        fused_grid = slab_buf ? resident((const void*)k_batch_fused<DT, true>)                          \
-                              : resident((const void*)k_batch_fused<DT, false>);                        \
+        fused_grid = slab_buf ? resident((const void*)k_batch_fused<DT, true, 1>)                       \
+                              : resident((const void*)k_batch_fused<DT, false, 1>);                     \
+        fused_grid2 = slab_buf ? resident((const void*)k_batch_fused<DT, true, group_vpl<DT>()>)        \
+                               : resident((const void*)k_batch_fused<DT, false, group_vpl<DT>()>);      \
         break;
         SPX_DT(SPX_F32)
         SPX_DT(SPX_F64)
@@ -780,10 +838,15 @@ spx_status launch_batch(const BatchLaunch& L, void* ws, size_t ws_bytes, hipStre
                 SPX_HIP(hipEventRecord(L.fork, s));                           \
                 SPX_HIP(hipStreamWaitEvent(L.side, L.fork, 0));               \
             }                                                                 \
-            if (slab_buf)                                                     \
-                k_batch_fused<DT, true><<<fused_grid, kBlock, 0, fs>>>(d);    \
-            else                                                              \
-                k_batch_fused<DT, false><<<fused_grid, kBlock, 0, fs>>>(d);   \
+            if (slab_buf) {                                                   \
+                k_batch_fused<DT, true, 1><<<fused_grid, kBlock, 0, fs>>>(d); \
+                if (d.gsize > kGroup)                                         \
+                    k_batch_fused<DT, true, group_vpl<DT>()><<<fused_grid2, kBlock, 0, fs>>>(d); \
+            } else {                                                          \
+                k_batch_fused<DT, false, 1><<<fused_grid, kBlock, 0, fs>>>(d); \
+                if (d.gsize > kGroup)                                         \
+                    k_batch_fused<DT, false, group_vpl<DT>()><<<fused_grid2, kBlock, 0, fs>>>(d); \
+            }                                                                 \
             if (branch) SPX_HIP(hipEventRecord(L.join, L.side));              \
         }                                                                     \
         k_batch_phase<DT, 1><<<L.persistent_grid, kBlock, 0, s>>>(d);         \
