@@ -177,11 +177,23 @@ def extra_poisson(torch, spx, synth, flush, reps=20):
             st = _stats(ts)
             w = warm_ms(torch, lambda: M.run(x, y), reps)
             gbs = b / (st["median_ms"] * 1e-3) / 1e9
-            out[f"{name}_{case}"] = {
+            rec = {
                 "workload": f"poisson3d_128_{name}_{case}", "plan": repr(M.last_plan()), "alg_bytes": b, **st,
                 "GB/s": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
                 "GFLOP/s": round(2 * nnz_s / (st["median_ms"] * 1e-3) / 1e9, 1),
                 "warm_ms": round(w, 5), "warm_pct_hbm_peak": round(100 * b / (w * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)}
+            # the dense-x product runs on the handle's storage copy: its own
+            # bytes (cells + x + y) beside the problem-level CSR figure above
+            fmt, ratio = M.storage_format()
+            if case == "dense_x" and fmt in ("dia", "ell"):
+                cells = ratio * A.nnz
+                per_cell = s + (0.125 if fmt == "dia" else 4)
+                fb = int(cells * per_cell + A.n * s + A.m * s)
+                fg = fb / (st["median_ms"] * 1e-3) / 1e9
+                rec.update({"format": fmt, "format_bytes": fb, "format_GB/s": round(fg, 1),
+                            "format_pct_hbm_peak": round(100 * fg / HBM_PEAK_GBS, 2),
+                            "format_warm_pct_hbm_peak": round(100 * fb / (w * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)})
+            out[f"{name}_{case}"] = rec
     return out
 
 

@@ -255,7 +255,9 @@ size_t spmspv_csc_noalloc_capacity(void);
  *
  * Storage-format pre-selection (Section 8's extension: pick the matrix
  * format per matrix, before the kernel): besides CSR the handle can keep
- * one of three copies: a sliced ELLPACK copy (SELL-C-sigma: slices of 64
+ * one of four copies: a diagonal copy (DIA: at most 32 diagonals stored
+ * one after another with a presence bit per cell, a thread per row, no
+ * column indices read), a sliced ELLPACK copy (SELL-C-sigma: slices of 64
  * rows, one wave per slice and a lane per row, rows sorted by descending
  * length within windows of 4096 rows, padding to the longest row of each
  * slice), an ELLPACK copy (every row padded to the longest row of the
@@ -264,18 +266,24 @@ size_t spmspv_csc_noalloc_capacity(void);
  * transposed, a wave per tile, row starts marked by bits, rows that cross
  * lanes or tiles joined by segmented sums in a fixed order; no padding
  * beyond the last tile). When it does, every plan of the SpMV pattern runs
- * on that copy; the other patterns are unchanged. By default a small
- * decision tree over the matrix features and the padding ratios (cells /
- * nnz; reading the sliced one copies row_ptr to the host once) decides,
- * trained on MI355X timings of the four formats. SPX_FORMAT_SELL forces the
+ * on that copy; the other patterns are unchanged. By default the DIA copy
+ * is taken whenever it applies: the value types but BOOL, the offsets of
+ * 256 rows spread over A (at most 32) hold every entry (one pass checks
+ * it), and its cells move at most 0.8 x the bytes of CSR's values and
+ * column indices; otherwise a small decision tree over the matrix features
+ * and the padding ratios (cells / nnz; reading the sliced one copies
+ * row_ptr to the host once) decides, trained on MI355X timings of the other
+ * four formats. SPX_FORMAT_SELL forces the
  * sliced copy (SPX_ERR_UNSUPPORTED when a row is longer than 4096 entries or
  * the copy would take more than 3 nnz + 65536 cells), SPX_FORMAT_ELL the ELL
  * copy (SPX_ERR_UNSUPPORTED beyond 4096 entries per row or 1.5 nnz + 65536
  * cells), SPX_FORMAT_CSR5 the CSR5 copy (any matrix; building it copies
- * row_ptr to the host and synchronizes the stream); two of these flags
- * together are SPX_ERR_ARG. SPX_FORMAT_CSR forbids every copy. Memory: 8 +
- * value size bytes per cell (4 more per row for the sliced copy; for CSR5,
- * 4 per row and 4 + 16 per tile of 1024 cells). */
+ * row_ptr to the host and synchronizes the stream), SPX_FORMAT_DIA the DIA
+ * copy (SPX_ERR_UNSUPPORTED for BOOL, beyond 32 diagonals or 4 nnz + 65536
+ * cells); two of these flags together are SPX_ERR_ARG. SPX_FORMAT_CSR
+ * forbids every copy. Memory: 8 + value size bytes per cell (4 more per row
+ * for the sliced copy; for CSR5, 4 per row and 4 + 16 per tile of 1024
+ * cells; for DIA, value size + 1/8 per cell). */
 #define SPX_VALIDATE 1u
 #define SPX_RENUMBER 4u
 #define SPX_NO_RENUMBER 8u
@@ -283,14 +291,15 @@ size_t spmspv_csc_noalloc_capacity(void);
 #define SPX_FORMAT_SELL 32u
 #define SPX_FORMAT_ELL 64u
 #define SPX_FORMAT_CSR5 128u
+#define SPX_FORMAT_DIA 256u
 spx_status spx_matrix_create(const spx_csr *A, uint32_t flags, void *stream, spx_matrix **out);
 spx_status spx_matrix_destroy(spx_matrix *H);
 
 /* The handle's CSC copy (device pointers owned by the handle). */
 spx_status spx_matrix_csc(const spx_matrix *H, spx_csc *out);
 
-/* Re-derives the CSC values (and those of the renumbered and sliced ELL
- * copies) from the borrowed CSR values (gathers through the permutations);
+/* Re-derives the CSC values (and those of the renumbered, sliced ELL, ELL,
+ * CSR5 and DIA copies) from the borrowed CSR values (gathers through the permutations);
  * call after the caller changed A's values in place. */
 spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
 
@@ -301,8 +310,8 @@ spx_status spx_matrix_values_updated(spx_matrix *H, void *stream);
 spx_status spx_matrix_column_order(const spx_matrix *H, int32_t *order, int32_t *renumbered, void *stream);
 
 /* *format = 1 if the handle keeps the sliced ELLPACK copy, 2 if it keeps
- * the ELLPACK copy, 3 if it keeps the CSR5 copy (see spx_matrix_create),
- * else 0; *padding_ratio (may be NULL) = that copy's cells / nnz (0 when
+ * the ELLPACK copy, 3 if it keeps the CSR5 copy, 4 if it keeps the DIA copy
+ * (see spx_matrix_create), else 0; *padding_ratio (may be NULL) = that copy's cells / nnz (0 when
  * there is no copy). Host only. */
 spx_status spx_matrix_format(const spx_matrix *H, int32_t *format, double *padding_ratio);
 

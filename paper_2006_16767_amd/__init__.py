@@ -17,7 +17,7 @@ import ctypes as C
 from . import _lib
 from ._lib import (BOOL, DIST_BALANCED, DIST_DIRECT, F32, F32_MINPLUS, F64, I32, NO_SYNC, PAT_CSC_SPMSPV,
                    PAT_CSR_SPMSPV, PAT_SPMV, VALIDATE, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, FORMAT_ELL,
-                   FORMAT_CSR5,
+                   FORMAT_CSR5, FORMAT_DIA,
                    WB_ATOMIC, WB_BUCKET, WB_LDS_ATOMIC, WB_NONE,
                    WB_MERGE, WB_SORT, Plan, SpxError)
 
@@ -137,7 +137,8 @@ class Matrix:
         _ensure_default_selector()
         h = C.c_void_p()
         flags = (VALIDATE if validate else 0) | {None: 0, True: RENUMBER, False: NO_RENUMBER}[renumber]
-        flags |= {None: 0, "csr": FORMAT_CSR, "sell": FORMAT_SELL, "ell": FORMAT_ELL, "csr5": FORMAT_CSR5}[fmt]
+        flags |= {None: 0, "csr": FORMAT_CSR, "sell": FORMAT_SELL, "ell": FORMAT_ELL, "csr5": FORMAT_CSR5,
+                  "dia": FORMAT_DIA}[fmt]
         _lib.call("spx_matrix_create", C.byref(self._csr), flags, _stream(stream), C.byref(h))
         self._h = h
         if dtype == BOOL:
@@ -257,13 +258,13 @@ class Matrix:
         _lib.call("spx_matrix_values_updated", self._h, _stream(stream))
 
     def storage_format(self):
-        """("sell", "ell" or "csr5", padding ratio) when the handle keeps the
-        sliced ELLPACK, the ELLPACK or the CSR5 copy that its SpMV plans run
-        on, else ("csr", 0.0)."""
+        """("sell", "ell", "csr5" or "dia", padding ratio) when the handle
+        keeps the sliced ELLPACK, the ELLPACK, the CSR5 or the diagonal copy
+        that its SpMV plans run on, else ("csr", 0.0)."""
         f = C.c_int32(0)
         r = C.c_double(0.0)
         _lib.call("spx_matrix_format", self._h, C.byref(f), C.byref(r))
-        return ("csr", "sell", "ell", "csr5")[f.value], float(r.value)
+        return ("csr", "sell", "ell", "csr5", "dia")[f.value], float(r.value)
 
     def column_order(self, stream=None):
         """The column ranking of the renumbered row-major copy (device int32

@@ -23,6 +23,7 @@ DIST_DIRECT, DIST_BALANCED = 0, 1
 WB_NONE, WB_ATOMIC, WB_SORT, WB_LDS_ATOMIC, WB_BUCKET, WB_MERGE = 0, 1, 2, 3, 4, 5
 VEC_DENSE, VEC_SPARSE = 0, 1
 VALIDATE, NO_SYNC, RENUMBER, NO_RENUMBER, FORMAT_CSR, FORMAT_SELL, FORMAT_ELL, FORMAT_CSR5 = 1, 2, 4, 8, 16, 32, 64, 128
+FORMAT_DIA = 256
 BFS_PUSH_ONLY = 1
 
 

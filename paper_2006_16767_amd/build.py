@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["prim.hip", "spmv_csr.hip", "spmspv_csc.hip", "spmspv_bucket.hip", "spmspv_merge.hip", "grad.hip",
            "batch.hip",
-           "bfs.hip", "pagerank.hip", "sell.hip", "csr5.hip", "noalloc.hip", "api.hip", "selector.cpp"]
+           "bfs.hip", "pagerank.hip", "sell.hip", "csr5.hip", "dia.hip", "noalloc.hip", "api.hip", "selector.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",

@@ -193,6 +193,7 @@ struct spx_matrix {
     SellMat sell;
     double sell_ratio = 0.0;
     EllMat ell;
+    DiaMat dia;
     Csr5Mat c5;
     // column-sorted copy of the renumbered CSR for the balanced SpMV with
     // 2048-item tiles (kept with the renumbered copy when n <= 2^21)
@@ -495,6 +496,7 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix* H) {
         if (p) hipFree(p);
     sell_free(&H->sell);
     ell_free(&H->ell);
+    dia_free(&H->dia);
     csr5_free(&H->c5);
     tile_sorted_free(&H->ts);
     if (H->drv_host) hipHostFree(H->drv_host);
@@ -672,11 +674,19 @@ static spx_status choose_format(spx_matrix* H, uint32_t flags, hipStream_t s) {
     const spx_csr& A = H->gorder ? H->gcsr : H->csr;
     if ((flags & SPX_FORMAT_CSR) || A.m == 0) return SPX_OK;
     const int nforced = ((flags & SPX_FORMAT_SELL) ? 1 : 0) + ((flags & SPX_FORMAT_ELL) ? 1 : 0) +
-                        ((flags & SPX_FORMAT_CSR5) ? 1 : 0);
-    if (nforced > 1) return fail(SPX_ERR_ARG, "SPX_FORMAT_SELL, SPX_FORMAT_ELL and SPX_FORMAT_CSR5 exclude each other");
+                        ((flags & SPX_FORMAT_CSR5) ? 1 : 0) + ((flags & SPX_FORMAT_DIA) ? 1 : 0);
+    if (nforced > 1)
+        return fail(SPX_ERR_ARG, "SPX_FORMAT_SELL, SPX_FORMAT_ELL, SPX_FORMAT_CSR5 and SPX_FORMAT_DIA exclude each other");
     const bool forced = (flags & SPX_FORMAT_SELL) != 0;
     const bool forced_ell = (flags & SPX_FORMAT_ELL) != 0;
     const bool forced_c5 = (flags & SPX_FORMAT_CSR5) != 0;
+    const bool forced_dia = (flags & SPX_FORMAT_DIA) != 0;
+    // the DIA copy first: where it applies it moves fewer bytes than CSR
+    // and than any padded copy (no column indices at all)
+    if (forced_dia || nforced == 0) {
+        SPX_TRY(dia_try_build(A, (int32_t)H->feat[3], forced_dia, &H->dia, s));
+        if (H->dia.vals || forced_dia) return SPX_OK;
+    }
     std::vector<int32_t> rp;
     SellPlanInfo info;
     bool fetched = false, shaped = false;
@@ -799,6 +809,7 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
     if (H->gsrc) SPX_TRY(gather_perm(H->csr.vals, H->gsrc, H->gvals, H->csr.nnz, vs, (hipStream_t)stream));
     if (H->sell.col) SPX_TRY(sell_refresh(H->sell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->ell.col) SPX_TRY(ell_refresh(H->ell, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
+    if (H->dia.vals) SPX_TRY(dia_refresh(H->dia, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->c5.col) SPX_TRY(csr5_refresh(H->c5, H->gorder ? H->gcsr : H->csr, (hipStream_t)stream));
     if (H->ts.pk) SPX_TRY(gather_perm(H->csr.vals, H->ts.src, H->ts.vals, H->csr.nnz, vs, (hipStream_t)stream));
     return SPX_OK;
@@ -806,9 +817,10 @@ extern "C" spx_status spx_matrix_values_updated(spx_matrix* H, void* stream) {
 
 extern "C" spx_status spx_matrix_format(const spx_matrix* H, int32_t* format, double* padding_ratio) {
     if (!H || !format) return fail(SPX_ERR_ARG, "null argument");
-    *format = H->sell.col ? 1 : H->ell.col ? 2 : H->c5.col ? 3 : 0;
+    *format = H->sell.col ? 1 : H->ell.col ? 2 : H->c5.col ? 3 : H->dia.vals ? 4 : 0;
     if (padding_ratio)
         *padding_ratio = H->sell.col  ? H->sell_ratio
+                         : H->dia.vals ? (double)H->dia.cells / (double)std::max<int32_t>(1, H->csr.nnz)
                          : H->ell.col ? (double)H->ell.cells / (double)std::max<int32_t>(1, H->csr.nnz)
                          : H->c5.col  ? (double)H->c5.cells / (double)std::max<int32_t>(1, H->csr.nnz)
                                       : 0.0;
@@ -1092,7 +1104,9 @@ static spx_status exec_plan(spx_matrix* H, const spx_vec* x, void* y, const spx_
         SPX_TRY(cached_part(H, A, 0, p, s, &part));
         record(H, H->ev_kern, true, s);
         bool cleared = false;
-        if (H->sell.col)
+        if (H->dia.vals)
+            SPX_TRY(dia_spmv(H->dia, dt, xd, y, s));
+        else if (H->sell.col)
             SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
         else if (H->ell.col)
             SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));
@@ -1263,7 +1277,9 @@ static spx_status exec_prepared(spx_matrix* H, const spx_vec* x, const void* xd,
     const int32_t* part = nullptr;
     SPX_TRY(cached_part(H, A, 0, p, s, &part));
     record(H, H->ev_kern, true, s);
-    if (H->sell.col && p->pattern == SPX_PAT_SPMV)
+    if (H->dia.vals && p->pattern == SPX_PAT_SPMV)
+        SPX_TRY(dia_spmv(H->dia, dt, xd, y, s));
+    else if (H->sell.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(sell_spmv(H->sell, dt, xd, y, s));
     else if (H->ell.col && p->pattern == SPX_PAT_SPMV)
         SPX_TRY(ell_spmv(H->ell, dt, xd, y, s));

@@ -364,6 +364,26 @@ spx_status ell_refresh(const EllMat& E, const spx_csr& A, hipStream_t s);
 void ell_free(EllMat* E);
 spx_status ell_spmv(const EllMat& E, int dtype, const void* x, void* y, hipStream_t s);
 
+// DIA copy of A: at most kDiaMax diagonals (ascending offsets col - row),
+// cell (d, i) at d * m + i with a presence bit; see dia.hip.
+constexpr int kDiaMax = 32;
+struct DiaMat {
+    int32_t m = 0, n = 0;
+    int nd = 0;                // diagonals
+    int64_t cells = 0;         // nd * m
+    int64_t words = 0;         // presence words per diagonal
+    int32_t* offs = nullptr;   // [nd]
+    void* vals = nullptr;      // [cells]
+    uint32_t* mask = nullptr;  // [nd * words]
+};
+// Builds the copy when A's entries lie on at most kDiaMax diagonals and it
+// moves fewer bytes than CSR; otherwise leaves *out empty and returns
+// SPX_OK (or, when forced, SPX_ERR_UNSUPPORTED).
+spx_status dia_try_build(const spx_csr& A, int32_t max_row, bool forced, DiaMat* out, hipStream_t s);
+spx_status dia_refresh(const DiaMat& D, const spx_csr& A, hipStream_t s);
+void dia_free(DiaMat* D);
+spx_status dia_spmv(const DiaMat& D, int dtype, const void* x, void* y, hipStream_t s);
+
 // CSR5-style copy of A: tiles of 64 lanes x 16 consecutive entries stored
 // transposed, with row-start bits per lane and the non-empty rows listed;
 // see csr5.hip.

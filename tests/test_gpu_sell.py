@@ -146,15 +146,16 @@ def test_padding_ratio_matches_the_layout_definition():
 def test_auto_format_follows_the_tree():
     """Up to 1.17M entries: rows of at most 7 entries go to ELL, up to 1158 to
     the sliced copy, longer to CSR5. Beyond: nearly equal rows to ELL up to
-    15.7M entries (the stencils) and to the sliced copy past that, rows
-    longer than 17 % of n to CSR5, the large R-MAT graphs stay in CSR."""
+    15.7M entries and to the sliced copy past that, rows longer than 17 % of
+    n to CSR5, the large R-MAT graphs stay in CSR. The stencils lie on 7
+    diagonals and take the DIA copy, which is tried before the tree."""
     _torch()
     assert spx.Matrix.from_host(synth.uniform_rows(65536, 65536, 8, 11)).storage_format()[0] == "sell"
     assert spx.Matrix.from_host(synth.uniform_rows(16384, 16384, 4, 44)).storage_format()[0] == "ell"
     assert spx.Matrix.from_host(cfg_matrix("cfg1")).storage_format()[0] == "sell"
     assert spx.Matrix.from_host(cfg_matrix("rmat16")).storage_format()[0] == "csr5"
-    assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "ell"
-    assert spx.Matrix.from_host(cfg_matrix("cfg3")).storage_format()[0] == "ell"
+    assert spx.Matrix.from_host(synth.poisson3d(64, np.float32)).storage_format()[0] == "dia"
+    assert spx.Matrix.from_host(cfg_matrix("cfg3")).storage_format()[0] == "dia"
     assert spx.Matrix.from_host(synth.powerlaw_rows(100_000, 50_000, 40.0, 31)).storage_format()[0] == "csr5"
     assert spx.Matrix.from_host(synth.rmat(18, 8, 5)).storage_format()[0] == "csr"
 
