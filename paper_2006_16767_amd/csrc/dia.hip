@@ -134,6 +134,56 @@ __global__ __launch_bounds__(kBlock) void k_dia_spmv(int32_t m, int32_t n, int n
     y[i] = S::out(acc.total());
 }
 
+// The same for 8-byte values, two consecutive rows per thread (one presence
+// word): the wave has twice the bytes in flight, which paid in FP64 (34.7
+// against 37.5 µs on Poisson 128^3) and not in FP32 (29.1 against 23.3).
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_dia_spmv2(int32_t m, int32_t n, int nd, const int32_t* __restrict__ offs,
+                                                      int64_t words, const typename SR<DT>::V* __restrict__ dvals,
+                                                      const uint32_t* __restrict__ mask,
+                                                      const typename SR<DT>::X* __restrict__ x,
+                                                      typename SR<DT>::Y* __restrict__ y) {
+    using S = SR<DT>;
+    constexpr int U = 8;
+    constexpr int R = 2;
+    __shared__ int32_t s_off[kDiaMax];
+    if (threadIdx.x < nd) s_off[threadIdx.x] = offs[threadIdx.x];
+    __syncthreads();
+    const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * R;
+    if (i0 >= m) return;
+    typename S::Acc acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = S::zero();
+    for (int d0 = 0; d0 < nd; d0 += U) {
+        uint32_t w[U];
+        typename S::V a[U][R];
+        typename S::X b[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (d0 + u < nd) {  // uniform
+                w[u] = mask[(int64_t)(d0 + u) * words + (i0 >> 5)];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t i = min(i0 + r, (int64_t)m - 1);
+                    const int64_t j = min(max(i + s_off[d0 + u], (int64_t)0), (int64_t)n - 1);
+                    a[u][r] = S::val(dvals, (int64_t)(d0 + u) * m + i);
+                    b[u][r] = S::xval(x, j);
+                }
+            } else {
+                w[u] = 0u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if ((w[u] >> ((i0 + r) & 31)) & 1u) acc[r] = S::fma(a[u][r], b[u][r], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (i0 + r < m) y[i0 + r] = S::out(acc[r]);
+}
+
 // ------------------------------------------------------------------ host side
 void dia_free(DiaMat* D) {
     void* ptrs[] = {D->offs, D->vals, D->mask};
@@ -242,10 +292,13 @@ spx_status dia_spmv(const DiaMat& D, int dtype, const void* x, void* y, hipStrea
                                                D.mask, (const typename SR<DT>::X*)x, (typename SR<DT>::Y*)y);  \
         break;
         SPX_DT(SPX_F32)
-        SPX_DT(SPX_F64)
         SPX_DT(SPX_I32)
         SPX_DT(SPX_F32_MINPLUS)
 #undef SPX_DT
+        case SPX_F64:
+            k_dia_spmv2<SPX_F64><<<(unsigned)ceil_div(D.m, kBlock * 2), kBlock, 0, s>>>(
+                D.m, D.n, D.nd, D.offs, D.words, (const double*)D.vals, D.mask, (const double*)x, (double*)y);
+            break;
         default:
             return fail(SPX_ERR_DTYPE, "DIA: dtype");
     }
