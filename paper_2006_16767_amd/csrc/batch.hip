@@ -14,7 +14,7 @@
 //                      exits once the queue head passes the item count);
 //                      beside B, on a branch of the graph of its own,
 //                      k_batch_fused walks the work units of the fused
-//                      groups (a queue of its own, a wave per unit):
+//                      groups (a queue per width, a wave per unit):
 //                        A: row-major plans scatter x into the vector's
 //                           bitvector / value slots; column-major plans zero
 //                           the vector's row of Y
@@ -27,18 +27,19 @@
 //
 // Fused row-major groups: a vector whose plan is row-major (SpMV or CSR
 // SpMSpV, any value type but BOOL), or whose entries reach
-// kFusedMinXSparsity of n, joins a group of up to 64 such vectors that share
-// one pass over A. Its phase-A items scatter x into the group's dense slab
-// X^T (n x 64, row = column of A, lane = slot in the group) and its phase-C
-// items clear it again. k_batch_fused walks work units of A for each group
-// (at most kFusedUnitNnz entries of at most kFusedUnitRows whole rows, or a
-// piece of a longer row) with a wave per unit and lane = vector; it is a
-// kernel of its own so that its registers (a handful besides the 32 slab
-// values in flight) set its occupancy, not those of the tile kernels.
-// Pieces of split rows are added to Y with atomics (their rows of Y are
-// zeroed by phase-A items of the group); every other row is written once. Non-support entries meet zeros in
-// the slab, so the bitvector validation of CSR SpMSpV becomes a product with
-// zero.
+// kFusedMinXSparsity of n, joins a group that shares one pass over A: 128
+// vectors of 4-byte values (two per lane), 64 of 8-byte ones. Its phase-A
+// items scatter x into the group's dense slab X^T (n rows = columns of A,
+// one slot per vector) and its phase-C items clear it again. k_batch_fused
+// walks work units of A for each group (at most kFusedUnitNnz entries of at
+// most kFusedUnitRows whole rows, or a piece of a longer row), a wave per
+// unit; a last group of at most 64 vectors is walked one per lane. It is a
+// kernel of its own (one per width) so that its registers set its
+// occupancy, not those of the tile kernels. Pieces of split rows are added
+// to Y with atomics (their rows of Y are zeroed by phase-A items of the
+// group); every other row is written once. Non-support entries meet zeros
+// in the slab, so the bitvector validation of CSR SpMSpV becomes a product
+// with zero.
 //
 // The launches are captured once into a HIP graph by the caller and
 // replayed. The per-vector bitvector and value slots are zero when a run
