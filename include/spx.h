@@ -402,7 +402,7 @@ spx_status spx_run_times(spx_matrix *H, double *out, int32_t cap, int32_t *count
  * features and the vector's nnz_x; a vector's nnz_s (the prefix of its
  * column lengths) is computed on the device when its plan is column-major,
  * or for every vector when the loaded trees test nnz_s. Vectors whose plan
- * is row-major, or that hold at least 1 % of n, share passes over A in
+ * is row-major, or that hold at least 2 % of n, share passes over A in
  * groups of 64 (not for BOOL). The calls are a plan kernel, a queue scan,
  * three persistent phase kernels and, on a parallel branch beside the
  * second, the groups' walk of A, captured once into a HIP graph and

@@ -74,7 +74,9 @@ template <int DT>
 constexpr int group_vpl() {
     return sizeof(typename SR<DT>::X) == 4 ? 2 : 1;
 }
-constexpr double kFusedMinXSparsity = 0.01;
+// a column-major vector this dense joins a fused group: at 1 % two vectors
+// could cost a whole pass over A, at 3 % too many products went to atomics
+constexpr double kFusedMinXSparsity = 0.02;
 constexpr int kSplitZeroRows = 64;  // split rows of Y zeroed per phase-A group item
 
 struct BatchPlan {
